@@ -1,0 +1,223 @@
+/*
+ * mffv.h -- matrix-free finite-volume conjugate gradient on AMD MI355X (gfx950).
+ *
+ * The library solves the linear system of an implicit single-phase TPFA
+ * finite-volume discretisation on a 3D Cartesian grid of unit cells
+ * (Sai et al., "Matrix-Free Finite Volume Kernels on a Dataflow Architecture",
+ * Sec. II-A, Eq. 3, 4 and 6, Alg. 1 and Alg. 2). The operator is never
+ * assembled: each application reads the face transmissibilities and forms
+ * T_KL (x_K - x_L) on the six face neighbours of every cell.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Grid nx x ny x nz, cell (i, j, k), flat index l = (i*ny + j)*nz + k
+ *   (z fastest, x slowest). n = nx*ny*nz cells.
+ * - Face arrays have n entries: tx[l] is the face between (i,j,k) and
+ *   (i+1,j,k), ty[l] between (i,j,k) and (i,j+1,k), tz[l] between (i,j,k) and
+ *   (i,j,k+1). Entries on the last plane/row/column are ignored (no-flow).
+ * - T = Upsilon * lambda (transmissibility times the constant mobility, Eq. 4).
+ * - Dirichlet cells D (Eq. 3) are eliminated symmetrically: the solved operator
+ *   on the unknown cells U is
+ *       (A x)_K = c_K x_K + sum_{L adj K} T_KL (x_K - x_L),  x_L := 0 for L in D,
+ *   i.e. minus the Jacobian of Eq. 6 plus an accumulation diagonal c >= 0;
+ *   on D cells A is the identity. This full-grid operator is symmetric
+ *   positive definite whenever D is non-empty or c > 0 somewhere.
+ * - Right-hand side b: b_K = sum_{L in D} T_KL p^D_L on U and p^D_K on D.
+ * - Relative residuals and all norms are taken over U only.
+ * - Pointers named as device pointers must be device memory of the current
+ *   HIP device (e.g. torch tensors); vectors are FP32 unless the name says
+ *   f64. The caller owns every vector it passes. Inputs and outputs of one call
+ *   must not alias unless stated.
+ * - All GPU work is enqueued on the stream given to mffv_create_grid, in
+ *   stream order. Calls that return results on the host synchronize that
+ *   stream before returning.
+ * - Return codes: MFFV_OK (0), MFFV_NOT_CONVERGED (1, a result: x holds the last
+ *   iterate and info is filled) or a negative error. Argument errors are found
+ *   before any GPU work is enqueued. No C++ exception crosses this interface.
+ *   The message of the last error of the calling thread is returned by
+ *   mffv_last_error(). A grid handle must not be used from two threads at once;
+ *   distinct handles are independent.
+ */
+#ifndef MFFV_H
+#define MFFV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MFFV_OK             0
+#define MFFV_NOT_CONVERGED  1
+#define MFFV_EINVAL        (-1)  /* bad argument: null, shape, non-finite or negative coefficient */
+#define MFFV_ENOMEM        (-2)  /* device allocation failed */
+#define MFFV_EHIP          (-3)  /* a HIP runtime call failed; message from hipGetErrorString */
+#define MFFV_EBREAKDOWN    (-4)  /* p.Ap <= 0 or non-finite scalar inside CG */
+#define MFFV_ESTATE        (-5)  /* call out of order, e.g. solve before coefficients are set */
+
+typedef struct mffv_grid mffv_grid;
+
+/* Arithmetic of a solve. */
+enum {
+    MFFV_FP32 = 0,     /* FP32 vectors, apply and dots; FP64 true residual reported  */
+    MFFV_FP64 = 1,     /* FP64 vectors, apply and dots (coefficients upcast from FP32) */
+    MFFV_FP32_IR = 2   /* FP32 CG corrections inside FP64 iterative refinement        */
+};
+
+/* Preconditioner of a solve. */
+enum {
+    MFFV_PRECOND_NONE = 0,     /* plain CG (Alg. 1)                                  */
+    MFFV_PRECOND_JACOBI = 1,   /* z = r / diag(A)                                    */
+    MFFV_PRECOND_LEARNED = 2   /* flexible CG with the 3D-conv network of opts.net   */
+};
+
+typedef struct mffv_net mffv_net;
+
+typedef struct {
+    double tol;          /* target relative residual ||b - A x|| / ||b|| over U (default 1e-6) */
+    int max_iter;        /* cap on CG iterations summed over refinement steps (<= 0: 100000) */
+    int precision;       /* MFFV_FP32 | MFFV_FP64 | MFFV_FP32_IR                              */
+    int precond;         /* MFFV_PRECOND_*                                                    */
+    double inner_tol;    /* FP32_IR: smallest relative reduction asked of one FP32 solve (1e-6) */
+    int max_outer;       /* FP32_IR: cap on refinement steps (default 10)                     */
+    int check_every;     /* iterations enqueued between host polls of the convergence flag (16) */
+    int use_graph;       /* 1: replay a captured HIP graph of check_every iterations          */
+    const mffv_net* net; /* network for MFFV_PRECOND_LEARNED                                  */
+} mffv_opts;
+
+typedef struct {
+    int status;                /* MFFV_OK, MFFV_NOT_CONVERGED or a negative error            */
+    int iters;                 /* CG iterations, summed over refinement steps                */
+    int ir_steps;              /* FP32 correction solves in FP32_IR (1 = no refinement needed) */
+    int fallbacks;             /* learned preconditioner: iterations that used Jacobi instead */
+    double rel_res_recursive;  /* recursively updated residual at exit, relative            */
+    double rel_res_true;       /* ||b - A x|| / ||b|| recomputed in FP64 on the GPU          */
+    double ms;                 /* device time of the solve (HIP events on the grid's stream) */
+} mffv_info;
+
+/* Library version string, e.g. "mffv 1.0 gfx950". Never NULL. */
+const char* mffv_version(void);
+
+/* Message of the last error returned on the calling thread ("" if none). */
+const char* mffv_last_error(void);
+
+/* Fill *opts with the defaults listed in mffv_opts. */
+void mffv_default_opts(mffv_opts* opts);
+
+/*
+ * Create a grid handle for an nx x ny x nz mesh (Sec. II-A, the 7-point
+ * stencil of the TPFA scheme). Requires nx >= 3 (two Dirichlet planes and at
+ * least one unknown plane), ny >= 1, nz >= 1 and n < 2^31. `stream` is a
+ * hipStream_t (NULL = the default stream) on which all later work of this
+ * handle is enqueued; the current HIP device at creation is the handle's
+ * device. Allocates the coefficient arrays (about 21 bytes per cell); solver
+ * workspace is allocated on first use. *out is set only on success.
+ */
+int mffv_create_grid(int nx, int ny, int nz, void* stream, mffv_grid** out);
+
+/* Release the handle and all device memory it owns. NULL is a no-op. */
+void mffv_destroy_grid(mffv_grid* grid);
+
+/*
+ * Face transmissibilities of unit cells from a cell permeability field
+ * (Eq. 4: Upsilon accounts for geometry and permeability). Each face takes the
+ * harmonic average of its two cells, 2 k_K k_L / (k_K + k_L), computed in FP64
+ * and rounded once to FP32; z faces use kz_ratio * k. Faces beyond the domain
+ * are written as 0. `k` (FP64, n entries) and tx/ty/tz (FP32, n entries each)
+ * are device pointers in the flat layout. Enqueued on `stream`; does not
+ * synchronize. Requires k > 0 and finite (not checked on the device).
+ */
+int mffv_perm_to_trans(int nx, int ny, int nz, const double* k, double kz_ratio,
+                       float* tx, float* ty, float* tz, void* stream);
+
+/*
+ * Set the operator of a grid (Eq. 3, 4 and 6 with the accumulation diagonal).
+ *   tx, ty, tz   device FP32 face transmissibilities, n each, >= 0 and finite.
+ *   accum        device FP32 per-cell accumulation c (n entries, >= 0), or NULL
+ *                to use accum_scalar for every cell.
+ *   dmask        device uint8 Dirichlet mask (n entries, nonzero = Dirichlet),
+ *                or NULL for the planes i = 0 and i = nx-1.
+ *   pD           device FP32 Dirichlet pressures (n entries, read on D only),
+ *                or NULL for 1 on i = 0 and 0 on i = nx-1.
+ *   b_out        device FP32 (n entries) receiving the right-hand side b, or NULL.
+ * The library copies what it needs into memory owned by the handle (faces that
+ * touch a Dirichlet cell are zeroed in that copy); the caller may free its
+ * arrays afterwards. Validates the inputs on the device and synchronizes the
+ * stream: returns MFFV_EINVAL for negative or non-finite T or c, non-finite
+ * pD, or a singular operator (no Dirichlet cell and c = 0 everywhere).
+ */
+int mffv_set_transmissibility(mffv_grid* grid, const float* tx, const float* ty, const float* tz,
+                              const float* accum, float accum_scalar, const uint8_t* dmask,
+                              const float* pD, float* b_out);
+
+/*
+ * y = A x on the full grid (Eq. 6 / Alg. 2 with the sign of the Jacobian flipped
+ * and the accumulation added; identity on Dirichlet cells). x and y are device
+ * FP32 vectors of n entries and must not alias. Enqueued; does not synchronize.
+ */
+int mffv_apply(mffv_grid* grid, const float* x, float* y);
+
+/* As mffv_apply with FP64 vectors; the FP32 coefficients are upcast exactly. */
+int mffv_apply_f64(mffv_grid* grid, const double* x, double* y);
+
+/*
+ * FP64 true residual r = b - A x over U (0 on D) and its relative norm
+ * ||r|| / ||b_U|| (Eq. 3 evaluated at x, sign flipped). b (FP32) and x (FP64)
+ * are device vectors; r_out (FP64 device, n entries) may be NULL.
+ * Synchronizes the stream to return *rel_out.
+ */
+int mffv_true_residual(mffv_grid* grid, const float* b, const double* x, double* r_out,
+                       double* rel_out);
+
+/*
+ * Solve A x = b with conjugate gradient (Alg. 1), the apply fused with the
+ * vector updates and the device-wide dot products.
+ *   b     device FP32 right-hand side (n entries); its D entries are the
+ *         Dirichlet values, which are copied into x.
+ *   x     device FP32; in: initial guess on U; out: the solution.
+ *   opts  NULL for the defaults. precision MFFV_FP32 runs FP32 CG and then
+ *         reports the FP64 true residual; MFFV_FP32_IR refines in an FP64
+ *         iterate held by the library and returns it rounded to FP32;
+ *         MFFV_FP64 runs CG in FP64 throughout.
+ *   info  may be NULL.
+ * Synchronizes the stream. Returns MFFV_OK when the target was met (on the
+ * recursive residual for MFFV_FP32 and MFFV_FP64, on the FP64 true residual
+ * for MFFV_FP32_IR), MFFV_NOT_CONVERGED when max_iter was reached, or an error.
+ */
+int mffv_cg_solve(mffv_grid* grid, const float* b, float* x, const mffv_opts* opts,
+                  mffv_info* info);
+
+/*
+ * As mffv_cg_solve with an FP64 right-hand side and an FP64 solution vector,
+ * so that MFFV_FP32_IR can return a field refined beyond FP32 resolution
+ * (relative residuals down to ~1e-12). precision must be MFFV_FP64 or
+ * MFFV_FP32_IR.
+ */
+int mffv_cg_solve_f64(mffv_grid* grid, const double* b, double* x, const mffv_opts* opts,
+                      mffv_info* info);
+
+/*
+ * Solve nsys independent systems (each its own grid handle with coefficients
+ * set, any sizes) in one persistent FP32 CG launch. grids, b and x are host
+ * arrays of nsys pointers; b[s] and x[s] are device FP32 vectors of grid s.
+ * All handles must share the device and stream of grids[0]. info (host, nsys
+ * entries) may be NULL. opts->precond may be NONE or JACOBI; precision is FP32.
+ * Synchronizes the stream. Returns MFFV_OK if every system converged,
+ * MFFV_NOT_CONVERGED if any did not, or an error.
+ */
+int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const* b,
+                          float* const* x, const mffv_opts* opts, mffv_info* info);
+
+/*
+ * Streaming copy dst[i] = src[i] of `bytes` bytes (a multiple of 16) with the
+ * library's own vector kernel: the achievable HBM ceiling the stencil kernels
+ * are compared with. Device pointers, 16-byte aligned. Enqueued on `stream`.
+ */
+int mffv_copy_probe(void* dst, const void* src, size_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFFV_H */

@@ -183,3 +183,29 @@ def constrained_residual_loops(p, tx, ty, tz, c, dmask, pd):
                     s += t * (p[ii, jj, kk] - p[i, j, k])
                 r[i, j, k] = s
     return r
+
+
+def apply_stencil(tx, ty, tz, c, dmask, x):
+    """Full-grid operator applied by array slicing, FP64 (no matrix).
+
+    Same operator as :func:`assemble` (pinned against it on small grids), for
+    grids too large to assemble: on unknown cells
+    ``c_K x_K + sum_L T_KL (x_K - x_L)`` with ``x_L`` taken as 0 on Dirichlet
+    cells, and ``x_K`` itself on Dirichlet cells.
+    """
+    d = np.asarray(dmask, dtype=bool)
+    x = np.asarray(x, dtype=np.float64).reshape(d.shape)
+    xu = np.where(d, 0.0, x)                  # Dirichlet values leave the unknowns' rows
+    y = np.broadcast_to(np.asarray(c, dtype=np.float64), d.shape) * x
+    y = np.array(y, dtype=np.float64)
+    for axis, t in ((0, tx), (1, ty), (2, tz)):
+        t = np.asarray(t, dtype=np.float64)
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[axis] = slice(0, -1)
+        hi[axis] = slice(1, None)
+        lo, hi = tuple(lo), tuple(hi)
+        tf = t[lo]
+        y[lo] += tf * (x[lo] - xu[hi])        # face seen from the lower cell
+        y[hi] += tf * (x[hi] - xu[lo])        # the same face seen from the upper cell
+    return np.where(d, x, y)

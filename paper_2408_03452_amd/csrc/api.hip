@@ -1,0 +1,751 @@
+// C ABI of libmffv: grid handles, operator set-up, apply, CG solves.
+//
+// The CG loop (Alg. 1) runs as two fused kernels per iteration with every
+// scalar kept on the device: phase A forms the new direction, applies the
+// operator to it, adds the previous step to the solution and reduces p.Ap;
+// phase B updates the residual and reduces r.r (and r.z). The host only
+// enqueues chunks of iterations (optionally as a replayed HIP graph) and polls
+// a convergence flag copied to pinned memory once per chunk, one chunk behind,
+// so the device never waits for the host.
+#include "mffv.h"
+#include "launch.hpp"
+#include "nn.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+using namespace mffv;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(MFFV_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+    } while (0)
+
+template <class T>
+int dalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) return MFFV_OK;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(MFFV_ENOMEM, std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
+                                     " bytes failed: " + hipGetErrorString(e));
+    }
+    return MFFV_OK;
+}
+
+template <class T>
+void dfree(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+}  // namespace
+
+struct CgGraph {
+    hipGraphExec_t exec = nullptr;
+    int chunk = 0;
+};
+
+struct mffv_grid {
+    Geom g{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    // operator
+    float *a = nullptr, *tx = nullptr, *ty = nullptr, *tz = nullptr, *dinv = nullptr;
+    double* a64 = nullptr;
+    uint8_t* dmask = nullptr;
+    int* flags = nullptr;
+    bool has_coef = false;
+    // FP32 workspace
+    float *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr, *z = nullptr, *xw = nullptr,
+          *bw = nullptr;
+    CgState<float>* st32 = nullptr;
+    // FP64 workspace
+    double *r64 = nullptr, *p064 = nullptr, *p164 = nullptr, *q64 = nullptr, *x64 = nullptr,
+           *b64 = nullptr, *rres = nullptr;
+    CgState<double>* st64 = nullptr;
+    // reductions and small device scalars
+    double* part = nullptr;  // partials, 4 * max_blocks doubles
+    int max_blocks = 0;
+    unsigned* cnt = nullptr;  // 4 counters
+    double* dscal = nullptr;  // [0] ||b_U||^2, [1] ||r||^2
+    // pinned host mirror of the loop flags, double-buffered
+    int* hflags = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    // launch shapes
+    March m32{}, m64{};
+    int nb_vec = 0;
+    // captured iteration chunks: [precond 0..2]
+    CgGraph graph32[3];
+    CgGraph graph64[2];
+};
+
+namespace {
+
+Coef coef_of(const mffv_grid* G) { return Coef{G->a, G->tx, G->ty, G->tz, G->a64}; }
+
+int check_grid(const mffv_grid* G, bool need_coef) {
+    if (!G) return fail(MFFV_EINVAL, "grid handle is NULL");
+    if (need_coef && !G->has_coef)
+        return fail(MFFV_ESTATE, "operator coefficients not set (call mffv_set_transmissibility)");
+    return MFFV_OK;
+}
+
+int set_device(const mffv_grid* G) {
+    HIP_TRY(hipSetDevice(G->device));
+    return MFFV_OK;
+}
+
+int ensure_ws32(mffv_grid* G) {
+    if (G->r) return MFFV_OK;
+    const size_t n = (size_t)G->g.n;
+    int rc;
+    if ((rc = dalloc(&G->r, n)) || (rc = dalloc(&G->p0, n)) || (rc = dalloc(&G->p1, n)) ||
+        (rc = dalloc(&G->q, n)) || (rc = dalloc(&G->z, n)) || (rc = dalloc(&G->xw, n)) ||
+        (rc = dalloc(&G->bw, n)) || (rc = dalloc(&G->st32, 1))) {
+        dfree(G->r); dfree(G->p0); dfree(G->p1); dfree(G->q); dfree(G->z); dfree(G->xw);
+        dfree(G->bw); dfree(G->st32);
+        return rc;
+    }
+    HIP_TRY(hipMemsetAsync(G->st32, 0, sizeof(CgState<float>), G->stream));
+    return MFFV_OK;
+}
+
+int ensure_x64(mffv_grid* G) {
+    if (G->x64) return MFFV_OK;
+    const size_t n = (size_t)G->g.n;
+    int rc;
+    if ((rc = dalloc(&G->x64, n)) || (rc = dalloc(&G->rres, n))) {
+        dfree(G->x64); dfree(G->rres);
+        return rc;
+    }
+    return MFFV_OK;
+}
+
+int ensure_ws64(mffv_grid* G) {
+    int rc = ensure_x64(G);
+    if (rc) return rc;
+    if (G->r64) return MFFV_OK;
+    const size_t n = (size_t)G->g.n;
+    if ((rc = dalloc(&G->r64, n)) || (rc = dalloc(&G->p064, n)) || (rc = dalloc(&G->p164, n)) ||
+        (rc = dalloc(&G->q64, n)) || (rc = dalloc(&G->b64, n)) || (rc = dalloc(&G->st64, 1))) {
+        dfree(G->r64); dfree(G->p064); dfree(G->p164); dfree(G->q64); dfree(G->b64);
+        dfree(G->st64);
+        return rc;
+    }
+    HIP_TRY(hipMemsetAsync(G->st64, 0, sizeof(CgState<double>), G->stream));
+    return MFFV_OK;
+}
+
+void drop_graphs(mffv_grid* G) {
+    for (auto& gr : G->graph32)
+        if (gr.exec) { (void)hipGraphExecDestroy(gr.exec); gr.exec = nullptr; }
+    for (auto& gr : G->graph64)
+        if (gr.exec) { (void)hipGraphExecDestroy(gr.exec); gr.exec = nullptr; }
+}
+
+// Residual r = b - A x in FP64 and ||r||^2, ||b_U||^2 into dscal[1], dscal[0].
+int true_residual_f64(mffv_grid* G, const void* b, int b_f64, const double* x, double* r) {
+    StencilIO<double> io;
+    io.src = x;
+    io.out = r;
+    io.rhs = b;
+    io.rhs_f64 = b_f64;
+    io.partials = G->part;
+    io.sum_out = G->dscal + 1;
+    io.counter = G->cnt + 0;
+    HIP_TRY(launch_stencil_f64(kResidual, G->g, coef_of(G), io, G->m64, G->stream));
+    HIP_TRY(launch_masked_norm2(G->g.n, G->dmask, b, b_f64, G->part + G->max_blocks, G->cnt + 1,
+                                G->dscal + 0, G->nb_vec, G->stream));
+    return MFFV_OK;
+}
+
+int read_rel(mffv_grid* G, double* rel, double* rn2_out = nullptr) {
+    double h[2];
+    HIP_TRY(hipMemcpyAsync(h, G->dscal, sizeof(h), hipMemcpyDeviceToHost, G->stream));
+    HIP_TRY(hipStreamSynchronize(G->stream));
+    if (rn2_out) *rn2_out = h[1];
+    *rel = h[0] > 0 ? std::sqrt(h[1] / h[0]) : std::sqrt(h[1]);
+    return MFFV_OK;
+}
+
+struct LoopResult {
+    int iters = 0;
+    int status = 0;
+    int fallbacks = 0;
+    double rel_rec = 0;
+};
+
+// Enqueue one CG iteration (phase A, phase B, and for flexible CG the
+// preconditioner and its dots).
+int enqueue_iter32(mffv_grid* G, int precond, const mffv_net* net) {
+    StencilIO<float> a;
+    a.src = (precond == MFFV_PRECOND_NONE) ? G->r : G->z;
+    a.p0 = G->p0;
+    a.p1 = G->p1;
+    a.out = G->q;
+    a.xsol = G->xw;
+    a.partials = reinterpret_cast<float*>(G->part);
+    a.st = G->st32;
+    HIP_TRY(launch_stencil_f32(kFusedCg, G->g, coef_of(G), a, G->m32, G->stream));
+    VecIO<float> v;
+    v.r = G->r;
+    v.q = G->q;
+    v.z = G->z;
+    v.dinv = G->dinv;
+    v.dmask = G->dmask;
+    v.partials = reinterpret_cast<float*>(G->part);
+    v.st = G->st32;
+    const int mode = precond == MFFV_PRECOND_NONE ? kBPlain
+                     : precond == MFFV_PRECOND_JACOBI ? kBJacobi : kBFlex;
+    HIP_TRY(launch_phase_b_f32(mode, G->g.n, v, G->nb_vec, G->stream));
+    if (precond == MFFV_PRECOND_LEARNED) {
+        int rc = nn_precondition(net, G->g, G->r, G->dinv, G->dmask, G->z, G->st32, G->stream);
+        if (rc) return rc;
+        HIP_TRY(launch_flex_dots_f32(G->g.n, v, G->nb_vec, G->stream));
+    }
+    return MFFV_OK;
+}
+
+int enqueue_iter64(mffv_grid* G, int precond) {
+    StencilIO<double> a;
+    a.src = G->r64;
+    a.p0 = G->p064;
+    a.p1 = G->p164;
+    a.out = G->q64;
+    a.xsol = G->x64;
+    a.partials = G->part;
+    a.st = G->st64;
+    if (precond != MFFV_PRECOND_NONE) return fail(MFFV_EINVAL, "FP64 CG supports precond NONE only");
+    HIP_TRY(launch_stencil_f64(kFusedCg, G->g, coef_of(G), a, G->m64, G->stream));
+    VecIO<double> v;
+    v.r = G->r64;
+    v.q = G->q64;
+    v.dmask = G->dmask;
+    v.partials = G->part;
+    v.st = G->st64;
+    HIP_TRY(launch_phase_b_f64(kBPlain, G->g.n, v, G->nb_vec, G->stream));
+    return MFFV_OK;
+}
+
+template <class F>
+int enqueue_chunk(mffv_grid* G, CgGraph& graph, int chunk, bool use_graph, F&& one_iter) {
+    if (use_graph) {
+        if (graph.exec && graph.chunk != chunk) {
+            (void)hipGraphExecDestroy(graph.exec);
+            graph.exec = nullptr;
+        }
+        if (!graph.exec) {
+            HIP_TRY(hipStreamBeginCapture(G->stream, hipStreamCaptureModeThreadLocal));
+            int rc = MFFV_OK;
+            for (int t = 0; t < chunk && rc == MFFV_OK; ++t) rc = one_iter();
+            hipGraph_t gr = nullptr;
+            hipError_t e = hipStreamEndCapture(G->stream, &gr);
+            if (rc) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return rc;
+            }
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&graph.exec, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+            graph.chunk = chunk;
+        }
+        HIP_TRY(hipGraphLaunch(graph.exec, G->stream));
+        return MFFV_OK;
+    }
+    for (int t = 0; t < chunk; ++t) {
+        int rc = one_iter();
+        if (rc) return rc;
+    }
+    return MFFV_OK;
+}
+
+// Run the CG loop until the device flag says stop. State layout: iter, done,
+// status, pending are consecutive ints in CgState.
+template <class State, class F>
+int drive_loop(mffv_grid* G, State* st, int max_iter, int chunk, CgGraph& graph, bool use_graph,
+               F&& one_iter) {
+    const int max_chunks = max_iter / chunk + 3;
+    int c = 0;
+    bool stop = false;
+    for (; c < max_chunks && !stop; ++c) {
+        int rc = enqueue_chunk(G, graph, chunk, use_graph, one_iter);
+        if (rc) return rc;
+        HIP_TRY(hipMemcpyAsync(G->hflags + 4 * (c & 1), &st->iter, 4 * sizeof(int),
+                               hipMemcpyDeviceToHost, G->stream));
+        HIP_TRY(hipEventRecord(G->ev[c & 1], G->stream));
+        if (c >= 1) {
+            HIP_TRY(hipEventSynchronize(G->ev[(c - 1) & 1]));
+            if (G->hflags[4 * ((c - 1) & 1) + 1]) stop = true;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(G->stream));
+    return MFFV_OK;
+}
+
+// FP32 CG on the workspace: solves A xw = bw from the xw given.
+int cg32(mffv_grid* G, double tol, int max_iter, int precond, const mffv_opts& o, LoopResult* out) {
+    const mffv_net* net = o.net;
+    if (precond == MFFV_PRECOND_LEARNED && !net)
+        return fail(MFFV_EINVAL, "precond LEARNED needs opts.net");
+    HIP_TRY(launch_copy_dirichlet_f32(G->g.n, G->dmask, G->bw, G->xw, G->stream));
+    {
+        StencilIO<float> io;
+        io.src = G->xw;
+        io.out = G->r;
+        io.rhs = G->bw;
+        HIP_TRY(launch_stencil_f32(kResidual, G->g, coef_of(G), io, G->m32, G->stream));
+    }
+    VecIO<float> v;
+    v.r = G->r;
+    v.z = (precond == MFFV_PRECOND_JACOBI) ? G->z : nullptr;
+    v.dinv = (precond == MFFV_PRECOND_JACOBI) ? G->dinv : nullptr;
+    v.dmask = G->dmask;
+    v.b = G->bw;
+    v.partials = reinterpret_cast<float*>(G->part);
+    v.st = G->st32;
+    v.tol2 = (float)(tol * tol);
+    v.max_iter = max_iter;
+    HIP_TRY(launch_phase_b_f32(kBInit, G->g.n, v, G->nb_vec, G->stream));
+    if (precond == MFFV_PRECOND_LEARNED) {
+        int rc = nn_precondition(net, G->g, G->r, G->dinv, G->dmask, G->z, G->st32, G->stream);
+        if (rc) return rc;
+        VecIO<float> f = v;
+        f.z = G->z;
+        f.dinv = G->dinv;
+        HIP_TRY(launch_flex_dots_f32(G->g.n, f, G->nb_vec, G->stream));
+    }
+    const int chunk = std::max(1, o.check_every);
+    const bool use_graph = o.use_graph && G->stream != nullptr && precond != MFFV_PRECOND_LEARNED;
+    int rc = drive_loop(G, G->st32, max_iter, chunk, G->graph32[precond], use_graph,
+                        [&]() { return enqueue_iter32(G, precond, net); });
+    if (rc) return rc;
+    HIP_TRY(launch_finalize_f32(G->g.n, G->xw, G->p0, G->p1, G->st32, G->stream));
+    CgState<float> hs;
+    HIP_TRY(hipMemcpyAsync(&hs, G->st32, sizeof(hs), hipMemcpyDeviceToHost, G->stream));
+    HIP_TRY(hipStreamSynchronize(G->stream));
+    out->iters = hs.iter;
+    out->status = hs.status;
+    out->fallbacks = hs.fallbacks;
+    out->rel_rec = hs.bnorm2 > 0 ? std::sqrt((double)hs.rr / (double)hs.bnorm2) : 0.0;
+    if (hs.status == 0 && !hs.done) out->status = MFFV_NOT_CONVERGED;
+    return MFFV_OK;
+}
+
+// FP64 CG on x64 with right-hand side b64.
+int cg64(mffv_grid* G, double tol, int max_iter, const mffv_opts& o, LoopResult* out) {
+    HIP_TRY(launch_copy_dirichlet_f64(G->g.n, G->dmask, G->b64, 1, G->x64, G->stream));
+    {
+        StencilIO<double> io;
+        io.src = G->x64;
+        io.out = G->r64;
+        io.rhs = G->b64;
+        io.rhs_f64 = 1;
+        HIP_TRY(launch_stencil_f64(kResidual, G->g, coef_of(G), io, G->m64, G->stream));
+    }
+    VecIO<double> v;
+    v.r = G->r64;
+    v.dmask = G->dmask;
+    v.b = G->b64;
+    v.b_f64 = 1;
+    v.partials = G->part;
+    v.st = G->st64;
+    v.tol2 = tol * tol;
+    v.max_iter = max_iter;
+    HIP_TRY(launch_phase_b_f64(kBInit, G->g.n, v, G->nb_vec, G->stream));
+    const int chunk = std::max(1, o.check_every);
+    const bool use_graph = o.use_graph && G->stream != nullptr;
+    int rc = drive_loop(G, G->st64, max_iter, chunk, G->graph64[0], use_graph,
+                        [&]() { return enqueue_iter64(G, MFFV_PRECOND_NONE); });
+    if (rc) return rc;
+    HIP_TRY(launch_finalize_f64(G->g.n, G->x64, G->p064, G->p164, G->st64, G->stream));
+    CgState<double> hs;
+    HIP_TRY(hipMemcpyAsync(&hs, G->st64, sizeof(hs), hipMemcpyDeviceToHost, G->stream));
+    HIP_TRY(hipStreamSynchronize(G->stream));
+    out->iters = hs.iter;
+    out->status = hs.status;
+    out->rel_rec = hs.bnorm2 > 0 ? std::sqrt(hs.rr / hs.bnorm2) : 0.0;
+    if (hs.status == 0 && !hs.done) out->status = MFFV_NOT_CONVERGED;
+    return MFFV_OK;
+}
+
+int status_code(int s) {
+    if (s == 0) return MFFV_OK;
+    if (s == 1) return MFFV_NOT_CONVERGED;
+    if (s == -4) return fail(MFFV_EBREAKDOWN, "CG breakdown: p.Ap <= 0 or a non-finite scalar");
+    return s;
+}
+
+mffv_opts resolve_opts(const mffv_opts* o) {
+    mffv_opts r;
+    mffv_default_opts(&r);
+    if (o) {
+        r = *o;
+        if (!(r.tol > 0)) r.tol = 1e-6;
+        if (r.max_iter <= 0) r.max_iter = 100000;
+        if (!(r.inner_tol > 0)) r.inner_tol = 1e-6;
+        if (r.max_outer <= 0) r.max_outer = 10;
+        if (r.check_every <= 0) r.check_every = 16;
+    }
+    return r;
+}
+
+int validate_opts(const mffv_opts& o) {
+    if (!std::isfinite(o.tol) || o.tol >= 1.0)
+        return fail(MFFV_EINVAL, "opts.tol must be in (0, 1)");
+    if (o.precision < MFFV_FP32 || o.precision > MFFV_FP32_IR)
+        return fail(MFFV_EINVAL, "opts.precision must be MFFV_FP32, MFFV_FP64 or MFFV_FP32_IR");
+    if (o.precond < MFFV_PRECOND_NONE || o.precond > MFFV_PRECOND_LEARNED)
+        return fail(MFFV_EINVAL, "opts.precond out of range");
+    if (o.precond == MFFV_PRECOND_LEARNED && !o.net)
+        return fail(MFFV_EINVAL, "precond LEARNED needs opts.net");
+    if (o.precision == MFFV_FP64 && o.precond != MFFV_PRECOND_NONE)
+        return fail(MFFV_EINVAL, "FP64 CG supports precond NONE only");
+    return MFFV_OK;
+}
+
+// Refinement (Sec. precision policy): FP64 iterate G->x64 and right-hand side
+// b; FP32 corrections. Fills info; leaves the refined field in x64.
+int solve_ir(mffv_grid* G, const void* b, int b_f64, const mffv_opts& o, mffv_info* info) {
+    int rc;
+    if ((rc = ensure_ws32(G)) || (rc = ensure_x64(G))) return rc;
+    HIP_TRY(launch_copy_dirichlet_f64(G->g.n, G->dmask, b, b_f64, G->x64, G->stream));
+    int total = 0, steps = 0, fallbacks = 0;
+    double rel = 0, rec = 0;
+    int status = MFFV_NOT_CONVERGED;
+    for (int outer = 0;; ++outer) {
+        if ((rc = true_residual_f64(G, b, b_f64, G->x64, G->rres))) return rc;
+        double rn2 = 0;
+        if ((rc = read_rel(G, &rel, &rn2))) return rc;
+        if (!std::isfinite(rel)) {
+            status = fail(MFFV_EBREAKDOWN, "non-finite residual in refinement");
+            break;
+        }
+        if (rel <= o.tol) {
+            status = MFFV_OK;
+            break;
+        }
+        if (outer >= o.max_outer || total >= o.max_iter) break;
+        // FP32 correction: A d = r / ||r||, to the reduction still needed
+        const double inner = std::min(0.5, std::max(o.tol / rel, o.inner_tol));
+        HIP_TRY(launch_scale_to_f32(G->g.n, G->rres, G->dscal + 1, G->bw, G->stream));
+        HIP_TRY(launch_fill_f32(G->g.n, G->xw, 0.f, G->stream));
+        LoopResult lr;
+        if ((rc = cg32(G, inner, o.max_iter - total, o.precond, o, &lr))) return rc;
+        total += lr.iters;
+        fallbacks += lr.fallbacks;
+        steps += 1;
+        rec = lr.rel_rec * rel;
+        if (lr.status < 0) {
+            status = status_code(lr.status);
+            break;
+        }
+        HIP_TRY(launch_axpy_f64_from_f32(G->g.n, G->dscal + 1, G->xw, G->x64, G->stream));
+    }
+    if (info) {
+        info->iters = total;
+        info->ir_steps = steps;
+        info->fallbacks = fallbacks;
+        info->rel_res_true = rel;
+        info->rel_res_recursive = rec;
+    }
+    return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mffv_version(void) { return "mffv 1.0 gfx950"; }
+
+const char* mffv_last_error(void) { return g_last_error.c_str(); }
+
+void mffv_default_opts(mffv_opts* o) {
+    if (!o) return;
+    o->tol = 1e-6;
+    o->max_iter = 100000;
+    o->precision = MFFV_FP32;
+    o->precond = MFFV_PRECOND_NONE;
+    o->inner_tol = 1e-6;
+    o->max_outer = 10;
+    o->check_every = 16;
+    o->use_graph = 1;
+    o->net = nullptr;
+}
+
+int mffv_create_grid(int nx, int ny, int nz, void* stream, mffv_grid** out) {
+    if (!out) return fail(MFFV_EINVAL, "out is NULL");
+    if (nx < 3 || ny < 1 || nz < 1)
+        return fail(MFFV_EINVAL, "grid needs nx >= 3, ny >= 1, nz >= 1");
+    const int64_t n = (int64_t)nx * ny * nz;
+    if (n >= (int64_t(1) << 31)) return fail(MFFV_EINVAL, "grid has 2^31 cells or more");
+    mffv_grid* G = new (std::nothrow) mffv_grid();
+    if (!G) return fail(MFFV_ENOMEM, "host allocation failed");
+    G->g = Geom{nx, ny, nz, n, (int64_t)ny * nz};
+    G->stream = static_cast<hipStream_t>(stream);
+    int rc = MFFV_OK;
+    hipError_t e = hipGetDevice(&G->device);
+    if (e != hipSuccess) {
+        delete G;
+        return hip_fail(e, "hipGetDevice");
+    }
+    const int vec = (nz % 4 == 0) ? 4 : 1;
+    G->m32 = plan_march(G->g, vec, 0, 1);
+    G->m64 = plan_march(G->g, 1, 0, 1);
+    G->nb_vec = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (n / 4 + kThreads - 1) / kThreads));
+    G->max_blocks = std::max({G->m32.blocks(), G->m64.blocks(), G->nb_vec});
+    if ((rc = dalloc(&G->a, n)) || (rc = dalloc(&G->a64, n)) || (rc = dalloc(&G->tx, n)) || (rc = dalloc(&G->ty, n)) ||
+        (rc = dalloc(&G->tz, n)) || (rc = dalloc(&G->dinv, n)) || (rc = dalloc(&G->dmask, n)) ||
+        (rc = dalloc(&G->flags, 8)) || (rc = dalloc(&G->part, 4 * (size_t)G->max_blocks)) ||
+        (rc = dalloc(&G->cnt, 4)) || (rc = dalloc(&G->dscal, 8))) {
+        mffv_destroy_grid(G);
+        return rc;
+    }
+    if ((e = hipHostMalloc(reinterpret_cast<void**>(&G->hflags), 8 * sizeof(int), 0)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&G->ev[0], hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&G->ev[1], hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreate(&G->t0)) != hipSuccess || (e = hipEventCreate(&G->t1)) != hipSuccess ||
+        (e = hipMemsetAsync(G->cnt, 0, 4 * sizeof(unsigned), G->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(G->stream)) != hipSuccess) {
+        mffv_destroy_grid(G);
+        return hip_fail(e, "grid set-up");
+    }
+    *out = G;
+    return MFFV_OK;
+}
+
+void mffv_destroy_grid(mffv_grid* G) {
+    if (!G) return;
+    (void)hipSetDevice(G->device);
+    (void)hipStreamSynchronize(G->stream);
+    drop_graphs(G);
+    dfree(G->a); dfree(G->a64); dfree(G->tx); dfree(G->ty); dfree(G->tz); dfree(G->dinv); dfree(G->dmask);
+    dfree(G->flags); dfree(G->part); dfree(G->cnt); dfree(G->dscal);
+    dfree(G->r); dfree(G->p0); dfree(G->p1); dfree(G->q); dfree(G->z); dfree(G->xw);
+    dfree(G->bw); dfree(G->st32);
+    dfree(G->r64); dfree(G->p064); dfree(G->p164); dfree(G->q64); dfree(G->x64); dfree(G->b64);
+    dfree(G->rres); dfree(G->st64);
+    if (G->hflags) (void)hipHostFree(G->hflags);
+    for (auto& e : G->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (G->t0) (void)hipEventDestroy(G->t0);
+    if (G->t1) (void)hipEventDestroy(G->t1);
+    delete G;
+}
+
+int mffv_perm_to_trans(int nx, int ny, int nz, const double* k, double kz_ratio, float* tx,
+                       float* ty, float* tz, void* stream) {
+    if (!k || !tx || !ty || !tz) return fail(MFFV_EINVAL, "NULL array");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(MFFV_EINVAL, "bad grid shape");
+    const int64_t n = (int64_t)nx * ny * nz;
+    if (n >= (int64_t(1) << 31)) return fail(MFFV_EINVAL, "grid has 2^31 cells or more");
+    if (!(kz_ratio > 0) || !std::isfinite(kz_ratio)) return fail(MFFV_EINVAL, "kz_ratio must be > 0");
+    Geom g{nx, ny, nz, n, (int64_t)ny * nz};
+    HIP_TRY(launch_perm_to_trans(g, k, kz_ratio, tx, ty, tz, static_cast<hipStream_t>(stream)));
+    return MFFV_OK;
+}
+
+int mffv_set_transmissibility(mffv_grid* G, const float* tx, const float* ty, const float* tz,
+                              const float* accum, float accum_scalar, const uint8_t* dmask,
+                              const float* pD, float* b_out) {
+    int rc = check_grid(G, false);
+    if (rc) return rc;
+    if (!tx || !ty || !tz) return fail(MFFV_EINVAL, "tx, ty and tz must be device arrays");
+    if (!accum && (!(accum_scalar >= 0.f) || !std::isfinite(accum_scalar)))
+        return fail(MFFV_EINVAL, "accumulation must be finite and >= 0");
+    if ((rc = set_device(G))) return rc;
+    drop_graphs(G);
+    G->has_coef = false;
+    HIP_TRY(hipMemsetAsync(G->flags, 0, 8 * sizeof(int), G->stream));
+    SetupIn in{tx, ty, tz, accum, accum_scalar, dmask, pD};
+    SetupOut out{G->a, G->a64, G->tx, G->ty, G->tz, G->dinv, G->dmask, b_out, G->flags};
+    HIP_TRY(launch_setup(G->g, in, out, G->stream));
+    int h[8];
+    HIP_TRY(hipMemcpyAsync(h, G->flags, sizeof(h), hipMemcpyDeviceToHost, G->stream));
+    HIP_TRY(hipStreamSynchronize(G->stream));
+    if (h[0]) return fail(MFFV_EINVAL, "transmissibility negative or not finite");
+    if (h[1]) return fail(MFFV_EINVAL, "accumulation negative or not finite");
+    if (h[2]) return fail(MFFV_EINVAL, "Dirichlet pressure not finite");
+    if (h[3] == 0 && !h[4])
+        return fail(MFFV_EINVAL, "singular operator: no Dirichlet cell and zero accumulation");
+    if (h[3] == G->g.n) return fail(MFFV_EINVAL, "every cell is a Dirichlet cell");
+    G->has_coef = true;
+    return MFFV_OK;
+}
+
+int mffv_apply(mffv_grid* G, const float* x, float* y) {
+    int rc = check_grid(G, true);
+    if (rc) return rc;
+    if (!x || !y) return fail(MFFV_EINVAL, "NULL vector");
+    if (x == y) return fail(MFFV_EINVAL, "x and y must not alias");
+    if ((rc = set_device(G))) return rc;
+    StencilIO<float> io;
+    io.src = x;
+    io.out = y;
+    March m = G->m32;
+    const bool aligned = ((uintptr_t)x % 16 == 0) && ((uintptr_t)y % 16 == 0);
+    if (m.vec == 4 && !aligned) m = plan_march(G->g, 1, 0, 1);
+    HIP_TRY(launch_stencil_f32(kApply, G->g, coef_of(G), io, m, G->stream));
+    return MFFV_OK;
+}
+
+int mffv_apply_f64(mffv_grid* G, const double* x, double* y) {
+    int rc = check_grid(G, true);
+    if (rc) return rc;
+    if (!x || !y) return fail(MFFV_EINVAL, "NULL vector");
+    if (x == y) return fail(MFFV_EINVAL, "x and y must not alias");
+    if ((rc = set_device(G))) return rc;
+    StencilIO<double> io;
+    io.src = x;
+    io.out = y;
+    HIP_TRY(launch_stencil_f64(kApply, G->g, coef_of(G), io, G->m64, G->stream));
+    return MFFV_OK;
+}
+
+int mffv_true_residual(mffv_grid* G, const float* b, const double* x, double* r_out,
+                       double* rel_out) {
+    int rc = check_grid(G, true);
+    if (rc) return rc;
+    if (!b || !x || !rel_out) return fail(MFFV_EINVAL, "NULL argument");
+    if ((rc = set_device(G)) || (rc = ensure_x64(G))) return rc;
+    double* r = r_out ? r_out : G->rres;
+    if ((rc = true_residual_f64(G, b, 0, x, r))) return rc;
+    return read_rel(G, rel_out);
+}
+
+int mffv_cg_solve(mffv_grid* G, const float* b, float* x, const mffv_opts* opts, mffv_info* info) {
+    int rc = check_grid(G, true);
+    if (rc) return rc;
+    if (!b || !x) return fail(MFFV_EINVAL, "NULL vector");
+    if (b == x) return fail(MFFV_EINVAL, "b and x must not alias");
+    mffv_opts o = resolve_opts(opts);
+    if ((rc = validate_opts(o))) return rc;
+    if ((rc = set_device(G)) || (rc = ensure_ws32(G))) return rc;
+    mffv_info inf{};
+    const int64_t n = G->g.n;
+    HIP_TRY(hipEventRecord(G->t0, G->stream));
+    int status = MFFV_OK;
+    if (o.precision == MFFV_FP32) {
+        HIP_TRY(hipMemcpyAsync(G->bw, b, n * sizeof(float), hipMemcpyDeviceToDevice, G->stream));
+        HIP_TRY(hipMemcpyAsync(G->xw, x, n * sizeof(float), hipMemcpyDeviceToDevice, G->stream));
+        LoopResult lr;
+        if ((rc = cg32(G, o.tol, o.max_iter, o.precond, o, &lr))) return rc;
+        HIP_TRY(hipMemcpyAsync(x, G->xw, n * sizeof(float), hipMemcpyDeviceToDevice, G->stream));
+        if ((rc = ensure_x64(G))) return rc;
+        HIP_TRY(launch_convert_f32_to_f64(n, G->xw, G->x64, G->stream));
+        if ((rc = true_residual_f64(G, b, 0, G->x64, G->rres))) return rc;
+        if ((rc = read_rel(G, &inf.rel_res_true))) return rc;
+        inf.iters = lr.iters;
+        inf.ir_steps = 1;
+        inf.fallbacks = lr.fallbacks;
+        inf.rel_res_recursive = lr.rel_rec;
+        status = lr.status;
+    } else if (o.precision == MFFV_FP32_IR) {
+        if ((rc = ensure_x64(G))) return rc;
+        HIP_TRY(launch_convert_f32_to_f64(n, x, G->x64, G->stream));
+        status = solve_ir(G, b, 0, o, &inf);
+        if (status < 0) return status;
+        HIP_TRY(launch_convert_f64_to_f32(n, G->x64, x, G->stream));
+    } else {
+        if ((rc = ensure_ws64(G))) return rc;
+        HIP_TRY(launch_convert_f32_to_f64(n, b, G->b64, G->stream));
+        HIP_TRY(launch_convert_f32_to_f64(n, x, G->x64, G->stream));
+        LoopResult lr;
+        if ((rc = cg64(G, o.tol, o.max_iter, o, &lr))) return rc;
+        HIP_TRY(launch_convert_f64_to_f32(n, G->x64, x, G->stream));
+        if ((rc = true_residual_f64(G, G->b64, 1, G->x64, G->rres))) return rc;
+        if ((rc = read_rel(G, &inf.rel_res_true))) return rc;
+        inf.iters = lr.iters;
+        inf.ir_steps = 1;
+        inf.rel_res_recursive = lr.rel_rec;
+        status = lr.status;
+    }
+    HIP_TRY(hipEventRecord(G->t1, G->stream));
+    HIP_TRY(hipEventSynchronize(G->t1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, G->t0, G->t1));
+    inf.ms = ms;
+    status = status_code(status);
+    inf.status = status;
+    if (info) *info = inf;
+    return status;
+}
+
+int mffv_cg_solve_f64(mffv_grid* G, const double* b, double* x, const mffv_opts* opts,
+                      mffv_info* info) {
+    int rc = check_grid(G, true);
+    if (rc) return rc;
+    if (!b || !x) return fail(MFFV_EINVAL, "NULL vector");
+    if (b == x) return fail(MFFV_EINVAL, "b and x must not alias");
+    mffv_opts o = resolve_opts(opts);
+    if ((rc = validate_opts(o))) return rc;
+    if (o.precision == MFFV_FP32)
+        return fail(MFFV_EINVAL, "mffv_cg_solve_f64 needs precision MFFV_FP64 or MFFV_FP32_IR");
+    if ((rc = set_device(G))) return rc;
+    mffv_info inf{};
+    const int64_t n = G->g.n;
+    HIP_TRY(hipEventRecord(G->t0, G->stream));
+    int status;
+    if (o.precision == MFFV_FP32_IR) {
+        if ((rc = ensure_x64(G))) return rc;
+        HIP_TRY(hipMemcpyAsync(G->x64, x, n * sizeof(double), hipMemcpyDeviceToDevice, G->stream));
+        status = solve_ir(G, b, 1, o, &inf);
+        if (status < 0) return status;
+        HIP_TRY(hipMemcpyAsync(x, G->x64, n * sizeof(double), hipMemcpyDeviceToDevice, G->stream));
+    } else {
+        if ((rc = ensure_ws64(G))) return rc;
+        HIP_TRY(hipMemcpyAsync(G->b64, b, n * sizeof(double), hipMemcpyDeviceToDevice, G->stream));
+        HIP_TRY(hipMemcpyAsync(G->x64, x, n * sizeof(double), hipMemcpyDeviceToDevice, G->stream));
+        LoopResult lr;
+        if ((rc = cg64(G, o.tol, o.max_iter, o, &lr))) return rc;
+        HIP_TRY(hipMemcpyAsync(x, G->x64, n * sizeof(double), hipMemcpyDeviceToDevice, G->stream));
+        if ((rc = true_residual_f64(G, b, 1, G->x64, G->rres))) return rc;
+        if ((rc = read_rel(G, &inf.rel_res_true))) return rc;
+        inf.iters = lr.iters;
+        inf.ir_steps = 1;
+        inf.rel_res_recursive = lr.rel_rec;
+        status = lr.status;
+    }
+    HIP_TRY(hipEventRecord(G->t1, G->stream));
+    HIP_TRY(hipEventSynchronize(G->t1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, G->t0, G->t1));
+    inf.ms = ms;
+    status = status_code(status);
+    inf.status = status;
+    if (info) *info = inf;
+    return status;
+}
+
+int mffv_copy_probe(void* dst, const void* src, size_t bytes, void* stream) {
+    if (!dst || !src) return fail(MFFV_EINVAL, "NULL pointer");
+    if (bytes % 16 || (uintptr_t)dst % 16 || (uintptr_t)src % 16)
+        return fail(MFFV_EINVAL, "copy probe needs 16-byte aligned pointers and sizes");
+    HIP_TRY(launch_copy_probe(src, dst, bytes, static_cast<hipStream_t>(stream)));
+    return MFFV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,10 @@
+#include "nn.hpp"
+
+namespace mffv {
+
+int nn_precondition(const mffv_net*, const Geom&, const float*, const float*, const uint8_t*,
+                    float*, CgState<float>*, hipStream_t) {
+    return MFFV_EINVAL;
+}
+
+}  // namespace mffv

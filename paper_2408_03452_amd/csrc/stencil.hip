@@ -1,0 +1,397 @@
+// Matrix-free TPFA stencil kernels: the apply of Eq. 6 / Alg. 2 (sign flipped,
+// plus the accumulation diagonal), the CG phase that fuses it with the
+// direction update, the deferred solution update and the p.Ap reduction
+// (Alg. 1), and the residual b - A x.
+//
+// Every kernel marches along x: a block owns a contiguous chunk of one plane
+// (kThreads*vec cells, z fastest) and walks through m.ci consecutive planes,
+// carrying the values of planes i-1, i, i+1 and the face Tx of plane i-1 in
+// registers, so each x-neighbour and x-face is read from memory once. The z
+// neighbours come from the adjacent lane by a cross-lane shuffle (only the
+// first and last lane of a wave load across a wave boundary), the y neighbours
+// are the rows +-nz of the same plane, which the chunk itself or the
+// neighbouring chunk of the same XCD has just read. Per cell the algorithmic
+// traffic of the apply is x, a, Tx, Ty, Tz in and y out: 24 bytes in FP32.
+#include "launch.hpp"
+
+#include <type_traits>
+
+namespace mffv {
+
+March plan_march(const Geom& g, int vec, int ci, int remap) {
+    March m;
+    m.vec = vec;
+    const int64_t per_block = (int64_t)kThreads * vec;
+    m.nchunk = (int)((g.plane + per_block - 1) / per_block);
+    if (ci <= 0) {
+        // default: enough blocks to give each CU several, but long marches
+        const int64_t target = 4096;
+        int64_t want = (int64_t)m.nchunk * g.nx / target;
+        ci = (int)(want < 1 ? 1 : (want > 64 ? 64 : want));
+        if (ci > g.nx) ci = g.nx;
+    }
+    m.ci = ci;
+    m.nich = (g.nx + ci - 1) / ci;
+    m.remap = remap;
+    return m;
+}
+
+namespace {
+
+__device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+__device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
+__device__ __forceinline__ float4 f4(float v) { return make_float4(v, v, v, v); }
+__device__ __forceinline__ float4 axpy4(float a, float4 x, float4 y) {
+    return make_float4(y.x + a * x.x, y.y + a * x.y, y.z + a * x.z, y.w + a * x.w);
+}
+
+// One cell of the eliminated operator in difference form:
+//   a x + sum over the six faces of T (x - x_nbr).
+template <class real, class creal>
+__device__ __forceinline__ real cell_op(creal a, real x, creal txp, real xxp, creal txm, real xxm,
+                                        creal typ, real xyp, creal tym, real xym, creal tzp,
+                                        real xzp, creal tzm, real xzm) {
+    real y = (real)a * x;
+    y += (real)txp * (x - xxp);
+    y += (real)txm * (x - xxm);
+    y += (real)typ * (x - xyp);
+    y += (real)tym * (x - xym);
+    y += (real)tzp * (x - xzp);
+    y += (real)tzm * (x - xzm);
+    return y;
+}
+
+// ---------------------------------------------------------------------------
+// FP32, four cells per thread along z (requires nz % 4 == 0).
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO<float> io, March m) {
+    __shared__ float red[kThreads / kWave];
+    __shared__ int lastflag;
+
+    int it = 0, pending = 0;
+    float beta = 0.f, alpha_prev = 0.f;
+    if (MODE == kFusedCg) {
+        if (io.st->done) return;  // the same for every block of the grid
+        it = io.st->iter;
+        beta = io.st->beta;
+        alpha_prev = io.st->alpha_prev;
+        pending = io.st->pending;
+    }
+    const float* pold = (it & 1) ? io.p0 : io.p1;
+    float* pnew = (it & 1) ? io.p1 : io.p0;
+    const bool use_pold = (MODE == kFusedCg) && it > 0;
+
+    const int b = m.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int pc = b % m.nchunk, ic = b / m.nchunk;
+    const int i0 = ic * m.ci;
+    const int i1 = min(g.nx, i0 + m.ci);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t P = g.plane;
+    const int64_t r0 = ((int64_t)pc * kThreads + threadIdx.x) * 4;
+    const bool valid = r0 < P;
+    int j = 0, k = 0;
+    if (valid) {
+        j = (int)(r0 / g.nz);
+        k = (int)(r0 - (int64_t)j * g.nz);
+    }
+    const bool hasjm = valid && j > 0;
+    const bool hasjp = valid && j + 1 < g.ny;
+    const bool haskm = valid && k > 0;
+    const bool haskp = valid && k + 4 < g.nz;
+    const int nz = g.nz;
+
+    // source value of the stencil: x, or r + beta p_old in the fused CG phase
+    auto S4 = [&](int64_t idx) -> float4 {
+        float4 v = ld4(io.src + idx);
+        if (use_pold) v = axpy4(beta, ld4(pold + idx), v);
+        return v;
+    };
+    auto S1 = [&](int64_t idx) -> float {
+        float v = io.src[idx];
+        if (use_pold) v += beta * pold[idx];
+        return v;
+    };
+
+    float4 sm = f4(0.f), sc = f4(0.f), sp = f4(0.f), txm = f4(0.f);
+    float4 poc = f4(0.f), pop = f4(0.f);  // p_old at own cells, planes i and i+1
+    float dot = 0.f;
+    int64_t base = (int64_t)i0 * P + r0;
+    if (valid && i0 < i1) {
+        if (use_pold) {
+            poc = ld4(pold + base);
+            sc = axpy4(beta, poc, ld4(io.src + base));
+        } else {
+            sc = ld4(io.src + base);
+        }
+        if (i0 > 0) {
+            sm = S4(base - P);
+            txm = ld4(c.tx + base - P);
+        } else {
+            sm = sc;
+        }
+    }
+    for (int i = i0; i < i1; ++i, base += P) {
+        float4 txc = f4(0.f), tyc = f4(0.f), tzc = f4(0.f), ac = f4(0.f), tyl = f4(0.f);
+        float4 sjm = sc, sjp = sc;
+        if (valid) {
+            if (i + 1 < g.nx) {
+                if (use_pold) {
+                    pop = ld4(pold + base + P);
+                    sp = axpy4(beta, pop, ld4(io.src + base + P));
+                } else {
+                    sp = ld4(io.src + base + P);
+                }
+            } else {
+                sp = sc;
+            }
+            txc = ld4(c.tx + base);
+            tyc = ld4(c.ty + base);
+            tzc = ld4(c.tz + base);
+            ac = ld4(c.a + base);
+            if (hasjm) {
+                tyl = ld4(c.ty + base - nz);
+                sjm = S4(base - nz);
+            }
+            if (hasjp) sjp = S4(base + nz);
+        }
+        // z neighbours across the float4 boundary from the adjacent lanes
+        float xl = __shfl_up(sc.w, 1, kWave);
+        float tzl = __shfl_up(tzc.w, 1, kWave);
+        float xr = __shfl_down(sc.x, 1, kWave);
+        if (valid) {
+            if (lane == 0 && haskm) {
+                xl = S1(base - 1);
+                tzl = c.tz[base - 1];
+            }
+            if (lane == kWave - 1 && haskp) xr = S1(base + 4);
+            if (!haskm) {
+                xl = sc.x;
+                tzl = 0.f;
+            }
+            if (!haskp) xr = sc.w;
+
+            float4 y;
+            y.x = cell_op<float, float>(ac.x, sc.x, txc.x, sp.x, txm.x, sm.x, tyc.x, sjp.x, tyl.x,
+                                        sjm.x, tzc.x, sc.y, tzl, xl);
+            y.y = cell_op<float, float>(ac.y, sc.y, txc.y, sp.y, txm.y, sm.y, tyc.y, sjp.y, tyl.y,
+                                        sjm.y, tzc.y, sc.z, tzc.x, sc.x);
+            y.z = cell_op<float, float>(ac.z, sc.z, txc.z, sp.z, txm.z, sm.z, tyc.z, sjp.z, tyl.z,
+                                        sjm.z, tzc.z, sc.w, tzc.y, sc.y);
+            y.w = cell_op<float, float>(ac.w, sc.w, txc.w, sp.w, txm.w, sm.w, tyc.w, sjp.w, tyl.w,
+                                        sjm.w, tzc.w, xr, tzc.z, sc.z);
+            if (MODE == kApply) {
+                st4(io.out + base, y);
+            } else if (MODE == kFusedCg) {
+                st4(pnew + base, sc);
+                st4(io.out + base, y);
+                if (pending) st4(io.xsol + base, axpy4(alpha_prev, poc, ld4(io.xsol + base)));
+                dot += sc.x * y.x + sc.y * y.y + sc.z * y.z + sc.w * y.w;
+            } else {  // residual r = b - A x
+                float4 bb;
+                if (io.rhs_f64) {
+                    const double* bd = static_cast<const double*>(io.rhs) + base;
+                    bb = make_float4((float)bd[0], (float)bd[1], (float)bd[2], (float)bd[3]);
+                } else {
+                    bb = ld4(static_cast<const float*>(io.rhs) + base);
+                }
+                st4(io.out + base, make_float4(bb.x - y.x, bb.y - y.y, bb.z - y.z, bb.w - y.w));
+            }
+        }
+        sm = sc;
+        sc = sp;
+        txm = txc;
+        poc = pop;
+    }
+
+    if (MODE == kFusedCg) {
+        const float tot = block_sum(dot, red);
+        if (threadIdx.x == 0) store_partial(io.partials + blockIdx.x, tot);
+        if (arrive_last(&io.st->cnt[0], gridDim.x, &lastflag)) {
+            const float pq = sum_partials(io.partials, (int)gridDim.x, red);
+            if (threadIdx.x == 0) {
+                CgState<float>* st = io.st;
+                st->pq = pq;
+                st->pending = 0;
+                if (!(pq > 0.f) || !isfinite(pq)) {
+                    st->alpha = 0.f;
+                    st->status = -4;
+                    st->done = 1;
+                } else {
+                    st->alpha = st->rho / pq;
+                }
+                reset_counter(&st->cnt[0]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One cell per thread (any nz; FP32 or FP64 vectors, FP32 coefficients).
+// ---------------------------------------------------------------------------
+template <class real, int MODE>
+__global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<real> io, March m) {
+    __shared__ real red[kThreads / kWave];
+    __shared__ int lastflag;
+
+    int it = 0, pending = 0;
+    real beta = 0, alpha_prev = 0;
+    if (MODE == kFusedCg) {
+        if (io.st->done) return;
+        it = io.st->iter;
+        beta = io.st->beta;
+        alpha_prev = io.st->alpha_prev;
+        pending = io.st->pending;
+    }
+    const real* pold = (it & 1) ? io.p0 : io.p1;
+    real* pnew = (it & 1) ? io.p1 : io.p0;
+    const bool use_pold = (MODE == kFusedCg) && it > 0;
+
+    const int b = m.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int pc = b % m.nchunk, ic = b / m.nchunk;
+    const int i0 = ic * m.ci;
+    const int i1 = min(g.nx, i0 + m.ci);
+    const int64_t P = g.plane;
+    const int64_t r0 = (int64_t)pc * kThreads + threadIdx.x;
+    const bool valid = r0 < P;
+    int j = 0, k = 0;
+    if (valid) {
+        j = (int)(r0 / g.nz);
+        k = (int)(r0 - (int64_t)j * g.nz);
+    }
+    const bool hasjm = j > 0, hasjp = j + 1 < g.ny, haskm = k > 0, haskp = k + 1 < g.nz;
+    const int nz = g.nz;
+
+    auto S = [&](int64_t idx) -> real {
+        real v = io.src[idx];
+        if (use_pold) v += beta * pold[idx];
+        return v;
+    };
+
+    real dot = 0;
+    if (valid && i0 < i1) {
+        int64_t base = (int64_t)i0 * P + r0;
+        real poc = use_pold ? pold[base] : real(0);
+        real sc = use_pold ? io.src[base] + beta * poc : io.src[base];
+        real sm = sc;
+        float txm = 0.f;
+        if (i0 > 0) {
+            sm = S(base - P);
+            txm = c.tx[base - P];
+        }
+        for (int i = i0; i < i1; ++i, base += P) {
+            real pop = 0, sp = sc;
+            if (i + 1 < g.nx) {
+                if (use_pold) {
+                    pop = pold[base + P];
+                    sp = io.src[base + P] + beta * pop;
+                } else {
+                    sp = io.src[base + P];
+                }
+            }
+            const float txc = c.tx[base], tyc = c.ty[base], tzc = c.tz[base];
+            const real ac = std::is_same<real, double>::value ? (real)c.a64[base] : (real)c.a[base];
+            float tyl = 0.f, tzl = 0.f;
+            real sjm = sc, sjp = sc, skm = sc, skp = sc;
+            if (hasjm) {
+                tyl = c.ty[base - nz];
+                sjm = S(base - nz);
+            }
+            if (hasjp) sjp = S(base + nz);
+            if (haskm) {
+                tzl = c.tz[base - 1];
+                skm = S(base - 1);
+            }
+            if (haskp) skp = S(base + 1);
+            const real y = ac * sc + cell_op<real, float>(0.f, sc, txc, sp, txm, sm, tyc, sjp, tyl, sjm, tzc,
+                                                skp, tzl, skm);
+            if (MODE == kApply) {
+                io.out[base] = y;
+            } else if (MODE == kFusedCg) {
+                pnew[base] = sc;
+                io.out[base] = y;
+                if (pending) io.xsol[base] += alpha_prev * poc;
+                dot += sc * y;
+            } else {
+                const real bb = io.rhs_f64 ? (real) static_cast<const double*>(io.rhs)[base]
+                                           : (real) static_cast<const float*>(io.rhs)[base];
+                const real r = bb - y;
+                io.out[base] = r;
+                dot += r * r;
+            }
+            sm = sc;
+            sc = sp;
+            txm = txc;
+            poc = pop;
+        }
+    }
+
+    if (MODE == kFusedCg || (MODE == kResidual && io.counter != nullptr)) {
+        const real tot = block_sum(dot, red);
+        if (threadIdx.x == 0) store_partial(io.partials + blockIdx.x, tot);
+        unsigned* cnt = (MODE == kFusedCg) ? &io.st->cnt[0] : io.counter;
+        if (arrive_last(cnt, gridDim.x, &lastflag)) {
+            const real s = sum_partials(io.partials, (int)gridDim.x, red);
+            if (threadIdx.x == 0) {
+                if (MODE == kFusedCg) {
+                    CgState<real>* st = io.st;
+                    st->pq = s;
+                    st->pending = 0;
+                    if (!(s > real(0)) || !isfinite(s)) {
+                        st->alpha = 0;
+                        st->status = -4;
+                        st->done = 1;
+                    } else {
+                        st->alpha = st->rho / s;
+                    }
+                } else if (io.sum_out) {
+                    *io.sum_out = s;
+                }
+                reset_counter(cnt);
+            }
+        }
+    }
+}
+
+template <class real, int MODE>
+hipError_t launch_s(const Geom& g, const Coef& c, const StencilIO<real>& io, const March& m,
+                    hipStream_t s) {
+    hipLaunchKernelGGL((stencil_s<real, MODE>), dim3(m.blocks()), dim3(kThreads), 0, s, g, c, io, m);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_v4(const Geom& g, const Coef& c, const StencilIO<float>& io, const March& m,
+                     hipStream_t s) {
+    hipLaunchKernelGGL((stencil_v4<MODE>), dim3(m.blocks()), dim3(kThreads), 0, s, g, c, io, m);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_stencil_f32(int mode, const Geom& g, const Coef& c, const StencilIO<float>& io,
+                              const March& m, hipStream_t s) {
+    if (m.vec == 4) {
+        switch (mode) {
+            case kApply: return launch_v4<kApply>(g, c, io, m, s);
+            case kFusedCg: return launch_v4<kFusedCg>(g, c, io, m, s);
+            default: return launch_v4<kResidual>(g, c, io, m, s);
+        }
+    }
+    switch (mode) {
+        case kApply: return launch_s<float, kApply>(g, c, io, m, s);
+        case kFusedCg: return launch_s<float, kFusedCg>(g, c, io, m, s);
+        default: return launch_s<float, kResidual>(g, c, io, m, s);
+    }
+}
+
+hipError_t launch_stencil_f64(int mode, const Geom& g, const Coef& c, const StencilIO<double>& io,
+                              const March& m, hipStream_t s) {
+    switch (mode) {
+        case kApply: return launch_s<double, kApply>(g, c, io, m, s);
+        case kFusedCg: return launch_s<double, kFusedCg>(g, c, io, m, s);
+        default: return launch_s<double, kResidual>(g, c, io, m, s);
+    }
+}
+
+}  // namespace mffv

@@ -1,0 +1,517 @@
+// Streaming kernels of the CG loop and its set-up: the residual update with
+// its dot products and the scalar recurrences of Alg. 1 (phase B), flexible-CG
+// dots, the final deferred solution update, operator set-up from the face
+// transmissibilities (Eq. 3 and 4) and small elementwise helpers.
+//
+// All reductions are deterministic: per-block partials, then the last block to
+// arrive sums them in a fixed order and updates the device-resident scalars.
+#include "launch.hpp"
+
+#include <cstring>
+
+namespace mffv {
+namespace {
+
+template <class real> struct VT;
+template <> struct VT<float> { using V = float4; static constexpr int W = 4; };
+template <> struct VT<double> { using V = double2; static constexpr int W = 2; };
+
+template <class real>
+__device__ __forceinline__ void ldv(const real* p, real (&v)[VT<real>::W]) {
+    typename VT<real>::V t = *reinterpret_cast<const typename VT<real>::V*>(p);
+    memcpy(v, &t, sizeof(t));
+}
+template <class real>
+__device__ __forceinline__ void stv(real* p, const real (&v)[VT<real>::W]) {
+    typename VT<real>::V t;
+    memcpy(&t, v, sizeof(t));
+    *reinterpret_cast<typename VT<real>::V*>(p) = t;
+}
+
+// ---------------------------------------------------------------------------
+// Phase B: r -= alpha q; r.r (and r.z) per block; the last block updates
+// beta, rho, the iteration count and the convergence flag.
+// ---------------------------------------------------------------------------
+template <class real, int MODE>
+__global__ __launch_bounds__(kThreads) void phase_b(int64_t n, VecIO<real> io) {
+    __shared__ real red[kThreads / kWave];
+    __shared__ int lastflag;
+    CgState<real>* st = io.st;
+    if (MODE != kBInit && st->done) return;
+    const real alpha = (MODE == kBInit) ? real(0) : st->alpha;
+    constexpr int W = VT<real>::W;
+    const int64_t nv = n / W;
+    real rr = 0, rz = 0, bb = 0;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+
+    auto one = [&](int64_t idx, real& r, real q) {
+        if (MODE != kBInit) r -= alpha * q;
+        rr += r * r;
+        if (MODE == kBJacobi || (MODE == kBInit && io.z != nullptr && io.dinv != nullptr)) {
+            const real z = (real)io.dinv[idx] * r;
+            io.z[idx] = z;
+            rz += r * z;
+        }
+        if (MODE == kBInit) {
+            if (!io.dmask[idx]) {
+                const real b = io.b_f64 ? (real) static_cast<const double*>(io.b)[idx]
+                                        : (real) static_cast<const float*>(io.b)[idx];
+                bb += b * b;
+            }
+        }
+    };
+
+    for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < nv; v += stride) {
+        const int64_t e = v * W;
+        real r[W], q[W];
+        ldv(io.r + e, r);
+        if (MODE != kBInit) ldv(io.q + e, q);
+#pragma unroll
+        for (int t = 0; t < W; ++t) one(e + t, r[t], MODE != kBInit ? q[t] : real(0));
+        if (MODE != kBInit) stv(io.r + e, r);
+    }
+    if (blockIdx.x == 0 && threadIdx.x < n - nv * W) {  // ragged tail
+        const int64_t e = nv * W + threadIdx.x;
+        real r = io.r[e];
+        one(e, r, MODE != kBInit ? io.q[e] : real(0));
+        if (MODE != kBInit) io.r[e] = r;
+    }
+
+    const int nb = gridDim.x;
+    real t0 = block_sum(rr, red);
+    real t1 = block_sum(rz, red);
+    real t2 = block_sum(bb, red);
+    if (threadIdx.x == 0) {
+        store_partial(io.partials + blockIdx.x, t0);
+        store_partial(io.partials + nb + blockIdx.x, t1);
+        store_partial(io.partials + 2 * nb + blockIdx.x, t2);
+    }
+    if (!arrive_last(&st->cnt[1], nb, &lastflag)) return;
+    const real srr = sum_partials(io.partials, nb, red);
+    const real srz = sum_partials(io.partials + nb, nb, red);
+    const real sbb = sum_partials(io.partials + 2 * nb, nb, red);
+    if (threadIdx.x != 0) return;
+    reset_counter(&st->cnt[1]);
+    st->rr = srr;
+    if (MODE == kBInit) {
+        const bool jac = io.z != nullptr && io.dinv != nullptr;
+        st->rho = jac ? srz : srr;
+        st->bnorm2 = sbb > real(0) ? sbb : srr;
+        st->thresh2 = io.tol2 * st->bnorm2;
+        st->max_iter = io.max_iter;
+        st->iter = 0;
+        st->alpha = 0;
+        st->alpha_prev = 0;
+        st->beta = 0;
+        st->pending = 0;
+        st->status = 0;
+        st->fallback = 0;
+        st->fallbacks = 0;
+        st->done = 0;
+        if (!isfinite(srr)) {
+            st->status = -4;
+            st->done = 1;
+        } else if (srr <= st->thresh2) {
+            st->done = 1;
+        }
+        return;
+    }
+    st->iter += 1;
+    st->alpha_prev = st->alpha;
+    st->pending = 1;
+    if (!isfinite(srr)) {
+        st->status = -4;
+        st->done = 1;
+    } else if (srr <= st->thresh2) {
+        st->done = 1;
+    } else if (st->iter >= st->max_iter) {
+        st->status = 1;
+        st->done = 1;
+    } else if (MODE == kBPlain) {
+        st->beta = srr / st->rho;
+        st->rho = srr;
+    } else if (MODE == kBJacobi) {
+        if (!(srz > real(0)) || !isfinite(srz)) {
+            st->status = -4;
+            st->done = 1;
+        } else {
+            st->beta = srz / st->rho;
+            st->rho = srz;
+        }
+    }
+}
+
+// Flexible CG: after the preconditioner wrote z = M(r), form z.r and z.q and
+// the Jacobi alternatives; beta = -(z.q)/(p.q) (the Polak-Ribiere beta of
+// Golub-Ye with r_{k+1} - r_k = -alpha q). If z.r <= 0 or is not finite the
+// iteration falls back to z = r / diag(A).
+template <class real>
+__global__ __launch_bounds__(kThreads) void flex_dots(int64_t n, VecIO<real> io) {
+    __shared__ real red[kThreads / kWave];
+    __shared__ int lastflag;
+    CgState<real>* st = io.st;
+    if (st->done) return;
+    const bool first = st->iter == 0;
+    real zr = 0, zq = 0, jr = 0, jq = 0;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
+        const real r = io.r[e], z = io.z[e], d = (real)io.dinv[e];
+        zr += z * r;
+        jr += d * r * r;
+        if (!first) {
+            const real q = io.q[e];
+            zq += z * q;
+            jq += d * r * q;
+        }
+    }
+    const int nb = gridDim.x;
+    real a0 = block_sum(zr, red), a1 = block_sum(zq, red), a2 = block_sum(jr, red),
+         a3 = block_sum(jq, red);
+    if (threadIdx.x == 0) {
+        store_partial(io.partials + blockIdx.x, a0);
+        store_partial(io.partials + nb + blockIdx.x, a1);
+        store_partial(io.partials + 2 * nb + blockIdx.x, a2);
+        store_partial(io.partials + 3 * nb + blockIdx.x, a3);
+    }
+    if (!arrive_last(&st->cnt[2], nb, &lastflag)) return;
+    const real szr = sum_partials(io.partials, nb, red);
+    const real szq = sum_partials(io.partials + nb, nb, red);
+    const real sjr = sum_partials(io.partials + 2 * nb, nb, red);
+    const real sjq = sum_partials(io.partials + 3 * nb, nb, red);
+    if (threadIdx.x != 0) return;
+    reset_counter(&st->cnt[2]);
+    const bool ok = (szr > real(0)) && isfinite(szr) && isfinite(szq);
+    st->fallback = ok ? 0 : 1;
+    if (!ok) st->fallbacks += 1;
+    const real rho = ok ? szr : sjr, zq_ = ok ? szq : sjq;
+    st->rho = rho;
+    st->zq = zq_;
+    st->beta = first ? real(0) : -zq_ / st->pq;
+    if (!(rho > real(0)) || !isfinite(rho)) {
+        st->status = -4;
+        st->done = 1;
+    }
+}
+
+template <class real>
+__global__ void fallback_fix(int64_t n, VecIO<real> io) {
+    if (io.st->done || !io.st->fallback) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
+        io.z[e] = (real)io.dinv[e] * io.r[e];
+}
+
+template <class real>
+__global__ void finalize(int64_t n, real* x, const real* p0, const real* p1, CgState<real>* st) {
+    if (!st->pending) return;
+    const real* p = ((st->iter - 1) & 1) ? p1 : p0;
+    const real a = st->alpha_prev;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
+        x[e] += a * p[e];
+}
+
+__global__ void clear_pending_f32(CgState<float>* st) { st->pending = 0; }
+__global__ void clear_pending_f64(CgState<double>* st) { st->pending = 0; }
+
+template <class real, class breal>
+__global__ void copy_dirichlet(int64_t n, const uint8_t* dmask, const breal* b, real* x) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
+        if (dmask[e]) x[e] = (real)b[e];
+}
+
+template <class vreal>
+__global__ __launch_bounds__(kThreads) void masked_norm2(int64_t n, const uint8_t* dmask,
+                                                         const vreal* v, double* partials,
+                                                         unsigned* counter, double* out) {
+    __shared__ double red[kThreads / kWave];
+    __shared__ int lastflag;
+    double s = 0;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride)
+        if (!dmask[e]) {
+            const double t = (double)v[e];
+            s += t * t;
+        }
+    const double tot = block_sum(s, red);
+    if (threadIdx.x == 0) store_partial(partials + blockIdx.x, tot);
+    if (!arrive_last(counter, gridDim.x, &lastflag)) return;
+    const double all = sum_partials(partials, (int)gridDim.x, red);
+    if (threadIdx.x == 0) {
+        *out = all;
+        reset_counter(counter);
+    }
+}
+
+__global__ void scale_to_f32(int64_t n, const double* r64, const double* norm2, float* r32) {
+    const double inv = 1.0 / sqrt(*norm2);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
+        r32[e] = (float)(r64[e] * inv);
+}
+
+__global__ void axpy_f64_from_f32(int64_t n, const double* norm2, const float* d, double* x) {
+    const double s = sqrt(*norm2);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
+        x[e] += s * (double)d[e];
+}
+
+template <class A, class B>
+__global__ void convert(int64_t n, const A* a, B* b) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
+        b[e] = (B)a[e];
+}
+
+__global__ void fill_f32(int64_t n, float* a, float v) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) a[e] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void copy_probe(const uint4* __restrict__ src,
+                                                       uint4* __restrict__ dst, int64_t n16) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n16; e += stride)
+        dst[e] = src[e];
+}
+
+// ---------------------------------------------------------------------------
+// Operator set-up.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double harmonic(double ka, double kb) { return 2.0 * ka * kb / (ka + kb); }
+
+__global__ void perm_to_trans(Geom g, const double* __restrict__ k, double kz_ratio, float* tx,
+                              float* ty, float* tz) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < g.n; l += stride) {
+        const int i = (int)(l / g.plane);
+        const int64_t rem = l - (int64_t)i * g.plane;
+        const int j = (int)(rem / g.nz);
+        const int kk = (int)(rem - (int64_t)j * g.nz);
+        const double kc = k[l];
+        tx[l] = (i + 1 < g.nx) ? (float)harmonic(kc, k[l + g.plane]) : 0.f;
+        ty[l] = (j + 1 < g.ny) ? (float)harmonic(kc, k[l + g.nz]) : 0.f;
+        tz[l] = (kk + 1 < g.nz) ? (float)(kz_ratio * harmonic(kc, k[l + 1])) : 0.f;
+    }
+}
+
+__device__ __forceinline__ bool is_dirichlet(const Geom& g, const uint8_t* dmask, int64_t l, int i) {
+    return dmask ? dmask[l] != 0 : (i == 0 || i == g.nx - 1);
+}
+
+__device__ __forceinline__ bool bad_face(float t) { return !(t >= 0.f) || !isfinite(t); }
+
+__global__ __launch_bounds__(kThreads) void setup_kernel(Geom g, SetupIn in, SetupOut out) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    int badT = 0, badC = 0, badP = 0, anyC = 0;
+    for (int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x; l < g.n; l += stride) {
+        const int i = (int)(l / g.plane);
+        const int64_t rem = l - (int64_t)i * g.plane;
+        const int j = (int)(rem / g.nz);
+        const int k = (int)(rem - (int64_t)j * g.nz);
+        const bool D = is_dirichlet(g, in.dmask, l, i);
+        // the six faces of the cell: T and whether the neighbour is a Dirichlet cell
+        float t[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        bool nd[6] = {false, false, false, false, false, false};
+        int64_t nb[6] = {0, 0, 0, 0, 0, 0};
+        if (i + 1 < g.nx) { t[0] = in.tx[l]; nb[0] = l + g.plane; nd[0] = is_dirichlet(g, in.dmask, nb[0], i + 1); }
+        if (i > 0)        { t[1] = in.tx[l - g.plane]; nb[1] = l - g.plane; nd[1] = is_dirichlet(g, in.dmask, nb[1], i - 1); }
+        if (j + 1 < g.ny) { t[2] = in.ty[l]; nb[2] = l + g.nz; nd[2] = is_dirichlet(g, in.dmask, nb[2], i); }
+        if (j > 0)        { t[3] = in.ty[l - g.nz]; nb[3] = l - g.nz; nd[3] = is_dirichlet(g, in.dmask, nb[3], i); }
+        if (k + 1 < g.nz) { t[4] = in.tz[l]; nb[4] = l + 1; nd[4] = is_dirichlet(g, in.dmask, nb[4], i); }
+        if (k > 0)        { t[5] = in.tz[l - 1]; nb[5] = l - 1; nd[5] = is_dirichlet(g, in.dmask, nb[5], i); }
+        // validate the faces this cell owns (+x, +y, +z)
+        if ((i + 1 < g.nx && bad_face(t[0])) || (j + 1 < g.ny && bad_face(t[2])) ||
+            (k + 1 < g.nz && bad_face(t[4])))
+            badT = 1;
+        const float cl = in.accum ? in.accum[l] : in.accum_scalar;
+        if (!(cl >= 0.f) || !isfinite(cl)) badC = 1;
+        if (!D && cl > 0.f) anyC = 1;
+        out.dmask[l] = D ? 1 : 0;
+        // faces kept in the device copy: both cells unknown
+        out.tx[l] = (!D && i + 1 < g.nx && !nd[0]) ? t[0] : 0.f;
+        out.ty[l] = (!D && j + 1 < g.ny && !nd[2]) ? t[2] : 0.f;
+        out.tz[l] = (!D && k + 1 < g.nz && !nd[4]) ? t[4] : 0.f;
+        if (D) {
+            const float pd = in.pd ? in.pd[l] : (i == 0 ? 1.f : 0.f);
+            if (!isfinite(pd)) badP = 1;
+            out.a[l] = 1.f;
+            out.a64[l] = 1.0;
+            out.dinv[l] = 1.f;
+            if (out.b) out.b[l] = pd;
+        } else {
+            double diag = (double)cl, to_d = (double)cl, bsum = 0.0;
+            for (int f = 0; f < 6; ++f) {
+                diag += (double)t[f];
+                if (nd[f]) {
+                    to_d += (double)t[f];
+                    const int ni = (f == 0) ? i + 1 : (f == 1 ? i - 1 : i);
+                    const float pd = in.pd ? in.pd[nb[f]] : (ni == 0 ? 1.f : 0.f);
+                    bsum += (double)t[f] * (double)pd;
+                }
+            }
+            out.a[l] = (float)to_d;
+            out.a64[l] = to_d;
+            out.dinv[l] = (float)(1.0 / diag);
+            if (out.b) out.b[l] = (float)bsum;
+        }
+    }
+    // one atomic per block and flag
+    badT = __syncthreads_or(badT);
+    badC = __syncthreads_or(badC);
+    badP = __syncthreads_or(badP);
+    anyC = __syncthreads_or(anyC);
+    if (threadIdx.x == 0) {
+        if (badT) atomicOr(&out.flags[0], 1);
+        if (badC) atomicOr(&out.flags[1], 1);
+        if (badP) atomicOr(&out.flags[2], 1);
+        if (anyC) atomicOr(&out.flags[4], 1);
+    }
+}
+
+// number of Dirichlet cells (exact count, one atomic per block)
+__global__ __launch_bounds__(kThreads) void count_dirichlet(int64_t n, const uint8_t* dmask, int* out) {
+    __shared__ int red[kThreads / kWave];
+    int c = 0;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) c += dmask[e] ? 1 : 0;
+    const int tot = block_sum(c, red);
+    if (threadIdx.x == 0 && tot) atomicAdd(out, tot);
+}
+
+int grid_for(int64_t n, int per_thread = 1, int cap = 8192) {
+    int64_t b = (n / per_thread + kThreads - 1) / kThreads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+}  // namespace
+
+hipError_t launch_phase_b_f32(int mode, int64_t n, const VecIO<float>& io, int nb, hipStream_t s) {
+    switch (mode) {
+        case kBInit: hipLaunchKernelGGL((phase_b<float, kBInit>), dim3(nb), dim3(kThreads), 0, s, n, io); break;
+        case kBPlain: hipLaunchKernelGGL((phase_b<float, kBPlain>), dim3(nb), dim3(kThreads), 0, s, n, io); break;
+        case kBJacobi: hipLaunchKernelGGL((phase_b<float, kBJacobi>), dim3(nb), dim3(kThreads), 0, s, n, io); break;
+        default: hipLaunchKernelGGL((phase_b<float, kBFlex>), dim3(nb), dim3(kThreads), 0, s, n, io); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_phase_b_f64(int mode, int64_t n, const VecIO<double>& io, int nb, hipStream_t s) {
+    switch (mode) {
+        case kBInit: hipLaunchKernelGGL((phase_b<double, kBInit>), dim3(nb), dim3(kThreads), 0, s, n, io); break;
+        case kBPlain: hipLaunchKernelGGL((phase_b<double, kBPlain>), dim3(nb), dim3(kThreads), 0, s, n, io); break;
+        case kBJacobi: hipLaunchKernelGGL((phase_b<double, kBJacobi>), dim3(nb), dim3(kThreads), 0, s, n, io); break;
+        default: hipLaunchKernelGGL((phase_b<double, kBFlex>), dim3(nb), dim3(kThreads), 0, s, n, io); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_flex_dots_f32(int64_t n, const VecIO<float>& io, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((flex_dots<float>), dim3(nb), dim3(kThreads), 0, s, n, io);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((fallback_fix<float>), dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, io);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_f32(int64_t n, float* x, float* p0, float* p1, CgState<float>* st,
+                               hipStream_t s) {
+    hipLaunchKernelGGL((finalize<float>), dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, x, p0, p1, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(clear_pending_f32, dim3(1), dim3(1), 0, s, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_f64(int64_t n, double* x, double* p0, double* p1, CgState<double>* st,
+                               hipStream_t s) {
+    hipLaunchKernelGGL((finalize<double>), dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, x, p0, p1, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(clear_pending_f64, dim3(1), dim3(1), 0, s, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_dirichlet_f32(int64_t n, const uint8_t* dmask, const float* b, float* x,
+                                     hipStream_t s) {
+    hipLaunchKernelGGL((copy_dirichlet<float, float>), dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, dmask, b, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_dirichlet_f64(int64_t n, const uint8_t* dmask, const void* b, int b_f64,
+                                     double* x, hipStream_t s) {
+    if (b_f64)
+        hipLaunchKernelGGL((copy_dirichlet<double, double>), dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, dmask,
+                           static_cast<const double*>(b), x);
+    else
+        hipLaunchKernelGGL((copy_dirichlet<double, float>), dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, dmask,
+                           static_cast<const float*>(b), x);
+    return hipGetLastError();
+}
+
+hipError_t launch_masked_norm2(int64_t n, const uint8_t* dmask, const void* v, int v_f64,
+                               double* partials, unsigned* counter, double* out, int nb,
+                               hipStream_t s) {
+    if (v_f64)
+        hipLaunchKernelGGL((masked_norm2<double>), dim3(nb), dim3(kThreads), 0, s, n, dmask,
+                           static_cast<const double*>(v), partials, counter, out);
+    else
+        hipLaunchKernelGGL((masked_norm2<float>), dim3(nb), dim3(kThreads), 0, s, n, dmask,
+                           static_cast<const float*>(v), partials, counter, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_to_f32(int64_t n, const double* r64, const double* norm2, float* r32,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(scale_to_f32, dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, r64, norm2, r32);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_f64_from_f32(int64_t n, const double* norm2, const float* d, double* x,
+                                    hipStream_t s) {
+    hipLaunchKernelGGL(axpy_f64_from_f32, dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, norm2, d, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_f32_to_f64(int64_t n, const float* a, double* b, hipStream_t s) {
+    hipLaunchKernelGGL((convert<float, double>), dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, a, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_f64_to_f32(int64_t n, const double* a, float* b, hipStream_t s) {
+    hipLaunchKernelGGL((convert<double, float>), dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, a, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(int64_t n, float* a, float v, hipStream_t s) {
+    hipLaunchKernelGGL(fill_f32, dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, a, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s) {
+    const int64_t n16 = (int64_t)(bytes / 16);
+    hipLaunchKernelGGL(copy_probe, dim3(grid_for(n16, 4, 16384)), dim3(kThreads), 0, s,
+                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_perm_to_trans(const Geom& g, const double* k, double kz_ratio, float* tx,
+                                float* ty, float* tz, hipStream_t s) {
+    hipLaunchKernelGGL(perm_to_trans, dim3(grid_for(g.n, 4)), dim3(kThreads), 0, s, g, k, kz_ratio, tx, ty, tz);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup(const Geom& g, const SetupIn& in, const SetupOut& out, hipStream_t s) {
+    hipLaunchKernelGGL(setup_kernel, dim3(grid_for(g.n, 4)), dim3(kThreads), 0, s, g, in, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(count_dirichlet, dim3(grid_for(g.n, 16, 4096)), dim3(kThreads), 0, s, g.n,
+                       (const uint8_t*)out.dmask, out.flags + 3);
+    return hipGetLastError();
+}
+
+}  // namespace mffv

@@ -1,0 +1,252 @@
+"""Python binding of libmffv (ctypes): the C entry points under the same names.
+
+Only argument marshalling happens here: tensors become device pointers, the
+torch stream becomes a ``hipStream_t``, negative return codes become
+:class:`MffvError`. Every step of the solver runs in the HIP library, which
+must have been built (``paper_2408_03452_amd.build``); importing a missing or
+broken library raises immediately instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads the HIP runtime that libmffv then shares
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmffv.so")
+
+OK = 0
+NOT_CONVERGED = 1
+EINVAL = -1
+ENOMEM = -2
+EHIP = -3
+EBREAKDOWN = -4
+ESTATE = -5
+
+FP32, FP64, FP32_IR = 0, 1, 2
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_LEARNED = 0, 1, 2
+
+
+class MffvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mffv error {code}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("precision", ctypes.c_int), ("precond", ctypes.c_int),
+                ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
+                ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("net", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("ir_steps", ctypes.c_int),
+                ("fallbacks", ctypes.c_int), ("rel_res_recursive", ctypes.c_double),
+                ("rel_res_true", ctypes.c_double), ("ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_P = ctypes.c_void_p
+
+
+def _declare(lib):
+    sig = {
+        "mffv_version": (ctypes.c_char_p, []),
+        "mffv_last_error": (ctypes.c_char_p, []),
+        "mffv_default_opts": (None, [ctypes.POINTER(Opts)]),
+        "mffv_create_grid": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _P,
+                                            ctypes.POINTER(_P)]),
+        "mffv_destroy_grid": (None, [_P]),
+        "mffv_perm_to_trans": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _P,
+                                              ctypes.c_double, _P, _P, _P, _P]),
+        "mffv_set_transmissibility": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_float, _P, _P,
+                                                     _P]),
+        "mffv_apply": (ctypes.c_int, [_P, _P, _P]),
+        "mffv_apply_f64": (ctypes.c_int, [_P, _P, _P]),
+        "mffv_true_residual": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
+        "mffv_cg_solve": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(Opts), ctypes.POINTER(Info)]),
+        "mffv_cg_solve_f64": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(Opts),
+                                             ctypes.POINTER(Info)]),
+        "mffv_cg_solve_batched": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int,
+                                                 ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                                 ctypes.POINTER(Opts), ctypes.POINTER(Info)]),
+        "mffv_copy_probe": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+def lib():
+    """The loaded libmffv (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2408_03452_amd.build` (hipcc, gfx950)")
+        _lib = _declare(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def version() -> str:
+    return lib().mffv_version().decode()
+
+
+def last_error() -> str:
+    return lib().mffv_last_error().decode()
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise MffvError(rc, last_error())
+    return rc
+
+
+def _ptr(t, dtype=None, n=None, name="array"):
+    """Device pointer of a tensor (or None / int passthrough)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, got {t.numel()}")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    lib().mffv_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Grid:
+    """Owning wrapper of an ``mffv_grid*``."""
+
+    def __init__(self, handle: int, shape, stream_ptr: int):
+        self.handle = handle
+        self.shape = tuple(shape)
+        self.n = shape[0] * shape[1] * shape[2]
+        self.stream_ptr = stream_ptr
+
+    def close(self):
+        if self.handle:
+            lib().mffv_destroy_grid(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def create_grid(nx: int, ny: int, nz: int, stream=None) -> Grid:
+    h = _P()
+    s = _stream(stream)
+    _check(lib().mffv_create_grid(nx, ny, nz, s, ctypes.byref(h)))
+    return Grid(h.value, (nx, ny, nz), s)
+
+
+def destroy_grid(grid: Grid) -> None:
+    grid.close()
+
+
+def perm_to_trans(nx, ny, nz, k, kz_ratio, tx, ty, tz, stream=None) -> None:
+    n = nx * ny * nz
+    _check(lib().mffv_perm_to_trans(nx, ny, nz, _ptr(k, torch.float64, n, "k"), kz_ratio,
+                                    _ptr(tx, torch.float32, n, "tx"),
+                                    _ptr(ty, torch.float32, n, "ty"),
+                                    _ptr(tz, torch.float32, n, "tz"), _stream(stream)))
+
+
+def set_transmissibility(grid: Grid, tx, ty, tz, accum=None, accum_scalar=0.0, dmask=None,
+                         pD=None, b_out=None) -> None:
+    n = grid.n
+    _check(lib().mffv_set_transmissibility(
+        grid.handle, _ptr(tx, torch.float32, n, "tx"), _ptr(ty, torch.float32, n, "ty"),
+        _ptr(tz, torch.float32, n, "tz"), _ptr(accum, torch.float32, n, "accum"),
+        float(accum_scalar), _ptr(dmask, torch.uint8, n, "dmask"),
+        _ptr(pD, torch.float32, n, "pD"), _ptr(b_out, torch.float32, n, "b_out")))
+
+
+def apply(grid: Grid, x, y) -> None:
+    _check(lib().mffv_apply(grid.handle, _ptr(x, torch.float32, grid.n, "x"),
+                            _ptr(y, torch.float32, grid.n, "y")))
+
+
+def apply_f64(grid: Grid, x, y) -> None:
+    _check(lib().mffv_apply_f64(grid.handle, _ptr(x, torch.float64, grid.n, "x"),
+                                _ptr(y, torch.float64, grid.n, "y")))
+
+
+def true_residual(grid: Grid, b, x, r_out=None) -> float:
+    rel = ctypes.c_double()
+    _check(lib().mffv_true_residual(grid.handle, _ptr(b, torch.float32, grid.n, "b"),
+                                    _ptr(x, torch.float64, grid.n, "x"),
+                                    _ptr(r_out, torch.float64, grid.n, "r_out"),
+                                    ctypes.byref(rel)))
+    return rel.value
+
+
+def cg_solve(grid: Grid, b, x, opts: Opts | None = None):
+    """Returns (status, info dict); raises MffvError on errors."""
+    info = Info()
+    rc = lib().mffv_cg_solve(grid.handle, _ptr(b, torch.float32, grid.n, "b"),
+                             _ptr(x, torch.float32, grid.n, "x"),
+                             ctypes.byref(opts) if opts is not None else None, ctypes.byref(info))
+    return _check(rc), info.as_dict()
+
+
+def cg_solve_f64(grid: Grid, b, x, opts: Opts | None = None):
+    info = Info()
+    rc = lib().mffv_cg_solve_f64(grid.handle, _ptr(b, torch.float64, grid.n, "b"),
+                                 _ptr(x, torch.float64, grid.n, "x"),
+                                 ctypes.byref(opts) if opts is not None else None,
+                                 ctypes.byref(info))
+    return _check(rc), info.as_dict()
+
+
+def cg_solve_batched(grids, b, x, opts: Opts | None = None):
+    """Solve len(grids) systems in one launch; returns (status, [info dict])."""
+    ns = len(grids)
+    if len(b) != ns or len(x) != ns:
+        raise ValueError("grids, b and x must have the same length")
+    G = (_P * ns)(*[g.handle for g in grids])
+    B = (_P * ns)(*[_ptr(bb, torch.float32, g.n, "b") for bb, g in zip(b, grids)])
+    X = (_P * ns)(*[_ptr(xx, torch.float32, g.n, "x") for xx, g in zip(x, grids)])
+    infos = (Info * ns)()
+    rc = lib().mffv_cg_solve_batched(G, ns, B, X, ctypes.byref(opts) if opts is not None else None,
+                                     infos)
+    return _check(rc), [i.as_dict() for i in infos]
+
+
+def copy_probe(dst, src, nbytes: int, stream=None) -> None:
+    _check(lib().mffv_copy_probe(_ptr(dst), _ptr(src), nbytes, _stream(stream)))

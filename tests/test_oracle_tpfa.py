@@ -171,3 +171,18 @@ def test_dense_solve_4cube_and_relative_residual():
     assert tpfa.relative_residual(A, b, p, dmask) < 1e-15
     # the full-grid system has the same solution (identity rows carry p^D)
     assert np.allclose(np.linalg.solve(A.toarray(), b), p, rtol=0, atol=1e-14)
+
+
+def test_slicing_apply_matches_assembled_operator():
+    shape = (6, 5, 7)
+    rng = np.random.default_rng(12)
+    k = lognormal_iid(shape, 2.0, 13)
+    tx, ty, tz = tpfa.transmissibility(k, kz_ratio=0.25)
+    c = rng.uniform(0, 1e-2, shape)
+    dmask, pd = tpfa.x_plane_dirichlet(shape)
+    dmask[2, 1, 3] = True          # an interior Dirichlet cell as well
+    A, _ = tpfa.assemble(tx, ty, tz, c, dmask, pd)
+    for _ in range(3):
+        x = rng.normal(size=shape)
+        y = tpfa.apply_stencil(tx, ty, tz, c, dmask, x).ravel()
+        assert np.allclose(y, A @ x.ravel(), rtol=1e-14, atol=1e-14)
