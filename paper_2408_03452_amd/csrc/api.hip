@@ -85,13 +85,15 @@ struct mffv_grid {
     double *r64 = nullptr, *p064 = nullptr, *p164 = nullptr, *q64 = nullptr, *x64 = nullptr,
            *b64 = nullptr, *rres = nullptr;
     CgState<double>* st64 = nullptr;
-    // reductions and small device scalars
-    double* part = nullptr;  // partials, 4 * max_blocks doubles
+    // per-block partial sums (stored as doubles, used as floats by FP32 kernels)
+    double* partA = nullptr;  // phase A: p.q, max_blocks
+    double* partB = nullptr;  // phase B / init: r.r, r.z, ||b_U||^2, 3 * nb_vec
+    double* partF = nullptr;  // flexible CG dots, 4 * nb_vec
+    double* partR = nullptr;  // residual and norm reductions, max_blocks
     int max_blocks = 0;
-    unsigned* cnt = nullptr;  // 4 counters
     double* dscal = nullptr;  // [0] ||b_U||^2, [1] ||r||^2
-    // pinned host mirror of the loop flags, double-buffered
-    int* hflags = nullptr;
+    // pinned host mirror of the loop state, double-buffered
+    char* hstate = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t t0 = nullptr, t1 = nullptr;
     // launch shapes
@@ -173,12 +175,11 @@ int true_residual_f64(mffv_grid* G, const void* b, int b_f64, const double* x, d
     io.out = r;
     io.rhs = b;
     io.rhs_f64 = b_f64;
-    io.partials = G->part;
-    io.sum_out = G->dscal + 1;
-    io.counter = G->cnt + 0;
+    io.partials = G->partR;
     HIP_TRY(launch_stencil_f64(kResidual, G->g, coef_of(G), io, G->m64, G->stream));
-    HIP_TRY(launch_masked_norm2(G->g.n, G->dmask, b, b_f64, G->part + G->max_blocks, G->cnt + 1,
-                                G->dscal + 0, G->nb_vec, G->stream));
+    HIP_TRY(launch_sum_partials(G->partR, G->m64.blocks(), G->dscal + 1, G->stream));
+    HIP_TRY(launch_masked_norm2(G->g.n, G->dmask, b, b_f64, G->partR, G->dscal + 0, G->nb_vec,
+                                G->stream));
     return MFFV_OK;
 }
 
@@ -201,14 +202,24 @@ struct LoopResult {
 // Enqueue one CG iteration (phase A, phase B, and for flexible CG the
 // preconditioner and its dots).
 int enqueue_iter32(mffv_grid* G, int precond, const mffv_net* net) {
+    float* pa = reinterpret_cast<float*>(G->partA);
+    float* pb = reinterpret_cast<float*>(G->partB);
+    float* pf = reinterpret_cast<float*>(G->partF);
     StencilIO<float> a;
     a.src = (precond == MFFV_PRECOND_NONE) ? G->r : G->z;
     a.p0 = G->p0;
     a.p1 = G->p1;
     a.out = G->q;
     a.xsol = G->xw;
-    a.partials = reinterpret_cast<float*>(G->part);
+    a.partials = pa;
     a.st = G->st32;
+    a.pb = pb;
+    a.nb_b = G->nb_vec;
+    a.pf = pf;
+    a.nb_f = G->nb_vec;
+    a.precond = precond;
+    a.dinv = G->dinv;
+    a.rres = G->r;
     HIP_TRY(launch_stencil_f32(kFusedCg, G->g, coef_of(G), a, G->m32, G->stream));
     VecIO<float> v;
     v.r = G->r;
@@ -216,35 +227,44 @@ int enqueue_iter32(mffv_grid* G, int precond, const mffv_net* net) {
     v.z = G->z;
     v.dinv = G->dinv;
     v.dmask = G->dmask;
-    v.partials = reinterpret_cast<float*>(G->part);
+    v.partials = pb;
+    v.pa = pa;
+    v.nb_a = G->m32.blocks();
     v.st = G->st32;
     const int mode = precond == MFFV_PRECOND_NONE ? kBPlain
                      : precond == MFFV_PRECOND_JACOBI ? kBJacobi : kBFlex;
     HIP_TRY(launch_phase_b_f32(mode, G->g.n, v, G->nb_vec, G->stream));
     if (precond == MFFV_PRECOND_LEARNED) {
-        int rc = nn_precondition(net, G->g, G->r, G->dinv, G->dmask, G->z, G->st32, G->stream);
+        int rc = nn_precondition(net, G->g, G->r, G->dinv, G->dmask, G->z, pb, G->nb_vec, G->st32,
+                                 G->stream);
         if (rc) return rc;
-        HIP_TRY(launch_flex_dots_f32(G->g.n, v, G->nb_vec, G->stream));
+        VecIO<float> f = v;
+        f.partials = pf;
+        HIP_TRY(launch_flex_dots_f32(G->g.n, f, G->nb_vec, G->stream));
     }
     return MFFV_OK;
 }
 
 int enqueue_iter64(mffv_grid* G, int precond) {
+    if (precond != MFFV_PRECOND_NONE) return fail(MFFV_EINVAL, "FP64 CG supports precond NONE only");
     StencilIO<double> a;
     a.src = G->r64;
     a.p0 = G->p064;
     a.p1 = G->p164;
     a.out = G->q64;
     a.xsol = G->x64;
-    a.partials = G->part;
+    a.partials = G->partA;
     a.st = G->st64;
-    if (precond != MFFV_PRECOND_NONE) return fail(MFFV_EINVAL, "FP64 CG supports precond NONE only");
+    a.pb = G->partB;
+    a.nb_b = G->nb_vec;
     HIP_TRY(launch_stencil_f64(kFusedCg, G->g, coef_of(G), a, G->m64, G->stream));
     VecIO<double> v;
     v.r = G->r64;
     v.q = G->q64;
     v.dmask = G->dmask;
-    v.partials = G->part;
+    v.partials = G->partB;
+    v.pa = G->partA;
+    v.nb_a = G->m64.blocks();
     v.st = G->st64;
     HIP_TRY(launch_phase_b_f64(kBPlain, G->g.n, v, G->nb_vec, G->stream));
     return MFFV_OK;
@@ -283,23 +303,24 @@ int enqueue_chunk(mffv_grid* G, CgGraph& graph, int chunk, bool use_graph, F&& o
     return MFFV_OK;
 }
 
-// Run the CG loop until the device flag says stop. State layout: iter, done,
-// status, pending are consecutive ints in CgState.
+// Run the CG loop until the device flag says stop: enqueue chunk c, copy the
+// state to pinned memory behind it, then wait for the copy of chunk c-1.
 template <class State, class F>
 int drive_loop(mffv_grid* G, State* st, int max_iter, int chunk, CgGraph& graph, bool use_graph,
                F&& one_iter) {
+    static_assert(sizeof(State) <= 256, "state mirror too small");
     const int max_chunks = max_iter / chunk + 3;
-    int c = 0;
     bool stop = false;
-    for (; c < max_chunks && !stop; ++c) {
+    for (int c = 0; c < max_chunks && !stop; ++c) {
         int rc = enqueue_chunk(G, graph, chunk, use_graph, one_iter);
         if (rc) return rc;
-        HIP_TRY(hipMemcpyAsync(G->hflags + 4 * (c & 1), &st->iter, 4 * sizeof(int),
+        HIP_TRY(hipMemcpyAsync(G->hstate + 256 * (c & 1), st, sizeof(State),
                                hipMemcpyDeviceToHost, G->stream));
         HIP_TRY(hipEventRecord(G->ev[c & 1], G->stream));
         if (c >= 1) {
             HIP_TRY(hipEventSynchronize(G->ev[(c - 1) & 1]));
-            if (G->hflags[4 * ((c - 1) & 1) + 1]) stop = true;
+            const State* hs = reinterpret_cast<const State*>(G->hstate + 256 * ((c - 1) & 1));
+            if (hs->done) stop = true;
         }
     }
     HIP_TRY(hipStreamSynchronize(G->stream));
@@ -319,23 +340,25 @@ int cg32(mffv_grid* G, double tol, int max_iter, int precond, const mffv_opts& o
         io.rhs = G->bw;
         HIP_TRY(launch_stencil_f32(kResidual, G->g, coef_of(G), io, G->m32, G->stream));
     }
+    float* pb = reinterpret_cast<float*>(G->partB);
     VecIO<float> v;
     v.r = G->r;
-    v.z = (precond == MFFV_PRECOND_JACOBI) ? G->z : nullptr;
-    v.dinv = (precond == MFFV_PRECOND_JACOBI) ? G->dinv : nullptr;
+    v.z = G->z;
+    v.dinv = G->dinv;
+    v.jacobi = precond == MFFV_PRECOND_JACOBI ? 1 : 0;
     v.dmask = G->dmask;
     v.b = G->bw;
-    v.partials = reinterpret_cast<float*>(G->part);
+    v.partials = pb;
     v.st = G->st32;
     v.tol2 = (float)(tol * tol);
     v.max_iter = max_iter;
     HIP_TRY(launch_phase_b_f32(kBInit, G->g.n, v, G->nb_vec, G->stream));
     if (precond == MFFV_PRECOND_LEARNED) {
-        int rc = nn_precondition(net, G->g, G->r, G->dinv, G->dmask, G->z, G->st32, G->stream);
+        int rc = nn_precondition(net, G->g, G->r, G->dinv, G->dmask, G->z, pb, G->nb_vec, G->st32,
+                                 G->stream);
         if (rc) return rc;
         VecIO<float> f = v;
-        f.z = G->z;
-        f.dinv = G->dinv;
+        f.partials = reinterpret_cast<float*>(G->partF);
         HIP_TRY(launch_flex_dots_f32(G->g.n, f, G->nb_vec, G->stream));
     }
     const int chunk = std::max(1, o.check_every);
@@ -347,11 +370,10 @@ int cg32(mffv_grid* G, double tol, int max_iter, int precond, const mffv_opts& o
     CgState<float> hs;
     HIP_TRY(hipMemcpyAsync(&hs, G->st32, sizeof(hs), hipMemcpyDeviceToHost, G->stream));
     HIP_TRY(hipStreamSynchronize(G->stream));
-    out->iters = hs.iter;
-    out->status = hs.status;
+    out->iters = hs.iters;
+    out->status = hs.done ? hs.status : MFFV_NOT_CONVERGED;
     out->fallbacks = hs.fallbacks;
     out->rel_rec = hs.bnorm2 > 0 ? std::sqrt((double)hs.rr / (double)hs.bnorm2) : 0.0;
-    if (hs.status == 0 && !hs.done) out->status = MFFV_NOT_CONVERGED;
     return MFFV_OK;
 }
 
@@ -371,7 +393,7 @@ int cg64(mffv_grid* G, double tol, int max_iter, const mffv_opts& o, LoopResult*
     v.dmask = G->dmask;
     v.b = G->b64;
     v.b_f64 = 1;
-    v.partials = G->part;
+    v.partials = G->partB;
     v.st = G->st64;
     v.tol2 = tol * tol;
     v.max_iter = max_iter;
@@ -385,10 +407,9 @@ int cg64(mffv_grid* G, double tol, int max_iter, const mffv_opts& o, LoopResult*
     CgState<double> hs;
     HIP_TRY(hipMemcpyAsync(&hs, G->st64, sizeof(hs), hipMemcpyDeviceToHost, G->stream));
     HIP_TRY(hipStreamSynchronize(G->stream));
-    out->iters = hs.iter;
-    out->status = hs.status;
+    out->iters = hs.iters;
+    out->status = hs.done ? hs.status : MFFV_NOT_CONVERGED;
     out->rel_rec = hs.bnorm2 > 0 ? std::sqrt(hs.rr / hs.bnorm2) : 0.0;
-    if (hs.status == 0 && !hs.done) out->status = MFFV_NOT_CONVERGED;
     return MFFV_OK;
 }
 
@@ -515,20 +536,21 @@ int mffv_create_grid(int nx, int ny, int nz, void* stream, mffv_grid** out) {
     const int vec = (nz % 4 == 0) ? 4 : 1;
     G->m32 = plan_march(G->g, vec, 0, 1);
     G->m64 = plan_march(G->g, 1, 0, 1);
-    G->nb_vec = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (n / 4 + kThreads - 1) / kThreads));
+    G->nb_vec = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n / 4 + kThreads - 1) / kThreads));
     G->max_blocks = std::max({G->m32.blocks(), G->m64.blocks(), G->nb_vec});
     if ((rc = dalloc(&G->a, n)) || (rc = dalloc(&G->a64, n)) || (rc = dalloc(&G->tx, n)) || (rc = dalloc(&G->ty, n)) ||
         (rc = dalloc(&G->tz, n)) || (rc = dalloc(&G->dinv, n)) || (rc = dalloc(&G->dmask, n)) ||
-        (rc = dalloc(&G->flags, 8)) || (rc = dalloc(&G->part, 4 * (size_t)G->max_blocks)) ||
-        (rc = dalloc(&G->cnt, 4)) || (rc = dalloc(&G->dscal, 8))) {
+        (rc = dalloc(&G->flags, 8)) || (rc = dalloc(&G->partA, (size_t)G->max_blocks)) ||
+        (rc = dalloc(&G->partB, 3 * (size_t)G->nb_vec)) ||
+        (rc = dalloc(&G->partF, 4 * (size_t)G->nb_vec)) ||
+        (rc = dalloc(&G->partR, (size_t)G->max_blocks)) || (rc = dalloc(&G->dscal, 8))) {
         mffv_destroy_grid(G);
         return rc;
     }
-    if ((e = hipHostMalloc(reinterpret_cast<void**>(&G->hflags), 8 * sizeof(int), 0)) != hipSuccess ||
+    if ((e = hipHostMalloc(reinterpret_cast<void**>(&G->hstate), 512, 0)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&G->ev[0], hipEventDisableTiming)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&G->ev[1], hipEventDisableTiming)) != hipSuccess ||
         (e = hipEventCreate(&G->t0)) != hipSuccess || (e = hipEventCreate(&G->t1)) != hipSuccess ||
-        (e = hipMemsetAsync(G->cnt, 0, 4 * sizeof(unsigned), G->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(G->stream)) != hipSuccess) {
         mffv_destroy_grid(G);
         return hip_fail(e, "grid set-up");
@@ -543,12 +565,13 @@ void mffv_destroy_grid(mffv_grid* G) {
     (void)hipStreamSynchronize(G->stream);
     drop_graphs(G);
     dfree(G->a); dfree(G->a64); dfree(G->tx); dfree(G->ty); dfree(G->tz); dfree(G->dinv); dfree(G->dmask);
-    dfree(G->flags); dfree(G->part); dfree(G->cnt); dfree(G->dscal);
+    dfree(G->flags); dfree(G->partA); dfree(G->partB); dfree(G->partF); dfree(G->partR);
+    dfree(G->dscal);
     dfree(G->r); dfree(G->p0); dfree(G->p1); dfree(G->q); dfree(G->z); dfree(G->xw);
     dfree(G->bw); dfree(G->st32);
     dfree(G->r64); dfree(G->p064); dfree(G->p164); dfree(G->q64); dfree(G->x64); dfree(G->b64);
     dfree(G->rres); dfree(G->st64);
-    if (G->hflags) (void)hipHostFree(G->hflags);
+    if (G->hstate) (void)hipHostFree(G->hstate);
     for (auto& e : G->ev)
         if (e) (void)hipEventDestroy(e);
     if (G->t0) (void)hipEventDestroy(G->t0);

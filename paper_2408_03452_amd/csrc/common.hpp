@@ -39,27 +39,32 @@ struct Coef {
 };
 
 // Scalars of one CG run, resident on the device between kernels so that the
-// host never sits between two iterations.
+// host never sits between two iterations. No kernel reduces its own partial
+// sums: every block of the consuming kernel sums the producer's per-block
+// partials in the same fixed order, so all blocks reach the same scalars
+// without atomics or cross-XCD fences, and block 0 records them here for the
+// kernels and the host that come later. Fields written while other blocks of
+// the same kernel read the state are double-buffered by iteration parity.
 template <class real>
 struct CgState {
-    real rho;         // r.z of the current residual (r.r for plain CG)
-    real rr;          // r.r of the current residual
-    real alpha;       // step of the current iteration
-    real alpha_prev;  // step of the previous iteration (deferred x update)
-    real beta;        // direction update of the current iteration
-    real pq;          // p.Ap of the current iteration
-    real thresh2;     // (tol * ||b_U||)^2
-    real zq;          // flexible CG: z_{k+1}.q_k
-    real bnorm2;      // ||b_U||^2
-    int iter;         // completed iterations
+    real rho[2];      // rho[k&1] = r_k.z_k (r_k.r_k for plain CG), written by phase A_k
+    real alpha[2];    // alpha[k&1] = step of iteration k, written by phase B_k
+    real pq[2];       // pq[k&1] = p_k.A p_k, written by phase B_k
+    real rr;          // r.r at the last convergence check
+    real beta;        // last direction update (for inspection)
+    real thresh2;     // (tol * ||b_U||)^2, fixed by phase A_0
+    real bnorm2;      // ||b_U||^2, fixed by phase A_0
+    real tol2;        // tol^2, set by the init kernel
+    int iterA;        // index k of the next phase A (written by phase B)
+    int iterB;        // index k of the next phase B (written by phase A)
     int done;         // 1 once converged, broken down or out of iterations
     int status;       // 0 ok, 1 not converged, -4 breakdown
-    int pending;      // 1 while x still lacks alpha_prev * p_prev
+    int iters;        // completed iterations at exit
+    int tail;         // 1 if x still lacks alpha_{iters-1} p_{iters-1} at exit
     int max_iter;
-    int fallback;     // flexible CG: this iteration uses the Jacobi z
+    int fallback;     // flexible CG: iteration iterA uses the Jacobi z
     int fallbacks;    // flexible CG: count of such iterations
-    int pad;
-    unsigned cnt[4];  // arrival counters of the last-block reductions
+    int pad[3];
 };
 
 // Map the hardware block index to a logical work index so that each XCD gets
@@ -92,43 +97,28 @@ __device__ __forceinline__ T block_sum(T v, T* lds /* kThreads/kWave entries */)
     return s;
 }
 
-// Publish one value per block; returns true in exactly one block, the last to
-// arrive, after which every block's value is visible to it. Partial values go
-// through agent-scope atomics so that they are coherent across the XCD L2s.
-template <class T>
-__device__ __forceinline__ void store_partial(T* slot, T v) {
-    __hip_atomic_store(slot, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <class T>
-__device__ __forceinline__ T load_partial(const T* slot) {
-    return __hip_atomic_load(const_cast<T*>(slot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned nblocks, int* flag_lds) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-        *flag_lds = (prev == nblocks - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    const bool last = *flag_lds != 0;
-    if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return last;
-}
-
-// Sum nparts partial values in a fixed order (strided per thread, then the
-// block tree): the result is bitwise reproducible for a given launch shape.
+// Sum nparts partial values written by an earlier kernel, in a fixed order
+// (strided per thread, then the block tree): every block that calls it gets
+// the same bits, and the result is reproducible for a given launch shape.
 template <class T>
 __device__ __forceinline__ T sum_partials(const T* parts, int nparts, T* lds) {
     T s = T(0);
-    for (int i = threadIdx.x; i < nparts; i += kThreads) s += load_partial(parts + i);
+    for (int i = threadIdx.x; i < nparts; i += kThreads) s += parts[i];
     return block_sum(s, lds);
 }
 
-__device__ __forceinline__ void reset_counter(unsigned* counter) {
-    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ bool first_thread() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
+// Read a flag once per block (thread 0) and share it through LDS, so that all
+// waves of the block take the same branch even if another block of the same
+// kernel sets the flag meanwhile.
+__device__ __forceinline__ bool block_flag(const int* flag) {
+    __shared__ int v;
+    if (threadIdx.x == 0) v = *flag;
+    __syncthreads();
+    const bool r = v != 0;
+    __syncthreads();
+    return r;
 }
 
 }  // namespace mffv

@@ -22,17 +22,22 @@ March plan_march(const Geom& g, int vec, int ci, int remap);
 // Vectors and scalars a stencil kernel works on.
 template <class real>
 struct StencilIO {
-    const real* src = nullptr;   // apply/residual: x; fused CG: r (or z when preconditioned)
-    real* p0 = nullptr;          // fused CG: direction buffers, chosen by iteration parity
+    const real* src = nullptr;   // apply/residual: x; fused CG: r (z when preconditioned)
+    real* p0 = nullptr;          // fused CG: direction buffers, p_k in p0 for even k, p1 for odd k
     real* p1 = nullptr;
     real* out = nullptr;         // apply: y; fused CG: q = A p; residual: r = b - A x
     real* xsol = nullptr;        // fused CG: solution, receives the deferred update
     const void* rhs = nullptr;   // residual: b
     int rhs_f64 = 0;             // residual: b is FP64
-    real* partials = nullptr;    // per-block partial dot products
+    real* partials = nullptr;    // per-block partial sums written by this kernel (p.q, or r.r)
     CgState<real>* st = nullptr; // fused CG: device scalars
-    real* sum_out = nullptr;     // residual: ||r||^2 written by the last block (may be null)
-    unsigned* counter = nullptr; // residual: arrival counter
+    const real* pb = nullptr;    // fused CG: partials of the previous phase B, [3][nb_b]
+    int nb_b = 0;
+    const real* pf = nullptr;    // flexible CG: partials of the preconditioner dots, [4][nb_f]
+    int nb_f = 0;
+    int precond = 0;             // 0 none, 1 Jacobi, 2 flexible
+    const float* dinv = nullptr; // flexible CG: Jacobi fallback z = dinv * r
+    const real* rres = nullptr;  // flexible CG: r (for the fallback)
 };
 
 enum StencilMode { kApply = 0, kFusedCg = 1, kResidual = 2 };
@@ -42,7 +47,8 @@ hipError_t launch_stencil_f32(int mode, const Geom& g, const Coef& c, const Sten
 hipError_t launch_stencil_f64(int mode, const Geom& g, const Coef& c, const StencilIO<double>& io,
                               const March& m, hipStream_t s);
 
-// Phase B of an iteration: r -= alpha q, dot products, scalar updates.
+// Phase B of an iteration: alpha from the phase-A partials, r -= alpha q,
+// per-block partial dots for the next phase A.
 enum PhaseBMode { kBInit = 0, kBPlain = 1, kBJacobi = 2, kBFlex = 3 };
 
 template <class real>
@@ -54,30 +60,37 @@ struct VecIO {
     const uint8_t* dmask = nullptr;
     const void* b = nullptr;       // init: right-hand side (for ||b_U||)
     int b_f64 = 0;
-    real* partials = nullptr;      // [3][nblocks]
+    real* partials = nullptr;      // this kernel's partials: [3][nblocks] (init/B) or [4][nblocks] (flex)
+    const real* pa = nullptr;      // partials of the phase A before (p.q), nb_a of them
+    int nb_a = 0;
+    const real* pb = nullptr;      // flexible dots: partials of the phase B before (r.r)
+    int nb_b = 0;
     CgState<real>* st = nullptr;
     real tol2 = 0;                 // init: tol^2
     int max_iter = 0;              // init: iteration cap
+    int jacobi = 0;                // init: also form z = dinv r and r.z
 };
 
 hipError_t launch_phase_b_f32(int mode, int64_t n, const VecIO<float>& io, int nblocks, hipStream_t s);
 hipError_t launch_phase_b_f64(int mode, int64_t n, const VecIO<double>& io, int nblocks, hipStream_t s);
-// Flexible CG: dots z.r and z.q of the new z, beta, and the Jacobi safeguard.
+// Flexible CG: partial dots z.r, z.q and their Jacobi counterparts of the new z.
 hipError_t launch_flex_dots_f32(int64_t n, const VecIO<float>& io, int nblocks, hipStream_t s);
-// x += alpha_prev * p_prev once the loop has stopped.
-hipError_t launch_finalize_f32(int64_t n, float* x, float* p0, float* p1, CgState<float>* st,
-                               hipStream_t s);
-hipError_t launch_finalize_f64(int64_t n, double* x, double* p0, double* p1, CgState<double>* st,
-                               hipStream_t s);
+// x += alpha_{k-1} p_{k-1} once the loop has stopped, if still owed.
+hipError_t launch_finalize_f32(int64_t n, float* x, const float* p0, const float* p1,
+                               const CgState<float>* st, hipStream_t s);
+hipError_t launch_finalize_f64(int64_t n, double* x, const double* p0, const double* p1,
+                               const CgState<double>* st, hipStream_t s);
+// out[0] = sum of n partials (one block, fixed order).
+hipError_t launch_sum_partials(const double* parts, int n, double* out, hipStream_t s);
 
 // Elementwise helpers.
 hipError_t launch_copy_dirichlet_f32(int64_t n, const uint8_t* dmask, const float* b, float* x,
                                      hipStream_t s);
 hipError_t launch_copy_dirichlet_f64(int64_t n, const uint8_t* dmask, const void* b, int b_f64,
                                      double* x, hipStream_t s);
+// ||v_U||^2 into *out (per-block partials, then one summing block).
 hipError_t launch_masked_norm2(int64_t n, const uint8_t* dmask, const void* v, int v_f64,
-                               double* partials, unsigned* counter, double* out, int nblocks,
-                               hipStream_t s);
+                               double* partials, double* out, int nblocks, hipStream_t s);
 hipError_t launch_scale_to_f32(int64_t n, const double* r64, const double* scale, float* r32,
                                hipStream_t s);
 hipError_t launch_axpy_f64_from_f32(int64_t n, const double* scale, const float* d, double* x,

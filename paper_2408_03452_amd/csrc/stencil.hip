@@ -61,26 +61,99 @@ __device__ __forceinline__ real cell_op(creal a, real x, creal txp, real xxp, cr
     return y;
 }
 
+// Start of phase A_k of the fused CG loop. Every block sums the partials of
+// the kernels before it (phase B: r.r, r.z, and at k = 0 ||b_U||^2; flexible
+// CG: the preconditioner dots) in the same order, tests convergence on r_k and
+// forms beta_{k-1}; block 0 records the scalars. Returns false, identically in
+// every block, once the loop is over.
+template <class real>
+struct PhaseA {
+    int k;
+    real beta;        // beta_{k-1}
+    real alpha_prev;  // alpha_{k-1}: the deferred solution update
+    bool fallback;    // flexible CG: this iteration uses z = r / diag(A)
+};
+
+template <class real>
+__device__ bool phase_a_start(const StencilIO<real>& io, real* lds, PhaseA<real>& o) {
+    CgState<real>* st = io.st;
+    if (block_flag(&st->done)) return false;
+    const int k = st->iterA;
+    const real rr = sum_partials(io.pb, io.nb_b, lds);
+    real rho = rr, zq = 0;
+    bool fallback = false;
+    if (io.precond == 1) {
+        rho = sum_partials(io.pb + io.nb_b, io.nb_b, lds);
+    } else if (io.precond == 2) {
+        const real zr = sum_partials(io.pf, io.nb_f, lds);
+        const real zqv = sum_partials(io.pf + io.nb_f, io.nb_f, lds);
+        const real jr = sum_partials(io.pf + 2 * io.nb_f, io.nb_f, lds);
+        const real jq = sum_partials(io.pf + 3 * io.nb_f, io.nb_f, lds);
+        fallback = !(zr > real(0)) || !isfinite(zr) || !isfinite(zqv);
+        rho = fallback ? jr : zr;
+        zq = fallback ? jq : zqv;
+    }
+    real thresh2 = st->thresh2, bnorm2 = st->bnorm2;
+    if (k == 0) {
+        const real bb = sum_partials(io.pb + 2 * io.nb_b, io.nb_b, lds);
+        bnorm2 = bb > real(0) ? bb : rr;
+        thresh2 = st->tol2 * bnorm2;
+    }
+    const bool conv = isfinite(rr) && rr <= thresh2;
+    const bool bad = !conv && (!isfinite(rr) || (io.precond != 0 && (!(rho > real(0)) || !isfinite(rho))));
+    const bool cap = k >= st->max_iter;
+    if (conv || bad || cap) {
+        if (first_thread()) {
+            st->done = 1;
+            st->status = conv ? 0 : (bad ? -4 : 1);
+            st->iters = k;
+            st->tail = k >= 1 ? 1 : 0;
+            st->rr = rr;
+            if (k == 0) {
+                st->thresh2 = thresh2;
+                st->bnorm2 = bnorm2;
+            }
+        }
+        return false;
+    }
+    o.k = k;
+    o.fallback = fallback;
+    o.alpha_prev = k >= 1 ? st->alpha[(k - 1) & 1] : real(0);
+    o.beta = k == 0 ? real(0)
+                    : (io.precond == 2 ? -zq / st->pq[(k - 1) & 1] : rho / st->rho[(k - 1) & 1]);
+    if (first_thread()) {
+        st->rho[k & 1] = rho;
+        st->iterB = k;
+        st->rr = rr;
+        st->beta = o.beta;
+        st->fallback = fallback ? 1 : 0;
+        if (fallback) st->fallbacks += 1;
+        if (k == 0) {
+            st->thresh2 = thresh2;
+            st->bnorm2 = bnorm2;
+        }
+    }
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 // FP32, four cells per thread along z (requires nz % 4 == 0).
 // ---------------------------------------------------------------------------
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO<float> io, March m) {
     __shared__ float red[kThreads / kWave];
-    __shared__ int lastflag;
 
-    int it = 0, pending = 0;
-    float beta = 0.f, alpha_prev = 0.f;
-    if (MODE == kFusedCg) {
-        if (io.st->done) return;  // the same for every block of the grid
-        it = io.st->iter;
-        beta = io.st->beta;
-        alpha_prev = io.st->alpha_prev;
-        pending = io.st->pending;
-    }
+    PhaseA<float> ph{0, 0.f, 0.f, false};
+    if (MODE == kFusedCg && !phase_a_start(io, red, ph)) return;
+    const int it = ph.k;
+    const float beta = ph.beta, alpha_prev = ph.alpha_prev;
+    const bool pending = it > 0;
     const float* pold = (it & 1) ? io.p0 : io.p1;
     float* pnew = (it & 1) ? io.p1 : io.p0;
     const bool use_pold = (MODE == kFusedCg) && it > 0;
+    // flexible CG fallback: the source is r / diag(A) instead of the network's z
+    const bool jz = (MODE == kFusedCg) && ph.fallback;
+    const float* zsrc = jz ? io.rres : io.src;
 
     const int b = m.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int pc = b % m.nchunk, ic = b / m.nchunk;
@@ -102,13 +175,22 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
     const int nz = g.nz;
 
     // source value of the stencil: x, or r + beta p_old in the fused CG phase
+    auto Z4 = [&](int64_t idx) -> float4 {
+        float4 v = ld4(zsrc + idx);
+        if (jz) {
+            const float4 d = ld4(io.dinv + idx);
+            v = make_float4(v.x * d.x, v.y * d.y, v.z * d.z, v.w * d.w);
+        }
+        return v;
+    };
     auto S4 = [&](int64_t idx) -> float4 {
-        float4 v = ld4(io.src + idx);
+        float4 v = Z4(idx);
         if (use_pold) v = axpy4(beta, ld4(pold + idx), v);
         return v;
     };
     auto S1 = [&](int64_t idx) -> float {
-        float v = io.src[idx];
+        float v = zsrc[idx];
+        if (jz) v *= io.dinv[idx];
         if (use_pold) v += beta * pold[idx];
         return v;
     };
@@ -120,9 +202,9 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
     if (valid && i0 < i1) {
         if (use_pold) {
             poc = ld4(pold + base);
-            sc = axpy4(beta, poc, ld4(io.src + base));
+            sc = axpy4(beta, poc, Z4(base));
         } else {
-            sc = ld4(io.src + base);
+            sc = Z4(base);
         }
         if (i0 > 0) {
             sm = S4(base - P);
@@ -138,9 +220,9 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
             if (i + 1 < g.nx) {
                 if (use_pold) {
                     pop = ld4(pold + base + P);
-                    sp = axpy4(beta, pop, ld4(io.src + base + P));
+                    sp = axpy4(beta, pop, Z4(base + P));
                 } else {
-                    sp = ld4(io.src + base + P);
+                    sp = Z4(base + P);
                 }
             } else {
                 sp = sc;
@@ -206,23 +288,7 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
 
     if (MODE == kFusedCg) {
         const float tot = block_sum(dot, red);
-        if (threadIdx.x == 0) store_partial(io.partials + blockIdx.x, tot);
-        if (arrive_last(&io.st->cnt[0], gridDim.x, &lastflag)) {
-            const float pq = sum_partials(io.partials, (int)gridDim.x, red);
-            if (threadIdx.x == 0) {
-                CgState<float>* st = io.st;
-                st->pq = pq;
-                st->pending = 0;
-                if (!(pq > 0.f) || !isfinite(pq)) {
-                    st->alpha = 0.f;
-                    st->status = -4;
-                    st->done = 1;
-                } else {
-                    st->alpha = st->rho / pq;
-                }
-                reset_counter(&st->cnt[0]);
-            }
-        }
+        if (threadIdx.x == 0) io.partials[blockIdx.x] = tot;
     }
 }
 
@@ -232,20 +298,17 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
 template <class real, int MODE>
 __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<real> io, March m) {
     __shared__ real red[kThreads / kWave];
-    __shared__ int lastflag;
 
-    int it = 0, pending = 0;
-    real beta = 0, alpha_prev = 0;
-    if (MODE == kFusedCg) {
-        if (io.st->done) return;
-        it = io.st->iter;
-        beta = io.st->beta;
-        alpha_prev = io.st->alpha_prev;
-        pending = io.st->pending;
-    }
+    PhaseA<real> ph{0, real(0), real(0), false};
+    if (MODE == kFusedCg && !phase_a_start(io, red, ph)) return;
+    const int it = ph.k;
+    const real beta = ph.beta, alpha_prev = ph.alpha_prev;
+    const bool pending = it > 0;
     const real* pold = (it & 1) ? io.p0 : io.p1;
     real* pnew = (it & 1) ? io.p1 : io.p0;
     const bool use_pold = (MODE == kFusedCg) && it > 0;
+    const bool jz = (MODE == kFusedCg) && ph.fallback;
+    const real* zsrc = jz ? io.rres : io.src;
 
     const int b = m.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int pc = b % m.nchunk, ic = b / m.nchunk;
@@ -262,8 +325,13 @@ __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<
     const bool hasjm = j > 0, hasjp = j + 1 < g.ny, haskm = k > 0, haskp = k + 1 < g.nz;
     const int nz = g.nz;
 
+    auto Z = [&](int64_t idx) -> real {
+        real v = zsrc[idx];
+        if (jz) v *= (real)io.dinv[idx];
+        return v;
+    };
     auto S = [&](int64_t idx) -> real {
-        real v = io.src[idx];
+        real v = Z(idx);
         if (use_pold) v += beta * pold[idx];
         return v;
     };
@@ -272,7 +340,7 @@ __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<
     if (valid && i0 < i1) {
         int64_t base = (int64_t)i0 * P + r0;
         real poc = use_pold ? pold[base] : real(0);
-        real sc = use_pold ? io.src[base] + beta * poc : io.src[base];
+        real sc = use_pold ? Z(base) + beta * poc : Z(base);
         real sm = sc;
         float txm = 0.f;
         if (i0 > 0) {
@@ -284,9 +352,9 @@ __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<
             if (i + 1 < g.nx) {
                 if (use_pold) {
                     pop = pold[base + P];
-                    sp = io.src[base + P] + beta * pop;
+                    sp = Z(base + P) + beta * pop;
                 } else {
-                    sp = io.src[base + P];
+                    sp = Z(base + P);
                 }
             }
             const float txc = c.tx[base], tyc = c.ty[base], tzc = c.tz[base];
@@ -303,8 +371,8 @@ __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<
                 skm = S(base - 1);
             }
             if (haskp) skp = S(base + 1);
-            const real y = ac * sc + cell_op<real, float>(0.f, sc, txc, sp, txm, sm, tyc, sjp, tyl, sjm, tzc,
-                                                skp, tzl, skm);
+            const real y = ac * sc + cell_op<real, float>(0.f, sc, txc, sp, txm, sm, tyc, sjp, tyl,
+                                                          sjm, tzc, skp, tzl, skm);
             if (MODE == kApply) {
                 io.out[base] = y;
             } else if (MODE == kFusedCg) {
@@ -326,30 +394,9 @@ __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<
         }
     }
 
-    if (MODE == kFusedCg || (MODE == kResidual && io.counter != nullptr)) {
+    if (MODE == kFusedCg || (MODE == kResidual && io.partials != nullptr)) {
         const real tot = block_sum(dot, red);
-        if (threadIdx.x == 0) store_partial(io.partials + blockIdx.x, tot);
-        unsigned* cnt = (MODE == kFusedCg) ? &io.st->cnt[0] : io.counter;
-        if (arrive_last(cnt, gridDim.x, &lastflag)) {
-            const real s = sum_partials(io.partials, (int)gridDim.x, red);
-            if (threadIdx.x == 0) {
-                if (MODE == kFusedCg) {
-                    CgState<real>* st = io.st;
-                    st->pq = s;
-                    st->pending = 0;
-                    if (!(s > real(0)) || !isfinite(s)) {
-                        st->alpha = 0;
-                        st->status = -4;
-                        st->done = 1;
-                    } else {
-                        st->alpha = st->rho / s;
-                    }
-                } else if (io.sum_out) {
-                    *io.sum_out = s;
-                }
-                reset_counter(cnt);
-            }
-        }
+        if (threadIdx.x == 0) io.partials[blockIdx.x] = tot;
     }
 }
 

@@ -29,16 +29,37 @@ __device__ __forceinline__ void stv(real* p, const real (&v)[VT<real>::W]) {
 }
 
 // ---------------------------------------------------------------------------
-// Phase B: r -= alpha q; r.r (and r.z) per block; the last block updates
-// beta, rho, the iteration count and the convergence flag.
+// Phase B_k: alpha_k from the phase-A partials (summed by every block), then
+// r -= alpha_k q with the per-block partials r.r (and r.z) that phase A_{k+1}
+// consumes. The init mode forms the partials of r_0 (and ||b_U||^2) and
+// resets the loop state.
 // ---------------------------------------------------------------------------
 template <class real, int MODE>
 __global__ __launch_bounds__(kThreads) void phase_b(int64_t n, VecIO<real> io) {
     __shared__ real red[kThreads / kWave];
-    __shared__ int lastflag;
     CgState<real>* st = io.st;
-    if (MODE != kBInit && st->done) return;
-    const real alpha = (MODE == kBInit) ? real(0) : st->alpha;
+    real alpha = 0;
+    if (MODE != kBInit) {
+        if (block_flag(&st->done)) return;
+        const int k = st->iterB;
+        const real pq = sum_partials(io.pa, io.nb_a, red);
+        if (!(pq > real(0)) || !isfinite(pq)) {
+            if (first_thread()) {
+                st->done = 1;
+                st->status = -4;
+                st->iters = k;
+                st->tail = 0;
+            }
+            return;
+        }
+        alpha = st->rho[k & 1] / pq;
+        if (first_thread()) {
+            st->alpha[k & 1] = alpha;
+            st->pq[k & 1] = pq;
+            st->iterA = k + 1;
+        }
+    }
+    const bool jac = (MODE == kBJacobi) || (MODE == kBInit && io.jacobi);
     constexpr int W = VT<real>::W;
     const int64_t nv = n / W;
     real rr = 0, rz = 0, bb = 0;
@@ -47,17 +68,15 @@ __global__ __launch_bounds__(kThreads) void phase_b(int64_t n, VecIO<real> io) {
     auto one = [&](int64_t idx, real& r, real q) {
         if (MODE != kBInit) r -= alpha * q;
         rr += r * r;
-        if (MODE == kBJacobi || (MODE == kBInit && io.z != nullptr && io.dinv != nullptr)) {
+        if (jac) {
             const real z = (real)io.dinv[idx] * r;
             io.z[idx] = z;
             rz += r * z;
         }
-        if (MODE == kBInit) {
-            if (!io.dmask[idx]) {
-                const real b = io.b_f64 ? (real) static_cast<const double*>(io.b)[idx]
-                                        : (real) static_cast<const float*>(io.b)[idx];
-                bb += b * b;
-            }
+        if (MODE == kBInit && !io.dmask[idx]) {
+            const real b = io.b_f64 ? (real) static_cast<const double*>(io.b)[idx]
+                                    : (real) static_cast<const float*>(io.b)[idx];
+            bb += b * b;
         }
     };
 
@@ -78,80 +97,41 @@ __global__ __launch_bounds__(kThreads) void phase_b(int64_t n, VecIO<real> io) {
     }
 
     const int nb = gridDim.x;
-    real t0 = block_sum(rr, red);
-    real t1 = block_sum(rz, red);
-    real t2 = block_sum(bb, red);
+    const real t0 = block_sum(rr, red);
+    const real t1 = block_sum(rz, red);
+    const real t2 = block_sum(bb, red);
     if (threadIdx.x == 0) {
-        store_partial(io.partials + blockIdx.x, t0);
-        store_partial(io.partials + nb + blockIdx.x, t1);
-        store_partial(io.partials + 2 * nb + blockIdx.x, t2);
+        io.partials[blockIdx.x] = t0;
+        io.partials[nb + blockIdx.x] = t1;
+        io.partials[2 * nb + blockIdx.x] = t2;
     }
-    if (!arrive_last(&st->cnt[1], nb, &lastflag)) return;
-    const real srr = sum_partials(io.partials, nb, red);
-    const real srz = sum_partials(io.partials + nb, nb, red);
-    const real sbb = sum_partials(io.partials + 2 * nb, nb, red);
-    if (threadIdx.x != 0) return;
-    reset_counter(&st->cnt[1]);
-    st->rr = srr;
-    if (MODE == kBInit) {
-        const bool jac = io.z != nullptr && io.dinv != nullptr;
-        st->rho = jac ? srz : srr;
-        st->bnorm2 = sbb > real(0) ? sbb : srr;
-        st->thresh2 = io.tol2 * st->bnorm2;
-        st->max_iter = io.max_iter;
-        st->iter = 0;
-        st->alpha = 0;
-        st->alpha_prev = 0;
-        st->beta = 0;
-        st->pending = 0;
+    if (MODE == kBInit && first_thread()) {
+        st->iterA = 0;
+        st->iterB = 0;
+        st->done = 0;
         st->status = 0;
+        st->iters = 0;
+        st->tail = 0;
+        st->tol2 = io.tol2;
+        st->max_iter = io.max_iter;
         st->fallback = 0;
         st->fallbacks = 0;
-        st->done = 0;
-        if (!isfinite(srr)) {
-            st->status = -4;
-            st->done = 1;
-        } else if (srr <= st->thresh2) {
-            st->done = 1;
-        }
-        return;
-    }
-    st->iter += 1;
-    st->alpha_prev = st->alpha;
-    st->pending = 1;
-    if (!isfinite(srr)) {
-        st->status = -4;
-        st->done = 1;
-    } else if (srr <= st->thresh2) {
-        st->done = 1;
-    } else if (st->iter >= st->max_iter) {
-        st->status = 1;
-        st->done = 1;
-    } else if (MODE == kBPlain) {
-        st->beta = srr / st->rho;
-        st->rho = srr;
-    } else if (MODE == kBJacobi) {
-        if (!(srz > real(0)) || !isfinite(srz)) {
-            st->status = -4;
-            st->done = 1;
-        } else {
-            st->beta = srz / st->rho;
-            st->rho = srz;
-        }
+        st->thresh2 = 0;
+        st->bnorm2 = 0;
     }
 }
 
-// Flexible CG: after the preconditioner wrote z = M(r), form z.r and z.q and
-// the Jacobi alternatives; beta = -(z.q)/(p.q) (the Polak-Ribiere beta of
-// Golub-Ye with r_{k+1} - r_k = -alpha q). If z.r <= 0 or is not finite the
-// iteration falls back to z = r / diag(A).
+// Flexible CG: after the preconditioner wrote z = M(r), per-block partials of
+// z.r, z.q and of the Jacobi alternatives (dinv r).r, (dinv r).q; the next
+// phase A sums them, takes beta = -(z.q)/(p.q) (the Golub-Ye Polak-Ribiere
+// beta, since r_{k+1} - r_k = -alpha q) and falls back to the Jacobi z when
+// z.r <= 0 or is not finite.
 template <class real>
 __global__ __launch_bounds__(kThreads) void flex_dots(int64_t n, VecIO<real> io) {
     __shared__ real red[kThreads / kWave];
-    __shared__ int lastflag;
     CgState<real>* st = io.st;
-    if (st->done) return;
-    const bool first = st->iter == 0;
+    if (block_flag(&st->done)) return;
+    const bool first = st->iterA == 0;
     real zr = 0, zq = 0, jr = 0, jq = 0;
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
@@ -165,54 +145,35 @@ __global__ __launch_bounds__(kThreads) void flex_dots(int64_t n, VecIO<real> io)
         }
     }
     const int nb = gridDim.x;
-    real a0 = block_sum(zr, red), a1 = block_sum(zq, red), a2 = block_sum(jr, red),
-         a3 = block_sum(jq, red);
+    const real a0 = block_sum(zr, red), a1 = block_sum(zq, red), a2 = block_sum(jr, red),
+               a3 = block_sum(jq, red);
     if (threadIdx.x == 0) {
-        store_partial(io.partials + blockIdx.x, a0);
-        store_partial(io.partials + nb + blockIdx.x, a1);
-        store_partial(io.partials + 2 * nb + blockIdx.x, a2);
-        store_partial(io.partials + 3 * nb + blockIdx.x, a3);
-    }
-    if (!arrive_last(&st->cnt[2], nb, &lastflag)) return;
-    const real szr = sum_partials(io.partials, nb, red);
-    const real szq = sum_partials(io.partials + nb, nb, red);
-    const real sjr = sum_partials(io.partials + 2 * nb, nb, red);
-    const real sjq = sum_partials(io.partials + 3 * nb, nb, red);
-    if (threadIdx.x != 0) return;
-    reset_counter(&st->cnt[2]);
-    const bool ok = (szr > real(0)) && isfinite(szr) && isfinite(szq);
-    st->fallback = ok ? 0 : 1;
-    if (!ok) st->fallbacks += 1;
-    const real rho = ok ? szr : sjr, zq_ = ok ? szq : sjq;
-    st->rho = rho;
-    st->zq = zq_;
-    st->beta = first ? real(0) : -zq_ / st->pq;
-    if (!(rho > real(0)) || !isfinite(rho)) {
-        st->status = -4;
-        st->done = 1;
+        io.partials[blockIdx.x] = a0;
+        io.partials[nb + blockIdx.x] = a1;
+        io.partials[2 * nb + blockIdx.x] = a2;
+        io.partials[3 * nb + blockIdx.x] = a3;
     }
 }
 
+// x += alpha_{K-1} p_{K-1} after the loop stopped at K iterations, if owed.
 template <class real>
-__global__ void fallback_fix(int64_t n, VecIO<real> io) {
-    if (io.st->done || !io.st->fallback) return;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
-        io.z[e] = (real)io.dinv[e] * io.r[e];
-}
-
-template <class real>
-__global__ void finalize(int64_t n, real* x, const real* p0, const real* p1, CgState<real>* st) {
-    if (!st->pending) return;
-    const real* p = ((st->iter - 1) & 1) ? p1 : p0;
-    const real a = st->alpha_prev;
+__global__ void finalize(int64_t n, real* x, const real* p0, const real* p1,
+                         const CgState<real>* st) {
+    if (!st->tail) return;
+    const int K = st->iters;
+    const real* p = ((K - 1) & 1) ? p1 : p0;
+    const real a = st->alpha[(K - 1) & 1];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
         x[e] += a * p[e];
 }
 
-__global__ void clear_pending_f32(CgState<float>* st) { st->pending = 0; }
-__global__ void clear_pending_f64(CgState<double>* st) { st->pending = 0; }
+__global__ __launch_bounds__(kThreads) void sum_partials_kernel(const double* parts, int n,
+                                                                double* out) {
+    __shared__ double red[kThreads / kWave];
+    const double s = sum_partials(parts, n, red);
+    if (threadIdx.x == 0) *out = s;
+}
 
 template <class real, class breal>
 __global__ void copy_dirichlet(int64_t n, const uint8_t* dmask, const breal* b, real* x) {
@@ -223,10 +184,8 @@ __global__ void copy_dirichlet(int64_t n, const uint8_t* dmask, const breal* b, 
 
 template <class vreal>
 __global__ __launch_bounds__(kThreads) void masked_norm2(int64_t n, const uint8_t* dmask,
-                                                         const vreal* v, double* partials,
-                                                         unsigned* counter, double* out) {
+                                                         const vreal* v, double* partials) {
     __shared__ double red[kThreads / kWave];
-    __shared__ int lastflag;
     double s = 0;
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride)
@@ -235,13 +194,7 @@ __global__ __launch_bounds__(kThreads) void masked_norm2(int64_t n, const uint8_
             s += t * t;
         }
     const double tot = block_sum(s, red);
-    if (threadIdx.x == 0) store_partial(partials + blockIdx.x, tot);
-    if (!arrive_last(counter, gridDim.x, &lastflag)) return;
-    const double all = sum_partials(partials, (int)gridDim.x, red);
-    if (threadIdx.x == 0) {
-        *out = all;
-        reset_counter(counter);
-    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
 __global__ void scale_to_f32(int64_t n, const double* r64, const double* norm2, float* r32) {
@@ -412,27 +365,23 @@ hipError_t launch_phase_b_f64(int mode, int64_t n, const VecIO<double>& io, int 
 
 hipError_t launch_flex_dots_f32(int64_t n, const VecIO<float>& io, int nb, hipStream_t s) {
     hipLaunchKernelGGL((flex_dots<float>), dim3(nb), dim3(kThreads), 0, s, n, io);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((fallback_fix<float>), dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, io);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize_f32(int64_t n, float* x, float* p0, float* p1, CgState<float>* st,
-                               hipStream_t s) {
+hipError_t launch_finalize_f32(int64_t n, float* x, const float* p0, const float* p1,
+                               const CgState<float>* st, hipStream_t s) {
     hipLaunchKernelGGL((finalize<float>), dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, x, p0, p1, st);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(clear_pending_f32, dim3(1), dim3(1), 0, s, st);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize_f64(int64_t n, double* x, double* p0, double* p1, CgState<double>* st,
-                               hipStream_t s) {
+hipError_t launch_finalize_f64(int64_t n, double* x, const double* p0, const double* p1,
+                               const CgState<double>* st, hipStream_t s) {
     hipLaunchKernelGGL((finalize<double>), dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, x, p0, p1, st);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(clear_pending_f64, dim3(1), dim3(1), 0, s, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const double* parts, int n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kThreads), 0, s, parts, n, out);
     return hipGetLastError();
 }
 
@@ -454,15 +403,16 @@ hipError_t launch_copy_dirichlet_f64(int64_t n, const uint8_t* dmask, const void
 }
 
 hipError_t launch_masked_norm2(int64_t n, const uint8_t* dmask, const void* v, int v_f64,
-                               double* partials, unsigned* counter, double* out, int nb,
-                               hipStream_t s) {
+                               double* partials, double* out, int nb, hipStream_t s) {
     if (v_f64)
         hipLaunchKernelGGL((masked_norm2<double>), dim3(nb), dim3(kThreads), 0, s, n, dmask,
-                           static_cast<const double*>(v), partials, counter, out);
+                           static_cast<const double*>(v), partials);
     else
         hipLaunchKernelGGL((masked_norm2<float>), dim3(nb), dim3(kThreads), 0, s, n, dmask,
-                           static_cast<const float*>(v), partials, counter, out);
-    return hipGetLastError();
+                           static_cast<const float*>(v), partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_sum_partials(partials, nb, out, s);
 }
 
 hipError_t launch_scale_to_f32(int64_t n, const double* r64, const double* norm2, float* r32,
