@@ -17,7 +17,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <vector>
 
 using namespace mffv;
 
@@ -168,8 +170,11 @@ void drop_graphs(mffv_grid* G) {
         if (gr.exec) { (void)hipGraphExecDestroy(gr.exec); gr.exec = nullptr; }
 }
 
-// Residual r = b - A x in FP64 and ||r||^2, ||b_U||^2 into dscal[1], dscal[0].
-int true_residual_f64(mffv_grid* G, const void* b, int b_f64, const double* x, double* r) {
+// Residual r = b - A x in FP64; ||r||^2 into out[1] and ||b_U||^2 into out[0]
+// (device doubles; by default the grid's dscal).
+int true_residual_f64(mffv_grid* G, const void* b, int b_f64, const double* x, double* r,
+                      double* out = nullptr) {
+    if (!out) out = G->dscal;
     StencilIO<double> io;
     io.src = x;
     io.out = r;
@@ -177,8 +182,8 @@ int true_residual_f64(mffv_grid* G, const void* b, int b_f64, const double* x, d
     io.rhs_f64 = b_f64;
     io.partials = G->partR;
     HIP_TRY(launch_stencil_f64(kResidual, G->g, coef_of(G), io, G->m64, G->stream));
-    HIP_TRY(launch_sum_partials(G->partR, G->m64.blocks(), G->dscal + 1, G->stream));
-    HIP_TRY(launch_masked_norm2(G->g.n, G->dmask, b, b_f64, G->partR, G->dscal + 0, G->nb_vec,
+    HIP_TRY(launch_sum_partials(G->partR, G->m64.blocks(), out + 1, G->stream));
+    HIP_TRY(launch_masked_norm2(G->g.n, G->dmask, b, b_f64, G->partR, out + 0, G->nb_vec,
                                 G->stream));
     return MFFV_OK;
 }
@@ -496,6 +501,183 @@ int solve_ir(mffv_grid* G, const void* b, int b_f64, const mffv_opts& o, mffv_in
     return status;
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched solves: a plan per distinct argument set, holding the device-side
+// descriptors and the captured graph [clear barriers -> persistent CG ->
+// per-system FP64 true residuals]; later calls with the same arguments replay
+// the graph. Plans are dropped when one of their grids is destroyed.
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+    std::vector<mffv_grid*> grids;
+    std::vector<const float*> b;
+    std::vector<float*> x;
+    int precond = 0, max_iter = 0, blocks_per_cu = 0;
+    double tol = 0;
+    void* dbuf = nullptr;
+    BatchSys* dsys = nullptr;
+    int* dblock_sys = nullptr;
+    unsigned* dbars = nullptr;
+    BatchResult* dres = nullptr;
+    double* dres64 = nullptr;  // [2*s]: ||b_U||^2, [2*s+1]: ||r||^2
+    int* derr = nullptr;
+    int nblocks = 0;
+    BatchRun run{};
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<int> blocks;   // per system
+};
+
+std::mutex g_plans_mu;
+int g_batch_bpc = 0;  // blocks per CU of the batched kernel (0 = occupancy limit)
+
+int batch_blocks_per_cu_override() { return g_batch_bpc; }
+std::vector<BatchPlan*> g_plans;
+
+void free_plan(BatchPlan* P) {
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->dbuf) (void)hipFree(P->dbuf);
+    if (P->e0) (void)hipEventDestroy(P->e0);
+    if (P->e1) (void)hipEventDestroy(P->e1);
+    delete P;
+}
+
+void drop_plans_with(const mffv_grid* G) {
+    std::lock_guard<std::mutex> lk(g_plans_mu);
+    for (auto it = g_plans.begin(); it != g_plans.end();) {
+        if (std::find((*it)->grids.begin(), (*it)->grids.end(), G) != (*it)->grids.end()) {
+            free_plan(*it);
+            it = g_plans.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+// Blocks per system in proportion to its work, estimated as cells times the
+// grid's extent (CG iterations grow with the extent).
+std::vector<int> share_blocks(const std::vector<mffv_grid*>& grids, int total) {
+    const int ns = (int)grids.size();
+    std::vector<double> w(ns);
+    double sw = 0;
+    for (int s = 0; s < ns; ++s) {
+        const Geom& g = grids[s]->g;
+        w[s] = (double)g.n * (double)(g.nx + g.ny + g.nz);
+        sw += w[s];
+    }
+    std::vector<int> B(ns);
+    int sum = 0;
+    for (int s = 0; s < ns; ++s) {
+        B[s] = std::max(1, (int)std::floor(total * w[s] / sw));
+        sum += B[s];
+    }
+    while (sum > total) {
+        int j = -1;
+        for (int s = 0; s < ns; ++s)
+            if (B[s] > 1 && (j < 0 || w[s] / B[s] < w[j] / B[j])) j = s;
+        if (j < 0) break;
+        --B[j];
+        --sum;
+    }
+    while (sum < total) {
+        int j = 0;
+        for (int s = 1; s < ns; ++s)
+            if (w[s] / B[s] > w[j] / B[j]) j = s;
+        ++B[j];
+        ++sum;
+    }
+    return B;
+}
+
+int build_plan(BatchPlan* P, hipStream_t stream) {
+    const int ns = (int)P->grids.size();
+    int rc;
+    for (mffv_grid* G : P->grids)
+        if ((rc = ensure_ws32(G)) || (rc = ensure_x64(G))) return rc;
+    int dev = 0, cus = 0, rate_khz = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
+    const int occ = batched_blocks_per_cu();
+    if (occ <= 0) return fail(MFFV_EHIP, "occupancy query of the batched kernel failed");
+    const int per_cu = P->blocks_per_cu > 0 ? std::min(P->blocks_per_cu, occ) : occ;
+    const int total = per_cu * cus;
+    if (ns > total)
+        return fail(MFFV_EINVAL, "more systems than co-resident blocks (" + std::to_string(total) + ")");
+    P->blocks = share_blocks(P->grids, total);
+    P->nblocks = total;
+    // device buffer: descriptors, block map, partials, barriers, results
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
+    const size_t o_sys = take(sizeof(BatchSys) * ns), o_map = take(sizeof(int) * total),
+                 o_part = take(sizeof(float) * 4 * total), o_bar = take(sizeof(unsigned) * 2 * ns),
+                 o_res = take(sizeof(BatchResult) * ns), o_r64 = take(sizeof(double) * 2 * ns),
+                 o_err = take(sizeof(int));
+    HIP_TRY(hipMalloc(&P->dbuf, off));
+    char* base = static_cast<char*>(P->dbuf);
+    P->dsys = reinterpret_cast<BatchSys*>(base + o_sys);
+    P->dblock_sys = reinterpret_cast<int*>(base + o_map);
+    float* dpart = reinterpret_cast<float*>(base + o_part);
+    P->dbars = reinterpret_cast<unsigned*>(base + o_bar);
+    P->dres = reinterpret_cast<BatchResult*>(base + o_res);
+    P->dres64 = reinterpret_cast<double*>(base + o_r64);
+    P->derr = reinterpret_cast<int*>(base + o_err);
+    std::vector<BatchSys> hs(ns);
+    std::vector<int> map(total);
+    int b0 = 0;
+    for (int s = 0; s < ns; ++s) {
+        mffv_grid* G = P->grids[s];
+        BatchSys& S = hs[s];
+        S.g = G->g;
+        S.c = coef_of(G);
+        S.dinv = G->dinv;
+        S.dmask = G->dmask;
+        S.b = P->b[s];
+        S.x = P->x[s];
+        S.r = G->r;
+        S.p0 = G->p0;
+        S.p1 = G->p1;
+        S.q = G->q;
+        S.z = G->z;
+        S.part = dpart + 4 * b0;
+        S.bar = P->dbars + 2 * s;
+        S.res = P->dres + s;
+        S.blk0 = b0;
+        S.nblk = P->blocks[s];
+        S.nchunk = (int)((G->g.plane + kThreads - 1) / kThreads);
+        const int64_t want = ((int64_t)S.nchunk * G->g.nx + 4 * S.nblk - 1) / (4 * (int64_t)S.nblk);
+        S.ci = (int)std::max<int64_t>(1, std::min<int64_t>(G->g.nx, want));
+        S.nich = (G->g.nx + S.ci - 1) / S.ci;
+        for (int t = 0; t < S.nblk; ++t) map[b0 + t] = s;
+        b0 += S.nblk;
+    }
+    HIP_TRY(hipMemcpy(P->dsys, hs.data(), sizeof(BatchSys) * ns, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(P->dblock_sys, map.data(), sizeof(int) * total, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(P->derr, 0, sizeof(int)));
+    P->run.tol2 = (float)(P->tol * P->tol);
+    P->run.max_iter = P->max_iter;
+    P->run.precond = P->precond;
+    P->run.limit_ticks = (uint64_t)rate_khz * 1000ull * 2ull;  // 2 s per barrier wait
+    P->run.err = P->derr;
+    HIP_TRY(hipEventCreate(&P->e0));
+    HIP_TRY(hipEventCreate(&P->e1));
+    (void)stream;
+    return MFFV_OK;
+}
+
+// Enqueue the whole batch: persistent CG, then each system's FP64 residual.
+int enqueue_batch(BatchPlan* P, hipStream_t stream) {
+    HIP_TRY(launch_batched_cg(P->dsys, P->dblock_sys, P->nblocks, P->dbars,
+                              2 * (int)P->grids.size(), P->run, stream));
+    for (size_t s = 0; s < P->grids.size(); ++s) {
+        mffv_grid* G = P->grids[s];
+        HIP_TRY(launch_convert_f32_to_f64(G->g.n, P->x[s], G->x64, stream));
+        int rc = true_residual_f64(G, P->b[s], 0, G->x64, G->rres, P->dres64 + 2 * s);
+        if (rc) return rc;
+    }
+    return MFFV_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -561,6 +743,7 @@ int mffv_create_grid(int nx, int ny, int nz, void* stream, mffv_grid** out) {
 
 void mffv_destroy_grid(mffv_grid* G) {
     if (!G) return;
+    drop_plans_with(G);
     (void)hipSetDevice(G->device);
     (void)hipStreamSynchronize(G->stream);
     drop_graphs(G);
@@ -760,6 +943,114 @@ int mffv_cg_solve_f64(mffv_grid* G, const double* b, double* x, const mffv_opts*
     status = status_code(status);
     inf.status = status;
     if (info) *info = inf;
+    return status;
+}
+
+int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const* b,
+                          float* const* x, const mffv_opts* opts, mffv_info* info) {
+    if (!grids || !b || !x || nsys <= 0) return fail(MFFV_EINVAL, "grids, b, x must be non-NULL and nsys > 0");
+    for (int s = 0; s < nsys; ++s) {
+        int rc = check_grid(grids[s], true);
+        if (rc) return rc;
+        if (!b[s] || !x[s]) return fail(MFFV_EINVAL, "NULL vector of system " + std::to_string(s));
+        if ((const void*)b[s] == (const void*)x[s]) return fail(MFFV_EINVAL, "b and x must not alias");
+        if (grids[s]->device != grids[0]->device || grids[s]->stream != grids[0]->stream)
+            return fail(MFFV_EINVAL, "all grids of a batch must share device and stream");
+        for (int t = 0; t < s; ++t)
+            if (grids[t] == grids[s]) return fail(MFFV_EINVAL, "a grid appears twice in the batch");
+    }
+    mffv_opts o = resolve_opts(opts);
+    int rc = validate_opts(o);
+    if (rc) return rc;
+    if (o.precision != MFFV_FP32) return fail(MFFV_EINVAL, "batched solves run in MFFV_FP32");
+    if (o.precond == MFFV_PRECOND_LEARNED)
+        return fail(MFFV_EINVAL, "batched solves support precond NONE or JACOBI");
+    if ((rc = set_device(grids[0]))) return rc;
+    hipStream_t stream = grids[0]->stream;
+    const int bpc = batch_blocks_per_cu_override();
+    std::lock_guard<std::mutex> lk(g_plans_mu);
+    BatchPlan* P = nullptr;
+    for (BatchPlan* c : g_plans) {
+        if ((int)c->grids.size() != nsys || c->precond != o.precond || c->tol != o.tol ||
+            c->max_iter != o.max_iter || c->blocks_per_cu != bpc)
+            continue;
+        bool same = true;
+        for (int s = 0; s < nsys && same; ++s)
+            same = c->grids[s] == grids[s] && c->b[s] == b[s] && c->x[s] == x[s];
+        if (same) { P = c; break; }
+    }
+    if (!P) {
+        P = new BatchPlan();
+        P->grids.assign(grids, grids + nsys);
+        P->b.assign(b, b + nsys);
+        P->x.assign(x, x + nsys);
+        P->precond = o.precond;
+        P->tol = o.tol;
+        P->max_iter = o.max_iter;
+        P->blocks_per_cu = bpc;
+        if ((rc = build_plan(P, stream))) {
+            free_plan(P);
+            return rc;
+        }
+        if (g_plans.size() >= 4) {
+            free_plan(g_plans.front());
+            g_plans.erase(g_plans.begin());
+        }
+        g_plans.push_back(P);
+    }
+    const bool use_graph = o.use_graph && stream != nullptr;
+    if (use_graph && !P->exec) {
+        HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        int erc = enqueue_batch(P, stream);
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamEndCapture(stream, &gr);
+        if (erc) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return erc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&P->exec, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    }
+    HIP_TRY(hipEventRecord(P->e0, stream));
+    if (use_graph) {
+        HIP_TRY(hipGraphLaunch(P->exec, stream));
+    } else if ((rc = enqueue_batch(P, stream))) {
+        return rc;
+    }
+    HIP_TRY(hipEventRecord(P->e1, stream));
+    HIP_TRY(hipEventSynchronize(P->e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, P->e0, P->e1));
+    std::vector<BatchResult> res(nsys);
+    std::vector<double> r64(2 * (size_t)nsys);
+    int err = 0;
+    HIP_TRY(hipMemcpy(res.data(), P->dres, sizeof(BatchResult) * nsys, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(r64.data(), P->dres64, sizeof(double) * 2 * nsys, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&err, P->derr, sizeof(int), hipMemcpyDeviceToHost));
+    if (err) {
+        HIP_TRY(hipMemset(P->derr, 0, sizeof(int)));
+        return fail(MFFV_EHIP, "batched CG: a per-system barrier wait expired (blocks not co-resident?)");
+    }
+    int status = MFFV_OK;
+    for (int s = 0; s < nsys; ++s) {
+        const BatchResult& R = res[s];
+        const int st = R.status == 0 ? MFFV_OK : (R.status == 1 ? MFFV_NOT_CONVERGED : MFFV_EBREAKDOWN);
+        if (st == MFFV_EBREAKDOWN) status = MFFV_EBREAKDOWN;
+        else if (st == MFFV_NOT_CONVERGED && status == MFFV_OK) status = MFFV_NOT_CONVERGED;
+        if (info) {
+            mffv_info& I = info[s];
+            I = mffv_info{};
+            I.status = st;
+            I.iters = R.iters;
+            I.ir_steps = 1;
+            I.rel_res_recursive = R.bnorm2 > 0 ? std::sqrt((double)R.rr / (double)R.bnorm2) : 0.0;
+            I.rel_res_true = r64[2 * s] > 0 ? std::sqrt(r64[2 * s + 1] / r64[2 * s]) : std::sqrt(r64[2 * s + 1]);
+            I.ms = ms;
+        }
+    }
+    if (status == MFFV_EBREAKDOWN) return fail(MFFV_EBREAKDOWN, "batched CG: breakdown in a system");
     return status;
 }
 

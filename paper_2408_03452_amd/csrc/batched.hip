@@ -1,8 +1,258 @@
-#include "mffv.h"
+// Batched CG: many independent systems of any sizes solved by one persistent
+// launch. Each system owns a contiguous range of the grid's blocks (sized by
+// its share of the work) and runs the whole of Alg. 1 inside the kernel: the
+// initial residual, then per iteration the fused phase A (direction update,
+// matrix-free apply, deferred solution update, p.Ap partial) and phase B
+// (residual update, r.r partial), separated by per-system barriers. After each
+// barrier every block of the system sums the system's partials in the same
+// order, so all of them take the same decisions without further
+// communication; converged systems' blocks leave while the others go on.
+//
+// Barriers spin on agent-scope atomics with a wall-clock watchdog: a block
+// that waits longer than the limit records an error and leaves, so a launch
+// whose blocks are not all resident ends with an error instead of hanging.
 #include "launch.hpp"
 
-extern "C" int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const* b,
-                                     float* const* x, const mffv_opts*, mffv_info*) {
-    if (!grids || !b || !x || nsys <= 0) return MFFV_EINVAL;
-    return MFFV_ESTATE;
+namespace mffv {
+namespace {
+
+__device__ __forceinline__ bool sys_barrier(unsigned* bar, unsigned nblk, uint64_t limit_ticks,
+                                            int* err) {
+    __shared__ int ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ok = 1;
+        if (nblk > 1) {
+            const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned prev =
+                __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (prev == nblk - 1) {
+                __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&bar[1], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                const uint64_t t0 = wall_clock64();
+                while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (wall_clock64() - t0 > limit_ticks) {
+                        ok = 0;
+                        atomicOr(err, 1);
+                        break;
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+        }
+    }
+    __syncthreads();
+    return ok != 0;
 }
+
+// Visit the cells of one work item (chunk pc of a plane, planes of group ic),
+// marching along x with the x-neighbours in registers. S(l) is the stencil's
+// source value at cell l; epi(l, s_l, (A s)_l) consumes each own cell.
+template <class SrcF, class EpiF>
+__device__ __forceinline__ void march_item(const Geom& g, const Coef& c, int pc, int ic, int ci,
+                                           SrcF S, EpiF epi) {
+    const int64_t P = g.plane;
+    const int64_t r0 = (int64_t)pc * kThreads + threadIdx.x;
+    if (r0 >= P) return;
+    const int i0 = ic * ci, i1 = min(g.nx, i0 + ci);
+    const int j = (int)(r0 / g.nz), k = (int)(r0 - (int64_t)j * g.nz);
+    const bool hasjm = j > 0, hasjp = j + 1 < g.ny, haskm = k > 0, haskp = k + 1 < g.nz;
+    const int nz = g.nz;
+    int64_t base = (int64_t)i0 * P + r0;
+    float sc = S(base), sm = sc, txm = 0.f;
+    if (i0 > 0) {
+        sm = S(base - P);
+        txm = c.tx[base - P];
+    }
+    for (int i = i0; i < i1; ++i, base += P) {
+        const float sp = (i + 1 < g.nx) ? S(base + P) : sc;
+        const float txc = c.tx[base], tyc = c.ty[base], tzc = c.tz[base], ac = c.a[base];
+        float tyl = 0.f, tzl = 0.f, sjm = sc, sjp = sc, skm = sc, skp = sc;
+        if (hasjm) {
+            tyl = c.ty[base - nz];
+            sjm = S(base - nz);
+        }
+        if (hasjp) sjp = S(base + nz);
+        if (haskm) {
+            tzl = c.tz[base - 1];
+            skm = S(base - 1);
+        }
+        if (haskp) skp = S(base + 1);
+        const float y = cell_op<float, float>(ac, sc, txc, sp, txm, sm, tyc, sjp, tyl, sjm, tzc, skp,
+                                              tzl, skm);
+        epi(base, sc, y);
+        sm = sc;
+        sc = sp;
+        txm = txc;
+    }
+}
+
+// Own cells of a work item without the stencil.
+template <class F>
+__device__ __forceinline__ void own_cells(const Geom& g, int pc, int ic, int ci, F f) {
+    const int64_t r0 = (int64_t)pc * kThreads + threadIdx.x;
+    if (r0 >= g.plane) return;
+    const int i0 = ic * ci, i1 = min(g.nx, i0 + ci);
+    for (int i = i0; i < i1; ++i) f((int64_t)i * g.plane + r0);
+}
+
+__global__ __launch_bounds__(kThreads) void batched_cg(const BatchSys* __restrict__ systems,
+                                                       const int* __restrict__ block_sys, BatchRun run) {
+    __shared__ float red[kThreads / kWave];
+    const BatchSys S = systems[block_sys[blockIdx.x]];
+    const int t = (int)blockIdx.x - S.blk0, B = S.nblk;
+    const Geom g = S.g;
+    const Coef c = S.c;
+    const int W = S.nchunk * S.nich;
+    const bool jac = run.precond == 1;
+    float* pq_part = S.part;
+    float* rr_part = S.part + B;
+    float* rz_part = S.part + 2 * B;
+    float* bb_part = S.part + 3 * B;
+
+    // initial residual r = b - A x' with x' = b on Dirichlet cells, x elsewhere
+    float rr = 0.f, rz = 0.f, bb = 0.f;
+    for (int w = t; w < W; w += B) {
+        const int pc = w % S.nchunk, ic = w / S.nchunk;
+        march_item(g, c, pc, ic, S.ci,
+                   [&](int64_t l) { return S.dmask[l] ? S.b[l] : S.x[l]; },
+                   [&](int64_t l, float, float y) {
+                       const float r = S.b[l] - y;
+                       S.r[l] = r;
+                       rr += r * r;
+                       if (jac) {
+                           const float z = S.dinv[l] * r;
+                           S.z[l] = z;
+                           rz += r * z;
+                       }
+                       if (!S.dmask[l]) bb += S.b[l] * S.b[l];
+                   });
+    }
+    {
+        const float a0 = block_sum(rr, red), a1 = block_sum(rz, red), a2 = block_sum(bb, red);
+        if (threadIdx.x == 0) {
+            rr_part[t] = a0;
+            rz_part[t] = a1;
+            bb_part[t] = a2;
+        }
+    }
+    if (!sys_barrier(S.bar, B, run.limit_ticks, run.err)) return;
+    rr = sum_partials(rr_part, B, red);
+    rz = sum_partials(rz_part, B, red);
+    bb = sum_partials(bb_part, B, red);
+    const float bnorm2 = bb > 0.f ? bb : rr;
+    const float thresh2 = run.tol2 * bnorm2;
+    float rho = jac ? rz : rr;
+    float beta = 0.f, alpha_prev = 0.f;
+    int k = 0, status = 0, tail = 0;
+    const float* src = jac ? S.z : S.r;
+
+    for (;;) {
+        const bool conv = isfinite(rr) && rr <= thresh2;
+        const bool bad = !conv && (!isfinite(rr) || (jac && (!(rho > 0.f) || !isfinite(rho))));
+        if (conv || bad || k >= run.max_iter) {
+            status = conv ? 0 : (bad ? -4 : 1);
+            tail = k >= 1 ? 1 : 0;
+            break;
+        }
+        // phase A
+        const float* pold = (k & 1) ? S.p0 : S.p1;
+        float* pnew = (k & 1) ? S.p1 : S.p0;
+        const bool up = k > 0;
+        float dot = 0.f;
+        for (int w = t; w < W; w += B) {
+            const int pc = w % S.nchunk, ic = w / S.nchunk;
+            march_item(g, c, pc, ic, S.ci,
+                       [&](int64_t l) { return up ? src[l] + beta * pold[l] : src[l]; },
+                       [&](int64_t l, float s, float y) {
+                           pnew[l] = s;
+                           S.q[l] = y;
+                           if (up) S.x[l] += alpha_prev * pold[l];
+                           dot += s * y;
+                       });
+        }
+        {
+            const float a0 = block_sum(dot, red);
+            if (threadIdx.x == 0) pq_part[t] = a0;
+        }
+        if (!sys_barrier(S.bar, B, run.limit_ticks, run.err)) return;
+        const float pq = sum_partials(pq_part, B, red);
+        if (!(pq > 0.f) || !isfinite(pq)) {
+            status = -4;
+            tail = 0;
+            break;
+        }
+        const float alpha = rho / pq;
+        // phase B
+        float r2 = 0.f, z2 = 0.f;
+        for (int w = t; w < W; w += B) {
+            const int pc = w % S.nchunk, ic = w / S.nchunk;
+            own_cells(g, pc, ic, S.ci, [&](int64_t l) {
+                const float r = S.r[l] - alpha * S.q[l];
+                S.r[l] = r;
+                r2 += r * r;
+                if (jac) {
+                    const float z = S.dinv[l] * r;
+                    S.z[l] = z;
+                    z2 += r * z;
+                }
+            });
+        }
+        {
+            const float a0 = block_sum(r2, red), a1 = block_sum(z2, red);
+            if (threadIdx.x == 0) {
+                rr_part[t] = a0;
+                rz_part[t] = a1;
+            }
+        }
+        if (!sys_barrier(S.bar, B, run.limit_ticks, run.err)) return;
+        rr = sum_partials(rr_part, B, red);
+        const float rho_new = jac ? sum_partials(rz_part, B, red) : rr;
+        beta = rho_new / rho;
+        rho = rho_new;
+        alpha_prev = alpha;
+        ++k;
+    }
+    // owed step, Dirichlet values
+    const float* plast = ((k - 1) & 1) ? S.p1 : S.p0;
+    for (int w = t; w < W; w += B) {
+        const int pc = w % S.nchunk, ic = w / S.nchunk;
+        own_cells(g, pc, ic, S.ci, [&](int64_t l) {
+            if (S.dmask[l]) S.x[l] = S.b[l];
+            else if (tail) S.x[l] += alpha_prev * plast[l];
+        });
+    }
+    if (t == 0 && threadIdx.x == 0) {
+        BatchResult* res = S.res;
+        res->iters = k;
+        res->status = status;
+        res->rr = rr;
+        res->bnorm2 = bnorm2;
+    }
+}
+
+__global__ void clear_barriers(unsigned* bars, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) bars[i] = 0u;
+}
+
+}  // namespace
+
+int batched_blocks_per_cu() {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_cg, kThreads, 0) != hipSuccess)
+        return 0;
+    return per_cu;
+}
+
+hipError_t launch_batched_cg(const BatchSys* systems, const int* block_sys, int nblocks,
+                             unsigned* bars, int nbars, const BatchRun& run, hipStream_t s) {
+    hipLaunchKernelGGL(clear_barriers, dim3(1), dim3(256), 0, s, bars, nbars);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(batched_cg, dim3(nblocks), dim3(kThreads), 0, s, systems, block_sys, run);
+    return hipGetLastError();
+}
+
+}  // namespace mffv

@@ -67,6 +67,22 @@ struct CgState {
     int pad[3];
 };
 
+// One cell of the eliminated operator in difference form:
+//   a x + sum over the six faces of T (x - x_nbr).
+template <class real, class creal>
+__device__ __forceinline__ real cell_op(creal a, real x, creal txp, real xxp, creal txm, real xxm,
+                                        creal typ, real xyp, creal tym, real xym, creal tzp,
+                                        real xzp, creal tzm, real xzm) {
+    real y = (real)a * x;
+    y += (real)txp * (x - xxp);
+    y += (real)txm * (x - xxm);
+    y += (real)typ * (x - xyp);
+    y += (real)tym * (x - xym);
+    y += (real)tzp * (x - xzp);
+    y += (real)tzm * (x - xzm);
+    return y;
+}
+
 // Map the hardware block index to a logical work index so that each XCD gets
 // a contiguous range of work. Blocks are dispatched round-robin over the XCDs
 // (block b runs on XCD b % 8); neighbouring logical tiles then share an L2.

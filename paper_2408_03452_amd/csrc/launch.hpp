@@ -100,6 +100,41 @@ hipError_t launch_convert_f64_to_f32(int64_t n, const double* a, float* b, hipSt
 hipError_t launch_fill_f32(int64_t n, float* a, float v, hipStream_t s);
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s);
 
+// Batched persistent CG.
+struct BatchResult {
+    int iters;
+    int status;    // 0 converged, 1 iteration cap, -4 breakdown
+    float rr;      // r.r at exit
+    float bnorm2;  // ||b_U||^2
+};
+
+struct BatchSys {
+    Geom g;
+    Coef c;
+    const float* dinv;
+    const uint8_t* dmask;
+    const float* b;
+    float* x;
+    float *r, *p0, *p1, *q, *z;  // workspace of the system's grid handle
+    float* part;                 // 4 * nblk partial sums
+    unsigned* bar;               // barrier: arrival count, generation
+    BatchResult* res;
+    int blk0, nblk;              // the system's blocks in the launch
+    int nchunk, nich, ci;        // work items: plane chunks x plane groups
+};
+
+struct BatchRun {
+    float tol2;
+    int max_iter;
+    int precond;            // 0 none, 1 Jacobi
+    uint64_t limit_ticks;   // barrier watchdog, in wall-clock ticks
+    int* err;               // set to 1 when a barrier wait expires
+};
+
+int batched_blocks_per_cu();
+hipError_t launch_batched_cg(const BatchSys* systems, const int* block_sys, int nblocks,
+                             unsigned* bars, int nbars, const BatchRun& run, hipStream_t s);
+
 // Operator set-up.
 hipError_t launch_perm_to_trans(const Geom& g, const double* k, double kz_ratio, float* tx,
                                 float* ty, float* tz, hipStream_t s);

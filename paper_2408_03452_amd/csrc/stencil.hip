@@ -45,22 +45,6 @@ __device__ __forceinline__ float4 axpy4(float a, float4 x, float4 y) {
     return make_float4(y.x + a * x.x, y.y + a * x.y, y.z + a * x.z, y.w + a * x.w);
 }
 
-// One cell of the eliminated operator in difference form:
-//   a x + sum over the six faces of T (x - x_nbr).
-template <class real, class creal>
-__device__ __forceinline__ real cell_op(creal a, real x, creal txp, real xxp, creal txm, real xxm,
-                                        creal typ, real xyp, creal tym, real xym, creal tzp,
-                                        real xzp, creal tzm, real xzm) {
-    real y = (real)a * x;
-    y += (real)txp * (x - xxp);
-    y += (real)txm * (x - xxm);
-    y += (real)typ * (x - xyp);
-    y += (real)tym * (x - xym);
-    y += (real)tzp * (x - xzp);
-    y += (real)tzm * (x - xzm);
-    return y;
-}
-
 // Start of phase A_k of the fused CG loop. Every block sums the partials of
 // the kernels before it (phase B: r.r, r.z, and at k = 0 ||b_U||^2; flexible
 // CG: the preconditioner dots) in the same order, tests convergence on r_k and
