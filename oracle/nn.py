@@ -1,0 +1,163 @@
+"""Oracle of the learned preconditioner's network: direct 3D convolutions.
+
+Test infrastructure only (see the package docstring).
+
+The network maps two input channels per cell (the scaled residual and a
+log-diagonal feature) through four 3x3x3 convolutions with 2 -> 16 -> 16 -> 16
+-> 1 channels and a ReLU after each of the first three. A convolution here is
+the cross-correlation with zero padding ("same" size):
+
+    y[K, o] = b[o] + sum_{tap} sum_{c} W[tap, c, o] * x[K + offset(tap), c],
+
+with ``tap = 9*(di+1) + 3*(dj+1) + (dk+1)`` for offsets ``di, dj, dk`` in
+{-1, 0, 1} along (x, y, z), and ``x = 0`` outside the grid.
+
+Everything is computed in FP64. Where the GPU path stores a tensor in BF16
+(weights, the network input, hidden activations, back-propagated activation
+gradients) the oracle rounds the same tensor to BF16 with round-to-nearest-even,
+so both sides see the same operands; sums are exact-ish FP64 here and FP32 on
+the GPU.
+
+Parameter vector layout (FP32 on the GPU): for each layer, W[27, cin, cout]
+(C order) then b[cout].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+LAYERS = ((2, 16, True), (16, 16, True), (16, 16, True), (16, 1, False))
+
+
+def n_params() -> int:
+    return sum(27 * ci * co + co for ci, co, _ in LAYERS)
+
+
+def bf16_round(x) -> np.ndarray:
+    """Round to the nearest BF16 value (ties to even), returned as FP64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    u = (u + 0x7FFF + lsb) & 0xFFFF0000
+    out = u.astype(np.uint32).view(np.float32).astype(np.float64)
+    return np.where(np.isfinite(f), out, f.astype(np.float64))
+
+
+def unpack(params):
+    """List of (W[27, cin, cout], b[cout]) per layer from the flat parameter vector."""
+    p = np.asarray(params, dtype=np.float64)
+    out, o = [], 0
+    for ci, co, _ in LAYERS:
+        W = p[o:o + 27 * ci * co].reshape(27, ci, co)
+        o += 27 * ci * co
+        b = p[o:o + co]
+        o += co
+        out.append((W, b))
+    assert o == p.size
+    return out
+
+
+def pack(layers) -> np.ndarray:
+    return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in layers])
+
+
+def init_params(seed: int = 0, last_scale: float = 0.0) -> np.ndarray:
+    """He-normal weights, zero biases; the last layer scaled by ``last_scale``
+    (0 makes the network output 0, so flexible CG starts as Jacobi-PCG)."""
+    rng = np.random.default_rng(seed)
+    layers = []
+    for li, (ci, co, _) in enumerate(LAYERS):
+        W = rng.normal(0.0, np.sqrt(2.0 / (27 * ci)), size=(27, ci, co))
+        if li == len(LAYERS) - 1:
+            W *= last_scale
+        layers.append((W, np.zeros(co)))
+    return pack(layers).astype(np.float32)
+
+
+def offsets():
+    return [(di, dj, dk) for di in (-1, 0, 1) for dj in (-1, 0, 1) for dk in (-1, 0, 1)]
+
+
+def shifted(x, off):
+    """s[K] = x[K + off] with zeros outside the grid (x has a trailing channel axis)."""
+    nx, ny, nz = x.shape[:3]
+    out = np.zeros_like(x)
+    src, dst = [], []
+    for d, n in zip(off, (nx, ny, nz)):
+        if d >= 0:
+            src.append(slice(d, n))
+            dst.append(slice(0, n - d))
+        else:
+            src.append(slice(0, n + d))
+            dst.append(slice(-d, n))
+    out[tuple(dst)] = x[tuple(src)]
+    return out
+
+
+def conv3d(x, W, b):
+    """y[K, o] = b[o] + sum_tap x[K + off(tap), :] @ W[tap]."""
+    y = np.broadcast_to(b, x.shape[:3] + (W.shape[2],)).astype(np.float64).copy()
+    for t, off in enumerate(offsets()):
+        y += shifted(x, off) @ W[t]
+    return y
+
+
+def conv3d_grads(x, W, dy):
+    """Gradients of conv3d with respect to W, b and x, given dL/dy."""
+    dW = np.zeros_like(W)
+    dx = np.zeros_like(x)
+    for t, off in enumerate(offsets()):
+        xs = shifted(x, off)
+        dW[t] = np.einsum("ijkc,ijko->co", xs, dy)
+        # y[K] uses x[K + off]: the gradient flows back to x[K'] from dy[K' - off]
+        dx += shifted(dy, tuple(-d for d in off)) @ W[t].T
+    db = dy.sum(axis=(0, 1, 2))
+    return dW, db, dx
+
+
+def forward(params, r_hat, feat, bf16: bool = True):
+    """Network output N (FP64, shape of the grid) and the cached activations."""
+    rnd = bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+    layers = [(rnd(W), np.asarray(b, dtype=np.float64)) for W, b in unpack(params)]
+    h = rnd(np.stack([r_hat, feat], axis=-1))
+    cache = [h]
+    for li, ((W, b), (_, _, relu)) in enumerate(zip(layers, LAYERS)):
+        y = conv3d(h, W, b)
+        if relu:
+            h = rnd(np.maximum(y, 0.0))
+            cache.append(h)
+        else:
+            h = y
+    return h[..., 0], cache, layers
+
+
+def loss_and_grads(params, r_hat, feat, skip, target, dmask, bf16: bool = True):
+    """Normalised squared error of the prediction ``skip + N`` against ``target``
+    over the unknown cells, and its gradient with respect to the parameters.
+
+    loss = sum_U (skip + N - target)^2 / sum_U target^2
+    """
+    rnd = bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+    out, cache, layers = forward(params, r_hat, feat, bf16)
+    u = ~np.asarray(dmask, dtype=bool)
+    e2 = float(np.sum(np.where(u, target, 0.0) ** 2))
+    diff = np.where(u, skip + out - target, 0.0)
+    loss = float(np.sum(diff ** 2) / e2)
+    dy = (2.0 * diff / e2)[..., None]
+    grads = [None] * len(layers)
+    for li in range(len(layers) - 1, -1, -1):
+        W, _ = layers[li]
+        x = cache[li]
+        dW, db, dx = conv3d_grads(x, W, dy)
+        grads[li] = (dW, db)
+        if li > 0:
+            dy = rnd(dx * (cache[li] > 0))   # ReLU of the layer below
+    return loss, pack(grads), out
+
+
+def adam(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step (bias-corrected); returns new (params, m, v)."""
+    m = beta1 * m + (1 - beta1) * grads
+    v = beta2 * v + (1 - beta2) * grads * grads
+    mh = m / (1 - beta1 ** step)
+    vh = v / (1 - beta2 ** step)
+    return params - lr * mh / (np.sqrt(vh) + eps), m, v
