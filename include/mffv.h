@@ -210,6 +210,86 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
                           float* const* x, const mffv_opts* opts, mffv_info* info);
 
 /*
+ * Learned preconditioner (flexible CG with opts.precond = MFFV_PRECOND_LEARNED).
+ *
+ * The network works on the Jacobi-scaled system A~ = D^-1/2 A D^-1/2,
+ * D = diag(A). Its two input channels per cell are the scaled residual
+ * r_hat = D^-1/2 r / s, with s^2 = r' D^-1 r / n_U, and r_hat times the
+ * log-diagonal feature of mffv_grid_feature; four 3x3x3 convolutions with
+ * 2 -> 16 -> 16 -> 16 -> 1 channels and a ReLU after each of the first three
+ * (zero padding at the grid boundary; y[K, o] = b[o] + sum_tap sum_c
+ * W[tap, c, o] x[K + offset(tap), c] with tap = 9 (dx+1) + 3 (dy+1) + (dz+1))
+ * map them to N. Inside flexible CG the preconditioned residual is
+ * z = D^-1 r + s D^-1/2 N on unknown cells and 0 on Dirichlet cells: Jacobi
+ * when N = 0. Training keeps the biases at zero, so N vanishes with r.
+ * Weights and activations are BF16 in the matrix-core products, accumulation
+ * is FP32, the master weights and Adam state are FP32. Parameter vector (FP32,
+ * mffv_net_num_params() entries): for each layer W[27][cin][cout] in C order,
+ * then b[cout]. Network calls use the current HIP device.
+ */
+
+/* Number of FP32 parameters of the network (15169). */
+int mffv_net_num_params(void);
+
+/* Create a network from host parameters (NULL: all zero). Synchronizes. */
+int mffv_net_create(const float* params, mffv_net** out);
+
+/* Release a network. NULL is a no-op. */
+void mffv_net_destroy(mffv_net* net);
+
+/* Copy the FP32 parameters and/or the last computed gradient to host arrays
+ * of mffv_net_num_params() floats (either may be NULL). Synchronizes. */
+int mffv_net_get_params(const mffv_net* net, float* params, float* grads);
+
+/* Replace the parameters from a host array and reset the Adam state. */
+int mffv_net_set_params(mffv_net* net, const float* params);
+
+/*
+ * Network output y = N(r_hat, feat) on an nx x ny x nz grid (flat layout of
+ * mffv.h), input channels (r_hat, r_hat * feat). r_hat, feat, out: device
+ * FP32 arrays of n cells. Enqueued on `stream`.
+ */
+int mffv_nn_forward(mffv_net* net, int nx, int ny, int nz, const float* r_hat, const float* feat,
+                    float* out, void* stream);
+
+/*
+ * Loss and parameter gradient of one training pair on the grid's operator
+ * (the gradient stays in the network; read it with mffv_net_get_params).
+ * r_hat is the scaled residual and target the scaled error of
+ * mffv_harvest_pair, so that A~ target = r_hat. With z = r_hat + N(r_hat, f):
+ *   loss = (z - target)' A~ (z - target) / (target' r_hat)
+ * over the unknown cells: the energy norm of the prediction error relative to
+ * that of the error (1 for z = 0; the Jacobi value for N = 0). With target
+ * NULL the loss is the energy functional (z' A~ z - 2 z' r_hat) / (r_hat' r_hat),
+ * minimal at z = A~^-1 r_hat, so any residual can serve as a training input.
+ * r_hat is taken as 0 on Dirichlet cells. Enqueued on the grid's stream;
+ * *loss (host, may be NULL) synchronizes it.
+ */
+int mffv_nn_loss_grad(mffv_net* net, mffv_grid* grid, const float* r_hat, const float* target,
+                      double* loss);
+
+/* mffv_nn_loss_grad followed by one Adam step (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias-corrected, biases fixed) with learning rate lr. */
+int mffv_nn_train_step(mffv_net* net, mffv_grid* grid, const float* r_hat, const float* target,
+                       float lr, double* loss);
+
+/* The network's second input channel for a grid: log(d) minus its mean over
+ * the unknown cells, d = diag(A); 0 on Dirichlet cells. feat: device FP32, n. */
+int mffv_grid_feature(mffv_grid* grid, float* feat);
+
+/*
+ * One training pair of the learned preconditioner from an iterate x of a solve
+ * of A x = b and a reference solution x_star, in the Jacobi-scaled space:
+ * r = b - A x (x must hold the Dirichlet values of b), s^2 = r' D^-1 r / n_U,
+ * r_hat = D^-1/2 r / s and target = D^1/2 (x_star - x) / s (so that
+ * A~ target = r_hat), both zero on Dirichlet cells. b, x: device FP32;
+ * x_star: device FP64; outputs device FP32 (n cells each). *scale (host, may
+ * be NULL) receives s and synchronizes the grid's stream.
+ */
+int mffv_harvest_pair(mffv_grid* grid, const float* b, const float* x, const double* x_star,
+                      float* r_hat, float* target, float* scale);
+
+/*
  * Streaming copy dst[i] = src[i] of `bytes` bytes (a multiple of 16) with the
  * library's own vector kernel: the achievable HBM ceiling the stencil kernels
  * are compared with. Device pointers, 16-byte aligned. Enqueued on `stream`.

@@ -2,9 +2,14 @@
 
 Test infrastructure only (see the package docstring).
 
-The network maps two input channels per cell (the scaled residual and a
-log-diagonal feature) through four 3x3x3 convolutions with 2 -> 16 -> 16 -> 16
--> 1 channels and a ReLU after each of the first three. A convolution here is
+The network maps two input channels per cell through four 3x3x3 convolutions
+with 2 -> 16 -> 16 -> 16 -> 1 channels and a ReLU after each of the first
+three. It works on the Jacobi-scaled system A~ = D^-1/2 A D^-1/2 (D = diag A):
+the input channels are the scaled residual r~ = D^-1/2 r / s (s makes its RMS
+over the unknown cells 1) and r~ times the log-diagonal feature
+f = log d - mean_U log d, so the output vanishes with the residual; the
+preconditioned residual is z = D^-1/2 (r~ + N) (times s), which is Jacobi
+when N = 0. A convolution here is
 the cross-correlation with zero padding ("same" size):
 
     y[K, o] = b[o] + sum_{tap} sum_{c} W[tap, c, o] * x[K + offset(tap), c],
@@ -62,7 +67,8 @@ def pack(layers) -> np.ndarray:
 
 def init_params(seed: int = 0, last_scale: float = 0.0) -> np.ndarray:
     """He-normal weights, zero biases; the last layer scaled by ``last_scale``
-    (0 makes the network output 0, so flexible CG starts as Jacobi-PCG)."""
+    (0 makes the network output 0, so flexible CG starts as Jacobi-PCG).
+    Training keeps the biases at zero, so N(0) = 0."""
     rng = np.random.default_rng(seed)
     layers = []
     for li, (ci, co, _) in enumerate(LAYERS):
@@ -114,11 +120,18 @@ def conv3d_grads(x, W, dy):
     return dW, db, dx
 
 
+def network_input(r_hat, feat):
+    """The two input channels (r_hat, r_hat * feat); the product is taken in FP32."""
+    r32 = np.asarray(r_hat, dtype=np.float32)
+    return np.stack([r32.astype(np.float64),
+                     (r32 * np.asarray(feat, dtype=np.float32)).astype(np.float64)], axis=-1)
+
+
 def forward(params, r_hat, feat, bf16: bool = True):
     """Network output N (FP64, shape of the grid) and the cached activations."""
     rnd = bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
     layers = [(rnd(W), np.asarray(b, dtype=np.float64)) for W, b in unpack(params)]
-    h = rnd(np.stack([r_hat, feat], axis=-1))
+    h = rnd(network_input(r_hat, feat))
     cache = [h]
     for li, ((W, b), (_, _, relu)) in enumerate(zip(layers, LAYERS)):
         y = conv3d(h, W, b)
@@ -130,19 +143,26 @@ def forward(params, r_hat, feat, bf16: bool = True):
     return h[..., 0], cache, layers
 
 
-def loss_and_grads(params, r_hat, feat, skip, target, dmask, bf16: bool = True):
-    """Normalised squared error of the prediction ``skip + N`` against ``target``
-    over the unknown cells, and its gradient with respect to the parameters.
+def loss_and_grads(params, r_hat, feat, target, dmask, apply_scaled, bf16: bool = True):
+    """Energy-norm loss of the prediction and its gradient.
 
-    loss = sum_U (skip + N - target)^2 / sum_U target^2
+    With z = r_hat + N(r_hat, feat) and the scaled error target (A~ target =
+    r_hat), the loss is the A~-norm of the prediction error relative to that
+    of the target, over the unknown cells:
+
+        loss = (z - target)' A~ (z - target) / (target' r_hat),
+
+    ``apply_scaled(v)`` returns A~ v for a grid-shaped v that is 0 on Dirichlet
+    cells. Returns (loss, gradient with respect to the parameter vector, N).
     """
     rnd = bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
     out, cache, layers = forward(params, r_hat, feat, bf16)
     u = ~np.asarray(dmask, dtype=bool)
-    e2 = float(np.sum(np.where(u, target, 0.0) ** 2))
-    diff = np.where(u, skip + out - target, 0.0)
-    loss = float(np.sum(diff ** 2) / e2)
-    dy = (2.0 * diff / e2)[..., None]
+    E = float(np.sum(np.where(u, target * r_hat, 0.0)))
+    delta = np.where(u, np.asarray(r_hat, dtype=np.float64) + out - target, 0.0)
+    Ad = np.where(u, apply_scaled(delta), 0.0)
+    loss = float(np.sum(delta * Ad) / E)
+    dy = (2.0 * Ad / E)[..., None]
     grads = [None] * len(layers)
     for li in range(len(layers) - 1, -1, -1):
         W, _ = layers[li]
@@ -152,6 +172,13 @@ def loss_and_grads(params, r_hat, feat, skip, target, dmask, bf16: bool = True):
         if li > 0:
             dy = rnd(dx * (cache[li] > 0))   # ReLU of the layer below
     return loss, pack(grads), out
+
+
+def scaled_operator(A, dmask):
+    """apply_scaled for loss_and_grads: v -> D^-1/2 A D^-1/2 v on the grid."""
+    dis = 1.0 / np.sqrt(A.diagonal())
+    shape = np.shape(dmask)
+    return lambda v: (dis * (A @ (dis * np.asarray(v, dtype=np.float64).ravel()))).reshape(shape)
 
 
 def adam(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -32,6 +32,14 @@ int fail(int code, const std::string& msg) {
     return code;
 }
 
+}  // namespace
+
+namespace mffv {
+int set_error(int code, const std::string& msg) { return fail(code, msg); }
+}  // namespace mffv
+
+namespace {
+
 int hip_fail(hipError_t e, const char* what) {
     return fail(MFFV_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
@@ -67,6 +75,8 @@ void dfree(T*& p) {
 struct CgGraph {
     hipGraphExec_t exec = nullptr;
     int chunk = 0;
+    const void* net = nullptr;  // learned preconditioner the graph was captured with
+    int net_gen = 0;            // and the generation of its workspace
 };
 
 struct mffv_grid {
@@ -79,6 +89,9 @@ struct mffv_grid {
     uint8_t* dmask = nullptr;
     int* flags = nullptr;
     bool has_coef = false;
+    int64_t n_unknown = 0;
+    float* feat = nullptr;     // learned preconditioner input feature (lazy)
+    bool feat_valid = false;
     // FP32 workspace
     float *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr, *z = nullptr, *xw = nullptr,
           *bw = nullptr;
@@ -163,6 +176,17 @@ int ensure_ws64(mffv_grid* G) {
     return MFFV_OK;
 }
 
+int ensure_feature(mffv_grid* G) {
+    if (G->feat_valid) return MFFV_OK;
+    int rc;
+    if (!G->feat && (rc = dalloc(&G->feat, (size_t)G->g.n))) return rc;
+    if ((rc = nn_feature(G->g, G->dinv, G->dmask, (float)G->n_unknown,
+                         reinterpret_cast<float*>(G->partR), G->feat, G->stream)))
+        return rc;
+    G->feat_valid = true;
+    return MFFV_OK;
+}
+
 void drop_graphs(mffv_grid* G) {
     for (auto& gr : G->graph32)
         if (gr.exec) { (void)hipGraphExecDestroy(gr.exec); gr.exec = nullptr; }
@@ -236,12 +260,13 @@ int enqueue_iter32(mffv_grid* G, int precond, const mffv_net* net) {
     v.pa = pa;
     v.nb_a = G->m32.blocks();
     v.st = G->st32;
+    v.dinv_dot = precond == MFFV_PRECOND_LEARNED ? 1 : 0;
     const int mode = precond == MFFV_PRECOND_NONE ? kBPlain
                      : precond == MFFV_PRECOND_JACOBI ? kBJacobi : kBFlex;
     HIP_TRY(launch_phase_b_f32(mode, G->g.n, v, G->nb_vec, G->stream));
     if (precond == MFFV_PRECOND_LEARNED) {
-        int rc = nn_precondition(net, G->g, G->r, G->dinv, G->dmask, G->z, pb, G->nb_vec, G->st32,
-                                 G->stream);
+        int rc = nn_precondition(net, G->g, G->r, G->dinv, G->dmask, G->z, pb + G->nb_vec, G->nb_vec,
+                                 G->feat, (float)G->n_unknown, G->stream);
         if (rc) return rc;
         VecIO<float> f = v;
         f.partials = pf;
@@ -276,9 +301,10 @@ int enqueue_iter64(mffv_grid* G, int precond) {
 }
 
 template <class F>
-int enqueue_chunk(mffv_grid* G, CgGraph& graph, int chunk, bool use_graph, F&& one_iter) {
+int enqueue_chunk(mffv_grid* G, CgGraph& graph, int chunk, bool use_graph, F&& one_iter,
+                  const void* net = nullptr, int net_gen = 0) {
     if (use_graph) {
-        if (graph.exec && graph.chunk != chunk) {
+        if (graph.exec && (graph.chunk != chunk || graph.net != net || graph.net_gen != net_gen)) {
             (void)hipGraphExecDestroy(graph.exec);
             graph.exec = nullptr;
         }
@@ -297,6 +323,8 @@ int enqueue_chunk(mffv_grid* G, CgGraph& graph, int chunk, bool use_graph, F&& o
             (void)hipGraphDestroy(gr);
             if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
             graph.chunk = chunk;
+            graph.net = net;
+            graph.net_gen = net_gen;
         }
         HIP_TRY(hipGraphLaunch(graph.exec, G->stream));
         return MFFV_OK;
@@ -312,12 +340,12 @@ int enqueue_chunk(mffv_grid* G, CgGraph& graph, int chunk, bool use_graph, F&& o
 // state to pinned memory behind it, then wait for the copy of chunk c-1.
 template <class State, class F>
 int drive_loop(mffv_grid* G, State* st, int max_iter, int chunk, CgGraph& graph, bool use_graph,
-               F&& one_iter) {
+               F&& one_iter, const void* net = nullptr, int net_gen = 0) {
     static_assert(sizeof(State) <= 256, "state mirror too small");
     const int max_chunks = max_iter / chunk + 3;
     bool stop = false;
     for (int c = 0; c < max_chunks && !stop; ++c) {
-        int rc = enqueue_chunk(G, graph, chunk, use_graph, one_iter);
+        int rc = enqueue_chunk(G, graph, chunk, use_graph, one_iter, net, net_gen);
         if (rc) return rc;
         HIP_TRY(hipMemcpyAsync(G->hstate + 256 * (c & 1), st, sizeof(State),
                                hipMemcpyDeviceToHost, G->stream));
@@ -337,6 +365,13 @@ int cg32(mffv_grid* G, double tol, int max_iter, int precond, const mffv_opts& o
     const mffv_net* net = o.net;
     if (precond == MFFV_PRECOND_LEARNED && !net)
         return fail(MFFV_EINVAL, "precond LEARNED needs opts.net");
+    int net_gen = 0;
+    if (precond == MFFV_PRECOND_LEARNED) {
+        int rc = ensure_feature(G);
+        if (rc) return rc;
+        net_gen = nn_prepare(net, G->g.n);
+        if (net_gen < 0) return net_gen;
+    }
     HIP_TRY(launch_copy_dirichlet_f32(G->g.n, G->dmask, G->bw, G->xw, G->stream));
     {
         StencilIO<float> io;
@@ -351,6 +386,7 @@ int cg32(mffv_grid* G, double tol, int max_iter, int precond, const mffv_opts& o
     v.z = G->z;
     v.dinv = G->dinv;
     v.jacobi = precond == MFFV_PRECOND_JACOBI ? 1 : 0;
+    v.dinv_dot = precond == MFFV_PRECOND_LEARNED ? 1 : 0;
     v.dmask = G->dmask;
     v.b = G->bw;
     v.partials = pb;
@@ -359,17 +395,18 @@ int cg32(mffv_grid* G, double tol, int max_iter, int precond, const mffv_opts& o
     v.max_iter = max_iter;
     HIP_TRY(launch_phase_b_f32(kBInit, G->g.n, v, G->nb_vec, G->stream));
     if (precond == MFFV_PRECOND_LEARNED) {
-        int rc = nn_precondition(net, G->g, G->r, G->dinv, G->dmask, G->z, pb, G->nb_vec, G->st32,
-                                 G->stream);
+        int rc = nn_precondition(net, G->g, G->r, G->dinv, G->dmask, G->z, pb + G->nb_vec, G->nb_vec,
+                                 G->feat, (float)G->n_unknown, G->stream);
         if (rc) return rc;
         VecIO<float> f = v;
         f.partials = reinterpret_cast<float*>(G->partF);
         HIP_TRY(launch_flex_dots_f32(G->g.n, f, G->nb_vec, G->stream));
     }
     const int chunk = std::max(1, o.check_every);
-    const bool use_graph = o.use_graph && G->stream != nullptr && precond != MFFV_PRECOND_LEARNED;
+    const bool use_graph = o.use_graph && G->stream != nullptr;
     int rc = drive_loop(G, G->st32, max_iter, chunk, G->graph32[precond], use_graph,
-                        [&]() { return enqueue_iter32(G, precond, net); });
+                        [&]() { return enqueue_iter32(G, precond, net); },
+                        precond == MFFV_PRECOND_LEARNED ? (const void*)net : nullptr, net_gen);
     if (rc) return rc;
     HIP_TRY(launch_finalize_f32(G->g.n, G->xw, G->p0, G->p1, G->st32, G->stream));
     CgState<float> hs;
@@ -725,7 +762,7 @@ int mffv_create_grid(int nx, int ny, int nz, void* stream, mffv_grid** out) {
         (rc = dalloc(&G->flags, 8)) || (rc = dalloc(&G->partA, (size_t)G->max_blocks)) ||
         (rc = dalloc(&G->partB, 3 * (size_t)G->nb_vec)) ||
         (rc = dalloc(&G->partF, 4 * (size_t)G->nb_vec)) ||
-        (rc = dalloc(&G->partR, (size_t)G->max_blocks)) || (rc = dalloc(&G->dscal, 8))) {
+        (rc = dalloc(&G->partR, (size_t)std::max(G->max_blocks, 1024))) || (rc = dalloc(&G->dscal, 8))) {
         mffv_destroy_grid(G);
         return rc;
     }
@@ -748,6 +785,7 @@ void mffv_destroy_grid(mffv_grid* G) {
     (void)hipStreamSynchronize(G->stream);
     drop_graphs(G);
     dfree(G->a); dfree(G->a64); dfree(G->tx); dfree(G->ty); dfree(G->tz); dfree(G->dinv); dfree(G->dmask);
+    dfree(G->feat);
     dfree(G->flags); dfree(G->partA); dfree(G->partB); dfree(G->partF); dfree(G->partR);
     dfree(G->dscal);
     dfree(G->r); dfree(G->p0); dfree(G->p1); dfree(G->q); dfree(G->z); dfree(G->xw);
@@ -798,6 +836,8 @@ int mffv_set_transmissibility(mffv_grid* G, const float* tx, const float* ty, co
     if (h[3] == 0 && !h[4])
         return fail(MFFV_EINVAL, "singular operator: no Dirichlet cell and zero accumulation");
     if (h[3] == G->g.n) return fail(MFFV_EINVAL, "every cell is a Dirichlet cell");
+    G->n_unknown = G->g.n - h[3];
+    G->feat_valid = false;
     G->has_coef = true;
     return MFFV_OK;
 }
@@ -1052,6 +1092,71 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
     }
     if (status == MFFV_EBREAKDOWN) return fail(MFFV_EBREAKDOWN, "batched CG: breakdown in a system");
     return status;
+}
+
+int mffv_harvest_pair(mffv_grid* G, const float* b, const float* x, const double* x_star,
+                      float* r_hat, float* target, float* scale) {
+    int rc = check_grid(G, true);
+    if (rc) return rc;
+    if (!b || !x || !x_star || !r_hat || !target) return fail(MFFV_EINVAL, "NULL array");
+    if ((rc = set_device(G)) || (rc = ensure_ws32(G))) return rc;
+    StencilIO<float> io;
+    io.src = x;
+    io.out = G->r;
+    io.rhs = b;
+    March m = G->m32;
+    if (m.vec == 4 && (((uintptr_t)x | (uintptr_t)b) % 16)) m = plan_march(G->g, 1, 0, 1);
+    HIP_TRY(launch_stencil_f32(kResidual, G->g, coef_of(G), io, m, G->stream));
+    float* sdev = reinterpret_cast<float*>(G->dscal + 2);
+    HIP_TRY(launch_harvest(G->g.n, G->r, x, x_star, G->dinv, G->dmask,
+                           reinterpret_cast<float*>(G->partR), (float)G->n_unknown, r_hat, target,
+                           sdev, G->stream));
+    if (scale) {
+        float h = 0.f;
+        HIP_TRY(hipMemcpyAsync(&h, sdev, sizeof(float), hipMemcpyDeviceToHost, G->stream));
+        HIP_TRY(hipStreamSynchronize(G->stream));
+        *scale = h;
+    }
+    return MFFV_OK;
+}
+
+int mffv_nn_loss_grad(mffv_net* net, mffv_grid* G, const float* r_hat, const float* target,
+                      double* loss) {
+    int rc = check_grid(G, true);
+    if (rc) return rc;
+    if (!net) return fail(MFFV_EINVAL, "network handle is NULL");
+    if (!r_hat) return fail(MFFV_EINVAL, "r_hat is NULL");
+    if ((rc = set_device(G)) || (rc = ensure_feature(G))) return rc;
+    if ((rc = nn_loss(net, G->g, coef_of(G), G->m32, G->dinv, G->dmask, G->feat, r_hat, target, true,
+                      G->stream)))
+        return rc;
+    if (loss) {
+        HIP_TRY(hipMemcpyAsync(loss, nn_loss_ptr(net), sizeof(double), hipMemcpyDeviceToHost, G->stream));
+        HIP_TRY(hipStreamSynchronize(G->stream));
+    }
+    return MFFV_OK;
+}
+
+int mffv_nn_train_step(mffv_net* net, mffv_grid* G, const float* r_hat, const float* target,
+                       float lr, double* loss) {
+    if (!(lr > 0.f) || !std::isfinite(lr)) return fail(MFFV_EINVAL, "learning rate must be > 0");
+    int rc = mffv_nn_loss_grad(net, G, r_hat, target, nullptr);
+    if (rc) return rc;
+    if ((rc = nn_adam(net, lr, G->stream))) return rc;
+    if (loss) {
+        HIP_TRY(hipMemcpyAsync(loss, nn_loss_ptr(net), sizeof(double), hipMemcpyDeviceToHost, G->stream));
+        HIP_TRY(hipStreamSynchronize(G->stream));
+    }
+    return MFFV_OK;
+}
+
+int mffv_grid_feature(mffv_grid* G, float* feat) {
+    int rc = check_grid(G, true);
+    if (rc) return rc;
+    if (!feat) return fail(MFFV_EINVAL, "feat is NULL");
+    if ((rc = set_device(G)) || (rc = ensure_feature(G))) return rc;
+    HIP_TRY(hipMemcpyAsync(feat, G->feat, G->g.n * sizeof(float), hipMemcpyDeviceToDevice, G->stream));
+    return MFFV_OK;
 }
 
 int mffv_copy_probe(void* dst, const void* src, size_t bytes, void* stream) {

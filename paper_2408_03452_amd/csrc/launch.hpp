@@ -4,6 +4,8 @@
 
 #include "common.hpp"
 
+#include <string>
+
 namespace mffv {
 
 // Work decomposition of a stencil kernel: a block owns a contiguous chunk of
@@ -18,6 +20,9 @@ struct March {
 };
 
 March plan_march(const Geom& g, int vec, int ci, int remap);
+
+// Record the message returned by mffv_last_error() on this thread; returns code.
+int set_error(int code, const std::string& msg);
 
 // Vectors and scalars a stencil kernel works on.
 template <class real>
@@ -69,6 +74,7 @@ struct VecIO {
     real tol2 = 0;                 // init: tol^2
     int max_iter = 0;              // init: iteration cap
     int jacobi = 0;                // init: also form z = dinv r and r.z
+    int dinv_dot = 0;              // flexible CG: r.(dinv r) into the second partial slot
 };
 
 hipError_t launch_phase_b_f32(int mode, int64_t n, const VecIO<float>& io, int nblocks, hipStream_t s);
@@ -80,6 +86,11 @@ hipError_t launch_finalize_f32(int64_t n, float* x, const float* p0, const float
                                const CgState<float>* st, hipStream_t s);
 hipError_t launch_finalize_f64(int64_t n, double* x, const double* p0, const double* p1,
                                const CgState<double>* st, hipStream_t s);
+// Learned-preconditioner training pair from the residual r of an iterate x
+// and a reference solution xstar (part: scratch of 1024 floats).
+hipError_t launch_harvest(int64_t n, const float* r, const float* x, const double* xstar,
+                          const float* dinv, const uint8_t* dmask, float* part, float n_u,
+                          float* r_hat, float* target, float* s_out, hipStream_t s);
 // out[0] = sum of n partials (one block, fixed order).
 hipError_t launch_sum_partials(const double* parts, int n, double* out, hipStream_t s);
 

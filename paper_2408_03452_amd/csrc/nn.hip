@@ -1,10 +1,878 @@
+// Learned preconditioner: a 4-layer 3x3x3 convolution network (channels
+// 2 -> 16 -> 16 -> 16 -> 1, ReLU after the first three) applied inside
+// flexible CG, and its training kernels.
+//
+// Convolutions are implicit GEMMs on the matrix cores: for each of the 27 taps
+// a 16-cell x 16-channel slab of the input (from an LDS tile with a one-cell
+// halo) is multiplied by the tap's 16 x 16 weight block with
+// v_mfma_f32_16x16x16_bf16 (BF16 operands, FP32 accumulation). A block owns a
+// 1 x 4 x 64 tile of output cells; each of its four waves computes one 64-cell
+// row as four 16-cell MFMA tiles. Activations are stored channels-last in
+// BF16 (32 bytes per cell for 16 channels). The first layer's two input
+// channels are packed as (tap, channel) pairs into K = 64 (54 used).
+//
+// Backward: the input gradient is the forward convolution of the output
+// gradient with the taps mirrored and the channel roles swapped, followed by
+// the ReLU mask of the layer below; the weight gradient is a GEMM over cells,
+// D[ci][co] += x[cell + off][ci] * dy[cell][co], with per-block partials
+// summed in a fixed order by a second kernel. Adam updates FP32 master
+// weights and rebuilds the BF16 operand layouts.
 #include "nn.hpp"
+#include "launch.hpp"
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace mffv {
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int TZ = 64, TY = 4;                  // output tile: 1 x TY x TZ cells
+constexpr int HX = 3, HY = TY + 2, HZ = TZ + 2;  // input tile with a one-cell halo
+constexpr int HCELLS = HX * HY * HZ;
+
+// parameter offsets of the FP32 master vector: per layer W[27][cin][cout], b[cout]
+constexpr int kCin[4] = {2, 16, 16, 16};
+constexpr int kCout[4] = {16, 16, 16, 1};
+constexpr int offW(int l) {
+    int o = 0;
+    for (int i = 0; i < l; ++i) o += 27 * kCin[i] * kCout[i] + kCout[i];
+    return o;
+}
+constexpr int offB(int l) { return offW(l) + 27 * kCin[l] * kCout[l]; }
+constexpr int kNParams = offW(4);
+static_assert(kNParams == 15169, "parameter count");
+
+// BF16 operand layouts (v4s per lane): forward and input-gradient weights
+constexpr int kWf1 = 0;                 // layer 1, 4 K-steps x 64 lanes
+constexpr int kWf2 = kWf1 + 4 * 64;     // layers 2..4, 27 taps x 64 lanes
+constexpr int kWf3 = kWf2 + 27 * 64;
+constexpr int kWf4 = kWf3 + 27 * 64;
+constexpr int kWb4 = kWf4 + 27 * 64;    // input gradient of layer 4 (2-channel path)
+constexpr int kWb3 = kWb4 + 4 * 64;
+constexpr int kWb2 = kWb3 + 27 * 64;
+constexpr int kWTotal = kWb2 + 27 * 64;  // in v4s units
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+struct Tile {
+    int i, j0, k0;
+};
+__device__ __forceinline__ Tile tile_of(int t, int ntj, int ntk) {
+    Tile T;
+    T.k0 = (t % ntk) * TZ;
+    T.j0 = ((t / ntk) % ntj) * TY;
+    T.i = t / (ntk * ntj);
+    return T;
+}
+__device__ __forceinline__ int hcell(int hx, int hy, int hz) { return (hx * HY + hy) * HZ + hz; }
+
+// Load the haloed input tile of a channels-last BF16 tensor with C channels.
+template <int C>
+__device__ __forceinline__ void load_halo(const uint16_t* __restrict__ in, const Geom& g, Tile T,
+                                          uint16_t* lds) {
+    if (C == 16) {
+        for (int c = threadIdx.x; c < HCELLS * 2; c += kThreads) {
+            const int cell = c >> 1, half = c & 1;
+            const int hz = cell % HZ, hy = (cell / HZ) % HY, hx = cell / (HZ * HY);
+            const int i = T.i - 1 + hx, j = T.j0 - 1 + hy, k = T.k0 - 1 + hz;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz) {
+                const int64_t l = ((int64_t)i * g.ny + j) * g.nz + k;
+                v = *reinterpret_cast<const uint4*>(in + l * 16 + half * 8);
+            }
+            *reinterpret_cast<uint4*>(lds + cell * 16 + half * 8) = v;
+        }
+    } else {
+        for (int cell = threadIdx.x; cell < HCELLS; cell += kThreads) {
+            const int hz = cell % HZ, hy = (cell / HZ) % HY, hx = cell / (HZ * HY);
+            const int i = T.i - 1 + hx, j = T.j0 - 1 + hy, k = T.k0 - 1 + hz;
+            uint32_t v = 0;
+            if (i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz) {
+                const int64_t l = ((int64_t)i * g.ny + j) * g.nz + k;
+                v = *reinterpret_cast<const uint32_t*>(in + l * 2);
+            }
+            *reinterpret_cast<uint32_t*>(lds + cell * 2) = v;
+        }
+    }
+}
+
+// Accumulate one wave's 64-cell row (4 MFMA tiles) of a 3x3x3 convolution.
+// C = 16: K = 27 taps x 16 channels; C = 2: K = 64 (tap, channel) pairs.
+template <int C>
+__device__ __forceinline__ void conv_row(const uint16_t* lds, const v4s* __restrict__ W, v4f acc[4]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m = lane & 15, kg = lane >> 4;
+    if (C == 16) {
+#pragma unroll
+        for (int t = 0; t < 27; ++t) {
+            const int dx = t / 9 - 1, dy = (t / 3) % 3 - 1, dz = t % 3 - 1;
+            const v4s b = W[t * 64 + lane];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const int cell = hcell(1 + dx, w + 1 + dy, mt * 16 + m + 1 + dz);
+                const v4s a = *reinterpret_cast<const v4s*>(lds + cell * 16 + kg * 4);
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[mt], 0, 0, 0);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int tA = s * 8 + 2 * kg, tB = tA + 1;
+            const v4s b = W[s * 64 + lane];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                uint32_t wa = 0, wb = 0;
+                if (tA < 27) {
+                    const int dx = tA / 9 - 1, dy = (tA / 3) % 3 - 1, dz = tA % 3 - 1;
+                    wa = *reinterpret_cast<const uint32_t*>(lds + hcell(1 + dx, w + 1 + dy, mt * 16 + m + 1 + dz) * 2);
+                }
+                if (tB < 27) {
+                    const int dx = tB / 9 - 1, dy = (tB / 3) % 3 - 1, dz = tB % 3 - 1;
+                    wb = *reinterpret_cast<const uint32_t*>(lds + hcell(1 + dx, w + 1 + dy, mt * 16 + m + 1 + dz) * 2);
+                }
+                v4s a;
+                a.x = (short)(wa & 0xffff);
+                a.y = (short)(wa >> 16);
+                a.z = (short)(wb & 0xffff);
+                a.w = (short)(wb >> 16);
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[mt], 0, 0, 0);
+            }
+        }
+    }
+}
+
+enum ConvOut {
+    kHiddenRelu = 0,  // + bias, ReLU, BF16 16 channels
+    kGradMasked = 1,  // input gradient: x (h_below > 0), BF16 16 channels
+    kFinal = 2,       // + bias, channel 0 only, FP32 (training output)
+    kPrecond = 3,     // + bias, z = dinv r + s sqrt(dinv) y on unknown cells, 0 on Dirichlet
+};
+
+struct ConvArgs {
+    const uint16_t* in;
+    const v4s* W;
+    const float* bias;      // kHiddenRelu, kFinal, kPrecond
+    uint16_t* out16;        // kHiddenRelu, kGradMasked
+    const uint16_t* below;  // kGradMasked: activation of the layer below (ReLU mask)
+    float* out32;           // kFinal, kPrecond
+    const float* r;         // kPrecond
+    const float* dinv;
+    const uint8_t* dmask;
+    const float* sscale;    // kPrecond: device scalar s
+    int ntj, ntk, ntiles;
+};
+
+template <int C, int MODE>
+__global__ __launch_bounds__(kThreads) void conv3d(Geom g, ConvArgs a) {
+    __shared__ __attribute__((aligned(16))) uint16_t lds[HCELLS * C];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int co = lane & 15, rg = lane >> 4;
+    const float s = (MODE == kPrecond) ? *a.sscale : 0.f;
+    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        const Tile T = tile_of(t, a.ntj, a.ntk);
+        __syncthreads();
+        load_halo<C>(a.in, g, T, lds);
+        __syncthreads();
+        v4f acc[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) acc[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+        conv_row<C>(lds, a.W, acc);
+        const int j = T.j0 + w;
+        if (j >= g.ny) continue;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = T.k0 + mt * 16 + rg * 4 + q;
+                if (k >= g.nz) continue;
+                const int64_t l = ((int64_t)T.i * g.ny + j) * g.nz + k;
+                const float v = acc[mt][q];
+                if (MODE == kHiddenRelu) {
+                    a.out16[l * 16 + co] = f2bf(fmaxf(v + a.bias[co], 0.f));
+                } else if (MODE == kGradMasked) {
+                    const bool on = bf2f(a.below[l * 16 + co]) > 0.f;
+                    a.out16[l * 16 + co] = f2bf(on ? v : 0.f);
+                } else if (co == 0) {
+                    const float y = v + a.bias[0];
+                    if (MODE == kFinal) {
+                        a.out32[l] = y;
+                    } else {
+                        const float di = a.dinv[l];
+                        a.out32[l] = a.dmask[l] ? 0.f : di * a.r[l] + s * sqrtf(di) * y;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Network input channels (rh, rh * feat) in BF16. For inference rh is the
+// Jacobi-scaled residual sqrt(dinv) r / s with s^2 = sum(dinv r^2) / n_U, the
+// sum taken from the phase-B partials pb (every block sums them; block 0 keeps
+// s for the last layer); for training rh = r is given already scaled.
+__global__ __launch_bounds__(kThreads) void nn_input(int64_t n, const float* r, const float* dinv,
+                                                     const float* feat, const float* pb, int nb,
+                                                     float n_u, float* sscale, uint16_t* x0,
+                                                     const uint8_t* dmask) {
+    __shared__ float red[kThreads / kWave];
+    float inv_s = 1.f;
+    if (pb) {
+        const float rr = sum_partials(pb, nb, red);
+        inv_s = rr > 0.f ? sqrtf(n_u / rr) : 0.f;
+        if (first_thread()) *sscale = rr > 0.f ? sqrtf(rr / n_u) : 0.f;
+    }
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x; l < n; l += stride) {
+        float rh = dinv ? sqrtf(dinv[l]) * r[l] * inv_s : r[l];
+        if (dmask && dmask[l]) rh = 0.f;
+        const uint32_t v = (uint32_t)f2bf(rh) | ((uint32_t)f2bf(rh * feat[l]) << 16);
+        reinterpret_cast<uint32_t*>(x0)[l] = v;
+    }
+}
+
+// Weight gradient of one layer over all cells: per-block partial D[t][ci][co]
+// (27 x 16 x 16) and bias-gradient partials. Wave w handles taps w, w+4, ...
+template <int CIN, int CDY>
+__global__ __launch_bounds__(kThreads) void conv_wgrad(Geom g, const uint16_t* __restrict__ x,
+                                                       const uint16_t* __restrict__ dy, int ntj,
+                                                       int ntk, int ntiles, float* part, float* dbpart) {
+    __shared__ __attribute__((aligned(16))) uint16_t lx[HCELLS * CIN];
+    __shared__ __attribute__((aligned(16))) uint16_t ld[TY * TZ * 16];
+    __shared__ float dbs[kThreads / kWave][16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int rc = lane & 15, kg = lane >> 4;
+    v4f acc[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
+    float db[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) db[c] = 0.f;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const Tile T = tile_of(t, ntj, ntk);
+        __syncthreads();
+        load_halo<CIN>(x, g, T, lx);
+        {   // output-gradient tile, no halo; thread = cell of the tile
+            const int c = threadIdx.x, yy = c / TZ, zz = c % TZ;
+            const int j = T.j0 + yy, k = T.k0 + zz;
+            const bool in = j < g.ny && k < g.nz;
+            const int64_t l = ((int64_t)T.i * g.ny + j) * g.nz + k;
+#pragma unroll
+            for (int ch = 0; ch < 16; ++ch) {
+                uint16_t v = 0;
+                if (in && ch < CDY) v = dy[l * CDY + ch];
+                ld[c * 16 + ch] = v;
+                db[ch] += bf2f(v);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ti = 0; ti < 7; ++ti) {
+            const int tap = w + 4 * ti;
+            if (tap >= 27) break;
+            const int dx = tap / 9 - 1, dyo = (tap / 3) % 3 - 1, dz = tap % 3 - 1;
+            for (int kc = 0; kc < TY * TZ / 16; ++kc) {
+                v4s A, B;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int c = kc * 16 + kg * 4 + q;
+                    const int yy = c / TZ, zz = c % TZ;
+                    const int cell = hcell(1 + dx, yy + 1 + dyo, zz + 1 + dz);
+                    const short av = (rc < CIN) ? (short)lx[cell * CIN + rc] : (short)0;
+                    const short bv = (short)ld[c * 16 + rc];
+                    if (q == 0) { A.x = av; B.x = bv; }
+                    if (q == 1) { A.y = av; B.y = bv; }
+                    if (q == 2) { A.z = av; B.z = bv; }
+                    if (q == 3) { A.w = av; B.w = bv; }
+                }
+                acc[ti] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, acc[ti], 0, 0, 0);
+            }
+        }
+    }
+    // partials: D[row = ci][col = co], lane holds rows kg*4 + q, column rc
+    float* P = part + (size_t)blockIdx.x * 27 * 256;
+#pragma unroll
+    for (int ti = 0; ti < 7; ++ti) {
+        const int tap = w + 4 * ti;
+        if (tap >= 27) break;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) P[tap * 256 + (kg * 4 + q) * 16 + rc] = acc[ti][q];
+    }
+    // bias gradient: per-thread sums, then waves, then block
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const float s = wave_sum(db[c]);
+        if (lane == 0) dbs[w][c] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        float s = 0.f;
+        for (int i = 0; i < kThreads / kWave; ++i) s += dbs[i][threadIdx.x];
+        dbpart[(size_t)blockIdx.x * 16 + threadIdx.x] = s;
+    }
+}
+
+// Sum the weight-gradient partials of one layer into the FP32 gradient vector.
+__global__ void reduce_wgrad(const float* part, const float* dbpart, int nblk, int cin, int cout,
+                             float* gW, float* gb) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nw = 27 * cin * cout;
+    if (e < nw) {
+        const int tap = e / (cin * cout), ci = (e / cout) % cin, co = e % cout;
+        const int src = tap * 256 + ci * 16 + co;
+        float s = 0.f;
+        for (int b = 0; b < nblk; ++b) s += part[(size_t)b * 27 * 256 + src];
+        gW[e] = s;
+    } else if (e < nw + cout) {
+        const int co = e - nw;
+        float s = 0.f;
+        for (int b = 0; b < nblk; ++b) s += dbpart[(size_t)b * 16 + co];
+        gb[co] = s;
+    }
+}
+
+// Energy-norm loss in the Jacobi-scaled space, z = rh + y on unknown cells.
+// With a target t (A~ t = rh): delta = z - t, E = t.rh, loss = delta.A~delta / E.
+// Without a target: delta = z, E = rh.rh and the energy functional
+// loss = (z.A~z - 2 z.rh) / E, minimal at z = A~^-1 rh (same gradient
+// direction, 2 (A~ z - rh) / E). The operator gets w = sqrt(dinv) delta.
+__global__ __launch_bounds__(kThreads) void loss_delta(int64_t n, const float* rh, const float* y,
+                                                       const float* tgt, const float* dinv,
+                                                       const uint8_t* dmask, float* w, float* epart) {
+    __shared__ float red[kThreads / kWave];
+    float e = 0.f;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x; l < n; l += stride) {
+        const bool d = dmask[l] != 0;
+        const float t = tgt ? tgt[l] : 0.f;
+        const float delta = d ? 0.f : rh[l] + y[l] - t;
+        w[l] = d ? 0.f : sqrtf(dinv[l]) * delta;
+        if (!d) e += (tgt ? t : rh[l]) * rh[l];
+    }
+    const float tt = block_sum(e, red);
+    if (threadIdx.x == 0) epart[blockIdx.x] = tt;
+}
+
+// Aw = A (sqrt(dinv) delta), A~ delta = sqrt(dinv) Aw: loss partials and the
+// output gradient (first of two BF16 channels).
+__global__ __launch_bounds__(kThreads) void loss_grad(int64_t n, const float* rh, const float* y,
+                                                      const float* tgt, const float* dinv,
+                                                      const uint8_t* dmask, const float* Aw,
+                                                      const float* epart, int nb_e, uint16_t* dy,
+                                                      float* part) {
+    __shared__ float red[kThreads / kWave];
+    const float E = sum_partials(epart, nb_e, red);
+    const float scale = E > 0.f ? 2.f / E : 0.f;
+    float s = 0.f;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x; l < n; l += stride) {
+        float g = 0.f;
+        if (!dmask[l]) {
+            const float ad = sqrtf(dinv[l]) * Aw[l];
+            const float z = rh[l] + y[l];
+            if (tgt) {
+                s += (z - tgt[l]) * ad;
+                g = scale * ad;
+            } else {
+                s += z * ad - 2.f * z * rh[l];
+                g = scale * (ad - rh[l]);
+            }
+        }
+        reinterpret_cast<uint32_t*>(dy)[l] = (uint32_t)f2bf(g);
+    }
+    const float t = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kThreads) void loss_final(const float* dpart, const float* epart, int nb,
+                                                       double* loss) {
+    __shared__ float red[kThreads / kWave];
+    const float D = sum_partials(dpart, nb, red);
+    const float E = sum_partials(epart, nb, red);
+    if (threadIdx.x == 0) *loss = E > 0.f ? (double)D / (double)E : 0.0;
+}
+
+__device__ __forceinline__ bool is_bias(int i) {
+    for (int l = 0; l < 4; ++l)
+        if (i >= offB(l) && i < offB(l) + kCout[l]) return true;
+    return false;
+}
+
+// Adam on the FP32 master weights; the biases stay fixed (the network output
+// then vanishes with its input).
+__global__ void adam_kernel(int np, float* p, const float* gr, float* m, float* v, float lr,
+                            float b1, float b2, float eps, float bc1, float bc2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np || is_bias(i)) return;
+    const float g = gr[i];
+    const float mi = b1 * m[i] + (1.f - b1) * g;
+    const float vi = b2 * v[i] + (1.f - b2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// BF16 operand layouts from the FP32 master weights.
+__global__ void prepare_weights(const float* p, v4s* W) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // one lane-slot (4 values)
+    if (idx >= kWTotal) return;
+    const int lane = idx & 63, kg = lane >> 4, col = lane & 15;
+    short v[4];
+    for (int q = 0; q < 4; ++q) {
+        float x = 0.f;
+        const int r = kg * 4 + q;  // row of the B operand (K index within the step)
+        if (idx < kWf2) {                                   // layer 1 forward
+            const int s = idx / 64, k = s * 16 + r, tap = k >> 1, ch = k & 1;
+            if (tap < 27) x = p[offW(0) + (tap * 2 + ch) * 16 + col];
+        } else if (idx < kWb4) {                            // layers 2..4 forward
+            const int l = idx < kWf3 ? 1 : (idx < kWf4 ? 2 : 3);
+            const int base = l == 1 ? kWf2 : (l == 2 ? kWf3 : kWf4);
+            const int tap = (idx - base) / 64;
+            if (l < 3) x = p[offW(l) + (tap * 16 + r) * 16 + col];
+            else if (col == 0) x = p[offW(3) + tap * 16 + r];
+        } else if (idx < kWb3) {                            // layer 4 input gradient
+            const int s = (idx - kWb4) / 64, k = s * 16 + r, tap = k >> 1, ch = k & 1;
+            if (tap < 27 && ch == 0) x = p[offW(3) + (26 - tap) * 16 + col];
+        } else {                                            // layers 3, 2 input gradient
+            const int l = idx < kWb2 ? 2 : 1;
+            const int base = l == 2 ? kWb3 : kWb2;
+            const int tap = (idx - base) / 64;
+            // W'[tap][cin' = co][cout' = ci] = W[26 - tap][ci][co]
+            x = p[offW(l) + ((26 - tap) * 16 + col) * 16 + r];
+        }
+        v[q] = (short)f2bf(x);
+    }
+    W[idx] = v4s{v[0], v[1], v[2], v[3]};
+}
+
+// log-diagonal feature: log(d) - mean_U log(d) on unknown cells, 0 on Dirichlet
+__global__ __launch_bounds__(kThreads) void logd_partials(int64_t n, const float* dinv,
+                                                          const uint8_t* dmask, float* part) {
+    __shared__ float red[kThreads / kWave];
+    float s = 0.f;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x; l < n; l += stride)
+        if (!dmask[l]) s -= logf(dinv[l]);
+    const float t = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kThreads) void feature_kernel(int64_t n, const float* dinv,
+                                                           const uint8_t* dmask, const float* part,
+                                                           int nb, float n_u, float* feat) {
+    __shared__ float red[kThreads / kWave];
+    const float mean = sum_partials(part, nb, red) / n_u;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x; l < n; l += stride)
+        feat[l] = dmask[l] ? 0.f : -logf(dinv[l]) - mean;
+}
+
+int nblocks_for(int64_t n, int cap) {
+    int64_t b = (n + kThreads - 1) / kThreads;
+    return (int)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+}  // namespace
+}  // namespace mffv
+
+using namespace mffv;
+
+struct mffv_net {
+    float* params = nullptr;  // FP32 master weights, kNParams
+    float* grads = nullptr;
+    float* m = nullptr;
+    float* v = nullptr;
+    v4s* W = nullptr;         // BF16 operand layouts
+    int step = 0;             // Adam steps taken
+    // activation workspace, sized for `cap` cells
+    int64_t cap = 0;
+    uint16_t* x0 = nullptr;   // 2 channels
+    uint16_t* h1 = nullptr;   // 16 channels each
+    uint16_t* h2 = nullptr;
+    uint16_t* h3 = nullptr;
+    uint16_t* g1 = nullptr;   // output gradients (16 channels)
+    uint16_t* g2 = nullptr;
+    uint16_t* dy4 = nullptr;  // 2 channels
+    float* y = nullptr;
+    float* t1 = nullptr;      // training scratch (FP32 cells)
+    float* t2 = nullptr;
+    float* part = nullptr;    // weight-gradient partials
+    float* dbpart = nullptr;
+    float* red = nullptr;     // reduction partials
+    float* sscale = nullptr;
+    double* loss = nullptr;
+    int wg_blocks = 0;
+    bool training_ws = false;
+    int ws_gen = 0;           // bumped whenever the workspace is reallocated
+};
+
+namespace {
+
+int nfail(int code, const std::string& m) { return set_error(code, m); }
+
+template <class T>
+int nalloc(T** p, size_t count) {
+    if (hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return MFFV_ENOMEM;
+    }
+    return MFFV_OK;
+}
+template <class T>
+void nfree(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+constexpr int kRedBlocks = 1024;
+
+void free_ws(mffv_net* N) {
+    nfree(N->x0); nfree(N->h1); nfree(N->h2); nfree(N->h3); nfree(N->g1); nfree(N->g2);
+    nfree(N->dy4); nfree(N->y); nfree(N->t1); nfree(N->t2);
+    N->cap = 0;
+    N->training_ws = false;
+}
+
+int ensure_ws(mffv_net* N, int64_t n, bool training) {
+    if (n <= N->cap && (!training || N->training_ws)) return MFFV_OK;
+    const int64_t cap = std::max<int64_t>(n, N->cap);
+    free_ws(N);
+    N->ws_gen += 1;
+    int rc;
+    if ((rc = nalloc(&N->x0, (size_t)cap * 2)) || (rc = nalloc(&N->h1, (size_t)cap * 16)) ||
+        (rc = nalloc(&N->h2, (size_t)cap * 16)) || (rc = nalloc(&N->y, (size_t)cap))) {
+        free_ws(N);
+        return nfail(rc, "network workspace allocation failed");
+    }
+    if (training) {
+        if ((rc = nalloc(&N->h3, (size_t)cap * 16)) || (rc = nalloc(&N->g1, (size_t)cap * 16)) ||
+            (rc = nalloc(&N->g2, (size_t)cap * 16)) || (rc = nalloc(&N->dy4, (size_t)cap * 2)) ||
+            (rc = nalloc(&N->t1, (size_t)cap)) || (rc = nalloc(&N->t2, (size_t)cap))) {
+            free_ws(N);
+            return nfail(rc, "network training workspace allocation failed");
+        }
+        N->training_ws = true;
+    }
+    N->cap = cap;
+    return MFFV_OK;
+}
+
+#define NHIP(expr)                                                              \
+    do {                                                                        \
+        hipError_t e_ = (expr);                                                 \
+        if (e_ != hipSuccess) return nfail(MFFV_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct Shape {
+    Geom g;
+    int ntj, ntk, ntiles;
+};
+
+Shape shape_of(int nx, int ny, int nz) {
+    Shape s;
+    s.g = Geom{nx, ny, nz, (int64_t)nx * ny * nz, (int64_t)ny * nz};
+    s.ntj = (ny + TY - 1) / TY;
+    s.ntk = (nz + TZ - 1) / TZ;
+    s.ntiles = nx * s.ntj * s.ntk;
+    return s;
+}
+
+template <int C, int MODE>
+int conv(const Shape& S, const ConvArgs& a0, hipStream_t st) {
+    ConvArgs a = a0;
+    a.ntj = S.ntj;
+    a.ntk = S.ntk;
+    a.ntiles = S.ntiles;
+    const int blocks = std::min(S.ntiles, 16384);
+    hipLaunchKernelGGL((conv3d<C, MODE>), dim3(blocks), dim3(kThreads), 0, st, S.g, a);
+    NHIP(hipGetLastError());
+    return MFFV_OK;
+}
+
+// Forward through the four layers from N->x0 (already filled); the last layer
+// either stores y (training) or forms the preconditioned z.
+int forward(mffv_net* N, const Shape& S, bool keep_h3, int last_mode, const ConvArgs& last,
+            hipStream_t st) {
+    ConvArgs a{};
+    a.in = N->x0;
+    a.W = N->W + kWf1;
+    a.bias = N->params + offB(0);
+    a.out16 = N->h1;
+    int rc;
+    if ((rc = conv<2, kHiddenRelu>(S, a, st))) return rc;
+    a.in = N->h1;
+    a.W = N->W + kWf2;
+    a.bias = N->params + offB(1);
+    a.out16 = N->h2;
+    if ((rc = conv<16, kHiddenRelu>(S, a, st))) return rc;
+    uint16_t* h3 = keep_h3 ? N->h3 : N->h1;  // inference reuses h1's buffer
+    a.in = N->h2;
+    a.W = N->W + kWf3;
+    a.bias = N->params + offB(2);
+    a.out16 = h3;
+    if ((rc = conv<16, kHiddenRelu>(S, a, st))) return rc;
+    ConvArgs f = last;
+    f.in = h3;
+    f.W = N->W + kWf4;
+    f.bias = N->params + offB(3);
+    if (last_mode == kFinal) return conv<16, kFinal>(S, f, st);
+    return conv<16, kPrecond>(S, f, st);
+}
+
+int backward(mffv_net* N, const Shape& S, hipStream_t st) {
+    int rc;
+    const int nb = N->wg_blocks = std::min(S.ntiles, 512);
+    auto wgrad = [&](int layer, const uint16_t* x, const uint16_t* dy) -> int {
+        if (layer == 0)
+            hipLaunchKernelGGL((conv_wgrad<2, 16>), dim3(nb), dim3(kThreads), 0, st, S.g, x, dy, S.ntj, S.ntk, S.ntiles, N->part, N->dbpart);
+        else if (layer == 3)
+            hipLaunchKernelGGL((conv_wgrad<16, 2>), dim3(nb), dim3(kThreads), 0, st, S.g, x, dy, S.ntj, S.ntk, S.ntiles, N->part, N->dbpart);
+        else
+            hipLaunchKernelGGL((conv_wgrad<16, 16>), dim3(nb), dim3(kThreads), 0, st, S.g, x, dy, S.ntj, S.ntk, S.ntiles, N->part, N->dbpart);
+        NHIP(hipGetLastError());
+        const int tot = 27 * kCin[layer] * kCout[layer] + kCout[layer];
+        hipLaunchKernelGGL(reduce_wgrad, dim3((tot + 255) / 256), dim3(256), 0, st, N->part, N->dbpart, nb,
+                           kCin[layer], kCout[layer], N->grads + offW(layer), N->grads + offB(layer));
+        NHIP(hipGetLastError());
+        return MFFV_OK;
+    };
+    // layer 4: dy4 -> grad of h3 (masked by h3 > 0) into g1
+    ConvArgs a{};
+    a.in = N->dy4;
+    a.W = N->W + kWb4;
+    a.out16 = N->g1;
+    a.below = N->h3;
+    if ((rc = conv<2, kGradMasked>(S, a, st))) return rc;
+    if ((rc = wgrad(3, N->h3, N->dy4))) return rc;
+    // layer 3: g1 -> grad of h2 into g2
+    a.in = N->g1;
+    a.W = N->W + kWb3;
+    a.out16 = N->g2;
+    a.below = N->h2;
+    if ((rc = conv<16, kGradMasked>(S, a, st))) return rc;
+    if ((rc = wgrad(2, N->h2, N->g1))) return rc;
+    // layer 2: g2 -> grad of h1 into g1
+    a.in = N->g2;
+    a.W = N->W + kWb2;
+    a.out16 = N->g1;
+    a.below = N->h1;
+    if ((rc = conv<16, kGradMasked>(S, a, st))) return rc;
+    if ((rc = wgrad(1, N->h1, N->g2))) return rc;
+    // layer 1
+    return wgrad(0, N->x0, N->g1);
+}
+
+int refresh_weights(mffv_net* N, hipStream_t st) {
+    hipLaunchKernelGGL(prepare_weights, dim3((kWTotal + 255) / 256), dim3(256), 0, st, N->params, N->W);
+    NHIP(hipGetLastError());
+    return MFFV_OK;
+}
+
+int check_net(const mffv_net* N) {
+    if (!N) return nfail(MFFV_EINVAL, "network handle is NULL");
+    return MFFV_OK;
+}
+
+int check_shape(int nx, int ny, int nz) {
+    if (nx < 1 || ny < 1 || nz < 1 || (int64_t)nx * ny * nz >= (int64_t(1) << 31))
+        return nfail(MFFV_EINVAL, "bad grid shape");
+    return MFFV_OK;
+}
+
+// One pass of forward + energy-norm loss (+ backward) for a training pair on
+// the operator (g, c). Fills N->loss (device).
+int loss_pass(mffv_net* N, const Shape& S, const Coef& c, const March& m, const float* dinv,
+              const uint8_t* dmask, const float* feat, const float* r_hat, const float* target,
+              bool grads, hipStream_t st) {
+    int rc;
+    const int64_t n = S.g.n;
+    const int nb = nblocks_for(n, kRedBlocks);
+    hipLaunchKernelGGL(nn_input, dim3(nb), dim3(kThreads), 0, st, n, r_hat, (const float*)nullptr, feat,
+                       (const float*)nullptr, 0, 1.f, (float*)nullptr, N->x0, dmask);
+    NHIP(hipGetLastError());
+    ConvArgs last{};
+    last.out32 = N->y;
+    if ((rc = forward(N, S, true, kFinal, last, st))) return rc;
+    hipLaunchKernelGGL(loss_delta, dim3(nb), dim3(kThreads), 0, st, n, r_hat, (const float*)N->y, target, dinv,
+                       dmask, N->t1, N->red);
+    NHIP(hipGetLastError());
+    StencilIO<float> io;
+    io.src = N->t1;
+    io.out = N->t2;
+    NHIP(launch_stencil_f32(kApply, S.g, c, io, m, st));
+    hipLaunchKernelGGL(loss_grad, dim3(nb), dim3(kThreads), 0, st, n, r_hat, (const float*)N->y, target, dinv,
+                       dmask, (const float*)N->t2, (const float*)N->red, nb, N->dy4, N->red + kRedBlocks);
+    NHIP(hipGetLastError());
+    hipLaunchKernelGGL(loss_final, dim3(1), dim3(kThreads), 0, st, (const float*)(N->red + kRedBlocks),
+                       (const float*)N->red, nb, N->loss);
+    NHIP(hipGetLastError());
+    if (grads) return backward(N, S, st);
+    return MFFV_OK;
+}
+
+}  // namespace
 
 namespace mffv {
 
-int nn_precondition(const mffv_net*, const Geom&, const float*, const float*, const uint8_t*,
-                    float*, const float*, int, CgState<float>*, hipStream_t) {
-    return MFFV_EINVAL;
+int nn_precondition(const mffv_net* Nc, const Geom& g, const float* r, const float* dinv,
+                    const uint8_t* dmask, float* z, const float* pb, int nb_b, const float* feat,
+                    float n_u, hipStream_t s) {
+    mffv_net* N = const_cast<mffv_net*>(Nc);
+    if (g.n > N->cap) return nfail(MFFV_ESTATE, "network workspace not prepared for this grid");
+    const Shape S = shape_of(g.nx, g.ny, g.nz);
+    hipLaunchKernelGGL(nn_input, dim3(nblocks_for(g.n, kRedBlocks)), dim3(kThreads), 0, s, g.n, r, dinv, feat,
+                       pb, nb_b, n_u, N->sscale, N->x0, (const uint8_t*)nullptr);
+    NHIP(hipGetLastError());
+    ConvArgs last{};
+    last.out32 = z;
+    last.r = r;
+    last.dinv = dinv;
+    last.dmask = dmask;
+    last.sscale = N->sscale;
+    return forward(N, S, false, kPrecond, last, s);
+}
+
+int nn_feature(const Geom& g, const float* dinv, const uint8_t* dmask, float n_u, float* part,
+               float* feat, hipStream_t s) {
+    const int nb = nblocks_for(g.n, kRedBlocks);
+    hipLaunchKernelGGL(logd_partials, dim3(nb), dim3(kThreads), 0, s, g.n, dinv, dmask, part);
+    NHIP(hipGetLastError());
+    hipLaunchKernelGGL(feature_kernel, dim3(nb), dim3(kThreads), 0, s, g.n, dinv, dmask, (const float*)part, nb,
+                       n_u, feat);
+    NHIP(hipGetLastError());
+    return MFFV_OK;
+}
+
+int nn_loss(mffv_net* N, const Geom& g, const Coef& c, const March& m, const float* dinv,
+            const uint8_t* dmask, const float* feat, const float* r_hat, const float* target,
+            bool grads, hipStream_t st) {
+    int rc = ensure_ws(N, g.n, true);
+    if (rc) return rc;
+    return loss_pass(N, shape_of(g.nx, g.ny, g.nz), c, m, dinv, dmask, feat, r_hat, target, grads, st);
+}
+
+int nn_adam(mffv_net* N, float lr, hipStream_t st) {
+    N->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float bc1 = 1.f - std::pow(b1, (float)N->step), bc2 = 1.f - std::pow(b2, (float)N->step);
+    hipLaunchKernelGGL(adam_kernel, dim3((kNParams + 255) / 256), dim3(256), 0, st, kNParams, N->params,
+                       (const float*)N->grads, N->m, N->v, lr, b1, b2, eps, bc1, bc2);
+    NHIP(hipGetLastError());
+    return refresh_weights(N, st);
+}
+
+const double* nn_loss_ptr(const mffv_net* N) { return N->loss; }
+
+int nn_prepare(const mffv_net* Nc, int64_t n) {
+    mffv_net* N = const_cast<mffv_net*>(Nc);
+    const int64_t before = N->cap;
+    const void* h1 = N->h1;
+    int rc = ensure_ws(N, n, false);
+    if (rc) return rc;
+    if (N->cap != before || N->h1 != h1) N->ws_gen += 1;
+    return N->ws_gen;
 }
 
 }  // namespace mffv
+
+extern "C" {
+
+int mffv_net_create(const float* params, mffv_net** out) {
+    if (!out) return nfail(MFFV_EINVAL, "out is NULL");
+    mffv_net* N = new (std::nothrow) mffv_net();
+    if (!N) return nfail(MFFV_ENOMEM, "host allocation failed");
+    int rc;
+    if ((rc = nalloc(&N->params, kNParams)) || (rc = nalloc(&N->grads, kNParams)) ||
+        (rc = nalloc(&N->m, kNParams)) || (rc = nalloc(&N->v, kNParams)) ||
+        (rc = nalloc(&N->W, kWTotal)) ||
+        (rc = nalloc(&N->part, (size_t)512 * 27 * 256)) || (rc = nalloc(&N->dbpart, (size_t)512 * 16)) ||
+        (rc = nalloc(&N->red, 2 * (size_t)kRedBlocks)) || (rc = nalloc(&N->sscale, 1)) ||
+        (rc = nalloc(&N->loss, 1))) {
+        mffv_net_destroy(N);
+        return nfail(rc, "network allocation failed");
+    }
+    std::vector<float> zero(kNParams, 0.f);
+    const float* src = params ? params : zero.data();
+    for (int i = 0; i < kNParams; ++i)
+        if (!std::isfinite(src[i])) {
+            mffv_net_destroy(N);
+            return nfail(MFFV_EINVAL, "non-finite network parameter");
+        }
+    if (hipMemcpy(N->params, src, kNParams * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(N->m, 0, kNParams * sizeof(float)) != hipSuccess ||
+        hipMemset(N->v, 0, kNParams * sizeof(float)) != hipSuccess ||
+        hipMemset(N->grads, 0, kNParams * sizeof(float)) != hipSuccess ||
+        refresh_weights(N, nullptr) != MFFV_OK || hipDeviceSynchronize() != hipSuccess) {
+        mffv_net_destroy(N);
+        return nfail(MFFV_EHIP, "network initialisation failed");
+    }
+    *out = N;
+    return MFFV_OK;
+}
+
+void mffv_net_destroy(mffv_net* N) {
+    if (!N) return;
+    (void)hipDeviceSynchronize();
+    free_ws(N);
+    nfree(N->params); nfree(N->grads); nfree(N->m); nfree(N->v); nfree(N->W); nfree(N->part);
+    nfree(N->dbpart); nfree(N->red); nfree(N->sscale); nfree(N->loss);
+    delete N;
+}
+
+int mffv_net_num_params(void) { return kNParams; }
+
+int mffv_net_get_params(const mffv_net* N, float* params, float* grads) {
+    int rc = check_net(N);
+    if (rc) return rc;
+    if (!params && !grads) return nfail(MFFV_EINVAL, "nothing to copy");
+    NHIP(hipDeviceSynchronize());
+    if (params) NHIP(hipMemcpy(params, N->params, kNParams * sizeof(float), hipMemcpyDeviceToHost));
+    if (grads) NHIP(hipMemcpy(grads, N->grads, kNParams * sizeof(float), hipMemcpyDeviceToHost));
+    return MFFV_OK;
+}
+
+int mffv_net_set_params(mffv_net* N, const float* params) {
+    int rc = check_net(N);
+    if (rc) return rc;
+    if (!params) return nfail(MFFV_EINVAL, "params is NULL");
+    for (int i = 0; i < kNParams; ++i)
+        if (!std::isfinite(params[i])) return nfail(MFFV_EINVAL, "non-finite network parameter");
+    NHIP(hipDeviceSynchronize());
+    NHIP(hipMemcpy(N->params, params, kNParams * sizeof(float), hipMemcpyHostToDevice));
+    NHIP(hipMemset(N->m, 0, kNParams * sizeof(float)));
+    NHIP(hipMemset(N->v, 0, kNParams * sizeof(float)));
+    N->step = 0;
+    if ((rc = refresh_weights(N, nullptr))) return rc;
+    NHIP(hipDeviceSynchronize());
+    return MFFV_OK;
+}
+
+int mffv_nn_forward(mffv_net* N, int nx, int ny, int nz, const float* r_hat, const float* feat,
+                    float* out, void* stream) {
+    int rc;
+    if ((rc = check_net(N)) || (rc = check_shape(nx, ny, nz))) return rc;
+    if (!r_hat || !feat || !out) return nfail(MFFV_EINVAL, "NULL array");
+    const Shape S = shape_of(nx, ny, nz);
+    if ((rc = ensure_ws(N, S.g.n, true))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(nn_input, dim3(nblocks_for(S.g.n, kRedBlocks)), dim3(kThreads), 0, st, S.g.n, r_hat,
+                       (const float*)nullptr, feat, (const float*)nullptr, 0, 1.f, (float*)nullptr, N->x0,
+                       (const uint8_t*)nullptr);
+    NHIP(hipGetLastError());
+    ConvArgs last{};
+    last.out32 = out;
+    return forward(N, S, true, kFinal, last, st);
+}
+
+}  // extern "C"

@@ -60,6 +60,7 @@ __global__ __launch_bounds__(kThreads) void phase_b(int64_t n, VecIO<real> io) {
         }
     }
     const bool jac = (MODE == kBJacobi) || (MODE == kBInit && io.jacobi);
+    const bool dd = !jac && io.dinv_dot;
     constexpr int W = VT<real>::W;
     const int64_t nv = n / W;
     real rr = 0, rz = 0, bb = 0;
@@ -72,6 +73,8 @@ __global__ __launch_bounds__(kThreads) void phase_b(int64_t n, VecIO<real> io) {
             const real z = (real)io.dinv[idx] * r;
             io.z[idx] = z;
             rz += r * z;
+        } else if (dd) {
+            rz += r * ((real)io.dinv[idx] * r);
         }
         if (MODE == kBInit && !io.dmask[idx]) {
             const real b = io.b_f64 ? (real) static_cast<const double*>(io.b)[idx]
@@ -166,6 +169,40 @@ __global__ void finalize(int64_t n, real* x, const real* p0, const real* p1,
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
         x[e] += a * p[e];
+}
+
+// Training pair of the learned preconditioner in the Jacobi-scaled space from
+// a residual r (0 on Dirichlet cells): s^2 = sum(dinv r^2) / n_U,
+// r_hat = sqrt(dinv) r / s and target = (x* - x) / (sqrt(dinv) s), the scaled
+// error (A~ target = r_hat with A~ = D^-1/2 A D^-1/2); both 0 on Dirichlet cells.
+__global__ __launch_bounds__(kThreads) void harvest_scale(int64_t n, const float* r, const float* x,
+                                                          const double* xstar, const float* dinv,
+                                                          const uint8_t* dmask, const float* part,
+                                                          int nb, float n_u, float* r_hat,
+                                                          float* target, float* s_out) {
+    __shared__ float red[kThreads / kWave];
+    const float rr = sum_partials(part, nb, red);
+    const float s = rr > 0.f ? sqrtf(rr / n_u) : 1.f;
+    const float inv = 1.f / s;
+    if (first_thread() && s_out) *s_out = s;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x; l < n; l += stride) {
+        const bool d = dmask[l] != 0;
+        const double sd = sqrt((double)dinv[l]);
+        r_hat[l] = d ? 0.f : (float)(sd * r[l]) * inv;
+        target[l] = d ? 0.f : (float)((xstar[l] - (double)x[l]) / (sd * (double)s));
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void dinv_sq_partials(int64_t n, const float* v,
+                                                             const float* dinv, float* part) {
+    __shared__ float red[kThreads / kWave];
+    float s = 0.f;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x; l < n; l += stride)
+        s += dinv[l] * v[l] * v[l];
+    const float t = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 __global__ __launch_bounds__(kThreads) void sum_partials_kernel(const double* parts, int n,
@@ -377,6 +414,18 @@ hipError_t launch_finalize_f32(int64_t n, float* x, const float* p0, const float
 hipError_t launch_finalize_f64(int64_t n, double* x, const double* p0, const double* p1,
                                const CgState<double>* st, hipStream_t s) {
     hipLaunchKernelGGL((finalize<double>), dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, x, p0, p1, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_harvest(int64_t n, const float* r, const float* x, const double* xstar,
+                          const float* dinv, const uint8_t* dmask, float* part, float n_u,
+                          float* r_hat, float* target, float* s_out, hipStream_t s) {
+    const int nb = grid_for(n, 1, 1024);
+    hipLaunchKernelGGL(dinv_sq_partials, dim3(nb), dim3(kThreads), 0, s, n, r, dinv, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(harvest_scale, dim3(nb), dim3(kThreads), 0, s, n, r, x, xstar, dinv, dmask,
+                       (const float*)part, nb, n_u, r_hat, target, s_out);
     return hipGetLastError();
 }
 

@@ -1,0 +1,218 @@
+"""Driver of the learned preconditioner: harvest training pairs from the
+solver's own Jacobi-PCG runs and train the network, through the C ABI.
+
+Every arithmetic step runs in libmffv (residuals, scaling, network forward and
+backward, Adam); this module only orders the calls and keeps the tensors.
+
+Everything happens in the Jacobi-scaled space A~ = D^-1/2 A D^-1/2. For a
+scaled residual r_hat the ideal output is the error A~^-1 r_hat; the network is
+trained so that z = r_hat + N(r_hat, feature) minimises the energy functional
+z' A~ z - 2 z' r_hat, whose minimiser is that error, so a residual alone is a
+training example and no reference solve is needed (with a known error target
+the same loss is the energy norm of the prediction error). With N = 0 the
+preconditioner is Jacobi.
+
+Training inputs. Residuals of Jacobi-PCG iterates (``harvest``) concentrate on
+the smooth error modes that a 9x9x9 receptive field cannot invert, and a
+network trained on them alone amplifies smooth components and makes flexible
+CG diverge. The recipe used here (``train_preconditioner``) therefore trains
+on white-noise residuals over the held-in operators and then adds residuals
+from the solver's own flexible-CG runs with the current network (``dagger``);
+harvested Jacobi pairs remain available as a validation set (their energy
+loss is reported by ``evaluate_loss``).
+"""
+from __future__ import annotations
+
+import random
+from dataclasses import dataclass
+
+import torch
+
+from . import mffv
+
+DEFAULT_ITERS = (1, 2, 4, 8, 16, 32, 64, 128, 256, 512)
+
+
+@dataclass
+class Sample:
+    grid: mffv.Grid          # the system's operator (kept alive with the pair)
+    r_hat: torch.Tensor
+    target: torch.Tensor
+    iteration: int
+
+
+def reference_solution(grid: mffv.Grid, b: torch.Tensor, tol: float = 1e-10) -> torch.Tensor:
+    x = torch.zeros(grid.n, dtype=torch.float64, device=b.device)
+    st, info = mffv.cg_solve_f64(grid, b.double(), x,
+                                 mffv.default_opts(tol=tol, precision=mffv.FP32_IR,
+                                                   precond=mffv.PRECOND_JACOBI))
+    if st != mffv.OK:
+        raise RuntimeError(f"reference solve failed: {info}")
+    return x
+
+
+def harvest(grid: mffv.Grid, b: torch.Tensor, iters=DEFAULT_ITERS, x_star=None) -> list:
+    """Training pairs at the given Jacobi-PCG iteration counts of one system."""
+    if x_star is None:
+        x_star = reference_solution(grid, b)
+    out = []
+    x = torch.zeros(grid.n, dtype=torch.float32, device=b.device)
+    for k in iters:
+        x.zero_()
+        st, info = mffv.cg_solve(grid, b, x, mffv.default_opts(
+            tol=1e-12, max_iter=k, precond=mffv.PRECOND_JACOBI))
+        if info["iters"] < k:       # converged before k: no more distinct pairs
+            break
+        r_hat, target = (torch.empty(grid.n, dtype=torch.float32, device=b.device)
+                         for _ in range(2))
+        mffv.harvest_pair(grid, b, x, x_star, r_hat, target)
+        out.append(Sample(grid, r_hat, target, k))
+    return out
+
+
+def white_samples(systems, count: int, seed: int) -> list:
+    """``count`` white-noise residual samples spread over the systems' operators."""
+    from synth import white_residuals
+    out = []
+    per = -(-count // len(systems))
+    for i, (grid, _b) in enumerate(systems):
+        fields = white_residuals(grid.shape, per, seed + i)
+        for f in fields:
+            if len(out) == count:
+                break
+            out.append(Sample(grid, torch.from_numpy(f.ravel()).cuda(), None, -1))
+    return out
+
+
+def dagger(net: mffv.Net, systems, iters=(2, 8, 32, 64, 128)) -> list:
+    """Residual samples from the solver's own flexible-CG runs with ``net``."""
+    out = []
+    for grid, b in systems:
+        x = torch.zeros(grid.n, dtype=torch.float32, device=b.device)
+        for k in iters:
+            x.zero_()
+            st, info = mffv.cg_solve(grid, b, x, mffv.default_opts(
+                tol=1e-12, max_iter=k, precond=mffv.PRECOND_LEARNED, net=net))
+            if info["iters"] < k:
+                break
+            r_hat, target = (torch.empty(grid.n, dtype=torch.float32, device=b.device)
+                             for _ in range(2))
+            mffv.harvest_pair(grid, b, x, x.double(), r_hat, target)
+            out.append(Sample(grid, r_hat, None, k))
+    return out
+
+
+LAYERS = ((2, 16), (16, 16), (16, 16), (16, 1))
+
+
+def init_params(seed: int = 0):
+    """He-normal weights with the last layer zero (the network starts as
+    Jacobi), zero biases; the library's parameter layout (W[27][cin][cout], b)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    parts = []
+    for li, (ci, co) in enumerate(LAYERS):
+        W = rng.normal(0.0, np.sqrt(2.0 / (27 * ci)), size=27 * ci * co)
+        if li == len(LAYERS) - 1:
+            W[:] = 0.0
+        parts += [W, np.zeros(co)]
+    p = np.concatenate(parts).astype(np.float32)
+    assert p.size == mffv.net_num_params()
+    return p
+
+
+def fcg_iterations(net: mffv.Net, systems, max_iter: int = 20000) -> int:
+    """Total flexible-CG iterations to 1e-6 over the systems (validation metric);
+    a system that does not converge counts max_iter."""
+    tot = 0
+    for grid, b in systems:
+        x = torch.zeros(grid.n, dtype=torch.float32, device=b.device)
+        st, info = mffv.cg_solve(grid, b, x, mffv.default_opts(
+            precond=mffv.PRECOND_LEARNED, net=net, max_iter=max_iter))
+        tot += info["iters"] if st == mffv.OK else max_iter
+    return tot
+
+
+def train_preconditioner(systems, validation=None, n_white: int = 256, epochs: int = 24,
+                         lr: float = 2e-3, lr_final: float = 1e-4, dagger_rounds: int = 2,
+                         dagger_epochs: int = 6, seed: int = 0, log=None) -> mffv.Net:
+    """The training recipe on held-in systems [(grid, b), ...].
+
+    White-noise residuals with the energy functional, then ``dagger_rounds``
+    rounds that add residuals of the solver's own flexible-CG runs with the
+    current network. After every epoch the network is scored by the total
+    flexible-CG iteration count on the validation systems (default: the first
+    two held-in systems) and the best parameters so far are kept; the zero
+    network (Jacobi) is the first candidate, so the result is never worse
+    than Jacobi on the validation systems.
+    """
+    import numpy as np
+    validation = systems[:2] if validation is None else validation
+    p0 = init_params(seed)
+    net = mffv.net_create(p0)
+    zero = p0.copy()
+    zero[:] = 0.0
+    best_p = p0.copy()                      # last layer zero: the network is Jacobi
+    best = fcg_iterations(net, validation)
+    if log:
+        log(f"validation FCG iterations with the zero network: {best}")
+
+    def run(samples, n_ep, lr0, lr1, tag, sd):
+        nonlocal best, best_p
+        rng = random.Random(sd)
+        order = list(range(len(samples)))
+        total, step = n_ep * len(samples), 0
+        for ep in range(n_ep):
+            rng.shuffle(order)
+            for i in order:
+                s = samples[i]
+                cur = lr0 * (lr1 / lr0) ** (step / max(1, total - 1))
+                mffv.nn_train_step(net, s.grid, s.r_hat, s.target, cur)
+                step += 1
+            it = fcg_iterations(net, validation)
+            if it < best:
+                best = it
+                best_p, _ = mffv.net_get_params(net)
+            if log:
+                log(f"{tag} epoch {ep}: validation FCG iterations {it} (best {best})")
+
+    run(white_samples(systems, n_white, seed), epochs, lr, lr_final, "white", seed)
+    for r in range(dagger_rounds):
+        mffv.net_set_params(net, best_p)
+        extra = dagger(net, systems)
+        more = white_samples(systems, n_white // 2, seed + 1000 * (r + 1))
+        run(extra + more, dagger_epochs, lr / 4, lr_final, f"dagger{r}", seed + r + 1)
+    mffv.net_set_params(net, best_p)
+    del zero, np
+    return net
+
+
+def train(net: mffv.Net, samples: list, epochs: int = 4, lr: float = 1e-3, seed: int = 0,
+          log_every: int = 0, lr_final: float | None = None):
+    """Adam over the samples in shuffled order; returns the per-epoch mean loss
+    (samples with target None use the energy functional)."""
+    rng = random.Random(seed)
+    order = list(range(len(samples)))
+    hist = []
+    step, total = 0, epochs * len(samples)
+    for ep in range(epochs):
+        rng.shuffle(order)
+        losses = []
+        for i in order:
+            s = samples[i]
+            frac = step / max(1, total - 1)
+            cur = lr if lr_final is None else lr * (lr_final / lr) ** frac
+            loss = mffv.nn_train_step(net, s.grid, s.r_hat, s.target, cur, want_loss=True)
+            losses.append(loss)
+            step += 1
+            if log_every and step % log_every == 0:
+                print(f"[train] step {step}/{total} loss {loss:.4f}", flush=True)
+        hist.append(sum(losses) / len(losses))
+    return hist
+
+
+def evaluate_loss(net: mffv.Net, samples: list) -> float:
+    tot = 0.0
+    for s in samples:
+        tot += mffv.nn_loss_grad(net, s.grid, s.r_hat, s.target)
+    return tot / max(1, len(samples))

@@ -77,6 +77,19 @@ def _declare(lib):
                                                  ctypes.POINTER(_P), ctypes.POINTER(_P),
                                                  ctypes.POINTER(Opts), ctypes.POINTER(Info)]),
         "mffv_copy_probe": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
+        "mffv_net_num_params": (ctypes.c_int, []),
+        "mffv_net_create": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
+        "mffv_net_destroy": (None, [_P]),
+        "mffv_net_get_params": (ctypes.c_int, [_P, _P, _P]),
+        "mffv_net_set_params": (ctypes.c_int, [_P, _P]),
+        "mffv_nn_forward": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P,
+                                           _P]),
+        "mffv_nn_loss_grad": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
+        "mffv_nn_train_step": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_float,
+                                              ctypes.POINTER(ctypes.c_double)]),
+        "mffv_grid_feature": (ctypes.c_int, [_P, _P]),
+        "mffv_harvest_pair": (ctypes.c_int, [_P, _P, _P, _P, _P, _P,
+                                             ctypes.POINTER(ctypes.c_float)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -138,11 +151,15 @@ def _stream(stream):
 
 
 def default_opts(**kw) -> Opts:
+    """mffv_opts with the library defaults; ``net=`` takes a :class:`Net`."""
     o = Opts()
     lib().mffv_default_opts(ctypes.byref(o))
     for k, v in kw.items():
         if not hasattr(o, k):
             raise KeyError(k)
+        if k == "net":
+            o._net = v
+            v = v.handle if v is not None else None
         setattr(o, k, v)
     return o
 
@@ -250,3 +267,107 @@ def cg_solve_batched(grids, b, x, opts: Opts | None = None):
 
 def copy_probe(dst, src, nbytes: int, stream=None) -> None:
     _check(lib().mffv_copy_probe(_ptr(dst), _ptr(src), nbytes, _stream(stream)))
+
+
+# --- learned preconditioner ------------------------------------------------
+
+
+class Net:
+    """Owning wrapper of an ``mffv_net*`` (network weights on the device)."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    def close(self):
+        if self.handle:
+            lib().mffv_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def net_num_params() -> int:
+    return lib().mffv_net_num_params()
+
+
+def _host_f32(a, n, name):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32).ravel()
+    if a.size != n:
+        raise ValueError(f"{name} must have {n} values")
+    return a
+
+
+def net_create(params=None) -> Net:
+    h = _P()
+    n = net_num_params()
+    arr = None if params is None else _host_f32(params, n, "params")
+    _check(lib().mffv_net_create(None if arr is None else arr.ctypes.data, ctypes.byref(h)))
+    net = Net(h.value)
+    net._keep = arr
+    return net
+
+
+def net_destroy(net: Net) -> None:
+    net.close()
+
+
+def net_get_params(net: Net):
+    """(params, grads) as host float32 arrays."""
+    import numpy as np
+    n = net_num_params()
+    p = np.empty(n, dtype=np.float32)
+    g = np.empty(n, dtype=np.float32)
+    _check(lib().mffv_net_get_params(net.handle, p.ctypes.data, g.ctypes.data))
+    return p, g
+
+
+def net_set_params(net: Net, params) -> None:
+    arr = _host_f32(params, net_num_params(), "params")
+    _check(lib().mffv_net_set_params(net.handle, arr.ctypes.data))
+
+
+def nn_forward(net: Net, shape, r_hat, feat, out, stream=None) -> None:
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    _check(lib().mffv_nn_forward(net.handle, nx, ny, nz, _ptr(r_hat, torch.float32, n, "r_hat"),
+                                 _ptr(feat, torch.float32, n, "feat"),
+                                 _ptr(out, torch.float32, n, "out"), _stream(stream)))
+
+
+def nn_loss_grad(net: Net, grid: Grid, r_hat, target) -> float:
+    """Energy-norm loss of one pair on the grid's operator; the gradient stays in the net."""
+    loss = ctypes.c_double()
+    n = grid.n
+    _check(lib().mffv_nn_loss_grad(net.handle, grid.handle, _ptr(r_hat, torch.float32, n, "r_hat"),
+                                   _ptr(target, torch.float32, n, "target"), ctypes.byref(loss)))
+    return loss.value
+
+
+def nn_train_step(net: Net, grid: Grid, r_hat, target, lr: float, want_loss: bool = False):
+    loss = ctypes.c_double()
+    n = grid.n
+    _check(lib().mffv_nn_train_step(net.handle, grid.handle, _ptr(r_hat, torch.float32, n, "r_hat"),
+                                    _ptr(target, torch.float32, n, "target"), float(lr),
+                                    ctypes.byref(loss) if want_loss else None))
+    return loss.value if want_loss else None
+
+
+def grid_feature(grid: Grid, feat) -> None:
+    _check(lib().mffv_grid_feature(grid.handle, _ptr(feat, torch.float32, grid.n, "feat")))
+
+
+def harvest_pair(grid: Grid, b, x, x_star, r_hat, target) -> float:
+    """Fill the scaled (r_hat, target) pair for iterate x; returns the scale s."""
+    s = ctypes.c_float()
+    n = grid.n
+    _check(lib().mffv_harvest_pair(grid.handle, _ptr(b, torch.float32, n, "b"),
+                                   _ptr(x, torch.float32, n, "x"),
+                                   _ptr(x_star, torch.float64, n, "x_star"),
+                                   _ptr(r_hat, torch.float32, n, "r_hat"),
+                                   _ptr(target, torch.float32, n, "target"), ctypes.byref(s)))
+    return s.value

@@ -14,4 +14,5 @@ from .perm import (  # noqa: F401
     Workload,
     WORKLOADS,
     workload_field,
+    white_residuals,
 )

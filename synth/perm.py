@@ -146,3 +146,13 @@ def workload_field(w: Workload, seed: int | None = None, shape=None) -> np.ndarr
     if w.kind == "channelised":
         return channelised(shape, seed)
     raise ValueError(f"unknown field kind {w.kind!r}")
+
+
+def white_residuals(shape, count: int, seed: int) -> np.ndarray:
+    """``count`` independent standard-normal fields of the grid's shape (FP32),
+    each rescaled to unit RMS: random residuals for training the learned
+    preconditioner."""
+    rng = np.random.default_rng(seed)
+    out = rng.standard_normal((count,) + tuple(shape)).astype(np.float32)
+    out /= np.sqrt(np.mean(out.reshape(count, -1) ** 2, axis=1)).reshape((count,) + (1,) * len(shape))
+    return out

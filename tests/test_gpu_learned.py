@@ -1,0 +1,206 @@
+"""Learned preconditioner on the GPU against the network oracle, and flexible
+CG with it: forward and gradients match the oracle to BF16 tolerance, a zero
+network is Jacobi-PCG, a harmful network is caught by the safeguard, and a
+trained network reduces the iteration count of flexible CG."""
+import numpy as np
+import pytest
+
+from oracle import krylov, nn, tpfa
+from synth import channelised, lognormal_iid
+from gpu_problem import gpu_problem, OracleProblem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mf():
+    from paper_2408_03452_amd import mffv
+    assert torch.cuda.is_available()
+    mffv.lib()
+    return mffv
+
+
+def dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a).ravel()).to("cuda", dtype)
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def random_params(seed):
+    rng = np.random.default_rng(seed)
+    p = nn.init_params(seed=seed, last_scale=0.7).astype(np.float64)
+    layers = nn.unpack(p)
+    layers = [(W, rng.normal(0, 0.1, size=b.shape)) for W, b in layers]
+    return nn.pack(layers).astype(np.float32)
+
+
+SHAPE = (6, 10, 70)   # two z tiles (one ragged), ragged y tiles
+
+
+def test_forward_matches_oracle(mf):
+    rng = np.random.default_rng(1)
+    p = random_params(2)
+    r = rng.normal(size=SHAPE).astype(np.float32)
+    f = rng.normal(size=SHAPE).astype(np.float32)
+    net = mf.net_create(p)
+    out = torch.empty(r.size, dtype=torch.float32, device="cuda")
+    mf.nn_forward(net, SHAPE, dev(r), dev(f), out)
+    torch.cuda.synchronize()
+    ref, _, _ = nn.forward(p, r.astype(np.float64), f.astype(np.float64), bf16=True)
+    got = host(out).reshape(SHAPE)
+    assert np.linalg.norm(got - ref) <= 1e-2 * np.linalg.norm(ref)
+    assert np.max(np.abs(got - ref)) <= 5e-2 * np.max(np.abs(ref))
+    pb, _ = mf.net_get_params(net)
+    assert np.array_equal(pb, p)
+
+
+def oracle_feature(ref):
+    d = ref.diag()
+    u = ~ref.dmask.ravel()
+    ld = np.log(d)
+    return np.where(u, ld - ld[u].mean(), 0.0).reshape(ref.shape)
+
+
+def test_gradients_match_oracle(mf):
+    rng = np.random.default_rng(3)
+    p = random_params(4)
+    k = lognormal_iid(SHAPE, 1.0, 6)
+    g, _, _ = gpu_problem(mf, k, c=1e-2)
+    ref = OracleProblem(k, c=1e-2)
+    dmask = ref.dmask
+    r = np.where(dmask, 0, rng.normal(size=SHAPE)).astype(np.float32)
+    tgt = np.where(dmask, 0, rng.normal(size=SHAPE) + 0.5 * r).astype(np.float32)
+    net = mf.net_create(p)
+    loss = mf.nn_loss_grad(net, g, dev(r), dev(tgt))
+    _, grad = mf.net_get_params(net)
+    ref_loss, ref_g, _ = nn.loss_and_grads(p, r.astype(np.float64), oracle_feature(ref),
+                                           tgt.astype(np.float64), dmask,
+                                           nn.scaled_operator(ref.A, dmask))
+    assert abs(loss - ref_loss) <= 1e-2 * abs(ref_loss)
+    o = 0
+    for ci, co, _ in nn.LAYERS:
+        for size in (27 * ci * co, co):
+            a_, b_ = grad[o:o + size].astype(np.float64), ref_g[o:o + size]
+            assert np.linalg.norm(a_ - b_) <= 3e-2 * np.linalg.norm(b_) + 1e-6, (o, size)
+            o += size
+    assert o == nn.n_params()
+
+
+def test_feature_and_harvest_match_oracle(mf):
+    shape = (10, 12, 16)
+    k = channelised(shape, 7)
+    g, _, b = gpu_problem(mf, k, c=1e-3)
+    ref = OracleProblem(k, c=1e-3)
+    feat = torch.empty(k.size, dtype=torch.float32, device="cuda")
+    mf.grid_feature(g, feat)
+    assert np.allclose(host(feat), oracle_feature(ref).ravel(), atol=1e-5, rtol=0)
+    # a pair from a truncated Jacobi-PCG iterate, in the Jacobi-scaled space
+    x = torch.zeros(k.size, dtype=torch.float32, device="cuda")
+    mf.cg_solve(g, b, x, mf.default_opts(max_iter=5, tol=1e-12, precond=mf.PRECOND_JACOBI))
+    xstar = torch.from_numpy(ref.direct()).cuda()
+    rh, tg = (torch.empty(k.size, dtype=torch.float32, device="cuda") for _ in range(2))
+    s = mf.harvest_pair(g, b, x, xstar, rh, tg)
+    xh = host(x)
+    u = ~ref.dmask.ravel()
+    d = ref.diag()
+    r = np.where(u, ref.b - ref.A @ xh, 0.0)
+    s_ref = np.sqrt(np.sum(r * r / d) / u.sum())
+    assert abs(s - s_ref) <= 1e-5 * s_ref
+    want_r = r / np.sqrt(d) / s_ref
+    want_t = np.where(u, (ref.direct() - xh) * np.sqrt(d), 0.0) / s_ref
+    assert np.allclose(host(rh), want_r, rtol=0, atol=1e-4 * np.abs(want_r).max())
+    assert np.allclose(host(tg), want_t, rtol=0, atol=1e-4 * np.abs(want_t).max())
+    # consistency of the pair: A~ target = r_hat
+    As = nn.scaled_operator(ref.A, ref.dmask)
+    assert np.allclose(As(host(tg).reshape(shape)).ravel()[u], host(rh)[u], rtol=0,
+                       atol=1e-3 * np.abs(want_r).max())
+
+
+def test_fcg_with_zero_network_is_jacobi_pcg(mf):
+    shape = (24, 24, 24)
+    k = channelised(shape, 11)
+    g, _, b = gpu_problem(mf, k, c=1e-3)
+    net = mf.net_create(nn.init_params(seed=0, last_scale=0.0))
+    xj = torch.zeros(k.size, dtype=torch.float32, device="cuda")
+    st, ij = mf.cg_solve(g, b, xj, mf.default_opts(precond=mf.PRECOND_JACOBI))
+    xf = torch.zeros(k.size, dtype=torch.float32, device="cuda")
+    st2, iff = mf.cg_solve(g, b, xf, mf.default_opts(precond=mf.PRECOND_LEARNED, net=net))
+    assert st == st2 == mf.OK
+    assert abs(ij["iters"] - iff["iters"]) <= 2 and iff["fallbacks"] == 0
+    ref = OracleProblem(k, c=1e-3)
+    p = ref.direct()
+    assert np.linalg.norm(host(xf) - p) <= 5e-5 * np.linalg.norm(p)
+    # and the oracle's flexible CG with the Jacobi preconditioner agrees on the count
+    orc = krylov.fcg(ref.Auu, ref.bu, krylov.jacobi(ref.Auu), tol=1e-6, max_iter=5000)
+    assert abs(iff["iters"] - orc.iters) <= max(3, orc.iters // 20)
+
+
+def harmful_params(c):
+    """A network whose output is -c * r_hat: z = (1 - c) r / d, so z.r < 0 for c > 1."""
+    layers = [(np.zeros((27, ci, co)), np.zeros(co)) for ci, co, _ in nn.LAYERS]
+    layers[0][0][13, 0, 0], layers[0][0][13, 0, 1] = 1.0, -1.0     # relu(r), relu(-r)
+    for li in (1, 2):
+        layers[li][0][13, 0, 0] = layers[li][0][13, 1, 1] = 1.0
+    layers[3][0][13, 0, 0], layers[3][0][13, 1, 0] = -c, c
+    return nn.pack(layers).astype(np.float32)
+
+
+def test_safeguard_falls_back_to_jacobi(mf):
+    shape = (16, 16, 16)
+    k = lognormal_iid(shape, 1.0, 4)
+    g, _, b = gpu_problem(mf, k, c=1e-3)
+    ref = OracleProblem(k, c=1e-3)
+    net = mf.net_create(harmful_params(8.0))
+    x = torch.zeros(k.size, dtype=torch.float32, device="cuda")
+    st, info = mf.cg_solve(g, b, x, mf.default_opts(precond=mf.PRECOND_LEARNED, net=net))
+    assert st == mf.OK
+    # every iteration rejected the network's z (the final convergence check
+    # does not consume a preconditioned residual)
+    assert info["fallbacks"] == info["iters"]
+    xj = torch.zeros(k.size, dtype=torch.float32, device="cuda")
+    _, ij = mf.cg_solve(g, b, xj, mf.default_opts(precond=mf.PRECOND_JACOBI))
+    assert abs(info["iters"] - ij["iters"]) <= 2
+    p = ref.direct()
+    assert np.linalg.norm(host(x) - p) <= 5e-5 * np.linalg.norm(p)
+
+
+def test_training_gains_over_the_zero_network(mf):
+    # held-in 32^3 channelised systems: train with the library's recipe, then
+    # compare flexible CG with the trained network against the same solver with
+    # the zero network (Jacobi-PCG) and against plain CG on held-out fields
+    import time
+    from paper_2408_03452_amd import learned
+    shape = (32, 32, 32)
+    held_in = [gpu_problem(mf, channelised(shape, seed), c=1e-3) for seed in range(3000, 3008)]
+    systems = [(g, b) for g, _, b in held_in]
+    # validation pairs from Jacobi-PCG iterates (energy loss of the zero net)
+    pairs = learned.harvest(*systems[0])
+    zero = mf.net_create(learned.init_params(0))
+    net = learned.train_preconditioner(systems, validation=systems[:2], n_white=256, epochs=16,
+                                       dagger_rounds=1, log=print)
+    l0, l1 = learned.evaluate_loss(zero, pairs), learned.evaluate_loss(net, pairs)
+    res = {}
+    for seed in (3500, 3501):
+        g, _, b = gpu_problem(mf, channelised(shape, seed), c=1e-3)
+        for name, opts in (("zero", mf.default_opts(precond=mf.PRECOND_LEARNED, net=zero)),
+                           ("trained", mf.default_opts(precond=mf.PRECOND_LEARNED, net=net)),
+                           ("plain", mf.default_opts())):
+            x = torch.zeros(g.n, dtype=torch.float32, device="cuda")
+            mf.cg_solve(g, b, x, opts)
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, info = mf.cg_solve(g, b, x, opts)
+            torch.cuda.synchronize()
+            assert st == mf.OK and info["rel_res_recursive"] <= 1e-6
+            res.setdefault(name, []).append((info["iters"], time.perf_counter() - t0))
+    print(f"\n[learned] validation energy loss zero-net {l0:.4f} trained {l1:.4f}; "
+          f"held-out (iters, s): {res}")
+    assert l1 < l0
+    for (iz, _), (it, tt), (ip, tp) in zip(res["zero"], res["trained"], res["plain"]):
+        assert it < 0.8 * iz          # the trained network cuts iterations
+        assert tt < tp                # and beats plain CG in time to 1e-6

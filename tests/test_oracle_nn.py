@@ -36,27 +36,66 @@ def test_conv_identity_kernel_and_scipy_correlate():
 
 
 def test_gradients_match_central_differences():
+    from oracle import tpfa
+    from synth import lognormal_iid
     rng = np.random.default_rng(3)
     shape = (4, 3, 5)
     params = nn.init_params(seed=4, last_scale=0.5).astype(np.float64)
     params[-1] = 0.1
-    r = rng.normal(size=shape)
+    k = lognormal_iid(shape, 1.0, 5)
+    dmask, pd = tpfa.x_plane_dirichlet(shape)
+    A, _ = tpfa.assemble(*tpfa.transmissibility(k), 1e-2, dmask, pd)
+    As = nn.scaled_operator(A, dmask)
+    r = np.where(dmask, 0.0, rng.normal(size=shape))
     f = rng.normal(size=shape)
-    skip = rng.normal(size=shape) * 0.1
-    tgt = rng.normal(size=shape)
-    dmask = np.zeros(shape, dtype=bool)
-    dmask[0] = True
-    loss, g, _ = nn.loss_and_grads(params, r, f, skip, tgt, dmask, bf16=False)
+    tgt = np.where(dmask, 0.0, rng.normal(size=shape))
+    tgt *= np.sign(np.sum(tgt * r)) or 1.0
+    loss, g, _ = nn.loss_and_grads(params, r, f, tgt, dmask, As, bf16=False)
     idx = rng.choice(params.size, 40, replace=False)
     h = 1e-6
     for i in idx:
         p1, p2 = params.copy(), params.copy()
         p1[i] += h
         p2[i] -= h
-        l1 = nn.loss_and_grads(p1, r, f, skip, tgt, dmask, bf16=False)[0]
-        l2 = nn.loss_and_grads(p2, r, f, skip, tgt, dmask, bf16=False)[0]
+        l1 = nn.loss_and_grads(p1, r, f, tgt, dmask, As, bf16=False)[0]
+        l2 = nn.loss_and_grads(p2, r, f, tgt, dmask, As, bf16=False)[0]
         fd = (l1 - l2) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def test_energy_loss_special_cases():
+    import scipy.sparse as sp
+    from oracle import tpfa
+    from synth import lognormal_iid
+    # a diagonal operator: A~ = I, the scaled error equals the scaled residual,
+    # so the zero network (Jacobi) is exact and the loss is 0
+    shape = (3, 2, 2)
+    A = sp.diags(np.full(12, 3.0)).tocsr()
+    nod = np.zeros(shape, dtype=bool)
+    r = np.random.default_rng(0).normal(size=shape)
+    p0 = nn.init_params(seed=0, last_scale=0.0)
+    loss, _, out = nn.loss_and_grads(p0, r, np.zeros(shape), r, nod, nn.scaled_operator(A, nod),
+                                     bf16=False)
+    assert loss == 0.0 and np.all(out == 0)
+    # a TPFA operator: the zero network's loss is the energy of the Jacobi
+    # error relative to the error's energy, from a dense solve
+    shape = (4, 3, 3)
+    k = lognormal_iid(shape, 1.0, 2)
+    dmask, pd = tpfa.x_plane_dirichlet(shape)
+    A, _ = tpfa.assemble(*tpfa.transmissibility(k), 1e-2, dmask, pd)
+    u = ~dmask.ravel()
+    dis = 1.0 / np.sqrt(A.diagonal())
+    At = (dis[:, None] * A.toarray() * dis[None, :])[np.ix_(u, u)]
+    rt = np.random.default_rng(1).normal(size=u.sum())
+    et = np.linalg.solve(At, rt)
+    want = (rt - et) @ At @ (rt - et) / (et @ rt)
+    rg = np.zeros(shape)
+    rg.ravel()[u] = rt
+    eg = np.zeros(shape)
+    eg.ravel()[u] = et
+    got, _, _ = nn.loss_and_grads(p0, rg, np.zeros(shape), eg, dmask,
+                                  nn.scaled_operator(A, dmask), bf16=False)
+    assert abs(got - want) <= 1e-12 * want
 
 
 def test_input_gradient_of_a_single_convolution():
