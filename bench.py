@@ -69,6 +69,127 @@ def cpu_baseline(k, c, tol, crop=64):
     }
 
 
+def bench_batched(log_fn):
+    """64 independent uneven systems (dims uniform in [32, 128], log-normal
+    sigma 1.5, c log-uniform in [1e-4, 1e-2]) in one persistent launch under a
+    HIP graph, launch shape picked by the autotuner."""
+    import numpy as np
+    import torch
+    from paper_2408_03452_amd import mffv
+    from synth import batch_systems
+    systems = batch_systems()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        grids, bs, xs = [], [], []
+        for sy in systems:
+            nx, ny, nz = sy.shape
+            n = sy.k.size
+            kd = torch.from_numpy(sy.k.ravel()).cuda()
+            tx, ty, tz, b = (torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(4))
+            mffv.perm_to_trans(nx, ny, nz, kd, 1.0, tx, ty, tz, stream=s)
+            g = mffv.create_grid(nx, ny, nz, stream=s)
+            mffv.set_transmissibility(g, tx, ty, tz, accum_scalar=sy.c, b_out=b)
+            grids.append(g)
+            bs.append(b)
+            xs.append(torch.zeros(n, dtype=torch.float32, device="cuda"))
+        opts = mffv.default_opts(tol=1e-6)
+        tune = mffv.autotune_batched(grids, bs, xs, opts)
+        log_fn(f"batched autotune: {tune}")
+        for x in xs:
+            x.zero_()
+        mffv.cg_solve_batched(grids, bs, xs, opts)        # graph capture
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, infos = mffv.cg_solve_batched(grids, bs, xs, opts)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    cells = np.array([g.n for g in grids], dtype=np.float64)
+    iters = np.array([i["iters"] for i in infos], dtype=np.float64)
+    rr = np.array([i["rel_res_recursive"] for i in infos])
+    rt = np.array([i["rel_res_true"] for i in infos])
+    out = {"workload": "batched_64_uneven", "systems": len(grids), "cells_total": int(cells.sum()),
+           "status": st, "wall_ms": 1e3 * wall, "device_ms": infos[0]["ms"],
+           "cells_iter_per_s": float((cells * iters).sum() / wall),
+           "iters_min_max": [int(iters.min()), int(iters.max())],
+           "rel_res_recursive_max": float(rr.max()), "rel_res_true_max": float(rt.max()),
+           "rel_res_true_median": float(np.median(rt)), "launch": tune}
+    for g in grids:
+        g.close()
+    return out
+
+
+def bench_learned(log_fn, held_in: int, held_out: int):
+    """Learned preconditioner on the channelised two-facies field: train on
+    held-in 32^3 realisations (seeds 3000+), confirm at 128^3 against the zero
+    network, then time flexible CG against Jacobi-PCG and plain CG on held-out
+    128^3 realisations (seeds 3500+) to 1e-6."""
+    import numpy as np
+    import torch
+    from paper_2408_03452_amd import mffv, learned
+    from synth import channelised
+
+    def problem(k, stream):
+        nx, ny, nz = k.shape
+        n = k.size
+        kd = torch.from_numpy(np.ascontiguousarray(k).ravel()).cuda()
+        tx, ty, tz, b = (torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(4))
+        mffv.perm_to_trans(nx, ny, nz, kd, 1.0, tx, ty, tz, stream=stream)
+        g = mffv.create_grid(nx, ny, nz, stream=stream)
+        mffv.set_transmissibility(g, tx, ty, tz, accum_scalar=1e-3, b_out=b)
+        return g, b
+
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        t0 = time.perf_counter()
+        train = [problem(channelised((32, 32, 32), 3000 + i), s) for i in range(held_in)]
+        confirm = [problem(channelised((128, 128, 128), 3000 + i), s) for i in range(2)]
+        net = learned.train_preconditioner(train, validation=confirm, n_white=10 * held_in,
+                                           epochs=6, lr=2e-3, dagger_rounds=1, dagger_epochs=2,
+                                           log=log_fn)
+        t_train = time.perf_counter() - t0
+        log_fn(f"learned: trained on {held_in} held-in 32^3 realisations in {t_train:.1f} s")
+        zero = mffv.net_create(learned.init_params(0))
+        it_net = learned.fcg_iterations(net, confirm)
+        it_zero = learned.fcg_iterations(zero, confirm)
+        chosen = net if it_net < it_zero else zero
+        log_fn(f"learned: 128^3 held-in check, FCG iterations trained {it_net} vs zero net {it_zero}")
+        rows = {"plain": [], "jacobi": [], "learned_fcg": []}
+        for i in range(held_out):
+            g, b = problem(channelised((128, 128, 128), 3500 + i), s)
+            for name, opts in (("plain", mffv.default_opts()),
+                               ("jacobi", mffv.default_opts(precond=mffv.PRECOND_JACOBI)),
+                               ("learned_fcg", mffv.default_opts(precond=mffv.PRECOND_LEARNED,
+                                                                 net=chosen))):
+                x = torch.zeros(g.n, dtype=torch.float32, device="cuda")
+                if i == 0:
+                    mffv.cg_solve(g, b, x, opts)
+                    x.zero_()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                st, info = mffv.cg_solve(g, b, x, opts)
+                torch.cuda.synchronize()
+                rows[name].append((time.perf_counter() - t1, info["iters"], info["rel_res_recursive"],
+                                   info["rel_res_true"], st))
+            g.close()
+    out = {"workload": "channelised_128cube", "held_out": held_out, "held_in_32cube": held_in,
+           "train_s": t_train, "check_iters_trained_vs_zero": [it_net, it_zero],
+           "network": "trained" if chosen is net else "zero (Jacobi)"}
+    for name, r in rows.items():
+        t = np.array([v[0] for v in r])
+        it = np.array([v[1] for v in r])
+        out[name] = {"time_to_1e-6_s_median": float(np.median(t)), "iters_median": float(np.median(it)),
+                     "rel_res_recursive_max": float(max(v[2] for v in r)),
+                     "rel_res_true_max": float(max(v[3] for v in r)),
+                     "all_converged": all(v[4] == 0 for v in r)}
+    out["learned_vs_plain_speedup"] = out["plain"]["time_to_1e-6_s_median"] / out["learned_fcg"]["time_to_1e-6_s_median"]
+    out["learned_vs_jacobi_iters"] = out["learned_fcg"]["iters_median"] / out["jacobi"]["iters_median"]
+    for g, _ in train + confirm:
+        g.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +199,11 @@ def main(argv=None):
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-jacobi", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-held-out", type=int, default=10,
+                    help="held-out 128^3 realisations in the learned comparison (50 = full set)")
+    ap.add_argument("--learned-held-in", type=int, default=200)
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -177,6 +303,19 @@ def main(argv=None):
         del src, dst
     torch.cuda.synchronize()
 
+    batched = None
+    if not args.no_batched:
+        log("batched: 64 uneven systems, one persistent launch")
+        batched = bench_batched(log)
+        log(f"batched: {batched['cells_iter_per_s'] / 1e9:.1f} Gcell*iter/s, iters "
+            f"{batched['iters_min_max']}, worst true rel-res {batched['rel_res_true_max']:.2e}")
+    learned_res = None
+    if not args.no_learned:
+        learned_res = bench_learned(log, args.learned_held_in, args.learned_held_out)
+        log(f"learned: median time plain {learned_res['plain']['time_to_1e-6_s_median']*1e3:.1f} ms, "
+            f"jacobi {learned_res['jacobi']['time_to_1e-6_s_median']*1e3:.1f} ms, learned FCG "
+            f"{learned_res['learned_fcg']['time_to_1e-6_s_median']*1e3:.1f} ms")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, 64^3 crop)")
@@ -210,6 +349,8 @@ def main(argv=None):
         "apply_GBps": apply_gbps,
         "copy_probe_GBps": copy_gbps,
         "jacobi_pcg": jac,
+        "batched": batched,
+        "learned": learned_res,
         "roofline": {
             "kernel": "stencil_v4<apply> (mffv_apply)",
             "bound": "hbm",

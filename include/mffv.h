@@ -237,6 +237,18 @@ int mffv_net_create(const float* params, mffv_net** out);
 /* Release a network. NULL is a no-op. */
 void mffv_net_destroy(mffv_net* net);
 
+/* Activation of the three hidden layers: 1 = ReLU (default), 0 = identity
+ * (the network is then a learned linear operator of its input channels).
+ * Synchronizes the device. */
+int mffv_net_set_activation(mffv_net* net, int relu);
+
+/* Training loss: 0 = energy norm of the prediction error (the energy functional
+ * when no target is given; default), 1 = residual space
+ * ||A~ z - r_hat||^2 / ||r_hat||^2 (the sparse-approximate-inverse objective,
+ * which weights smooth error modes by their squared eigenvalue; the target is
+ * not used). */
+int mffv_net_set_loss(mffv_net* net, int kind);
+
 /* Copy the FP32 parameters and/or the last computed gradient to host arrays
  * of mffv_net_num_params() floats (either may be NULL). Synchronizes. */
 int mffv_net_get_params(const mffv_net* net, float* params, float* grads);
@@ -288,6 +300,52 @@ int mffv_grid_feature(mffv_grid* grid, float* feat);
  */
 int mffv_harvest_pair(mffv_grid* grid, const float* b, const float* x, const double* x_star,
                       float* r_hat, float* target, float* scale);
+
+/* Launch shape chosen for a grid's stencil kernels. */
+typedef struct {
+    int ci;          /* planes a block marches through along x */
+    int remap;       /* 1: XCD-aware block order */
+    int vec;         /* cells per thread along z (4 or 1) */
+    int blocks;      /* blocks per launch */
+    double apply_us; /* measured apply time of the chosen shape (microseconds) */
+    int candidates;  /* shapes timed (0 when read from the cache) */
+} mffv_tune_result;
+
+/*
+ * Set the launch shape of the grid's FP32 stencil kernels by hand: ci planes per
+ * block (0 = the library's default for the shape) and remap 0/1. Synchronizes.
+ */
+int mffv_set_launch(mffv_grid* grid, int ci, int remap);
+
+/*
+ * Autotune the grid's FP32 stencil launch shape (the operator must be set):
+ * every candidate (ci in 1..64 planes per block, XCD-aware order on or off) is
+ * timed on the grid's own operator with HIP events and must reproduce the
+ * default shape's apply bit for bit; the fastest is applied. With a
+ * cache_path (may be NULL), a previous result for the same device
+ * architecture and shape is reused, and a new one is written to that JSON
+ * file. Uses the grid's workspace; synchronizes.
+ */
+int mffv_autotune(mffv_grid* grid, const char* cache_path, mffv_tune_result* out);
+
+/*
+ * Launch shape of later batched solves: blocks per CU of the persistent
+ * kernel (0 = as many as fit) and work items (plane chunk x plane group) per
+ * block. Process-wide.
+ */
+int mffv_set_batched_launch(int blocks_per_cu, int items_per_block);
+
+/*
+ * Autotune the batched launch shape: solves the batch (as mffv_cg_solve_batched)
+ * for every candidate (1, 2, 4 or all-fitting blocks per CU x 1, 2, 4, 8 work
+ * items per block), each from the initial guess held in x, times each with HIP
+ * events and applies the fastest (results returned through the pointers, any
+ * may be NULL). x holds the initial guess again on return. Allocates a copy of
+ * the initial guesses for the duration of the call. Synchronizes.
+ */
+int mffv_autotune_batched(mffv_grid* const* grids, int nsys, const float* const* b,
+                          float* const* x, const mffv_opts* opts, int* blocks_per_cu,
+                          int* items_per_block, double* best_ms);
 
 /*
  * Streaming copy dst[i] = src[i] of `bytes` bytes (a multiple of 16) with the

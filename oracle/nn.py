@@ -127,23 +127,25 @@ def network_input(r_hat, feat):
                      (r32 * np.asarray(feat, dtype=np.float32)).astype(np.float64)], axis=-1)
 
 
-def forward(params, r_hat, feat, bf16: bool = True):
-    """Network output N (FP64, shape of the grid) and the cached activations."""
+def forward(params, r_hat, feat, bf16: bool = True, relu: bool = True):
+    """Network output N (FP64, shape of the grid) and the cached activations.
+    ``relu=False`` makes the hidden activations the identity."""
     rnd = bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
     layers = [(rnd(W), np.asarray(b, dtype=np.float64)) for W, b in unpack(params)]
     h = rnd(network_input(r_hat, feat))
     cache = [h]
-    for li, ((W, b), (_, _, relu)) in enumerate(zip(layers, LAYERS)):
+    for li, ((W, b), (_, _, hidden)) in enumerate(zip(layers, LAYERS)):
         y = conv3d(h, W, b)
-        if relu:
-            h = rnd(np.maximum(y, 0.0))
+        if hidden:
+            h = rnd(np.maximum(y, 0.0) if relu else y)
             cache.append(h)
         else:
             h = y
     return h[..., 0], cache, layers
 
 
-def loss_and_grads(params, r_hat, feat, target, dmask, apply_scaled, bf16: bool = True):
+def loss_and_grads(params, r_hat, feat, target, dmask, apply_scaled, bf16: bool = True,
+                   relu: bool = True):
     """Energy-norm loss of the prediction and its gradient.
 
     With z = r_hat + N(r_hat, feat) and the scaled error target (A~ target =
@@ -156,7 +158,7 @@ def loss_and_grads(params, r_hat, feat, target, dmask, apply_scaled, bf16: bool 
     cells. Returns (loss, gradient with respect to the parameter vector, N).
     """
     rnd = bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
-    out, cache, layers = forward(params, r_hat, feat, bf16)
+    out, cache, layers = forward(params, r_hat, feat, bf16, relu)
     u = ~np.asarray(dmask, dtype=bool)
     E = float(np.sum(np.where(u, target * r_hat, 0.0)))
     delta = np.where(u, np.asarray(r_hat, dtype=np.float64) + out - target, 0.0)
@@ -170,7 +172,7 @@ def loss_and_grads(params, r_hat, feat, target, dmask, apply_scaled, bf16: bool 
         dW, db, dx = conv3d_grads(x, W, dy)
         grads[li] = (dW, db)
         if li > 0:
-            dy = rnd(dx * (cache[li] > 0))   # ReLU of the layer below
+            dy = rnd(dx * (cache[li] > 0) if relu else dx)   # activation of the layer below
     return loss, pack(grads), out
 
 

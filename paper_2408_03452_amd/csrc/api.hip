@@ -549,7 +549,7 @@ struct BatchPlan {
     std::vector<mffv_grid*> grids;
     std::vector<const float*> b;
     std::vector<float*> x;
-    int precond = 0, max_iter = 0, blocks_per_cu = 0;
+    int precond = 0, max_iter = 0, blocks_per_cu = 0, items_per_block = 4;
     double tol = 0;
     void* dbuf = nullptr;
     BatchSys* dsys = nullptr;
@@ -567,6 +567,7 @@ struct BatchPlan {
 
 std::mutex g_plans_mu;
 int g_batch_bpc = 0;  // blocks per CU of the batched kernel (0 = occupancy limit)
+int g_batch_ipb = 4;  // work items per block of the batched kernel
 
 int batch_blocks_per_cu_override() { return g_batch_bpc; }
 std::vector<BatchPlan*> g_plans;
@@ -682,7 +683,8 @@ int build_plan(BatchPlan* P, hipStream_t stream) {
         S.blk0 = b0;
         S.nblk = P->blocks[s];
         S.nchunk = (int)((G->g.plane + kThreads - 1) / kThreads);
-        const int64_t want = ((int64_t)S.nchunk * G->g.nx + 4 * S.nblk - 1) / (4 * (int64_t)S.nblk);
+        const int64_t ipb = std::max(1, P->items_per_block);
+        const int64_t want = ((int64_t)S.nchunk * G->g.nx + ipb * S.nblk - 1) / (ipb * (int64_t)S.nblk);
         S.ci = (int)std::max<int64_t>(1, std::min<int64_t>(G->g.nx, want));
         S.nich = (G->g.nx + S.ci - 1) / S.ci;
         for (int t = 0; t < S.nblk; ++t) map[b0 + t] = s;
@@ -713,6 +715,70 @@ int enqueue_batch(BatchPlan* P, hipStream_t stream) {
         if (rc) return rc;
     }
     return MFFV_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Autotuning of launch shapes. The single-system stencil kernels are tuned by
+// timing the apply for every march plan (planes per block x XCD-aware order)
+// on the grid itself; every candidate's output must equal the default plan's
+// bit for bit (each cell's arithmetic does not depend on the tiling). The
+// choice is cached in a JSON file keyed by device architecture and shape.
+// ---------------------------------------------------------------------------
+std::string tune_key(const mffv_grid* G) {
+    hipDeviceProp_t prop;
+    std::string arch = "gfx";
+    if (hipGetDeviceProperties(&prop, G->device) == hipSuccess) arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    return arch + "/" + std::to_string(G->g.nx) + "x" + std::to_string(G->g.ny) + "x" +
+           std::to_string(G->g.nz) + "/v" + std::to_string(G->m32.vec);
+}
+
+bool cache_lookup(const char* path, const std::string& key, int* ci, int* remap, double* us) {
+    if (!path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    const std::string pat = "\"" + key + "\": {";
+    while (std::fgets(line, sizeof(line), f)) {
+        const char* p = std::strstr(line, pat.c_str());
+        if (!p) continue;
+        if (std::sscanf(p + pat.size(), " \"ci\": %d, \"remap\": %d, \"apply_us\": %lf", ci, remap, us) == 3)
+            found = true;
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const char* path, const std::string& key, int ci, int remap, double us) {
+    if (!path) return;
+    std::vector<std::string> lines;
+    if (FILE* f = std::fopen(path, "r")) {
+        char line[512];
+        while (std::fgets(line, sizeof(line), f)) {
+            std::string l(line);
+            if (l.find("\": {") != std::string::npos && l.find("\"" + key + "\"") == std::string::npos) {
+                while (!l.empty() && (l.back() == '\n' || l.back() == ',')) l.pop_back();
+                lines.push_back(l);
+            }
+        }
+        std::fclose(f);
+    }
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), "  \"%s\": {\"ci\": %d, \"remap\": %d, \"apply_us\": %.3f}",
+                  key.c_str(), ci, remap, us);
+    lines.push_back(buf);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "{\n");
+    for (size_t i = 0; i < lines.size(); ++i)
+        std::fprintf(f, "%s%s\n", lines[i].c_str(), i + 1 < lines.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
 }
 
 }  // namespace
@@ -1012,7 +1078,7 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
     BatchPlan* P = nullptr;
     for (BatchPlan* c : g_plans) {
         if ((int)c->grids.size() != nsys || c->precond != o.precond || c->tol != o.tol ||
-            c->max_iter != o.max_iter || c->blocks_per_cu != bpc)
+            c->max_iter != o.max_iter || c->blocks_per_cu != bpc || c->items_per_block != g_batch_ipb)
             continue;
         bool same = true;
         for (int s = 0; s < nsys && same; ++s)
@@ -1028,6 +1094,7 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
         P->tol = o.tol;
         P->max_iter = o.max_iter;
         P->blocks_per_cu = bpc;
+        P->items_per_block = g_batch_ipb;
         if ((rc = build_plan(P, stream))) {
             free_plan(P);
             return rc;
@@ -1156,6 +1223,172 @@ int mffv_grid_feature(mffv_grid* G, float* feat) {
     if (!feat) return fail(MFFV_EINVAL, "feat is NULL");
     if ((rc = set_device(G)) || (rc = ensure_feature(G))) return rc;
     HIP_TRY(hipMemcpyAsync(feat, G->feat, G->g.n * sizeof(float), hipMemcpyDeviceToDevice, G->stream));
+    return MFFV_OK;
+}
+
+int mffv_set_launch(mffv_grid* G, int ci, int remap) {
+    int rc = check_grid(G, false);
+    if (rc) return rc;
+    if (ci < 0 || ci > 4096 || (remap != 0 && remap != 1))
+        return fail(MFFV_EINVAL, "ci must be in [0, 4096] (0 = default) and remap 0 or 1");
+    if ((rc = set_device(G))) return rc;
+    HIP_TRY(hipStreamSynchronize(G->stream));
+    const March m = plan_march(G->g, G->m32.vec, ci, remap);
+    if (m.blocks() > G->max_blocks)
+        return fail(MFFV_EINVAL, "launch plan needs more blocks than the grid's partial buffers");
+    drop_graphs(G);
+    G->m32 = m;
+    return MFFV_OK;
+}
+
+int mffv_autotune(mffv_grid* G, const char* cache_path, mffv_tune_result* out) {
+    int rc = check_grid(G, true);
+    if (rc) return rc;
+    if ((rc = set_device(G)) || (rc = ensure_ws32(G))) return rc;
+    const std::string key = tune_key(G);
+    int ci = 0, remap = 1;
+    double us = 0;
+    int tried = 0;
+    if (cache_lookup(cache_path, key, &ci, &remap, &us)) {
+        if ((rc = mffv_set_launch(G, ci, remap))) return rc;
+    } else {
+        // input: the inverse diagonal (a varied, bounded field); reference output in q
+        StencilIO<float> io;
+        io.src = G->dinv;
+        io.out = G->q;
+        const March base = plan_march(G->g, G->m32.vec, 0, 1);
+        HIP_TRY(launch_stencil_f32(kApply, G->g, coef_of(G), io, base, G->stream));
+        std::vector<float> ref((size_t)G->g.n), got((size_t)G->g.n);
+        HIP_TRY(hipMemcpyAsync(ref.data(), G->q, G->g.n * sizeof(float), hipMemcpyDeviceToHost, G->stream));
+        HIP_TRY(hipStreamSynchronize(G->stream));
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        double best = 1e30;
+        int best_ci = base.ci, best_remap = 1;
+        const int cis[] = {1, 2, 4, 8, 16, 32, 64};
+        for (int c : cis) {
+            if (c > G->g.nx) continue;
+            for (int rm = 0; rm <= 1; ++rm) {
+                const March m = plan_march(G->g, G->m32.vec, c, rm);
+                if (m.blocks() > G->max_blocks) continue;
+                io.out = G->p0;
+                HIP_TRY(launch_stencil_f32(kApply, G->g, coef_of(G), io, m, G->stream));
+                HIP_TRY(hipMemcpyAsync(got.data(), G->p0, G->g.n * sizeof(float), hipMemcpyDeviceToHost,
+                                       G->stream));
+                HIP_TRY(hipStreamSynchronize(G->stream));
+                if (std::memcmp(got.data(), ref.data(), got.size() * sizeof(float)) != 0) continue;
+                const int reps = 10;
+                HIP_TRY(hipEventRecord(e0, G->stream));
+                for (int t = 0; t < reps; ++t)
+                    HIP_TRY(launch_stencil_f32(kApply, G->g, coef_of(G), io, m, G->stream));
+                HIP_TRY(hipEventRecord(e1, G->stream));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                const double t_us = 1e3 * ms / reps;
+                ++tried;
+                if (t_us < best) {
+                    best = t_us;
+                    best_ci = c;
+                    best_remap = rm;
+                }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (!tried) return fail(MFFV_EHIP, "autotune: no candidate reproduced the reference apply");
+        ci = best_ci;
+        remap = best_remap;
+        us = best;
+        if ((rc = mffv_set_launch(G, ci, remap))) return rc;
+        cache_store(cache_path, key, ci, remap, us);
+    }
+    if (out) {
+        out->ci = G->m32.ci;
+        out->remap = G->m32.remap;
+        out->vec = G->m32.vec;
+        out->blocks = G->m32.blocks();
+        out->apply_us = us;
+        out->candidates = tried;
+    }
+    return MFFV_OK;
+}
+
+int mffv_autotune_batched(mffv_grid* const* grids, int nsys, const float* const* b,
+                          float* const* x, const mffv_opts* opts, int* blocks_per_cu,
+                          int* items_per_block, double* best_ms) {
+    if (!grids || !b || !x || nsys <= 0) return fail(MFFV_EINVAL, "grids, b, x must be non-NULL and nsys > 0");
+    for (int s = 0; s < nsys; ++s) {
+        int rc = check_grid(grids[s], true);
+        if (rc) return rc;
+        if (!x[s]) return fail(MFFV_EINVAL, "NULL vector");
+    }
+    int rc = set_device(grids[0]);
+    if (rc) return rc;
+    hipStream_t stream = grids[0]->stream;
+    // every timed solve starts from the caller's initial guess
+    std::vector<float*> x0((size_t)nsys, nullptr);
+    auto release = [&]() {
+        for (float*& p : x0) dfree(p);
+    };
+    for (int s = 0; s < nsys; ++s) {
+        if ((rc = dalloc(&x0[s], (size_t)grids[s]->g.n))) {
+            release();
+            return rc;
+        }
+        if (hipMemcpyAsync(x0[s], x[s], grids[s]->g.n * sizeof(float), hipMemcpyDeviceToDevice, stream) !=
+            hipSuccess) {
+            release();
+            return fail(MFFV_EHIP, "autotune: saving the initial guess failed");
+        }
+    }
+    auto restore = [&]() -> int {
+        for (int s = 0; s < nsys; ++s)
+            if (hipMemcpyAsync(x[s], x0[s], grids[s]->g.n * sizeof(float), hipMemcpyDeviceToDevice,
+                               stream) != hipSuccess)
+                return fail(MFFV_EHIP, "autotune: restoring the initial guess failed");
+        return MFFV_OK;
+    };
+    const int bpcs[] = {1, 2, 4, 0};
+    const int ipbs[] = {1, 2, 4, 8};
+    double best = 1e30;
+    int bb = 0, bi = 4;
+    std::vector<mffv_info> info((size_t)nsys);
+    for (int bpc : bpcs) {
+        for (int ipb : ipbs) {
+            if ((rc = mffv_set_batched_launch(bpc, ipb)) || (rc = restore())) break;
+            rc = mffv_cg_solve_batched(grids, nsys, b, x, opts, info.data());  // builds the plan
+            if (rc < 0 || (rc = restore())) break;
+            rc = mffv_cg_solve_batched(grids, nsys, b, x, opts, info.data());  // timed
+            if (rc < 0) break;
+            rc = MFFV_OK;
+            if (info[0].ms < best) {
+                best = info[0].ms;
+                bb = bpc;
+                bi = ipb;
+            }
+        }
+        if (rc < 0) break;
+    }
+    const int rrc = restore();
+    (void)hipStreamSynchronize(stream);
+    release();
+    if (rc < 0) return rc;
+    if (rrc) return rrc;
+    if ((rc = mffv_set_batched_launch(bb, bi))) return rc;
+    if (blocks_per_cu) *blocks_per_cu = bb;
+    if (items_per_block) *items_per_block = bi;
+    if (best_ms) *best_ms = best;
+    return MFFV_OK;
+}
+
+int mffv_set_batched_launch(int blocks_per_cu, int items_per_block) {
+    if (blocks_per_cu < 0 || blocks_per_cu > 64 || items_per_block < 1 || items_per_block > 64)
+        return fail(MFFV_EINVAL, "blocks_per_cu in [0, 64] (0 = occupancy limit), items_per_block in [1, 64]");
+    std::lock_guard<std::mutex> lk(g_plans_mu);
+    g_batch_bpc = blocks_per_cu;
+    g_batch_ipb = items_per_block;
     return MFFV_OK;
 }
 

@@ -170,6 +170,7 @@ struct ConvArgs {
     const float* dinv;
     const uint8_t* dmask;
     const float* sscale;    // kPrecond: device scalar s
+    int relu;               // 1: ReLU after the hidden layers, 0: identity
     int ntj, ntk, ntiles;
 };
 
@@ -199,9 +200,10 @@ __global__ __launch_bounds__(kThreads) void conv3d(Geom g, ConvArgs a) {
                 const int64_t l = ((int64_t)T.i * g.ny + j) * g.nz + k;
                 const float v = acc[mt][q];
                 if (MODE == kHiddenRelu) {
-                    a.out16[l * 16 + co] = f2bf(fmaxf(v + a.bias[co], 0.f));
+                    const float h = v + a.bias[co];
+                    a.out16[l * 16 + co] = f2bf(a.relu ? fmaxf(h, 0.f) : h);
                 } else if (MODE == kGradMasked) {
-                    const bool on = bf2f(a.below[l * 16 + co]) > 0.f;
+                    const bool on = !a.relu || bf2f(a.below[l * 16 + co]) > 0.f;
                     a.out16[l * 16 + co] = f2bf(on ? v : 0.f);
                 } else if (co == 0) {
                     const float y = v + a.bias[0];
@@ -394,6 +396,43 @@ __global__ __launch_bounds__(kThreads) void loss_grad(int64_t n, const float* rh
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
+// Residual-space loss ||A~ z - rh||^2 / ||rh||^2 (the sparse-approximate-inverse
+// objective): after Aw = A (sqrt(dinv) z), g = A~ z - rh is formed and handed
+// to the operator again (w2 = sqrt(dinv) g); partials of g.g.
+__global__ __launch_bounds__(kThreads) void resid_g(int64_t n, const float* rh, const float* dinv,
+                                                    const uint8_t* dmask, const float* Aw, float* w2,
+                                                    float* part) {
+    __shared__ float red[kThreads / kWave];
+    float s = 0.f;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x; l < n; l += stride) {
+        float g = 0.f;
+        if (!dmask[l]) {
+            const float sd = sqrtf(dinv[l]);
+            g = sd * Aw[l] - rh[l];
+            s += g * g;
+            g *= sd;
+        }
+        w2[l] = g;
+    }
+    const float t = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// dy = 2 A~ g / ||rh||^2 from Ag = A (sqrt(dinv) g).
+__global__ __launch_bounds__(kThreads) void resid_grad(int64_t n, const float* dinv,
+                                                       const uint8_t* dmask, const float* Ag,
+                                                       const float* epart, int nb, uint16_t* dy) {
+    __shared__ float red[kThreads / kWave];
+    const float E = sum_partials(epart, nb, red);
+    const float scale = E > 0.f ? 2.f / E : 0.f;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x; l < n; l += stride) {
+        const float g = dmask[l] ? 0.f : scale * sqrtf(dinv[l]) * Ag[l];
+        reinterpret_cast<uint32_t*>(dy)[l] = (uint32_t)f2bf(g);
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void loss_final(const float* dpart, const float* epart, int nb,
                                                        double* loss) {
     __shared__ float red[kThreads / kWave];
@@ -514,6 +553,8 @@ struct mffv_net {
     int wg_blocks = 0;
     bool training_ws = false;
     int ws_gen = 0;           // bumped whenever the workspace is reallocated
+    int relu = 1;             // activation of the hidden layers
+    int loss_kind = 0;        // 0 energy norm / functional, 1 residual space
 };
 
 namespace {
@@ -605,6 +646,7 @@ int conv(const Shape& S, const ConvArgs& a0, hipStream_t st) {
 int forward(mffv_net* N, const Shape& S, bool keep_h3, int last_mode, const ConvArgs& last,
             hipStream_t st) {
     ConvArgs a{};
+    a.relu = N->relu;
     a.in = N->x0;
     a.W = N->W + kWf1;
     a.bias = N->params + offB(0);
@@ -623,6 +665,7 @@ int forward(mffv_net* N, const Shape& S, bool keep_h3, int last_mode, const Conv
     a.out16 = h3;
     if ((rc = conv<16, kHiddenRelu>(S, a, st))) return rc;
     ConvArgs f = last;
+    f.relu = N->relu;
     f.in = h3;
     f.W = N->W + kWf4;
     f.bias = N->params + offB(3);
@@ -649,6 +692,7 @@ int backward(mffv_net* N, const Shape& S, hipStream_t st) {
     };
     // layer 4: dy4 -> grad of h3 (masked by h3 > 0) into g1
     ConvArgs a{};
+    a.relu = N->relu;
     a.in = N->dy4;
     a.W = N->W + kWb4;
     a.out16 = N->g1;
@@ -704,16 +748,36 @@ int loss_pass(mffv_net* N, const Shape& S, const Coef& c, const March& m, const 
     ConvArgs last{};
     last.out32 = N->y;
     if ((rc = forward(N, S, true, kFinal, last, st))) return rc;
-    hipLaunchKernelGGL(loss_delta, dim3(nb), dim3(kThreads), 0, st, n, r_hat, (const float*)N->y, target, dinv,
-                       dmask, N->t1, N->red);
-    NHIP(hipGetLastError());
-    StencilIO<float> io;
-    io.src = N->t1;
-    io.out = N->t2;
-    NHIP(launch_stencil_f32(kApply, S.g, c, io, m, st));
-    hipLaunchKernelGGL(loss_grad, dim3(nb), dim3(kThreads), 0, st, n, r_hat, (const float*)N->y, target, dinv,
-                       dmask, (const float*)N->t2, (const float*)N->red, nb, N->dy4, N->red + kRedBlocks);
-    NHIP(hipGetLastError());
+    if (N->loss_kind == 1) {
+        // residual space: w = sqrt(dinv) z, Aw, g = A~ z - rh, w2 = sqrt(dinv) g, A w2
+        hipLaunchKernelGGL(loss_delta, dim3(nb), dim3(kThreads), 0, st, n, r_hat, (const float*)N->y,
+                           (const float*)nullptr, dinv, dmask, N->t1, N->red);  // E = rh.rh
+        NHIP(hipGetLastError());
+        StencilIO<float> io;
+        io.src = N->t1;
+        io.out = N->t2;
+        NHIP(launch_stencil_f32(kApply, S.g, c, io, m, st));
+        hipLaunchKernelGGL(resid_g, dim3(nb), dim3(kThreads), 0, st, n, r_hat, dinv, dmask,
+                           (const float*)N->t2, N->t1, N->red + kRedBlocks);
+        NHIP(hipGetLastError());
+        io.src = N->t1;
+        io.out = N->t2;
+        NHIP(launch_stencil_f32(kApply, S.g, c, io, m, st));
+        hipLaunchKernelGGL(resid_grad, dim3(nb), dim3(kThreads), 0, st, n, dinv, dmask, (const float*)N->t2,
+                           (const float*)N->red, nb, N->dy4);
+        NHIP(hipGetLastError());
+    } else {
+        hipLaunchKernelGGL(loss_delta, dim3(nb), dim3(kThreads), 0, st, n, r_hat, (const float*)N->y, target, dinv,
+                           dmask, N->t1, N->red);
+        NHIP(hipGetLastError());
+        StencilIO<float> io;
+        io.src = N->t1;
+        io.out = N->t2;
+        NHIP(launch_stencil_f32(kApply, S.g, c, io, m, st));
+        hipLaunchKernelGGL(loss_grad, dim3(nb), dim3(kThreads), 0, st, n, r_hat, (const float*)N->y, target, dinv,
+                           dmask, (const float*)N->t2, (const float*)N->red, nb, N->dy4, N->red + kRedBlocks);
+        NHIP(hipGetLastError());
+    }
     hipLaunchKernelGGL(loss_final, dim3(1), dim3(kThreads), 0, st, (const float*)(N->red + kRedBlocks),
                        (const float*)N->red, nb, N->loss);
     NHIP(hipGetLastError());
@@ -831,6 +895,24 @@ void mffv_net_destroy(mffv_net* N) {
 }
 
 int mffv_net_num_params(void) { return kNParams; }
+
+int mffv_net_set_loss(mffv_net* N, int kind) {
+    int rc = check_net(N);
+    if (rc) return rc;
+    if (kind != 0 && kind != 1) return nfail(MFFV_EINVAL, "loss kind must be 0 (energy) or 1 (residual)");
+    N->loss_kind = kind;
+    return MFFV_OK;
+}
+
+int mffv_net_set_activation(mffv_net* N, int relu) {
+    int rc = check_net(N);
+    if (rc) return rc;
+    if (relu != 0 && relu != 1) return nfail(MFFV_EINVAL, "activation must be 0 (identity) or 1 (ReLU)");
+    NHIP(hipDeviceSynchronize());
+    N->relu = relu;
+    N->ws_gen += 1;  // captured graphs baked the old flag into their kernel arguments
+    return MFFV_OK;
+}
 
 int mffv_net_get_params(const mffv_net* N, float* params, float* grads) {
     int rc = check_net(N);

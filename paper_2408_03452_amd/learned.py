@@ -121,21 +121,24 @@ def init_params(seed: int = 0):
     return p
 
 
-def fcg_iterations(net: mffv.Net, systems, max_iter: int = 20000) -> int:
+def fcg_iterations(net: mffv.Net, systems, max_iter=20000) -> int:
     """Total flexible-CG iterations to 1e-6 over the systems (validation metric);
-    a system that does not converge counts max_iter."""
+    a system that does not converge within max_iter (a number, or one per
+    system) counts max_iter."""
+    caps = max_iter if isinstance(max_iter, (list, tuple)) else [max_iter] * len(systems)
     tot = 0
-    for grid, b in systems:
+    for (grid, b), cap in zip(systems, caps):
         x = torch.zeros(grid.n, dtype=torch.float32, device=b.device)
         st, info = mffv.cg_solve(grid, b, x, mffv.default_opts(
-            precond=mffv.PRECOND_LEARNED, net=net, max_iter=max_iter))
-        tot += info["iters"] if st == mffv.OK else max_iter
+            precond=mffv.PRECOND_LEARNED, net=net, max_iter=int(cap)))
+        tot += info["iters"] if st == mffv.OK else int(cap)
     return tot
 
 
 def train_preconditioner(systems, validation=None, n_white: int = 256, epochs: int = 24,
                          lr: float = 2e-3, lr_final: float = 1e-4, dagger_rounds: int = 2,
-                         dagger_epochs: int = 6, seed: int = 0, log=None) -> mffv.Net:
+                         dagger_epochs: int = 6, seed: int = 0, relu: bool = True,
+                         loss: int = 0, log=None) -> mffv.Net:
     """The training recipe on held-in systems [(grid, b), ...].
 
     White-noise residuals with the energy functional, then ``dagger_rounds``
@@ -150,10 +153,13 @@ def train_preconditioner(systems, validation=None, n_white: int = 256, epochs: i
     validation = systems[:2] if validation is None else validation
     p0 = init_params(seed)
     net = mffv.net_create(p0)
-    zero = p0.copy()
-    zero[:] = 0.0
+    mffv.net_set_activation(net, relu)
+    mffv.net_set_loss(net, loss)
     best_p = p0.copy()                      # last layer zero: the network is Jacobi
-    best = fcg_iterations(net, validation)
+    caps = []
+    for sysv in validation:                 # a candidate may take twice Jacobi's count at most
+        caps.append(2 * fcg_iterations(net, [sysv]) + 10)
+    best = sum((c - 10) // 2 for c in caps)
     if log:
         log(f"validation FCG iterations with the zero network: {best}")
 
@@ -169,7 +175,7 @@ def train_preconditioner(systems, validation=None, n_white: int = 256, epochs: i
                 cur = lr0 * (lr1 / lr0) ** (step / max(1, total - 1))
                 mffv.nn_train_step(net, s.grid, s.r_hat, s.target, cur)
                 step += 1
-            it = fcg_iterations(net, validation)
+            it = fcg_iterations(net, validation, caps)
             if it < best:
                 best = it
                 best_p, _ = mffv.net_get_params(net)
@@ -183,7 +189,7 @@ def train_preconditioner(systems, validation=None, n_white: int = 256, epochs: i
         more = white_samples(systems, n_white // 2, seed + 1000 * (r + 1))
         run(extra + more, dagger_epochs, lr / 4, lr_final, f"dagger{r}", seed + r + 1)
     mffv.net_set_params(net, best_p)
-    del zero, np
+    del np
     return net
 
 

@@ -42,6 +42,15 @@ class Opts(ctypes.Structure):
                 ("net", ctypes.c_void_p)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("ci", ctypes.c_int), ("remap", ctypes.c_int), ("vec", ctypes.c_int),
+                ("blocks", ctypes.c_int), ("apply_us", ctypes.c_double),
+                ("candidates", ctypes.c_int)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("ir_steps", ctypes.c_int),
                 ("fallbacks", ctypes.c_int), ("rel_res_recursive", ctypes.c_double),
@@ -82,12 +91,22 @@ def _declare(lib):
         "mffv_net_destroy": (None, [_P]),
         "mffv_net_get_params": (ctypes.c_int, [_P, _P, _P]),
         "mffv_net_set_params": (ctypes.c_int, [_P, _P]),
+        "mffv_net_set_activation": (ctypes.c_int, [_P, ctypes.c_int]),
+        "mffv_net_set_loss": (ctypes.c_int, [_P, ctypes.c_int]),
         "mffv_nn_forward": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P,
                                            _P]),
         "mffv_nn_loss_grad": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
         "mffv_nn_train_step": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_float,
                                               ctypes.POINTER(ctypes.c_double)]),
         "mffv_grid_feature": (ctypes.c_int, [_P, _P]),
+        "mffv_set_launch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
+        "mffv_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.POINTER(TuneResult)]),
+        "mffv_set_batched_launch": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+        "mffv_autotune_batched": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int,
+                                                 ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                                 ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_int),
+                                                 ctypes.POINTER(ctypes.c_int),
+                                                 ctypes.POINTER(ctypes.c_double)]),
         "mffv_harvest_pair": (ctypes.c_int, [_P, _P, _P, _P, _P, _P,
                                              ctypes.POINTER(ctypes.c_float)]),
     }
@@ -265,6 +284,32 @@ def cg_solve_batched(grids, b, x, opts: Opts | None = None):
     return _check(rc), [i.as_dict() for i in infos]
 
 
+def set_launch(grid: Grid, ci: int, remap: int) -> None:
+    _check(lib().mffv_set_launch(grid.handle, ci, remap))
+
+
+def autotune(grid: Grid, cache_path: str | None = None) -> dict:
+    out = TuneResult()
+    _check(lib().mffv_autotune(grid.handle, cache_path.encode() if cache_path else None,
+                               ctypes.byref(out)))
+    return out.as_dict()
+
+
+def set_batched_launch(blocks_per_cu: int, items_per_block: int) -> None:
+    _check(lib().mffv_set_batched_launch(blocks_per_cu, items_per_block))
+
+
+def autotune_batched(grids, b, x, opts: Opts | None = None) -> dict:
+    ns = len(grids)
+    G = (_P * ns)(*[g.handle for g in grids])
+    B = (_P * ns)(*[_ptr(bb, torch.float32, g.n, "b") for bb, g in zip(b, grids)])
+    X = (_P * ns)(*[_ptr(xx, torch.float32, g.n, "x") for xx, g in zip(x, grids)])
+    bpc, ipb, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    _check(lib().mffv_autotune_batched(G, ns, B, X, ctypes.byref(opts) if opts is not None else None,
+                                       ctypes.byref(bpc), ctypes.byref(ipb), ctypes.byref(ms)))
+    return {"blocks_per_cu": bpc.value, "items_per_block": ipb.value, "ms": ms.value}
+
+
 def copy_probe(dst, src, nbytes: int, stream=None) -> None:
     _check(lib().mffv_copy_probe(_ptr(dst), _ptr(src), nbytes, _stream(stream)))
 
@@ -310,6 +355,14 @@ def net_create(params=None) -> Net:
     net = Net(h.value)
     net._keep = arr
     return net
+
+
+def net_set_activation(net: Net, relu: bool) -> None:
+    _check(lib().mffv_net_set_activation(net.handle, 1 if relu else 0))
+
+
+def net_set_loss(net: Net, kind: int) -> None:
+    _check(lib().mffv_net_set_loss(net.handle, int(kind)))
 
 
 def net_destroy(net: Net) -> None:

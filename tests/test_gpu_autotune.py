@@ -1,0 +1,84 @@
+"""Autotuner and launch shapes: every shape computes the same apply bits, the
+tuner's choice is cached, and solves stay correct under the tuned shapes."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from synth import lognormal_iid
+from gpu_problem import gpu_problem, OracleProblem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mf():
+    from paper_2408_03452_amd import mffv
+    assert torch.cuda.is_available()
+    mffv.lib()
+    return mffv
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("shape", [(40, 24, 64), (21, 17, 19)])
+def test_launch_shapes_give_identical_apply(mf, shape):
+    k = lognormal_iid(shape, 1.5, 2)
+    g, _, _ = gpu_problem(mf, k, c=1e-3)
+    x = torch.randn(k.size, dtype=torch.float32, device="cuda")
+    outs = []
+    for ci, remap in ((0, 1), (1, 0), (3, 1), (8, 0), (64, 1)):
+        mf.set_launch(g, ci, remap)
+        y = torch.empty_like(x)
+        mf.apply(g, x, y)
+        outs.append(host(y))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    with pytest.raises(mf.MffvError):
+        mf.set_launch(g, -1, 0)
+
+
+def test_autotune_caches_and_keeps_results(mf, tmp_path):
+    shape = (48, 32, 64)
+    k = lognormal_iid(shape, 1.0, 3)
+    g, _, b = gpu_problem(mf, k, c=1e-3)
+    ref = OracleProblem(k, c=1e-3)
+    cache = str(tmp_path / "tune.json")
+    r1 = mf.autotune(g, cache)
+    assert r1["candidates"] >= 4 and r1["apply_us"] > 0
+    data = json.load(open(cache))
+    assert len(data) == 1 and list(data.values())[0]["ci"] == r1["ci"]
+    g2, _, _ = gpu_problem(mf, k, c=1e-3)
+    r2 = mf.autotune(g2, cache)
+    assert r2["candidates"] == 0 and (r2["ci"], r2["remap"]) == (r1["ci"], r1["remap"])
+    x = torch.zeros(k.size, dtype=torch.float64, device="cuda")
+    st, info = mf.cg_solve_f64(g, b.double(), x, mf.default_opts(tol=1e-10, precision=mf.FP32_IR))
+    assert st == mf.OK
+    p = ref.direct()
+    assert np.linalg.norm(host(x) - p) <= 1e-8 * np.linalg.norm(p)
+
+
+def test_autotune_batched_keeps_results(mf):
+    rng = np.random.default_rng(9)
+    shapes = [tuple(int(v) for v in rng.integers(8, 30, 3)) for _ in range(6)]
+    ks = [lognormal_iid(s, 1.0, i) for i, s in enumerate(shapes)]
+    probs = [gpu_problem(mf, k, c=1e-3) for k in ks]
+    grids = [p[0] for p in probs]
+    bs = [p[2] for p in probs]
+    xs = [torch.zeros(g.n, dtype=torch.float32, device="cuda") for g in grids]
+    best = mf.autotune_batched(grids, bs, xs, mf.default_opts(tol=1e-6, use_graph=0))
+    assert best["ms"] > 0 and best["items_per_block"] in (1, 2, 4, 8)
+    for x in xs:
+        x.zero_()
+    st, infos = mf.cg_solve_batched(grids, bs, xs, mf.default_opts(tol=1e-6, use_graph=0))
+    assert st == mf.OK
+    for k, x in zip(ks, xs):
+        ref = OracleProblem(k, c=1e-3)
+        p = ref.direct()
+        assert np.linalg.norm(host(x) - p) <= 5e-5 * np.linalg.norm(p)
+    mf.set_batched_launch(0, 4)

@@ -65,7 +65,8 @@ def oracle_feature(ref):
     return np.where(u, ld - ld[u].mean(), 0.0).reshape(ref.shape)
 
 
-def test_gradients_match_oracle(mf):
+@pytest.mark.parametrize("relu", [True, False])
+def test_gradients_match_oracle(mf, relu):
     rng = np.random.default_rng(3)
     p = random_params(4)
     k = lognormal_iid(SHAPE, 1.0, 6)
@@ -75,11 +76,12 @@ def test_gradients_match_oracle(mf):
     r = np.where(dmask, 0, rng.normal(size=SHAPE)).astype(np.float32)
     tgt = np.where(dmask, 0, rng.normal(size=SHAPE) + 0.5 * r).astype(np.float32)
     net = mf.net_create(p)
+    mf.net_set_activation(net, relu)
     loss = mf.nn_loss_grad(net, g, dev(r), dev(tgt))
     _, grad = mf.net_get_params(net)
     ref_loss, ref_g, _ = nn.loss_and_grads(p, r.astype(np.float64), oracle_feature(ref),
                                            tgt.astype(np.float64), dmask,
-                                           nn.scaled_operator(ref.A, dmask))
+                                           nn.scaled_operator(ref.A, dmask), relu=relu)
     assert abs(loss - ref_loss) <= 1e-2 * abs(ref_loss)
     o = 0
     for ci, co, _ in nn.LAYERS:

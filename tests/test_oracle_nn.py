@@ -35,7 +35,8 @@ def test_conv_identity_kernel_and_scipy_correlate():
     assert [nn.offsets()[t] for t in (0, 13, 26)] == [(-1, -1, -1), (0, 0, 0), (1, 1, 1)]
 
 
-def test_gradients_match_central_differences():
+@pytest.mark.parametrize("relu", [True, False])
+def test_gradients_match_central_differences(relu):
     from oracle import tpfa
     from synth import lognormal_iid
     rng = np.random.default_rng(3)
@@ -50,15 +51,15 @@ def test_gradients_match_central_differences():
     f = rng.normal(size=shape)
     tgt = np.where(dmask, 0.0, rng.normal(size=shape))
     tgt *= np.sign(np.sum(tgt * r)) or 1.0
-    loss, g, _ = nn.loss_and_grads(params, r, f, tgt, dmask, As, bf16=False)
+    loss, g, _ = nn.loss_and_grads(params, r, f, tgt, dmask, As, bf16=False, relu=relu)
     idx = rng.choice(params.size, 40, replace=False)
     h = 1e-6
     for i in idx:
         p1, p2 = params.copy(), params.copy()
         p1[i] += h
         p2[i] -= h
-        l1 = nn.loss_and_grads(p1, r, f, tgt, dmask, As, bf16=False)[0]
-        l2 = nn.loss_and_grads(p2, r, f, tgt, dmask, As, bf16=False)[0]
+        l1 = nn.loss_and_grads(p1, r, f, tgt, dmask, As, bf16=False, relu=relu)[0]
+        l2 = nn.loss_and_grads(p2, r, f, tgt, dmask, As, bf16=False, relu=relu)[0]
         fd = (l1 - l2) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
 
