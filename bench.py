@@ -32,7 +32,13 @@ if ROOT not in sys.path:
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published peak
 APPLY_BYTES_PER_CELL = 24       # x, a, Tx, Ty, Tz read; y written (FP32)
 CG_BYTES_PER_CELL_ITER = 52     # fused phase A (40) + phase B (12), FP32
+PHASE_A_BYTES_PER_CELL = 40     # r, p_old, x, a, Tx, Ty, Tz read; p, q, x written
+PHASE_B_BYTES_PER_CELL = 12     # r, q read; r written
 METRIC = "time to rel-resid 1e-6 (learned FCG vs plain CG); stencil-apply HBM GB/s"
+# HBM bytes per phase-A launch on the 256^3 workload from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, scaled by the same counters on a copy of known size (null until taken
+# for the current kernel)
+TRAFFIC_PHASE_A = None
 
 
 def cells_iter_rate(cells: float, iters: float, seconds: float) -> float:
@@ -229,6 +235,11 @@ def main(argv=None):
         g = mffv.create_grid(nx, ny, nz, stream=s)
         mffv.set_transmissibility(g, tx, ty, tz, accum_scalar=w.c, b_out=b)
         del kd
+        # launch shape of the stencil kernels: the library's autotuner (bitwise
+        # apply probe, timed phase A), outside the timed region
+        tune = mffv.autotune(g, None)
+        log(f"autotune: ci {tune['ci']}, remap {tune['remap']}, {tune['blocks']} blocks, phase A "
+            f"{tune['phase_a_us']:.1f} us, apply {tune['apply_us']:.1f} us ({tune['candidates']} candidates)")
         x = torch.zeros(n, dtype=torch.float32, device=dev)
         opts = mffv.default_opts(tol=w.tol, precision=mffv.FP32_IR, check_every=16, use_graph=1)
 
@@ -254,6 +265,17 @@ def main(argv=None):
         iters = statistics.mean(i["iters"] for i in infos)
         log(f"solve: {ms_per_step:.2f} ms, {iters:.0f} iterations, true rel-res "
             f"{infos[-1]['rel_res_true']:.3e}, ir_steps {infos[-1]['ir_steps']}")
+
+        # the dominant kernel of the step, the fused CG phase A, timed per launch
+        # with HIP events on the grid's stream during one more (untimed) solve
+        x.zero_()
+        st, tinfo = mffv.cg_solve(g, b, x, mffv.default_opts(
+            tol=w.tol, precision=mffv.FP32_IR, check_every=16, use_graph=1, timing=1))
+        phase_a_us, phase_b_us = tinfo["phase_a_us"], tinfo["phase_b_us"]
+        phase_a_gbps = PHASE_A_BYTES_PER_CELL * n / (phase_a_us * 1e-6) / 1e9
+        phase_b_gbps = PHASE_B_BYTES_PER_CELL * n / (phase_b_us * 1e-6) / 1e9
+        log(f"phase A: {phase_a_us:.1f} us/launch ({phase_a_gbps:.0f} GB/s), phase B: "
+            f"{phase_b_us:.1f} us/launch ({phase_b_gbps:.0f} GB/s), over {tinfo['timed_iters']} iterations")
 
         # Jacobi-PCG on the same system (context for the preconditioned comparison)
         jac = None
@@ -339,7 +361,8 @@ def main(argv=None):
         "config": {"workload": w.name, "grid": list(w.shape), "cells": n,
                    "sigma": w.sigma, "corr_len_cells": w.corr_len, "accumulation": w.c,
                    "tol": w.tol, "precision": "FP32 CG + FP64 true residual/refinement",
-                   "precond": "none", "initial_guess": "zero"},
+                   "precond": "none", "initial_guess": "zero",
+                   "launch": {k: tune[k] for k in ("ci", "remap", "vec", "blocks")}},
         "iters": iters,
         "rel_res_true": infos[-1]["rel_res_true"],
         "ir_steps": infos[-1]["ir_steps"],
@@ -351,16 +374,22 @@ def main(argv=None):
         "jacobi_pcg": jac,
         "batched": batched,
         "learned": learned_res,
+        "phase_a_us": phase_a_us,
+        "phase_a_GBps": phase_a_gbps,
+        "phase_b_us": phase_b_us,
+        "phase_b_GBps": phase_b_gbps,
         "roofline": {
-            "kernel": "stencil_v4<apply> (mffv_apply)",
+            "kernel": "stencil_v4<1> (fused CG phase A: direction update, apply, deferred "
+                      "solution update, p.Ap partials)",
             "bound": "hbm",
-            "achieved": apply_gbps,
+            "achieved": phase_a_gbps,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
-            "frac": apply_gbps / HBM_PEAK_GBPS,
-            "traffic": None,
-            "bytes_per_cell": APPLY_BYTES_PER_CELL,
+            "frac": phase_a_gbps / HBM_PEAK_GBPS,
+            "traffic": TRAFFIC_PHASE_A,
+            "bytes_per_cell": PHASE_A_BYTES_PER_CELL,
             "cells_per_launch": n,
+            "launch_us": phase_a_us,
         },
         "cpu_baseline": cpu,
     }

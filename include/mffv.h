@@ -84,6 +84,9 @@ typedef struct {
     int check_every;     /* iterations enqueued between host polls of the convergence flag (16) */
     int use_graph;       /* 1: replay a captured HIP graph of check_every iterations          */
     const mffv_net* net; /* network for MFFV_PRECOND_LEARNED                                  */
+    int timing;          /* 1 (mffv_cg_solve, FP32 or FP32_IR): time each kernel of the first
+                            32 FP32 CG iterations with HIP events (no graph replay, same
+                            arithmetic); means returned in mffv_info                      */
 } mffv_opts;
 
 typedef struct {
@@ -94,6 +97,14 @@ typedef struct {
     double rel_res_recursive;  /* recursively updated residual at exit, relative            */
     double rel_res_true;       /* ||b - A x|| / ||b|| recomputed in FP64 on the GPU          */
     double ms;                 /* device time of the solve (HIP events on the grid's stream) */
+    /* opts.timing: mean duration per launch, in microseconds, over timed_iters FP32
+       iterations that did work (HIP events on the grid's stream): the fused phase A (direction
+       update, apply, deferred solution update, p.Ap partials), phase B (residual
+       update and its dots) and, for flexible CG, the network and its dots. */
+    double phase_a_us;
+    double phase_b_us;
+    double precond_us;
+    int timed_iters;
 } mffv_info;
 
 /* Library version string, e.g. "mffv 1.0 gfx950". Never NULL. */
@@ -309,6 +320,7 @@ typedef struct {
     int blocks;      /* blocks per launch */
     double apply_us; /* measured apply time of the chosen shape (microseconds) */
     int candidates;  /* shapes timed (0 when read from the cache) */
+    double phase_a_us; /* measured time of the fused CG phase A of the chosen shape */
 } mffv_tune_result;
 
 /*
@@ -319,12 +331,14 @@ int mffv_set_launch(mffv_grid* grid, int ci, int remap);
 
 /*
  * Autotune the grid's FP32 stencil launch shape (the operator must be set):
- * every candidate (ci in 1..64 planes per block, XCD-aware order on or off) is
- * timed on the grid's own operator with HIP events and must reproduce the
- * default shape's apply bit for bit; the fastest is applied. With a
- * cache_path (may be NULL), a previous result for the same device
- * architecture and shape is reused, and a new one is written to that JSON
- * file. Uses the grid's workspace; synchronizes.
+ * every candidate (ci in 1..64 planes per block, XCD-aware order on or off)
+ * must reproduce the default shape's apply bit for bit; it is then timed on
+ * the grid's own operator with HIP events, as an apply and as the fused CG
+ * phase A (the solver's hot kernel) over the first 32 iterations of a solve, and the shape
+ * with the fastest phase A is applied. With a cache_path (may be NULL), a
+ * previous result for the same device architecture and shape is reused, and a
+ * new one is written to that JSON file. Uses the grid's workspace (overwrites
+ * the solver's work vectors); synchronizes.
  */
 int mffv_autotune(mffv_grid* grid, const char* cache_path, mffv_tune_result* out);
 

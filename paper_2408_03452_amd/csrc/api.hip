@@ -79,6 +79,8 @@ struct CgGraph {
     int net_gen = 0;            // and the generation of its workspace
 };
 
+constexpr int kTimedIters = 32;
+
 struct mffv_grid {
     Geom g{};
     hipStream_t stream = nullptr;
@@ -111,6 +113,12 @@ struct mffv_grid {
     char* hstate = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t t0 = nullptr, t1 = nullptr;
+    // per-kernel timing of the first kTimedIters FP32 iterations (opts.timing)
+    hipEvent_t tev[kTimedIters][4] = {};
+    bool tev_made = false;
+    bool timing = false;
+    int timed = 0;
+    int timed_real = -1;  // iterations of the first timed CG run that did work
     // launch shapes
     March m32{}, m64{};
     int nb_vec = 0;
@@ -231,6 +239,9 @@ struct LoopResult {
 // Enqueue one CG iteration (phase A, phase B, and for flexible CG the
 // preconditioner and its dots).
 int enqueue_iter32(mffv_grid* G, int precond, const mffv_net* net) {
+    hipEvent_t* ev = nullptr;
+    if (G->timing && G->timed < kTimedIters) ev = G->tev[G->timed++];
+    if (ev) HIP_TRY(hipEventRecord(ev[0], G->stream));
     float* pa = reinterpret_cast<float*>(G->partA);
     float* pb = reinterpret_cast<float*>(G->partB);
     float* pf = reinterpret_cast<float*>(G->partF);
@@ -250,6 +261,7 @@ int enqueue_iter32(mffv_grid* G, int precond, const mffv_net* net) {
     a.dinv = G->dinv;
     a.rres = G->r;
     HIP_TRY(launch_stencil_f32(kFusedCg, G->g, coef_of(G), a, G->m32, G->stream));
+    if (ev) HIP_TRY(hipEventRecord(ev[1], G->stream));
     VecIO<float> v;
     v.r = G->r;
     v.q = G->q;
@@ -264,6 +276,7 @@ int enqueue_iter32(mffv_grid* G, int precond, const mffv_net* net) {
     const int mode = precond == MFFV_PRECOND_NONE ? kBPlain
                      : precond == MFFV_PRECOND_JACOBI ? kBJacobi : kBFlex;
     HIP_TRY(launch_phase_b_f32(mode, G->g.n, v, G->nb_vec, G->stream));
+    if (ev) HIP_TRY(hipEventRecord(ev[2], G->stream));
     if (precond == MFFV_PRECOND_LEARNED) {
         int rc = nn_precondition(net, G->g, G->r, G->dinv, G->dmask, G->z, pb + G->nb_vec, G->nb_vec,
                                  G->feat, (float)G->n_unknown, G->stream);
@@ -272,6 +285,43 @@ int enqueue_iter32(mffv_grid* G, int precond, const mffv_net* net) {
         f.partials = pf;
         HIP_TRY(launch_flex_dots_f32(G->g.n, f, G->nb_vec, G->stream));
     }
+    if (ev) HIP_TRY(hipEventRecord(ev[3], G->stream));
+    return MFFV_OK;
+}
+
+// Start per-kernel timing for the next solve (events are created once per grid).
+int timing_begin(mffv_grid* G, bool on) {
+    G->timing = on;
+    G->timed = 0;
+    G->timed_real = -1;
+    if (!on || G->tev_made) return MFFV_OK;
+    for (auto& row : G->tev)
+        for (auto& e : row) HIP_TRY(hipEventCreate(&e));
+    G->tev_made = true;
+    return MFFV_OK;
+}
+
+// Mean durations (us) of phase A, phase B and the preconditioner over the
+// iterations that were timed; the stream must be synchronized.
+int timing_end(mffv_grid* G, mffv_info* inf) {
+    if (!G->timing) return MFFV_OK;
+    // launches after convergence return at once: time only iterations that did work
+    const int nt = G->timed_real >= 0 ? std::min(G->timed, G->timed_real) : G->timed;
+    double sum[3] = {0, 0, 0};
+    for (int t = 0; t < nt; ++t) {
+        for (int k = 0; k < 3; ++k) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, G->tev[t][k], G->tev[t][k + 1]));
+            sum[k] += ms;
+        }
+    }
+    if (nt > 0) {
+        inf->phase_a_us = 1e3 * sum[0] / nt;
+        inf->phase_b_us = 1e3 * sum[1] / nt;
+        inf->precond_us = 1e3 * sum[2] / nt;
+    }
+    inf->timed_iters = nt;
+    G->timing = false;
     return MFFV_OK;
 }
 
@@ -403,7 +453,7 @@ int cg32(mffv_grid* G, double tol, int max_iter, int precond, const mffv_opts& o
         HIP_TRY(launch_flex_dots_f32(G->g.n, f, G->nb_vec, G->stream));
     }
     const int chunk = std::max(1, o.check_every);
-    const bool use_graph = o.use_graph && G->stream != nullptr;
+    const bool use_graph = o.use_graph && !o.timing && G->stream != nullptr;
     int rc = drive_loop(G, G->st32, max_iter, chunk, G->graph32[precond], use_graph,
                         [&]() { return enqueue_iter32(G, precond, net); },
                         precond == MFFV_PRECOND_LEARNED ? (const void*)net : nullptr, net_gen);
@@ -415,6 +465,7 @@ int cg32(mffv_grid* G, double tol, int max_iter, int precond, const mffv_opts& o
     out->iters = hs.iters;
     out->status = hs.done ? hs.status : MFFV_NOT_CONVERGED;
     out->fallbacks = hs.fallbacks;
+    if (G->timing && G->timed_real < 0) G->timed_real = hs.iters;
     out->rel_rec = hs.bnorm2 > 0 ? std::sqrt((double)hs.rr / (double)hs.bnorm2) : 0.0;
     return MFFV_OK;
 }
@@ -735,7 +786,8 @@ std::string tune_key(const mffv_grid* G) {
            std::to_string(G->g.nz) + "/v" + std::to_string(G->m32.vec);
 }
 
-bool cache_lookup(const char* path, const std::string& key, int* ci, int* remap, double* us) {
+bool cache_lookup(const char* path, const std::string& key, int* ci, int* remap, double* us,
+                  double* pa_us) {
     if (!path) return false;
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
@@ -745,14 +797,15 @@ bool cache_lookup(const char* path, const std::string& key, int* ci, int* remap,
     while (std::fgets(line, sizeof(line), f)) {
         const char* p = std::strstr(line, pat.c_str());
         if (!p) continue;
-        if (std::sscanf(p + pat.size(), " \"ci\": %d, \"remap\": %d, \"apply_us\": %lf", ci, remap, us) == 3)
+        if (std::sscanf(p + pat.size(), " \"ci\": %d, \"remap\": %d, \"apply_us\": %lf, \"phase_a_us\": %lf",
+                        ci, remap, us, pa_us) == 4)
             found = true;
     }
     std::fclose(f);
     return found;
 }
 
-void cache_store(const char* path, const std::string& key, int ci, int remap, double us) {
+void cache_store(const char* path, const std::string& key, int ci, int remap, double us, double pa_us) {
     if (!path) return;
     std::vector<std::string> lines;
     if (FILE* f = std::fopen(path, "r")) {
@@ -767,8 +820,8 @@ void cache_store(const char* path, const std::string& key, int ci, int remap, do
         std::fclose(f);
     }
     char buf[512];
-    std::snprintf(buf, sizeof(buf), "  \"%s\": {\"ci\": %d, \"remap\": %d, \"apply_us\": %.3f}",
-                  key.c_str(), ci, remap, us);
+    std::snprintf(buf, sizeof(buf), "  \"%s\": {\"ci\": %d, \"remap\": %d, \"apply_us\": %.3f, \"phase_a_us\": %.3f}",
+                  key.c_str(), ci, remap, us, pa_us);
     lines.push_back(buf);
     const std::string tmp = std::string(path) + ".tmp";
     FILE* f = std::fopen(tmp.c_str(), "w");
@@ -800,6 +853,7 @@ void mffv_default_opts(mffv_opts* o) {
     o->check_every = 16;
     o->use_graph = 1;
     o->net = nullptr;
+    o->timing = 0;
 }
 
 int mffv_create_grid(int nx, int ny, int nz, void* stream, mffv_grid** out) {
@@ -863,6 +917,9 @@ void mffv_destroy_grid(mffv_grid* G) {
         if (e) (void)hipEventDestroy(e);
     if (G->t0) (void)hipEventDestroy(G->t0);
     if (G->t1) (void)hipEventDestroy(G->t1);
+    for (auto& row : G->tev)
+        for (auto& e : row)
+            if (e) (void)hipEventDestroy(e);
     delete G;
 }
 
@@ -958,6 +1015,7 @@ int mffv_cg_solve(mffv_grid* G, const float* b, float* x, const mffv_opts* opts,
     if ((rc = set_device(G)) || (rc = ensure_ws32(G))) return rc;
     mffv_info inf{};
     const int64_t n = G->g.n;
+    if ((rc = timing_begin(G, o.timing != 0 && o.precision != MFFV_FP64))) return rc;
     HIP_TRY(hipEventRecord(G->t0, G->stream));
     int status = MFFV_OK;
     if (o.precision == MFFV_FP32) {
@@ -1000,6 +1058,7 @@ int mffv_cg_solve(mffv_grid* G, const float* b, float* x, const mffv_opts* opts,
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, G->t0, G->t1));
     inf.ms = ms;
+    if ((rc = timing_end(G, &inf))) return rc;
     status = status_code(status);
     inf.status = status;
     if (info) *info = inf;
@@ -1247,9 +1306,9 @@ int mffv_autotune(mffv_grid* G, const char* cache_path, mffv_tune_result* out) {
     if ((rc = set_device(G)) || (rc = ensure_ws32(G))) return rc;
     const std::string key = tune_key(G);
     int ci = 0, remap = 1;
-    double us = 0;
+    double us = 0, pa_us = 0;
     int tried = 0;
-    if (cache_lookup(cache_path, key, &ci, &remap, &us)) {
+    if (cache_lookup(cache_path, key, &ci, &remap, &us, &pa_us)) {
         if ((rc = mffv_set_launch(G, ci, remap))) return rc;
     } else {
         // input: the inverse diagonal (a varied, bounded field); reference output in q
@@ -1264,8 +1323,10 @@ int mffv_autotune(mffv_grid* G, const char* cache_path, mffv_tune_result* out) {
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
+        const March keep = G->m32;
         double best = 1e30;
         int best_ci = base.ci, best_remap = 1;
+        double best_apply = 0;
         const int cis[] = {1, 2, 4, 8, 16, 32, 64};
         for (int c : cis) {
             if (c > G->g.nx) continue;
@@ -1286,10 +1347,28 @@ int mffv_autotune(mffv_grid* G, const char* cache_path, mffv_tune_result* out) {
                 HIP_TRY(hipEventSynchronize(e1));
                 float ms = 0;
                 HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                const double t_us = 1e3 * ms / reps;
+                const double apply_us = 1e3 * ms / reps;
+                // the CG's own hot kernel: phase A over the first 32 iterations of a solve of A x = dinv
+                G->m32 = m;
+                HIP_TRY(hipMemcpyAsync(G->bw, G->dinv, G->g.n * sizeof(float), hipMemcpyDeviceToDevice,
+                                       G->stream));
+                HIP_TRY(hipMemsetAsync(G->xw, 0, G->g.n * sizeof(float), G->stream));
+                mffv_opts o;
+                mffv_default_opts(&o);
+                o.use_graph = 0;
+                o.timing = 1;
+                if ((rc = timing_begin(G, true))) return rc;
+                LoopResult lr;
+                rc = cg32(G, 1e-30, 40, MFFV_PRECOND_NONE, o, &lr);
+                G->m32 = keep;
+                if (rc) return rc;
+                mffv_info inf{};
+                if ((rc = timing_end(G, &inf))) return rc;
+                const double score = inf.timed_iters > 0 ? inf.phase_a_us : apply_us;
                 ++tried;
-                if (t_us < best) {
-                    best = t_us;
+                if (score < best) {
+                    best = score;
+                    best_apply = apply_us;
                     best_ci = c;
                     best_remap = rm;
                 }
@@ -1300,9 +1379,10 @@ int mffv_autotune(mffv_grid* G, const char* cache_path, mffv_tune_result* out) {
         if (!tried) return fail(MFFV_EHIP, "autotune: no candidate reproduced the reference apply");
         ci = best_ci;
         remap = best_remap;
-        us = best;
+        us = best_apply;
+        pa_us = best;
         if ((rc = mffv_set_launch(G, ci, remap))) return rc;
-        cache_store(cache_path, key, ci, remap, us);
+        cache_store(cache_path, key, ci, remap, us, pa_us);
     }
     if (out) {
         out->ci = G->m32.ci;
@@ -1311,6 +1391,7 @@ int mffv_autotune(mffv_grid* G, const char* cache_path, mffv_tune_result* out) {
         out->blocks = G->m32.blocks();
         out->apply_us = us;
         out->candidates = tried;
+        out->phase_a_us = pa_us;
     }
     return MFFV_OK;
 }

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 namespace mffv {
@@ -51,8 +52,8 @@ static_assert(kNParams == 15169, "parameter count");
 constexpr int kWf1 = 0;                 // layer 1, 4 K-steps x 64 lanes
 constexpr int kWf2 = kWf1 + 4 * 64;     // layers 2..4, 27 taps x 64 lanes
 constexpr int kWf3 = kWf2 + 27 * 64;
-constexpr int kWf4 = kWf3 + 27 * 64;
-constexpr int kWb4 = kWf4 + 27 * 64;    // input gradient of layer 4 (2-channel path)
+constexpr int kWf4 = kWf3 + 27 * 64;    // layer 4: 9 (dx, dy) groups x 64 lanes, rows = dz
+constexpr int kWb4 = kWf4 + 9 * 64;     // input gradient of layer 4 (2-channel path)
 constexpr int kWb3 = kWb4 + 4 * 64;
 constexpr int kWb2 = kWb3 + 27 * 64;
 constexpr int kWTotal = kWb2 + 27 * 64;  // in v4s units
@@ -107,48 +108,152 @@ __device__ __forceinline__ void load_halo(const uint16_t* __restrict__ in, const
     }
 }
 
-// Accumulate one wave's 64-cell row (4 MFMA tiles) of a 3x3x3 convolution.
+// Forward and input-gradient convolutions march along x: a block owns a
+// column of TY x TZ output cells and a run of consecutive x planes, and keeps
+// the haloed input planes i-1, i, i+1 (and the one being prefetched) in a ring
+// of four LDS slots, so every input plane is read from memory once per run
+// instead of three times. The next plane is fetched into registers while the
+// matrix cores work on the current one.
+constexpr int kRing = 4;
+constexpr int PCELLS = HY * HZ;  // cells of one haloed plane
+
+// In LDS the four 8-byte channel quads of a 16-channel cell are stored in the
+// order q ^ ((cell >> 2) & 3): the 16 lanes that read quad q of 16 consecutive
+// cells then touch 16 distinct 8-byte bank slots instead of four.
+//
+// One haloed input plane held in registers between its fetch and its LDS store.
+template <int C>
+struct PlaneRegs {
+    static constexpr int kPer = C == 16 ? (PCELLS * 2 + kThreads - 1) / kThreads : (PCELLS + kThreads - 1) / kThreads;
+    typename std::conditional<C == 16, uint4, uint32_t>::type v[kPer];
+};
+
+template <int C>
+__device__ __forceinline__ void fetch_plane(const uint16_t* __restrict__ in, const Geom& g, int i, int j0,
+                                            int k0, PlaneRegs<C>& R) {
+    const bool iin = i >= 0 && i < g.nx;
+#pragma unroll
+    for (int u = 0; u < PlaneRegs<C>::kPer; ++u) {
+        const int c = threadIdx.x + u * kThreads;
+        if constexpr (C == 16) {
+            const int cell = c >> 1, half = c & 1;
+            const int hy = cell / HZ, hz = cell % HZ;
+            const int j = j0 - 1 + hy, k = k0 - 1 + hz;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (cell < PCELLS && iin && j >= 0 && j < g.ny && k >= 0 && k < g.nz) {
+                const int64_t l = ((int64_t)i * g.ny + j) * g.nz + k;
+                v = *reinterpret_cast<const uint4*>(in + l * 16 + half * 8);
+            }
+            R.v[u] = v;
+        } else {
+            const int hy = c / HZ, hz = c % HZ;
+            const int j = j0 - 1 + hy, k = k0 - 1 + hz;
+            uint32_t v = 0;
+            if (c < PCELLS && iin && j >= 0 && j < g.ny && k >= 0 && k < g.nz) {
+                const int64_t l = ((int64_t)i * g.ny + j) * g.nz + k;
+                v = *reinterpret_cast<const uint32_t*>(in + l * 2);
+            }
+            R.v[u] = v;
+        }
+    }
+}
+
+template <int C>
+__device__ __forceinline__ void store_plane(const PlaneRegs<C>& R, uint16_t* slot) {
+#pragma unroll
+    for (int u = 0; u < PlaneRegs<C>::kPer; ++u) {
+        const int c = threadIdx.x + u * kThreads;
+        if constexpr (C == 16) {
+            // 8-byte channel quad q of cell `cell` sits at quad position q ^ swz(cell)
+            if (c < PCELLS * 2) {
+                const int cell = c >> 1, half = c & 1, sw = (cell >> 2) & 3;
+                uint4 v = R.v[u];
+                if (sw & 1) v = make_uint4(v.z, v.w, v.x, v.y);
+                *reinterpret_cast<uint4*>(slot + cell * 16 + (half ^ (sw >> 1)) * 8) = v;
+            }
+        } else {
+            if (c < PCELLS) *reinterpret_cast<uint32_t*>(slot + c * 2) = R.v[u];
+        }
+    }
+}
+
+// Accumulate one wave's 64-cell output row (4 MFMA tiles of 16 cells) from the
+// three haloed planes at p[0..2] (x offsets -1, 0, +1). The weights are the A
+// operand (rows: output channels) and the activations the B operand (columns:
+// cells), so lane (m, g) ends with output channels 4g..4g+3 of cell m.
 // C = 16: K = 27 taps x 16 channels; C = 2: K = 64 (tap, channel) pairs.
 template <int C>
-__device__ __forceinline__ void conv_row(const uint16_t* lds, const v4s* __restrict__ W, v4f acc[4]) {
+__device__ __forceinline__ void conv_row(const uint16_t* const p[3], const v4s* wr, v4f acc[4]) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m = lane & 15, kg = lane >> 4;
     if (C == 16) {
 #pragma unroll
         for (int t = 0; t < 27; ++t) {
-            const int dx = t / 9 - 1, dy = (t / 3) % 3 - 1, dz = t % 3 - 1;
-            const v4s b = W[t * 64 + lane];
+            const int dx = t / 9, dy = (t / 3) % 3, dz = t % 3;
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
-                const int cell = hcell(1 + dx, w + 1 + dy, mt * 16 + m + 1 + dz);
-                const v4s a = *reinterpret_cast<const v4s*>(lds + cell * 16 + kg * 4);
-                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[mt], 0, 0, 0);
+                const int cell = (w + dy) * HZ + mt * 16 + m + dz;
+                const v4s x = *reinterpret_cast<const v4s*>(p[dx] + cell * 16 + ((kg ^ (cell >> 2)) & 3) * 4);
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wr[t], x, acc[mt], 0, 0, 0);
             }
         }
     } else {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int tA = s * 8 + 2 * kg, tB = tA + 1;
-            const v4s b = W[s * 64 + lane];
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
                 uint32_t wa = 0, wb = 0;
                 if (tA < 27) {
-                    const int dx = tA / 9 - 1, dy = (tA / 3) % 3 - 1, dz = tA % 3 - 1;
-                    wa = *reinterpret_cast<const uint32_t*>(lds + hcell(1 + dx, w + 1 + dy, mt * 16 + m + 1 + dz) * 2);
+                    const int dx = tA / 9, dy = (tA / 3) % 3, dz = tA % 3;
+                    wa = *reinterpret_cast<const uint32_t*>(p[dx] + ((w + dy) * HZ + mt * 16 + m + dz) * 2);
                 }
                 if (tB < 27) {
-                    const int dx = tB / 9 - 1, dy = (tB / 3) % 3 - 1, dz = tB % 3 - 1;
-                    wb = *reinterpret_cast<const uint32_t*>(lds + hcell(1 + dx, w + 1 + dy, mt * 16 + m + 1 + dz) * 2);
+                    const int dx = tB / 9, dy = (tB / 3) % 3, dz = tB % 3;
+                    wb = *reinterpret_cast<const uint32_t*>(p[dx] + ((w + dy) * HZ + mt * 16 + m + dz) * 2);
                 }
-                v4s a;
-                a.x = (short)(wa & 0xffff);
-                a.y = (short)(wa >> 16);
-                a.z = (short)(wb & 0xffff);
-                a.w = (short)(wb >> 16);
-                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[mt], 0, 0, 0);
+                v4s x;
+                x.x = (short)(wa & 0xffff);
+                x.y = (short)(wa >> 16);
+                x.z = (short)(wb & 0xffff);
+                x.w = (short)(wb >> 16);
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wr[s], x, acc[mt], 0, 0, 0);
             }
         }
+    }
+}
+
+// The last layer (16 -> 1 channel) of one wave's 64-cell row. With a single
+// output channel the MFMA rows carry the three z taps instead: for each of the
+// 9 (dx, dy) groups, D[dz][z] += sum_ci W[dx][dy][dz][ci] x[i+dx-1][j+dy-1][z][ci]
+// over the unshifted cells z, and the output is D[0][z-1] + D[1][z] + D[2][z+1],
+// the z neighbours taken from the adjacent lanes. A fifth tile holds the two
+// cells beyond the row ends (column 0: z = k0-1, the others: z = k0+64).
+// Returns, on lanes 0..15, the outputs of cells m, m+16, m+32, m+48 of the row.
+__device__ __forceinline__ void conv_last_row(const uint16_t* const p[3], const v4s* wz, float y[4]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m = lane & 15, kg = lane >> 4;
+    v4f acc[5];
+#pragma unroll
+    for (int t = 0; t < 5; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int grp = 0; grp < 9; ++grp) {
+        const int dx = grp / 3, dy = grp % 3;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+            const int hz = t < 4 ? t * 16 + m + 1 : (m == 0 ? 0 : HZ - 1);
+            const int cell = (w + dy) * HZ + hz;
+            const v4s x = *reinterpret_cast<const v4s*>(p[dx] + cell * 16 + ((kg ^ (cell >> 2)) & 3) * 4);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wz[grp], x, acc[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const float left = __shfl(acc[t][0], (lane + 63) & 63);
+        const float right = __shfl(acc[t][2], (lane + 1) & 63);
+        const float lb = __shfl(t > 0 ? acc[t - 1][0] : acc[4][0], t > 0 ? 15 : 0);
+        const float rb = __shfl(t < 3 ? acc[t + 1][2] : acc[4][2], t < 3 ? 0 : 1);
+        y[t] = acc[t][1] + (m == 0 ? lb : left) + (m == 15 ? rb : right);
     }
 }
 
@@ -171,51 +276,120 @@ struct ConvArgs {
     const uint8_t* dmask;
     const float* sscale;    // kPrecond: device scalar s
     int relu;               // 1: ReLU after the hidden layers, 0: identity
-    int ntj, ntk, ntiles;
+    int ntk;                // column tiles along z
+    int ncols;              // column tiles in total (y tiles x z tiles)
+    int run;                // x planes per block
 };
 
+__device__ __forceinline__ uint32_t pack_bf2(float lo, float hi) {
+    return (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
+}
+
+// grid: ncols * ceil(nx / run) blocks of kThreads.
 template <int C, int MODE>
 __global__ __launch_bounds__(kThreads) void conv3d(Geom g, ConvArgs a) {
-    __shared__ __attribute__((aligned(16))) uint16_t lds[HCELLS * C];
+    __shared__ __attribute__((aligned(16))) uint16_t lds[kRing * PCELLS * C];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int co = lane & 15, rg = lane >> 4;
+    const int m = lane & 15, rg = lane >> 4;
+    const int col = blockIdx.x % a.ncols, chunk = blockIdx.x / a.ncols;
+    const int j0 = (col / a.ntk) * TY, k0 = (col % a.ntk) * TZ;
+    const int i0 = chunk * a.run;
+    const int i1 = min(g.nx, i0 + a.run);
+    const int j = j0 + w;
+    constexpr bool kLast = MODE == kFinal || MODE == kPrecond;
+    constexpr int NW = kLast ? 9 : (C == 16 ? 27 : 4);
+    v4s wr[NW];
+#pragma unroll
+    for (int t = 0; t < NW; ++t) wr[t] = a.W[t * 64 + lane];
+    float bias[4] = {0.f, 0.f, 0.f, 0.f};
+    if (MODE == kHiddenRelu) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bias[q] = a.bias[rg * 4 + q];
+    } else if (MODE == kFinal || MODE == kPrecond) {
+        bias[0] = a.bias[0];
+    }
     const float s = (MODE == kPrecond) ? *a.sscale : 0.f;
-    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        const Tile T = tile_of(t, a.ntj, a.ntk);
-        __syncthreads();
-        load_halo<C>(a.in, g, T, lds);
-        __syncthreads();
-        v4f acc[4];
+    const float floor_act = a.relu ? 0.f : -INFINITY;   // hidden activation: max(x, floor)
+    const uint32_t keep_all = a.relu ? 0u : 1u;          // input gradient without a ReLU mask
+    // slot of plane p: (p - i0 + 1) & 3
+    {
+        // the first three planes: all loads in flight before the first LDS store
+        PlaneRegs<C> R0, R1, R2;
+        fetch_plane<C>(a.in, g, i0 - 1, j0, k0, R0);
+        fetch_plane<C>(a.in, g, i0, j0, k0, R1);
+        fetch_plane<C>(a.in, g, i0 + 1, j0, k0, R2);
+        store_plane<C>(R0, lds);
+        store_plane<C>(R1, lds + PCELLS * C);
+        store_plane<C>(R2, lds + 2 * PCELLS * C);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int i = i0; i < i1; ++i) {
+        const bool more = i + 1 < i1;
+        PlaneRegs<C> R;
+        if (more) fetch_plane<C>(a.in, g, i + 2, j0, k0, R);
+        if (j < g.ny) {
+            const uint16_t* p[3];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) acc[mt] = v4f{0.f, 0.f, 0.f, 0.f};
-        conv_row<C>(lds, a.W, acc);
-        const int j = T.j0 + w;
-        if (j >= g.ny) continue;
+            for (int d = 0; d < 3; ++d) p[d] = lds + ((i - i0 + d) & 3) * PCELLS * C;
+            const int64_t row = ((int64_t)i * g.ny + j) * g.nz;
+            if constexpr (kLast) {
+                float y[4];
+                conv_last_row(p, wr, y);
+                if (rg == 0) {
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int k = T.k0 + mt * 16 + rg * 4 + q;
-                if (k >= g.nz) continue;
-                const int64_t l = ((int64_t)T.i * g.ny + j) * g.nz + k;
-                const float v = acc[mt][q];
-                if (MODE == kHiddenRelu) {
-                    const float h = v + a.bias[co];
-                    a.out16[l * 16 + co] = f2bf(a.relu ? fmaxf(h, 0.f) : h);
-                } else if (MODE == kGradMasked) {
-                    const bool on = !a.relu || bf2f(a.below[l * 16 + co]) > 0.f;
-                    a.out16[l * 16 + co] = f2bf(on ? v : 0.f);
-                } else if (co == 0) {
-                    const float y = v + a.bias[0];
-                    if (MODE == kFinal) {
-                        a.out32[l] = y;
-                    } else {
-                        const float di = a.dinv[l];
-                        a.out32[l] = a.dmask[l] ? 0.f : di * a.r[l] + s * sqrtf(di) * y;
+                    for (int mt = 0; mt < 4; ++mt) {
+                        const int k = k0 + mt * 16 + m;
+                        if (k >= g.nz) continue;
+                        const int64_t l = row + k;
+                        const float v = y[mt] + bias[0];
+                        if (MODE == kFinal) {
+                            a.out32[l] = v;
+                        } else {
+                            const float di = a.dinv[l];
+                            a.out32[l] = a.dmask[l] ? 0.f : di * a.r[l] + s * sqrtf(di) * v;
+                        }
                     }
                 }
+            } else {
+            v4f acc[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) acc[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+            conv_row<C>(p, wr, acc);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const int k = k0 + mt * 16 + m;
+                if (k >= g.nz) continue;
+                const int64_t l = row + k;
+                // Both epilogues are branch-free: hipcc (ROCm 7.2) miscompiled a
+                // per-lane select between the accumulator and 0 written with a
+                // branch here (the accumulator register was cleared on every lane).
+                if (MODE == kHiddenRelu) {
+                    float h[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) h[q] = fmaxf(acc[mt][q] + bias[q], floor_act);
+                    *reinterpret_cast<uint2*>(a.out16 + l * 16 + rg * 4) =
+                        make_uint2(pack_bf2(h[0], h[1]), pack_bf2(h[2], h[3]));
+                } else if (MODE == kGradMasked) {
+                    float h[4];
+                    const uint2 bl = *reinterpret_cast<const uint2*>(a.below + l * 16 + rg * 4);
+                    // ReLU mask: keep the gradient where the activation below is > 0
+                    // (positive BF16 values are positive as signed 16-bit integers)
+                    const uint32_t bw[4] = {bl.x << 16, bl.x & 0xffff0000u, bl.y << 16, bl.y & 0xffff0000u};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t pos = (uint32_t)((int32_t)bw[q] > 0);
+                        const uint32_t keep = 0u - (pos | keep_all);
+                        h[q] = __uint_as_float(__float_as_uint(acc[mt][q]) & keep);
+                    }
+                    *reinterpret_cast<uint2*>(a.out16 + l * 16 + rg * 4) =
+                        make_uint2(pack_bf2(h[0], h[1]), pack_bf2(h[2], h[3]));
+                }
+            }
             }
         }
+        if (more) store_plane<C>(R, lds + ((i - i0 + 3) & 3) * PCELLS * C);
+        __syncthreads();
     }
 }
 
@@ -473,12 +647,14 @@ __global__ void prepare_weights(const float* p, v4s* W) {
         if (idx < kWf2) {                                   // layer 1 forward
             const int s = idx / 64, k = s * 16 + r, tap = k >> 1, ch = k & 1;
             if (tap < 27) x = p[offW(0) + (tap * 2 + ch) * 16 + col];
-        } else if (idx < kWb4) {                            // layers 2..4 forward
-            const int l = idx < kWf3 ? 1 : (idx < kWf4 ? 2 : 3);
-            const int base = l == 1 ? kWf2 : (l == 2 ? kWf3 : kWf4);
+        } else if (idx < kWf4) {                            // layers 2, 3 forward
+            const int l = idx < kWf3 ? 1 : 2;
+            const int base = l == 1 ? kWf2 : kWf3;
             const int tap = (idx - base) / 64;
-            if (l < 3) x = p[offW(l) + (tap * 16 + r) * 16 + col];
-            else if (col == 0) x = p[offW(3) + tap * 16 + r];
+            x = p[offW(l) + (tap * 16 + r) * 16 + col];
+        } else if (idx < kWb4) {                            // layer 4 forward: row = dz
+            const int grp = (idx - kWf4) / 64;              // (dx, dy) group
+            if (col < 3) x = p[offW(3) + (grp * 3 + col) * 16 + r];
         } else if (idx < kWb3) {                            // layer 4 input gradient
             const int s = (idx - kWb4) / 64, k = s * 16 + r, tap = k >> 1, ch = k & 1;
             if (tap < 27 && ch == 0) x = p[offW(3) + (26 - tap) * 16 + col];
@@ -629,14 +805,36 @@ Shape shape_of(int nx, int ny, int nz) {
     return s;
 }
 
+// Blocks of a kernel that fit on the device at once (CUs x resident blocks per CU).
+template <class K>
+int64_t resident_blocks(K kernel) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess)
+        return 768;
+    return std::max<int64_t>(1, (int64_t)cus * per_cu);
+}
+
+// x planes per block of the marching convolution: the shortest run for which
+// all blocks are resident at once (one round, no tail), but at least two
+// planes, so the two halo planes of a run cost at most one plane per output plane.
+int conv_run(const Shape& S, int64_t slots) {
+    const int64_t cols = (int64_t)S.ntj * S.ntk;
+    int64_t run = (S.g.nx * cols + slots - 1) / slots;
+    run = std::max<int64_t>(run, 2);
+    return (int)std::min<int64_t>(run, S.g.nx);
+}
+
 template <int C, int MODE>
 int conv(const Shape& S, const ConvArgs& a0, hipStream_t st) {
+    static const int64_t slots = resident_blocks(conv3d<C, MODE>);
     ConvArgs a = a0;
-    a.ntj = S.ntj;
     a.ntk = S.ntk;
-    a.ntiles = S.ntiles;
-    const int blocks = std::min(S.ntiles, 16384);
-    hipLaunchKernelGGL((conv3d<C, MODE>), dim3(blocks), dim3(kThreads), 0, st, S.g, a);
+    a.ncols = S.ntj * S.ntk;
+    a.run = conv_run(S, slots);
+    const int64_t blocks = (int64_t)a.ncols * ((S.g.nx + a.run - 1) / a.run);
+    hipLaunchKernelGGL((conv3d<C, MODE>), dim3((unsigned)blocks), dim3(kThreads), 0, st, S.g, a);
     NHIP(hipGetLastError());
     return MFFV_OK;
 }

@@ -39,7 +39,14 @@ March plan_march(const Geom& g, int vec, int ci, int remap) {
 namespace {
 
 __device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
-__device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
+// Results are written with streaming (nontemporal) stores: they are read again
+// only by the next kernel, and keeping them out of the way in L2 leaves room
+// for the neighbour rows the other blocks still need.
+typedef float f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st4(float* p, float4 v) {
+    const f4v w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<f4v*>(p));
+}
 __device__ __forceinline__ float4 f4(float v) { return make_float4(v, v, v, v); }
 __device__ __forceinline__ float4 axpy4(float a, float4 x, float4 y) {
     return make_float4(y.x + a * x.x, y.y + a * x.y, y.z + a * x.z, y.w + a * x.w);

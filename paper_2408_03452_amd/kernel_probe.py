@@ -1,0 +1,61 @@
+"""A short, fixed sequence of the solver's kernels for hardware-counter runs.
+
+Runs, on the correlated log-normal 256^3 workload: 10 stencil applies, one
+FP32 CG solve capped at 64 iterations (no graph replay, so every phase-A and
+phase-B launch is its own dispatch), and 5 streaming copies of 1 GiB. The copy
+moves a known number of bytes (1 GiB read, 1 GiB written per dispatch), which
+calibrates the FETCH_SIZE / WRITE_SIZE counters against the stencil kernels'
+algorithmic bytes.
+
+    rocprofv3 --pmc FETCH_SIZE -d OUT -o probe -- python3 -m paper_2408_03452_amd.kernel_probe
+    rocprofv3 --pmc WRITE_SIZE -d OUT -o probe -- python3 -m paper_2408_03452_amd.kernel_probe
+"""
+from __future__ import annotations
+
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main() -> int:
+    import torch
+    from paper_2408_03452_amd import mffv
+    from synth import WORKLOADS, workload_field
+
+    w = WORKLOADS["lognormal_corr8_256cube"]
+    nx, ny, nz = w.shape
+    n = w.n
+    print(f"[probe] {mffv.version()}: {w.name} {w.shape}", flush=True)
+    k = workload_field(w)
+    dev = torch.device("cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        kd = torch.from_numpy(k.ravel()).to(dev)
+        tx, ty, tz, b = (torch.empty(n, dtype=torch.float32, device=dev) for _ in range(4))
+        mffv.perm_to_trans(nx, ny, nz, kd, w.kz_ratio, tx, ty, tz, stream=s)
+        g = mffv.create_grid(nx, ny, nz, stream=s)
+        mffv.set_transmissibility(g, tx, ty, tz, accum_scalar=w.c, b_out=b)
+        del kd
+        xa = torch.randn(n, dtype=torch.float32, device=dev)
+        ya = torch.empty_like(xa)
+        for _ in range(10):
+            mffv.apply(g, xa, ya)
+        x = torch.zeros(n, dtype=torch.float32, device=dev)
+        st, info = mffv.cg_solve(g, b, x, mffv.default_opts(tol=w.tol, max_iter=64, use_graph=0))
+        print(f"[probe] cg: {info['iters']} iterations, status {st}", flush=True)
+        nbytes = 1 << 30
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            mffv.copy_probe(dst, src, nbytes, stream=s)
+    torch.cuda.synchronize()
+    g.close()
+    print("[probe] done", flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

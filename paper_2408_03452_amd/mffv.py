@@ -39,13 +39,13 @@ class Opts(ctypes.Structure):
                 ("precision", ctypes.c_int), ("precond", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("net", ctypes.c_void_p)]
+                ("net", ctypes.c_void_p), ("timing", ctypes.c_int)]
 
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("ci", ctypes.c_int), ("remap", ctypes.c_int), ("vec", ctypes.c_int),
                 ("blocks", ctypes.c_int), ("apply_us", ctypes.c_double),
-                ("candidates", ctypes.c_int)]
+                ("candidates", ctypes.c_int), ("phase_a_us", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -54,7 +54,9 @@ class TuneResult(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("ir_steps", ctypes.c_int),
                 ("fallbacks", ctypes.c_int), ("rel_res_recursive", ctypes.c_double),
-                ("rel_res_true", ctypes.c_double), ("ms", ctypes.c_double)]
+                ("rel_res_true", ctypes.c_double), ("ms", ctypes.c_double),
+                ("phase_a_us", ctypes.c_double), ("phase_b_us", ctypes.c_double),
+                ("precond_us", ctypes.c_double), ("timed_iters", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -121,10 +123,11 @@ def lib():
     """The loaded libmffv (raises if it is not built)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+        path = os.environ.get("MFFV_LIBRARY", LIB_PATH)
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with "
                                "`python -m paper_2408_03452_amd.build` (hipcc, gfx950)")
-        _lib = _declare(ctypes.CDLL(LIB_PATH))
+        _lib = _declare(ctypes.CDLL(path))
     return _lib
 
 

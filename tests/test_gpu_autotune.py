@@ -82,3 +82,22 @@ def test_autotune_batched_keeps_results(mf):
         p = ref.direct()
         assert np.linalg.norm(host(x) - p) <= 5e-5 * np.linalg.norm(p)
     mf.set_batched_launch(0, 4)
+
+
+def test_kernel_timing_keeps_results(mf):
+    shape = (40, 24, 64)
+    k = lognormal_iid(shape, 1.0, 5)
+    g, _, b = gpu_problem(mf, k, c=1e-3)
+    xs = []
+    for timing in (0, 1):
+        x = torch.zeros(k.size, dtype=torch.float32, device="cuda")
+        st, info = mf.cg_solve(g, b, x, mf.default_opts(tol=1e-6, timing=timing))
+        assert st == mf.OK
+        xs.append(host(x))
+        if timing:
+            assert info["timed_iters"] == min(32, info["iters"])
+            assert info["phase_a_us"] > 0 and info["phase_b_us"] > 0 and info["precond_us"] >= 0
+            assert info["phase_a_us"] < info["ms"] * 1e3
+        else:
+            assert info["timed_iters"] == 0 and info["phase_a_us"] == 0
+    assert np.array_equal(xs[0], xs[1])
