@@ -9,7 +9,7 @@ coefficients and the right-hand side) are resident in device memory before
 the timed region starts.
 
 Besides the headline time it measures, on the grid's own stream with HIP
-events: the stencil apply (24 algorithmic bytes per cell) against the MI355X
+events: the stencil apply (20 algorithmic bytes per cell) against the MI355X
 HBM peak, the library's streaming copy (the achievable ceiling), and the
 FP64 oracle on the host (SciPy CSR CG, one thread) on a 64^3 crop of the same
 field as the CPU baseline.
@@ -30,9 +30,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published peak
-APPLY_BYTES_PER_CELL = 24       # x, a, Tx, Ty, Tz read; y written (FP32)
-CG_BYTES_PER_CELL_ITER = 52     # fused phase A (40) + phase B (12), FP32
-PHASE_A_BYTES_PER_CELL = 40     # r, p_old, x, a, Tx, Ty, Tz read; p, q, x written
+# Algorithmic bytes per cell (FP32). With a scalar accumulation and the x-plane
+# Dirichlet set (every workload here) the identity coefficient is the
+# accumulation itself away from the Dirichlet planes and is not a per-cell
+# stream: the kernels read it only on the four planes at the ends.
+APPLY_BYTES_PER_CELL = 20       # x, Tx, Ty, Tz read; y written
+CG_BYTES_PER_CELL_ITER = 48     # fused phase A (36) + phase B (12)
+PHASE_A_BYTES_PER_CELL = 36     # r, p_old, x, Tx, Ty, Tz read; p, q, x written
 PHASE_B_BYTES_PER_CELL = 12     # r, q read; r written
 METRIC = "time to rel-resid 1e-6 (learned FCG vs plain CG); stencil-apply HBM GB/s"
 # HBM bytes per phase-A launch on the 256^3 workload from rocprofv3 FETCH_SIZE and
@@ -73,6 +77,85 @@ def cpu_baseline(k, c, tol, crop=64):
         "time_to_solution_s": dt,
         "iters": res.iters,
     }
+
+
+def bench_large(log_fn, solve: bool, cg_iters: int = 200):
+    """The 512 x 512 x 1024 anisotropic workload (268 M cells, 1 GiB per FP32
+    vector): stencil apply and fused CG phases timed with HIP events on the
+    grid's stream at a size no cache holds, a fixed number of CG iterations
+    for the per-iteration rate, and with ``solve`` the full FP32 + FP64
+    refinement solve to 1e-8."""
+    import torch
+    from paper_2408_03452_amd import mffv
+    from synth import WORKLOADS, workload_field
+
+    w = WORKLOADS["anisotropic_512x512x1024"]
+    nx, ny, nz = w.shape
+    n = w.n
+    t0 = time.perf_counter()
+    k = workload_field(w)
+    log_fn(f"large: field {w.shape} generated in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda")
+    s = torch.cuda.Stream()
+    out = {"workload": w.name, "grid": list(w.shape), "cells": n, "kz_ratio": w.kz_ratio,
+           "accumulation": w.c}
+    with torch.cuda.stream(s):
+        kd = torch.from_numpy(k).to(dev).view(-1)
+        del k
+        tx, ty, tz, b = (torch.empty(n, dtype=torch.float32, device=dev) for _ in range(4))
+        mffv.perm_to_trans(nx, ny, nz, kd, w.kz_ratio, tx, ty, tz, stream=s)
+        del kd
+        g = mffv.create_grid(nx, ny, nz, stream=s)
+        mffv.set_transmissibility(g, tx, ty, tz, accum_scalar=w.c, b_out=b)
+        del tx, ty, tz
+        tune = mffv.autotune(g, None)
+        out["launch"] = {kk: tune[kk] for kk in ("ci", "remap", "vec", "blocks")}
+        xa = torch.randn(n, dtype=torch.float32, device=dev)
+        ya = torch.empty_like(xa)
+        for _ in range(3):
+            mffv.apply(g, xa, ya)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(20):
+            mffv.apply(g, xa, ya)
+        e1.record(s)
+        e1.synchronize()
+        apply_us = e0.elapsed_time(e1) / 20 * 1e3
+        del xa, ya
+        out["apply_us"] = apply_us
+        out["apply_GBps"] = APPLY_BYTES_PER_CELL * n / (apply_us * 1e-6) / 1e9
+        x = torch.zeros(n, dtype=torch.float32, device=dev)
+        st, info = mffv.cg_solve(g, b, x, mffv.default_opts(tol=1e-30, max_iter=cg_iters, timing=1))
+        out["phase_a_us"] = info["phase_a_us"]
+        out["phase_a_GBps"] = PHASE_A_BYTES_PER_CELL * n / (info["phase_a_us"] * 1e-6) / 1e9
+        out["phase_b_us"] = info["phase_b_us"]
+        x.zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, info = mffv.cg_solve(g, b, x, mffv.default_opts(tol=1e-30, max_iter=cg_iters))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        out["cg_iters_fixed"] = info["iters"]
+        out["cg_ms_per_iter"] = dt * 1e3 / max(1, info["iters"])
+        out["cells_iter_per_s"] = cells_iter_rate(n, info["iters"], dt)
+        log_fn(f"large: apply {apply_us:.0f} us ({out['apply_GBps']:.0f} GB/s), phase A "
+               f"{out['phase_a_us']:.0f} us ({out['phase_a_GBps']:.0f} GB/s), CG "
+               f"{out['cg_ms_per_iter']:.3f} ms/iter ({out['cells_iter_per_s'] / 1e9:.1f} Gcell*iter/s)")
+        if solve:
+            x.zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st, info = mffv.cg_solve(g, b, x, mffv.default_opts(
+                tol=w.tol_refined, precision=mffv.FP32_IR, max_iter=400000, check_every=32))
+            torch.cuda.synchronize()
+            out["solve"] = {"tol": w.tol_refined, "status": st, "s": time.perf_counter() - t1,
+                            "iters": info["iters"], "ir_steps": info["ir_steps"],
+                            "rel_res_true": info["rel_res_true"]}
+            log_fn(f"large: solve to {w.tol_refined:g}: {out['solve']['s']:.1f} s, "
+                   f"{info['iters']} iterations, true rel-res {info['rel_res_true']:.2e}")
+        g.close()
+    torch.cuda.synchronize()
+    return out
 
 
 def bench_batched(log_fn):
@@ -210,6 +293,10 @@ def main(argv=None):
     ap.add_argument("--learned-held-out", type=int, default=10,
                     help="held-out 128^3 realisations in the learned comparison (50 = full set)")
     ap.add_argument("--learned-held-in", type=int, default=200)
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 512x512x1024 apply / CG-rate measurement")
+    ap.add_argument("--large-solve", action="store_true",
+                    help="also solve the 512x512x1024 system to 1e-8 (minutes)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -325,6 +412,9 @@ def main(argv=None):
         del src, dst
     torch.cuda.synchronize()
 
+    large = None
+    if not args.no_large:
+        large = bench_large(log, args.large_solve)
     batched = None
     if not args.no_batched:
         log("batched: 64 uneven systems, one persistent launch")
@@ -372,6 +462,7 @@ def main(argv=None):
         "apply_GBps": apply_gbps,
         "copy_probe_GBps": copy_gbps,
         "jacobi_pcg": jac,
+        "large": large,
         "batched": batched,
         "learned": learned_res,
         "phase_a_us": phase_a_us,

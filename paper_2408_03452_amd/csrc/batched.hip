@@ -68,7 +68,8 @@ __device__ __forceinline__ void march_item(const Geom& g, const Coef& c, int pc,
     }
     for (int i = i0; i < i1; ++i, base += P) {
         const float sp = (i + 1 < g.nx) ? S(base + P) : sc;
-        const float txc = c.tx[base], tyc = c.ty[base], tzc = c.tz[base], ac = c.a[base];
+        const float txc = c.tx[base], tyc = c.ty[base], tzc = c.tz[base];
+        const float ac = coef_plane_uniform(c, i, g.nx) ? c.a_const : c.a[base];
         float tyl = 0.f, tzl = 0.f, sjm = sc, sjp = sc, skm = sc, skp = sc;
         if (hasjm) {
             tyl = c.ty[base - nz];

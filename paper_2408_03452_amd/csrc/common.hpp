@@ -36,7 +36,17 @@ struct Coef {
     const float* ty;
     const float* tz;
     const double* a64;
+    // a_uniform: a (and a64) equal a_const on the planes 2 <= i < nx - 2, so the
+    // kernels read the arrays only on the two planes at each end (a scalar
+    // accumulation with the x-plane Dirichlet set: away from those planes the
+    // identity coefficient is the accumulation alone)
+    int a_uniform;
+    float a_const;
 };
+
+__device__ __forceinline__ bool coef_plane_uniform(const Coef& c, int i, int nx) {
+    return c.a_uniform && i >= 2 && i < nx - 2;
+}
 
 // Scalars of one CG run, resident on the device between kernels so that the
 // host never sits between two iterations. No kernel reduces its own partial

@@ -221,7 +221,7 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
             txc = ld4(c.tx + base);
             tyc = ld4(c.ty + base);
             tzc = ld4(c.tz + base);
-            ac = ld4(c.a + base);
+            ac = coef_plane_uniform(c, i, g.nx) ? f4(c.a_const) : ld4(c.a + base);
             if (hasjm) {
                 tyl = ld4(c.ty + base - nz);
                 sjm = S4(base - nz);
@@ -349,7 +349,8 @@ __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<
                 }
             }
             const float txc = c.tx[base], tyc = c.ty[base], tzc = c.tz[base];
-            const real ac = std::is_same<real, double>::value ? (real)c.a64[base] : (real)c.a[base];
+            const real ac = coef_plane_uniform(c, i, g.nx) ? (real)c.a_const
+                            : std::is_same<real, double>::value ? (real)c.a64[base] : (real)c.a[base];
             float tyl = 0.f, tzl = 0.f;
             real sjm = sc, sjp = sc, skm = sc, skp = sc;
             if (hasjm) {

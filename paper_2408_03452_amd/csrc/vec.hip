@@ -260,6 +260,17 @@ __global__ void fill_f32(int64_t n, float* a, float v) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) a[e] = v;
 }
 
+// flag[0] = 1 if the two arrays differ in any bit (flag cleared by the caller);
+// every block that finds a difference stores the same value.
+__global__ __launch_bounds__(kThreads) void differ(int64_t n, const uint32_t* __restrict__ a,
+                                                   const uint32_t* __restrict__ b, int* flag) {
+    int d = 0;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) d |= a[e] != b[e];
+    d = __syncthreads_or(d);
+    if (d && threadIdx.x == 0) flag[0] = 1;
+}
+
 __global__ __launch_bounds__(kThreads) void copy_probe(const uint4* __restrict__ src,
                                                        uint4* __restrict__ dst, int64_t n16) {
     const int64_t stride = (int64_t)gridDim.x * kThreads;
@@ -488,6 +499,12 @@ hipError_t launch_convert_f64_to_f32(int64_t n, const double* a, float* b, hipSt
 
 hipError_t launch_fill_f32(int64_t n, float* a, float v, hipStream_t s) {
     hipLaunchKernelGGL(fill_f32, dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, a, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_differ(int64_t n, const float* a, const float* b, int* flag, hipStream_t s) {
+    hipLaunchKernelGGL(differ, dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n,
+                       reinterpret_cast<const uint32_t*>(a), reinterpret_cast<const uint32_t*>(b), flag);
     return hipGetLastError();
 }
 

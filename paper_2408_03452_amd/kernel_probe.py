@@ -1,6 +1,7 @@
 """A short, fixed sequence of the solver's kernels for hardware-counter runs.
 
-Runs, on the correlated log-normal 256^3 workload: 10 stencil applies, one
+Runs, on the correlated log-normal 256^3 workload with the autotuned launch
+shape (as bench.py): 10 stencil applies, one
 FP32 CG solve capped at 64 iterations (no graph replay, so every phase-A and
 phase-B launch is its own dispatch), and 5 streaming copies of 1 GiB. The copy
 moves a known number of bytes (1 GiB read, 1 GiB written per dispatch), which
@@ -39,6 +40,8 @@ def main() -> int:
         g = mffv.create_grid(nx, ny, nz, stream=s)
         mffv.set_transmissibility(g, tx, ty, tz, accum_scalar=w.c, b_out=b)
         del kd
+        tune = mffv.autotune(g, None)   # the launch shape bench.py times
+        print(f"[probe] launch: ci {tune['ci']}, remap {tune['remap']}, {tune['blocks']} blocks", flush=True)
         xa = torch.randn(n, dtype=torch.float32, device=dev)
         ya = torch.empty_like(xa)
         for _ in range(10):

@@ -1,0 +1,67 @@
+"""Summarise rocprofv3 CSV output per kernel and launch size.
+
+    python3 -m paper_2408_03452_amd.tracesum trace DIR    # --kernel-trace --output-format csv
+    python3 -m paper_2408_03452_amd.tracesum pmc DIR      # --pmc ... --output-format csv
+
+``trace`` groups the dispatches of ``*kernel_trace.csv`` by (kernel, grid
+size) and prints calls, total, mean and median duration. ``pmc`` groups the
+rows of ``*counter_collection.csv`` by (kernel, grid size, counter) and prints
+the mean counter value per dispatch; dispatches whose value is below 1 % of
+the group's largest (launches that returned at once, e.g. after convergence)
+are counted separately and left out of the mean.
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import glob
+import os
+import statistics
+import sys
+
+
+def _short(name: str) -> str:
+    name = name.replace("mffv::(anonymous namespace)::", "").replace("mffv::", "")
+    return name.split("(")[0] if "(" in name else name
+
+
+def _files(d: str, suffix: str) -> list:
+    return sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+
+
+def trace(d: str, top: int = 30) -> None:
+    groups = collections.defaultdict(list)
+    for f in _files(d, "kernel_trace.csv"):
+        with open(f, newline="") as fh:
+            for row in csv.DictReader(fh):
+                dur = (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e3
+                key = (_short(row["Kernel_Name"]), row.get("Grid_Size", "?"))
+                groups[key].append(dur)
+    tot_all = sum(sum(v) for v in groups.values())
+    print("| kernel | grid (work-items) | calls | total ms | mean us | median us | % of GPU time |")
+    print("|---|---:|---:|---:|---:|---:|---:|")
+    for (name, grid), v in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        print(f"| `{name}` | {grid} | {len(v)} | {sum(v) / 1e3:.2f} | {statistics.fmean(v):.2f} | "
+              f"{statistics.median(v):.2f} | {100 * sum(v) / tot_all:.2f} |")
+
+
+def pmc(d: str, top: int = 30) -> None:
+    groups = collections.defaultdict(list)
+    for f in _files(d, "counter_collection.csv"):
+        with open(f, newline="") as fh:
+            for row in csv.DictReader(fh):
+                key = (_short(row["Kernel_Name"]), row.get("Grid_Size", "?"), row["Counter_Name"])
+                groups[key].append(float(row["Counter_Value"]))
+    print("| kernel | grid (work-items) | counter | dispatches | mean per dispatch | skipped (< 1 % of max) |")
+    print("|---|---:|---|---:|---:|---:|")
+    for (name, grid, ctr), v in sorted(groups.items(), key=lambda kv: -max(kv[1]))[:top]:
+        hi = max(v)
+        keep = [x for x in v if x >= 0.01 * hi] or v
+        print(f"| `{name}` | {grid} | {ctr} | {len(keep)} | {statistics.fmean(keep):.1f} | {len(v) - len(keep)} |")
+
+
+if __name__ == "__main__":
+    if len(sys.argv) != 3 or sys.argv[1] not in ("trace", "pmc"):
+        print(__doc__)
+        sys.exit(2)
+    (trace if sys.argv[1] == "trace" else pmc)(sys.argv[2])
