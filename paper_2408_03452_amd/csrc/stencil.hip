@@ -133,6 +133,11 @@ __device__ bool phase_a_start(const StencilIO<real>& io, real* lds, PhaseA<real>
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO<float> io, March m) {
     __shared__ float red[kThreads / kWave];
+    // the chunk's own source values and y faces of the current plane (double
+    // buffered): y neighbours inside the chunk are read from here, only the
+    // rows just outside it from memory
+    __shared__ float4 ls[2][kThreads];
+    __shared__ float4 lty[2][kThreads];
 
     PhaseA<float> ph{0, 0.f, 0.f, false};
     if (MODE == kFusedCg && !phase_a_start(io, red, ph)) return;
@@ -164,6 +169,10 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
     const bool haskm = valid && k > 0;
     const bool haskp = valid && k + 4 < g.nz;
     const int nz = g.nz;
+    // offsets (cells) of the y neighbours from the chunk's first cell
+    const int64_t c0 = (int64_t)pc * kThreads * 4;
+    const int64_t jm_rel = r0 - nz - c0, jp_rel = r0 + nz - c0;
+    const bool jm_in = jm_rel >= 0, jp_in = jp_rel < (int64_t)kThreads * 4;
 
     // source value of the stencil: x, or r + beta p_old in the fused CG phase
     auto Z4 = [&](int64_t idx) -> float4 {
@@ -204,7 +213,8 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
             sm = sc;
         }
     }
-    for (int i = i0; i < i1; ++i, base += P) {
+    int buf = 0;
+    for (int i = i0; i < i1; ++i, base += P, buf ^= 1) {
         float4 txc = f4(0.f), tyc = f4(0.f), tzc = f4(0.f), ac = f4(0.f), tyl = f4(0.f);
         float4 sjm = sc, sjp = sc;
         if (valid) {
@@ -222,11 +232,21 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
             tyc = ld4(c.ty + base);
             tzc = ld4(c.tz + base);
             ac = coef_plane_uniform(c, i, g.nx) ? f4(c.a_const) : ld4(c.a + base);
+        }
+        ls[buf][threadIdx.x] = sc;
+        lty[buf][threadIdx.x] = tyc;
+        __syncthreads();
+        if (valid) {
             if (hasjm) {
-                tyl = ld4(c.ty + base - nz);
-                sjm = S4(base - nz);
+                if (jm_in) {
+                    sjm = ls[buf][jm_rel >> 2];
+                    tyl = lty[buf][jm_rel >> 2];
+                } else {
+                    tyl = ld4(c.ty + base - nz);
+                    sjm = S4(base - nz);
+                }
             }
-            if (hasjp) sjp = S4(base + nz);
+            if (hasjp) sjp = jp_in ? ls[buf][jp_rel >> 2] : S4(base + nz);
         }
         // z neighbours across the float4 boundary from the adjacent lanes
         float xl = __shfl_up(sc.w, 1, kWave);
