@@ -40,9 +40,10 @@ PHASE_A_BYTES_PER_CELL = 36     # r, p_old, x, Tx, Ty, Tz read; p, q, x written
 PHASE_B_BYTES_PER_CELL = 12     # r, q read; r written
 METRIC = "time to rel-resid 1e-6 (learned FCG vs plain CG); stencil-apply HBM GB/s"
 # HBM bytes per phase-A launch on the 256^3 workload from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE, scaled by the same counters on a copy of known size (null until taken
-# for the current kernel)
-TRAFFIC_PHASE_A = None
+# WRITE_SIZE (kernel_probe at the launch shape below), scaled by the same counters
+# on a copy of known size; reported only when this run's autotuner picks that shape
+TRAFFIC_PHASE_A = {"bytes": 676877702, "launch": {"ci": 16, "remap": 1},
+                   "profile": "profiles/stencil_cg_phase_a_lognormal_corr8_256cube_hbm_traffic.md"}
 
 
 def cells_iter_rate(cells: float, iters: float, seconds: float) -> float:
@@ -477,7 +478,9 @@ def main(argv=None):
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": phase_a_gbps / HBM_PEAK_GBPS,
-            "traffic": TRAFFIC_PHASE_A,
+            "traffic": (TRAFFIC_PHASE_A["bytes"]
+                        if all(tune[k] == v for k, v in TRAFFIC_PHASE_A["launch"].items()) else None),
+            "traffic_source": TRAFFIC_PHASE_A["profile"],
             "bytes_per_cell": PHASE_A_BYTES_PER_CELL,
             "cells_per_launch": n,
             "launch_us": phase_a_us,

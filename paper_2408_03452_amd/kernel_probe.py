@@ -1,15 +1,16 @@
 """A short, fixed sequence of the solver's kernels for hardware-counter runs.
 
-Runs, on the correlated log-normal 256^3 workload with the autotuned launch
-shape (as bench.py): 10 stencil applies, one
+Runs, on the correlated log-normal 256^3 workload with a given launch shape
+(the one bench.py's autotuner picked, default ci 8, remap 0): 10 stencil applies, one
 FP32 CG solve capped at 64 iterations (no graph replay, so every phase-A and
 phase-B launch is its own dispatch), and 5 streaming copies of 1 GiB. The copy
 moves a known number of bytes (1 GiB read, 1 GiB written per dispatch), which
 calibrates the FETCH_SIZE / WRITE_SIZE counters against the stencil kernels'
 algorithmic bytes.
 
-    rocprofv3 --pmc FETCH_SIZE -d OUT -o probe -- python3 -m paper_2408_03452_amd.kernel_probe
-    rocprofv3 --pmc WRITE_SIZE -d OUT -o probe -- python3 -m paper_2408_03452_amd.kernel_probe
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT -o probe -- python3 -m paper_2408_03452_amd.kernel_probe
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT -o probe -- python3 -m paper_2408_03452_amd.kernel_probe
+    python3 -m paper_2408_03452_amd.tracesum pmc OUT
 """
 from __future__ import annotations
 
@@ -21,7 +22,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
-def main() -> int:
+def main(argv=None) -> int:
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--ci", type=int, default=8, help="planes per block (bench.py: config.launch.ci)")
+    ap.add_argument("--remap", type=int, default=0, help="XCD-aware order (config.launch.remap)")
+    args = ap.parse_args(argv)
     import torch
     from paper_2408_03452_amd import mffv
     from synth import WORKLOADS, workload_field
@@ -40,8 +46,10 @@ def main() -> int:
         g = mffv.create_grid(nx, ny, nz, stream=s)
         mffv.set_transmissibility(g, tx, ty, tz, accum_scalar=w.c, b_out=b)
         del kd
-        tune = mffv.autotune(g, None)   # the launch shape bench.py times
-        print(f"[probe] launch: ci {tune['ci']}, remap {tune['remap']}, {tune['blocks']} blocks", flush=True)
+        # the launch shape bench.py's autotuner picked (timing under a counter
+        # run is distorted, so the shape is given rather than tuned here)
+        mffv.set_launch(g, args.ci, args.remap)
+        print(f"[probe] launch: ci {args.ci}, remap {args.remap}", flush=True)
         xa = torch.randn(n, dtype=torch.float32, device=dev)
         ya = torch.empty_like(xa)
         for _ in range(10):

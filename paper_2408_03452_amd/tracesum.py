@@ -25,6 +25,19 @@ def _short(name: str) -> str:
     return name.split("(")[0] if "(" in name else name
 
 
+def _grid(row: dict) -> str:
+    """Launch size in work-items, from whichever grid columns the CSV has."""
+    if row.get("Grid_Size"):
+        return row["Grid_Size"]
+    dims = [row.get(f"Grid_Size_{a}") for a in "XYZ"]
+    if any(dims):
+        n = 1
+        for d in dims:
+            n *= int(d or 1)
+        return str(n)
+    return "?"
+
+
 def _files(d: str, suffix: str) -> list:
     return sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
 
@@ -35,7 +48,7 @@ def trace(d: str, top: int = 30) -> None:
         with open(f, newline="") as fh:
             for row in csv.DictReader(fh):
                 dur = (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e3
-                key = (_short(row["Kernel_Name"]), row.get("Grid_Size", "?"))
+                key = (_short(row["Kernel_Name"]), _grid(row))
                 groups[key].append(dur)
     tot_all = sum(sum(v) for v in groups.values())
     print("| kernel | grid (work-items) | calls | total ms | mean us | median us | % of GPU time |")
@@ -50,7 +63,7 @@ def pmc(d: str, top: int = 30) -> None:
     for f in _files(d, "counter_collection.csv"):
         with open(f, newline="") as fh:
             for row in csv.DictReader(fh):
-                key = (_short(row["Kernel_Name"]), row.get("Grid_Size", "?"), row["Counter_Name"])
+                key = (_short(row["Kernel_Name"]), _grid(row), row["Counter_Name"])
                 groups[key].append(float(row["Counter_Value"]))
     print("| kernel | grid (work-items) | counter | dispatches | mean per dispatch | skipped (< 1 % of max) |")
     print("|---|---:|---|---:|---:|---:|")
