@@ -38,12 +38,18 @@ APPLY_BYTES_PER_CELL = 20       # x, Tx, Ty, Tz read; y written
 CG_BYTES_PER_CELL_ITER = 48     # fused phase A (36) + phase B (12)
 PHASE_A_BYTES_PER_CELL = 36     # r, p_old, x, Tx, Ty, Tz read; p, q, x written
 PHASE_B_BYTES_PER_CELL = 12     # r, q read; r written
+MERGED_BYTES_PER_CELL = 44      # single-reduction iteration: r, q, p, x, Tx, Ty, Tz read;
+                                # r, p, q, x written
 METRIC = "time to rel-resid 1e-6 (learned FCG vs plain CG); stencil-apply HBM GB/s"
-# HBM bytes per phase-A launch on the 256^3 workload from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (kernel_probe at the launch shape below), scaled by the same counters
-# on a copy of known size; reported only when this run's autotuner picks that shape
-TRAFFIC_PHASE_A = {"bytes": 676877702, "launch": {"ci": 16, "remap": 1},
-                   "profile": "profiles/stencil_cg_phase_a_lognormal_corr8_256cube_hbm_traffic.md"}
+# HBM bytes per launch of the step's dominant kernel on the 256^3 workload from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE (kernel_probe at the launch shape given),
+# scaled by the same counters on a copy of known size; reported only when this
+# run uses that kernel and its autotuner picks that shape
+TRAFFIC = {
+    "two_phase": {"bytes": 676877702, "launch": {"ci": 16, "remap": 1},
+                  "profile": "profiles/stencil_cg_phase_a_lognormal_corr8_256cube_hbm_traffic.md"},
+    "single_reduction": None,
+}
 
 
 def cells_iter_rate(cells: float, iters: float, seconds: float) -> float:
@@ -127,8 +133,10 @@ def bench_large(log_fn, solve: bool, cg_iters: int = 200):
         out["apply_GBps"] = APPLY_BYTES_PER_CELL * n / (apply_us * 1e-6) / 1e9
         x = torch.zeros(n, dtype=torch.float32, device=dev)
         st, info = mffv.cg_solve(g, b, x, mffv.default_opts(tol=1e-30, max_iter=cg_iters, timing=1))
-        out["phase_a_us"] = info["phase_a_us"]
-        out["phase_a_GBps"] = PHASE_A_BYTES_PER_CELL * n / (info["phase_a_us"] * 1e-6) / 1e9
+        bpc = MERGED_BYTES_PER_CELL if info["single_reduction"] else PHASE_A_BYTES_PER_CELL
+        out["single_reduction"] = info["single_reduction"] == 1
+        out["iter_kernel_us"] = info["phase_a_us"]
+        out["iter_kernel_GBps"] = bpc * n / (info["phase_a_us"] * 1e-6) / 1e9
         out["phase_b_us"] = info["phase_b_us"]
         x.zero_()
         torch.cuda.synchronize()
@@ -139,8 +147,8 @@ def bench_large(log_fn, solve: bool, cg_iters: int = 200):
         out["cg_iters_fixed"] = info["iters"]
         out["cg_ms_per_iter"] = dt * 1e3 / max(1, info["iters"])
         out["cells_iter_per_s"] = cells_iter_rate(n, info["iters"], dt)
-        log_fn(f"large: apply {apply_us:.0f} us ({out['apply_GBps']:.0f} GB/s), phase A "
-               f"{out['phase_a_us']:.0f} us ({out['phase_a_GBps']:.0f} GB/s), CG "
+        log_fn(f"large: apply {apply_us:.0f} us ({out['apply_GBps']:.0f} GB/s), iteration kernel "
+               f"{out['iter_kernel_us']:.0f} us ({out['iter_kernel_GBps']:.0f} GB/s), CG "
                f"{out['cg_ms_per_iter']:.3f} ms/iter ({out['cells_iter_per_s'] / 1e9:.1f} Gcell*iter/s)")
         if solve:
             x.zero_()
@@ -354,16 +362,37 @@ def main(argv=None):
         log(f"solve: {ms_per_step:.2f} ms, {iters:.0f} iterations, true rel-res "
             f"{infos[-1]['rel_res_true']:.3e}, ir_steps {infos[-1]['ir_steps']}")
 
-        # the dominant kernel of the step, the fused CG phase A, timed per launch
-        # with HIP events on the grid's stream during one more (untimed) solve
+        # the dominant kernel of the step (the single-reduction CG iteration, or
+        # phase A of the two-phase iteration), timed per launch with HIP events on
+        # the grid's stream during one more (untimed) solve with the same options
         x.zero_()
         st, tinfo = mffv.cg_solve(g, b, x, mffv.default_opts(
             tol=w.tol, precision=mffv.FP32_IR, check_every=16, use_graph=1, timing=1))
-        phase_a_us, phase_b_us = tinfo["phase_a_us"], tinfo["phase_b_us"]
+        merged = tinfo["single_reduction"] == 1
+        dom_us = tinfo["phase_a_us"]
+        dom_bytes = MERGED_BYTES_PER_CELL if merged else PHASE_A_BYTES_PER_CELL
+        dom_gbps = dom_bytes * n / (dom_us * 1e-6) / 1e9
+        log(f"{'single-reduction iteration' if merged else 'phase A'}: {dom_us:.1f} us/launch "
+            f"({dom_gbps:.0f} GB/s algorithmic), over {tinfo['timed_iters']} iterations")
+        traffic = TRAFFIC["single_reduction" if merged else "two_phase"]
+        # both forms of the iteration, per launch (the other one for comparison)
+        forms = {}
+        for sr in (0, 1):
+            if sr == int(merged):
+                tf = tinfo
+            else:
+                x.zero_()
+                st, tf = mffv.cg_solve(g, b, x, mffv.default_opts(
+                    tol=w.tol, precision=mffv.FP32_IR, check_every=16, use_graph=1, timing=1,
+                    single_reduction=sr))
+            forms[sr] = tf
+        phase_a_us, phase_b_us = forms[0]["phase_a_us"], forms[0]["phase_b_us"]
         phase_a_gbps = PHASE_A_BYTES_PER_CELL * n / (phase_a_us * 1e-6) / 1e9
         phase_b_gbps = PHASE_B_BYTES_PER_CELL * n / (phase_b_us * 1e-6) / 1e9
-        log(f"phase A: {phase_a_us:.1f} us/launch ({phase_a_gbps:.0f} GB/s), phase B: "
-            f"{phase_b_us:.1f} us/launch ({phase_b_gbps:.0f} GB/s), over {tinfo['timed_iters']} iterations")
+        merged_us = forms[1]["phase_a_us"]
+        merged_gbps = MERGED_BYTES_PER_CELL * n / (merged_us * 1e-6) / 1e9
+        log(f"two-phase: phase A {phase_a_us:.1f} us ({phase_a_gbps:.0f} GB/s) + phase B {phase_b_us:.1f} us "
+            f"({phase_b_gbps:.0f} GB/s); single-reduction: {merged_us:.1f} us ({merged_gbps:.0f} GB/s)")
 
         # Jacobi-PCG on the same system (context for the preconditioned comparison)
         jac = None
@@ -458,7 +487,8 @@ def main(argv=None):
         "rel_res_true": infos[-1]["rel_res_true"],
         "ir_steps": infos[-1]["ir_steps"],
         "cells_iter_per_s": gpu_rate,
-        "cg_effective_GBps": CG_BYTES_PER_CELL_ITER * gpu_rate / 1e9,
+        "cg_effective_GBps": (MERGED_BYTES_PER_CELL if merged else CG_BYTES_PER_CELL_ITER) * gpu_rate / 1e9,
+        "single_reduction": merged,
         "apply_us": apply_ms * 1e3,
         "apply_GBps": apply_gbps,
         "copy_probe_GBps": copy_gbps,
@@ -470,20 +500,24 @@ def main(argv=None):
         "phase_a_GBps": phase_a_gbps,
         "phase_b_us": phase_b_us,
         "phase_b_GBps": phase_b_gbps,
+        "single_reduction_us": merged_us,
+        "single_reduction_GBps": merged_gbps,
         "roofline": {
-            "kernel": "stencil_v4<1> (fused CG phase A: direction update, apply, deferred "
-                      "solution update, p.Ap partials)",
+            "kernel": ("stencil_v4<3> (single-reduction CG iteration: residual and direction "
+                       "updates, apply, deferred solution update, four dot partials)" if merged else
+                       "stencil_v4<1> (fused CG phase A: direction update, apply, deferred "
+                       "solution update, p.Ap partials)"),
             "bound": "hbm",
-            "achieved": phase_a_gbps,
+            "achieved": dom_gbps,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
-            "frac": phase_a_gbps / HBM_PEAK_GBPS,
-            "traffic": (TRAFFIC_PHASE_A["bytes"]
-                        if all(tune[k] == v for k, v in TRAFFIC_PHASE_A["launch"].items()) else None),
-            "traffic_source": TRAFFIC_PHASE_A["profile"],
-            "bytes_per_cell": PHASE_A_BYTES_PER_CELL,
+            "frac": dom_gbps / HBM_PEAK_GBPS,
+            "traffic": (traffic["bytes"] if traffic and all(tune[k] == v for k, v in
+                                                            traffic["launch"].items()) else None),
+            "traffic_source": traffic["profile"] if traffic else None,
+            "bytes_per_cell": dom_bytes,
             "cells_per_launch": n,
-            "launch_us": phase_a_us,
+            "launch_us": dom_us,
         },
         "cpu_baseline": cpu,
     }

@@ -84,6 +84,11 @@ typedef struct {
     int check_every;     /* iterations enqueued between host polls of the convergence flag (16) */
     int use_graph;       /* 1: replay a captured HIP graph of check_every iterations          */
     const mffv_net* net; /* network for MFFV_PRECOND_LEARNED                                  */
+    int single_reduction; /* 1: plain FP32 CG on the four-cells-per-thread path (nz % 4 == 0,
+                            16-byte aligned vectors) runs one kernel per iteration with a
+                            single reduction phase (r.r of the next iteration from a
+                            one-step recurrence on the exact r.r); 0 (default): the
+                            two-phase iteration, faster on one GPU                      */
     int timing;          /* 1 (mffv_cg_solve, FP32 or FP32_IR): time each kernel of the first
                             32 FP32 CG iterations with HIP events (no graph replay, same
                             arithmetic); means returned in mffv_info                      */
@@ -105,6 +110,8 @@ typedef struct {
     double phase_b_us;
     double precond_us;
     int timed_iters;
+    int single_reduction;      /* 1 if the FP32 iterations ran the single-reduction loop
+                                  (then phase_a_us is that one kernel, phase_b_us ~ 0) */
 } mffv_info;
 
 /* Library version string, e.g. "mffv 1.0 gfx950". Never NULL. */

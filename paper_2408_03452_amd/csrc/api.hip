@@ -98,6 +98,11 @@ struct mffv_grid {
     float *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr, *z = nullptr, *xw = nullptr,
           *bw = nullptr;
     CgState<float>* st32 = nullptr;
+    // single-reduction CG: second r and q buffers, scalars, partials [2][4][max_blocks]
+    float *r2 = nullptr, *q2 = nullptr, *partM = nullptr;
+    MergedState* ms = nullptr;
+    int mpar = 0;              // parity of the next single-reduction launch
+    CgGraph graphM;
     // FP64 workspace
     double *r64 = nullptr, *p064 = nullptr, *p164 = nullptr, *q64 = nullptr, *x64 = nullptr,
            *b64 = nullptr, *rres = nullptr;
@@ -204,6 +209,7 @@ void drop_graphs(mffv_grid* G) {
         if (gr.exec) { (void)hipGraphExecDestroy(gr.exec); gr.exec = nullptr; }
     for (auto& gr : G->graph64)
         if (gr.exec) { (void)hipGraphExecDestroy(gr.exec); gr.exec = nullptr; }
+    if (G->graphM.exec) { (void)hipGraphExecDestroy(G->graphM.exec); G->graphM.exec = nullptr; }
 }
 
 // Residual r = b - A x in FP64; ||r||^2 into out[1] and ||b_U||^2 into out[0]
@@ -238,6 +244,7 @@ struct LoopResult {
     int status = 0;
     int fallbacks = 0;
     double rel_rec = 0;
+    bool merged = false;  // ran the single-reduction loop
 };
 
 // Enqueue one CG iteration (phase A, phase B, and for flexible CG the
@@ -390,6 +397,10 @@ int enqueue_chunk(mffv_grid* G, CgGraph& graph, int chunk, bool use_graph, F&& o
     return MFFV_OK;
 }
 
+template <class real>
+bool state_done(const CgState<real>& st) { return st.done != 0; }
+bool state_done(const MergedState& st) { return st.s[0].done || st.s[1].done; }
+
 // Run the CG loop until the device flag says stop: enqueue chunk c, copy the
 // state to pinned memory behind it, then wait for the copy of chunk c-1.
 template <class State, class F>
@@ -407,10 +418,65 @@ int drive_loop(mffv_grid* G, State* st, int max_iter, int chunk, CgGraph& graph,
         if (c >= 1) {
             HIP_TRY(hipEventSynchronize(G->ev[(c - 1) & 1]));
             const State* hs = reinterpret_cast<const State*>(G->hstate + 256 * ((c - 1) & 1));
-            if (hs->done) stop = true;
+            if (state_done(*hs)) stop = true;
         }
     }
     HIP_TRY(hipStreamSynchronize(G->stream));
+    return MFFV_OK;
+}
+
+int ensure_merged(mffv_grid* G) {
+    if (G->ms) return MFFV_OK;
+    const size_t n = (size_t)G->g.n;
+    int rc;
+    if ((rc = dalloc(&G->r2, n)) || (rc = dalloc(&G->q2, n)) ||
+        (rc = dalloc(&G->partM, 8 * (size_t)G->max_blocks)) || (rc = dalloc(&G->ms, 1))) {
+        dfree(G->r2); dfree(G->q2); dfree(G->partM); dfree(G->ms);
+        return rc;
+    }
+    return MFFV_OK;
+}
+
+// The single-reduction loop applies to plain FP32 CG on the float4 path.
+bool merged_applies(const mffv_grid* G, int precond, const mffv_opts& o) {
+    return o.single_reduction && precond == MFFV_PRECOND_NONE && G->m32.vec == 4;
+}
+
+// Enqueue kernel K of the single-reduction CG; K's parity is G->mpar. Buffers
+// R[0] = r2, R[1] = r (r_0 from the initial residual), Q[0] = q2, Q[1] = q,
+// P[0] = p0, P[1] = p1: kernel K reads index (K + 1) & 1 and writes K & 1.
+int enqueue_merged(mffv_grid* G) {
+    const int par = G->mpar;
+    hipEvent_t* ev = nullptr;
+    if (G->timing && G->timed < kTimedIters) ev = G->tev[G->timed++];
+    if (ev) HIP_TRY(hipEventRecord(ev[0], G->stream));
+    float* R[2] = {G->r2, G->r};
+    float* Q[2] = {G->q2, G->q};
+    float* Pv[2] = {G->p0, G->p1};
+    const int nb = G->m32.blocks();
+    float* part = reinterpret_cast<float*>(G->partM);
+    StencilIO<float> a;
+    a.src = R[par ^ 1];
+    a.qin = Q[par ^ 1];
+    a.pin = Pv[par ^ 1];
+    a.rout = R[par];
+    a.pout = Pv[par];
+    a.out = Q[par];
+    a.xsol = G->xw;
+    a.partials = part + (size_t)par * 4 * nb;
+    a.pf = part + (size_t)(par ^ 1) * 4 * nb;
+    a.nb_f = nb;
+    a.pb = reinterpret_cast<float*>(G->partB);
+    a.nb_b = G->nb_vec;
+    a.ms = G->ms;
+    a.parity = par;
+    HIP_TRY(launch_stencil_f32(kMergedCg, G->g, coef_of(G), a, G->m32, G->stream));
+    if (ev) {
+        HIP_TRY(hipEventRecord(ev[1], G->stream));
+        HIP_TRY(hipEventRecord(ev[2], G->stream));
+        HIP_TRY(hipEventRecord(ev[3], G->stream));
+    }
+    G->mpar ^= 1;
     return MFFV_OK;
 }
 
@@ -448,6 +514,29 @@ int cg32(mffv_grid* G, double tol, int max_iter, int precond, const mffv_opts& o
     v.tol2 = (float)(tol * tol);
     v.max_iter = max_iter;
     HIP_TRY(launch_phase_b_f32(kBInit, G->g.n, v, G->nb_vec, G->stream));
+    if (merged_applies(G, precond, o)) {
+        int rc = ensure_merged(G);
+        if (rc) return rc;
+        HIP_TRY(launch_merged_init(G->ms, (float)(tol * tol), max_iter, G->stream));
+        G->mpar = 0;
+        // an even chunk keeps every captured launch's parity right on replay
+        const int chunk = std::max(2, (o.check_every + 1) & ~1);
+        const bool use_graph = o.use_graph && !o.timing && G->stream != nullptr;
+        rc = drive_loop(G, G->ms, max_iter + 1, chunk, G->graphM, use_graph,
+                        [&]() { return enqueue_merged(G); });
+        if (rc) return rc;
+        MergedState hs;
+        HIP_TRY(hipMemcpyAsync(&hs, G->ms, sizeof(hs), hipMemcpyDeviceToHost, G->stream));
+        HIP_TRY(hipStreamSynchronize(G->stream));
+        const MergedSlot& sl = hs.s[0].done ? hs.s[0] : hs.s[1];
+        out->iters = sl.iters;
+        out->status = (hs.s[0].done || hs.s[1].done) ? sl.status : MFFV_NOT_CONVERGED;
+        out->fallbacks = 0;
+        out->rel_rec = sl.bnorm2 > 0 ? std::sqrt((double)sl.rr / (double)sl.bnorm2) : 0.0;
+        out->merged = true;
+        if (G->timing && G->timed_real < 0) G->timed_real = sl.iters;
+        return MFFV_OK;
+    }
     if (precond == MFFV_PRECOND_LEARNED) {
         int rc = nn_precondition(net, G->g, G->r, G->dinv, G->dmask, G->z, pb + G->nb_vec, G->nb_vec,
                                  G->feat, (float)G->n_unknown, G->stream);
@@ -542,6 +631,8 @@ int validate_opts(const mffv_opts& o) {
         return fail(MFFV_EINVAL, "precond LEARNED needs opts.net");
     if (o.precision == MFFV_FP64 && o.precond != MFFV_PRECOND_NONE)
         return fail(MFFV_EINVAL, "FP64 CG supports precond NONE only");
+    if (o.single_reduction != 0 && o.single_reduction != 1)
+        return fail(MFFV_EINVAL, "opts.single_reduction must be 0 or 1");
     return MFFV_OK;
 }
 
@@ -552,6 +643,7 @@ int solve_ir(mffv_grid* G, const void* b, int b_f64, const mffv_opts& o, mffv_in
     if ((rc = ensure_ws32(G)) || (rc = ensure_x64(G))) return rc;
     HIP_TRY(launch_copy_dirichlet_f64(G->g.n, G->dmask, b, b_f64, G->x64, G->stream));
     int total = 0, steps = 0, fallbacks = 0;
+    bool merged = false;
     double rel = 0, rec = 0;
     int status = MFFV_NOT_CONVERGED;
     for (int outer = 0;; ++outer) {
@@ -575,6 +667,7 @@ int solve_ir(mffv_grid* G, const void* b, int b_f64, const mffv_opts& o, mffv_in
         if ((rc = cg32(G, inner, o.max_iter - total, o.precond, o, &lr))) return rc;
         total += lr.iters;
         fallbacks += lr.fallbacks;
+        merged = merged || lr.merged;
         steps += 1;
         rec = lr.rel_rec * rel;
         if (lr.status < 0) {
@@ -589,6 +682,7 @@ int solve_ir(mffv_grid* G, const void* b, int b_f64, const mffv_opts& o, mffv_in
         info->fallbacks = fallbacks;
         info->rel_res_true = rel;
         info->rel_res_recursive = rec;
+        info->single_reduction = merged ? 1 : 0;
     }
     return status;
 }
@@ -858,6 +952,7 @@ void mffv_default_opts(mffv_opts* o) {
     o->use_graph = 1;
     o->net = nullptr;
     o->timing = 0;
+    o->single_reduction = 0;
 }
 
 int mffv_create_grid(int nx, int ny, int nz, void* stream, mffv_grid** out) {
@@ -914,6 +1009,7 @@ void mffv_destroy_grid(mffv_grid* G) {
     dfree(G->dscal);
     dfree(G->r); dfree(G->p0); dfree(G->p1); dfree(G->q); dfree(G->z); dfree(G->xw);
     dfree(G->bw); dfree(G->st32);
+    dfree(G->r2); dfree(G->q2); dfree(G->partM); dfree(G->ms);
     dfree(G->r64); dfree(G->p064); dfree(G->p164); dfree(G->q64); dfree(G->x64); dfree(G->b64);
     dfree(G->rres); dfree(G->st64);
     if (G->hstate) (void)hipHostFree(G->hstate);
@@ -1040,6 +1136,7 @@ int mffv_cg_solve(mffv_grid* G, const float* b, float* x, const mffv_opts* opts,
         inf.ir_steps = 1;
         inf.fallbacks = lr.fallbacks;
         inf.rel_res_recursive = lr.rel_rec;
+        inf.single_reduction = lr.merged ? 1 : 0;
         status = lr.status;
     } else if (o.precision == MFFV_FP32_IR) {
         if ((rc = ensure_x64(G))) return rc;

@@ -77,6 +77,27 @@ struct CgState {
     int pad[3];
 };
 
+// Scalars of the single-reduction CG (one kernel per iteration). Kernel K
+// reads slot K & 1 and writes slot (K + 1) & 1, so no block reads a field that
+// another block of the same kernel writes; once a kernel finds the run over it
+// marks both slots done.
+struct MergedSlot {
+    int k;            // index K of the kernel that reads this slot
+    int done;         // 1 once converged, broken down or out of iterations
+    int status;       // 0 ok, 1 not converged, -4 breakdown
+    int iters;        // completed iterations at exit
+    float rr;         // r.r of the last completed iteration (exact)
+    float thresh2;    // (tol * ||b_U||)^2
+    float bnorm2;     // ||b_U||^2
+    float beta;       // last direction update (for inspection)
+};
+struct MergedState {
+    MergedSlot s[2];
+    float tol2;
+    int max_iter;
+    int pad[2];
+};
+
 // One cell of the eliminated operator in difference form:
 //   a x + sum over the six faces of T (x - x_nbr).
 template <class real, class creal>

@@ -16,6 +16,8 @@ struct March {
     int nchunk;  // chunks per plane
     int nich;    // plane groups along x
     int remap;   // 1: XCD-aware block order
+    int nseg;    // float4 path with nz > 256: chunks are 4 rows x 256 cells, nz / 256 per row
+                 // group (each wave one contiguous row segment); 0: flat chunks of the plane
     int blocks() const { return nchunk * nich; }
 };
 
@@ -43,9 +45,18 @@ struct StencilIO {
     int precond = 0;             // 0 none, 1 Jacobi, 2 flexible
     const float* dinv = nullptr; // flexible CG: Jacobi fallback z = dinv * r
     const real* rres = nullptr;  // flexible CG: r (for the fallback)
+    // single-reduction CG: previous r, q, p (read), new r, p, q (written), the
+    // scalars, the launch's parity and the dot partials [4][nb] of this kernel
+    // (partials) and of the previous one (pf, nb_f)
+    const real* qin = nullptr;
+    const real* pin = nullptr;
+    real* rout = nullptr;
+    real* pout = nullptr;
+    MergedState* ms = nullptr;
+    int parity = 0;
 };
 
-enum StencilMode { kApply = 0, kFusedCg = 1, kResidual = 2 };
+enum StencilMode { kApply = 0, kFusedCg = 1, kResidual = 2, kMergedCg = 3 };
 
 hipError_t launch_stencil_f32(int mode, const Geom& g, const Coef& c, const StencilIO<float>& io,
                               const March& m, hipStream_t s);
@@ -110,6 +121,7 @@ hipError_t launch_convert_f32_to_f64(int64_t n, const float* a, double* b, hipSt
 hipError_t launch_convert_f64_to_f32(int64_t n, const double* a, float* b, hipStream_t s);
 hipError_t launch_fill_f32(int64_t n, float* a, float v, hipStream_t s);
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s);
+hipError_t launch_merged_init(MergedState* ms, float tol2, int max_iter, hipStream_t s);
 // flag[0] = 1 if a and b (n floats) differ in any bit; flag[0] must be 0 before.
 hipError_t launch_differ(int64_t n, const float* a, const float* b, int* flag, hipStream_t s);
 

@@ -22,7 +22,16 @@ March plan_march(const Geom& g, int vec, int ci, int remap) {
     March m;
     m.vec = vec;
     const int64_t per_block = (int64_t)kThreads * vec;
-    m.nchunk = (int)((g.plane + per_block - 1) / per_block);
+    const int seg = kWave * 4;  // cells of one wave's row segment in the float4 path
+    if (vec == 4 && g.nz > seg && g.nz % seg == 0) {
+        // long rows: a flat chunk would be a single row, with every y neighbour
+        // outside it; 4 rows x 256 cells keep three of each four inside
+        m.nseg = g.nz / seg;
+        m.nchunk = ((g.ny + kThreads / kWave - 1) / (kThreads / kWave)) * m.nseg;
+    } else {
+        m.nseg = 0;
+        m.nchunk = (int)((g.plane + per_block - 1) / per_block);
+    }
     if (ci <= 0) {
         // default: enough blocks to give each CU several, but long marches
         const int64_t target = 4096;
@@ -127,6 +136,81 @@ __device__ bool phase_a_start(const StencilIO<real>& io, real* lds, PhaseA<real>
     return true;
 }
 
+// Start of kernel K of the single-reduction CG (Chronopoulos-Gear style: one
+// reduction phase per iteration). Kernel K - 1 left the partial sums of
+// p.q, r.r, r.q and q.q of its iterate (pq, rho_{K-1}, rq, qq); every block sums
+// them in the same order and forms
+//   alpha_{K-1} = rho_{K-1} / pq,
+//   rho_K = ||r_{K-1} - alpha q_{K-1}||^2 = rho_{K-1} - 2 alpha rq + alpha^2 qq,
+//   beta_{K-1} = rho_K / rho_{K-1},
+// the recurrence taking one step from the exact rho_{K-1}, so its rounding does
+// not accumulate. The convergence test uses the exact rho_{K-1}: the run stops
+// with x_{K-1}, which kernel K-1 completed. Kernel 0 takes r_0 and ||b_U||^2
+// from the initial-residual partials. Returns false, identically in every
+// block, once the run is over.
+struct MergedPh {
+    int k;
+    float alpha;  // alpha_{K-1} (0 for K = 0)
+    float beta;   // beta_{K-1} (0 for K = 0)
+};
+
+__device__ bool merged_start(const StencilIO<float>& io, float* lds, MergedPh& o) {
+    MergedState* ms = io.ms;
+    MergedSlot* cur = &ms->s[io.parity];
+    MergedSlot* nxt = &ms->s[io.parity ^ 1];
+    if (block_flag(&cur->done)) return false;
+    const int K = cur->k;
+    float rr, thresh2, bnorm2, alpha = 0.f, beta = 0.f;
+    bool bad = false;
+    if (K == 0) {
+        rr = sum_partials(io.pb, io.nb_b, lds);
+        const float bb = sum_partials(io.pb + 2 * io.nb_b, io.nb_b, lds);
+        bnorm2 = bb > 0.f ? bb : rr;
+        thresh2 = ms->tol2 * bnorm2;
+    } else {
+        const int nb = io.nb_f;
+        const float pq = sum_partials(io.pf, nb, lds);
+        rr = sum_partials(io.pf + nb, nb, lds);
+        const float rq = sum_partials(io.pf + 2 * nb, nb, lds);
+        const float qq = sum_partials(io.pf + 3 * nb, nb, lds);
+        thresh2 = cur->thresh2;
+        bnorm2 = cur->bnorm2;
+        bad = !(pq > 0.f) || !isfinite(pq);
+        alpha = rr / pq;
+        const float rho = rr - 2.f * alpha * rq + alpha * alpha * qq;
+        beta = rho > 0.f ? rho / rr : 0.f;  // a cancelled recurrence restarts the directions
+    }
+    const bool conv = isfinite(rr) && rr <= thresh2;
+    bad = !conv && (bad || !isfinite(rr));
+    const int done_iters = K == 0 ? 0 : K - 1;
+    const bool cap = done_iters >= ms->max_iter;
+    if (conv || bad || cap) {
+        if (first_thread()) {
+            for (MergedSlot* sl : {nxt, cur}) {
+                sl->status = conv ? 0 : (bad ? -4 : 1);
+                sl->iters = done_iters;
+                sl->rr = rr;
+                sl->thresh2 = thresh2;
+                sl->bnorm2 = bnorm2;
+                sl->done = 1;
+            }
+        }
+        return false;
+    }
+    if (first_thread()) {
+        nxt->k = K + 1;
+        nxt->done = 0;
+        nxt->rr = rr;
+        nxt->thresh2 = thresh2;
+        nxt->bnorm2 = bnorm2;
+        nxt->beta = beta;
+    }
+    o.k = K;
+    o.alpha = alpha;
+    o.beta = beta;
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 // FP32, four cells per thread along z (requires nz % 4 == 0).
 // ---------------------------------------------------------------------------
@@ -139,17 +223,28 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
     __shared__ float4 ls[2][kThreads];
     __shared__ float4 lty[2][kThreads];
 
+    constexpr bool kCg = MODE == kFusedCg || MODE == kMergedCg;
     PhaseA<float> ph{0, 0.f, 0.f, false};
     if (MODE == kFusedCg && !phase_a_start(io, red, ph)) return;
+    if (MODE == kMergedCg) {
+        // r_K = r_{K-1} - alpha q_{K-1} on the fly, then the same direction
+        // update and deferred solution update as phase A
+        MergedPh mp{0, 0.f, 0.f};
+        if (!merged_start(io, red, mp)) return;
+        ph.k = mp.k;
+        ph.beta = mp.beta;
+        ph.alpha_prev = mp.alpha;
+    }
     const int it = ph.k;
     const float beta = ph.beta, alpha_prev = ph.alpha_prev;
     const bool pending = it > 0;
-    const float* pold = (it & 1) ? io.p0 : io.p1;
-    float* pnew = (it & 1) ? io.p1 : io.p0;
-    const bool use_pold = (MODE == kFusedCg) && it > 0;
+    const float* pold = MODE == kMergedCg ? io.pin : ((it & 1) ? io.p0 : io.p1);
+    float* pnew = MODE == kMergedCg ? io.pout : ((it & 1) ? io.p1 : io.p0);
+    const bool use_pold = kCg && it > 0;
     // flexible CG fallback: the source is r / diag(A) instead of the network's z
     const bool jz = (MODE == kFusedCg) && ph.fallback;
     const float* zsrc = jz ? io.rres : io.src;
+    const bool rupd = MODE == kMergedCg && it > 0;  // r_K = r_{K-1} - alpha q_{K-1}
 
     const int b = m.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int pc = b % m.nchunk, ic = b / m.nchunk;
@@ -157,22 +252,33 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
     const int i1 = min(g.nx, i0 + m.ci);
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t P = g.plane;
-    const int64_t r0 = ((int64_t)pc * kThreads + threadIdx.x) * 4;
-    const bool valid = r0 < P;
+    int64_t r0;
+    bool valid;
     int j = 0, k = 0;
-    if (valid) {
-        j = (int)(r0 / g.nz);
-        k = (int)(r0 - (int64_t)j * g.nz);
+    int ystep;  // threads between a cell and its y neighbour inside the chunk
+    if (m.nseg) {
+        j = (pc / m.nseg) * (kThreads / kWave) + (int)(threadIdx.x / kWave);
+        k = (pc % m.nseg) * kWave * 4 + lane * 4;
+        valid = j < g.ny;
+        r0 = (int64_t)j * g.nz + k;
+        ystep = kWave;
+    } else {
+        r0 = ((int64_t)pc * kThreads + threadIdx.x) * 4;
+        valid = r0 < P;
+        if (valid) {
+            j = (int)(r0 / g.nz);
+            k = (int)(r0 - (int64_t)j * g.nz);
+        }
+        ystep = g.nz / 4;
     }
     const bool hasjm = valid && j > 0;
     const bool hasjp = valid && j + 1 < g.ny;
     const bool haskm = valid && k > 0;
     const bool haskp = valid && k + 4 < g.nz;
     const int nz = g.nz;
-    // offsets (cells) of the y neighbours from the chunk's first cell
-    const int64_t c0 = (int64_t)pc * kThreads * 4;
-    const int64_t jm_rel = r0 - nz - c0, jp_rel = r0 + nz - c0;
-    const bool jm_in = jm_rel >= 0, jp_in = jp_rel < (int64_t)kThreads * 4;
+    // LDS slots of the y neighbours when they lie inside the chunk
+    const int jm_slot = (int)threadIdx.x - ystep, jp_slot = (int)threadIdx.x + ystep;
+    const bool jm_in = jm_slot >= 0, jp_in = jp_slot < kThreads;
 
     // source value of the stencil: x, or r + beta p_old in the fused CG phase
     auto Z4 = [&](int64_t idx) -> float4 {
@@ -181,6 +287,7 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
             const float4 d = ld4(io.dinv + idx);
             v = make_float4(v.x * d.x, v.y * d.y, v.z * d.z, v.w * d.w);
         }
+        if (rupd) v = axpy4(-alpha_prev, ld4(io.qin + idx), v);
         return v;
     };
     auto S4 = [&](int64_t idx) -> float4 {
@@ -191,20 +298,23 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
     auto S1 = [&](int64_t idx) -> float {
         float v = zsrc[idx];
         if (jz) v *= io.dinv[idx];
+        if (rupd) v -= alpha_prev * io.qin[idx];
         if (use_pold) v += beta * pold[idx];
         return v;
     };
 
     float4 sm = f4(0.f), sc = f4(0.f), sp = f4(0.f), txm = f4(0.f);
     float4 poc = f4(0.f), pop = f4(0.f);  // p_old at own cells, planes i and i+1
-    float dot = 0.f;
+    float4 zc = f4(0.f), zp = f4(0.f);    // single-reduction CG: r_K at own cells
+    float dot = 0.f, d_rr = 0.f, d_rq = 0.f, d_qq = 0.f;
     int64_t base = (int64_t)i0 * P + r0;
     if (valid && i0 < i1) {
+        zc = Z4(base);
         if (use_pold) {
             poc = ld4(pold + base);
-            sc = axpy4(beta, poc, Z4(base));
+            sc = axpy4(beta, poc, zc);
         } else {
-            sc = Z4(base);
+            sc = zc;
         }
         if (i0 > 0) {
             sm = S4(base - P);
@@ -219,11 +329,12 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
         float4 sjm = sc, sjp = sc;
         if (valid) {
             if (i + 1 < g.nx) {
+                zp = Z4(base + P);
                 if (use_pold) {
                     pop = ld4(pold + base + P);
-                    sp = axpy4(beta, pop, Z4(base + P));
+                    sp = axpy4(beta, pop, zp);
                 } else {
-                    sp = Z4(base + P);
+                    sp = zp;
                 }
             } else {
                 sp = sc;
@@ -239,14 +350,14 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
         if (valid) {
             if (hasjm) {
                 if (jm_in) {
-                    sjm = ls[buf][jm_rel >> 2];
-                    tyl = lty[buf][jm_rel >> 2];
+                    sjm = ls[buf][jm_slot];
+                    tyl = lty[buf][jm_slot];
                 } else {
                     tyl = ld4(c.ty + base - nz);
                     sjm = S4(base - nz);
                 }
             }
-            if (hasjp) sjp = jp_in ? ls[buf][jp_rel >> 2] : S4(base + nz);
+            if (hasjp) sjp = jp_in ? ls[buf][jp_slot] : S4(base + nz);
         }
         // z neighbours across the float4 boundary from the adjacent lanes
         float xl = __shfl_up(sc.w, 1, kWave);
@@ -275,11 +386,17 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
                                         sjm.w, tzc.w, xr, tzc.z, sc.z);
             if (MODE == kApply) {
                 st4(io.out + base, y);
-            } else if (MODE == kFusedCg) {
+            } else if (kCg) {
                 st4(pnew + base, sc);
                 st4(io.out + base, y);
                 if (pending) st4(io.xsol + base, axpy4(alpha_prev, poc, ld4(io.xsol + base)));
                 dot += sc.x * y.x + sc.y * y.y + sc.z * y.z + sc.w * y.w;
+                if (MODE == kMergedCg) {
+                    st4(io.rout + base, zc);
+                    d_rr += zc.x * zc.x + zc.y * zc.y + zc.z * zc.z + zc.w * zc.w;
+                    d_rq += zc.x * y.x + zc.y * y.y + zc.z * y.z + zc.w * y.w;
+                    d_qq += y.x * y.x + y.y * y.y + y.z * y.z + y.w * y.w;
+                }
             } else {  // residual r = b - A x
                 float4 bb;
                 if (io.rhs_f64) {
@@ -295,11 +412,22 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
         sc = sp;
         txm = txc;
         poc = pop;
+        zc = zp;
     }
 
     if (MODE == kFusedCg) {
         const float tot = block_sum(dot, red);
         if (threadIdx.x == 0) io.partials[blockIdx.x] = tot;
+    } else if (MODE == kMergedCg) {
+        const int nb = gridDim.x;
+        const float a0 = block_sum(dot, red), a1 = block_sum(d_rr, red), a2 = block_sum(d_rq, red),
+                    a3 = block_sum(d_qq, red);
+        if (threadIdx.x == 0) {
+            io.partials[blockIdx.x] = a0;
+            io.partials[nb + blockIdx.x] = a1;
+            io.partials[2 * nb + blockIdx.x] = a2;
+            io.partials[3 * nb + blockIdx.x] = a3;
+        }
     }
 }
 
@@ -434,9 +562,11 @@ hipError_t launch_stencil_f32(int mode, const Geom& g, const Coef& c, const Sten
         switch (mode) {
             case kApply: return launch_v4<kApply>(g, c, io, m, s);
             case kFusedCg: return launch_v4<kFusedCg>(g, c, io, m, s);
+            case kMergedCg: return launch_v4<kMergedCg>(g, c, io, m, s);
             default: return launch_v4<kResidual>(g, c, io, m, s);
         }
     }
+    if (mode == kMergedCg) return hipErrorInvalidValue;  // float4 path only
     switch (mode) {
         case kApply: return launch_s<float, kApply>(g, c, io, m, s);
         case kFusedCg: return launch_s<float, kFusedCg>(g, c, io, m, s);

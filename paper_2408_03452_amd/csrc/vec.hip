@@ -260,6 +260,24 @@ __global__ void fill_f32(int64_t n, float* a, float v) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) a[e] = v;
 }
 
+// Scalars of a single-reduction CG run before kernel 0 (plain vector stores).
+__global__ void merged_init(MergedState* ms, float tol2, int max_iter) {
+    if (threadIdx.x != 0) return;
+    for (int i = 0; i < 2; ++i) {
+        MergedSlot& sl = ms->s[i];
+        sl.k = 0;
+        sl.done = 0;
+        sl.status = 1;
+        sl.iters = 0;
+        sl.rr = 0.f;
+        sl.thresh2 = 0.f;
+        sl.bnorm2 = 0.f;
+        sl.beta = 0.f;
+    }
+    ms->tol2 = tol2;
+    ms->max_iter = max_iter;
+}
+
 // flag[0] = 1 if the two arrays differ in any bit (flag cleared by the caller);
 // every block that finds a difference stores the same value.
 __global__ __launch_bounds__(kThreads) void differ(int64_t n, const uint32_t* __restrict__ a,
@@ -499,6 +517,11 @@ hipError_t launch_convert_f64_to_f32(int64_t n, const double* a, float* b, hipSt
 
 hipError_t launch_fill_f32(int64_t n, float* a, float v, hipStream_t s) {
     hipLaunchKernelGGL(fill_f32, dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, a, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_merged_init(MergedState* ms, float tol2, int max_iter, hipStream_t s) {
+    hipLaunchKernelGGL(merged_init, dim3(1), dim3(kWave), 0, s, ms, tol2, max_iter);
     return hipGetLastError();
 }
 

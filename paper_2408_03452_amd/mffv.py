@@ -39,7 +39,8 @@ class Opts(ctypes.Structure):
                 ("precision", ctypes.c_int), ("precond", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("net", ctypes.c_void_p), ("timing", ctypes.c_int)]
+                ("net", ctypes.c_void_p), ("single_reduction", ctypes.c_int),
+                ("timing", ctypes.c_int)]
 
 
 class TuneResult(ctypes.Structure):
@@ -56,7 +57,8 @@ class Info(ctypes.Structure):
                 ("fallbacks", ctypes.c_int), ("rel_res_recursive", ctypes.c_double),
                 ("rel_res_true", ctypes.c_double), ("ms", ctypes.c_double),
                 ("phase_a_us", ctypes.c_double), ("phase_b_us", ctypes.c_double),
-                ("precond_us", ctypes.c_double), ("timed_iters", ctypes.c_int)]
+                ("precond_us", ctypes.c_double), ("timed_iters", ctypes.c_int),
+                ("single_reduction", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -96,7 +96,8 @@ def test_kernel_timing_keeps_results(mf):
         xs.append(host(x))
         if timing:
             assert info["timed_iters"] == min(32, info["iters"])
-            assert info["phase_a_us"] > 0 and info["phase_b_us"] > 0 and info["precond_us"] >= 0
+            assert info["phase_a_us"] > 0 and info["phase_b_us"] >= 0 and info["precond_us"] >= 0
+            assert info["phase_b_us"] > 0 or info["single_reduction"] == 1
             assert info["phase_a_us"] < info["ms"] * 1e3
         else:
             assert info["timed_iters"] == 0 and info["phase_a_us"] == 0

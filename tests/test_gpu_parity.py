@@ -38,6 +38,7 @@ def host(t):
 
 SHAPES = [(32, 32, 32),        # float4 path, one chunk per plane
           (9, 40, 64),         # float4 path, several chunks and a ragged chunk
+          (5, 9, 512),         # float4 path, long rows: 4-row x 256-cell chunks, ragged row group
           (7, 13, 37),         # one cell per thread (nz odd), ragged
           (3, 5, 8),           # a single unknown plane
           (6, 1, 1)]           # a 1D column
@@ -105,6 +106,48 @@ def test_apply_unaligned_and_custom_dirichlet(mf):
     mf.apply(g, xs[1:], ys[1:])
     want = ref.A @ x.astype(np.float64)
     assert np.all(np.abs(host(ys[1:]) - want) <= 3e-6 * ref.diag() * np.abs(x).max())
+
+
+def test_long_rows_refined_solve_matches_direct(mf):
+    """nz > 256: the float4 kernels use 4-row x 256-cell chunks (z-segment halos
+    between chunks of one row); the refined solve must match the direct solve."""
+    shape = (6, 7, 768)
+    k = lognormal_iid(shape, 1.0, 21)
+    g, _, b = gpu_problem(mf, k, c=1e-3)
+    ref = OracleProblem(k, c=1e-3)
+    x = torch.zeros(k.size, dtype=torch.float64, device="cuda")
+    st, info = mf.cg_solve_f64(g, b.double(), x, mf.default_opts(tol=1e-10, precision=mf.FP32_IR))
+    assert st == mf.OK and info["rel_res_true"] <= 1e-10
+    p = ref.direct()
+    assert np.linalg.norm(host(x) - p) <= 1e-8 * np.linalg.norm(p)
+
+
+@pytest.mark.parametrize("shape", [(24, 20, 32), (6, 7, 768)])
+def test_single_reduction_matches_two_phase(mf, shape):
+    """The single-reduction iteration (one kernel per iteration, r.r from a
+    one-step recurrence on the exact value) and the two-phase iteration solve
+    the same FP32 system: both reach the recursive target, the true residuals
+    of the FP32 results are of the same size (the FP32 attainable accuracy, set
+    by the same vector recurrence), their iteration counts stay close, and both
+    refined fields match the direct solve."""
+    k = lognormal_iid(shape, 1.5, 31)
+    g, _, b = gpu_problem(mf, k, c=1e-3)
+    ref = OracleProblem(k, c=1e-3)
+    p = ref.direct()
+    res, true = {}, {}
+    for sr in (1, 0):
+        x = torch.zeros(k.size, dtype=torch.float32, device="cuda")
+        st, info = mf.cg_solve(g, b, x, mf.default_opts(tol=1e-6, single_reduction=sr))
+        assert st == mf.OK and info["single_reduction"] == sr
+        assert info["rel_res_recursive"] <= 1e-6 and info["rel_res_true"] <= 1e-4
+        x64 = torch.zeros(k.size, dtype=torch.float64, device="cuda")
+        st, info64 = mf.cg_solve_f64(g, b.double(), x64, mf.default_opts(
+            tol=1e-10, precision=mf.FP32_IR, single_reduction=sr))
+        assert st == mf.OK and info64["single_reduction"] == sr
+        assert np.linalg.norm(host(x64) - p) <= 1e-8 * np.linalg.norm(p)
+        res[sr], true[sr] = info["iters"], info["rel_res_true"]
+    assert abs(res[1] - res[0]) <= max(3, 0.05 * res[0])
+    assert true[1] <= 4 * true[0] + 1e-6 and true[0] <= 4 * true[1] + 1e-6
 
 
 def test_apply_symmetry_on_device(mf):
