@@ -89,6 +89,10 @@ typedef struct {
                             single reduction phase (r.r of the next iteration from a
                             one-step recurrence on the exact r.r); 0 (default): the
                             two-phase iteration, faster on one GPU                      */
+    int nn_every;        /* MFFV_PRECOND_LEARNED: apply the network every nn_every-th
+                            iteration (1 = every one, the default) and the Jacobi step
+                            z = r / diag(A) in between; flexible CG accepts the varying
+                            preconditioner (1..64)                                     */
     int timing;          /* 1 (mffv_cg_solve, FP32 or FP32_IR): time each kernel of the first
                             32 FP32 CG iterations with HIP events (no graph replay, same
                             arithmetic); means returned in mffv_info                      */

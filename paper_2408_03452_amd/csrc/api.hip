@@ -102,6 +102,7 @@ struct mffv_grid {
     float *r2 = nullptr, *q2 = nullptr, *partM = nullptr;
     MergedState* ms = nullptr;
     int mpar = 0;              // parity of the next single-reduction launch
+    int flex_count = 0;        // flexible CG: iterations enqueued since the run started
     CgGraph graphM;
     // FP64 workspace
     double *r64 = nullptr, *p064 = nullptr, *p164 = nullptr, *q64 = nullptr, *x64 = nullptr,
@@ -249,7 +250,10 @@ struct LoopResult {
 
 // Enqueue one CG iteration (phase A, phase B, and for flexible CG the
 // preconditioner and its dots).
-int enqueue_iter32(mffv_grid* G, int precond, const mffv_net* net) {
+int enqueue_iter32(mffv_grid* G, int precond, const mffv_net* net, int nn_every = 1) {
+    // flexible CG: the network preconditions every nn_every-th iteration, Jacobi
+    // the others (the position in the loop is counted per enqueued iteration)
+    const bool use_nn = (++G->flex_count % nn_every) == 0;
     hipEvent_t* ev = nullptr;
     if (G->timing && G->timed < kTimedIters) ev = G->tev[G->timed++];
     if (ev) HIP_TRY(hipEventRecord(ev[0], G->stream));
@@ -289,9 +293,13 @@ int enqueue_iter32(mffv_grid* G, int precond, const mffv_net* net) {
     HIP_TRY(launch_phase_b_f32(mode, G->g.n, v, G->nb_vec, G->stream));
     if (ev) HIP_TRY(hipEventRecord(ev[2], G->stream));
     if (precond == MFFV_PRECOND_LEARNED) {
-        int rc = nn_precondition(net, G->g, G->r, G->dinv, G->dmask, G->z, pb + G->nb_vec, G->nb_vec,
-                                 G->feat, (float)G->n_unknown, G->stream);
-        if (rc) return rc;
+        if (use_nn) {
+            int rc = nn_precondition(net, G->g, G->r, G->dinv, G->dmask, G->z, pb + G->nb_vec, G->nb_vec,
+                                     G->feat, (float)G->n_unknown, G->stream);
+            if (rc) return rc;
+        } else {
+            HIP_TRY(launch_jacobi_z(G->g.n, G->r, G->dinv, G->dmask, G->z, G->stream));
+        }
         VecIO<float> f = v;
         f.partials = pf;
         HIP_TRY(launch_flex_dots_f32(G->g.n, f, G->nb_vec, G->stream));
@@ -545,11 +553,15 @@ int cg32(mffv_grid* G, double tol, int max_iter, int precond, const mffv_opts& o
         f.partials = reinterpret_cast<float*>(G->partF);
         HIP_TRY(launch_flex_dots_f32(G->g.n, f, G->nb_vec, G->stream));
     }
-    const int chunk = std::max(1, o.check_every);
+    const int nn_every = precond == MFFV_PRECOND_LEARNED ? std::max(1, o.nn_every) : 1;
+    // a chunk holding whole network periods keeps the captured pattern right on replay
+    const int chunk = (std::max(1, o.check_every) + nn_every - 1) / nn_every * nn_every;
     const bool use_graph = o.use_graph && !o.timing && G->stream != nullptr;
+    G->flex_count = 0;
     int rc = drive_loop(G, G->st32, max_iter, chunk, G->graph32[precond], use_graph,
-                        [&]() { return enqueue_iter32(G, precond, net); },
-                        precond == MFFV_PRECOND_LEARNED ? (const void*)net : nullptr, net_gen);
+                        [&]() { return enqueue_iter32(G, precond, net, nn_every); },
+                        precond == MFFV_PRECOND_LEARNED ? (const void*)net : nullptr,
+                        net_gen * 64 + nn_every);
     if (rc) return rc;
     HIP_TRY(launch_finalize_f32(G->g.n, G->xw, G->p0, G->p1, G->st32, G->stream));
     CgState<float> hs;
@@ -633,6 +645,8 @@ int validate_opts(const mffv_opts& o) {
         return fail(MFFV_EINVAL, "FP64 CG supports precond NONE only");
     if (o.single_reduction != 0 && o.single_reduction != 1)
         return fail(MFFV_EINVAL, "opts.single_reduction must be 0 or 1");
+    if (o.nn_every < 1 || o.nn_every > 64)
+        return fail(MFFV_EINVAL, "opts.nn_every must be in [1, 64]");
     return MFFV_OK;
 }
 
@@ -953,6 +967,7 @@ void mffv_default_opts(mffv_opts* o) {
     o->net = nullptr;
     o->timing = 0;
     o->single_reduction = 0;
+    o->nn_every = 1;
 }
 
 int mffv_create_grid(int nx, int ny, int nz, void* stream, mffv_grid** out) {

@@ -122,6 +122,8 @@ hipError_t launch_convert_f64_to_f32(int64_t n, const double* a, float* b, hipSt
 hipError_t launch_fill_f32(int64_t n, float* a, float v, hipStream_t s);
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_merged_init(MergedState* ms, float tol2, int max_iter, hipStream_t s);
+hipError_t launch_jacobi_z(int64_t n, const float* r, const float* dinv, const uint8_t* dmask, float* z,
+                           hipStream_t s);
 // flag[0] = 1 if a and b (n floats) differ in any bit; flag[0] must be 0 before.
 hipError_t launch_differ(int64_t n, const float* a, const float* b, int* flag, hipStream_t s);
 

@@ -260,6 +260,16 @@ __global__ void fill_f32(int64_t n, float* a, float v) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) a[e] = v;
 }
 
+// z = r / diag(A) on unknown cells, 0 on Dirichlet cells: the Jacobi step that
+// flexible CG takes between applications of the network.
+__global__ __launch_bounds__(kThreads) void jacobi_z(int64_t n, const float* __restrict__ r,
+                                                     const float* __restrict__ dinv,
+                                                     const uint8_t* __restrict__ dmask, float* z) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x; l < n; l += stride)
+        z[l] = dmask[l] ? 0.f : dinv[l] * r[l];
+}
+
 // Scalars of a single-reduction CG run before kernel 0 (plain vector stores).
 __global__ void merged_init(MergedState* ms, float tol2, int max_iter) {
     if (threadIdx.x != 0) return;
@@ -517,6 +527,12 @@ hipError_t launch_convert_f64_to_f32(int64_t n, const double* a, float* b, hipSt
 
 hipError_t launch_fill_f32(int64_t n, float* a, float v, hipStream_t s) {
     hipLaunchKernelGGL(fill_f32, dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, a, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_z(int64_t n, const float* r, const float* dinv, const uint8_t* dmask, float* z,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(jacobi_z, dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, r, dinv, dmask, z);
     return hipGetLastError();
 }
 

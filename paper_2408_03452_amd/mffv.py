@@ -40,7 +40,7 @@ class Opts(ctypes.Structure):
                 ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("net", ctypes.c_void_p), ("single_reduction", ctypes.c_int),
-                ("timing", ctypes.c_int)]
+                ("nn_every", ctypes.c_int), ("timing", ctypes.c_int)]
 
 
 class TuneResult(ctypes.Structure):

@@ -151,6 +151,34 @@ def harmful_params(c):
     return nn.pack(layers).astype(np.float32)
 
 
+@pytest.mark.parametrize("every", [2, 3])
+def test_network_every_kth_iteration(mf, every):
+    """opts.nn_every: the network preconditions every k-th iteration and the
+    Jacobi step the others. With a network whose output is a scaled Jacobi step
+    (z = 0.5 r / d) every iteration's z is a multiple of r / d, so flexible CG
+    takes the same directions as Jacobi-PCG (up to scale) and needs the same
+    count; with the zero network it is Jacobi-PCG outright."""
+    shape = (24, 24, 24)
+    k = channelised(shape, 11)
+    g, _, b = gpu_problem(mf, k, c=1e-3)
+    ref = OracleProblem(k, c=1e-3)
+    p = ref.direct()
+    xj = torch.zeros(k.size, dtype=torch.float32, device="cuda")
+    st, ij = mf.cg_solve(g, b, xj, mf.default_opts(precond=mf.PRECOND_JACOBI))
+    assert st == mf.OK
+    for params in (nn.init_params(seed=0, last_scale=0.0), harmful_params(0.5)):
+        net = mf.net_create(params)
+        for use_graph in (1, 0):
+            xf = torch.zeros(k.size, dtype=torch.float32, device="cuda")
+            st, info = mf.cg_solve(g, b, xf, mf.default_opts(precond=mf.PRECOND_LEARNED, net=net,
+                                                             nn_every=every, use_graph=use_graph))
+            assert st == mf.OK and info["fallbacks"] == 0
+            assert abs(info["iters"] - ij["iters"]) <= max(2, ij["iters"] // 50)
+            assert np.linalg.norm(host(xf) - p) <= 5e-5 * np.linalg.norm(p)
+    with pytest.raises(mf.MffvError):
+        mf.cg_solve(g, b, xj, mf.default_opts(precond=mf.PRECOND_LEARNED, net=net, nn_every=0))
+
+
 def test_safeguard_falls_back_to_jacobi(mf):
     shape = (16, 16, 16)
     k = lognormal_iid(shape, 1.0, 4)
