@@ -46,7 +46,7 @@ METRIC = "time to rel-resid 1e-6 (learned FCG vs plain CG); stencil-apply HBM GB
 # scaled by the same counters on a copy of known size; reported only when this
 # run uses that kernel and its autotuner picks that shape
 TRAFFIC = {
-    "two_phase": {"bytes": 676877702, "launch": {"ci": 16, "remap": 1},
+    "two_phase": {"bytes": 676877702, "launch": {"ci": 16, "remap": 1, "seg": -1},
                   "profile": "profiles/stencil_cg_phase_a_lognormal_corr8_256cube_hbm_traffic.md"},
     "single_reduction": None,
 }
@@ -116,7 +116,7 @@ def bench_large(log_fn, solve: bool, cg_iters: int = 200):
         mffv.set_transmissibility(g, tx, ty, tz, accum_scalar=w.c, b_out=b)
         del tx, ty, tz
         tune = mffv.autotune(g, None)
-        out["launch"] = {kk: tune[kk] for kk in ("ci", "remap", "vec", "blocks")}
+        out["launch"] = {kk: tune[kk] for kk in ("ci", "remap", "seg", "vec", "blocks")}
         xa = torch.randn(n, dtype=torch.float32, device=dev)
         ya = torch.empty_like(xa)
         for _ in range(3):
@@ -353,7 +353,7 @@ def main(argv=None):
         # launch shape of the stencil kernels: the library's autotuner (bitwise
         # apply probe, timed phase A), outside the timed region
         tune = mffv.autotune(g, None)
-        log(f"autotune: ci {tune['ci']}, remap {tune['remap']}, {tune['blocks']} blocks, phase A "
+        log(f"autotune: ci {tune['ci']}, remap {tune['remap']}, seg {tune['seg']}, {tune['blocks']} blocks, phase A "
             f"{tune['phase_a_us']:.1f} us, apply {tune['apply_us']:.1f} us ({tune['candidates']} candidates)")
         x = torch.zeros(n, dtype=torch.float32, device=dev)
         opts = mffv.default_opts(tol=w.tol, precision=mffv.FP32_IR, check_every=16, use_graph=1)
@@ -501,7 +501,7 @@ def main(argv=None):
                    "sigma": w.sigma, "corr_len_cells": w.corr_len, "accumulation": w.c,
                    "tol": w.tol, "precision": "FP32 CG + FP64 true residual/refinement",
                    "precond": "none", "initial_guess": "zero",
-                   "launch": {k: tune[k] for k in ("ci", "remap", "vec", "blocks")}},
+                   "launch": {k: tune[k] for k in ("ci", "remap", "seg", "vec", "blocks")}},
         "iters": iters,
         "rel_res_true": infos[-1]["rel_res_true"],
         "ir_steps": infos[-1]["ir_steps"],

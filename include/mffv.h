@@ -221,7 +221,8 @@ int mffv_cg_solve_f64(mffv_grid* grid, const double* b, double* x, const mffv_op
 
 /*
  * Solve nsys independent systems (each its own grid handle with coefficients
- * set, any sizes) in one persistent FP32 CG launch. grids, b and x are host
+ * set, any sizes below 2^30 cells; larger ones return MFFV_EINVAL) in one
+ * persistent FP32 CG launch. grids, b and x are host
  * arrays of nsys pointers; b[s] and x[s] are device FP32 vectors of grid s.
  * All handles must share the device and stream of grids[0]. info (host, nsys
  * entries) may be NULL. opts->precond may be NONE or JACOBI; precision is FP32.
@@ -332,17 +333,23 @@ typedef struct {
     double apply_us; /* measured apply time of the chosen shape (microseconds) */
     int candidates;  /* shapes timed (0 when read from the cache) */
     double phase_a_us; /* measured time of the fused CG phase A of the chosen shape */
+    int seg;         /* chunk shape: row segments of seg cells, -1 = flat chunks */
 } mffv_tune_result;
 
 /*
  * Set the launch shape of the grid's FP32 stencil kernels by hand: ci planes per
- * block (0 = the library's default for the shape) and remap 0/1. Synchronizes.
+ * block (0 = the library's default for the shape), remap 0/1, and the shape of
+ * a block's chunk of a plane: seg = 0 (the library's default), -1 (flat: 1024
+ * consecutive cells of the plane) or a power of two in [16, 1024] that divides
+ * nz (row segments: 4096/seg rows of seg cells, the float4 path only).
+ * Invalid values return MFFV_EINVAL. Synchronizes.
  */
-int mffv_set_launch(mffv_grid* grid, int ci, int remap);
+int mffv_set_launch(mffv_grid* grid, int ci, int remap, int seg);
 
 /*
  * Autotune the grid's FP32 stencil launch shape (the operator must be set):
- * every candidate (ci in 1..64 planes per block, XCD-aware order on or off)
+ * every candidate (ci in 1..64 planes per block, XCD-aware order on or off,
+ * flat chunks or row segments of 32..256 cells)
  * must reproduce the default shape's apply bit for bit; it is then timed on
  * the grid's own operator with HIP events, as an apply and as the fused CG
  * phase A (the solver's hot kernel) over the first 32 iterations of a solve, and the shape

@@ -793,6 +793,9 @@ std::vector<int> share_blocks(const std::vector<mffv_grid*>& grids, int total) {
 int build_plan(BatchPlan* P, hipStream_t stream) {
     const int ns = (int)P->grids.size();
     int rc;
+    // the batched kernel addresses a system's vectors with 32-bit byte offsets
+    for (mffv_grid* G : P->grids)
+        if (G->g.n >= (int64_t(1) << 30)) return fail(MFFV_EINVAL, "batched systems must have fewer than 2^30 cells");
     for (mffv_grid* G : P->grids)
         if ((rc = ensure_ws32(G)) || (rc = ensure_x64(G))) return rc;
     int dev = 0, cus = 0, rate_khz = 0;
@@ -898,7 +901,7 @@ std::string tune_key(const mffv_grid* G) {
            std::to_string(G->g.nz) + "/v" + std::to_string(G->m32.vec);
 }
 
-bool cache_lookup(const char* path, const std::string& key, int* ci, int* remap, double* us,
+bool cache_lookup(const char* path, const std::string& key, int* ci, int* remap, int* seg, double* us,
                   double* pa_us) {
     if (!path) return false;
     FILE* f = std::fopen(path, "r");
@@ -909,15 +912,17 @@ bool cache_lookup(const char* path, const std::string& key, int* ci, int* remap,
     while (std::fgets(line, sizeof(line), f)) {
         const char* p = std::strstr(line, pat.c_str());
         if (!p) continue;
-        if (std::sscanf(p + pat.size(), " \"ci\": %d, \"remap\": %d, \"apply_us\": %lf, \"phase_a_us\": %lf",
-                        ci, remap, us, pa_us) == 4)
+        if (std::sscanf(p + pat.size(),
+                        " \"ci\": %d, \"remap\": %d, \"seg\": %d, \"apply_us\": %lf, \"phase_a_us\": %lf", ci,
+                        remap, seg, us, pa_us) == 5)
             found = true;
     }
     std::fclose(f);
     return found;
 }
 
-void cache_store(const char* path, const std::string& key, int ci, int remap, double us, double pa_us) {
+void cache_store(const char* path, const std::string& key, int ci, int remap, int seg, double us,
+                 double pa_us) {
     if (!path) return;
     std::vector<std::string> lines;
     if (FILE* f = std::fopen(path, "r")) {
@@ -932,8 +937,9 @@ void cache_store(const char* path, const std::string& key, int ci, int remap, do
         std::fclose(f);
     }
     char buf[512];
-    std::snprintf(buf, sizeof(buf), "  \"%s\": {\"ci\": %d, \"remap\": %d, \"apply_us\": %.3f, \"phase_a_us\": %.3f}",
-                  key.c_str(), ci, remap, us, pa_us);
+    std::snprintf(buf, sizeof(buf),
+                  "  \"%s\": {\"ci\": %d, \"remap\": %d, \"seg\": %d, \"apply_us\": %.3f, \"phase_a_us\": %.3f}",
+                  key.c_str(), ci, remap, seg, us, pa_us);
     lines.push_back(buf);
     const std::string tmp = std::string(path) + ".tmp";
     FILE* f = std::fopen(tmp.c_str(), "w");
@@ -990,7 +996,17 @@ int mffv_create_grid(int nx, int ny, int nz, void* stream, mffv_grid** out) {
     G->m32 = plan_march(G->g, vec, 0, 1);
     G->m64 = plan_march(G->g, 1, 0, 1);
     G->nb_vec = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n / 4 + kThreads - 1) / kThreads));
-    G->max_blocks = std::max({G->m32.blocks(), G->m64.blocks(), G->nb_vec});
+    // partial sums for any launch shape mffv_set_launch accepts, up to 2^18 blocks
+    int64_t worst = 0;
+    for (int sg = -1; sg <= kThreads * 4; sg = sg < 16 ? 16 : 2 * sg) {
+        if (sg > 0 && !march_seg_ok(G->g, vec, sg)) continue;
+        const March m1 = plan_march(G->g, vec, 1, 1, sg);
+        worst = std::max<int64_t>(worst, (int64_t)m1.nchunk * m1.nich);
+    }
+    const March m1 = plan_march(G->g, 1, 1, 1);
+    worst = std::max<int64_t>(worst, (int64_t)m1.nchunk * m1.nich);
+    G->max_blocks = std::max({G->m32.blocks(), G->m64.blocks(), G->nb_vec,
+                              (int)std::min<int64_t>(worst, 1 << 18)});
     if ((rc = dalloc(&G->a, n)) || (rc = dalloc(&G->a64, n)) || (rc = dalloc(&G->tx, n)) || (rc = dalloc(&G->ty, n)) ||
         (rc = dalloc(&G->tz, n)) || (rc = dalloc(&G->dinv, n)) || (rc = dalloc(&G->dmask, n)) ||
         (rc = dalloc(&G->flags, 8)) || (rc = dalloc(&G->partA, (size_t)G->max_blocks)) ||
@@ -1405,14 +1421,18 @@ int mffv_grid_feature(mffv_grid* G, float* feat) {
     return MFFV_OK;
 }
 
-int mffv_set_launch(mffv_grid* G, int ci, int remap) {
+int mffv_set_launch(mffv_grid* G, int ci, int remap, int seg) {
     int rc = check_grid(G, false);
     if (rc) return rc;
     if (ci < 0 || ci > 4096 || (remap != 0 && remap != 1))
         return fail(MFFV_EINVAL, "ci must be in [0, 4096] (0 = default) and remap 0 or 1");
+    if (seg < -1 || (seg > 0 && !march_seg_ok(G->g, G->m32.vec, seg)))
+        return fail(MFFV_EINVAL,
+                    "seg must be 0 (default), -1 (flat chunks) or a power of two in [16, 1024] dividing nz "
+                    "(float4 path only)");
     if ((rc = set_device(G))) return rc;
     HIP_TRY(hipStreamSynchronize(G->stream));
-    const March m = plan_march(G->g, G->m32.vec, ci, remap);
+    const March m = plan_march(G->g, G->m32.vec, ci, remap, seg);
     if (m.blocks() > G->max_blocks)
         return fail(MFFV_EINVAL, "launch plan needs more blocks than the grid's partial buffers");
     drop_graphs(G);
@@ -1425,11 +1445,11 @@ int mffv_autotune(mffv_grid* G, const char* cache_path, mffv_tune_result* out) {
     if (rc) return rc;
     if ((rc = set_device(G)) || (rc = ensure_ws32(G))) return rc;
     const std::string key = tune_key(G);
-    int ci = 0, remap = 1;
+    int ci = 0, remap = 1, seg = 0;
     double us = 0, pa_us = 0;
     int tried = 0;
-    if (cache_lookup(cache_path, key, &ci, &remap, &us, &pa_us)) {
-        if ((rc = mffv_set_launch(G, ci, remap))) return rc;
+    if (cache_lookup(cache_path, key, &ci, &remap, &seg, &us, &pa_us)) {
+        if ((rc = mffv_set_launch(G, ci, remap, seg))) return rc;
     } else {
         // input: the inverse diagonal (a varied, bounded field); reference output in
         // z, which the unpreconditioned timing solves below leave alone
@@ -1443,13 +1463,18 @@ int mffv_autotune(mffv_grid* G, const char* cache_path, mffv_tune_result* out) {
         HIP_TRY(hipEventCreate(&e1));
         const March keep = G->m32;
         double best = 1e30;
-        int best_ci = base.ci, best_remap = 1;
+        int best_ci = base.ci, best_remap = 1, best_seg = 0;
         double best_apply = 0;
         const int cis[] = {1, 2, 4, 8, 16, 32, 64};
+        // chunk shapes: flat, and row segments of 32..256 cells (16..4 rows a chunk)
+        std::vector<int> segs{-1};
+        for (int sg = 32; sg <= 256; sg *= 2)
+            if (march_seg_ok(G->g, G->m32.vec, sg)) segs.push_back(sg);
+        for (int sg : segs)
         for (int c : cis) {
             if (c > G->g.nx) continue;
             for (int rm = 0; rm <= 1; ++rm) {
-                const March m = plan_march(G->g, G->m32.vec, c, rm);
+                const March m = plan_march(G->g, G->m32.vec, c, rm, sg);
                 if (m.blocks() > G->max_blocks) continue;
                 io.out = G->p0;
                 HIP_TRY(launch_stencil_f32(kApply, G->g, coef_of(G), io, m, G->stream));
@@ -1492,6 +1517,7 @@ int mffv_autotune(mffv_grid* G, const char* cache_path, mffv_tune_result* out) {
                     best_apply = apply_us;
                     best_ci = c;
                     best_remap = rm;
+                    best_seg = m.seg > 0 ? m.seg : -1;
                 }
             }
         }
@@ -1500,14 +1526,16 @@ int mffv_autotune(mffv_grid* G, const char* cache_path, mffv_tune_result* out) {
         if (!tried) return fail(MFFV_EHIP, "autotune: no candidate reproduced the reference apply");
         ci = best_ci;
         remap = best_remap;
+        seg = best_seg;
         us = best_apply;
         pa_us = best;
-        if ((rc = mffv_set_launch(G, ci, remap))) return rc;
-        cache_store(cache_path, key, ci, remap, us, pa_us);
+        if ((rc = mffv_set_launch(G, ci, remap, seg))) return rc;
+        cache_store(cache_path, key, ci, remap, seg, us, pa_us);
     }
     if (out) {
         out->ci = G->m32.ci;
         out->remap = G->m32.remap;
+        out->seg = G->m32.seg > 0 ? G->m32.seg : -1;
         out->vec = G->m32.vec;
         out->blocks = G->m32.blocks();
         out->apply_us = us;

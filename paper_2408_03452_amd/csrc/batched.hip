@@ -99,6 +99,176 @@ __device__ __forceinline__ void own_cells(const Geom& g, int pc, int ic, int ci,
     for (int i = i0; i < i1; ++i) f((int64_t)i * g.plane + r0);
 }
 
+// Byte-offset access from a block-uniform base in global memory. The
+// system's pointers come from a descriptor in device memory, so the compiler
+// cannot infer their address space by itself; without it every access would
+// be a flat one (slower to wait on, and able to alias the kernel's own stack,
+// which keeps the dot accumulators out of registers). A batched system has
+// fewer than 2^30 cells (checked when the batch is planned), so every byte
+// offset fits in 32 bits: a scalar base plus one 32-bit vector offset.
+typedef __attribute__((address_space(1))) char gchar;
+typedef __attribute__((address_space(1))) float gfloat;
+__device__ __forceinline__ float ldo(const float* p, uint32_t off) {
+    return *(const gfloat*)((const gchar*)p + off);
+}
+__device__ __forceinline__ void sto(float* p, uint32_t off, float v) { *(gfloat*)((gchar*)p + off) = v; }
+
+// Raw operands of one plane step of phase A: the direction sources (s_k and
+// p_{k-1}) at the next plane and at the four in-plane neighbours, the own
+// faces and diagonal, the faces shared with the previous y and z neighbours,
+// and the solution value for the deferred update. Loaded before use, so that
+// the loads of several plane steps are in flight together.
+struct StepA {
+    float zp, pp, zjm, pjm, zjp, pjp, zkm, pkm, zkp, pkp;
+    float tx, ty, tz, ac, tyl, tzl, xo;
+};
+
+struct CellA {
+    bool hasjm, hasjp, haskm, haskp;
+    uint32_t nz4, P4;  // byte strides of y and x
+};
+
+__device__ __forceinline__ void load_a(StepA& o, const BatchSys& S, const CellA& cc, const float* src,
+                                       const float* pold, bool up, uint32_t off, int i) {
+    const Geom& g = S.g;
+    o.zp = o.pp = o.zjm = o.pjm = o.zjp = o.pjp = o.zkm = o.pkm = o.zkp = o.pkp = 0.f;
+    o.tyl = o.tzl = o.xo = 0.f;
+    if (i + 1 < g.nx) {
+        o.zp = ldo(src, off + cc.P4);
+        if (up) o.pp = ldo(pold, off + cc.P4);
+    }
+    o.tx = ldo(S.c.tx, off);
+    o.ty = ldo(S.c.ty, off);
+    o.tz = ldo(S.c.tz, off);
+    o.ac = coef_plane_uniform(S.c, i, g.nx) ? S.c.a_const : ldo(S.c.a, off);
+    if (cc.hasjm) {
+        o.tyl = ldo(S.c.ty, off - cc.nz4);
+        o.zjm = ldo(src, off - cc.nz4);
+        if (up) o.pjm = ldo(pold, off - cc.nz4);
+    }
+    if (cc.hasjp) {
+        o.zjp = ldo(src, off + cc.nz4);
+        if (up) o.pjp = ldo(pold, off + cc.nz4);
+    }
+    if (cc.haskm) {
+        o.tzl = ldo(S.c.tz, off - 4u);
+        o.zkm = ldo(src, off - 4u);
+        if (up) o.pkm = ldo(pold, off - 4u);
+    }
+    if (cc.haskp) {
+        o.zkp = ldo(src, off + 4u);
+        if (up) o.pkp = ldo(pold, off + 4u);
+    }
+    if (up) o.xo = ldo(S.x, off);
+}
+
+// Phase A of one work item (chunk pc of a plane, planes of group ic): the
+// direction update p_k = s_k + beta p_{k-1} at every stencil point, q = A p_k,
+// the deferred x += alpha_{k-1} p_{k-1}, and the partial sum of p.q. Two plane
+// steps at a time: both steps' loads are issued before either is computed.
+__device__ __forceinline__ float phase_a_item(const BatchSys& S, int pc, int ic, const float* src,
+                                              const float* pold, float* pnew, bool up, float beta,
+                                              float alpha_prev) {
+    const Geom& g = S.g;
+    const uint32_t P = (uint32_t)g.plane;
+    const uint32_t r0 = (uint32_t)pc * kThreads + threadIdx.x;
+    float dot = 0.f;
+    if (r0 >= P) return dot;
+    const int i0 = ic * S.ci, i1 = min(g.nx, i0 + S.ci);
+    const uint32_t j = r0 / (uint32_t)g.nz, k = r0 - j * (uint32_t)g.nz;
+    CellA cc;
+    cc.hasjm = j > 0;
+    cc.hasjp = (int)j + 1 < g.ny;
+    cc.haskm = k > 0;
+    cc.haskp = (int)k + 1 < g.nz;
+    cc.nz4 = 4u * (uint32_t)g.nz;
+    cc.P4 = 4u * P;
+    uint32_t off = 4u * ((uint32_t)i0 * P + r0);
+    float poc = up ? ldo(pold, off) : 0.f;
+    float sc = up ? ldo(src, off) + beta * poc : ldo(src, off);
+    float sm = sc, txm = 0.f;
+    if (i0 > 0) {
+        sm = up ? ldo(src, off - cc.P4) + beta * ldo(pold, off - cc.P4) : ldo(src, off - cc.P4);
+        txm = ldo(S.c.tx, off - cc.P4);
+    }
+    auto step = [&](const StepA& a, uint32_t o, int i) {
+        const float sp = i + 1 < g.nx ? a.zp + beta * a.pp : sc;
+        const float sjm = cc.hasjm ? a.zjm + beta * a.pjm : sc;
+        const float sjp = cc.hasjp ? a.zjp + beta * a.pjp : sc;
+        const float skm = cc.haskm ? a.zkm + beta * a.pkm : sc;
+        const float skp = cc.haskp ? a.zkp + beta * a.pkp : sc;
+        const float y =
+            cell_op<float, float>(a.ac, sc, a.tx, sp, txm, sm, a.ty, sjp, a.tyl, sjm, a.tz, skp, a.tzl, skm);
+        sto(pnew, o, sc);
+        sto(S.q, o, y);
+        if (up) sto(S.x, o, a.xo + alpha_prev * poc);
+        dot += sc * y;
+        sm = sc;
+        sc = sp;
+        txm = a.tx;
+        poc = a.pp;
+    };
+    int i = i0;
+    for (; i + 1 < i1; i += 2, off += 2u * cc.P4) {
+        StepA a0, a1;
+        load_a(a0, S, cc, src, pold, up, off, i);
+        load_a(a1, S, cc, src, pold, up, off + cc.P4, i + 1);
+        step(a0, off, i);
+        step(a1, off + cc.P4, i + 1);
+    }
+    if (i < i1) {
+        StepA a0;
+        load_a(a0, S, cc, src, pold, up, off, i);
+        step(a0, off, i);
+    }
+    return dot;
+}
+
+// Phase B of one work item: r -= alpha q (and z = r / diag(A) with Jacobi),
+// with the partial sums of r.r and r.z; four planes' loads at a time.
+__device__ __forceinline__ float2 phase_b_item(const BatchSys& S, int pc, int ic, bool jac, float alpha) {
+    const Geom& g = S.g;
+    const uint32_t P = (uint32_t)g.plane;
+    const uint32_t r0 = (uint32_t)pc * kThreads + threadIdx.x;
+    float r2 = 0.f, z2 = 0.f;
+    if (r0 >= P) return make_float2(r2, z2);
+    const int i0 = ic * S.ci, i1 = min(g.nx, i0 + S.ci);
+    const uint32_t P4 = 4u * P;
+    uint32_t off = 4u * ((uint32_t)i0 * P + r0);
+    int i = i0;
+    for (; i + 3 < i1; i += 4, off += 4u * P4) {
+        float rv[4], qv[4], dv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            rv[u] = ldo(S.r, off + u * P4);
+            qv[u] = ldo(S.q, off + u * P4);
+            dv[u] = jac ? ldo(S.dinv, off + u * P4) : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float r = rv[u] - alpha * qv[u];
+            sto(S.r, off + u * P4, r);
+            r2 += r * r;
+            if (jac) {
+                const float z = dv[u] * r;
+                sto(S.z, off + u * P4, z);
+                z2 += r * z;
+            }
+        }
+    }
+    for (; i < i1; ++i, off += P4) {
+        const float r = ldo(S.r, off) - alpha * ldo(S.q, off);
+        sto(S.r, off, r);
+        r2 += r * r;
+        if (jac) {
+            const float z = ldo(S.dinv, off) * r;
+            sto(S.z, off, z);
+            z2 += r * z;
+        }
+    }
+    return make_float2(r2, z2);
+}
+
 __global__ __launch_bounds__(kThreads) void batched_cg(const BatchSys* __restrict__ systems,
                                                        const int* __restrict__ block_sys, BatchRun run) {
     __shared__ float red[kThreads / kWave];
@@ -163,17 +333,8 @@ __global__ __launch_bounds__(kThreads) void batched_cg(const BatchSys* __restric
         float* pnew = (k & 1) ? S.p1 : S.p0;
         const bool up = k > 0;
         float dot = 0.f;
-        for (int w = t; w < W; w += B) {
-            const int pc = w % S.nchunk, ic = w / S.nchunk;
-            march_item(g, c, pc, ic, S.ci,
-                       [&](int64_t l) { return up ? src[l] + beta * pold[l] : src[l]; },
-                       [&](int64_t l, float s, float y) {
-                           pnew[l] = s;
-                           S.q[l] = y;
-                           if (up) S.x[l] += alpha_prev * pold[l];
-                           dot += s * y;
-                       });
-        }
+        for (int w = t; w < W; w += B)
+            dot += phase_a_item(S, w % S.nchunk, w / S.nchunk, src, pold, pnew, up, beta, alpha_prev);
         {
             const float a0 = block_sum(dot, red);
             if (threadIdx.x == 0) pq_part[t] = a0;
@@ -189,17 +350,9 @@ __global__ __launch_bounds__(kThreads) void batched_cg(const BatchSys* __restric
         // phase B
         float r2 = 0.f, z2 = 0.f;
         for (int w = t; w < W; w += B) {
-            const int pc = w % S.nchunk, ic = w / S.nchunk;
-            own_cells(g, pc, ic, S.ci, [&](int64_t l) {
-                const float r = S.r[l] - alpha * S.q[l];
-                S.r[l] = r;
-                r2 += r * r;
-                if (jac) {
-                    const float z = S.dinv[l] * r;
-                    S.z[l] = z;
-                    z2 += r * z;
-                }
-            });
+            const float2 v = phase_b_item(S, w % S.nchunk, w / S.nchunk, jac, alpha);
+            r2 += v.x;
+            z2 += v.y;
         }
         {
             const float a0 = block_sum(r2, red), a1 = block_sum(z2, red);

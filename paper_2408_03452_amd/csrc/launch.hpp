@@ -16,12 +16,18 @@ struct March {
     int nchunk;  // chunks per plane
     int nich;    // plane groups along x
     int remap;   // 1: XCD-aware block order
-    int nseg;    // float4 path with nz > 256: chunks are 4 rows x 256 cells, nz / 256 per row
-                 // group (each wave one contiguous row segment); 0: flat chunks of the plane
+    int nseg;    // float4 path, row-segment chunks: segments per row (nz / seg); 0: flat
+                 // chunks of kThreads * 4 consecutive cells of the plane
+    int seg;     // cells per row segment (a power of two, 16..1024, dividing nz)
+    int tps_log2;  // log2 of the threads per row segment (seg / 4); a chunk holds
+                   // kThreads >> tps_log2 rows
     int blocks() const { return nchunk * nich; }
 };
 
-March plan_march(const Geom& g, int vec, int ci, int remap);
+// seg: 0 = the library's default chunk shape for the grid, -1 = flat chunks,
+// > 0 = row segments of seg cells (the caller has checked march_seg_ok).
+March plan_march(const Geom& g, int vec, int ci, int remap, int seg = 0);
+bool march_seg_ok(const Geom& g, int vec, int seg);
 
 // Record the message returned by mffv_last_error() on this thread; returns code.
 int set_error(int code, const std::string& msg);

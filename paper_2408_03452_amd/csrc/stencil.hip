@@ -18,18 +18,33 @@
 
 namespace mffv {
 
-March plan_march(const Geom& g, int vec, int ci, int remap) {
+bool march_seg_ok(const Geom& g, int vec, int seg) {
+    return vec == 4 && seg >= 16 && seg <= kThreads * 4 && (seg & (seg - 1)) == 0 && g.nz % seg == 0;
+}
+
+March plan_march(const Geom& g, int vec, int ci, int remap, int seg) {
     March m;
     m.vec = vec;
     const int64_t per_block = (int64_t)kThreads * vec;
-    const int seg = kWave * 4;  // cells of one wave's row segment in the float4 path
-    if (vec == 4 && g.nz > seg && g.nz % seg == 0) {
-        // long rows: a flat chunk would be a single row, with every y neighbour
-        // outside it; 4 rows x 256 cells keep three of each four inside
+    if (seg == 0) {
+        // default: long rows as segments of 256 cells (4 rows per chunk; a flat
+        // chunk would be a single row with every y neighbour outside it)
+        seg = (vec == 4 && g.nz > kWave * 4 && g.nz % (kWave * 4) == 0) ? kWave * 4 : -1;
+    }
+    if (seg > 0 && march_seg_ok(g, vec, seg)) {
+        // a chunk is kThreads*4/seg rows x seg cells: taller chunks keep more of
+        // the y neighbours inside the chunk, at the price of z neighbours read
+        // across the segment ends
+        m.seg = seg;
         m.nseg = g.nz / seg;
-        m.nchunk = ((g.ny + kThreads / kWave - 1) / (kThreads / kWave)) * m.nseg;
+        m.tps_log2 = 0;
+        while ((1 << m.tps_log2) < seg / 4) ++m.tps_log2;
+        const int rows = kThreads >> m.tps_log2;
+        m.nchunk = ((g.ny + rows - 1) / rows) * m.nseg;
     } else {
+        m.seg = 0;
         m.nseg = 0;
+        m.tps_log2 = 0;
         m.nchunk = (int)((g.plane + per_block - 1) / per_block);
     }
     if (ci <= 0) {
@@ -256,12 +271,19 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
     bool valid;
     int j = 0, k = 0;
     int ystep;  // threads between a cell and its y neighbour inside the chunk
+    // z neighbours not held by the adjacent lane (ends of a wave or of a row
+    // segment) are read from memory
+    bool zl_mem = lane == 0, zr_mem = lane == kWave - 1;
     if (m.nseg) {
-        j = (pc / m.nseg) * (kThreads / kWave) + (int)(threadIdx.x / kWave);
-        k = (pc % m.nseg) * kWave * 4 + lane * 4;
+        const int tps = 1 << m.tps_log2;
+        const int col = (int)threadIdx.x & (tps - 1);
+        j = (pc / m.nseg) * (kThreads >> m.tps_log2) + ((int)threadIdx.x >> m.tps_log2);
+        k = (pc % m.nseg) * m.seg + col * 4;
         valid = j < g.ny;
         r0 = (int64_t)j * g.nz + k;
-        ystep = kWave;
+        ystep = tps;
+        zl_mem = zl_mem || col == 0;
+        zr_mem = zr_mem || col == tps - 1;
     } else {
         r0 = ((int64_t)pc * kThreads + threadIdx.x) * 4;
         valid = r0 < P;
@@ -364,11 +386,11 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
         float tzl = __shfl_up(tzc.w, 1, kWave);
         float xr = __shfl_down(sc.x, 1, kWave);
         if (valid) {
-            if (lane == 0 && haskm) {
+            if (zl_mem && haskm) {
                 xl = S1(base - 1);
                 tzl = c.tz[base - 1];
             }
-            if (lane == kWave - 1 && haskp) xr = S1(base + 4);
+            if (zr_mem && haskp) xr = S1(base + 4);
             if (!haskm) {
                 xl = sc.x;
                 tzl = 0.f;

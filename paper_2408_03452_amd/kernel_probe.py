@@ -27,6 +27,8 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--ci", type=int, default=8, help="planes per block (bench.py: config.launch.ci)")
     ap.add_argument("--remap", type=int, default=0, help="XCD-aware order (config.launch.remap)")
+    ap.add_argument("--seg", type=int, default=0,
+                    help="chunk shape: 0 default, -1 flat, else row-segment cells (config.launch.seg)")
     args = ap.parse_args(argv)
     import torch
     from paper_2408_03452_amd import mffv
@@ -48,8 +50,8 @@ def main(argv=None) -> int:
         del kd
         # the launch shape bench.py's autotuner picked (timing under a counter
         # run is distorted, so the shape is given rather than tuned here)
-        mffv.set_launch(g, args.ci, args.remap)
-        print(f"[probe] launch: ci {args.ci}, remap {args.remap}", flush=True)
+        mffv.set_launch(g, args.ci, args.remap, args.seg)
+        print(f"[probe] launch: ci {args.ci}, remap {args.remap}, seg {args.seg}", flush=True)
         xa = torch.randn(n, dtype=torch.float32, device=dev)
         ya = torch.empty_like(xa)
         for _ in range(10):

@@ -46,7 +46,8 @@ class Opts(ctypes.Structure):
 class TuneResult(ctypes.Structure):
     _fields_ = [("ci", ctypes.c_int), ("remap", ctypes.c_int), ("vec", ctypes.c_int),
                 ("blocks", ctypes.c_int), ("apply_us", ctypes.c_double),
-                ("candidates", ctypes.c_int), ("phase_a_us", ctypes.c_double)]
+                ("candidates", ctypes.c_int), ("phase_a_us", ctypes.c_double),
+                ("seg", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -103,7 +104,7 @@ def _declare(lib):
         "mffv_nn_train_step": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_float,
                                               ctypes.POINTER(ctypes.c_double)]),
         "mffv_grid_feature": (ctypes.c_int, [_P, _P]),
-        "mffv_set_launch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
+        "mffv_set_launch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
         "mffv_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.POINTER(TuneResult)]),
         "mffv_set_batched_launch": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
         "mffv_autotune_batched": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int,
@@ -289,8 +290,9 @@ def cg_solve_batched(grids, b, x, opts: Opts | None = None):
     return _check(rc), [i.as_dict() for i in infos]
 
 
-def set_launch(grid: Grid, ci: int, remap: int) -> None:
-    _check(lib().mffv_set_launch(grid.handle, ci, remap))
+def set_launch(grid: Grid, ci: int, remap: int, seg: int = 0) -> None:
+    """ci planes per block, remap 0/1, seg: 0 default, -1 flat, else row-segment length."""
+    _check(lib().mffv_set_launch(grid.handle, ci, remap, seg))
 
 
 def autotune(grid: Grid, cache_path: str | None = None) -> dict:

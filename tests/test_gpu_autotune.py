@@ -26,21 +26,53 @@ def host(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("shape", [(40, 24, 64), (21, 17, 19)])
+@pytest.mark.parametrize("shape", [(40, 24, 64), (21, 17, 19), (9, 37, 256), (5, 11, 512)])
 def test_launch_shapes_give_identical_apply(mf, shape):
     k = lognormal_iid(shape, 1.5, 2)
     g, _, _ = gpu_problem(mf, k, c=1e-3)
     x = torch.randn(k.size, dtype=torch.float32, device="cuda")
+    nz = shape[2]
+    # chunk shapes: default, flat, and every row-segment length the float4 path accepts
+    segs = [0, -1] + ([s for s in (16, 32, 64, 128, 256, 512, 1024) if nz % s == 0] if nz % 4 == 0 else [])
     outs = []
-    for ci, remap in ((0, 1), (1, 0), (3, 1), (8, 0), (64, 1)):
-        mf.set_launch(g, ci, remap)
-        y = torch.empty_like(x)
-        mf.apply(g, x, y)
-        outs.append(host(y))
+    for seg in segs:
+        for ci, remap in ((0, 1), (1, 0), (3, 1), (8, 0), (64, 1)):
+            mf.set_launch(g, ci, remap, seg)
+            y = torch.empty_like(x)
+            mf.apply(g, x, y)
+            outs.append(host(y))
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
     with pytest.raises(mf.MffvError):
         mf.set_launch(g, -1, 0)
+    for bad in (-2, 8, 24, 2048):
+        with pytest.raises(mf.MffvError):
+            mf.set_launch(g, 0, 1, bad)
+    if nz % 4:
+        with pytest.raises(mf.MffvError):
+            mf.set_launch(g, 0, 1, 16)
+
+
+_SEG_SHAPE = (14, 18, 256)
+
+
+@pytest.fixture(scope="module")
+def seg_problem():
+    k = lognormal_iid(_SEG_SHAPE, 1.0, 4)
+    return k, OracleProblem(k, c=1e-3).direct()
+
+
+@pytest.mark.parametrize("seg", [-1, 16, 64, 256])
+@pytest.mark.parametrize("single_reduction", [0, 1])
+def test_chunk_shapes_solve_to_the_direct_solution(mf, seg_problem, seg, single_reduction):
+    k, p = seg_problem
+    g, _, b = gpu_problem(mf, k, c=1e-3)
+    mf.set_launch(g, 4, 1, seg)
+    x = torch.zeros(k.size, dtype=torch.float64, device="cuda")
+    st, info = mf.cg_solve_f64(g, b.double(), x, mf.default_opts(
+        tol=1e-10, precision=mf.FP32_IR, single_reduction=single_reduction))
+    assert st == mf.OK and info["single_reduction"] == single_reduction
+    assert np.linalg.norm(host(x) - p) <= 1e-8 * np.linalg.norm(p)
 
 
 def test_autotune_caches_and_keeps_results(mf, tmp_path):
@@ -55,7 +87,8 @@ def test_autotune_caches_and_keeps_results(mf, tmp_path):
     assert len(data) == 1 and list(data.values())[0]["ci"] == r1["ci"]
     g2, _, _ = gpu_problem(mf, k, c=1e-3)
     r2 = mf.autotune(g2, cache)
-    assert r2["candidates"] == 0 and (r2["ci"], r2["remap"]) == (r1["ci"], r1["remap"])
+    assert r2["candidates"] == 0 and (r2["ci"], r2["remap"], r2["seg"]) == (r1["ci"], r1["remap"], r1["seg"])
+    assert r1["seg"] in (-1, 32, 64)
     x = torch.zeros(k.size, dtype=torch.float64, device="cuda")
     st, info = mf.cg_solve_f64(g, b.double(), x, mf.default_opts(tol=1e-10, precision=mf.FP32_IR))
     assert st == mf.OK
