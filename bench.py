@@ -41,15 +41,34 @@ PHASE_B_BYTES_PER_CELL = 12     # r, q read; r written
 MERGED_BYTES_PER_CELL = 44      # single-reduction iteration: r, q, p, x, Tx, Ty, Tz read;
                                 # r, p, q, x written
 METRIC = "time to rel-resid 1e-6 (learned FCG vs plain CG); stencil-apply HBM GB/s"
+# launch shapes the stencil autotuner reports: the CG kernels' and the apply's own
+LAUNCH_KEYS = ("ci", "remap", "seg", "vec", "blocks", "apply_ci", "apply_remap", "apply_seg", "apply_blocks")
 # HBM bytes per launch of the step's dominant kernel on the 256^3 workload from
-# rocprofv3 FETCH_SIZE and WRITE_SIZE (kernel_probe at the launch shape given),
+# rocprofv3 FETCH_SIZE and WRITE_SIZE (kernel_probe at each launch shape given),
 # scaled by the same counters on a copy of known size; reported only when this
-# run uses that kernel and its autotuner picks that shape
+# run uses that kernel and its autotuner picks one of these shapes
 TRAFFIC = {
-    "two_phase": {"bytes": 676877702, "launch": {"ci": 16, "remap": 1, "seg": -1},
-                  "profile": "profiles/stencil_cg_phase_a_lognormal_corr8_256cube_hbm_traffic.md"},
+    "two_phase": {
+        "profile": "profiles/stencil_cg_phase_a_lognormal_corr8_256cube_hbm_traffic.md",
+        "by_launch": [
+            ({"ci": 8, "remap": 0, "seg": -1}, 723725273),
+            ({"ci": 8, "remap": 1, "seg": -1}, 689172501),
+            ({"ci": 16, "remap": 0, "seg": -1}, 703661484),
+            ({"ci": 16, "remap": 1, "seg": -1}, 677122137),
+        ],
+    },
     "single_reduction": None,
 }
+
+
+def traffic_for(traffic, tune):
+    """Measured HBM bytes per launch at the tuned shape, or None."""
+    if not traffic:
+        return None
+    for launch, nbytes in traffic["by_launch"]:
+        if all(tune[k] == v for k, v in launch.items()):
+            return nbytes
+    return None
 
 
 def cells_iter_rate(cells: float, iters: float, seconds: float) -> float:
@@ -116,7 +135,7 @@ def bench_large(log_fn, solve: bool, cg_iters: int = 200):
         mffv.set_transmissibility(g, tx, ty, tz, accum_scalar=w.c, b_out=b)
         del tx, ty, tz
         tune = mffv.autotune(g, None)
-        out["launch"] = {kk: tune[kk] for kk in ("ci", "remap", "seg", "vec", "blocks")}
+        out["launch"] = {kk: tune[kk] for kk in LAUNCH_KEYS}
         xa = torch.randn(n, dtype=torch.float32, device=dev)
         ya = torch.empty_like(xa)
         for _ in range(3):
@@ -353,8 +372,9 @@ def main(argv=None):
         # launch shape of the stencil kernels: the library's autotuner (bitwise
         # apply probe, timed phase A), outside the timed region
         tune = mffv.autotune(g, None)
-        log(f"autotune: ci {tune['ci']}, remap {tune['remap']}, seg {tune['seg']}, {tune['blocks']} blocks, phase A "
-            f"{tune['phase_a_us']:.1f} us, apply {tune['apply_us']:.1f} us ({tune['candidates']} candidates)")
+        log(f"autotune: CG kernels ci {tune['ci']}, remap {tune['remap']}, seg {tune['seg']}, {tune['blocks']} "
+            f"blocks, phase A {tune['phase_a_us']:.1f} us; apply ci {tune['apply_ci']}, remap "
+            f"{tune['apply_remap']}, seg {tune['apply_seg']}, {tune['apply_us']:.1f} us ({tune['candidates']} candidates)")
         x = torch.zeros(n, dtype=torch.float32, device=dev)
         opts = mffv.default_opts(tol=w.tol, precision=mffv.FP32_IR, check_every=16, use_graph=1)
 
@@ -501,7 +521,7 @@ def main(argv=None):
                    "sigma": w.sigma, "corr_len_cells": w.corr_len, "accumulation": w.c,
                    "tol": w.tol, "precision": "FP32 CG + FP64 true residual/refinement",
                    "precond": "none", "initial_guess": "zero",
-                   "launch": {k: tune[k] for k in ("ci", "remap", "seg", "vec", "blocks")}},
+                   "launch": {k: tune[k] for k in LAUNCH_KEYS}},
         "iters": iters,
         "rel_res_true": infos[-1]["rel_res_true"],
         "ir_steps": infos[-1]["ir_steps"],
@@ -531,8 +551,7 @@ def main(argv=None):
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": dom_gbps / HBM_PEAK_GBPS,
-            "traffic": (traffic["bytes"] if traffic and all(tune[k] == v for k, v in
-                                                            traffic["launch"].items()) else None),
+            "traffic": traffic_for(traffic, tune),
             "traffic_source": traffic["profile"] if traffic else None,
             "bytes_per_cell": dom_bytes,
             "cells_per_launch": n,

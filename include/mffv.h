@@ -334,10 +334,13 @@ typedef struct {
     int candidates;  /* shapes timed (0 when read from the cache) */
     double phase_a_us; /* measured time of the fused CG phase A of the chosen shape */
     int seg;         /* chunk shape: row segments of seg cells, -1 = flat chunks */
+    /* the apply's own shape (mffv_apply), chosen on the apply's time */
+    int apply_ci, apply_remap, apply_seg, apply_blocks;
 } mffv_tune_result;
 
 /*
- * Set the launch shape of the grid's FP32 stencil kernels by hand: ci planes per
+ * Set the launch shape of the grid's FP32 stencil kernels (the CG kernels and
+ * the apply) by hand: ci planes per
  * block (0 = the library's default for the shape), remap 0/1, and the shape of
  * a block's chunk of a plane: seg = 0 (the library's default), -1 (flat: 1024
  * consecutive cells of the plane) or a power of two in [16, 1024] that divides
@@ -352,8 +355,9 @@ int mffv_set_launch(mffv_grid* grid, int ci, int remap, int seg);
  * flat chunks or row segments of 32..256 cells)
  * must reproduce the default shape's apply bit for bit; it is then timed on
  * the grid's own operator with HIP events, as an apply and as the fused CG
- * phase A (the solver's hot kernel) over the first 32 iterations of a solve, and the shape
- * with the fastest phase A is applied. With a cache_path (may be NULL), a
+ * phase A (the solver's hot kernel) over the first 32 iterations of a solve. The
+ * shape with the fastest phase A is applied to the CG kernels and the one with
+ * the fastest apply to mffv_apply. With a cache_path (may be NULL), a
  * previous result for the same device architecture and shape is reused, and a
  * new one is written to that JSON file. Uses the grid's workspace (overwrites
  * the solver's work vectors); synchronizes.
@@ -369,7 +373,7 @@ int mffv_set_batched_launch(int blocks_per_cu, int items_per_block);
 
 /*
  * Autotune the batched launch shape: solves the batch (as mffv_cg_solve_batched)
- * for every candidate (1, 2, 4 or all-fitting blocks per CU x 1, 2, 4, 8 work
+ * for every candidate (1, 2, 3, 4 or all-fitting blocks per CU x 1, 2, 4, 8, 16 work
  * items per block), each from the initial guess held in x, times each with HIP
  * events and applies the fastest (results returned through the pointers, any
  * may be NULL). x holds the initial guess again on return. Allocates a copy of

@@ -127,8 +127,8 @@ struct mffv_grid {
     bool timing = false;
     int timed = 0;
     int timed_real = -1;  // iterations of the first timed CG run that did work
-    // launch shapes
-    March m32{}, m64{};
+    // launch shapes: FP32 CG kernels, the FP32 apply (tuned on its own), FP64
+    March m32{}, m_apply{}, m64{};
     int nb_vec = 0;
     // captured iteration chunks: [precond 0..2]
     CgGraph graph32[3];
@@ -901,8 +901,15 @@ std::string tune_key(const mffv_grid* G) {
            std::to_string(G->g.nz) + "/v" + std::to_string(G->m32.vec);
 }
 
-bool cache_lookup(const char* path, const std::string& key, int* ci, int* remap, int* seg, double* us,
-                  double* pa_us) {
+// A tuned launch: the shape of the CG kernels (chosen on the fused phase A)
+// and the shape of the apply (chosen on the apply itself).
+struct TuneRec {
+    int ci = 0, remap = 1, seg = 0;
+    int aci = 0, aremap = 1, aseg = 0;
+    double apply_us = 0, pa_us = 0;
+};
+
+bool cache_lookup(const char* path, const std::string& key, TuneRec* t) {
     if (!path) return false;
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
@@ -912,17 +919,20 @@ bool cache_lookup(const char* path, const std::string& key, int* ci, int* remap,
     while (std::fgets(line, sizeof(line), f)) {
         const char* p = std::strstr(line, pat.c_str());
         if (!p) continue;
+        TuneRec r;
         if (std::sscanf(p + pat.size(),
-                        " \"ci\": %d, \"remap\": %d, \"seg\": %d, \"apply_us\": %lf, \"phase_a_us\": %lf", ci,
-                        remap, seg, us, pa_us) == 5)
+                        " \"ci\": %d, \"remap\": %d, \"seg\": %d, \"apply_ci\": %d, \"apply_remap\": %d, "
+                        "\"apply_seg\": %d, \"apply_us\": %lf, \"phase_a_us\": %lf",
+                        &r.ci, &r.remap, &r.seg, &r.aci, &r.aremap, &r.aseg, &r.apply_us, &r.pa_us) == 8) {
+            *t = r;
             found = true;
+        }
     }
     std::fclose(f);
     return found;
 }
 
-void cache_store(const char* path, const std::string& key, int ci, int remap, int seg, double us,
-                 double pa_us) {
+void cache_store(const char* path, const std::string& key, const TuneRec& t) {
     if (!path) return;
     std::vector<std::string> lines;
     if (FILE* f = std::fopen(path, "r")) {
@@ -938,8 +948,9 @@ void cache_store(const char* path, const std::string& key, int ci, int remap, in
     }
     char buf[512];
     std::snprintf(buf, sizeof(buf),
-                  "  \"%s\": {\"ci\": %d, \"remap\": %d, \"seg\": %d, \"apply_us\": %.3f, \"phase_a_us\": %.3f}",
-                  key.c_str(), ci, remap, seg, us, pa_us);
+                  "  \"%s\": {\"ci\": %d, \"remap\": %d, \"seg\": %d, \"apply_ci\": %d, \"apply_remap\": %d, "
+                  "\"apply_seg\": %d, \"apply_us\": %.3f, \"phase_a_us\": %.3f}",
+                  key.c_str(), t.ci, t.remap, t.seg, t.aci, t.aremap, t.aseg, t.apply_us, t.pa_us);
     lines.push_back(buf);
     const std::string tmp = std::string(path) + ".tmp";
     FILE* f = std::fopen(tmp.c_str(), "w");
@@ -994,6 +1005,7 @@ int mffv_create_grid(int nx, int ny, int nz, void* stream, mffv_grid** out) {
     }
     const int vec = (nz % 4 == 0) ? 4 : 1;
     G->m32 = plan_march(G->g, vec, 0, 1);
+    G->m_apply = G->m32;
     G->m64 = plan_march(G->g, 1, 0, 1);
     G->nb_vec = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n / 4 + kThreads - 1) / kThreads));
     // partial sums for any launch shape mffv_set_launch accepts, up to 2^18 blocks
@@ -1109,7 +1121,7 @@ int mffv_apply(mffv_grid* G, const float* x, float* y) {
     StencilIO<float> io;
     io.src = x;
     io.out = y;
-    March m = G->m32;
+    March m = G->m_apply;
     const bool aligned = ((uintptr_t)x % 16 == 0) && ((uintptr_t)y % 16 == 0);
     if (m.vec == 4 && !aligned) m = plan_march(G->g, 1, 0, 1);
     HIP_TRY(launch_stencil_f32(kApply, G->g, coef_of(G), io, m, G->stream));
@@ -1437,19 +1449,37 @@ int mffv_set_launch(mffv_grid* G, int ci, int remap, int seg) {
         return fail(MFFV_EINVAL, "launch plan needs more blocks than the grid's partial buffers");
     drop_graphs(G);
     G->m32 = m;
+    G->m_apply = m;
     return MFFV_OK;
 }
+
+}  // extern "C"
+
+namespace {
+// Apply a tuned record: the CG kernels' shape, then the apply's own.
+int set_launches(mffv_grid* G, const TuneRec& t) {
+    int rc = mffv_set_launch(G, t.ci, t.remap, t.seg);
+    if (rc) return rc;
+    if (t.aseg < -1 || (t.aseg > 0 && !march_seg_ok(G->g, G->m32.vec, t.aseg)) || t.aci < 1 || t.aci > 4096)
+        return fail(MFFV_EINVAL, "autotune cache: invalid apply shape");
+    const March m = plan_march(G->g, G->m32.vec, t.aci, t.aremap, t.aseg);
+    if (m.blocks() > G->max_blocks) return fail(MFFV_EINVAL, "autotune cache: apply shape needs too many blocks");
+    G->m_apply = m;
+    return MFFV_OK;
+}
+}  // namespace
+
+extern "C" {
 
 int mffv_autotune(mffv_grid* G, const char* cache_path, mffv_tune_result* out) {
     int rc = check_grid(G, true);
     if (rc) return rc;
     if ((rc = set_device(G)) || (rc = ensure_ws32(G))) return rc;
     const std::string key = tune_key(G);
-    int ci = 0, remap = 1, seg = 0;
-    double us = 0, pa_us = 0;
+    TuneRec rec;
     int tried = 0;
-    if (cache_lookup(cache_path, key, &ci, &remap, &seg, &us, &pa_us)) {
-        if ((rc = mffv_set_launch(G, ci, remap, seg))) return rc;
+    if (cache_lookup(cache_path, key, &rec)) {
+        if ((rc = set_launches(G, rec))) return rc;
     } else {
         // input: the inverse diagonal (a varied, bounded field); reference output in
         // z, which the unpreconditioned timing solves below leave alone
@@ -1462,13 +1492,46 @@ int mffv_autotune(mffv_grid* G, const char* cache_path, mffv_tune_result* out) {
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
         const March keep = G->m32;
-        double best = 1e30;
-        int best_ci = base.ci, best_remap = 1, best_seg = 0;
-        double best_apply = 0;
+        // time one shape: its apply (reps launches) and phase A over the first 32
+        // iterations of a solve of A x = dinv; returns an error code
+        auto time_shape = [&](const March& m, int reps, double* apply_us, double* pa_us) -> int {
+            HIP_TRY(hipEventRecord(e0, G->stream));
+            for (int t = 0; t < reps; ++t)
+                HIP_TRY(launch_stencil_f32(kApply, G->g, coef_of(G), io, m, G->stream));
+            HIP_TRY(hipEventRecord(e1, G->stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            *apply_us = 1e3 * ms / reps;
+            G->m32 = m;
+            HIP_TRY(hipMemcpyAsync(G->bw, G->dinv, G->g.n * sizeof(float), hipMemcpyDeviceToDevice,
+                                   G->stream));
+            HIP_TRY(hipMemsetAsync(G->xw, 0, G->g.n * sizeof(float), G->stream));
+            mffv_opts o;
+            mffv_default_opts(&o);
+            o.use_graph = 0;
+            o.timing = 1;
+            int r = timing_begin(G, true);
+            if (r) return r;
+            LoopResult lr;
+            r = cg32(G, 1e-30, 40, MFFV_PRECOND_NONE, o, &lr);
+            G->m32 = keep;
+            if (r) return r;
+            mffv_info inf{};
+            if ((r = timing_end(G, &inf))) return r;
+            *pa_us = inf.timed_iters > 0 ? inf.phase_a_us : *apply_us;
+            return MFFV_OK;
+        };
+        struct Cand {
+            March m;
+            double apply_us, pa_us;
+        };
+        std::vector<Cand> cands;
         const int cis[] = {1, 2, 4, 8, 16, 32, 64};
-        // chunk shapes: flat, and row segments of 32..256 cells (16..4 rows a chunk)
+        // chunk shapes: flat, and row segments of 32..256 cells (16..4 rows a
+        // chunk) shorter than a row (a whole-row segment is the flat chunk)
         std::vector<int> segs{-1};
-        for (int sg = 32; sg <= 256; sg *= 2)
+        for (int sg = 32; sg <= 256 && sg < G->g.nz; sg *= 2)
             if (march_seg_ok(G->g, G->m32.vec, sg)) segs.push_back(sg);
         for (int sg : segs)
         for (int c : cis) {
@@ -1485,52 +1548,56 @@ int mffv_autotune(mffv_grid* G, const char* cache_path, mffv_tune_result* out) {
                 HIP_TRY(hipMemcpyAsync(&differs, G->flags + 5, sizeof(int), hipMemcpyDeviceToHost, G->stream));
                 HIP_TRY(hipStreamSynchronize(G->stream));
                 if (differs) continue;
-                const int reps = 10;
-                HIP_TRY(hipEventRecord(e0, G->stream));
-                for (int t = 0; t < reps; ++t)
-                    HIP_TRY(launch_stencil_f32(kApply, G->g, coef_of(G), io, m, G->stream));
-                HIP_TRY(hipEventRecord(e1, G->stream));
-                HIP_TRY(hipEventSynchronize(e1));
-                float ms = 0;
-                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                const double apply_us = 1e3 * ms / reps;
-                // the CG's own hot kernel: phase A over the first 32 iterations of a solve of A x = dinv
-                G->m32 = m;
-                HIP_TRY(hipMemcpyAsync(G->bw, G->dinv, G->g.n * sizeof(float), hipMemcpyDeviceToDevice,
-                                       G->stream));
-                HIP_TRY(hipMemsetAsync(G->xw, 0, G->g.n * sizeof(float), G->stream));
-                mffv_opts o;
-                mffv_default_opts(&o);
-                o.use_graph = 0;
-                o.timing = 1;
-                if ((rc = timing_begin(G, true))) return rc;
-                LoopResult lr;
-                rc = cg32(G, 1e-30, 40, MFFV_PRECOND_NONE, o, &lr);
-                G->m32 = keep;
-                if (rc) return rc;
-                mffv_info inf{};
-                if ((rc = timing_end(G, &inf))) return rc;
-                const double score = inf.timed_iters > 0 ? inf.phase_a_us : apply_us;
+                Cand cd{m, 0, 0};
+                if ((rc = time_shape(m, 10, &cd.apply_us, &cd.pa_us))) return rc;
+                cands.push_back(cd);
                 ++tried;
-                if (score < best) {
-                    best = score;
-                    best_apply = apply_us;
-                    best_ci = c;
-                    best_remap = rm;
-                    best_seg = m.seg > 0 ? m.seg : -1;
-                }
             }
         }
+        // timings of one pass move by a few per cent: the best few of each kind
+        // are timed twice more and ranked by their fastest time
+        auto refine = [&](bool by_apply) -> int {
+            std::vector<size_t> idx(cands.size());
+            for (size_t t = 0; t < idx.size(); ++t) idx[t] = t;
+            std::sort(idx.begin(), idx.end(), [&](size_t x, size_t y) {
+                return by_apply ? cands[x].apply_us < cands[y].apply_us : cands[x].pa_us < cands[y].pa_us;
+            });
+            idx.resize(std::min<size_t>(idx.size(), 4));
+            double best = 1e30;
+            for (size_t t : idx) {
+                for (int rep = 0; rep < 2; ++rep) {
+                    double a = 0, pa = 0;
+                    int r = time_shape(cands[t].m, 50, &a, &pa);
+                    if (r) return r;
+                    cands[t].apply_us = std::min(cands[t].apply_us, a);
+                    cands[t].pa_us = std::min(cands[t].pa_us, pa);
+                }
+                const double v = by_apply ? cands[t].apply_us : cands[t].pa_us;
+                if (v < best) {
+                    best = v;
+                    const March& m = cands[t].m;
+                    const int sgv = m.seg > 0 ? m.seg : -1;
+                    if (by_apply) {
+                        rec.aci = m.ci;
+                        rec.aremap = m.remap;
+                        rec.aseg = sgv;
+                        rec.apply_us = v;
+                    } else {
+                        rec.ci = m.ci;
+                        rec.remap = m.remap;
+                        rec.seg = sgv;
+                        rec.pa_us = v;
+                    }
+                }
+            }
+            return MFFV_OK;
+        };
+        if (!cands.empty() && ((rc = refine(false)) || (rc = refine(true)))) return rc;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (!tried) return fail(MFFV_EHIP, "autotune: no candidate reproduced the reference apply");
-        ci = best_ci;
-        remap = best_remap;
-        seg = best_seg;
-        us = best_apply;
-        pa_us = best;
-        if ((rc = mffv_set_launch(G, ci, remap, seg))) return rc;
-        cache_store(cache_path, key, ci, remap, seg, us, pa_us);
+        if ((rc = set_launches(G, rec))) return rc;
+        cache_store(cache_path, key, rec);
     }
     if (out) {
         out->ci = G->m32.ci;
@@ -1538,9 +1605,13 @@ int mffv_autotune(mffv_grid* G, const char* cache_path, mffv_tune_result* out) {
         out->seg = G->m32.seg > 0 ? G->m32.seg : -1;
         out->vec = G->m32.vec;
         out->blocks = G->m32.blocks();
-        out->apply_us = us;
+        out->apply_us = rec.apply_us;
         out->candidates = tried;
-        out->phase_a_us = pa_us;
+        out->phase_a_us = rec.pa_us;
+        out->apply_ci = G->m_apply.ci;
+        out->apply_remap = G->m_apply.remap;
+        out->apply_seg = G->m_apply.seg > 0 ? G->m_apply.seg : -1;
+        out->apply_blocks = G->m_apply.blocks();
     }
     return MFFV_OK;
 }
@@ -1580,8 +1651,8 @@ int mffv_autotune_batched(mffv_grid* const* grids, int nsys, const float* const*
                 return fail(MFFV_EHIP, "autotune: restoring the initial guess failed");
         return MFFV_OK;
     };
-    const int bpcs[] = {1, 2, 4, 0};
-    const int ipbs[] = {1, 2, 4, 8};
+    const int bpcs[] = {1, 2, 3, 4, 0};
+    const int ipbs[] = {1, 2, 4, 8, 16};
     double best = 1e30;
     int bb = 0, bi = 4;
     std::vector<mffv_info> info((size_t)nsys);

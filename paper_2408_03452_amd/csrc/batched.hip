@@ -113,6 +113,16 @@ __device__ __forceinline__ float ldo(const float* p, uint32_t off) {
 }
 __device__ __forceinline__ void sto(float* p, uint32_t off, float v) { *(gfloat*)((gchar*)p + off) = v; }
 
+// Plane steps whose loads are issued together in phase A and phase B.
+#ifndef MFFV_BATCH_UNROLL_A
+#define MFFV_BATCH_UNROLL_A 3
+#endif
+#ifndef MFFV_BATCH_UNROLL_B
+#define MFFV_BATCH_UNROLL_B 8
+#endif
+constexpr int kUnrollA = MFFV_BATCH_UNROLL_A;
+constexpr int kUnrollB = MFFV_BATCH_UNROLL_B;
+
 // Raw operands of one plane step of phase A: the direction sources (s_k and
 // p_{k-1}) at the next plane and at the four in-plane neighbours, the own
 // faces and diagonal, the faces shared with the previous y and z neighbours,
@@ -209,14 +219,14 @@ __device__ __forceinline__ float phase_a_item(const BatchSys& S, int pc, int ic,
         poc = a.pp;
     };
     int i = i0;
-    for (; i + 1 < i1; i += 2, off += 2u * cc.P4) {
-        StepA a0, a1;
-        load_a(a0, S, cc, src, pold, up, off, i);
-        load_a(a1, S, cc, src, pold, up, off + cc.P4, i + 1);
-        step(a0, off, i);
-        step(a1, off + cc.P4, i + 1);
+    for (; i + kUnrollA - 1 < i1; i += kUnrollA, off += kUnrollA * cc.P4) {
+        StepA a[kUnrollA];
+#pragma unroll
+        for (int u = 0; u < kUnrollA; ++u) load_a(a[u], S, cc, src, pold, up, off + u * cc.P4, i + u);
+#pragma unroll
+        for (int u = 0; u < kUnrollA; ++u) step(a[u], off + u * cc.P4, i + u);
     }
-    if (i < i1) {
+    for (; i < i1; ++i, off += cc.P4) {
         StepA a0;
         load_a(a0, S, cc, src, pold, up, off, i);
         step(a0, off, i);
@@ -225,7 +235,7 @@ __device__ __forceinline__ float phase_a_item(const BatchSys& S, int pc, int ic,
 }
 
 // Phase B of one work item: r -= alpha q (and z = r / diag(A) with Jacobi),
-// with the partial sums of r.r and r.z; four planes' loads at a time.
+// with the partial sums of r.r and r.z; kUnrollB planes' loads at a time.
 __device__ __forceinline__ float2 phase_b_item(const BatchSys& S, int pc, int ic, bool jac, float alpha) {
     const Geom& g = S.g;
     const uint32_t P = (uint32_t)g.plane;
@@ -236,16 +246,16 @@ __device__ __forceinline__ float2 phase_b_item(const BatchSys& S, int pc, int ic
     const uint32_t P4 = 4u * P;
     uint32_t off = 4u * ((uint32_t)i0 * P + r0);
     int i = i0;
-    for (; i + 3 < i1; i += 4, off += 4u * P4) {
-        float rv[4], qv[4], dv[4];
+    for (; i + kUnrollB - 1 < i1; i += kUnrollB, off += kUnrollB * P4) {
+        float rv[kUnrollB], qv[kUnrollB], dv[kUnrollB];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kUnrollB; ++u) {
             rv[u] = ldo(S.r, off + u * P4);
             qv[u] = ldo(S.q, off + u * P4);
             dv[u] = jac ? ldo(S.dinv, off + u * P4) : 0.f;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kUnrollB; ++u) {
             const float r = rv[u] - alpha * qv[u];
             sto(S.r, off + u * P4, r);
             r2 += r * r;

@@ -47,7 +47,8 @@ class TuneResult(ctypes.Structure):
     _fields_ = [("ci", ctypes.c_int), ("remap", ctypes.c_int), ("vec", ctypes.c_int),
                 ("blocks", ctypes.c_int), ("apply_us", ctypes.c_double),
                 ("candidates", ctypes.c_int), ("phase_a_us", ctypes.c_double),
-                ("seg", ctypes.c_int)]
+                ("seg", ctypes.c_int), ("apply_ci", ctypes.c_int), ("apply_remap", ctypes.c_int),
+                ("apply_seg", ctypes.c_int), ("apply_blocks", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -4,7 +4,10 @@
     python3 -m paper_2408_03452_amd.tracesum pmc DIR      # --pmc ... --output-format csv
 
 ``trace`` groups the dispatches of ``*kernel_trace.csv`` by (kernel, grid
-size) and prints calls, total, mean and median duration. ``pmc`` groups the
+size) and prints calls, total, mean and median duration. A group whose sorted
+durations have a gap of more than 2x between neighbours, with at least 1 % of
+the calls on each side, holds launches of different workloads that happen to
+share a launch size; it is split there into the rows "fast" and "slow". ``pmc`` groups the
 rows of ``*counter_collection.csv`` by (kernel, grid size, counter) and prints
 the mean counter value per dispatch; dispatches whose value is below 1 % of
 the group's largest (launches that returned at once, e.g. after convergence)
@@ -42,14 +45,32 @@ def _files(d: str, suffix: str) -> list:
     return sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
 
 
+def _split(v: list) -> list:
+    """[(label, durations)]: one cluster, or two at the widest > 2x gap."""
+    s = sorted(v)
+    n = len(s)
+    lo = max(1, n // 100)
+    best, at = 2.0, None
+    for i in range(lo - 1, n - lo):
+        if s[i] > 0 and s[i + 1] / s[i] > best:
+            best, at = s[i + 1] / s[i], i + 1
+    if at is None:
+        return [("", v)]
+    return [(" (fast)", s[:at]), (" (slow)", s[at:])]
+
+
 def trace(d: str, top: int = 30) -> None:
-    groups = collections.defaultdict(list)
+    raw = collections.defaultdict(list)
     for f in _files(d, "kernel_trace.csv"):
         with open(f, newline="") as fh:
             for row in csv.DictReader(fh):
                 dur = (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e3
                 key = (_short(row["Kernel_Name"]), _grid(row))
-                groups[key].append(dur)
+                raw[key].append(dur)
+    groups = {}
+    for (name, grid), v in raw.items():
+        for label, part in _split(v):
+            groups[(name + label, grid)] = part
     tot_all = sum(sum(v) for v in groups.values())
     print("| kernel | grid (work-items) | calls | total ms | mean us | median us | % of GPU time |")
     print("|---|---:|---:|---:|---:|---:|---:|")

@@ -87,8 +87,16 @@ def test_autotune_caches_and_keeps_results(mf, tmp_path):
     assert len(data) == 1 and list(data.values())[0]["ci"] == r1["ci"]
     g2, _, _ = gpu_problem(mf, k, c=1e-3)
     r2 = mf.autotune(g2, cache)
-    assert r2["candidates"] == 0 and (r2["ci"], r2["remap"], r2["seg"]) == (r1["ci"], r1["remap"], r1["seg"])
-    assert r1["seg"] in (-1, 32, 64)
+    keys = ("ci", "remap", "seg", "apply_ci", "apply_remap", "apply_seg", "apply_blocks")
+    assert r2["candidates"] == 0 and all(r2[k] == r1[k] for k in keys)
+    assert r1["seg"] in (-1, 32) and r1["apply_seg"] in (-1, 32)
+    # the apply runs at its own tuned shape and still equals the default shape's bits
+    xa = torch.randn(k.size, dtype=torch.float32, device="cuda")
+    ya, yb = torch.empty_like(xa), torch.empty_like(xa)
+    mf.apply(g2, xa, ya)
+    mf.set_launch(g2, 0, 1, 0)
+    mf.apply(g2, xa, yb)
+    assert torch.equal(ya, yb)
     x = torch.zeros(k.size, dtype=torch.float64, device="cuda")
     st, info = mf.cg_solve_f64(g, b.double(), x, mf.default_opts(tol=1e-10, precision=mf.FP32_IR))
     assert st == mf.OK
@@ -105,7 +113,7 @@ def test_autotune_batched_keeps_results(mf):
     bs = [p[2] for p in probs]
     xs = [torch.zeros(g.n, dtype=torch.float32, device="cuda") for g in grids]
     best = mf.autotune_batched(grids, bs, xs, mf.default_opts(tol=1e-6, use_graph=0))
-    assert best["ms"] > 0 and best["items_per_block"] in (1, 2, 4, 8)
+    assert best["ms"] > 0 and best["items_per_block"] in (1, 2, 4, 8, 16)
     for x in xs:
         x.zero_()
     st, infos = mf.cg_solve_batched(grids, bs, xs, mf.default_opts(tol=1e-6, use_graph=0))
