@@ -327,12 +327,34 @@ __global__ __launch_bounds__(kThreads) void conv3d(Geom g, ConvArgs a) {
     for (int i = i0; i < i1; ++i) {
         const bool more = i + 1 < i1;
         PlaneRegs<C> R;
+        const int64_t row = ((int64_t)i * g.ny + j) * g.nz;
+        // The epilogue's own operands are loaded first, by every lane from a
+        // clamped (always valid) address and without branches: their latency
+        // then overlaps the matrix work, and since memory counters drain in
+        // issue order, waiting for them never waits for the plane fetch below.
+        // (A data-dependent load, e.g. r only where dmask is 0, would put one
+        // memory round trip after another into every plane step.)
+        float er[4], ed[4];
+        uint32_t em[4];
+        uint2 eb[4];
+        {
+            const int64_t rowc = ((int64_t)i * g.ny + min(j, g.ny - 1)) * g.nz;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const int64_t l = rowc + min(k0 + mt * 16 + m, g.nz - 1);
+                if (MODE == kPrecond) {
+                    er[mt] = a.r[l];
+                    ed[mt] = a.dinv[l];
+                    em[mt] = a.dmask[l];
+                }
+                if (MODE == kGradMasked) eb[mt] = *reinterpret_cast<const uint2*>(a.below + l * 16 + rg * 4);
+            }
+        }
         if (more) fetch_plane<C>(a.in, g, i + 2, j0, k0, R);
         if (j < g.ny) {
             const uint16_t* p[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) p[d] = lds + ((i - i0 + d) & 3) * PCELLS * C;
-            const int64_t row = ((int64_t)i * g.ny + j) * g.nz;
             if constexpr (kLast) {
                 float y[4];
                 conv_last_row(p, wr, y);
@@ -346,8 +368,8 @@ __global__ __launch_bounds__(kThreads) void conv3d(Geom g, ConvArgs a) {
                         if (MODE == kFinal) {
                             a.out32[l] = v;
                         } else {
-                            const float di = a.dinv[l];
-                            a.out32[l] = a.dmask[l] ? 0.f : di * a.r[l] + s * sqrtf(di) * v;
+                            const float di = ed[mt];
+                            a.out32[l] = em[mt] ? 0.f : di * er[mt] + s * sqrtf(di) * v;
                         }
                     }
                 }
@@ -372,7 +394,7 @@ __global__ __launch_bounds__(kThreads) void conv3d(Geom g, ConvArgs a) {
                         make_uint2(pack_bf2(h[0], h[1]), pack_bf2(h[2], h[3]));
                 } else if (MODE == kGradMasked) {
                     float h[4];
-                    const uint2 bl = *reinterpret_cast<const uint2*>(a.below + l * 16 + rg * 4);
+                    const uint2 bl = eb[mt];
                     // ReLU mask: keep the gradient where the activation below is > 0
                     // (positive BF16 values are positive as signed 16-bit integers)
                     const uint32_t bw[4] = {bl.x << 16, bl.x & 0xffff0000u, bl.y << 16, bl.y & 0xffff0000u};
