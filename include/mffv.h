@@ -87,7 +87,8 @@ typedef struct {
     int single_reduction; /* 1: plain FP32 CG on the four-cells-per-thread path (nz % 4 == 0,
                             16-byte aligned vectors) runs one kernel per iteration with a
                             single reduction phase (r.r of the next iteration from a
-                            one-step recurrence on the exact r.r); 0 (default): the
+                            one-step recurrence on the exact r.r), and a batched plain-CG
+                            solve runs one barrier per iteration; 0 (default): the
                             two-phase iteration, faster on one GPU                      */
     int nn_every;        /* MFFV_PRECOND_LEARNED: apply the network every nn_every-th
                             iteration (1 = every one, the default) and the Jacobi step

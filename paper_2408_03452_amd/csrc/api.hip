@@ -713,6 +713,7 @@ struct BatchPlan {
     std::vector<const float*> b;
     std::vector<float*> x;
     int precond = 0, max_iter = 0, blocks_per_cu = 0, items_per_block = 4;
+    int merged = 0;  // single-reduction iteration
     double tol = 0;
     void* dbuf = nullptr;
     BatchSys* dsys = nullptr;
@@ -796,8 +797,10 @@ int build_plan(BatchPlan* P, hipStream_t stream) {
     // the batched kernel addresses a system's vectors with 32-bit byte offsets
     for (mffv_grid* G : P->grids)
         if (G->g.n >= (int64_t(1) << 30)) return fail(MFFV_EINVAL, "batched systems must have fewer than 2^30 cells");
-    for (mffv_grid* G : P->grids)
+    for (mffv_grid* G : P->grids) {
         if ((rc = ensure_ws32(G)) || (rc = ensure_x64(G))) return rc;
+        if (P->merged && (rc = ensure_merged(G))) return rc;
+    }
     int dev = 0, cus = 0, rate_khz = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -814,7 +817,7 @@ int build_plan(BatchPlan* P, hipStream_t stream) {
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
     const size_t o_sys = take(sizeof(BatchSys) * ns), o_map = take(sizeof(int) * total),
-                 o_part = take(sizeof(float) * 4 * total), o_bar = take(sizeof(unsigned) * 2 * ns),
+                 o_part = take(sizeof(float) * 8 * total), o_bar = take(sizeof(unsigned) * 2 * ns),
                  o_res = take(sizeof(BatchResult) * ns), o_r64 = take(sizeof(double) * 2 * ns),
                  o_err = take(sizeof(int));
     HIP_TRY(hipMalloc(&P->dbuf, off));
@@ -843,7 +846,9 @@ int build_plan(BatchPlan* P, hipStream_t stream) {
         S.p1 = G->p1;
         S.q = G->q;
         S.z = G->z;
-        S.part = dpart + 4 * b0;
+        S.r2 = P->merged ? G->r2 : nullptr;
+        S.q2 = P->merged ? G->q2 : nullptr;
+        S.part = dpart + 8 * b0;
         S.bar = P->dbars + 2 * s;
         S.res = P->dres + s;
         S.blk0 = b0;
@@ -862,6 +867,7 @@ int build_plan(BatchPlan* P, hipStream_t stream) {
     P->run.tol2 = (float)(P->tol * P->tol);
     P->run.max_iter = P->max_iter;
     P->run.precond = P->precond;
+    P->run.merged = P->merged;
     P->run.limit_ticks = (uint64_t)rate_khz * 1000ull * 2ull;  // 2 s per barrier wait
     P->run.err = P->derr;
     HIP_TRY(hipEventCreate(&P->e0));
@@ -1281,10 +1287,12 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
     if ((rc = set_device(grids[0]))) return rc;
     hipStream_t stream = grids[0]->stream;
     const int bpc = batch_blocks_per_cu_override();
+    // the single-reduction iteration applies to plain CG
+    const int merged = (o.single_reduction && o.precond == MFFV_PRECOND_NONE) ? 1 : 0;
     std::lock_guard<std::mutex> lk(g_plans_mu);
     BatchPlan* P = nullptr;
     for (BatchPlan* c : g_plans) {
-        if ((int)c->grids.size() != nsys || c->precond != o.precond || c->tol != o.tol ||
+        if ((int)c->grids.size() != nsys || c->precond != o.precond || c->tol != o.tol || c->merged != merged ||
             c->max_iter != o.max_iter || c->blocks_per_cu != bpc || c->items_per_block != g_batch_ipb)
             continue;
         bool same = true;
@@ -1298,6 +1306,7 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
         P->b.assign(b, b + nsys);
         P->x.assign(x, x + nsys);
         P->precond = o.precond;
+        P->merged = merged;
         P->tol = o.tol;
         P->max_iter = o.max_iter;
         P->blocks_per_cu = bpc;
@@ -1362,6 +1371,7 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
             I.rel_res_recursive = R.bnorm2 > 0 ? std::sqrt((double)R.rr / (double)R.bnorm2) : 0.0;
             I.rel_res_true = r64[2 * s] > 0 ? std::sqrt(r64[2 * s + 1] / r64[2 * s]) : std::sqrt(r64[2 * s + 1]);
             I.ms = ms;
+            I.single_reduction = P->merged;
         }
     }
     if (status == MFFV_EBREAKDOWN) return fail(MFFV_EBREAKDOWN, "batched CG: breakdown in a system");

@@ -279,6 +279,121 @@ __device__ __forceinline__ float2 phase_b_item(const BatchSys& S, int pc, int ic
     return make_float2(r2, z2);
 }
 
+// Raw operands of one plane step of the single-reduction iteration: the
+// previous residual, product and direction (r_{K-1}, q_{K-1}, p_{K-1}) at the
+// next plane and at the four in-plane neighbours, the own faces and diagonal,
+// the faces shared with the previous y and z neighbours, and x.
+struct StepM {
+    float zp, qp, pp, zjm, qjm, pjm, zjp, qjp, pjp, zkm, qkm, pkm, zkp, qkp, pkp;
+    float tx, ty, tz, ac, tyl, tzl, xo;
+};
+
+__device__ __forceinline__ void load_m(StepM& o, const BatchSys& S, const CellA& cc, const float* rin,
+                                       const float* qin, const float* pold, bool up, uint32_t off, int i) {
+    const Geom& g = S.g;
+    o.zp = o.qp = o.pp = o.zjm = o.qjm = o.pjm = o.zjp = o.qjp = o.pjp = 0.f;
+    o.zkm = o.qkm = o.pkm = o.zkp = o.qkp = o.pkp = 0.f;
+    o.tyl = o.tzl = o.xo = 0.f;
+    auto three = [&](uint32_t at, float& z, float& q, float& pp) {
+        z = ldo(rin, at);
+        if (up) {
+            q = ldo(qin, at);
+            pp = ldo(pold, at);
+        }
+    };
+    if (i + 1 < g.nx) three(off + cc.P4, o.zp, o.qp, o.pp);
+    o.tx = ldo(S.c.tx, off);
+    o.ty = ldo(S.c.ty, off);
+    o.tz = ldo(S.c.tz, off);
+    o.ac = coef_plane_uniform(S.c, i, g.nx) ? S.c.a_const : ldo(S.c.a, off);
+    if (cc.hasjm) {
+        o.tyl = ldo(S.c.ty, off - cc.nz4);
+        three(off - cc.nz4, o.zjm, o.qjm, o.pjm);
+    }
+    if (cc.hasjp) three(off + cc.nz4, o.zjp, o.qjp, o.pjp);
+    if (cc.haskm) {
+        o.tzl = ldo(S.c.tz, off - 4u);
+        three(off - 4u, o.zkm, o.qkm, o.pkm);
+    }
+    if (cc.haskp) three(off + 4u, o.zkp, o.qkp, o.pkp);
+    if (up) o.xo = ldo(S.x, off);
+}
+
+// One work item of single-reduction iteration K (Alg. 1 with one reduction
+// phase per iteration): r_K = r_{K-1} - alpha q_{K-1} and the direction
+// p_K = r_K + beta p_{K-1} on the fly at every stencil point, q_K = A p_K, the
+// deferred x_K = x_{K-1} + alpha p_{K-1}, and the partial sums of p.q, r.r,
+// r.q and q.q of iteration K; two plane steps' loads at a time. K = 0 (up
+// false) takes r_0 as it is.
+__device__ __forceinline__ float4 merged_item(const BatchSys& S, int pc, int ic, const float* rin,
+                                              const float* qin, const float* pold, float* rout, float* qout,
+                                              float* pnew, bool up, float alpha, float beta) {
+    const Geom& g = S.g;
+    const uint32_t P = (uint32_t)g.plane;
+    const uint32_t r0 = (uint32_t)pc * kThreads + threadIdx.x;
+    float pq = 0.f, rr = 0.f, rq = 0.f, qq = 0.f;
+    if (r0 >= P) return make_float4(pq, rr, rq, qq);
+    const int i0 = ic * S.ci, i1 = min(g.nx, i0 + S.ci);
+    const uint32_t j = r0 / (uint32_t)g.nz, k = r0 - j * (uint32_t)g.nz;
+    CellA cc;
+    cc.hasjm = j > 0;
+    cc.hasjp = (int)j + 1 < g.ny;
+    cc.haskm = k > 0;
+    cc.haskp = (int)k + 1 < g.nz;
+    cc.nz4 = 4u * (uint32_t)g.nz;
+    cc.P4 = 4u * P;
+    auto resid = [&](float z, float q) { return up ? z - alpha * q : z; };
+    auto dir = [&](float z, float q, float pp) { return up ? resid(z, q) + beta * pp : z; };
+    uint32_t off = 4u * ((uint32_t)i0 * P + r0);
+    float poc = up ? ldo(pold, off) : 0.f;
+    float zc = resid(ldo(rin, off), up ? ldo(qin, off) : 0.f);
+    float sc = up ? zc + beta * poc : zc;
+    float sm = sc, txm = 0.f;
+    if (i0 > 0) {
+        const uint32_t o = off - cc.P4;
+        sm = dir(ldo(rin, o), up ? ldo(qin, o) : 0.f, up ? ldo(pold, o) : 0.f);
+        txm = ldo(S.c.tx, o);
+    }
+    auto step = [&](const StepM& a, uint32_t o, int i) {
+        const bool nxt = i + 1 < g.nx;
+        const float zn = nxt ? resid(a.zp, a.qp) : zc;
+        const float sp = nxt ? (up ? zn + beta * a.pp : zn) : sc;
+        const float sjm = cc.hasjm ? dir(a.zjm, a.qjm, a.pjm) : sc;
+        const float sjp = cc.hasjp ? dir(a.zjp, a.qjp, a.pjp) : sc;
+        const float skm = cc.haskm ? dir(a.zkm, a.qkm, a.pkm) : sc;
+        const float skp = cc.haskp ? dir(a.zkp, a.qkp, a.pkp) : sc;
+        const float y =
+            cell_op<float, float>(a.ac, sc, a.tx, sp, txm, sm, a.ty, sjp, a.tyl, sjm, a.tz, skp, a.tzl, skm);
+        sto(rout, o, zc);
+        sto(pnew, o, sc);
+        sto(qout, o, y);
+        if (up) sto(S.x, o, a.xo + alpha * poc);
+        pq += sc * y;
+        rr += zc * zc;
+        rq += zc * y;
+        qq += y * y;
+        sm = sc;
+        sc = sp;
+        zc = zn;
+        txm = a.tx;
+        poc = a.pp;
+    };
+    int i = i0;
+    for (; i + 1 < i1; i += 2, off += 2u * cc.P4) {
+        StepM a0, a1;
+        load_m(a0, S, cc, rin, qin, pold, up, off, i);
+        load_m(a1, S, cc, rin, qin, pold, up, off + cc.P4, i + 1);
+        step(a0, off, i);
+        step(a1, off + cc.P4, i + 1);
+    }
+    if (i < i1) {
+        StepM a0;
+        load_m(a0, S, cc, rin, qin, pold, up, off, i);
+        step(a0, off, i);
+    }
+    return make_float4(pq, rr, rq, qq);
+}
+
 __global__ __launch_bounds__(kThreads) void batched_cg(const BatchSys* __restrict__ systems,
                                                        const int* __restrict__ block_sys, BatchRun run) {
     __shared__ float red[kThreads / kWave];
@@ -330,7 +445,73 @@ __global__ __launch_bounds__(kThreads) void batched_cg(const BatchSys* __restric
     int k = 0, status = 0, tail = 0;
     const float* src = jac ? S.z : S.r;
 
-    for (;;) {
+    if (run.merged) {
+        // Single-reduction iteration K: the partial sums of iteration K-1 give
+        // alpha_{K-1} = rho_{K-1} / p.q, rho_K = rho_{K-1} - 2 alpha r.q + alpha^2 q.q
+        // (one step from the exact rho_{K-1}) and beta_{K-1} = rho_K / rho_{K-1}.
+        // Convergence is tested on the exact rho_{K-1}; iteration K-1 completed
+        // x_{K-1}, so the run stops with no owed update. One barrier per iteration.
+        //
+        // With a single barrier per iteration the partial sums are double
+        // buffered: iteration K writes set (K+1) & 1 and iteration K+1 reads it,
+        // so no block overwrites sums another block may still be reading (set 0
+        // holds the initial residual's sums, read before iteration 0's barrier).
+        float alpha = 0.f, bm = 0.f;
+        int K = 0;
+        for (;;) {
+            bool bad = false;
+            if (K > 0) {
+                const float* rd = S.part + 4 * B * (K & 1);
+                const float pq = sum_partials(rd, B, red);
+                rr = sum_partials(rd + B, B, red);
+                const float rq = sum_partials(rd + 2 * B, B, red);
+                const float qq = sum_partials(rd + 3 * B, B, red);
+                bad = !(pq > 0.f) || !isfinite(pq);
+                alpha = rr / pq;
+                const float rnext = rr - 2.f * alpha * rq + alpha * alpha * qq;
+                bm = rnext > 0.f ? rnext / rr : 0.f;  // a cancelled recurrence restarts the directions
+            }
+            const bool conv = isfinite(rr) && rr <= thresh2;
+            bad = !conv && (bad || !isfinite(rr));
+            const int done = K == 0 ? 0 : K - 1;
+            if (conv || bad || done >= run.max_iter) {
+                status = conv ? 0 : (bad ? -4 : 1);
+                k = done;
+                break;
+            }
+            const bool up = K > 0;
+            const float* rin = (K & 1) ? S.r2 : S.r;
+            float* rout = (K & 1) ? S.r : S.r2;
+            const float* qin = (K & 1) ? S.q : S.q2;
+            float* qout = (K & 1) ? S.q2 : S.q;
+            const float* pold = (K & 1) ? S.p0 : S.p1;
+            float* pnew = (K & 1) ? S.p1 : S.p0;
+            float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int w = t; w < W; w += B) {
+                const float4 v =
+                    merged_item(S, w % S.nchunk, w / S.nchunk, rin, qin, pold, rout, qout, pnew, up, alpha, bm);
+                d.x += v.x;
+                d.y += v.y;
+                d.z += v.z;
+                d.w += v.w;
+            }
+            {
+                const float a0 = block_sum(d.x, red), a1 = block_sum(d.y, red), a2 = block_sum(d.z, red),
+                            a3 = block_sum(d.w, red);
+                if (threadIdx.x == 0) {
+                    float* wr = S.part + 4 * B * ((K + 1) & 1);
+                    wr[t] = a0;
+                    wr[B + t] = a1;
+                    wr[2 * B + t] = a2;
+                    wr[3 * B + t] = a3;
+                }
+            }
+            if (!sys_barrier(S.bar, B, run.limit_ticks, run.err)) return;
+            ++K;
+        }
+    }
+
+    while (!run.merged) {
         const bool conv = isfinite(rr) && rr <= thresh2;
         const bool bad = !conv && (!isfinite(rr) || (jac && (!(rho > 0.f) || !isfinite(rho))));
         if (conv || bad || k >= run.max_iter) {

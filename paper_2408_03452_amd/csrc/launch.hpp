@@ -149,7 +149,8 @@ struct BatchSys {
     const float* b;
     float* x;
     float *r, *p0, *p1, *q, *z;  // workspace of the system's grid handle
-    float* part;                 // 4 * nblk partial sums
+    float *r2, *q2;              // second r and q buffers (single-reduction form only)
+    float* part;                 // 2 sets of 4 * nblk partial sums
     unsigned* bar;               // barrier: arrival count, generation
     BatchResult* res;
     int blk0, nblk;              // the system's blocks in the launch
@@ -160,6 +161,7 @@ struct BatchRun {
     float tol2;
     int max_iter;
     int precond;            // 0 none, 1 Jacobi
+    int merged;             // 1: single-reduction iteration (plain CG only)
     uint64_t limit_ticks;   // barrier watchdog, in wall-clock ticks
     int* err;               // set to 1 when a barrier wait expires
 };

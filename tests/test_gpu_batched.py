@@ -126,3 +126,42 @@ def test_batched_uneven_64_systems_workload(mf):
     # FP32 fields: rounding x to FP32 alone leaves a true residual of order
     # 1e-5 on the largest (128^3) systems; the recursive residual met 1e-6 above
     assert worst < 1e-4
+
+
+def test_batched_single_reduction_matches_oracle_and_two_phase(mf):
+    """The single-reduction batched iteration (one barrier per iteration) reaches
+    the oracle's fields, takes about the two-phase form's iteration count, and
+    is deterministic; with Jacobi the batch keeps the two-phase form."""
+    systems = small_batch(7)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        probs = [gpu_problem(mf, k, c=c, stream=s) for _, k, c in systems]
+        grids = [p[0] for p in probs]
+        bs = [p[2] for p in probs]
+
+        def run(**kw):
+            xs = [torch.zeros(k.size, dtype=torch.float32, device="cuda") for _, k, _ in systems]
+            st, infos = mf.cg_solve_batched(grids, bs, xs, mf.default_opts(tol=1e-6, **kw))
+            torch.cuda.synchronize()
+            return st, infos, [host(x) for x in xs]
+
+        st2, inf2, x2 = run(single_reduction=0)
+        st1, inf1, x1 = run(single_reduction=1)
+        st1b, inf1b, x1b = run(single_reduction=1)
+        stj, infj, _ = run(single_reduction=1, precond=mf.PRECOND_JACOBI)
+    assert st1 == st2 == stj == mf.OK
+    assert all(i["single_reduction"] == 1 for i in inf1)
+    assert all(i["single_reduction"] == 0 for i in inf2 + infj)
+    for a, b in zip(x1, x1b):
+        assert np.array_equal(a, b)
+    for (shape, k, c), xa, xb, ia, ib in zip(systems, x1, x2, inf1, inf2):
+        ref = OracleProblem(k, c=c)
+        p = ref.direct()
+        assert ia["status"] == mf.OK and ia["rel_res_recursive"] <= 1e-6
+        assert np.linalg.norm(xa - p) <= 5e-5 * np.linalg.norm(p), shape
+        # FP32 recurrences drift from the true residual in both forms; the
+        # single-reduction one must stay within a small factor of the two-phase one
+        assert ia["rel_res_true"] <= max(1e-4, 10 * ib["rel_res_true"]), (shape, ia, ib)
+        assert abs(ia["iters"] - ib["iters"]) <= max(3, ib["iters"] // 20), (shape, ia["iters"], ib["iters"])
+        assert np.linalg.norm(xa - xb) <= 5e-5 * np.linalg.norm(p), shape
+        assert np.array_equal(xa.reshape(shape)[0], np.ones(shape[1:]))   # Dirichlet values
