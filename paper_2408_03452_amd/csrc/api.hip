@@ -817,7 +817,7 @@ int build_plan(BatchPlan* P, hipStream_t stream) {
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
     const size_t o_sys = take(sizeof(BatchSys) * ns), o_map = take(sizeof(int) * total),
-                 o_part = take(sizeof(float) * 8 * total), o_bar = take(sizeof(unsigned) * 2 * ns),
+                 o_part = take(sizeof(float) * 8 * total), o_bar = take(sizeof(unsigned) * (2 * (size_t)ns + 2 * (size_t)total)),
                  o_res = take(sizeof(BatchResult) * ns), o_r64 = take(sizeof(double) * 2 * ns),
                  o_err = take(sizeof(int));
     HIP_TRY(hipMalloc(&P->dbuf, off));
@@ -850,6 +850,7 @@ int build_plan(BatchPlan* P, hipStream_t stream) {
         S.q2 = P->merged ? G->q2 : nullptr;
         S.part = dpart + 8 * b0;
         S.bar = P->dbars + 2 * s;
+        S.xch = reinterpret_cast<unsigned long long*>(P->dbars + 2 * ns) + b0;
         S.res = P->dres + s;
         S.blk0 = b0;
         S.nblk = P->blocks[s];
@@ -878,8 +879,9 @@ int build_plan(BatchPlan* P, hipStream_t stream) {
 
 // Enqueue the whole batch: persistent CG, then each system's FP64 residual.
 int enqueue_batch(BatchPlan* P, hipStream_t stream) {
+    // barrier words of every system, then the 64-bit exchange slot of every block
     HIP_TRY(launch_batched_cg(P->dsys, P->dblock_sys, P->nblocks, P->dbars,
-                              2 * (int)P->grids.size(), P->run, stream));
+                              2 * (int)P->grids.size() + 2 * P->nblocks, P->run, stream));
     for (size_t s = 0; s < P->grids.size(); ++s) {
         mffv_grid* G = P->grids[s];
         HIP_TRY(launch_convert_f32_to_f64(G->g.n, P->x[s], G->x64, stream));

@@ -47,6 +47,50 @@ __device__ __forceinline__ bool sys_barrier(unsigned* bar, unsigned nblk, uint64
     return ok != 0;
 }
 
+// Exchange of one partial sum per block without a fence. Each block publishes
+// its value with the tag of the exchange in one 64-bit relaxed atomic word;
+// every block waits until all of the system's words carry that tag and sums
+// the values in sum_partials' order (so the result has the same bits). Only
+// the values inside these words pass between blocks, which is why no release
+// or acquire is needed: use it where the blocks have no other data to share
+// (phase B touches only the cells the same thread wrote in phase A). A block
+// cannot overwrite its word with the next tag before every block has read
+// this one: the fenced barrier at the end of the iteration lies in between.
+// Returns false (after recording the error) if a wait exceeds the limit.
+__device__ __forceinline__ bool exchange_sum(unsigned long long* xch, int t, int nblk, unsigned tag, float v,
+                                             uint64_t limit_ticks, int* err, float* red, float* out) {
+    __shared__ int ok;
+    if (threadIdx.x == 0) {
+        ok = 1;
+        __hip_atomic_store(&xch[t], ((unsigned long long)tag << 32) | __float_as_uint(v), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    float s = 0.f;
+    bool mine = true;
+    for (int i = threadIdx.x; i < nblk; i += kThreads) {
+        const uint64_t t0 = wall_clock64();
+        unsigned long long w;
+        for (;;) {
+            w = __hip_atomic_load(&xch[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((unsigned)(w >> 32) == tag) break;
+            __builtin_amdgcn_s_sleep(1);
+            if (wall_clock64() - t0 > limit_ticks) {
+                mine = false;
+                break;
+            }
+        }
+        if (!mine) break;
+        s += __uint_as_float((unsigned)w);
+    }
+    if (!mine) {
+        ok = 0;
+        atomicOr(err, 1);
+    }
+    *out = block_sum(s, red);  // its barriers also publish ok
+    return ok != 0;
+}
+
 // Visit the cells of one work item (chunk pc of a plane, planes of group ic),
 // marching along x with the x-neighbours in registers. S(l) is the stencil's
 // source value at cell l; epi(l, s_l, (A s)_l) consumes each own cell.
@@ -403,7 +447,6 @@ __global__ __launch_bounds__(kThreads) void batched_cg(const BatchSys* __restric
     const Coef c = S.c;
     const int W = S.nchunk * S.nich;
     const bool jac = run.precond == 1;
-    float* pq_part = S.part;
     float* rr_part = S.part + B;
     float* rz_part = S.part + 2 * B;
     float* bb_part = S.part + 3 * B;
@@ -526,12 +569,14 @@ __global__ __launch_bounds__(kThreads) void batched_cg(const BatchSys* __restric
         float dot = 0.f;
         for (int w = t; w < W; w += B)
             dot += phase_a_item(S, w % S.nchunk, w / S.nchunk, src, pold, pnew, up, beta, alpha_prev);
-        {
+        // p.q: a fence-free exchange (phase B needs no other block's data)
+        float pq = 0.f;
+        if (B > 1) {
             const float a0 = block_sum(dot, red);
-            if (threadIdx.x == 0) pq_part[t] = a0;
+            if (!exchange_sum(S.xch, t, B, (unsigned)k + 1u, a0, run.limit_ticks, run.err, red, &pq)) return;
+        } else {
+            pq = block_sum(dot, red);
         }
-        if (!sys_barrier(S.bar, B, run.limit_ticks, run.err)) return;
-        const float pq = sum_partials(pq_part, B, red);
         if (!(pq > 0.f) || !isfinite(pq)) {
             status = -4;
             tail = 0;

@@ -152,6 +152,7 @@ struct BatchSys {
     float *r2, *q2;              // second r and q buffers (single-reduction form only)
     float* part;                 // 2 sets of 4 * nblk partial sums
     unsigned* bar;               // barrier: arrival count, generation
+    unsigned long long* xch;     // per block of the system: (tag << 32) | bits of its p.q partial
     BatchResult* res;
     int blk0, nblk;              // the system's blocks in the launch
     int nchunk, nich, ci;        // work items: plane chunks x plane groups
