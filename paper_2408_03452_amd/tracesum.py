@@ -4,10 +4,11 @@
     python3 -m paper_2408_03452_amd.tracesum pmc DIR      # --pmc ... --output-format csv
 
 ``trace`` groups the dispatches of ``*kernel_trace.csv`` by (kernel, grid
-size) and prints calls, total, mean and median duration. A group whose sorted
-durations have a gap of more than 2x between neighbours, with at least 1 % of
-the calls on each side, holds launches of different workloads that happen to
-share a launch size; it is split there into the rows "fast" and "slow". ``pmc`` groups the
+size) and prints calls, total, mean and median duration. A group whose
+durations form two clusters (a two-means split of the log durations) with
+medians more than 2x apart, each holding at least 1 % of the calls, holds
+launches of different workloads that happen to share a launch size; it is
+split into the rows "fast" and "slow". ``pmc`` groups the
 rows of ``*counter_collection.csv`` by (kernel, grid size, counter) and prints
 the mean counter value per dispatch; dispatches whose value is below 1 % of
 the group's largest (launches that returned at once, e.g. after convergence)
@@ -18,6 +19,7 @@ from __future__ import annotations
 import collections
 import csv
 import glob
+import math
 import os
 import statistics
 import sys
@@ -46,15 +48,31 @@ def _files(d: str, suffix: str) -> list:
 
 
 def _split(v: list) -> list:
-    """[(label, durations)]: one cluster, or two at the widest > 2x gap."""
+    """[(label, durations)]: one cluster, or two when a two-means split of the
+    log durations gives clusters whose medians differ by more than 2x, each
+    with at least 1 % of the calls."""
     s = sorted(v)
     n = len(s)
     lo = max(1, n // 100)
-    best, at = 2.0, None
-    for i in range(lo - 1, n - lo):
-        if s[i] > 0 and s[i + 1] / s[i] > best:
-            best, at = s[i + 1] / s[i], i + 1
-    if at is None:
+    if n < 2 * lo or s[0] <= 0:
+        return [("", v)]
+    x = [math.log(d) for d in s]
+    pre, pre2 = [0.0], [0.0]
+    for t in x:
+        pre.append(pre[-1] + t)
+        pre2.append(pre2[-1] + t * t)
+
+    def sse(a, b):  # sum of squared deviations of x[a:b]
+        m = b - a
+        sm = pre[b] - pre[a]
+        return (pre2[b] - pre2[a]) - sm * sm / m
+
+    best, at = None, None
+    for i in range(lo, n - lo + 1):
+        c = sse(0, i) + sse(i, n)
+        if best is None or c < best:
+            best, at = c, i
+    if at is None or statistics.median(s[at:]) <= 2.0 * statistics.median(s[:at]):
         return [("", v)]
     return [(" (fast)", s[:at]), (" (slow)", s[at:])]
 

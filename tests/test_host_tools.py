@@ -3,10 +3,9 @@ script's traffic lookup and one-GPU guard."""
 import csv
 import json
 import os
+import statistics
 import subprocess
 import sys
-
-import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
@@ -35,6 +34,12 @@ def test_split_separates_workloads_that_share_a_launch_size():
     assert len(tracesum._split([100.0 + i for i in range(50)])) == 1
     # a handful of outliers (< 1 % of the calls) do not make a row of their own
     assert len(tracesum._split([110.0] * 1000 + [5.0] * 3)) == 1
+    # launches in between (cold starts, early exits) do not hide two workloads
+    mixed = fast + slow + [30.0 + 10 * i for i in range(8)] + [3.0] * 5
+    parts = tracesum._split(mixed)
+    assert len(parts) == 2
+    assert abs(statistics.median(parts[1][1]) - statistics.median(slow)) < 1.0
+    assert abs(statistics.median(parts[0][1]) - statistics.median(fast)) < 1.0
 
 
 def test_trace_summary_rows(tmp_path, capsys):
