@@ -323,6 +323,106 @@ def bench_learned(log_fn, held_in: int, held_out: int):
 
     for g, _ in train + confirm:
         g.close()
+    out["_params"] = mffv.net_get_params(chosen)[0]
+    return out
+
+
+def bench_large_learned(log_fn, c3_params, n_crops: int = 100, n_eval: int = 4):
+    """Learned preconditioner on the 512 x 512 x 1024 anisotropic workload: the
+    network trained on the channelised field is fine-tuned on 32^3 crops of this
+    field (white noise, then its own flexible-CG residuals), flexible CG with
+    either network is compared with Jacobi-PCG and plain CG to 1e-6 on held-out
+    128^3 crops, and the iteration time of each method is measured on the full
+    grid (a solve of the full grid to 1e-8 with the network is beyond a bench
+    run: plain CG alone needs about 400,000 iterations)."""
+    import numpy as np
+    import torch
+    from paper_2408_03452_amd import mffv, learned
+    from synth import WORKLOADS, workload_field
+
+    w = WORKLOADS["anisotropic_512x512x1024"]
+    nx, ny, nz = w.shape
+    t0 = time.perf_counter()
+    k = workload_field(w)
+    log_fn(f"large-learned: field {w.shape} generated in {time.perf_counter() - t0:.1f} s")
+    rng = np.random.default_rng(4100)
+
+    def positions(size, count):
+        return [(int(rng.integers(0, nx - size + 1)), int(rng.integers(0, ny - size + 1)),
+                 int(rng.integers(0, nz - size + 1))) for _ in range(count)]
+
+    def problem(kc, stream):
+        cx, cy, cz = kc.shape
+        kd = torch.from_numpy(np.ascontiguousarray(kc).ravel()).cuda()
+        tx, ty, tz, b = (torch.empty(kc.size, dtype=torch.float32, device="cuda") for _ in range(4))
+        mffv.perm_to_trans(cx, cy, cz, kd, w.kz_ratio, tx, ty, tz, stream=stream)
+        g = mffv.create_grid(cx, cy, cz, stream=stream)
+        mffv.set_transmissibility(g, tx, ty, tz, accum_scalar=w.c, b_out=b)
+        return g, b
+
+    def crop(pos, size):
+        i, j, l = pos
+        return k[i:i + size, j:j + size, l:l + size]
+
+    out = {"workload": w.name, "finetune_crops_32cube": n_crops, "eval_crops_128cube": n_eval}
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        t1 = time.perf_counter()
+        train = [problem(crop(p, 32), s) for p in positions(32, n_crops)]
+        tuned = learned.train_preconditioner(train, validation=train[:8], n_white=10 * n_crops, epochs=3,
+                                             lr=1e-3, dagger_rounds=1, dagger_epochs=2, init=c3_params,
+                                             log=log_fn)
+        out["finetune_s"] = time.perf_counter() - t1
+        log_fn(f"large-learned: fine-tuned on {n_crops} crops of 32^3 in {out['finetune_s']:.1f} s")
+        c3 = mffv.net_create(c3_params)
+        # (name, preconditioner, network)
+        methods = (("plain", mffv.PRECOND_NONE, None),
+                   ("jacobi", mffv.PRECOND_JACOBI, None),
+                   ("learned_fcg_channelised_net", mffv.PRECOND_LEARNED, c3),
+                   ("learned_fcg_finetuned", mffv.PRECOND_LEARNED, tuned))
+        rows = {name: [] for name, _, _ in methods}
+        for pos in positions(128, n_eval):
+            g, b = problem(crop(pos, 128), s)
+            for name, pre, net in methods:
+                x = torch.zeros(g.n, dtype=torch.float32, device="cuda")
+                mffv.cg_solve(g, b, x, mffv.default_opts(max_iter=4, precond=pre, net=net))
+                x.zero_()
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                st, info = mffv.cg_solve(g, b, x, mffv.default_opts(precond=pre, net=net))
+                torch.cuda.synchronize()
+                rows[name].append((time.perf_counter() - t2, info["iters"], info["rel_res_true"], st))
+            g.close()
+        out["crops_128cube"] = {
+            name: {"time_to_1e-6_s_median": float(np.median([v[0] for v in r])),
+                   "iters_median": float(np.median([v[1] for v in r])),
+                   "rel_res_true_max": float(max(v[2] for v in r)),
+                   "all_converged": all(v[3] == 0 for v in r)} for name, r in rows.items()}
+        log_fn("large-learned: 128^3 crops, median time to 1e-6 (iterations): " + ", ".join(
+            f"{n} {v['time_to_1e-6_s_median'] * 1e3:.1f} ms ({v['iters_median']:.0f})"
+            for n, v in out["crops_128cube"].items()))
+        for g, _ in train:
+            g.close()
+        # iteration time of each method on the full grid
+        g, b = problem(k, s)
+        del k
+        full = {}
+        for name, pre, net in methods:
+            iters = 20 if pre == mffv.PRECOND_LEARNED else 100
+            x = torch.zeros(g.n, dtype=torch.float32, device="cuda")
+            o = mffv.default_opts(tol=1e-30, max_iter=iters, precond=pre, net=net)
+            mffv.cg_solve(g, b, x, mffv.default_opts(tol=1e-30, max_iter=4, precond=pre, net=net))
+            x.zero_()
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            st, info = mffv.cg_solve(g, b, x, o)
+            torch.cuda.synchronize()
+            full[name] = {"ms_per_iter": (time.perf_counter() - t3) * 1e3 / max(1, info["iters"]),
+                          "iters": info["iters"]}
+        out["full_grid_ms_per_iter"] = full
+        log_fn("large-learned: full grid ms per iteration: " + ", ".join(
+            f"{n} {v['ms_per_iter']:.2f}" for n, v in full.items()))
+        g.close()
     return out
 
 
@@ -342,6 +442,9 @@ def main(argv=None):
     ap.add_argument("--learned-held-in", type=int, default=200)
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 512x512x1024 apply / CG-rate measurement")
+    ap.add_argument("--large-learned", action="store_true",
+                    help="fine-tune the learned preconditioner on crops of the 512x512x1024 workload and "
+                         "compare the methods there (needs the learned section)")
     ap.add_argument("--large-solve", action="store_true",
                     help="also solve the 512x512x1024 system to 1e-8 (minutes)")
     args = ap.parse_args(argv)
@@ -491,11 +594,17 @@ def main(argv=None):
         log(f"batched: {batched['cells_iter_per_s'] / 1e9:.1f} Gcell*iter/s, iters "
             f"{batched['iters_min_max']}, worst true rel-res {batched['rel_res_true_max']:.2e}")
     learned_res = None
+    large_learned = None
     if not args.no_learned:
         learned_res = bench_learned(log, args.learned_held_in, args.learned_held_out)
+        c3_params = learned_res.pop("_params")
         log("learned: median time to 1e-6 (iterations): " + ", ".join(
             f"{k} {learned_res[k]['time_to_1e-6_s_median']*1e3:.1f} ms ({learned_res[k]['iters_median']:.0f})"
             for k in ("plain", "jacobi", "learned_fcg")))
+        if args.large_learned:
+            large_learned = bench_large_learned(log, c3_params)
+    elif args.large_learned:
+        log("large-learned: skipped (it fine-tunes the network of the learned section, which --no-learned removes)")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -535,6 +644,7 @@ def main(argv=None):
         "large": large,
         "batched": batched,
         "learned": learned_res,
+        "large_learned": large_learned,
         "phase_a_us": phase_a_us,
         "phase_a_GBps": phase_a_gbps,
         "phase_b_us": phase_b_us,

@@ -138,7 +138,7 @@ def fcg_iterations(net: mffv.Net, systems, max_iter=20000) -> int:
 def train_preconditioner(systems, validation=None, n_white: int = 256, epochs: int = 24,
                          lr: float = 2e-3, lr_final: float = 1e-4, dagger_rounds: int = 2,
                          dagger_epochs: int = 6, seed: int = 0, relu: bool = True,
-                         loss: int = 0, log=None) -> mffv.Net:
+                         loss: int = 0, init=None, log=None) -> mffv.Net:
     """The training recipe on held-in systems [(grid, b), ...].
 
     White-noise residuals with the energy functional, then ``dagger_rounds``
@@ -147,21 +147,23 @@ def train_preconditioner(systems, validation=None, n_white: int = 256, epochs: i
     flexible-CG iteration count on the validation systems (default: the first
     two held-in systems) and the best parameters so far are kept; the zero
     network (Jacobi) is the first candidate, so the result is never worse
-    than Jacobi on the validation systems.
+    than Jacobi on the validation systems. With ``init`` (a parameter vector,
+    e.g. a network trained on another field) training continues from it
+    (fine-tuning), and that network is the first candidate instead.
     """
     import numpy as np
     validation = systems[:2] if validation is None else validation
-    p0 = init_params(seed)
+    p0 = init_params(seed) if init is None else np.array(init, dtype=np.float32).ravel()
     net = mffv.net_create(p0)
     mffv.net_set_activation(net, relu)
     mffv.net_set_loss(net, loss)
-    best_p = p0.copy()                      # last layer zero: the network is Jacobi
+    best_p = p0.copy()                      # the starting network (zero last layer: Jacobi)
     caps = []
-    for sysv in validation:                 # a candidate may take twice Jacobi's count at most
+    for sysv in validation:                 # a candidate may take twice the start's count at most
         caps.append(2 * fcg_iterations(net, [sysv]) + 10)
     best = sum((c - 10) // 2 for c in caps)
     if log:
-        log(f"validation FCG iterations with the zero network: {best}")
+        log(f"validation FCG iterations with the {'zero' if init is None else 'starting'} network: {best}")
 
     def run(samples, n_ep, lr0, lr1, tag, sd):
         nonlocal best, best_p

@@ -234,3 +234,24 @@ def test_training_gains_over_the_zero_network(mf):
     for (iz, _), (it, tt), (ip, tp) in zip(res["zero"], res["trained"], res["plain"]):
         assert it < 0.8 * iz          # the trained network cuts iterations
         assert tt < tp                # and beats plain CG in time to 1e-6
+
+
+def test_finetuning_starts_from_the_given_network(mf):
+    """train_preconditioner(init=...) continues from a given network, and that
+    network is the first candidate of the epoch selection: the result never
+    takes more flexible-CG iterations on the validation systems than it."""
+    from paper_2408_03452_amd import learned
+    shape = (16, 16, 16)
+    systems = [gpu_problem(mf, channelised(shape, seed), c=1e-3) for seed in (3000, 3001, 3002)]
+    systems = [(g, b) for g, _, b in systems]
+    start = learned.train_preconditioner(systems, validation=systems[:2], n_white=12, epochs=2,
+                                         dagger_rounds=0)
+    p_start, _ = mf.net_get_params(start)
+    it_start = learned.fcg_iterations(start, systems[:2])
+    tuned = learned.train_preconditioner(systems, validation=systems[:2], n_white=12, epochs=1,
+                                         lr=1e-3, dagger_rounds=0, init=p_start)
+    assert learned.fcg_iterations(tuned, systems[:2]) <= it_start
+    # with no epoch better than the start, the start comes back unchanged
+    same = learned.train_preconditioner(systems, validation=systems[:2], n_white=4, epochs=1,
+                                        lr=1e-12, lr_final=1e-12, dagger_rounds=0, init=p_start)
+    assert np.array_equal(mf.net_get_params(same)[0], p_start)
