@@ -373,6 +373,17 @@ int mffv_autotune(mffv_grid* grid, const char* cache_path, mffv_tune_result* out
 int mffv_set_batched_launch(int blocks_per_cu, int items_per_block);
 
 /*
+ * Limit of one per-system wait (barrier or partial-sum exchange) of the
+ * persistent batched kernel, in seconds (default 2; process-wide, applies to
+ * later batched solves). A block whose wait exceeds it records an error and
+ * leaves, and the solve returns MFFV_EHIP, so a launch whose blocks cannot all
+ * be resident ends instead of hanging. 0 makes every wait that is not
+ * satisfied at once fail: for callers that test that failure path. Values
+ * outside [0, 3600] return MFFV_EINVAL.
+ */
+int mffv_set_batched_watchdog(double seconds);
+
+/*
  * Autotune the batched launch shape: solves the batch (as mffv_cg_solve_batched)
  * for every candidate (1, 2, 3, 4 or all-fitting blocks per CU x 1, 2, 4, 8, 16 work
  * items per block), each from the initial guess held in x, times each with HIP

@@ -714,6 +714,7 @@ struct BatchPlan {
     std::vector<float*> x;
     int precond = 0, max_iter = 0, blocks_per_cu = 0, items_per_block = 4;
     int merged = 0;  // single-reduction iteration
+    double watchdog_s = 2.0;
     double tol = 0;
     void* dbuf = nullptr;
     BatchSys* dsys = nullptr;
@@ -732,6 +733,7 @@ struct BatchPlan {
 std::mutex g_plans_mu;
 int g_batch_bpc = 0;  // blocks per CU of the batched kernel (0 = occupancy limit)
 int g_batch_ipb = 4;  // work items per block of the batched kernel
+double g_batch_watchdog_s = 2.0;  // limit of one per-system wait of the batched kernel
 
 int batch_blocks_per_cu_override() { return g_batch_bpc; }
 std::vector<BatchPlan*> g_plans;
@@ -869,7 +871,9 @@ int build_plan(BatchPlan* P, hipStream_t stream) {
     P->run.max_iter = P->max_iter;
     P->run.precond = P->precond;
     P->run.merged = P->merged;
-    P->run.limit_ticks = (uint64_t)rate_khz * 1000ull * 2ull;  // 2 s per barrier wait
+    // limit of one per-system wait, in wall-clock ticks (0: a wait not satisfied
+    // at once fails)
+    P->run.limit_ticks = (uint64_t)((double)rate_khz * 1000.0 * P->watchdog_s);
     P->run.err = P->derr;
     HIP_TRY(hipEventCreate(&P->e0));
     HIP_TRY(hipEventCreate(&P->e1));
@@ -1295,7 +1299,8 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
     BatchPlan* P = nullptr;
     for (BatchPlan* c : g_plans) {
         if ((int)c->grids.size() != nsys || c->precond != o.precond || c->tol != o.tol || c->merged != merged ||
-            c->max_iter != o.max_iter || c->blocks_per_cu != bpc || c->items_per_block != g_batch_ipb)
+            c->max_iter != o.max_iter || c->blocks_per_cu != bpc || c->items_per_block != g_batch_ipb ||
+            c->watchdog_s != g_batch_watchdog_s)
             continue;
         bool same = true;
         for (int s = 0; s < nsys && same; ++s)
@@ -1313,6 +1318,7 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
         P->max_iter = o.max_iter;
         P->blocks_per_cu = bpc;
         P->items_per_block = g_batch_ipb;
+        P->watchdog_s = g_batch_watchdog_s;
         if ((rc = build_plan(P, stream))) {
             free_plan(P);
             return rc;
@@ -1356,7 +1362,8 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
     HIP_TRY(hipMemcpy(&err, P->derr, sizeof(int), hipMemcpyDeviceToHost));
     if (err) {
         HIP_TRY(hipMemset(P->derr, 0, sizeof(int)));
-        return fail(MFFV_EHIP, "batched CG: a per-system barrier wait expired (blocks not co-resident?)");
+        return fail(MFFV_EHIP, "batched CG: a per-system wait (barrier or partial-sum exchange) exceeded the "
+                                "watchdog limit (blocks not co-resident?)");
     }
     int status = MFFV_OK;
     for (int s = 0; s < nsys; ++s) {
@@ -1702,6 +1709,14 @@ int mffv_set_batched_launch(int blocks_per_cu, int items_per_block) {
     std::lock_guard<std::mutex> lk(g_plans_mu);
     g_batch_bpc = blocks_per_cu;
     g_batch_ipb = items_per_block;
+    return MFFV_OK;
+}
+
+int mffv_set_batched_watchdog(double seconds) {
+    if (!(seconds >= 0.0 && seconds <= 3600.0))
+        return fail(MFFV_EINVAL, "the batched watchdog limit must be in [0, 3600] seconds");
+    std::lock_guard<std::mutex> lk(g_plans_mu);
+    g_batch_watchdog_s = seconds;
     return MFFV_OK;
 }
 

@@ -11,6 +11,8 @@
 // Barriers spin on agent-scope atomics with a wall-clock watchdog: a block
 // that waits longer than the limit records an error and leaves, so a launch
 // whose blocks are not all resident ends with an error instead of hanging.
+// A limit of 0 makes every wait that is not satisfied at once fail (the
+// failure path can then be tested with kernels that all exit normally).
 #include "launch.hpp"
 
 namespace mffv {
@@ -33,7 +35,7 @@ __device__ __forceinline__ bool sys_barrier(unsigned* bar, unsigned nblk, uint64
                 const uint64_t t0 = wall_clock64();
                 while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
                     __builtin_amdgcn_s_sleep(1);
-                    if (wall_clock64() - t0 > limit_ticks) {
+                    if (limit_ticks == 0 || wall_clock64() - t0 > limit_ticks) {
                         ok = 0;
                         atomicOr(err, 1);
                         break;
@@ -75,7 +77,7 @@ __device__ __forceinline__ bool exchange_sum(unsigned long long* xch, int t, int
             w = __hip_atomic_load(&xch[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if ((unsigned)(w >> 32) == tag) break;
             __builtin_amdgcn_s_sleep(1);
-            if (wall_clock64() - t0 > limit_ticks) {
+            if (limit_ticks == 0 || wall_clock64() - t0 > limit_ticks) {
                 mine = false;
                 break;
             }

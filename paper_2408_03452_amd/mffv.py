@@ -108,6 +108,7 @@ def _declare(lib):
         "mffv_set_launch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
         "mffv_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.POINTER(TuneResult)]),
         "mffv_set_batched_launch": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+        "mffv_set_batched_watchdog": (ctypes.c_int, [ctypes.c_double]),
         "mffv_autotune_batched": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int,
                                                  ctypes.POINTER(_P), ctypes.POINTER(_P),
                                                  ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_int),
@@ -305,6 +306,11 @@ def autotune(grid: Grid, cache_path: str | None = None) -> dict:
 
 def set_batched_launch(blocks_per_cu: int, items_per_block: int) -> None:
     _check(lib().mffv_set_batched_launch(blocks_per_cu, items_per_block))
+
+
+def set_batched_watchdog(seconds: float) -> None:
+    """Limit of one per-system wait of the batched kernel (0: fail at once)."""
+    _check(lib().mffv_set_batched_watchdog(float(seconds)))
 
 
 def autotune_batched(grids, b, x, opts: Opts | None = None) -> dict:

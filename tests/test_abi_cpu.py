@@ -64,6 +64,10 @@ def test_argument_errors_before_any_gpu_work(mf):
     assert L.mffv_perm_to_trans(4, 4, 4, 16, -1.0, 32, 48, 64, None) == mf.EINVAL
     assert L.mffv_copy_probe(16, 32, 17, None) == mf.EINVAL
     assert L.mffv_cg_solve_batched(None, 0, None, None, None, None) == mf.EINVAL
+    assert L.mffv_set_batched_launch(-1, 4) == mf.EINVAL
+    assert L.mffv_set_batched_watchdog(-1.0) == mf.EINVAL
+    assert L.mffv_set_batched_watchdog(float("nan")) == mf.EINVAL
+    assert L.mffv_set_batched_watchdog(2.0) == mf.OK       # the default again
     L.mffv_destroy_grid(None)  # no-op
 
 

@@ -165,3 +165,33 @@ def test_batched_single_reduction_matches_oracle_and_two_phase(mf):
         assert abs(ia["iters"] - ib["iters"]) <= max(3, ib["iters"] // 20), (shape, ia["iters"], ib["iters"])
         assert np.linalg.norm(xa - xb) <= 5e-5 * np.linalg.norm(p), shape
         assert np.array_equal(xa.reshape(shape)[0], np.ones(shape[1:]))   # Dirichlet values
+
+
+def test_batched_watchdog_reports_and_recovers(mf):
+    """With a watchdog limit of 0 every per-system wait that is not satisfied at
+    once fails: the blocks record the error and leave (every kernel exits
+    normally), and the solve reports it. The same batch then solves correctly
+    with the default limit."""
+    systems = small_batch(11, n=3)
+    systems[0] = ((24, 20, 18), lognormal_iid((24, 20, 18), 1.5, 7), 1e-3)   # several blocks
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        probs = [gpu_problem(mf, k, c=c, stream=s) for _, k, c in systems]
+        grids = [p[0] for p in probs]
+        bs = [p[2] for p in probs]
+        xs = [torch.zeros(k.size, dtype=torch.float32, device="cuda") for _, k, _ in systems]
+        try:
+            mf.set_batched_watchdog(0.0)
+            with pytest.raises(mf.MffvError) as err:
+                mf.cg_solve_batched(grids, bs, xs, mf.default_opts(tol=1e-6))
+            assert "barrier" in str(err.value) or "wait" in str(err.value)
+        finally:
+            mf.set_batched_watchdog(2.0)
+        for x in xs:
+            x.zero_()
+        st, infos = mf.cg_solve_batched(grids, bs, xs, mf.default_opts(tol=1e-6))
+    torch.cuda.synchronize()
+    assert st == mf.OK
+    for (shape, k, c), x in zip(systems, xs):
+        p = OracleProblem(k, c=c).direct()
+        assert np.linalg.norm(host(x) - p) <= 5e-5 * np.linalg.norm(p), shape
