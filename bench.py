@@ -35,9 +35,27 @@ HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published peak
 # accumulation itself away from the Dirichlet planes and is not a per-cell
 # stream: the kernels read it only on the four planes at the ends.
 APPLY_BYTES_PER_CELL = 20       # x, Tx, Ty, Tz read; y written
-CG_BYTES_PER_CELL_ITER = 48     # fused phase A (36) + phase B (12)
-PHASE_A_BYTES_PER_CELL = 36     # r, p_old, x, Tx, Ty, Tz read; p, q, x written
+CG_BYTES_PER_CELL_ITER = 46     # fused phase A (34 on average) + phase B (12)
 PHASE_B_BYTES_PER_CELL = 12     # r, q read; r written
+
+
+def phase_a_bytes(k: int) -> int:
+    """Algorithmic bytes per cell of phase A of iteration k. It reads r and the
+    faces Tx, Ty, Tz and writes p and q; from k = 1 on it also reads p_{k-1};
+    on even k >= 2 it applies two deferred solution steps, reading x and
+    p_{k-2} and writing x."""
+    if k == 0:
+        return 24
+    return 40 if k % 2 == 0 else 28
+
+
+def phase_a_bytes_mean(iters: int) -> float:
+    """Mean algorithmic bytes per cell over the phase-A launches of iterations 0..iters-1."""
+    iters = max(1, int(iters))
+    return sum(phase_a_bytes(k) for k in range(iters)) / iters
+
+
+PHASE_A_BYTES_PER_CELL = 34     # steady-state mean of phase_a_bytes over two iterations
 MERGED_BYTES_PER_CELL = 44      # single-reduction iteration: r, q, p, x, Tx, Ty, Tz read;
                                 # r, p, q, x written
 METRIC = "time to rel-resid 1e-6 (learned FCG vs plain CG); stencil-apply HBM GB/s"
@@ -50,11 +68,11 @@ LAUNCH_KEYS = ("ci", "remap", "seg", "vec", "blocks", "apply_ci", "apply_remap",
 TRAFFIC = {
     "two_phase": {
         "profile": "profiles/stencil_cg_phase_a_lognormal_corr8_256cube_hbm_traffic.md",
-        "by_launch": [
-            ({"ci": 8, "remap": 0, "seg": -1}, 723725273),
-            ({"ci": 8, "remap": 1, "seg": -1}, 689172501),
-            ({"ci": 16, "remap": 0, "seg": -1}, 703661484),
-            ({"ci": 16, "remap": 1, "seg": -1}, 677122137),
+        "by_launch": [            # mean over the phase-A launches of a 64-iteration solve
+            ({"ci": 8, "remap": 0, "seg": -1}, 689158750),
+            ({"ci": 8, "remap": 1, "seg": -1}, 653083314),
+            ({"ci": 16, "remap": 0, "seg": -1}, 669059721),
+            ({"ci": 16, "remap": 1, "seg": -1}, 642284444),
         ],
     },
     "single_reduction": None,
@@ -152,10 +170,11 @@ def bench_large(log_fn, solve: bool, cg_iters: int = 200):
         out["apply_GBps"] = APPLY_BYTES_PER_CELL * n / (apply_us * 1e-6) / 1e9
         x = torch.zeros(n, dtype=torch.float32, device=dev)
         st, info = mffv.cg_solve(g, b, x, mffv.default_opts(tol=1e-30, max_iter=cg_iters, timing=1))
-        bpc = MERGED_BYTES_PER_CELL if info["single_reduction"] else PHASE_A_BYTES_PER_CELL
+        bpc = MERGED_BYTES_PER_CELL if info["single_reduction"] else phase_a_bytes_mean(info["timed_iters"])
         out["single_reduction"] = info["single_reduction"] == 1
         out["iter_kernel_us"] = info["phase_a_us"]
         out["iter_kernel_GBps"] = bpc * n / (info["phase_a_us"] * 1e-6) / 1e9
+        out["iter_kernel_bytes_per_cell"] = bpc
         out["phase_b_us"] = info["phase_b_us"]
         x.zero_()
         torch.cuda.synchronize()
@@ -512,7 +531,7 @@ def main(argv=None):
             tol=w.tol, precision=mffv.FP32_IR, check_every=16, use_graph=1, timing=1))
         merged = tinfo["single_reduction"] == 1
         dom_us = tinfo["phase_a_us"]
-        dom_bytes = MERGED_BYTES_PER_CELL if merged else PHASE_A_BYTES_PER_CELL
+        dom_bytes = MERGED_BYTES_PER_CELL if merged else phase_a_bytes_mean(tinfo["timed_iters"])
         dom_gbps = dom_bytes * n / (dom_us * 1e-6) / 1e9
         log(f"{'single-reduction iteration' if merged else 'phase A'}: {dom_us:.1f} us/launch "
             f"({dom_gbps:.0f} GB/s algorithmic), over {tinfo['timed_iters']} iterations")
@@ -529,7 +548,7 @@ def main(argv=None):
                     single_reduction=sr))
             forms[sr] = tf
         phase_a_us, phase_b_us = forms[0]["phase_a_us"], forms[0]["phase_b_us"]
-        phase_a_gbps = PHASE_A_BYTES_PER_CELL * n / (phase_a_us * 1e-6) / 1e9
+        phase_a_gbps = phase_a_bytes_mean(forms[0]["timed_iters"]) * n / (phase_a_us * 1e-6) / 1e9
         phase_b_gbps = PHASE_B_BYTES_PER_CELL * n / (phase_b_us * 1e-6) / 1e9
         merged_us = forms[1]["phase_a_us"]
         merged_gbps = MERGED_BYTES_PER_CELL * n / (merged_us * 1e-6) / 1e9

@@ -70,7 +70,7 @@ struct CgState {
     int done;         // 1 once converged, broken down or out of iterations
     int status;       // 0 ok, 1 not converged, -4 breakdown
     int iters;        // completed iterations at exit
-    int tail;         // 1 if x still lacks alpha_{iters-1} p_{iters-1} at exit
+    int tail;         // steps x lacks at exit: 1 (alpha_{iters-1} p_{iters-1}) or 2 (and alpha_{iters-2} p_{iters-2})
     int max_iter;
     int fallback;     // flexible CG: iteration iterA uses the Jacobi z
     int fallbacks;    // flexible CG: count of such iterations

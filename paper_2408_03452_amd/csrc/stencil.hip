@@ -86,6 +86,7 @@ struct PhaseA {
     int k;
     real beta;        // beta_{k-1}
     real alpha_prev;  // alpha_{k-1}: the deferred solution update
+    real alpha_prev2; // alpha_{k-2}: with it, on even k >= 2 (see phase A below)
     bool fallback;    // flexible CG: this iteration uses z = r / diag(A)
 };
 
@@ -122,7 +123,9 @@ __device__ bool phase_a_start(const StencilIO<real>& io, real* lds, PhaseA<real>
             st->done = 1;
             st->status = conv ? 0 : (bad ? -4 : 1);
             st->iters = k;
-            st->tail = k >= 1 ? 1 : 0;
+            // x holds the steps up to the last even k' <= k - 1: one step
+            // owed for odd k, two for even k >= 2
+            st->tail = k == 0 ? 0 : ((k & 1) ? 1 : 2);
             st->rr = rr;
             if (k == 0) {
                 st->thresh2 = thresh2;
@@ -134,6 +137,7 @@ __device__ bool phase_a_start(const StencilIO<real>& io, real* lds, PhaseA<real>
     o.k = k;
     o.fallback = fallback;
     o.alpha_prev = k >= 1 ? st->alpha[(k - 1) & 1] : real(0);
+    o.alpha_prev2 = k >= 2 ? st->alpha[k & 1] : real(0);  // phase B_k has not written it yet
     o.beta = k == 0 ? real(0)
                     : (io.precond == 2 ? -zq / st->pq[(k - 1) & 1] : rho / st->rho[(k - 1) & 1]);
     if (first_thread()) {
@@ -239,7 +243,7 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
     __shared__ float4 lty[2][kThreads];
 
     constexpr bool kCg = MODE == kFusedCg || MODE == kMergedCg;
-    PhaseA<float> ph{0, 0.f, 0.f, false};
+    PhaseA<float> ph{0, 0.f, 0.f, 0.f, false};
     if (MODE == kFusedCg && !phase_a_start(io, red, ph)) return;
     if (MODE == kMergedCg) {
         // r_K = r_{K-1} - alpha q_{K-1} on the fly, then the same direction
@@ -251,8 +255,14 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
         ph.alpha_prev = mp.alpha;
     }
     const int it = ph.k;
-    const float beta = ph.beta, alpha_prev = ph.alpha_prev;
-    const bool pending = it > 0;
+    const float beta = ph.beta, alpha_prev = ph.alpha_prev, alpha_prev2 = ph.alpha_prev2;
+    // Deferred solution update. The single-reduction kernel applies
+    // alpha_{k-1} p_{k-1} every iteration. The two-phase CG applies two steps on
+    // even k >= 2, x += alpha_{k-2} p_{k-2} + alpha_{k-1} p_{k-1}, and none on odd
+    // k: x is read and written every other iteration (p_{k-2} is read at the own
+    // cell from the buffer p_k is about to replace). The finalize kernel adds
+    // what is owed when the loop stops.
+    const bool pending = MODE == kMergedCg ? it > 0 : (it >= 2 && (it & 1) == 0);
     const float* pold = MODE == kMergedCg ? io.pin : ((it & 1) ? io.p0 : io.p1);
     float* pnew = MODE == kMergedCg ? io.pout : ((it & 1) ? io.p1 : io.p0);
     const bool use_pold = kCg && it > 0;
@@ -409,9 +419,13 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
             if (MODE == kApply) {
                 st4(io.out + base, y);
             } else if (kCg) {
+                if (pending) {
+                    float4 xv = axpy4(alpha_prev, poc, ld4(io.xsol + base));
+                    if (MODE == kFusedCg) xv = axpy4(alpha_prev2, ld4(pnew + base), xv);
+                    st4(io.xsol + base, xv);
+                }
                 st4(pnew + base, sc);
                 st4(io.out + base, y);
-                if (pending) st4(io.xsol + base, axpy4(alpha_prev, poc, ld4(io.xsol + base)));
                 dot += sc.x * y.x + sc.y * y.y + sc.z * y.z + sc.w * y.w;
                 if (MODE == kMergedCg) {
                     st4(io.rout + base, zc);
@@ -460,11 +474,12 @@ template <class real, int MODE>
 __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<real> io, March m) {
     __shared__ real red[kThreads / kWave];
 
-    PhaseA<real> ph{0, real(0), real(0), false};
+    PhaseA<real> ph{0, real(0), real(0), real(0), false};
     if (MODE == kFusedCg && !phase_a_start(io, red, ph)) return;
     const int it = ph.k;
-    const real beta = ph.beta, alpha_prev = ph.alpha_prev;
-    const bool pending = it > 0;
+    const real beta = ph.beta, alpha_prev = ph.alpha_prev, alpha_prev2 = ph.alpha_prev2;
+    // two deferred steps on even k >= 2, as in the four-cells-per-thread kernel
+    const bool pending = it >= 2 && (it & 1) == 0;
     const real* pold = (it & 1) ? io.p0 : io.p1;
     real* pnew = (it & 1) ? io.p1 : io.p0;
     const bool use_pold = (MODE == kFusedCg) && it > 0;
@@ -538,9 +553,9 @@ __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<
             if (MODE == kApply) {
                 io.out[base] = y;
             } else if (MODE == kFusedCg) {
+                if (pending) io.xsol[base] += alpha_prev2 * pnew[base] + alpha_prev * poc;
                 pnew[base] = sc;
                 io.out[base] = y;
-                if (pending) io.xsol[base] += alpha_prev * poc;
                 dot += sc * y;
             } else {
                 const real bb = io.rhs_f64 ? (real) static_cast<const double*>(io.rhs)[base]

@@ -48,7 +48,9 @@ __global__ __launch_bounds__(kThreads) void phase_b(int64_t n, VecIO<real> io) {
                 st->done = 1;
                 st->status = -4;
                 st->iters = k;
-                st->tail = 0;
+                // x_k lacks alpha_{k-1} p_{k-1} when k is odd (phase A applies
+                // steps on even k only)
+                st->tail = (k & 1) ? 1 : 0;
             }
             return;
         }
@@ -158,17 +160,22 @@ __global__ __launch_bounds__(kThreads) void flex_dots(int64_t n, VecIO<real> io)
     }
 }
 
-// x += alpha_{K-1} p_{K-1} after the loop stopped at K iterations, if owed.
+// The steps owed when the loop stopped at K iterations: x += alpha_{K-1}
+// p_{K-1} (tail 1), and also alpha_{K-2} p_{K-2} (tail 2). p_j is in p1 for odd
+// j and p0 for even j; the loop left both.
 template <class real>
 __global__ void finalize(int64_t n, real* x, const real* p0, const real* p1,
                          const CgState<real>* st) {
-    if (!st->tail) return;
+    const int tail = st->tail;
+    if (!tail) return;
     const int K = st->iters;
-    const real* p = ((K - 1) & 1) ? p1 : p0;
+    const real* pa = ((K - 1) & 1) ? p1 : p0;
     const real a = st->alpha[(K - 1) & 1];
+    const real* pb = ((K - 2) & 1) ? p1 : p0;
+    const real b = tail == 2 ? st->alpha[(K - 2) & 1] : real(0);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
-        x[e] += a * p[e];
+        x[e] += tail == 2 ? b * pb[e] + a * pa[e] : a * pa[e];
 }
 
 // Training pair of the learned preconditioner in the Jacobi-scaled space from
