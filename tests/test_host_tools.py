@@ -85,3 +85,14 @@ def test_bench_refuses_more_than_one_gpu():
                          capture_output=True, text=True, timeout=120)
     assert res.returncode != 0
     assert "one GPU" in (res.stdout + res.stderr)
+
+
+def test_bench_phase_a_byte_model():
+    """Phase A moves 24 B/cell at k = 0 (r, faces in; p, q out), 28 on odd k
+    (also p_{k-1} in) and 40 on even k >= 2 (also x and p_{k-2} in, x out)."""
+    import bench
+    assert [bench.phase_a_bytes(k) for k in range(5)] == [24, 28, 40, 28, 40]
+    assert bench.phase_a_bytes_mean(32) == 33.5
+    assert bench.phase_a_bytes_mean(64) == 33.75
+    assert bench.PHASE_A_BYTES_PER_CELL == (28 + 40) / 2
+    assert bench.CG_BYTES_PER_CELL_ITER == bench.PHASE_A_BYTES_PER_CELL + bench.PHASE_B_BYTES_PER_CELL
