@@ -97,6 +97,15 @@ typedef struct {
     int timing;          /* 1 (mffv_cg_solve, FP32 or FP32_IR): time each kernel of the first
                             32 FP32 CG iterations with HIP events (no graph replay, same
                             arithmetic); means returned in mffv_info                      */
+    int async;           /* 1: capture-safe, no host synchronisation. mffv_cg_solve_batched
+                            (and mffv_cg_solve, which then runs the persistent solver on its
+                            one system; precision MFFV_FP32, precond NONE or JACOBI) only
+                            enqueue work on the stream; info, if not NULL, is a DEVICE
+                            array (one mffv_info per system) written when the stream
+                            reaches it, with status MFFV_EHIP if a wait of the persistent
+                            kernel expired. The first call with a given set of arguments
+                            allocates the solver's plan: under stream capture it returns
+                            MFFV_EINVAL, so make it once outside capture.               */
 } mffv_opts;
 
 typedef struct {
@@ -207,6 +216,9 @@ int mffv_true_residual(mffv_grid* grid, const float* b, const double* x, double*
  * Synchronizes the stream. Returns MFFV_OK when the target was met (on the
  * recursive residual for MFFV_FP32 and MFFV_FP64, on the FP64 true residual
  * for MFFV_FP32_IR), MFFV_NOT_CONVERGED when max_iter was reached, or an error.
+ * With opts->async = 1 (MFFV_FP32, precond NONE or JACOBI) the solve runs in
+ * the persistent kernel of mffv_cg_solve_batched on this one system: nothing
+ * is synchronized and info is a device pointer (see mffv_opts).
  */
 int mffv_cg_solve(mffv_grid* grid, const float* b, float* x, const mffv_opts* opts,
                   mffv_info* info);
@@ -228,7 +240,9 @@ int mffv_cg_solve_f64(mffv_grid* grid, const double* b, double* x, const mffv_op
  * All handles must share the device and stream of grids[0]. info (host, nsys
  * entries) may be NULL. opts->precond may be NONE or JACOBI; precision is FP32.
  * Synchronizes the stream. Returns MFFV_OK if every system converged,
- * MFFV_NOT_CONVERGED if any did not, or an error.
+ * MFFV_NOT_CONVERGED if any did not, or an error. With opts->async = 1 it
+ * only enqueues the solve (capture-safe once the plan exists, see mffv_opts),
+ * info is a device array, and the return value only reports argument errors.
  */
 int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const* b,
                           float* const* x, const mffv_opts* opts, mffv_info* info);

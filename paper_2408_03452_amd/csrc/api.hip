@@ -645,6 +645,7 @@ int validate_opts(const mffv_opts& o) {
         return fail(MFFV_EINVAL, "FP64 CG supports precond NONE only");
     if (o.single_reduction != 0 && o.single_reduction != 1)
         return fail(MFFV_EINVAL, "opts.single_reduction must be 0 or 1");
+    if (o.async != 0 && o.async != 1) return fail(MFFV_EINVAL, "opts.async must be 0 or 1");
     if (o.nn_every < 1 || o.nn_every > 64)
         return fail(MFFV_EINVAL, "opts.nn_every must be in [1, 64]");
     return MFFV_OK;
@@ -881,11 +882,30 @@ int build_plan(BatchPlan* P, hipStream_t stream) {
     return MFFV_OK;
 }
 
+// Per-system results of an asynchronous batched solve, written into the
+// caller's device array of mffv_info (the same fields the synchronous call
+// fills on the host, without the timing).
+__global__ void batch_info(int ns, const BatchResult* res, const double* r64, const int* err, int merged,
+                           mffv_info* out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ns) return;
+    const BatchResult R = res[s];
+    mffv_info I{};
+    I.status = *err ? MFFV_EHIP
+                    : (R.status == 0 ? MFFV_OK : (R.status == 1 ? MFFV_NOT_CONVERGED : MFFV_EBREAKDOWN));
+    I.iters = R.iters;
+    I.ir_steps = 1;
+    I.rel_res_recursive = R.bnorm2 > 0.f ? sqrt((double)R.rr / (double)R.bnorm2) : 0.0;
+    I.rel_res_true = r64[2 * s] > 0 ? sqrt(r64[2 * s + 1] / r64[2 * s]) : sqrt(r64[2 * s + 1]);
+    I.single_reduction = merged;
+    out[s] = I;
+}
+
 // Enqueue the whole batch: persistent CG, then each system's FP64 residual.
 int enqueue_batch(BatchPlan* P, hipStream_t stream) {
     // barrier words of every system, then the 64-bit exchange slot of every block
     HIP_TRY(launch_batched_cg(P->dsys, P->dblock_sys, P->nblocks, P->dbars,
-                              2 * (int)P->grids.size() + 2 * P->nblocks, P->run, stream));
+                              2 * (int)P->grids.size() + 2 * P->nblocks, P->derr, P->run, stream));
     for (size_t s = 0; s < P->grids.size(); ++s) {
         mffv_grid* G = P->grids[s];
         HIP_TRY(launch_convert_f32_to_f64(G->g.n, P->x[s], G->x64, stream));
@@ -995,6 +1015,7 @@ void mffv_default_opts(mffv_opts* o) {
     o->use_graph = 1;
     o->net = nullptr;
     o->timing = 0;
+    o->async = 0;
     o->single_reduction = 0;
     o->nn_every = 1;
 }
@@ -1171,6 +1192,15 @@ int mffv_cg_solve(mffv_grid* G, const float* b, float* x, const mffv_opts* opts,
     if (b == x) return fail(MFFV_EINVAL, "b and x must not alias");
     mffv_opts o = resolve_opts(opts);
     if ((rc = validate_opts(o))) return rc;
+    if (o.async) {
+        // no host synchronisation: the whole solve runs in the persistent kernel
+        if (o.precision != MFFV_FP32 || o.precond == MFFV_PRECOND_LEARNED)
+            return fail(MFFV_EINVAL, "opts.async needs precision MFFV_FP32 and precond NONE or JACOBI");
+        mffv_grid* const gs[1] = {G};
+        const float* const bs[1] = {b};
+        float* const xs[1] = {x};
+        return mffv_cg_solve_batched(gs, 1, bs, xs, &o, info);
+    }
     if ((rc = set_device(G)) || (rc = ensure_ws32(G))) return rc;
     mffv_info inf{};
     const int64_t n = G->g.n;
@@ -1308,6 +1338,12 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
         if (same) { P = c; break; }
     }
     if (!P) {
+        // building a plan allocates, which stream capture does not allow
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (o.async && stream && hipStreamIsCapturing(stream, &cs) == hipSuccess &&
+            cs != hipStreamCaptureStatusNone)
+            return fail(MFFV_EINVAL, "the first batched solve with these arguments allocates its plan: make it "
+                                     "outside stream capture");
         P = new BatchPlan();
         P->grids.assign(grids, grids + nsys);
         P->b.assign(b, b + nsys);
@@ -1328,6 +1364,16 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
             g_plans.erase(g_plans.begin());
         }
         g_plans.push_back(P);
+    }
+    if (o.async) {
+        // capture-safe: kernels only, no host synchronisation; info is device memory
+        if ((rc = enqueue_batch(P, stream))) return rc;
+        if (info) {
+            hipLaunchKernelGGL(batch_info, dim3((nsys + 255) / 256), dim3(256), 0, stream, nsys, P->dres,
+                               P->dres64, P->derr, P->merged, info);
+            HIP_TRY(hipGetLastError());
+        }
+        return MFFV_OK;
     }
     const bool use_graph = o.use_graph && stream != nullptr;
     if (use_graph && !P->exec) {

@@ -625,8 +625,10 @@ __global__ __launch_bounds__(kThreads) void batched_cg(const BatchSys* __restric
     }
 }
 
-__global__ void clear_barriers(unsigned* bars, int n) {
+// Start of a launch: barrier words, exchange slots and the watchdog flag to 0.
+__global__ void clear_barriers(unsigned* bars, int n, int* err) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) bars[i] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *err = 0;
 }
 
 }  // namespace
@@ -639,8 +641,8 @@ int batched_blocks_per_cu() {
 }
 
 hipError_t launch_batched_cg(const BatchSys* systems, const int* block_sys, int nblocks,
-                             unsigned* bars, int nbars, const BatchRun& run, hipStream_t s) {
-    hipLaunchKernelGGL(clear_barriers, dim3(1), dim3(256), 0, s, bars, nbars);
+                             unsigned* bars, int nbars, int* err, const BatchRun& run, hipStream_t s) {
+    hipLaunchKernelGGL(clear_barriers, dim3(1), dim3(256), 0, s, bars, nbars, err);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(batched_cg, dim3(nblocks), dim3(kThreads), 0, s, systems, block_sys, run);

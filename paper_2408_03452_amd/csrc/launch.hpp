@@ -169,7 +169,7 @@ struct BatchRun {
 
 int batched_blocks_per_cu();
 hipError_t launch_batched_cg(const BatchSys* systems, const int* block_sys, int nblocks,
-                             unsigned* bars, int nbars, const BatchRun& run, hipStream_t s);
+                             unsigned* bars, int nbars, int* err, const BatchRun& run, hipStream_t s);
 
 // Operator set-up.
 hipError_t launch_perm_to_trans(const Geom& g, const double* k, double kz_ratio, float* tx,

@@ -40,7 +40,8 @@ class Opts(ctypes.Structure):
                 ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("net", ctypes.c_void_p), ("single_reduction", ctypes.c_int),
-                ("nn_every", ctypes.c_int), ("timing", ctypes.c_int)]
+                ("nn_every", ctypes.c_int), ("timing", ctypes.c_int),
+                ("async_", ctypes.c_int)]   # mffv_opts.async (a Python keyword)
 
 
 class TuneResult(ctypes.Structure):
@@ -85,12 +86,13 @@ def _declare(lib):
         "mffv_apply": (ctypes.c_int, [_P, _P, _P]),
         "mffv_apply_f64": (ctypes.c_int, [_P, _P, _P]),
         "mffv_true_residual": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
-        "mffv_cg_solve": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(Opts), ctypes.POINTER(Info)]),
+        # info: a host mffv_info (array) or, with opts.async, a device array
+        "mffv_cg_solve": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(Opts), _P]),
         "mffv_cg_solve_f64": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(Opts),
                                              ctypes.POINTER(Info)]),
         "mffv_cg_solve_batched": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int,
                                                  ctypes.POINTER(_P), ctypes.POINTER(_P),
-                                                 ctypes.POINTER(Opts), ctypes.POINTER(Info)]),
+                                                 ctypes.POINTER(Opts), _P]),
         "mffv_copy_probe": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
         "mffv_net_num_params": (ctypes.c_int, []),
         "mffv_net_create": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
@@ -260,12 +262,31 @@ def true_residual(grid: Grid, b, x, r_out=None) -> float:
     return rel.value
 
 
+def _device_infos(ns: int, like):
+    """A device array of ns mffv_info structs (for opts.async_)."""
+    return torch.zeros(ns * ctypes.sizeof(Info), dtype=torch.uint8, device=like.device)
+
+
+def infos_from_device(arr) -> list:
+    """Read the device mffv_info array of an asynchronous solve (synchronizes)."""
+    host = arr.detach().cpu().numpy().tobytes()
+    size = ctypes.sizeof(Info)
+    return [Info.from_buffer_copy(host[i * size:(i + 1) * size]).as_dict() for i in range(len(host) // size)]
+
+
 def cg_solve(grid: Grid, b, x, opts: Opts | None = None):
-    """Returns (status, info dict); raises MffvError on errors."""
+    """Returns (status, info dict); raises MffvError on errors. With
+    ``opts.async_`` the solve is only enqueued (capture-safe once its plan
+    exists) and the second item is a device array for infos_from_device."""
+    bp = _ptr(b, torch.float32, grid.n, "b")
+    xp = _ptr(x, torch.float32, grid.n, "x")
+    if opts is not None and opts.async_:
+        dinfo = _device_infos(1, x)
+        rc = lib().mffv_cg_solve(grid.handle, bp, xp, ctypes.byref(opts), dinfo.data_ptr())
+        return _check(rc), dinfo
     info = Info()
-    rc = lib().mffv_cg_solve(grid.handle, _ptr(b, torch.float32, grid.n, "b"),
-                             _ptr(x, torch.float32, grid.n, "x"),
-                             ctypes.byref(opts) if opts is not None else None, ctypes.byref(info))
+    rc = lib().mffv_cg_solve(grid.handle, bp, xp, ctypes.byref(opts) if opts is not None else None,
+                             ctypes.addressof(info))
     return _check(rc), info.as_dict()
 
 
@@ -286,9 +307,14 @@ def cg_solve_batched(grids, b, x, opts: Opts | None = None):
     G = (_P * ns)(*[g.handle for g in grids])
     B = (_P * ns)(*[_ptr(bb, torch.float32, g.n, "b") for bb, g in zip(b, grids)])
     X = (_P * ns)(*[_ptr(xx, torch.float32, g.n, "x") for xx, g in zip(x, grids)])
+    if opts is not None and opts.async_:
+        # only enqueued: the infos land in device memory (read with infos_from_device)
+        dinfo = _device_infos(ns, x[0])
+        rc = lib().mffv_cg_solve_batched(G, ns, B, X, ctypes.byref(opts), dinfo.data_ptr())
+        return _check(rc), dinfo
     infos = (Info * ns)()
     rc = lib().mffv_cg_solve_batched(G, ns, B, X, ctypes.byref(opts) if opts is not None else None,
-                                     infos)
+                                     ctypes.addressof(infos))
     return _check(rc), [i.as_dict() for i in infos]
 
 
