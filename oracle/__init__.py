@@ -14,8 +14,10 @@ SciPy's CSR product as the only library step. Modules:
 * ``krylov`` -- CG, Jacobi-PCG, flexible CG, mixed-precision iterative refinement.
 * ``nn``     -- direct 3D convolution network (forward, backward, Adam) in FP64
                on BF16-rounded operands, for the learned preconditioner.
+* ``timestep`` -- backward-Euler time steps with storage and wells, each solved
+               directly (a step's residual is linear, one Newton step).
 
 Each function is pinned by CPU tests against closed forms, invariants, dense
 solves and brute force (``tests/test_oracle_*.py``).
 """
-from . import tpfa, krylov  # noqa: F401
+from . import tpfa, krylov, timestep  # noqa: F401
