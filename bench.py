@@ -37,6 +37,7 @@ HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published peak
 APPLY_BYTES_PER_CELL = 20       # x, Tx, Ty, Tz read; y written
 CG_BYTES_PER_CELL_ITER = 46     # fused phase A (34 on average) + phase B (12)
 PHASE_B_BYTES_PER_CELL = 12     # r, q read; r written
+STEP_RHS_BYTES_PER_CELL = 21    # b, p_old, WI, pw (4 B each) and the Dirichlet mask (1 B) read; rhs written
 
 
 def phase_a_bytes(k: int) -> int:
@@ -219,6 +220,88 @@ def bench_large(log_fn, solve: bool, cg_iters: int = 200):
         g.close()
     torch.cuda.synchronize()
     return out
+
+
+def bench_time_steps(log_fn, shape, tx, ty, tz, nsteps: int = 8):
+    """Backward-Euler time steps with wells on the headline grid and field:
+    storage c = 2^-7 per cell, an injector column (pw = 2) and a producer
+    column (pw = -1) with well index 1 (Peaceman form, so the operator's
+    accumulation is c + WI), the x-plane Dirichlet planes at 1 and 0. Each
+    step solves from the previous pressure to a true relative residual of 1e-6
+    (FP32 CG + FP64 refinement). The mass balance of one more step is checked
+    from the fields in FP64; the right-hand-side kernel is timed with HIP
+    events."""
+    import numpy as np
+    import torch
+    from paper_2408_03452_amd import mffv
+
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    c = 2.0 ** -7
+    wi = np.zeros(shape, dtype=np.float32)
+    pw = np.zeros(shape, dtype=np.float32)
+    inj, prod = (nx // 4, ny // 4), (3 * nx // 4, 3 * ny // 4)
+    wi[inj[0], inj[1], :] = wi[prod[0], prod[1], :] = 1.0
+    pw[inj[0], inj[1], :], pw[prod[0], prod[1], :] = 2.0, -1.0
+    dev = torch.device("cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        wi_t, pw_t = (torch.from_numpy(a.ravel()).to(dev) for a in (wi, pw))
+        b = torch.empty(n, dtype=torch.float32, device=dev)
+        g = mffv.create_grid(nx, ny, nz, stream=s)
+        mffv.set_transmissibility(g, tx, ty, tz, accum=wi_t + c, b_out=b)
+        mffv.autotune(g, None)
+        opts = mffv.default_opts(tol=1e-6, precision=mffv.FP32_IR, check_every=16, use_graph=1)
+        p0 = torch.zeros(n, dtype=torch.float32, device=dev)
+        p0.view(nx, ny * nz)[0] = 1.0
+        p = p0.clone()
+        mffv.time_steps(g, 1, b, p, c_scalar=c, wi=wi_t, pw=pw_t, opts=opts)   # warmup
+        p.copy_(p0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, infos = mffv.time_steps(g, nsteps, b, p, c_scalar=c, wi=wi_t, pw=pw_t, opts=opts)
+        torch.cuda.synchronize()
+        ms_step = (time.perf_counter() - t0) * 1e3 / nsteps
+        if st != mffv.OK:
+            raise RuntimeError(f"time steps did not converge: {infos}")
+        p_prev = p.clone()
+        mffv.time_steps(g, 1, b, p, c_scalar=c, wi=wi_t, pw=pw_t, opts=opts)
+        # right-hand-side kernel: b, p_old, wi, pw and the Dirichlet mask in, rhs out
+        rhs = torch.empty_like(b)
+        for _ in range(3):
+            mffv.step_rhs(g, b, p_prev, rhs, c_scalar=c, wi=wi_t, pw=pw_t)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(50):
+            mffv.step_rhs(g, b, p_prev, rhs, c_scalar=c, wi=wi_t, pw=pw_t)
+        e1.record(s)
+        e1.synchronize()
+        rhs_us = e0.elapsed_time(e1) * 1e3 / 50
+        p0h, p1h = (t.cpu().numpy().astype(np.float64).reshape(shape) for t in (p_prev, p))
+        T = [t.cpu().numpy().astype(np.float64).reshape(shape) for t in (tx, ty, tz)]
+        g.close()
+    # mass balance of the last step: storage change against sources, wells and
+    # the flow across the Dirichlet planes (interior fluxes cancel pairwise)
+    u = np.ones(shape, dtype=bool)
+    u[0] = u[-1] = False
+    storage = c * np.sum((p1h - p0h)[u])
+    wells = np.sum((wi * (pw - p1h))[u])
+    left = np.sum(T[0][0] * (1.0 - p1h[1]))
+    right = np.sum(T[0][nx - 2] * (0.0 - p1h[nx - 2]))
+    scale = np.sum(np.abs(wi * (pw - p1h))) + np.sum(np.abs(T[0][0] * (1.0 - p1h[1]))) + \
+        np.sum(np.abs(T[0][nx - 2] * p1h[nx - 2]))
+    balance = abs(storage - (wells + left + right)) / scale
+    res = {"nsteps": nsteps, "ms_per_step": ms_step,
+           "iters_per_step": [i["iters"] for i in infos],
+           "rel_res_true_max": max(i["rel_res_true"] for i in infos),
+           "mass_balance_rel": balance,
+           "step_rhs_us": rhs_us,
+           "step_rhs_GBps": STEP_RHS_BYTES_PER_CELL * n / (rhs_us * 1e-6) / 1e9,
+           "config": {"storage": c, "wells": "injector column pw 2, producer column pw -1, WI 1",
+                      "tol": 1e-6, "initial": "p = 0 inside, Dirichlet planes 1 and 0"}}
+    log_fn(f"time steps: {ms_step:.1f} ms/step, iterations {res['iters_per_step']}, mass balance "
+           f"{balance:.1e}, rhs kernel {rhs_us:.1f} us ({res['step_rhs_GBps']:.0f} GB/s)")
+    return res
 
 
 def bench_batched(log_fn):
@@ -455,6 +538,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-jacobi", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-timesteps", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-held-out", type=int, default=10,
                     help="held-out 128^3 realisations in the learned comparison (50 = full set)")
@@ -603,6 +687,10 @@ def main(argv=None):
         del src, dst
     torch.cuda.synchronize()
 
+    tsteps = None
+    if not args.no_timesteps:
+        tsteps = bench_time_steps(log, w.shape, tx, ty, tz)
+    del tx, ty, tz
     large = None
     if not args.no_large:
         large = bench_large(log, args.large_solve)
@@ -661,6 +749,7 @@ def main(argv=None):
         "copy_probe_GBps": copy_gbps,
         "jacobi_pcg": jac,
         "large": large,
+        "time_steps": tsteps,
         "batched": batched,
         "learned": learned_res,
         "large_learned": large_learned,

@@ -248,6 +248,51 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
                           float* const* x, const mffv_opts* opts, mffv_info* info);
 
 /*
+ * Backward-Euler time stepping with wells (Sec. II-A: the pressure system
+ * comes from an implicit backward-Euler discretisation in time with TPFA
+ * fluxes in space, Eq. 3-4, and each time step is solved by Newton steps
+ * J dp = -r, Eq. 5). Per step n -> n+1 and unknown cell K:
+ *   c_K (p_K^{n+1} - p_K^n) + sum_L T_KL (p_K^{n+1} - p_L^{n+1})
+ *                           + WI_K (p_K^{n+1} - pw_K) = q_K,
+ * and p_K^{n+1} = p_K^D on Dirichlet cells. c is the storage coefficient
+ * (porosity x total compressibility x cell volume / time step; 0 gives the
+ * paper's incompressible model), WI >= 0 the well index of a perforated cell
+ * (Peaceman form, 0 elsewhere), pw its bottom-hole pressure and q a source
+ * rate (positive = injection). The residual is linear in p, so one Newton
+ * step from p^n solves the step; MFFV_FP32_IR's FP64 refinement steps are the
+ * further Newton steps.
+ *
+ * The operator must carry c + WI as its accumulation: call
+ * mffv_set_transmissibility with accum = c + WI (per cell, or the scalar c
+ * when there are no wells), and keep its b_out as b here.
+ *
+ * mffv_step_rhs writes the right-hand side of one step,
+ *   rhs_K = b_K + c_K p_K^n + WI_K pw_K + q_K on unknown cells, b_K on
+ * Dirichlet cells, in FP32 evaluated left to right. b, p_old, rhs: device FP32
+ * arrays of n cells; c (NULL: c_scalar everywhere), wi and pw (both or
+ * neither), q: device FP32 arrays or NULL. rhs must not alias an input.
+ * Enqueued on the grid's stream. Errors: MFFV_EINVAL (NULL b, p_old or rhs,
+ * wi without pw, c_scalar negative or not finite, aliasing), MFFV_ESTATE
+ * (coefficients not set).
+ *
+ * mffv_time_steps runs nsteps >= 0 steps in place on p (in: p^n, out:
+ * p^{n+nsteps}): each forms its right-hand side in grid-owned memory
+ * (allocated by the first call) and solves with mffv_cg_solve from p^n as
+ * the initial guess. opts as for mffv_cg_solve, with precision MFFV_FP32 or
+ * MFFV_FP32_IR and async 0. info (host, nsteps entries) may be NULL.
+ * Synchronizes the stream. Returns MFFV_OK, MFFV_NOT_CONVERGED if a step
+ * missed the tolerance (its info says which; the later steps still run), or
+ * the first error (p then holds the last completed step, or the failed
+ * step's iterate).
+ */
+int mffv_step_rhs(mffv_grid* grid, const float* b, const float* c, float c_scalar,
+                  const float* p_old, const float* wi, const float* pw, const float* q,
+                  float* rhs);
+int mffv_time_steps(mffv_grid* grid, int nsteps, const float* b, const float* c, float c_scalar,
+                    const float* wi, const float* pw, const float* q, float* p,
+                    const mffv_opts* opts, mffv_info* info);
+
+/*
  * Learned preconditioner (flexible CG with opts.precond = MFFV_PRECOND_LEARNED).
  *
  * The network works on the Jacobi-scaled system A~ = D^-1/2 A D^-1/2,

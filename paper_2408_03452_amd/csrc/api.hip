@@ -97,6 +97,7 @@ struct mffv_grid {
     // FP32 workspace
     float *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr, *z = nullptr, *xw = nullptr,
           *bw = nullptr;
+    float* step_rhs = nullptr;  // right-hand side of the time steps
     CgState<float>* st32 = nullptr;
     // single-reduction CG: second r and q buffers, scalars, partials [2][4][max_blocks]
     float *r2 = nullptr, *q2 = nullptr, *partM = nullptr;
@@ -1084,7 +1085,7 @@ void mffv_destroy_grid(mffv_grid* G) {
     dfree(G->flags); dfree(G->partA); dfree(G->partB); dfree(G->partF); dfree(G->partR);
     dfree(G->dscal);
     dfree(G->r); dfree(G->p0); dfree(G->p1); dfree(G->q); dfree(G->z); dfree(G->xw);
-    dfree(G->bw); dfree(G->st32);
+    dfree(G->bw); dfree(G->st32); dfree(G->step_rhs);
     dfree(G->r2); dfree(G->q2); dfree(G->partM); dfree(G->ms);
     dfree(G->r64); dfree(G->p064); dfree(G->p164); dfree(G->q64); dfree(G->x64); dfree(G->b64);
     dfree(G->rres); dfree(G->st64);
@@ -1430,6 +1431,65 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
         }
     }
     if (status == MFFV_EBREAKDOWN) return fail(MFFV_EBREAKDOWN, "batched CG: breakdown in a system");
+    return status;
+}
+
+// ---------------------------------------------------------------------------
+// Backward-Euler time stepping with wells: each step forms its right-hand side
+// from the previous pressure and solves with the previous pressure as the
+// initial guess (for this linear residual, one Newton step; with
+// MFFV_FP32_IR the FP64 refinement steps are the further Newton steps).
+// ---------------------------------------------------------------------------
+namespace {
+int check_step_args(const float* b, const float* c, float c_scalar, const float* wi, const float* pw) {
+    if (!b) return fail(MFFV_EINVAL, "b must be a device array");
+    if (!wi != !pw) return fail(MFFV_EINVAL, "wi and pw must be given together");
+    if (!c && (!(c_scalar >= 0.f) || !std::isfinite(c_scalar)))
+        return fail(MFFV_EINVAL, "c_scalar must be finite and >= 0");
+    return MFFV_OK;
+}
+StepRhsIn step_in(const mffv_grid* G, const float* b, const float* c, float c_scalar, const float* p_old,
+                  const float* wi, const float* pw, const float* q) {
+    return StepRhsIn{G->dmask, b, c, c_scalar, p_old, wi, pw, q};
+}
+}  // namespace
+
+int mffv_step_rhs(mffv_grid* G, const float* b, const float* c, float c_scalar, const float* p_old,
+                  const float* wi, const float* pw, const float* q, float* rhs) {
+    int rc = check_grid(G, true);
+    if (rc || (rc = check_step_args(b, c, c_scalar, wi, pw))) return rc;
+    if (!p_old || !rhs) return fail(MFFV_EINVAL, "p_old and rhs must be device arrays");
+    for (const float* in : {b, c, p_old, wi, pw, q})
+        if (in == rhs) return fail(MFFV_EINVAL, "rhs must not alias an input");
+    if ((rc = set_device(G))) return rc;
+    HIP_TRY(launch_step_rhs(G->g.n, step_in(G, b, c, c_scalar, p_old, wi, pw, q), rhs, G->stream));
+    return MFFV_OK;
+}
+
+int mffv_time_steps(mffv_grid* G, int nsteps, const float* b, const float* c, float c_scalar,
+                    const float* wi, const float* pw, const float* q, float* p, const mffv_opts* opts,
+                    mffv_info* info) {
+    int rc = check_grid(G, true);
+    if (rc || (rc = check_step_args(b, c, c_scalar, wi, pw))) return rc;
+    if (!p) return fail(MFFV_EINVAL, "p must be a device array");
+    if (nsteps < 0) return fail(MFFV_EINVAL, "nsteps must be >= 0");
+    for (const float* in : {b, c, wi, pw, q})
+        if (in == p) return fail(MFFV_EINVAL, "p must not alias an input");
+    mffv_opts o = resolve_opts(opts);
+    if ((rc = validate_opts(o))) return rc;
+    if (o.async) return fail(MFFV_EINVAL, "time steps run synchronously (opts.async must be 0)");
+    if (o.precision == MFFV_FP64) return fail(MFFV_EINVAL, "time steps solve in MFFV_FP32 or MFFV_FP32_IR");
+    if ((rc = set_device(G))) return rc;
+    if (!G->step_rhs && (rc = dalloc(&G->step_rhs, (size_t)G->g.n))) return rc;
+    int status = MFFV_OK;
+    for (int s = 0; s < nsteps; ++s) {
+        HIP_TRY(launch_step_rhs(G->g.n, step_in(G, b, c, c_scalar, p, wi, pw, q), G->step_rhs, G->stream));
+        mffv_info one{};
+        rc = mffv_cg_solve(G, G->step_rhs, p, &o, &one);
+        if (info) info[s] = one;
+        if (rc < 0) return rc;
+        if (rc == MFFV_NOT_CONVERGED) status = MFFV_NOT_CONVERGED;
+    }
     return status;
 }
 

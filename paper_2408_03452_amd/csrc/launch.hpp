@@ -124,6 +124,20 @@ hipError_t launch_scale_to_f32(int64_t n, const double* r64, const double* scale
 hipError_t launch_axpy_f64_from_f32(int64_t n, const double* scale, const float* d, double* x,
                                     hipStream_t s);
 hipError_t launch_convert_f32_to_f64(int64_t n, const float* a, double* b, hipStream_t s);
+
+// Backward-Euler step right-hand side (optional arrays may be NULL; wi and pw
+// come together).
+struct StepRhsIn {
+    const uint8_t* dmask;
+    const float* b;
+    const float* c;  // NULL: c_scalar everywhere
+    float c_scalar;
+    const float* p_old;
+    const float* wi;
+    const float* pw;
+    const float* q;
+};
+hipError_t launch_step_rhs(int64_t n, const StepRhsIn& in, float* rhs, hipStream_t s);
 hipError_t launch_convert_f64_to_f32(int64_t n, const double* a, float* b, hipStream_t s);
 hipError_t launch_fill_f32(int64_t n, float* a, float v, hipStream_t s);
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s);

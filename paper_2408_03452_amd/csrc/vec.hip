@@ -417,6 +417,27 @@ __global__ __launch_bounds__(kThreads) void count_dirichlet(int64_t n, const uin
     if (threadIdx.x == 0 && tot) atomicAdd(out, tot);
 }
 
+// Right-hand side of one backward-Euler step of the pressure equation with
+// wells: the storage term carries the previous pressure, a well perforation
+// adds its index times the bottom-hole pressure (the index itself belongs to
+// the operator's diagonal), a source adds its rate, and Dirichlet rows keep
+// their value:
+//   rhs_K = b_K + c_K p_K^n + WI_K pw_K + q_K   (K not Dirichlet)
+//   rhs_K = b_K = p_K^D                           (K Dirichlet)
+// evaluated left to right in FP32.
+__global__ __launch_bounds__(kThreads) void step_rhs_kernel(int64_t n, StepRhsIn in, float* __restrict__ rhs) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
+        float v = in.b[e];
+        if (!in.dmask[e]) {
+            v += (in.c ? in.c[e] : in.c_scalar) * in.p_old[e];
+            if (in.wi) v += in.wi[e] * in.pw[e];
+            if (in.q) v += in.q[e];
+        }
+        rhs[e] = v;
+    }
+}
+
 int grid_for(int64_t n, int per_thread = 1, int cap = 8192) {
     int64_t b = (n / per_thread + kThreads - 1) / kThreads;
     if (b < 1) b = 1;
@@ -564,6 +585,11 @@ hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream
 hipError_t launch_perm_to_trans(const Geom& g, const double* k, double kz_ratio, float* tx,
                                 float* ty, float* tz, hipStream_t s) {
     hipLaunchKernelGGL(perm_to_trans, dim3(grid_for(g.n, 4)), dim3(kThreads), 0, s, g, k, kz_ratio, tx, ty, tz);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_rhs(int64_t n, const StepRhsIn& in, float* rhs, hipStream_t s) {
+    hipLaunchKernelGGL(step_rhs_kernel, dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, in, rhs);
     return hipGetLastError();
 }
 

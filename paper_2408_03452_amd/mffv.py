@@ -93,6 +93,9 @@ def _declare(lib):
         "mffv_cg_solve_batched": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int,
                                                  ctypes.POINTER(_P), ctypes.POINTER(_P),
                                                  ctypes.POINTER(Opts), _P]),
+        "mffv_step_rhs": (ctypes.c_int, [_P, _P, _P, ctypes.c_float, _P, _P, _P, _P, _P]),
+        "mffv_time_steps": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_float, _P, _P, _P, _P,
+                                           ctypes.POINTER(Opts), _P]),
         "mffv_copy_probe": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
         "mffv_net_num_params": (ctypes.c_int, []),
         "mffv_net_create": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
@@ -316,6 +319,29 @@ def cg_solve_batched(grids, b, x, opts: Opts | None = None):
     rc = lib().mffv_cg_solve_batched(G, ns, B, X, ctypes.byref(opts) if opts is not None else None,
                                      ctypes.addressof(infos))
     return _check(rc), [i.as_dict() for i in infos]
+
+
+def step_rhs(grid: Grid, b, p_old, rhs, c=None, c_scalar=0.0, wi=None, pw=None, q=None) -> None:
+    """Right-hand side of one backward-Euler step with wells (mffv_step_rhs)."""
+    n = grid.n
+    _check(lib().mffv_step_rhs(grid.handle, _ptr(b, torch.float32, n, "b"), _ptr(c, torch.float32, n, "c"),
+                               float(c_scalar), _ptr(p_old, torch.float32, n, "p_old"),
+                               _ptr(wi, torch.float32, n, "wi"), _ptr(pw, torch.float32, n, "pw"),
+                               _ptr(q, torch.float32, n, "q"), _ptr(rhs, torch.float32, n, "rhs")))
+
+
+def time_steps(grid: Grid, nsteps: int, b, p, c=None, c_scalar=0.0, wi=None, pw=None, q=None,
+               opts: Opts | None = None):
+    """nsteps backward-Euler steps in place on p (mffv_time_steps); returns
+    (status, per-step info dicts). The operator's accumulation must be c + wi."""
+    n = grid.n
+    infos = (Info * max(nsteps, 1))()
+    rc = lib().mffv_time_steps(grid.handle, int(nsteps), _ptr(b, torch.float32, n, "b"),
+                               _ptr(c, torch.float32, n, "c"), float(c_scalar),
+                               _ptr(wi, torch.float32, n, "wi"), _ptr(pw, torch.float32, n, "pw"),
+                               _ptr(q, torch.float32, n, "q"), _ptr(p, torch.float32, n, "p"),
+                               ctypes.byref(opts) if opts is not None else None, ctypes.addressof(infos))
+    return _check(rc), [infos[i].as_dict() for i in range(nsteps)]
 
 
 def set_launch(grid: Grid, ci: int, remap: int, seg: int = 0) -> None:

@@ -68,6 +68,8 @@ def test_argument_errors_before_any_gpu_work(mf):
     assert L.mffv_set_batched_watchdog(-1.0) == mf.EINVAL
     assert L.mffv_set_batched_watchdog(float("nan")) == mf.EINVAL
     assert L.mffv_set_batched_watchdog(2.0) == mf.OK       # the default again
+    assert L.mffv_step_rhs(None, 1, None, 0.0, 2, None, None, None, 3) == mf.EINVAL
+    assert L.mffv_time_steps(None, 1, 1, None, 0.0, None, None, None, 2, None, None) == mf.EINVAL
     L.mffv_destroy_grid(None)  # no-op
 
 
