@@ -16,8 +16,9 @@ SciPy's CSR product as the only library step. Modules:
                on BF16-rounded operands, for the learned preconditioner.
 * ``timestep`` -- backward-Euler time steps with storage and wells, each solved
                directly (a step's residual is linear, one Newton step).
+* ``faces``  -- the same operator on a face-list (unstructured) mesh.
 
 Each function is pinned by CPU tests against closed forms, invariants, dense
 solves and brute force (``tests/test_oracle_*.py``).
 """
-from . import tpfa, krylov, timestep  # noqa: F401
+from . import tpfa, krylov, timestep, faces  # noqa: F401

@@ -16,3 +16,4 @@ from .perm import (  # noqa: F401
     workload_field,
     white_residuals,
 )
+from .mesh import cartesian_faces, random_face_mesh  # noqa: F401
