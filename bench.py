@@ -37,6 +37,10 @@ HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published peak
 APPLY_BYTES_PER_CELL = 20       # x, Tx, Ty, Tz read; y written
 CG_BYTES_PER_CELL_ITER = 46     # fused phase A (34 on average) + phase B (12)
 PHASE_B_BYTES_PER_CELL = 12     # r, q read; r written
+# face-list apply per cell: a, x, y, the row pointer, and per face entry (6 on
+# the Cartesian mesh) its neighbour index and T; the gathered neighbour values
+# are taken as cache hits
+FACE_APPLY_BYTES_PER_CELL = 16 + 6 * 8
 STEP_RHS_BYTES_PER_CELL = 21    # b, p_old, WI, pw (4 B each) and the Dirichlet mask (1 B) read; rhs written
 
 
@@ -304,6 +308,77 @@ def bench_time_steps(log_fn, shape, tx, ty, tz, nsteps: int = 8):
     return res
 
 
+def bench_faces(log_fn, shape, tx, ty, tz, c, cg_iters: int = 200):
+    """The headline grid and field as a face-list mesh (3 x 256^2 x 255 faces):
+    the face-list apply in the Cartesian numbering and with the cells randomly
+    renumbered, and the face-list CG iteration rate over a fixed number of
+    iterations, each timed with HIP events on the grid's stream."""
+    import numpy as np
+    import torch
+    from paper_2408_03452_amd import mffv
+    from synth import cartesian_faces
+
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    fk, fl, ax = cartesian_faces(shape)
+    dmask = np.zeros(shape, dtype=np.uint8)
+    dmask[0] = dmask[-1] = 1
+    pd = np.zeros(shape, dtype=np.float32)
+    pd[0] = 1.0
+    dev = torch.device("cuda")
+    s = torch.cuda.Stream()
+    res = {"faces": int(fk.size), "bytes_per_cell": FACE_APPLY_BYTES_PER_CELL}
+    with torch.cuda.stream(s):
+        fk_t = torch.from_numpy(fk).to(dev)
+        ax_t = torch.from_numpy(ax).to(dev)
+        T = torch.where(ax_t == 0, tx[fk_t], torch.where(ax_t == 1, ty[fk_t], tz[fk_t])).contiguous()
+        del fk_t, ax_t
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        rng = np.random.default_rng(7)
+        for label, perm in (("cartesian_order", None), ("random_order", rng.permutation(n))):
+            if perm is None:
+                g = mffv.create_grid_faces(n, fk, fl, stream=s)
+                dm, pdv = dmask.ravel(), pd.ravel()
+            else:
+                g = mffv.create_grid_faces(n, perm[fk], perm[fl], stream=s)
+                dm = np.empty(n, dtype=np.uint8)
+                dm[perm] = dmask.ravel()
+                pdv = np.empty(n, dtype=np.float32)
+                pdv[perm] = pd.ravel()
+            b = torch.empty(n, dtype=torch.float32, device=dev)
+            mffv.set_face_transmissibility(g, T, accum_scalar=c, dmask=torch.from_numpy(dm).to(dev),
+                                           pD=torch.from_numpy(pdv).to(dev), b_out=b)
+            xa = torch.randn(n, dtype=torch.float32, device=dev)
+            ya = torch.empty_like(xa)
+            for _ in range(3):
+                mffv.apply(g, xa, ya)
+            e0.record(s)
+            for _ in range(20):
+                mffv.apply(g, xa, ya)
+            e1.record(s)
+            e1.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / 20
+            r = {"apply_us": us, "apply_GBps": FACE_APPLY_BYTES_PER_CELL * n / (us * 1e-6) / 1e9}
+            x = torch.zeros(n, dtype=torch.float32, device=dev)
+            opts = mffv.default_opts(tol=1e-30, max_iter=cg_iters, check_every=16, use_graph=1)
+            mffv.cg_solve(g, b, x, opts)
+            x.zero_()
+            e0.record(s)
+            st, info = mffv.cg_solve(g, b, x, opts)
+            e1.record(s)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            r["cg_ms_per_iter"] = ms / info["iters"]
+            r["cells_iter_per_s"] = n * info["iters"] / (ms * 1e-3)
+            res[label] = r
+            log_fn(f"faces ({label}): apply {us:.1f} us ({r['apply_GBps']:.0f} GB/s at "
+                   f"{FACE_APPLY_BYTES_PER_CELL} B/cell), CG {r['cg_ms_per_iter'] * 1e3:.1f} us/iter "
+                   f"({r['cells_iter_per_s'] / 1e9:.1f} Gcell*iter/s)")
+            g.close()
+            del b, xa, ya, x
+    return res
+
+
 def bench_batched(log_fn):
     """64 independent uneven systems (dims uniform in [32, 128], log-normal
     sigma 1.5, c log-uniform in [1e-4, 1e-2]) in one persistent launch under a
@@ -539,6 +614,7 @@ def main(argv=None):
     ap.add_argument("--no-jacobi", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-timesteps", action="store_true")
+    ap.add_argument("--no-faces", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-held-out", type=int, default=10,
                     help="held-out 128^3 realisations in the learned comparison (50 = full set)")
@@ -690,6 +766,9 @@ def main(argv=None):
     tsteps = None
     if not args.no_timesteps:
         tsteps = bench_time_steps(log, w.shape, tx, ty, tz)
+    face_res = None
+    if not args.no_faces:
+        face_res = bench_faces(log, w.shape, tx, ty, tz, w.c)
     del tx, ty, tz
     large = None
     if not args.no_large:
@@ -750,6 +829,7 @@ def main(argv=None):
         "jacobi_pcg": jac,
         "large": large,
         "time_steps": tsteps,
+        "faces": face_res,
         "batched": batched,
         "learned": learned_res,
         "large_learned": large_learned,

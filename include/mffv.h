@@ -184,6 +184,34 @@ int mffv_set_transmissibility(mffv_grid* grid, const float* tx, const float* ty,
                               const float* pD, float* b_out);
 
 /*
+ * Face-list (unstructured) grids: the TPFA operator of Eq. 3-4 on any mesh
+ * given as cells and faces, the generalisation the paper names as future
+ * work (Sec. VI). Face f joins cells face_k[f] and face_l[f]; the operator on
+ * an unknown cell K is c_K p_K + sum over K's faces of T_f (p_K - p_L), with
+ * the same Dirichlet elimination as on the Cartesian grid.
+ *
+ * mffv_create_grid_faces: n >= 1 cells (n < 2^31), nfaces >= 0 faces (fewer
+ * than 2^30) as HOST int arrays (copied; two different cells in [0, n) per
+ * face; repeated pairs add up). The handle works with mffv_apply,
+ * mffv_apply_f64, mffv_true_residual, mffv_cg_solve (FP32, FP32_IR; precond
+ * NONE or JACOBI; the two-phase iteration), mffv_cg_solve_f64 and the time
+ * steps. The entry points that need the Cartesian structure (launch shapes,
+ * the network, batched solves) return MFFV_EINVAL for it.
+ *
+ * mffv_set_face_transmissibility: T is a device FP32 array of nfaces
+ * (T_f = Upsilon_f lambda_f >= 0, finite), accum/accum_scalar the
+ * accumulation as in mffv_set_transmissibility, dmask a device uint8 array of
+ * n (NULL: no Dirichlet cell), pD device FP32 Dirichlet values (NULL: 0), b_out
+ * (device, may be NULL) receives the right-hand side. Synchronizes the stream.
+ * Errors as mffv_set_transmissibility; MFFV_EINVAL on a Cartesian handle.
+ */
+int mffv_create_grid_faces(int n, int nfaces, const int* face_k, const int* face_l, void* stream,
+                           mffv_grid** out);
+int mffv_set_face_transmissibility(mffv_grid* grid, const float* T, const float* accum,
+                                   float accum_scalar, const uint8_t* dmask, const float* pD,
+                                   float* b_out);
+
+/*
  * y = A x on the full grid (Eq. 6 / Alg. 2 with the sign of the Jacobian flipped
  * and the accumulation added; identity on Dirichlet cells). x and y are device
  * FP32 vectors of n entries and must not alias. Enqueued; does not synchronize.

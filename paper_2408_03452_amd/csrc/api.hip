@@ -98,6 +98,12 @@ struct mffv_grid {
     float *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr, *z = nullptr, *xw = nullptr,
           *bw = nullptr;
     float* step_rhs = nullptr;  // right-hand side of the time steps
+    // face-list grid: CSR rows of every cell's faces (entry -> neighbour, face,
+    // masked T); NULL on a Cartesian grid
+    bool faces = false;
+    int nfaces = 0;
+    int *csr_rp = nullptr, *csr_col = nullptr, *csr_ef = nullptr;
+    float* csr_val = nullptr;
     CgState<float>* st32 = nullptr;
     // single-reduction CG: second r and q buffers, scalars, partials [2][4][max_blocks]
     float *r2 = nullptr, *q2 = nullptr, *partM = nullptr;
@@ -139,7 +145,15 @@ struct mffv_grid {
 namespace {
 
 Coef coef_of(const mffv_grid* G) {
-    return Coef{G->a, G->tx, G->ty, G->tz, G->a64, G->a_uniform ? 1 : 0, G->a_const};
+    return Coef{G->a,           G->tx,      G->ty,       G->tz,     G->a64, G->a_uniform ? 1 : 0,
+                G->a_const,     G->csr_rp,  G->csr_col,  G->csr_val};
+}
+
+// Entry points that need the Cartesian structure (launch shapes, the network,
+// the batched kernel) refuse face-list grids.
+int check_cartesian(const mffv_grid* G, const char* what) {
+    if (G && G->faces) return fail(MFFV_EINVAL, std::string(what) + " needs a Cartesian grid");
+    return MFFV_OK;
 }
 
 int check_grid(const mffv_grid* G, bool need_coef) {
@@ -1021,6 +1035,32 @@ void mffv_default_opts(mffv_opts* o) {
     o->nn_every = 1;
 }
 
+namespace {
+// Coefficient arrays, partial sums, events and the pinned state mirror of a
+// grid whose sizes (g, max_blocks, nb_vec) are set; cartesian: also the face
+// arrays of the stencil kernels.
+int alloc_grid(mffv_grid* G, bool cartesian) {
+    const size_t n = (size_t)G->g.n;
+    int rc;
+    if ((rc = dalloc(&G->a, n)) || (rc = dalloc(&G->a64, n)) ||
+        (cartesian && ((rc = dalloc(&G->tx, n)) || (rc = dalloc(&G->ty, n)) || (rc = dalloc(&G->tz, n)))) ||
+        (rc = dalloc(&G->dinv, n)) || (rc = dalloc(&G->dmask, n)) ||
+        (rc = dalloc(&G->flags, 8)) || (rc = dalloc(&G->partA, (size_t)G->max_blocks)) ||
+        (rc = dalloc(&G->partB, 3 * (size_t)G->nb_vec)) ||
+        (rc = dalloc(&G->partF, 4 * (size_t)G->nb_vec)) ||
+        (rc = dalloc(&G->partR, (size_t)std::max(G->max_blocks, 1024))) || (rc = dalloc(&G->dscal, 8)))
+        return rc;
+    hipError_t e;
+    if ((e = hipHostMalloc(reinterpret_cast<void**>(&G->hstate), 512, 0)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&G->ev[0], hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&G->ev[1], hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreate(&G->t0)) != hipSuccess || (e = hipEventCreate(&G->t1)) != hipSuccess ||
+        (e = hipStreamSynchronize(G->stream)) != hipSuccess)
+        return hip_fail(e, "grid set-up");
+    return MFFV_OK;
+}
+}  // namespace
+
 int mffv_create_grid(int nx, int ny, int nz, void* stream, mffv_grid** out) {
     if (!out) return fail(MFFV_EINVAL, "out is NULL");
     if (nx < 3 || ny < 1 || nz < 1)
@@ -1053,22 +1093,77 @@ int mffv_create_grid(int nx, int ny, int nz, void* stream, mffv_grid** out) {
     worst = std::max<int64_t>(worst, (int64_t)m1.nchunk * m1.nich);
     G->max_blocks = std::max({G->m32.blocks(), G->m64.blocks(), G->nb_vec,
                               (int)std::min<int64_t>(worst, 1 << 18)});
-    if ((rc = dalloc(&G->a, n)) || (rc = dalloc(&G->a64, n)) || (rc = dalloc(&G->tx, n)) || (rc = dalloc(&G->ty, n)) ||
-        (rc = dalloc(&G->tz, n)) || (rc = dalloc(&G->dinv, n)) || (rc = dalloc(&G->dmask, n)) ||
-        (rc = dalloc(&G->flags, 8)) || (rc = dalloc(&G->partA, (size_t)G->max_blocks)) ||
-        (rc = dalloc(&G->partB, 3 * (size_t)G->nb_vec)) ||
-        (rc = dalloc(&G->partF, 4 * (size_t)G->nb_vec)) ||
-        (rc = dalloc(&G->partR, (size_t)std::max(G->max_blocks, 1024))) || (rc = dalloc(&G->dscal, 8))) {
+    if ((rc = alloc_grid(G, !G->faces))) {
         mffv_destroy_grid(G);
         return rc;
     }
-    if ((e = hipHostMalloc(reinterpret_cast<void**>(&G->hstate), 512, 0)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&G->ev[0], hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&G->ev[1], hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreate(&G->t0)) != hipSuccess || (e = hipEventCreate(&G->t1)) != hipSuccess ||
-        (e = hipStreamSynchronize(G->stream)) != hipSuccess) {
+    *out = G;
+    return MFFV_OK;
+}
+
+int mffv_create_grid_faces(int n, int nfaces, const int* face_k, const int* face_l, void* stream,
+                           mffv_grid** out) {
+    if (!out) return fail(MFFV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || nfaces < 0) return fail(MFFV_EINVAL, "a face-list grid needs n >= 1 and nfaces >= 0");
+    if (nfaces > 0 && (!face_k || !face_l)) return fail(MFFV_EINVAL, "face_k and face_l must be host arrays");
+    if ((int64_t)nfaces * 2 >= (int64_t(1) << 31)) return fail(MFFV_EINVAL, "2^30 faces or more");
+    // CSR rows on the host: each face appears in the rows of both its cells
+    std::vector<int> rp((size_t)n + 1, 0);
+    for (int f = 0; f < nfaces; ++f) {
+        const int k = face_k[f], l = face_l[f];
+        if (k < 0 || k >= n || l < 0 || l >= n || k == l)
+            return fail(MFFV_EINVAL, "face " + std::to_string(f) + " must join two different cells in [0, n)");
+        ++rp[(size_t)k + 1];
+        ++rp[(size_t)l + 1];
+    }
+    for (int i = 0; i < n; ++i) rp[(size_t)i + 1] += rp[i];
+    std::vector<int> col((size_t)2 * nfaces), ef((size_t)2 * nfaces), fill(rp.begin(), rp.end() - 1);
+    for (int f = 0; f < nfaces; ++f) {
+        const int k = face_k[f], l = face_l[f];
+        col[fill[k]] = l;
+        ef[fill[k]++] = f;
+        col[fill[l]] = k;
+        ef[fill[l]++] = f;
+    }
+    mffv_grid* G = new (std::nothrow) mffv_grid();
+    if (!G) return fail(MFFV_ENOMEM, "host allocation failed");
+    G->faces = true;
+    G->nfaces = nfaces;
+    G->g = Geom{n, 1, 1, n, 1};
+    G->stream = static_cast<hipStream_t>(stream);
+    hipError_t e = hipGetDevice(&G->device);
+    if (e != hipSuccess) {
+        delete G;
+        return hip_fail(e, "hipGetDevice");
+    }
+    // one thread per cell in a grid-stride loop
+    const int nb = (int)std::min<int64_t>(8192, ((int64_t)n + kThreads - 1) / kThreads);
+    G->m32 = March{1, 1, nb, 1, 0, 0, 0, 0};
+    G->m_apply = G->m32;
+    G->m64 = G->m32;
+    G->nb_vec = (int)std::min<int64_t>(1024, std::max<int64_t>(1, ((int64_t)n / 4 + kThreads - 1) / kThreads));
+    G->max_blocks = std::max(nb, G->nb_vec);
+    const size_t ne = (size_t)2 * nfaces;
+    int rc;
+    if ((rc = alloc_grid(G, false)) || (rc = dalloc(&G->csr_rp, (size_t)n + 1)) ||
+        (ne && ((rc = dalloc(&G->csr_col, ne)) || (rc = dalloc(&G->csr_ef, ne)) || (rc = dalloc(&G->csr_val, ne))))) {
         mffv_destroy_grid(G);
-        return hip_fail(e, "grid set-up");
+        return rc;
+    }
+    if ((e = hipMemcpy(G->csr_rp, rp.data(), rp.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess ||
+        (ne && (e = hipMemcpy(G->csr_col, col.data(), ne * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) ||
+        (ne && (e = hipMemcpy(G->csr_ef, ef.data(), ne * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)) {
+        mffv_destroy_grid(G);
+        return hip_fail(e, "face-list upload");
+    }
+    if (!G->csr_col) {
+        // a grid without faces: the row pointers are all 0 and no entry is read,
+        // but the operator form needs non-NULL entry arrays
+        if ((rc = dalloc(&G->csr_col, 1)) || (rc = dalloc(&G->csr_ef, 1)) || (rc = dalloc(&G->csr_val, 1))) {
+            mffv_destroy_grid(G);
+            return rc;
+        }
     }
     *out = G;
     return MFFV_OK;
@@ -1086,6 +1181,7 @@ void mffv_destroy_grid(mffv_grid* G) {
     dfree(G->dscal);
     dfree(G->r); dfree(G->p0); dfree(G->p1); dfree(G->q); dfree(G->z); dfree(G->xw);
     dfree(G->bw); dfree(G->st32); dfree(G->step_rhs);
+    dfree(G->csr_rp); dfree(G->csr_col); dfree(G->csr_ef); dfree(G->csr_val);
     dfree(G->r2); dfree(G->q2); dfree(G->partM); dfree(G->ms);
     dfree(G->r64); dfree(G->p064); dfree(G->p164); dfree(G->q64); dfree(G->x64); dfree(G->b64);
     dfree(G->rres); dfree(G->st64);
@@ -1116,7 +1212,8 @@ int mffv_set_transmissibility(mffv_grid* G, const float* tx, const float* ty, co
                               const float* accum, float accum_scalar, const uint8_t* dmask,
                               const float* pD, float* b_out) {
     int rc = check_grid(G, false);
-    if (rc) return rc;
+    if (rc || (rc = check_cartesian(G, "mffv_set_transmissibility (use mffv_set_face_transmissibility)")))
+        return rc;
     if (!tx || !ty || !tz) return fail(MFFV_EINVAL, "tx, ty and tz must be device arrays");
     if (!accum && (!(accum_scalar >= 0.f) || !std::isfinite(accum_scalar)))
         return fail(MFFV_EINVAL, "accumulation must be finite and >= 0");
@@ -1142,6 +1239,38 @@ int mffv_set_transmissibility(mffv_grid* G, const float* tx, const float* ty, co
     // coefficient is the accumulation itself on every plane not next to D
     G->a_uniform = accum == nullptr && dmask == nullptr;
     G->a_const = accum_scalar;
+    G->has_coef = true;
+    return MFFV_OK;
+}
+
+int mffv_set_face_transmissibility(mffv_grid* G, const float* T, const float* accum, float accum_scalar,
+                                   const uint8_t* dmask, const float* pD, float* b_out) {
+    int rc = check_grid(G, false);
+    if (rc) return rc;
+    if (!G->faces) return fail(MFFV_EINVAL, "mffv_set_face_transmissibility needs a face-list grid");
+    if (!T && G->nfaces > 0) return fail(MFFV_EINVAL, "T must be a device array");
+    if (!accum && (!(accum_scalar >= 0.f) || !std::isfinite(accum_scalar)))
+        return fail(MFFV_EINVAL, "accumulation must be finite and >= 0");
+    if ((rc = set_device(G))) return rc;
+    drop_graphs(G);
+    G->has_coef = false;
+    HIP_TRY(hipMemsetAsync(G->flags, 0, 8 * sizeof(int), G->stream));
+    CsrSetupIn in{G->csr_rp, G->csr_col, G->csr_ef, T, accum, accum_scalar, dmask, pD};
+    SetupOut out{G->a, G->a64, nullptr, nullptr, nullptr, G->dinv, G->dmask, b_out, G->flags};
+    HIP_TRY(launch_csr_setup(G->g.n, in, out, G->csr_val, G->stream));
+    int h[8];
+    HIP_TRY(hipMemcpyAsync(h, G->flags, sizeof(h), hipMemcpyDeviceToHost, G->stream));
+    HIP_TRY(hipStreamSynchronize(G->stream));
+    if (h[0]) return fail(MFFV_EINVAL, "transmissibility negative or not finite");
+    if (h[1]) return fail(MFFV_EINVAL, "accumulation negative or not finite");
+    if (h[2]) return fail(MFFV_EINVAL, "Dirichlet pressure not finite");
+    if (h[3] == 0 && !h[4])
+        return fail(MFFV_EINVAL, "singular operator: no Dirichlet cell and zero accumulation");
+    if (h[3] == G->g.n) return fail(MFFV_EINVAL, "every cell is a Dirichlet cell");
+    G->n_unknown = G->g.n - h[3];
+    G->feat_valid = false;
+    G->a_uniform = false;
+    G->a_const = 0.f;
     G->has_coef = true;
     return MFFV_OK;
 }
@@ -1193,6 +1322,8 @@ int mffv_cg_solve(mffv_grid* G, const float* b, float* x, const mffv_opts* opts,
     if (b == x) return fail(MFFV_EINVAL, "b and x must not alias");
     mffv_opts o = resolve_opts(opts);
     if ((rc = validate_opts(o))) return rc;
+    if (o.precond == MFFV_PRECOND_LEARNED && (rc = check_cartesian(G, "the learned preconditioner")))
+        return rc;
     if (o.async) {
         // no host synchronisation: the whole solve runs in the persistent kernel
         if (o.precision != MFFV_FP32 || o.precond == MFFV_PRECOND_LEARNED)
@@ -1310,6 +1441,7 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
         if (rc) return rc;
         if (!b[s] || !x[s]) return fail(MFFV_EINVAL, "NULL vector of system " + std::to_string(s));
         if ((const void*)b[s] == (const void*)x[s]) return fail(MFFV_EINVAL, "b and x must not alias");
+        if ((rc = check_cartesian(grids[s], "mffv_cg_solve_batched"))) return rc;
         if (grids[s]->device != grids[0]->device || grids[s]->stream != grids[0]->stream)
             return fail(MFFV_EINVAL, "all grids of a batch must share device and stream");
         for (int t = 0; t < s; ++t)
@@ -1496,7 +1628,7 @@ int mffv_time_steps(mffv_grid* G, int nsteps, const float* b, const float* c, fl
 int mffv_harvest_pair(mffv_grid* G, const float* b, const float* x, const double* x_star,
                       float* r_hat, float* target, float* scale) {
     int rc = check_grid(G, true);
-    if (rc) return rc;
+    if (rc || (rc = check_cartesian(G, "mffv_harvest_pair"))) return rc;
     if (!b || !x || !x_star || !r_hat || !target) return fail(MFFV_EINVAL, "NULL array");
     if ((rc = set_device(G)) || (rc = ensure_ws32(G))) return rc;
     StencilIO<float> io;
@@ -1522,7 +1654,7 @@ int mffv_harvest_pair(mffv_grid* G, const float* b, const float* x, const double
 int mffv_nn_loss_grad(mffv_net* net, mffv_grid* G, const float* r_hat, const float* target,
                       double* loss) {
     int rc = check_grid(G, true);
-    if (rc) return rc;
+    if (rc || (rc = check_cartesian(G, "the network"))) return rc;
     if (!net) return fail(MFFV_EINVAL, "network handle is NULL");
     if (!r_hat) return fail(MFFV_EINVAL, "r_hat is NULL");
     if ((rc = set_device(G)) || (rc = ensure_feature(G))) return rc;
@@ -1551,7 +1683,7 @@ int mffv_nn_train_step(mffv_net* net, mffv_grid* G, const float* r_hat, const fl
 
 int mffv_grid_feature(mffv_grid* G, float* feat) {
     int rc = check_grid(G, true);
-    if (rc) return rc;
+    if (rc || (rc = check_cartesian(G, "mffv_grid_feature"))) return rc;
     if (!feat) return fail(MFFV_EINVAL, "feat is NULL");
     if ((rc = set_device(G)) || (rc = ensure_feature(G))) return rc;
     HIP_TRY(hipMemcpyAsync(feat, G->feat, G->g.n * sizeof(float), hipMemcpyDeviceToDevice, G->stream));
@@ -1560,7 +1692,7 @@ int mffv_grid_feature(mffv_grid* G, float* feat) {
 
 int mffv_set_launch(mffv_grid* G, int ci, int remap, int seg) {
     int rc = check_grid(G, false);
-    if (rc) return rc;
+    if (rc || (rc = check_cartesian(G, "mffv_set_launch"))) return rc;
     if (ci < 0 || ci > 4096 || (remap != 0 && remap != 1))
         return fail(MFFV_EINVAL, "ci must be in [0, 4096] (0 = default) and remap 0 or 1");
     if (seg < -1 || (seg > 0 && !march_seg_ok(G->g, G->m32.vec, seg)))
@@ -1598,7 +1730,7 @@ extern "C" {
 
 int mffv_autotune(mffv_grid* G, const char* cache_path, mffv_tune_result* out) {
     int rc = check_grid(G, true);
-    if (rc) return rc;
+    if (rc || (rc = check_cartesian(G, "mffv_autotune"))) return rc;
     if ((rc = set_device(G)) || (rc = ensure_ws32(G))) return rc;
     const std::string key = tune_key(G);
     TuneRec rec;
@@ -1747,6 +1879,7 @@ int mffv_autotune_batched(mffv_grid* const* grids, int nsys, const float* const*
     if (!grids || !b || !x || nsys <= 0) return fail(MFFV_EINVAL, "grids, b, x must be non-NULL and nsys > 0");
     for (int s = 0; s < nsys; ++s) {
         int rc = check_grid(grids[s], true);
+        if (!rc) rc = check_cartesian(grids[s], "mffv_autotune_batched");
         if (rc) return rc;
         if (!x[s]) return fail(MFFV_EINVAL, "NULL vector");
     }

@@ -42,6 +42,12 @@ struct Coef {
     // identity coefficient is the accumulation alone)
     int a_uniform;
     float a_const;
+    // face-list (unstructured) operator, NULL on a Cartesian grid: each cell's
+    // faces as a CSR row of neighbour cells and transmissibilities, zero on
+    // every face that touches a Dirichlet cell (the role of tx, ty, tz above)
+    const int* rp;     // row pointers, n + 1
+    const int* col;    // neighbour cell of each entry
+    const float* val;  // T of each entry
 };
 
 __device__ __forceinline__ bool coef_plane_uniform(const Coef& c, int i, int nx) {

@@ -577,6 +577,71 @@ __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<
     }
 }
 
+// ---------------------------------------------------------------------------
+// Face-list (unstructured) operator: one thread per cell (grid-stride), the
+// cell's faces a CSR row of (neighbour, T), so that y = a x + sum_f T_f (x -
+// x_nbr) as on the Cartesian grid; modes and the fused CG step as in
+// stencil_s. Faces that touch a Dirichlet cell carry T = 0 and are skipped.
+// ---------------------------------------------------------------------------
+template <class real, int MODE>
+__global__ __launch_bounds__(kThreads) void stencil_csr(int64_t n, Coef c, StencilIO<real> io) {
+    __shared__ real red[kThreads / kWave];
+
+    PhaseA<real> ph{0, real(0), real(0), real(0), false};
+    if (MODE == kFusedCg && !phase_a_start(io, red, ph)) return;
+    const int it = ph.k;
+    const real beta = ph.beta, alpha_prev = ph.alpha_prev, alpha_prev2 = ph.alpha_prev2;
+    const bool pending = it >= 2 && (it & 1) == 0;
+    const real* pold = (it & 1) ? io.p0 : io.p1;
+    real* pnew = (it & 1) ? io.p1 : io.p0;
+    const bool use_pold = (MODE == kFusedCg) && it > 0;
+    auto S = [&](int64_t idx) -> real {
+        real v = io.src[idx];
+        if (use_pold) v += beta * pold[idx];
+        return v;
+    };
+
+    real dot = 0;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t K = (int64_t)blockIdx.x * kThreads + threadIdx.x; K < n; K += stride) {
+        const real poc = use_pold ? pold[K] : real(0);
+        const real sc = use_pold ? io.src[K] + beta * poc : io.src[K];
+        const real ac = std::is_same<real, double>::value ? (real)c.a64[K] : (real)c.a[K];
+        real flux = 0;
+        const int e1 = c.rp[K + 1];
+        for (int e = c.rp[K]; e < e1; ++e) {
+            const float t = c.val[e];
+            if (t != 0.f) flux += (real)t * (sc - S(c.col[e]));
+        }
+        const real y = ac * sc + flux;
+        if (MODE == kApply) {
+            io.out[K] = y;
+        } else if (MODE == kFusedCg) {
+            if (pending) io.xsol[K] += alpha_prev2 * pnew[K] + alpha_prev * poc;
+            pnew[K] = sc;
+            io.out[K] = y;
+            dot += sc * y;
+        } else {
+            const real bb = io.rhs_f64 ? (real) static_cast<const double*>(io.rhs)[K]
+                                       : (real) static_cast<const float*>(io.rhs)[K];
+            const real r = bb - y;
+            io.out[K] = r;
+            dot += r * r;
+        }
+    }
+    if (MODE == kFusedCg || (MODE == kResidual && io.partials != nullptr)) {
+        const real tot = block_sum(dot, red);
+        if (threadIdx.x == 0) io.partials[blockIdx.x] = tot;
+    }
+}
+
+template <class real, int MODE>
+hipError_t launch_csr(const Geom& g, const Coef& c, const StencilIO<real>& io, const March& m,
+                      hipStream_t s) {
+    hipLaunchKernelGGL((stencil_csr<real, MODE>), dim3(m.blocks()), dim3(kThreads), 0, s, g.n, c, io);
+    return hipGetLastError();
+}
+
 template <class real, int MODE>
 hipError_t launch_s(const Geom& g, const Coef& c, const StencilIO<real>& io, const March& m,
                     hipStream_t s) {
@@ -595,6 +660,14 @@ hipError_t launch_v4(const Geom& g, const Coef& c, const StencilIO<float>& io, c
 
 hipError_t launch_stencil_f32(int mode, const Geom& g, const Coef& c, const StencilIO<float>& io,
                               const March& m, hipStream_t s) {
+    if (c.rp) {
+        switch (mode) {
+            case kApply: return launch_csr<float, kApply>(g, c, io, m, s);
+            case kFusedCg: return launch_csr<float, kFusedCg>(g, c, io, m, s);
+            case kResidual: return launch_csr<float, kResidual>(g, c, io, m, s);
+            default: return hipErrorInvalidValue;  // the single-reduction form is Cartesian only
+        }
+    }
     if (m.vec == 4) {
         switch (mode) {
             case kApply: return launch_v4<kApply>(g, c, io, m, s);
@@ -613,6 +686,13 @@ hipError_t launch_stencil_f32(int mode, const Geom& g, const Coef& c, const Sten
 
 hipError_t launch_stencil_f64(int mode, const Geom& g, const Coef& c, const StencilIO<double>& io,
                               const March& m, hipStream_t s) {
+    if (c.rp) {
+        switch (mode) {
+            case kApply: return launch_csr<double, kApply>(g, c, io, m, s);
+            case kFusedCg: return launch_csr<double, kFusedCg>(g, c, io, m, s);
+            default: return launch_csr<double, kResidual>(g, c, io, m, s);
+        }
+    }
     switch (mode) {
         case kApply: return launch_s<double, kApply>(g, c, io, m, s);
         case kFusedCg: return launch_s<double, kFusedCg>(g, c, io, m, s);

@@ -407,6 +407,62 @@ __global__ __launch_bounds__(kThreads) void setup_kernel(Geom g, SetupIn in, Set
     }
 }
 
+// Face-list operator set-up: one thread per cell over its CSR row (entry e:
+// neighbour col[e], face ef[e]), with the outputs of the Cartesian set-up
+// (identity coefficient, masked faces, 1/diag, mask, b, flags). Without a
+// mask no cell is Dirichlet; without pD the Dirichlet values are 0.
+__global__ __launch_bounds__(kThreads) void csr_setup_kernel(int64_t n, CsrSetupIn in, SetupOut out,
+                                                             float* val) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    int badT = 0, badC = 0, badP = 0, anyC = 0;
+    for (int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x; l < n; l += stride) {
+        const bool D = in.dmask && in.dmask[l];
+        const float cl = in.accum ? in.accum[l] : in.accum_scalar;
+        if (!(cl >= 0.f) || !isfinite(cl)) badC = 1;
+        if (!D && cl > 0.f) anyC = 1;
+        out.dmask[l] = D ? 1 : 0;
+        double diag = (double)cl, to_d = (double)cl, bsum = 0.0;
+        const int e1 = in.rp[l + 1];
+        for (int e = in.rp[l]; e < e1; ++e) {
+            const float t = in.T[in.ef[e]];
+            if (bad_face(t)) badT = 1;
+            const int nb = in.col[e];
+            const bool nd = in.dmask && in.dmask[nb];
+            val[e] = (!D && !nd) ? t : 0.f;
+            if (!D) {
+                diag += (double)t;
+                if (nd) {
+                    to_d += (double)t;
+                    bsum += (double)t * (double)(in.pd ? in.pd[nb] : 0.f);
+                }
+            }
+        }
+        if (D) {
+            const float pd = in.pd ? in.pd[l] : 0.f;
+            if (!isfinite(pd)) badP = 1;
+            out.a[l] = 1.f;
+            out.a64[l] = 1.0;
+            out.dinv[l] = 1.f;
+            if (out.b) out.b[l] = pd;
+        } else {
+            out.a[l] = (float)to_d;
+            out.a64[l] = to_d;
+            out.dinv[l] = (float)(1.0 / diag);
+            if (out.b) out.b[l] = (float)bsum;
+        }
+    }
+    badT = __syncthreads_or(badT);
+    badC = __syncthreads_or(badC);
+    badP = __syncthreads_or(badP);
+    anyC = __syncthreads_or(anyC);
+    if (threadIdx.x == 0) {
+        if (badT) atomicOr(&out.flags[0], 1);
+        if (badC) atomicOr(&out.flags[1], 1);
+        if (badP) atomicOr(&out.flags[2], 1);
+        if (anyC) atomicOr(&out.flags[4], 1);
+    }
+}
+
 // number of Dirichlet cells (exact count, one atomic per block)
 __global__ __launch_bounds__(kThreads) void count_dirichlet(int64_t n, const uint8_t* dmask, int* out) {
     __shared__ int red[kThreads / kWave];
@@ -585,6 +641,16 @@ hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream
 hipError_t launch_perm_to_trans(const Geom& g, const double* k, double kz_ratio, float* tx,
                                 float* ty, float* tz, hipStream_t s) {
     hipLaunchKernelGGL(perm_to_trans, dim3(grid_for(g.n, 4)), dim3(kThreads), 0, s, g, k, kz_ratio, tx, ty, tz);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_setup(int64_t n, const CsrSetupIn& in, const SetupOut& out, float* val,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(csr_setup_kernel, dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, in, out, val);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(count_dirichlet, dim3(grid_for(n, 16, 4096)), dim3(kThreads), 0, s, n,
+                       (const uint8_t*)out.dmask, out.flags + 3);
     return hipGetLastError();
 }
 

@@ -93,6 +93,8 @@ def _declare(lib):
         "mffv_cg_solve_batched": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int,
                                                  ctypes.POINTER(_P), ctypes.POINTER(_P),
                                                  ctypes.POINTER(Opts), _P]),
+        "mffv_create_grid_faces": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _P, _P, ctypes.POINTER(_P)]),
+        "mffv_set_face_transmissibility": (ctypes.c_int, [_P, _P, _P, ctypes.c_float, _P, _P, _P]),
         "mffv_step_rhs": (ctypes.c_int, [_P, _P, _P, ctypes.c_float, _P, _P, _P, _P, _P]),
         "mffv_time_steps": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_float, _P, _P, _P, _P,
                                            ctypes.POINTER(Opts), _P]),
@@ -226,6 +228,33 @@ def create_grid(nx: int, ny: int, nz: int, stream=None) -> Grid:
 
 def destroy_grid(grid: Grid) -> None:
     grid.close()
+
+
+def create_grid_faces(n: int, face_k, face_l, stream=None) -> Grid:
+    """Face-list grid of n cells; face_k/face_l are host integer arrays of the
+    cells each face joins (copied)."""
+    import numpy as np
+    fk = np.ascontiguousarray(face_k, dtype=np.int32)
+    fl = np.ascontiguousarray(face_l, dtype=np.int32)
+    if fk.shape != fl.shape or fk.ndim != 1:
+        raise ValueError("face_k and face_l must be 1-D arrays of the same length")
+    s = _stream(stream)
+    h = _P()
+    _check(lib().mffv_create_grid_faces(int(n), int(fk.size), fk.ctypes.data if fk.size else None,
+                                        fl.ctypes.data if fl.size else None, s, ctypes.byref(h)))
+    g = Grid(h.value, (int(n), 1, 1), s)
+    g.nfaces = int(fk.size)
+    return g
+
+
+def set_face_transmissibility(grid: Grid, T, accum=None, accum_scalar=0.0, dmask=None, pD=None,
+                              b_out=None) -> None:
+    n = grid.n
+    _check(lib().mffv_set_face_transmissibility(
+        grid.handle, _ptr(T, torch.float32, getattr(grid, "nfaces", None), "T"),
+        _ptr(accum, torch.float32, n, "accum"),
+        float(accum_scalar), _ptr(dmask, torch.uint8, n, "dmask"), _ptr(pD, torch.float32, n, "pD"),
+        _ptr(b_out, torch.float32, n, "b_out")))
 
 
 def perm_to_trans(nx, ny, nz, k, kz_ratio, tx, ty, tz, stream=None) -> None:

@@ -70,6 +70,17 @@ def test_argument_errors_before_any_gpu_work(mf):
     assert L.mffv_set_batched_watchdog(2.0) == mf.OK       # the default again
     assert L.mffv_step_rhs(None, 1, None, 0.0, 2, None, None, None, 3) == mf.EINVAL
     assert L.mffv_time_steps(None, 1, 1, None, 0.0, None, None, None, 2, None, None) == mf.EINVAL
+    # face-list grids: faces are checked on the host before any device work
+    fk = (ctypes.c_int * 2)(0, 1)
+    bad_l = (ctypes.c_int * 2)(1, 1)                      # a face joining a cell to itself
+    far_l = (ctypes.c_int * 2)(1, 4)                      # a cell out of range
+    for fl_ in (bad_l, far_l):
+        assert L.mffv_create_grid_faces(4, 2, fk, fl_, None, ctypes.byref(h)) == mf.EINVAL
+    assert "face 1" in mf.last_error()
+    assert L.mffv_create_grid_faces(0, 0, None, None, None, ctypes.byref(h)) == mf.EINVAL
+    assert L.mffv_create_grid_faces(4, 2, None, None, None, ctypes.byref(h)) == mf.EINVAL
+    assert L.mffv_create_grid_faces(4, 0, None, None, None, None) == mf.EINVAL
+    assert L.mffv_set_face_transmissibility(None, 1, None, 0.0, None, None, None) == mf.EINVAL
     L.mffv_destroy_grid(None)  # no-op
 
 
