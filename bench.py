@@ -37,10 +37,15 @@ HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published peak
 APPLY_BYTES_PER_CELL = 20       # x, Tx, Ty, Tz read; y written
 CG_BYTES_PER_CELL_ITER = 46     # fused phase A (34 on average) + phase B (12)
 PHASE_B_BYTES_PER_CELL = 12     # r, q read; r written
-# face-list apply per cell: a, x, y, the row pointer, and per face entry (6 on
-# the Cartesian mesh) its neighbour index and T; the gathered neighbour values
-# are taken as cache hits
-FACE_APPLY_BYTES_PER_CELL = 16 + 6 * 8
+# face-list apply: a, x, y per cell (12 B) and, per face, two entries (one in
+# each cell's row) of neighbour index and T (16 B); the gathered neighbour
+# values are taken as cache hits, slice padding is not counted
+
+
+def face_apply_bytes(n: int, nfaces: int) -> int:
+    return 12 * n + 16 * nfaces
+
+
 STEP_RHS_BYTES_PER_CELL = 21    # b, p_old, WI, pw (4 B each) and the Dirichlet mask (1 B) read; rhs written
 
 
@@ -327,7 +332,8 @@ def bench_faces(log_fn, shape, tx, ty, tz, c, cg_iters: int = 200):
     pd[0] = 1.0
     dev = torch.device("cuda")
     s = torch.cuda.Stream()
-    res = {"faces": int(fk.size), "bytes_per_cell": FACE_APPLY_BYTES_PER_CELL}
+    nbytes = face_apply_bytes(n, int(fk.size))
+    res = {"faces": int(fk.size), "bytes_per_cell": nbytes / n}
     with torch.cuda.stream(s):
         fk_t = torch.from_numpy(fk).to(dev)
         ax_t = torch.from_numpy(ax).to(dev)
@@ -358,7 +364,7 @@ def bench_faces(log_fn, shape, tx, ty, tz, c, cg_iters: int = 200):
             e1.record(s)
             e1.synchronize()
             us = e0.elapsed_time(e1) * 1e3 / 20
-            r = {"apply_us": us, "apply_GBps": FACE_APPLY_BYTES_PER_CELL * n / (us * 1e-6) / 1e9}
+            r = {"apply_us": us, "apply_GBps": nbytes / (us * 1e-6) / 1e9}
             x = torch.zeros(n, dtype=torch.float32, device=dev)
             opts = mffv.default_opts(tol=1e-30, max_iter=cg_iters, check_every=16, use_graph=1)
             mffv.cg_solve(g, b, x, opts)
@@ -372,7 +378,7 @@ def bench_faces(log_fn, shape, tx, ty, tz, c, cg_iters: int = 200):
             r["cells_iter_per_s"] = n * info["iters"] / (ms * 1e-3)
             res[label] = r
             log_fn(f"faces ({label}): apply {us:.1f} us ({r['apply_GBps']:.0f} GB/s at "
-                   f"{FACE_APPLY_BYTES_PER_CELL} B/cell), CG {r['cg_ms_per_iter'] * 1e3:.1f} us/iter "
+                   f"{nbytes / n:.1f} B/cell), CG {r['cg_ms_per_iter'] * 1e3:.1f} us/iter "
                    f"({r['cells_iter_per_s'] / 1e9:.1f} Gcell*iter/s)")
             g.close()
             del b, xa, ya, x

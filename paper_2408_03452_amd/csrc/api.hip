@@ -98,11 +98,11 @@ struct mffv_grid {
     float *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr, *z = nullptr, *xw = nullptr,
           *bw = nullptr;
     float* step_rhs = nullptr;  // right-hand side of the time steps
-    // face-list grid: CSR rows of every cell's faces (entry -> neighbour, face,
-    // masked T); NULL on a Cartesian grid
+    // face-list grid: every cell's faces in the sliced layout of Coef (slice
+    // pointers; entry -> neighbour, face, masked T); NULL on a Cartesian grid
     bool faces = false;
     int nfaces = 0;
-    int *csr_rp = nullptr, *csr_col = nullptr, *csr_ef = nullptr;
+    int *csr_sp = nullptr, *csr_col = nullptr, *csr_ef = nullptr;
     float* csr_val = nullptr;
     CgState<float>* st32 = nullptr;
     // single-reduction CG: second r and q buffers, scalars, partials [2][4][max_blocks]
@@ -146,7 +146,7 @@ namespace {
 
 Coef coef_of(const mffv_grid* G) {
     return Coef{G->a,           G->tx,      G->ty,       G->tz,     G->a64, G->a_uniform ? 1 : 0,
-                G->a_const,     G->csr_rp,  G->csr_col,  G->csr_val};
+                G->a_const,     G->csr_sp,  G->csr_col,  G->csr_val};
 }
 
 // Entry points that need the Cartesian structure (launch shapes, the network,
@@ -1108,7 +1108,7 @@ int mffv_create_grid_faces(int n, int nfaces, const int* face_k, const int* face
     if (n < 1 || nfaces < 0) return fail(MFFV_EINVAL, "a face-list grid needs n >= 1 and nfaces >= 0");
     if (nfaces > 0 && (!face_k || !face_l)) return fail(MFFV_EINVAL, "face_k and face_l must be host arrays");
     if ((int64_t)nfaces * 2 >= (int64_t(1) << 31)) return fail(MFFV_EINVAL, "2^30 faces or more");
-    // CSR rows on the host: each face appears in the rows of both its cells
+    // rows on the host: each face appears in the rows of both its cells
     std::vector<int> rp((size_t)n + 1, 0);
     for (int f = 0; f < nfaces; ++f) {
         const int k = face_k[f], l = face_l[f];
@@ -1118,13 +1118,36 @@ int mffv_create_grid_faces(int n, int nfaces, const int* face_k, const int* face
         ++rp[(size_t)l + 1];
     }
     for (int i = 0; i < n; ++i) rp[(size_t)i + 1] += rp[i];
-    std::vector<int> col((size_t)2 * nfaces), ef((size_t)2 * nfaces), fill(rp.begin(), rp.end() - 1);
+    std::vector<int> rcol((size_t)2 * nfaces), ref((size_t)2 * nfaces), fill(rp.begin(), rp.end() - 1);
     for (int f = 0; f < nfaces; ++f) {
         const int k = face_k[f], l = face_l[f];
-        col[fill[k]] = l;
-        ef[fill[k]++] = f;
-        col[fill[l]] = k;
-        ef[fill[l]++] = f;
+        rcol[fill[k]] = l;
+        ref[fill[k]++] = f;
+        rcol[fill[l]] = k;
+        ref[fill[l]++] = f;
+    }
+    // sliced layout: kWave consecutive cells per slice, each slice as wide as
+    // its longest row, entries column-major; padding points at the cell itself
+    const int ns = (n + kWave - 1) / kWave;
+    std::vector<int> sp((size_t)ns + 1, 0);
+    for (int sl = 0; sl < ns; ++sl) {
+        int w = 0;
+        for (int K = sl * kWave; K < std::min(n, (sl + 1) * kWave); ++K) w = std::max(w, rp[K + 1] - rp[K]);
+        if ((int64_t)sp[sl] + (int64_t)w * kWave >= (int64_t(1) << 31))
+            return fail(MFFV_EINVAL, "face-list grid: too many entries after slicing (2^31)");
+        sp[(size_t)sl + 1] = sp[sl] + w * kWave;
+    }
+    const size_t ne = (size_t)sp[ns];
+    std::vector<int> col(ne), ef(ne, -1);
+    for (int K = 0; K < n; ++K) {
+        const int sl = K / kWave, lane = K % kWave;
+        const int w = (sp[(size_t)sl + 1] - sp[sl]) / kWave;
+        for (int j = 0; j < w; ++j) {
+            const size_t e = (size_t)sp[sl] + (size_t)j * kWave + lane;
+            const bool real = j < rp[K + 1] - rp[K];
+            col[e] = real ? rcol[(size_t)rp[K] + j] : K;
+            ef[e] = real ? ref[(size_t)rp[K] + j] : -1;
+        }
     }
     mffv_grid* G = new (std::nothrow) mffv_grid();
     if (!G) return fail(MFFV_ENOMEM, "host allocation failed");
@@ -1144,21 +1167,20 @@ int mffv_create_grid_faces(int n, int nfaces, const int* face_k, const int* face
     G->m64 = G->m32;
     G->nb_vec = (int)std::min<int64_t>(1024, std::max<int64_t>(1, ((int64_t)n / 4 + kThreads - 1) / kThreads));
     G->max_blocks = std::max(nb, G->nb_vec);
-    const size_t ne = (size_t)2 * nfaces;
     int rc;
-    if ((rc = alloc_grid(G, false)) || (rc = dalloc(&G->csr_rp, (size_t)n + 1)) ||
+    if ((rc = alloc_grid(G, false)) || (rc = dalloc(&G->csr_sp, (size_t)ns + 1)) ||
         (ne && ((rc = dalloc(&G->csr_col, ne)) || (rc = dalloc(&G->csr_ef, ne)) || (rc = dalloc(&G->csr_val, ne))))) {
         mffv_destroy_grid(G);
         return rc;
     }
-    if ((e = hipMemcpy(G->csr_rp, rp.data(), rp.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess ||
+    if ((e = hipMemcpy(G->csr_sp, sp.data(), sp.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess ||
         (ne && (e = hipMemcpy(G->csr_col, col.data(), ne * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) ||
         (ne && (e = hipMemcpy(G->csr_ef, ef.data(), ne * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)) {
         mffv_destroy_grid(G);
         return hip_fail(e, "face-list upload");
     }
     if (!G->csr_col) {
-        // a grid without faces: the row pointers are all 0 and no entry is read,
+        // a grid without faces: the slice pointers are all 0 and no entry is read,
         // but the operator form needs non-NULL entry arrays
         if ((rc = dalloc(&G->csr_col, 1)) || (rc = dalloc(&G->csr_ef, 1)) || (rc = dalloc(&G->csr_val, 1))) {
             mffv_destroy_grid(G);
@@ -1181,7 +1203,7 @@ void mffv_destroy_grid(mffv_grid* G) {
     dfree(G->dscal);
     dfree(G->r); dfree(G->p0); dfree(G->p1); dfree(G->q); dfree(G->z); dfree(G->xw);
     dfree(G->bw); dfree(G->st32); dfree(G->step_rhs);
-    dfree(G->csr_rp); dfree(G->csr_col); dfree(G->csr_ef); dfree(G->csr_val);
+    dfree(G->csr_sp); dfree(G->csr_col); dfree(G->csr_ef); dfree(G->csr_val);
     dfree(G->r2); dfree(G->q2); dfree(G->partM); dfree(G->ms);
     dfree(G->r64); dfree(G->p064); dfree(G->p164); dfree(G->q64); dfree(G->x64); dfree(G->b64);
     dfree(G->rres); dfree(G->st64);
@@ -1255,7 +1277,7 @@ int mffv_set_face_transmissibility(mffv_grid* G, const float* T, const float* ac
     drop_graphs(G);
     G->has_coef = false;
     HIP_TRY(hipMemsetAsync(G->flags, 0, 8 * sizeof(int), G->stream));
-    CsrSetupIn in{G->csr_rp, G->csr_col, G->csr_ef, T, accum, accum_scalar, dmask, pD};
+    CsrSetupIn in{G->csr_sp, G->csr_col, G->csr_ef, T, accum, accum_scalar, dmask, pD};
     SetupOut out{G->a, G->a64, nullptr, nullptr, nullptr, G->dinv, G->dmask, b_out, G->flags};
     HIP_TRY(launch_csr_setup(G->g.n, in, out, G->csr_val, G->stream));
     int h[8];

@@ -43,9 +43,13 @@ struct Coef {
     int a_uniform;
     float a_const;
     // face-list (unstructured) operator, NULL on a Cartesian grid: each cell's
-    // faces as a CSR row of neighbour cells and transmissibilities, zero on
-    // every face that touches a Dirichlet cell (the role of tx, ty, tz above)
-    const int* rp;     // row pointers, n + 1
+    // faces as neighbour cells and transmissibilities, zero on every face that
+    // touches a Dirichlet cell (the role of tx, ty, tz above). Sliced layout:
+    // the cells in slices of kWave consecutive cells; slice s holds entries
+    // [sp[s], sp[s+1]), column-major, so entry j of cell K sits at
+    // sp[K / kWave] + j * kWave + K % kWave and a wave reads each entry column
+    // of its slice in one coalesced access. Padding entries carry T = 0.
+    const int* sp;     // slice pointers, ceil(n / kWave) + 1
     const int* col;    // neighbour cell of each entry
     const float* val;  // T of each entry
 };

@@ -198,10 +198,10 @@ struct SetupOut {
     int* flags;  // [0] bad T, [1] bad c, [2] bad pD, [3] #Dirichlet cells, [4] any c > 0
 };
 hipError_t launch_setup(const Geom& g, const SetupIn& in, const SetupOut& out, hipStream_t s);
-// Face-list grids: CSR rows of every cell's faces (entry e: neighbour col[e],
-// face ef[e] of the caller's face array T).
+// Face-list grids: every cell's faces in the sliced layout of Coef (entry e:
+// neighbour col[e], face ef[e] of the caller's face array T, -1 for padding).
 struct CsrSetupIn {
-    const int* rp; const int* col; const int* ef; const float* T;
+    const int* sp; const int* col; const int* ef; const float* T;
     const float* accum; float accum_scalar;
     const uint8_t* dmask; const float* pd;
 };

@@ -578,10 +578,11 @@ __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<
 }
 
 // ---------------------------------------------------------------------------
-// Face-list (unstructured) operator: one thread per cell (grid-stride), the
-// cell's faces a CSR row of (neighbour, T), so that y = a x + sum_f T_f (x -
-// x_nbr) as on the Cartesian grid; modes and the fused CG step as in
-// stencil_s. Faces that touch a Dirichlet cell carry T = 0 and are skipped.
+// Face-list (unstructured) operator: one thread per cell (grid-stride, so a
+// wave always holds one slice of the sliced layout), the cell's faces its
+// (neighbour, T) entries, so that y = a x + sum_f T_f (x - x_nbr) as on the
+// Cartesian grid; modes and the fused CG step as in stencil_s. Faces that
+// touch a Dirichlet cell, and padding, carry T = 0 and are skipped.
 // ---------------------------------------------------------------------------
 template <class real, int MODE>
 __global__ __launch_bounds__(kThreads) void stencil_csr(int64_t n, Coef c, StencilIO<real> io) {
@@ -608,10 +609,28 @@ __global__ __launch_bounds__(kThreads) void stencil_csr(int64_t n, Coef c, Stenc
         const real sc = use_pold ? io.src[K] + beta * poc : io.src[K];
         const real ac = std::is_same<real, double>::value ? (real)c.a64[K] : (real)c.a[K];
         real flux = 0;
-        const int e1 = c.rp[K + 1];
-        for (int e = c.rp[K]; e < e1; ++e) {
-            const float t = c.val[e];
-            if (t != 0.f) flux += (real)t * (sc - S(c.col[e]));
+        const int64_t sl = K / kWave;
+        const int e1 = c.sp[sl + 1];
+        // entries in groups of kGroup: their indices and T, then the gathers,
+        // are in flight together (the sum keeps the entry order). Measured on
+        // a hexahedral mesh: 8 suits the apply, 4 the fused CG step, whose
+        // gathers load two vectors per entry
+        constexpr int kGroup = MODE == kFusedCg ? 4 : 8;
+        for (int e = c.sp[sl] + (int)(K - sl * kWave); e < e1; e += kGroup * kWave) {
+            float t[kGroup];
+            int nbr[kGroup];
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) {
+                const int eu = e + u * kWave;
+                t[u] = eu < e1 ? c.val[eu] : 0.f;
+                nbr[u] = eu < e1 ? c.col[eu] : 0;
+            }
+            real sv[kGroup];
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) sv[u] = t[u] != 0.f ? S(nbr[u]) : sc;
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u)
+                if (t[u] != 0.f) flux += (real)t[u] * (sc - sv[u]);
         }
         const real y = ac * sc + flux;
         if (MODE == kApply) {
@@ -660,7 +679,7 @@ hipError_t launch_v4(const Geom& g, const Coef& c, const StencilIO<float>& io, c
 
 hipError_t launch_stencil_f32(int mode, const Geom& g, const Coef& c, const StencilIO<float>& io,
                               const March& m, hipStream_t s) {
-    if (c.rp) {
+    if (c.sp) {
         switch (mode) {
             case kApply: return launch_csr<float, kApply>(g, c, io, m, s);
             case kFusedCg: return launch_csr<float, kFusedCg>(g, c, io, m, s);
@@ -686,7 +705,7 @@ hipError_t launch_stencil_f32(int mode, const Geom& g, const Coef& c, const Sten
 
 hipError_t launch_stencil_f64(int mode, const Geom& g, const Coef& c, const StencilIO<double>& io,
                               const March& m, hipStream_t s) {
-    if (c.rp) {
+    if (c.sp) {
         switch (mode) {
             case kApply: return launch_csr<double, kApply>(g, c, io, m, s);
             case kFusedCg: return launch_csr<double, kFusedCg>(g, c, io, m, s);

@@ -407,8 +407,9 @@ __global__ __launch_bounds__(kThreads) void setup_kernel(Geom g, SetupIn in, Set
     }
 }
 
-// Face-list operator set-up: one thread per cell over its CSR row (entry e:
-// neighbour col[e], face ef[e]), with the outputs of the Cartesian set-up
+// Face-list operator set-up: one thread per cell over its entries in the
+// sliced layout (entry e: neighbour col[e], face ef[e], -1 for padding), with
+// the outputs of the Cartesian set-up
 // (identity coefficient, masked faces, 1/diag, mask, b, flags). Without a
 // mask no cell is Dirichlet; without pD the Dirichlet values are 0.
 __global__ __launch_bounds__(kThreads) void csr_setup_kernel(int64_t n, CsrSetupIn in, SetupOut out,
@@ -422,8 +423,13 @@ __global__ __launch_bounds__(kThreads) void csr_setup_kernel(int64_t n, CsrSetup
         if (!D && cl > 0.f) anyC = 1;
         out.dmask[l] = D ? 1 : 0;
         double diag = (double)cl, to_d = (double)cl, bsum = 0.0;
-        const int e1 = in.rp[l + 1];
-        for (int e = in.rp[l]; e < e1; ++e) {
+        const int64_t sl = l / kWave;
+        const int e1 = in.sp[sl + 1];
+        for (int e = in.sp[sl] + (int)(l - sl * kWave); e < e1; e += kWave) {
+            if (in.ef[e] < 0) {  // padding of a slice's shorter rows
+                val[e] = 0.f;
+                continue;
+            }
             const float t = in.T[in.ef[e]];
             if (bad_face(t)) badT = 1;
             const int nb = in.col[e];
