@@ -46,7 +46,9 @@ def face_apply_bytes(n: int, nfaces: int) -> int:
     return 12 * n + 16 * nfaces
 
 
-STEP_RHS_BYTES_PER_CELL = 21    # b, p_old, WI, pw (4 B each) and the Dirichlet mask (1 B) read; rhs written
+STEP_RHS_BYTES_PER_CELL = 21
+# arrays read / written per cell by each kernel (FP32), for the streaming probe
+STREAM_MIXES = {"apply": (4, 1), "phase_a_odd": (5, 2), "phase_a_even": (7, 3), "phase_b": (2, 1)}    # b, p_old, WI, pw (4 B each) and the Dirichlet mask (1 B) read; rhs written
 
 
 def phase_a_bytes(k: int) -> int:
@@ -767,6 +769,30 @@ def main(argv=None):
         copy_gbps = 2 * nbytes / (copy_ms * 1e-3) / 1e9
         log(f"copy probe: {copy_gbps:.0f} GB/s (read + write)")
         del src, dst
+        # each kernel's mix of arrays read and written, streamed without its
+        # arithmetic or neighbours: the achievable ceiling of that mix
+        arrs = [torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0) for _ in range(10)]
+        stream_ceil = {}
+        for name, (ni, no) in STREAM_MIXES.items():
+            ins, outs = arrs[:ni], arrs[ni:ni + no]
+            for _ in range(3):
+                mffv.stream_probe(ins, outs, stream=s)
+            e0.record(s)
+            for _ in range(20):
+                mffv.stream_probe(ins, outs, stream=s)
+            e1.record(s)
+            e1.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / 20
+            stream_ceil[name] = {"in": ni, "out": no, "us": us, "GBps": 4 * (ni + no) * n / (us * 1e-6) / 1e9}
+        del arrs
+        # phase A alternates between the odd and even mixes
+        pa_ceiling_us = 0.5 * (stream_ceil["phase_a_odd"]["us"] + stream_ceil["phase_a_even"]["us"])
+        stream_ceil["phase_a_vs_its_mix"] = pa_ceiling_us / phase_a_us
+        stream_ceil["apply_vs_its_mix"] = stream_ceil["apply"]["us"] / (apply_ms * 1e3)
+        log("stream mixes: " + ", ".join(f"{k} {v['us']:.1f} us ({v['GBps']:.0f} GB/s)"
+                                          for k, v in stream_ceil.items() if isinstance(v, dict))
+            + f"; phase A runs at {stream_ceil['phase_a_vs_its_mix']:.2f} of its mix's rate, the apply at "
+              f"{stream_ceil['apply_vs_its_mix']:.2f}")
     torch.cuda.synchronize()
 
     tsteps = None
@@ -834,6 +860,7 @@ def main(argv=None):
         "copy_probe_GBps": copy_gbps,
         "jacobi_pcg": jac,
         "large": large,
+        "stream_ceilings": stream_ceil,
         "time_steps": tsteps,
         "faces": face_res,
         "batched": batched,

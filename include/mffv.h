@@ -489,6 +489,19 @@ int mffv_autotune_batched(mffv_grid* const* grids, int nsys, const float* const*
  */
 int mffv_copy_probe(void* dst, const void* src, size_t bytes, void* stream);
 
+/*
+ * Streaming probe: out[j][i] = sum_k in[k][i] for i < n, j < nout, four
+ * cells per thread with the nontemporal stores of the stencil kernels. With
+ * the numbers of arrays a stencil kernel reads and writes (e.g. 4 in / 1 out
+ * for the apply), its rate is the achievable ceiling for that kernel's mix of
+ * reads and writes, without its arithmetic or neighbour accesses. in and out
+ * are host arrays of nin (1..8) and nout (1..4) device FP32 pointers, 16-byte
+ * aligned; n a multiple of 4; no output may alias an input. Enqueued on
+ * `stream`. Errors: MFFV_EINVAL.
+ */
+int mffv_stream_probe(const float* const* in, int nin, float* const* out, int nout, int64_t n,
+                      void* stream);
+
 #ifdef __cplusplus
 }
 #endif

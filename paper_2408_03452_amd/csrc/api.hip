@@ -1981,6 +1981,28 @@ int mffv_set_batched_watchdog(double seconds) {
     return MFFV_OK;
 }
 
+int mffv_stream_probe(const float* const* in, int nin, float* const* out, int nout, int64_t n,
+                      void* stream) {
+    if (!in || !out || nin < 1 || nin > kStreamProbeIn || nout < 1 || nout > kStreamProbeOut)
+        return fail(MFFV_EINVAL, "stream probe: 1..8 input and 1..4 output arrays");
+    if (n < 0 || n % 4) return fail(MFFV_EINVAL, "stream probe: n must be a multiple of 4");
+    StreamProbeIO io{};
+    io.nin = nin;
+    io.nout = nout;
+    for (int k = 0; k < nin; ++k) {
+        if (!in[k] || (uintptr_t)in[k] % 16) return fail(MFFV_EINVAL, "stream probe: 16-byte aligned inputs");
+        io.in[k] = in[k];
+    }
+    for (int j = 0; j < nout; ++j) {
+        if (!out[j] || (uintptr_t)out[j] % 16) return fail(MFFV_EINVAL, "stream probe: 16-byte aligned outputs");
+        for (int k = 0; k < nin; ++k)
+            if ((const float*)out[j] == in[k]) return fail(MFFV_EINVAL, "stream probe: an output aliases an input");
+        io.out[j] = out[j];
+    }
+    HIP_TRY(launch_stream_probe(n, io, static_cast<hipStream_t>(stream)));
+    return MFFV_OK;
+}
+
 int mffv_copy_probe(void* dst, const void* src, size_t bytes, void* stream) {
     if (!dst || !src) return fail(MFFV_EINVAL, "NULL pointer");
     if (bytes % 16 || (uintptr_t)dst % 16 || (uintptr_t)src % 16)

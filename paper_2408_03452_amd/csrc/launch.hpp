@@ -141,6 +141,14 @@ hipError_t launch_step_rhs(int64_t n, const StepRhsIn& in, float* rhs, hipStream
 hipError_t launch_convert_f64_to_f32(int64_t n, const double* a, float* b, hipStream_t s);
 hipError_t launch_fill_f32(int64_t n, float* a, float v, hipStream_t s);
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s);
+constexpr int kStreamProbeIn = 8, kStreamProbeOut = 4;
+struct StreamProbeIO {
+    const float* in[kStreamProbeIn];
+    float* out[kStreamProbeOut];
+    int nin, nout;
+};
+// n FP32 cells (a multiple of 4), 16-byte aligned arrays
+hipError_t launch_stream_probe(int64_t n, const StreamProbeIO& io, hipStream_t s);
 hipError_t launch_merged_init(MergedState* ms, float tol2, int max_iter, hipStream_t s);
 hipError_t launch_jacobi_z(int64_t n, const float* r, const float* dinv, const uint8_t* dmask, float* z,
                            hipStream_t s);

@@ -313,6 +313,28 @@ __global__ __launch_bounds__(kThreads) void copy_probe(const uint4* __restrict__
         dst[e] = src[e];
 }
 
+// Streaming probe: every output array receives the sum of the input arrays,
+// four cells per thread, with the nontemporal stores the stencil kernels use:
+// the achievable rate of a kernel that streams the same numbers of arrays in
+// and out as a given stencil kernel, without its arithmetic or neighbours.
+typedef float sp4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(kThreads) void stream_probe(int64_t n4, StreamProbeIO io) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n4; e += stride) {
+        sp4 v[kStreamProbeIn];
+#pragma unroll
+        for (int k = 0; k < kStreamProbeIn; ++k)
+            if (k < io.nin) v[k] = reinterpret_cast<const sp4*>(io.in[k])[e];
+        sp4 sum = v[0];
+#pragma unroll
+        for (int k = 1; k < kStreamProbeIn; ++k)
+            if (k < io.nin) sum += v[k];
+#pragma unroll
+        for (int j = 0; j < kStreamProbeOut; ++j)
+            if (j < io.nout) __builtin_nontemporal_store(sum, reinterpret_cast<sp4*>(io.out[j]) + e);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Operator set-up.
 // ---------------------------------------------------------------------------
@@ -634,6 +656,12 @@ hipError_t launch_merged_init(MergedState* ms, float tol2, int max_iter, hipStre
 hipError_t launch_differ(int64_t n, const float* a, const float* b, int* flag, hipStream_t s) {
     hipLaunchKernelGGL(differ, dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n,
                        reinterpret_cast<const uint32_t*>(a), reinterpret_cast<const uint32_t*>(b), flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_probe(int64_t n, const StreamProbeIO& io, hipStream_t s) {
+    const int64_t n4 = n / 4;
+    hipLaunchKernelGGL(stream_probe, dim3(grid_for(n4, 4, 16384)), dim3(kThreads), 0, s, n4, io);
     return hipGetLastError();
 }
 

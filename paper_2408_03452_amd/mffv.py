@@ -99,6 +99,8 @@ def _declare(lib):
         "mffv_time_steps": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_float, _P, _P, _P, _P,
                                            ctypes.POINTER(Opts), _P]),
         "mffv_copy_probe": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
+        "mffv_stream_probe": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(_P), ctypes.c_int,
+                                             ctypes.c_int64, _P]),
         "mffv_net_num_params": (ctypes.c_int, []),
         "mffv_net_create": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
         "mffv_net_destroy": (None, [_P]),
@@ -403,6 +405,15 @@ def autotune_batched(grids, b, x, opts: Opts | None = None) -> dict:
     _check(lib().mffv_autotune_batched(G, ns, B, X, ctypes.byref(opts) if opts is not None else None,
                                        ctypes.byref(bpc), ctypes.byref(ipb), ctypes.byref(ms)))
     return {"blocks_per_cu": bpc.value, "items_per_block": ipb.value, "ms": ms.value}
+
+
+def stream_probe(ins, outs, stream=None) -> None:
+    """Streaming probe (mffv_stream_probe): every tensor of outs receives the
+    sum of the tensors of ins (FP32 device tensors of one length)."""
+    n = ins[0].numel()
+    I = (_P * len(ins))(*[_ptr(t, torch.float32, n, "in") for t in ins])
+    O = (_P * len(outs))(*[_ptr(t, torch.float32, n, "out") for t in outs])
+    _check(lib().mffv_stream_probe(I, len(ins), O, len(outs), n, _stream(stream)))
 
 
 def copy_probe(dst, src, nbytes: int, stream=None) -> None:
