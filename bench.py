@@ -315,11 +315,13 @@ def bench_time_steps(log_fn, shape, tx, ty, tz, nsteps: int = 8):
     return res
 
 
-def bench_faces(log_fn, shape, tx, ty, tz, c, cg_iters: int = 200):
+def bench_faces(log_fn, shape, tx, ty, tz, c, cg_iters: int = 200, rcm: bool = False):
     """The headline grid and field as a face-list mesh (3 x 256^2 x 255 faces):
     the face-list apply in the Cartesian numbering and with the cells randomly
     renumbered, and the face-list CG iteration rate over a fixed number of
-    iterations, each timed with HIP events on the grid's stream."""
+    iterations, each timed with HIP events on the grid's stream. With rcm, the
+    random numbering is also renumbered by mffv_face_order (reverse
+    Cuthill-McKee on the host) and timed again."""
     import numpy as np
     import torch
     from paper_2408_03452_amd import mffv
@@ -343,7 +345,15 @@ def bench_faces(log_fn, shape, tx, ty, tz, c, cg_iters: int = 200):
         del fk_t, ax_t
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         rng = np.random.default_rng(7)
-        for label, perm in (("cartesian_order", None), ("random_order", rng.permutation(n))):
+        rand = rng.permutation(n)
+        cases = [("cartesian_order", None), ("random_order", rand)]
+        if rcm:
+            t0 = time.perf_counter()
+            new = mffv.face_order(n, rand[fk], rand[fl])
+            res["rcm_host_s"] = time.perf_counter() - t0
+            log_fn(f"faces: reverse Cuthill-McKee of the random numbering on the host, {res['rcm_host_s']:.1f} s")
+            cases.append(("rcm_of_random_order", new.astype(np.int64)[rand]))
+        for label, perm in cases:
             if perm is None:
                 g = mffv.create_grid_faces(n, fk, fl, stream=s)
                 dm, pdv = dmask.ravel(), pd.ravel()
@@ -623,6 +633,8 @@ def main(argv=None):
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-timesteps", action="store_true")
     ap.add_argument("--no-faces", action="store_true")
+    ap.add_argument("--faces-rcm", action="store_true",
+                    help="also renumber the randomly numbered face-list mesh with mffv_face_order (about 30 s on the host)")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-held-out", type=int, default=10,
                     help="held-out 128^3 realisations in the learned comparison (50 = full set)")
@@ -800,7 +812,7 @@ def main(argv=None):
         tsteps = bench_time_steps(log, w.shape, tx, ty, tz)
     face_res = None
     if not args.no_faces:
-        face_res = bench_faces(log, w.shape, tx, ty, tz, w.c)
+        face_res = bench_faces(log, w.shape, tx, ty, tz, w.c, rcm=args.faces_rcm)
     del tx, ty, tz
     large = None
     if not args.no_large:

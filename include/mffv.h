@@ -207,6 +207,18 @@ int mffv_set_transmissibility(mffv_grid* grid, const float* tx, const float* ty,
  */
 int mffv_create_grid_faces(int n, int nfaces, const int* face_k, const int* face_l, void* stream,
                            mffv_grid** out);
+
+/*
+ * A locality-preserving numbering of a face-list mesh (host only, no device
+ * work): reverse Cuthill-McKee (breadth-first from a pseudo-peripheral cell
+ * of each connected component, neighbours by increasing degree, the whole
+ * order reversed). new_index (host, n ints) receives the new number of every
+ * cell, a permutation of [0, n). Renumbering the mesh with it before
+ * mffv_create_grid_faces keeps neighbouring cells close in memory, which the
+ * face-list kernels' neighbour gathers need. Faces as for
+ * mffv_create_grid_faces. Errors: MFFV_EINVAL.
+ */
+int mffv_face_order(int n, int nfaces, const int* face_k, const int* face_l, int* new_index);
 int mffv_set_face_transmissibility(mffv_grid* grid, const float* T, const float* accum,
                                    float accum_scalar, const uint8_t* dmask, const float* pD,
                                    float* b_out);

@@ -1101,6 +1101,89 @@ int mffv_create_grid(int nx, int ny, int nz, void* stream, mffv_grid** out) {
     return MFFV_OK;
 }
 
+int mffv_face_order(int n, int nfaces, const int* face_k, const int* face_l, int* new_index) {
+    if (n < 1 || nfaces < 0 || !new_index) return fail(MFFV_EINVAL, "face order needs n >= 1, nfaces >= 0, new_index");
+    if (nfaces > 0 && (!face_k || !face_l)) return fail(MFFV_EINVAL, "face_k and face_l must be host arrays");
+    if ((int64_t)nfaces * 2 >= (int64_t(1) << 31)) return fail(MFFV_EINVAL, "2^30 faces or more");
+    // adjacency of the cell graph
+    std::vector<int> rp((size_t)n + 1, 0);
+    for (int f = 0; f < nfaces; ++f) {
+        const int k = face_k[f], l = face_l[f];
+        if (k < 0 || k >= n || l < 0 || l >= n || k == l)
+            return fail(MFFV_EINVAL, "face " + std::to_string(f) + " must join two different cells in [0, n)");
+        ++rp[(size_t)k + 1];
+        ++rp[(size_t)l + 1];
+    }
+    for (int i = 0; i < n; ++i) rp[(size_t)i + 1] += rp[i];
+    std::vector<int> adj((size_t)2 * nfaces), fill(rp.begin(), rp.end() - 1);
+    for (int f = 0; f < nfaces; ++f) {
+        adj[fill[face_k[f]]++] = face_l[f];
+        adj[fill[face_l[f]]++] = face_k[f];
+    }
+    auto deg = [&](int v) { return rp[(size_t)v + 1] - rp[v]; };
+    // each cell's neighbours by increasing degree (ties by index), as
+    // Cuthill-McKee visits them
+    for (int v = 0; v < n; ++v)
+        std::sort(adj.begin() + rp[v], adj.begin() + rp[(size_t)v + 1], [&](int a, int b) {
+            return deg(a) != deg(b) ? deg(a) < deg(b) : a < b;
+        });
+    std::vector<int> order;
+    order.reserve((size_t)n);
+    std::vector<int> level((size_t)n, -1);
+    // breadth-first sweep from `root` over its unvisited component: returns the
+    // visited cells in order (appended to `out`) and marks them with `mark`
+    std::vector<int> stamp((size_t)n, 0);
+    int sweep_id = 0;
+    auto bfs = [&](int root, std::vector<int>& out) {
+        ++sweep_id;
+        const size_t first = out.size();
+        out.push_back(root);
+        stamp[root] = sweep_id;
+        level[root] = 0;
+        for (size_t h = first; h < out.size(); ++h) {
+            const int v = out[h];
+            for (int e = rp[v]; e < rp[(size_t)v + 1]; ++e) {
+                const int w = adj[e];
+                if (stamp[w] == sweep_id || level[w] == -2) continue;
+                stamp[w] = sweep_id;
+                level[w] = level[v] + 1;
+                out.push_back(w);
+            }
+        }
+        return first;
+    };
+    std::vector<int> scratch;
+    for (int s0 = 0; s0 < n; ++s0) {
+        if (level[s0] == -2) continue;
+        // start: a cell of minimum degree in this component, moved twice to a
+        // minimum-degree cell of the last breadth-first level (pseudo-peripheral)
+        int root = s0;
+        for (int pass = 0; pass < 3; ++pass) {
+            scratch.clear();
+            bfs(root, scratch);
+            int best = root, last = level[scratch.back()];
+            if (pass == 0) {
+                for (int v : scratch)
+                    if (deg(v) < deg(best) || (deg(v) == deg(best) && v < best)) best = v;
+            } else {
+                best = scratch.back();
+                for (int v : scratch)
+                    if (level[v] == last && (deg(v) < deg(best) || (deg(v) == deg(best) && v < best))) best = v;
+            }
+            root = best;
+        }
+        scratch.clear();
+        bfs(root, scratch);
+        for (int v : scratch) {
+            level[v] = -2;  // numbered
+            order.push_back(v);
+        }
+    }
+    // reversed Cuthill-McKee order: the last visited cell gets index 0
+    for (int i = 0; i < n; ++i) new_index[order[(size_t)n - 1 - i]] = i;
+    return MFFV_OK;
+}
+
 int mffv_create_grid_faces(int n, int nfaces, const int* face_k, const int* face_l, void* stream,
                            mffv_grid** out) {
     if (!out) return fail(MFFV_EINVAL, "out is NULL");

@@ -95,6 +95,7 @@ def _declare(lib):
                                                  ctypes.POINTER(Opts), _P]),
         "mffv_create_grid_faces": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _P, _P, ctypes.POINTER(_P)]),
         "mffv_set_face_transmissibility": (ctypes.c_int, [_P, _P, _P, ctypes.c_float, _P, _P, _P]),
+        "mffv_face_order": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _P, _P]),
         "mffv_step_rhs": (ctypes.c_int, [_P, _P, _P, ctypes.c_float, _P, _P, _P, _P, _P]),
         "mffv_time_steps": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_float, _P, _P, _P, _P,
                                            ctypes.POINTER(Opts), _P]),
@@ -247,6 +248,18 @@ def create_grid_faces(n: int, face_k, face_l, stream=None) -> Grid:
     g = Grid(h.value, (int(n), 1, 1), s)
     g.nfaces = int(fk.size)
     return g
+
+
+def face_order(n: int, face_k, face_l):
+    """Reverse Cuthill-McKee numbering of a face-list mesh (mffv_face_order):
+    a host int32 array, the new number of every cell."""
+    import numpy as np
+    fk = np.ascontiguousarray(face_k, dtype=np.int32)
+    fl = np.ascontiguousarray(face_l, dtype=np.int32)
+    out = np.empty(int(n), dtype=np.int32)
+    _check(lib().mffv_face_order(int(n), int(fk.size), fk.ctypes.data if fk.size else None,
+                                 fl.ctypes.data if fl.size else None, out.ctypes.data))
+    return out
 
 
 def set_face_transmissibility(grid: Grid, T, accum=None, accum_scalar=0.0, dmask=None, pD=None,
