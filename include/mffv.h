@@ -6,7 +6,12 @@
  * (Sai et al., "Matrix-Free Finite Volume Kernels on a Dataflow Architecture",
  * Sec. II-A, Eq. 3, 4 and 6, Alg. 1 and Alg. 2). The operator is never
  * assembled: each application reads the face transmissibilities and forms
- * T_KL (x_K - x_L) on the six face neighbours of every cell.
+ * T_KL (x_K - x_L) on the six face neighbours of every cell. The same
+ * operator runs on face-list (unstructured) meshes (mffv_create_grid_faces),
+ * and backward-Euler time steps with wells are solved one after another
+ * (mffv_time_steps). Conventions below are stated for the Cartesian grid; a
+ * face-list grid has n cells numbered by the caller and its faces in place of
+ * tx, ty, tz.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
