@@ -581,65 +581,53 @@ __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<
 // Face-list (unstructured) operator: one thread per cell (grid-stride, so a
 // wave always holds one slice of the sliced layout), the cell's faces its
 // (neighbour, T) entries, so that y = a x + sum_f T_f (x - x_nbr) as on the
-// Cartesian grid; modes and the fused CG step as in stencil_s. Faces that
-// touch a Dirichlet cell, and padding, carry T = 0 and are skipped.
+// Cartesian grid. Faces that touch a Dirichlet cell, and padding, carry T = 0
+// and are skipped.
 // ---------------------------------------------------------------------------
+// sum_f T_f (x_K - x_nbr) over cell K's entries. The entries go in groups of
+// kGroup: their indices and T, then their gathers, are in flight together,
+// and the sum keeps the entry order.
+template <class real>
+__device__ __forceinline__ real csr_flux(const Coef& c, int64_t K, real xk, const real* __restrict__ x) {
+    constexpr int kGroup = 8;
+    real flux = 0;
+    const int64_t sl = K / kWave;
+    const int e1 = c.sp[sl + 1];
+    for (int e = c.sp[sl] + (int)(K - sl * kWave); e < e1; e += kGroup * kWave) {
+        float t[kGroup];
+        int nbr[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            const int eu = e + u * kWave;
+            t[u] = eu < e1 ? c.val[eu] : 0.f;
+            nbr[u] = eu < e1 ? c.col[eu] : 0;
+        }
+        real xv[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) xv[u] = t[u] != 0.f ? x[nbr[u]] : xk;
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u)
+            if (t[u] != 0.f) flux += (real)t[u] * (xk - xv[u]);
+    }
+    return flux;
+}
+
+template <class real>
+__device__ __forceinline__ real csr_diag(const Coef& c, int64_t K) {
+    return std::is_same<real, double>::value ? (real)c.a64[K] : (real)c.a[K];
+}
+
+// apply (y = A x) and residual (r = b - A x, with r.r partials if asked)
 template <class real, int MODE>
 __global__ __launch_bounds__(kThreads) void stencil_csr(int64_t n, Coef c, StencilIO<real> io) {
     __shared__ real red[kThreads / kWave];
-
-    PhaseA<real> ph{0, real(0), real(0), real(0), false};
-    if (MODE == kFusedCg && !phase_a_start(io, red, ph)) return;
-    const int it = ph.k;
-    const real beta = ph.beta, alpha_prev = ph.alpha_prev, alpha_prev2 = ph.alpha_prev2;
-    const bool pending = it >= 2 && (it & 1) == 0;
-    const real* pold = (it & 1) ? io.p0 : io.p1;
-    real* pnew = (it & 1) ? io.p1 : io.p0;
-    const bool use_pold = (MODE == kFusedCg) && it > 0;
-    auto S = [&](int64_t idx) -> real {
-        real v = io.src[idx];
-        if (use_pold) v += beta * pold[idx];
-        return v;
-    };
-
     real dot = 0;
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     for (int64_t K = (int64_t)blockIdx.x * kThreads + threadIdx.x; K < n; K += stride) {
-        const real poc = use_pold ? pold[K] : real(0);
-        const real sc = use_pold ? io.src[K] + beta * poc : io.src[K];
-        const real ac = std::is_same<real, double>::value ? (real)c.a64[K] : (real)c.a[K];
-        real flux = 0;
-        const int64_t sl = K / kWave;
-        const int e1 = c.sp[sl + 1];
-        // entries in groups of kGroup: their indices and T, then the gathers,
-        // are in flight together (the sum keeps the entry order). Measured on
-        // a hexahedral mesh: 8 suits the apply, 4 the fused CG step, whose
-        // gathers load two vectors per entry
-        constexpr int kGroup = MODE == kFusedCg ? 4 : 8;
-        for (int e = c.sp[sl] + (int)(K - sl * kWave); e < e1; e += kGroup * kWave) {
-            float t[kGroup];
-            int nbr[kGroup];
-#pragma unroll
-            for (int u = 0; u < kGroup; ++u) {
-                const int eu = e + u * kWave;
-                t[u] = eu < e1 ? c.val[eu] : 0.f;
-                nbr[u] = eu < e1 ? c.col[eu] : 0;
-            }
-            real sv[kGroup];
-#pragma unroll
-            for (int u = 0; u < kGroup; ++u) sv[u] = t[u] != 0.f ? S(nbr[u]) : sc;
-#pragma unroll
-            for (int u = 0; u < kGroup; ++u)
-                if (t[u] != 0.f) flux += (real)t[u] * (sc - sv[u]);
-        }
-        const real y = ac * sc + flux;
+        const real xk = io.src[K];
+        const real y = csr_diag<real>(c, K) * xk + csr_flux(c, K, xk, io.src);
         if (MODE == kApply) {
             io.out[K] = y;
-        } else if (MODE == kFusedCg) {
-            if (pending) io.xsol[K] += alpha_prev2 * pnew[K] + alpha_prev * poc;
-            pnew[K] = sc;
-            io.out[K] = y;
-            dot += sc * y;
         } else {
             const real bb = io.rhs_f64 ? (real) static_cast<const double*>(io.rhs)[K]
                                        : (real) static_cast<const float*>(io.rhs)[K];
@@ -648,17 +636,68 @@ __global__ __launch_bounds__(kThreads) void stencil_csr(int64_t n, Coef c, Stenc
             dot += r * r;
         }
     }
-    if (MODE == kFusedCg || (MODE == kResidual && io.partials != nullptr)) {
+    if (MODE == kResidual && io.partials != nullptr) {
         const real tot = block_sum(dot, red);
         if (threadIdx.x == 0) io.partials[blockIdx.x] = tot;
     }
 }
 
+// The face-list CG step in two kernels. Forming p = r + beta p_old at every
+// neighbour on the fly, as the Cartesian kernels do, costs two gathers per
+// face here; instead the first kernel forms p elementwise (with the deferred
+// solution update) and the second applies A to the stored p, gathering one
+// vector. The second finds the iteration in the state the first recorded.
+template <class real>
+__global__ __launch_bounds__(kThreads) void csr_direction(int64_t n, StencilIO<real> io) {
+    __shared__ real red[kThreads / kWave];
+    PhaseA<real> ph{0, real(0), real(0), real(0), false};
+    if (!phase_a_start(io, red, ph)) return;
+    const int it = ph.k;
+    const real beta = ph.beta, alpha_prev = ph.alpha_prev, alpha_prev2 = ph.alpha_prev2;
+    const bool pending = it >= 2 && (it & 1) == 0;
+    const real* pold = (it & 1) ? io.p0 : io.p1;
+    real* pnew = (it & 1) ? io.p1 : io.p0;
+    const bool use_pold = it > 0;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t K = (int64_t)blockIdx.x * kThreads + threadIdx.x; K < n; K += stride) {
+        const real poc = use_pold ? pold[K] : real(0);
+        const real sc = use_pold ? io.src[K] + beta * poc : io.src[K];
+        if (pending) io.xsol[K] += alpha_prev2 * pnew[K] + alpha_prev * poc;
+        pnew[K] = sc;
+    }
+}
+
+template <class real>
+__global__ __launch_bounds__(kThreads) void csr_apply_dot(int64_t n, Coef c, StencilIO<real> io) {
+    __shared__ real red[kThreads / kWave];
+    if (block_flag(&io.st->done)) return;
+    const int it = io.st->iterB;  // recorded by csr_direction for this iteration
+    const real* p = (it & 1) ? io.p1 : io.p0;
+    real dot = 0;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t K = (int64_t)blockIdx.x * kThreads + threadIdx.x; K < n; K += stride) {
+        const real pk = p[K];
+        const real y = csr_diag<real>(c, K) * pk + csr_flux(c, K, pk, p);
+        io.out[K] = y;
+        dot += pk * y;
+    }
+    const real tot = block_sum(dot, red);
+    if (threadIdx.x == 0) io.partials[blockIdx.x] = tot;
+}
+
 template <class real, int MODE>
 hipError_t launch_csr(const Geom& g, const Coef& c, const StencilIO<real>& io, const March& m,
                       hipStream_t s) {
-    hipLaunchKernelGGL((stencil_csr<real, MODE>), dim3(m.blocks()), dim3(kThreads), 0, s, g.n, c, io);
-    return hipGetLastError();
+    if constexpr (MODE == kFusedCg) {
+        hipLaunchKernelGGL((csr_direction<real>), dim3(m.blocks()), dim3(kThreads), 0, s, g.n, io);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((csr_apply_dot<real>), dim3(m.blocks()), dim3(kThreads), 0, s, g.n, c, io);
+        return hipGetLastError();
+    } else {
+        hipLaunchKernelGGL((stencil_csr<real, MODE>), dim3(m.blocks()), dim3(kThreads), 0, s, g.n, c, io);
+        return hipGetLastError();
+    }
 }
 
 template <class real, int MODE>
