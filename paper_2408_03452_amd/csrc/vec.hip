@@ -522,6 +522,35 @@ __global__ __launch_bounds__(kThreads) void step_rhs_kernel(int64_t n, StepRhsIn
     }
 }
 
+// The same, four cells per thread (n % 4 == 0, 16-byte aligned arrays).
+__global__ __launch_bounds__(kThreads) void step_rhs_v4(int64_t n4, StepRhsIn in, float4* __restrict__ rhs) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n4; e += stride) {
+        const float4 b = reinterpret_cast<const float4*>(in.b)[e];
+        const uchar4 d = reinterpret_cast<const uchar4*>(in.dmask)[e];
+        const float4 p = reinterpret_cast<const float4*>(in.p_old)[e];
+        const float4 c = in.c ? reinterpret_cast<const float4*>(in.c)[e] : make_float4(in.c_scalar, in.c_scalar,
+                                                                                        in.c_scalar, in.c_scalar);
+        float4 w = make_float4(0.f, 0.f, 0.f, 0.f), pw = w, q = w;
+        if (in.wi) {
+            w = reinterpret_cast<const float4*>(in.wi)[e];
+            pw = reinterpret_cast<const float4*>(in.pw)[e];
+        }
+        if (in.q) q = reinterpret_cast<const float4*>(in.q)[e];
+        auto cell = [&](float bv, unsigned char dv, float pv, float cv, float wv, float pwv, float qv) {
+            float v = bv;
+            if (!dv) {
+                v += cv * pv;
+                if (in.wi) v += wv * pwv;
+                if (in.q) v += qv;
+            }
+            return v;
+        };
+        rhs[e] = make_float4(cell(b.x, d.x, p.x, c.x, w.x, pw.x, q.x), cell(b.y, d.y, p.y, c.y, w.y, pw.y, q.y),
+                             cell(b.z, d.z, p.z, c.z, w.z, pw.z, q.z), cell(b.w, d.w, p.w, c.w, w.w, pw.w, q.w));
+    }
+}
+
 int grid_for(int64_t n, int per_thread = 1, int cap = 8192) {
     int64_t b = (n / per_thread + kThreads - 1) / kThreads;
     if (b < 1) b = 1;
@@ -689,7 +718,16 @@ hipError_t launch_csr_setup(int64_t n, const CsrSetupIn& in, const SetupOut& out
 }
 
 hipError_t launch_step_rhs(int64_t n, const StepRhsIn& in, float* rhs, hipStream_t s) {
-    hipLaunchKernelGGL(step_rhs_kernel, dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, in, rhs);
+    auto a16 = [](const void* p) { return ((uintptr_t)p % 16) == 0; };
+    const bool v4 = n % 4 == 0 && a16(in.b) && a16(in.p_old) && a16(rhs) && (uintptr_t)in.dmask % 4 == 0 &&
+                    (!in.c || a16(in.c)) && (!in.wi || (a16(in.wi) && a16(in.pw))) && (!in.q || a16(in.q));
+    if (v4) {
+        const int64_t n4 = n / 4;
+        hipLaunchKernelGGL(step_rhs_v4, dim3(grid_for(n4, 4)), dim3(kThreads), 0, s, n4, in,
+                           reinterpret_cast<float4*>(rhs));
+    } else {
+        hipLaunchKernelGGL(step_rhs_kernel, dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, in, rhs);
+    }
     return hipGetLastError();
 }
 

@@ -52,8 +52,8 @@ def setup(mf, k, c, wi, s):
     return g, b
 
 
-def test_step_rhs_matches_oracle(mf):
-    shape = (21, 17, 19)
+@pytest.mark.parametrize("shape", [(21, 17, 19), (20, 16, 12)])   # one cell per thread; four
+def test_step_rhs_matches_oracle(mf, shape):
     k, c, wi, pw, q, p0 = wells_case(shape, 5)
     ref = OracleProblem(k, accum=c + wi)
     p0[ref.dmask] = ref.pd[ref.dmask]
