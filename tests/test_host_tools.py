@@ -96,3 +96,19 @@ def test_bench_phase_a_byte_model():
     assert bench.phase_a_bytes_mean(64) == 33.75
     assert bench.PHASE_A_BYTES_PER_CELL == (28 + 40) / 2
     assert bench.CG_BYTES_PER_CELL_ITER == bench.PHASE_A_BYTES_PER_CELL + bench.PHASE_B_BYTES_PER_CELL
+
+
+def test_stream_mixes_match_the_byte_model():
+    """Each kernel's mix of FP32 arrays read / written, streamed by the probe,
+    moves the kernel's algorithmic bytes per cell: apply 20, phase A 28 (odd k)
+    and 40 (even k), phase B 12."""
+    import bench
+    m = bench.STREAM_MIXES
+    assert 4 * sum(m["apply"]) == bench.APPLY_BYTES_PER_CELL
+    assert 4 * sum(m["phase_a_odd"]) == bench.phase_a_bytes(1)
+    assert 4 * sum(m["phase_a_even"]) == bench.phase_a_bytes(2)
+    assert 4 * sum(m["phase_b"]) == bench.PHASE_B_BYTES_PER_CELL
+    # writes: apply y; phase A p, q (+ x on even k); phase B r
+    assert [m[k][1] for k in ("apply", "phase_a_odd", "phase_a_even", "phase_b")] == [1, 2, 3, 1]
+    # face-list apply: 12 B per cell and 16 B per face
+    assert bench.face_apply_bytes(10, 3) == 12 * 10 + 16 * 3
