@@ -459,10 +459,11 @@ int mffv_set_launch(mffv_grid* grid, int ci, int remap, int seg);
  * every candidate (ci in 1..64 planes per block, XCD-aware order on or off,
  * flat chunks or row segments of 32..256 cells)
  * must reproduce the default shape's apply bit for bit; it is then timed on
- * the grid's own operator with HIP events, as an apply and as the fused CG
- * phase A (the solver's hot kernel) over the first 32 iterations of a solve. The
- * shape with the fastest phase A is applied to the CG kernels and the one with
- * the fastest apply to mffv_apply. With a cache_path (may be NULL), a
+ * the grid's own operator with HIP events, as an apply and as the CG iteration
+ * (fused phase A, the solver's hot kernel, plus phase B, whose prologue sums
+ * one partial per phase-A block) over the first 32 iterations of a solve. The
+ * shape with the fastest iteration is applied to the CG kernels and the one
+ * with the fastest apply to mffv_apply. With a cache_path (may be NULL), a
  * previous result for the same device architecture and shape is reused, and a
  * new one is written to that JSON file. Uses the grid's workspace (overwrites
  * the solver's work vectors); synchronizes.

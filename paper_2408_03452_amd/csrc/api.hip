@@ -1856,7 +1856,7 @@ int mffv_autotune(mffv_grid* G, const char* cache_path, mffv_tune_result* out) {
         const March keep = G->m32;
         // time one shape: its apply (reps launches) and phase A over the first 32
         // iterations of a solve of A x = dinv; returns an error code
-        auto time_shape = [&](const March& m, int reps, double* apply_us, double* pa_us) -> int {
+        auto time_shape = [&](const March& m, int reps, double* apply_us, double* pa_us, double* it_us) -> int {
             HIP_TRY(hipEventRecord(e0, G->stream));
             for (int t = 0; t < reps; ++t)
                 HIP_TRY(launch_stencil_f32(kApply, G->g, coef_of(G), io, m, G->stream));
@@ -1882,11 +1882,14 @@ int mffv_autotune(mffv_grid* G, const char* cache_path, mffv_tune_result* out) {
             mffv_info inf{};
             if ((r = timing_end(G, &inf))) return r;
             *pa_us = inf.timed_iters > 0 ? inf.phase_a_us : *apply_us;
+            // the whole iteration: phase B's prologue sums one partial per
+            // phase-A block, so the shape changes its cost too
+            *it_us = inf.timed_iters > 0 ? inf.phase_a_us + inf.phase_b_us : *apply_us;
             return MFFV_OK;
         };
         struct Cand {
             March m;
-            double apply_us, pa_us;
+            double apply_us, pa_us, it_us;
         };
         std::vector<Cand> cands;
         const int cis[] = {1, 2, 4, 8, 16, 32, 64};
@@ -1910,8 +1913,8 @@ int mffv_autotune(mffv_grid* G, const char* cache_path, mffv_tune_result* out) {
                 HIP_TRY(hipMemcpyAsync(&differs, G->flags + 5, sizeof(int), hipMemcpyDeviceToHost, G->stream));
                 HIP_TRY(hipStreamSynchronize(G->stream));
                 if (differs) continue;
-                Cand cd{m, 0, 0};
-                if ((rc = time_shape(m, 10, &cd.apply_us, &cd.pa_us))) return rc;
+                Cand cd{m, 0, 0, 0};
+                if ((rc = time_shape(m, 10, &cd.apply_us, &cd.pa_us, &cd.it_us))) return rc;
                 cands.push_back(cd);
                 ++tried;
             }
@@ -1922,19 +1925,22 @@ int mffv_autotune(mffv_grid* G, const char* cache_path, mffv_tune_result* out) {
             std::vector<size_t> idx(cands.size());
             for (size_t t = 0; t < idx.size(); ++t) idx[t] = t;
             std::sort(idx.begin(), idx.end(), [&](size_t x, size_t y) {
-                return by_apply ? cands[x].apply_us < cands[y].apply_us : cands[x].pa_us < cands[y].pa_us;
+                return by_apply ? cands[x].apply_us < cands[y].apply_us : cands[x].it_us < cands[y].it_us;
             });
             idx.resize(std::min<size_t>(idx.size(), 4));
             double best = 1e30;
             for (size_t t : idx) {
                 for (int rep = 0; rep < 2; ++rep) {
-                    double a = 0, pa = 0;
-                    int r = time_shape(cands[t].m, 50, &a, &pa);
+                    double a = 0, pa = 0, it = 0;
+                    int r = time_shape(cands[t].m, 50, &a, &pa, &it);
                     if (r) return r;
                     cands[t].apply_us = std::min(cands[t].apply_us, a);
-                    cands[t].pa_us = std::min(cands[t].pa_us, pa);
+                    if (it < cands[t].it_us) {  // phase A of the fastest iteration
+                        cands[t].it_us = it;
+                        cands[t].pa_us = pa;
+                    }
                 }
-                const double v = by_apply ? cands[t].apply_us : cands[t].pa_us;
+                const double v = by_apply ? cands[t].apply_us : cands[t].it_us;
                 if (v < best) {
                     best = v;
                     const March& m = cands[t].m;
@@ -1948,7 +1954,7 @@ int mffv_autotune(mffv_grid* G, const char* cache_path, mffv_tune_result* out) {
                         rec.ci = m.ci;
                         rec.remap = m.remap;
                         rec.seg = sgv;
-                        rec.pa_us = v;
+                        rec.pa_us = cands[t].pa_us;
                     }
                 }
             }
