@@ -1120,62 +1120,57 @@ int mffv_face_order(int n, int nfaces, const int* face_k, const int* face_l, int
         adj[fill[face_k[f]]++] = face_l[f];
         adj[fill[face_l[f]]++] = face_k[f];
     }
-    auto deg = [&](int v) { return rp[(size_t)v + 1] - rp[v]; };
+    std::vector<int> dg((size_t)n);
+    for (int v = 0; v < n; ++v) dg[v] = rp[(size_t)v + 1] - rp[v];
     // each cell's neighbours by increasing degree (ties by index), as
     // Cuthill-McKee visits them
     for (int v = 0; v < n; ++v)
         std::sort(adj.begin() + rp[v], adj.begin() + rp[(size_t)v + 1], [&](int a, int b) {
-            return deg(a) != deg(b) ? deg(a) < deg(b) : a < b;
+            return dg[a] != dg[b] ? dg[a] < dg[b] : a < b;
         });
     std::vector<int> order;
     order.reserve((size_t)n);
-    std::vector<int> level((size_t)n, -1);
-    // breadth-first sweep from `root` over its unvisited component: returns the
-    // visited cells in order (appended to `out`) and marks them with `mark`
-    std::vector<int> stamp((size_t)n, 0);
+    // per cell: the breadth-first sweep that last reached it and its level
+    // there; numbered cells (earlier components) are never reached again
+    std::vector<int> stamp((size_t)n, 0), level((size_t)n, 0);
     int sweep_id = 0;
-    auto bfs = [&](int root, std::vector<int>& out) {
+    std::vector<int> sweep;
+    auto bfs = [&](int root) {
         ++sweep_id;
-        const size_t first = out.size();
-        out.push_back(root);
+        sweep.clear();
+        sweep.push_back(root);
         stamp[root] = sweep_id;
         level[root] = 0;
-        for (size_t h = first; h < out.size(); ++h) {
-            const int v = out[h];
+        for (size_t h = 0; h < sweep.size(); ++h) {
+            const int v = sweep[h];
             for (int e = rp[v]; e < rp[(size_t)v + 1]; ++e) {
                 const int w = adj[e];
-                if (stamp[w] == sweep_id || level[w] == -2) continue;
+                if (stamp[w] == sweep_id) continue;
                 stamp[w] = sweep_id;
                 level[w] = level[v] + 1;
-                out.push_back(w);
+                sweep.push_back(w);
             }
         }
-        return first;
     };
-    std::vector<int> scratch;
+    auto better = [&](int a, int b) { return dg[a] != dg[b] ? dg[a] < dg[b] : a < b; };
+    std::vector<char> numbered((size_t)n, 0);
     for (int s0 = 0; s0 < n; ++s0) {
-        if (level[s0] == -2) continue;
-        // start: a cell of minimum degree in this component, moved twice to a
-        // minimum-degree cell of the last breadth-first level (pseudo-peripheral)
+        if (numbered[s0]) continue;
+        // start: the component's cell of minimum degree, moved once to a
+        // minimum-degree cell of the last breadth-first level from it (a
+        // pseudo-peripheral cell); the sweep from there is the order
+        bfs(s0);
         int root = s0;
-        for (int pass = 0; pass < 3; ++pass) {
-            scratch.clear();
-            bfs(root, scratch);
-            int best = root, last = level[scratch.back()];
-            if (pass == 0) {
-                for (int v : scratch)
-                    if (deg(v) < deg(best) || (deg(v) == deg(best) && v < best)) best = v;
-            } else {
-                best = scratch.back();
-                for (int v : scratch)
-                    if (level[v] == last && (deg(v) < deg(best) || (deg(v) == deg(best) && v < best))) best = v;
-            }
-            root = best;
-        }
-        scratch.clear();
-        bfs(root, scratch);
-        for (int v : scratch) {
-            level[v] = -2;  // numbered
+        for (int v : sweep)
+            if (better(v, root)) root = v;
+        bfs(root);
+        int far = sweep.back();
+        const int last = level[far];
+        for (size_t h = sweep.size(); h-- > 0 && level[sweep[h]] == last;)
+            if (better(sweep[h], far)) far = sweep[h];
+        bfs(far);
+        for (int v : sweep) {
+            numbered[v] = 1;
             order.push_back(v);
         }
     }
