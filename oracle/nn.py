@@ -111,9 +111,11 @@ def conv3d_grads(x, W, dy):
     """Gradients of conv3d with respect to W, b and x, given dL/dy."""
     dW = np.zeros_like(W)
     dx = np.zeros_like(x)
+    ci, co = x.shape[-1], dy.shape[-1]
+    dyf = dy.reshape(-1, co)
     for t, off in enumerate(offsets()):
         xs = shifted(x, off)
-        dW[t] = np.einsum("ijkc,ijko->co", xs, dy)
+        dW[t] = xs.reshape(-1, ci).T @ dyf          # sum over cells of x[K + off] dy[K]
         # y[K] uses x[K + off]: the gradient flows back to x[K'] from dy[K' - off]
         dx += shifted(dy, tuple(-d for d in off)) @ W[t].T
     db = dy.sum(axis=(0, 1, 2))
@@ -144,36 +146,77 @@ def forward(params, r_hat, feat, bf16: bool = True, relu: bool = True):
     return h[..., 0], cache, layers
 
 
-def loss_and_grads(params, r_hat, feat, target, dmask, apply_scaled, bf16: bool = True,
-                   relu: bool = True):
-    """Energy-norm loss of the prediction and its gradient.
+def prediction_loss(z, r_hat, dmask, apply_scaled, kind=0, target=None):
+    """Loss of a preconditioned residual ``z`` and its gradient with respect to z.
 
-    With z = r_hat + N(r_hat, feat) and the scaled error target (A~ target =
-    r_hat), the loss is the A~-norm of the prediction error relative to that
-    of the target, over the unknown cells:
+    All three are quadratic forms of the Jacobi-scaled operator A~ over the
+    unknown cells (``apply_scaled(v)`` returns A~ v for a grid-shaped v that is
+    0 on Dirichlet cells; z, r_hat and target are taken as 0 there):
 
-        loss = (z - target)' A~ (z - target) / (target' r_hat),
+    * ``kind=0`` with a target t (the scaled error, A~ t = r_hat): the energy
+      norm of the prediction error relative to that of the error,
+      ``(z - t)' A~ (z - t) / (t' r_hat)``; gradient ``2 A~ (z - t) / (t' r_hat)``.
+    * ``kind=0`` without a target: the energy functional
+      ``(z' A~ z - 2 z' r_hat) / (r_hat' r_hat)``, whose minimiser is the error
+      A~^-1 r_hat (the quadratic CG minimises); gradient
+      ``2 (A~ z - r_hat) / (r_hat' r_hat)``.
+    * ``kind=1``: the residual-space loss ``||A~ z - r_hat||^2 / ||r_hat||^2``;
+      gradient ``2 A~ (A~ z - r_hat) / ||r_hat||^2`` (A~ is symmetric).
 
-    ``apply_scaled(v)`` returns A~ v for a grid-shaped v that is 0 on Dirichlet
-    cells. Returns (loss, gradient with respect to the parameter vector, N).
+    Returns (loss, dloss/dz as a grid-shaped array, 0 on Dirichlet cells).
     """
-    rnd = bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
-    out, cache, layers = forward(params, r_hat, feat, bf16, relu)
     u = ~np.asarray(dmask, dtype=bool)
-    E = float(np.sum(np.where(u, target * r_hat, 0.0)))
-    delta = np.where(u, np.asarray(r_hat, dtype=np.float64) + out - target, 0.0)
-    Ad = np.where(u, apply_scaled(delta), 0.0)
-    loss = float(np.sum(delta * Ad) / E)
-    dy = (2.0 * Ad / E)[..., None]
+    rh = np.where(u, np.asarray(r_hat, dtype=np.float64), 0.0)
+    zz = np.where(u, np.asarray(z, dtype=np.float64), 0.0)
+    Aop = lambda v: np.where(u, apply_scaled(v), 0.0)
+    if kind == 1:
+        E = float(np.sum(rh * rh))
+        g = Aop(zz) - rh
+        return float(np.sum(g * g) / E), 2.0 * Aop(g) / E
+    if kind != 0:
+        raise ValueError("loss kind must be 0 or 1")
+    if target is None:
+        E = float(np.sum(rh * rh))
+        Az = Aop(zz)
+        return float((np.sum(zz * Az) - 2.0 * np.sum(zz * rh)) / E), 2.0 * (Az - rh) / E
+    t = np.where(u, np.asarray(target, dtype=np.float64), 0.0)
+    E = float(np.sum(t * rh))
+    delta = zz - t
+    Ad = Aop(delta)
+    return float(np.sum(delta * Ad) / E), 2.0 * Ad / E
+
+
+def backprop(layers, cache, dy, bf16: bool = True, relu: bool = True):
+    """Parameter gradient (flat vector) of the network for the output gradient
+    ``dy`` (grid-shaped), from the activations ``cache`` and the BF16-rounded
+    layers of :func:`forward`. Each back-propagated activation gradient is
+    rounded to BF16 (with ``bf16``), as the GPU stores it."""
+    rnd = bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+    g = rnd(np.asarray(dy, dtype=np.float64))[..., None]
     grads = [None] * len(layers)
     for li in range(len(layers) - 1, -1, -1):
         W, _ = layers[li]
-        x = cache[li]
-        dW, db, dx = conv3d_grads(x, W, dy)
+        dW, db, dx = conv3d_grads(cache[li], W, g)
         grads[li] = (dW, db)
         if li > 0:
-            dy = rnd(dx * (cache[li] > 0) if relu else dx)   # activation of the layer below
-    return loss, pack(grads), out
+            g = rnd(dx * (cache[li] > 0) if relu else dx)   # activation of the layer below
+    return pack(grads)
+
+
+def loss_and_grads(params, r_hat, feat, target, dmask, apply_scaled, bf16: bool = True,
+                   relu: bool = True, kind: int = 0):
+    """Training loss of one sample and its gradient with respect to the
+    parameter vector: z = r_hat + N(r_hat, feat) scored by
+    :func:`prediction_loss` (``kind`` 0: the energy norm of the prediction
+    error with a target, the energy functional without one; 1: the residual
+    space). r_hat is taken as 0 on Dirichlet cells, also as network input.
+    Returns (loss, gradient, N).
+    """
+    u = ~np.asarray(dmask, dtype=bool)
+    rh = np.where(u, np.asarray(r_hat, dtype=np.float64), 0.0)
+    out, cache, layers = forward(params, rh, feat, bf16, relu)
+    loss, dz = prediction_loss(rh + out, rh, dmask, apply_scaled, kind, target)
+    return loss, backprop(layers, cache, dz, bf16, relu), out
 
 
 def scaled_operator(A, dmask):
@@ -183,10 +226,28 @@ def scaled_operator(A, dmask):
     return lambda v: (dis * (A @ (dis * np.asarray(v, dtype=np.float64).ravel()))).reshape(shape)
 
 
-def adam(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
-    """One Adam step (bias-corrected); returns new (params, m, v)."""
-    m = beta1 * m + (1 - beta1) * grads
-    v = beta2 * v + (1 - beta2) * grads * grads
-    mh = m / (1 - beta1 ** step)
-    vh = v / (1 - beta2 ** step)
-    return params - lr * mh / (np.sqrt(vh) + eps), m, v
+def adam(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, frozen=None):
+    """One Adam step (Kingma and Ba, bias-corrected); returns new (params, m, v).
+    Entries where ``frozen`` is true keep their parameter and moments."""
+    m_new = beta1 * m + (1 - beta1) * grads
+    v_new = beta2 * v + (1 - beta2) * grads * grads
+    mh = m_new / (1 - beta1 ** step)
+    vh = v_new / (1 - beta2 ** step)
+    p_new = params - lr * mh / (np.sqrt(vh) + eps)
+    if frozen is not None:
+        keep = np.asarray(frozen, dtype=bool)
+        p_new = np.where(keep, params, p_new)
+        m_new = np.where(keep, m, m_new)
+        v_new = np.where(keep, v, v_new)
+    return p_new, m_new, v_new
+
+
+def bias_mask() -> np.ndarray:
+    """True at the bias entries of the parameter vector (held fixed in training)."""
+    mask = np.zeros(n_params(), dtype=bool)
+    o = 0
+    for ci, co, _ in LAYERS:
+        o += 27 * ci * co
+        mask[o:o + co] = True
+        o += co
+    return mask

@@ -124,3 +124,200 @@ def test_zero_last_layer_gives_zero_output_and_adam_first_step():
     # first step: m_hat = g, v_hat = g^2 -> update -lr * g / (|g| + eps)
     assert np.allclose(newp, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
     assert nn.n_params() == 27 * 2 * 16 + 16 + 2 * (27 * 16 * 16 + 16) + 27 * 16 + 1
+
+
+# --- the three training losses: prediction_loss pinned by closed forms --------
+
+def _dense_scaled(shape, seed, c=1e-2):
+    """A TPFA operator with x-plane Dirichlet cells, its Jacobi-scaled form on
+    the unknown cells as a dense matrix, and apply_scaled for the oracle."""
+    from oracle import tpfa
+    from synth import lognormal_iid
+    k = lognormal_iid(shape, 1.0, seed)
+    dmask, pd = tpfa.x_plane_dirichlet(shape)
+    A, _ = tpfa.assemble(*tpfa.transmissibility(k), c, dmask, pd)
+    u = ~dmask.ravel()
+    dis = 1.0 / np.sqrt(A.diagonal())
+    At = (dis[:, None] * A.toarray() * dis[None, :])[np.ix_(u, u)]
+    return dmask, u, At, nn.scaled_operator(A, dmask)
+
+
+def _grid(u, shape, v):
+    g = np.zeros(int(np.prod(shape)))
+    g[u] = v
+    return g.reshape(shape)
+
+
+def test_losses_at_the_closed_form_minimiser():
+    """On a dense 4^3 system the error z* = A~^-1 r_hat minimises the energy
+    functional with value -r_hat' A~^-1 r_hat / r_hat' r_hat and zero gradient,
+    and zeroes the residual-space loss and its gradient; completing the square
+    gives F(z) - F(z*) = (z - z*)' A~ (z - z*) / r_hat' r_hat for any z."""
+    shape = (4, 4, 4)
+    dmask, u, At, As = _dense_scaled(shape, 7)
+    rng = np.random.default_rng(8)
+    rt = rng.normal(size=u.sum())
+    zs = np.linalg.solve(At, rt)
+    rh, zg = _grid(u, shape, rt), _grid(u, shape, zs)
+    F, dF = nn.prediction_loss(zg, rh, dmask, As, kind=0)
+    assert abs(F - (-(rt @ zs) / (rt @ rt))) <= 1e-13 * abs(F)
+    assert np.max(np.abs(dF)) <= 1e-12
+    R, dR = nn.prediction_loss(zg, rh, dmask, As, kind=1)
+    assert R <= 1e-24 and np.max(np.abs(dR)) <= 1e-12
+    for _ in range(3):
+        zt = rng.normal(size=u.sum())
+        Fz, _ = nn.prediction_loss(_grid(u, shape, zt), rh, dmask, As, kind=0)
+        gap = (zt - zs) @ At @ (zt - zs) / (rt @ rt)
+        assert abs((Fz - F) - gap) <= 1e-12 * gap and gap > 0
+        # residual space: ||A~ z - r||^2 / ||r||^2 = (z - z*)' A~^2 (z - z*) / ||r||^2
+        Rz, _ = nn.prediction_loss(_grid(u, shape, zt), rh, dmask, As, kind=1)
+        e = At @ (zt - zs)
+        assert abs(Rz - e @ e / (rt @ rt)) <= 1e-12 * Rz
+
+
+def test_losses_with_the_identity_operator():
+    """A~ = I: the energy functional is ||z - r||^2/||r||^2 - 1 and the
+    residual-space loss ||z - r||^2/||r||^2; a target t = r gives the energy
+    norm ||z - r||^2 / ||r||^2."""
+    shape = (3, 4, 5)
+    nod = np.zeros(shape, dtype=bool)
+    ident = lambda v: np.asarray(v, dtype=np.float64)
+    rng = np.random.default_rng(9)
+    r, z = rng.normal(size=shape), rng.normal(size=shape)
+    d2 = np.sum((z - r) ** 2) / np.sum(r * r)
+    F, dF = nn.prediction_loss(z, r, nod, ident, kind=0)
+    R, dR = nn.prediction_loss(z, r, nod, ident, kind=1)
+    T, dT = nn.prediction_loss(z, r, nod, ident, kind=0, target=r)
+    assert abs(F - (d2 - 1.0)) <= 1e-14 and abs(R - d2) <= 1e-14 and abs(T - d2) <= 1e-14
+    for g in (dF, dR, dT):
+        assert np.allclose(g, 2.0 * (z - r) / np.sum(r * r), rtol=1e-14, atol=1e-15)
+
+
+def test_energy_norm_and_functional_differ_by_a_constant():
+    """With the consistent target t = A~^-1 r: (z - t)'A~(z - t) = z'A~z - 2 z'r + t'r,
+    so E_t(z) t'r = F(z) r'r + t'r for every z."""
+    shape = (4, 3, 4)
+    dmask, u, At, As = _dense_scaled(shape, 10)
+    rng = np.random.default_rng(11)
+    rt = rng.normal(size=u.sum())
+    tt = np.linalg.solve(At, rt)
+    rh, tg = _grid(u, shape, rt), _grid(u, shape, tt)
+    for _ in range(3):
+        z = _grid(u, shape, rng.normal(size=u.sum()))
+        E, _ = nn.prediction_loss(z, rh, dmask, As, kind=0, target=tg)
+        F, _ = nn.prediction_loss(z, rh, dmask, As, kind=0)
+        assert abs(E * (tt @ rt) - (F * (rt @ rt) + tt @ rt)) <= 1e-12 * abs(E * (tt @ rt))
+
+
+def _pass_through(alpha):
+    """Identity-activation network with N = alpha * (first input channel): the
+    centre tap carries channel 0 through the three hidden layers."""
+    layers = [(np.zeros((27, ci, co)), np.zeros(co)) for ci, co, _ in nn.LAYERS]
+    for li in range(3):
+        layers[li][0][13, 0, 0] = 1.0
+    layers[3][0][13, 0, 0] = alpha
+    return nn.pack(layers)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_network_loss_in_closed_form_for_a_pass_through_network(kind):
+    """N = alpha r_hat, so z = (1 + alpha) r_hat: the functional is
+    ((1+a)^2 r'A~r - 2 (1+a) r'r) / r'r and the residual loss
+    ||(1+a) A~r - r||^2 / r'r. The derivative with respect to the last layer's
+    centre weight is dL/da, and with respect to the first layer's it is a dL/da
+    (N = w4 w3 w2 w1 r_hat), from the dense matrix."""
+    shape = (5, 3, 4)
+    dmask, u, At, As = _dense_scaled(shape, 12)
+    rng = np.random.default_rng(13)
+    rt = rng.normal(size=u.sum()).astype(np.float32).astype(np.float64)   # FP32 network input
+    rh = _grid(u, shape, rt)
+    a = 0.37
+    loss, g, out = nn.loss_and_grads(_pass_through(a), rh, rng.normal(size=shape), None, dmask, As,
+                                     bf16=False, relu=False, kind=kind)
+    assert np.allclose(out, a * rh, rtol=0, atol=1e-15)
+    rr, rAr, Ar = rt @ rt, rt @ At @ rt, At @ rt
+    if kind == 0:
+        want = ((1 + a) ** 2 * rAr - 2 * (1 + a) * rr) / rr
+        dlda = (2 * (1 + a) * rAr - 2 * rr) / rr
+    else:
+        e = (1 + a) * Ar - rt
+        want = e @ e / rr
+        dlda = 2 * e @ Ar / rr
+    assert abs(loss - want) <= 1e-13 * abs(want)
+    w4 = nn.n_params() - 1 - 27 * 16          # W4[13, 0, 0]
+    w4 += 13 * 16
+    w1 = 13 * 2 * 16                          # W1[13, 0, 0]
+    assert abs(g[w4] - dlda) <= 1e-12 * abs(dlda)
+    assert abs(g[w1] - a * dlda) <= 1e-12 * abs(a * dlda)
+
+
+@pytest.mark.parametrize("kind,with_target", [(0, False), (1, False), (0, True)])
+@pytest.mark.parametrize("relu", [True, False])
+def test_every_loss_gradient_matches_central_differences(kind, with_target, relu):
+    from oracle import tpfa
+    from synth import lognormal_iid
+    rng = np.random.default_rng(14)
+    shape = (4, 3, 5)
+    params = nn.init_params(seed=15, last_scale=0.5).astype(np.float64)
+    k = lognormal_iid(shape, 1.0, 16)
+    dmask, pd = tpfa.x_plane_dirichlet(shape)
+    A, _ = tpfa.assemble(*tpfa.transmissibility(k), 1e-2, dmask, pd)
+    As = nn.scaled_operator(A, dmask)
+    r = np.where(dmask, 0.0, rng.normal(size=shape))
+    f = rng.normal(size=shape)
+    tgt = None
+    if with_target:
+        tgt = np.where(dmask, 0.0, rng.normal(size=shape))
+        tgt *= np.sign(np.sum(tgt * r)) or 1.0
+    loss, g, _ = nn.loss_and_grads(params, r, f, tgt, dmask, As, bf16=False, relu=relu, kind=kind)
+    h = 1e-6
+    for i in rng.choice(params.size, 30, replace=False):
+        p1, p2 = params.copy(), params.copy()
+        p1[i] += h
+        p2[i] -= h
+        l1 = nn.loss_and_grads(p1, r, f, tgt, dmask, As, bf16=False, relu=relu, kind=kind)[0]
+        l2 = nn.loss_and_grads(p2, r, f, tgt, dmask, As, bf16=False, relu=relu, kind=kind)[0]
+        fd = (l1 - l2) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+# --- Adam: closed forms of the bias-corrected moments ------------------------
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    """With a constant gradient the bias-corrected moments are exactly g and
+    g^2 at every step, so each step moves by lr g / (|g| + eps)."""
+    g = np.array([0.5, -2.0, 1e-3, 3e-7])
+    p, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    for t in range(1, 8):
+        p, m, v = nn.adam(p, g, m, v, step=t, lr=0.01)
+        assert np.allclose(p, -0.01 * t * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+
+
+def test_adam_single_impulse_then_zero_gradients():
+    """A gradient g at step 1 and 0 afterwards: m_t = (1-b1) b1^(t-1) g and
+    v_t = (1-b2) b2^(t-1) g^2, so step t moves by
+    lr (1-b1) b1^(t-1)/(1-b1^t) g / (sqrt((1-b2) b2^(t-1)/(1-b2^t)) |g| + eps)."""
+    b1, b2, lr, eps = 0.9, 0.999, 1e-2, 1e-8
+    g = np.array([1.5, -0.25])
+    p, m, v = np.zeros(2), np.zeros(2), np.zeros(2)
+    want = np.zeros(2)
+    for t in range(1, 6):
+        p, m, v = nn.adam(p, g if t == 1 else np.zeros(2), m, v, step=t, lr=lr)
+        mh = (1 - b1) * b1 ** (t - 1) / (1 - b1 ** t) * g
+        vh = (1 - b2) * b2 ** (t - 1) / (1 - b2 ** t) * g * g
+        want = want - lr * mh / (np.sqrt(vh) + eps)
+        assert np.allclose(p, want, rtol=1e-12, atol=0)
+
+
+def test_adam_frozen_entries_and_bias_mask():
+    mask = nn.bias_mask()
+    assert mask.sum() == 16 + 16 + 16 + 1
+    layers = nn.unpack(np.arange(nn.n_params(), dtype=np.float64))
+    flat_b = np.concatenate([b for _, b in layers])
+    assert np.array_equal(np.flatnonzero(mask), flat_b.astype(int))
+    p = np.ones(nn.n_params())
+    g = np.full(nn.n_params(), 0.5)
+    z = np.zeros(nn.n_params())
+    p1, m1, v1 = nn.adam(p, g, z, z, step=1, lr=0.1, frozen=mask)
+    assert np.all(p1[mask] == 1.0) and np.all(m1[mask] == 0) and np.all(v1[mask] == 0)
+    assert np.allclose(p1[~mask], 1.0 - 0.1 * 0.5 / (0.5 + 1e-8), rtol=1e-14)
