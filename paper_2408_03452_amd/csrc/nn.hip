@@ -848,13 +848,16 @@ int conv_run(const Shape& S, int64_t slots) {
     return (int)std::min<int64_t>(run, S.g.nx);
 }
 
+// Planes per block set by mffv_set_nn_run (0: conv_run's choice).
+int g_nn_run = 0;
+
 template <int C, int MODE>
 int conv(const Shape& S, const ConvArgs& a0, hipStream_t st) {
     static const int64_t slots = resident_blocks(conv3d<C, MODE>);
     ConvArgs a = a0;
     a.ntk = S.ntk;
     a.ncols = S.ntj * S.ntk;
-    a.run = conv_run(S, slots);
+    a.run = g_nn_run > 0 ? std::min(g_nn_run, S.g.nx) : conv_run(S, slots);
     const int64_t blocks = (int64_t)a.ncols * ((S.g.nx + a.run - 1) / a.run);
     hipLaunchKernelGGL((conv3d<C, MODE>), dim3((unsigned)blocks), dim3(kThreads), 0, st, S.g, a);
     NHIP(hipGetLastError());
@@ -1121,6 +1124,12 @@ int mffv_net_set_loss(mffv_net* N, int kind) {
     if (rc) return rc;
     if (kind != 0 && kind != 1) return nfail(MFFV_EINVAL, "loss kind must be 0 (energy) or 1 (residual)");
     N->loss_kind = kind;
+    return MFFV_OK;
+}
+
+int mffv_set_nn_run(int run) {
+    if (run < 0) return nfail(MFFV_EINVAL, "run must be >= 0");
+    g_nn_run = run;
     return MFFV_OK;
 }
 

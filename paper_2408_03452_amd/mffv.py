@@ -109,6 +109,7 @@ def _declare(lib):
         "mffv_net_set_params": (ctypes.c_int, [_P, _P]),
         "mffv_net_set_activation": (ctypes.c_int, [_P, ctypes.c_int]),
         "mffv_net_set_loss": (ctypes.c_int, [_P, ctypes.c_int]),
+        "mffv_set_nn_run": (ctypes.c_int, [ctypes.c_int]),
         "mffv_nn_forward": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P,
                                            _P]),
         "mffv_nn_loss_grad": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
@@ -482,6 +483,11 @@ def net_set_activation(net: Net, relu: bool) -> None:
 
 def net_set_loss(net: Net, kind: int) -> None:
     _check(lib().mffv_net_set_loss(net.handle, int(kind)))
+
+
+def set_nn_run(run: int) -> None:
+    """Planes per block of the network's marching convolutions (0: automatic)."""
+    _check(lib().mffv_set_nn_run(int(run)))
 
 
 def net_destroy(net: Net) -> None:
