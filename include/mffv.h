@@ -104,7 +104,8 @@ typedef struct {
                             arithmetic); means returned in mffv_info                      */
     int async;           /* 1: capture-safe, no host synchronisation. mffv_cg_solve_batched
                             (and mffv_cg_solve, which then runs the persistent solver on its
-                            one system; precision MFFV_FP32, precond NONE or JACOBI) only
+                            one system; precision MFFV_FP32 or MFFV_FP32_IR, precond NONE
+                            or JACOBI) only
                             enqueue work on the stream; info, if not NULL, is a DEVICE
                             array (one mffv_info per system) written when the stream
                             reaches it, with status MFFV_EHIP if a wait of the persistent
@@ -280,14 +281,28 @@ int mffv_cg_solve_f64(mffv_grid* grid, const double* b, double* x, const mffv_op
 /*
  * Solve nsys independent systems (each its own grid handle with coefficients
  * set, any sizes below 2^30 cells; larger ones return MFFV_EINVAL) in one
- * persistent FP32 CG launch. grids, b and x are host
- * arrays of nsys pointers; b[s] and x[s] are device FP32 vectors of grid s.
- * All handles must share the device and stream of grids[0]. info (host, nsys
- * entries) may be NULL. opts->precond may be NONE or JACOBI; precision is FP32.
- * Synchronizes the stream. Returns MFFV_OK if every system converged,
- * MFFV_NOT_CONVERGED if any did not, or an error. With opts->async = 1 it
- * only enqueues the solve (capture-safe once the plan exists, see mffv_opts),
- * info is a device array, and the return value only reports argument errors.
+ * persistent FP32 CG launch (Alg. 1 per system). grids, b and x are host
+ * arrays of nsys pointers; b[s] and x[s] are device FP32 vectors of grid s
+ * (x: initial guess in, solution out). All handles must share the device and
+ * stream of grids[0]. info (host, nsys entries) may be NULL. opts->precond
+ * may be NONE or JACOBI. Each system's starting residual is formed in FP64.
+ *   precision MFFV_FP32: one FP32 CG pass per system, stopped on the
+ *     recursive residual; rel_res_true is the FP64 true residual of the
+ *     returned x.
+ *   precision MFFV_FP32_IR: after a pass, a system whose FP64 true residual
+ *     still exceeds opts->tol runs another FP32 pass on A dx = r from that
+ *     residual (to a reduction min(0.5, max(tol / rel, inner_tol))) and adds
+ *     dx to x, up to opts->max_outer corrections, all inside the same launch;
+ *     the status is MFFV_OK when the true residual of the returned FP32 x
+ *     meets tol. (Rounding x to FP32 alone leaves a true residual of a few
+ *     1e-7 on grids of ~100 planes, which bounds what FP32 x can reach.)
+ * A plan made by an earlier call (same grids, vectors and options) is reused;
+ * it holds no copy of the coefficients, so setting a grid's coefficients again
+ * needs no new plan. Synchronizes the stream. Returns MFFV_OK if every system
+ * converged, MFFV_NOT_CONVERGED if any did not, or an error. With
+ * opts->async = 1 it only enqueues the solve (capture-safe once the plan
+ * exists, see mffv_opts), info is a device array, and the return value only
+ * reports argument errors.
  */
 int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const* b,
                           float* const* x, const mffv_opts* opts, mffv_info* info);
@@ -376,6 +391,15 @@ int mffv_net_set_activation(mffv_net* net, int relu);
  * which weights smooth error modes by their squared eigenvalue; the target is
  * not used). */
 int mffv_net_set_loss(mffv_net* net, int kind);
+
+/* Launch shape of the network's convolutions, process-wide: each block of a
+ * convolution marches through `run` consecutive x planes (clamped to nx),
+ * keeping the planes it needs in a ring of LDS slots; 0 (the default) picks the
+ * shortest run for which all blocks are resident at once. Every run gives the
+ * same result; callers use it to pin a march length (e.g. tests). Applies to
+ * later launches: HIP graphs that a solve has already captured keep theirs.
+ * Errors: MFFV_EINVAL for run < 0. */
+int mffv_set_nn_run(int run);
 
 /* Copy the FP32 parameters and/or the last computed gradient to host arrays
  * of mffv_net_num_params() floats (either may be NULL). Synchronizes. */

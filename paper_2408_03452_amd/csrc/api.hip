@@ -90,6 +90,7 @@ struct mffv_grid {
     double* a64 = nullptr;
     uint8_t* dmask = nullptr;
     int* flags = nullptr;
+    CoefScalars* cdev = nullptr;  // a_uniform and a_const in device memory (read by batched solves)
     bool has_coef = false;
     int64_t n_unknown = 0;
     float* feat = nullptr;     // learned preconditioner input feature (lazy)
@@ -217,6 +218,15 @@ int ensure_feature(mffv_grid* G) {
                          reinterpret_cast<float*>(G->partR), G->feat, G->stream)))
         return rc;
     G->feat_valid = true;
+    return MFFV_OK;
+}
+
+// Copy the operator's scalars to the grid's device struct; the batched kernel
+// reads them there at every launch (stream-ordered after earlier solves).
+int store_coef_scalars(mffv_grid* G) {
+    const CoefScalars cs{G->a_uniform ? 1 : 0, G->a_const};
+    HIP_TRY(hipMemcpyAsync(G->cdev, &cs, sizeof(cs), hipMemcpyHostToDevice, G->stream));
+    HIP_TRY(hipStreamSynchronize(G->stream));
     return MFFV_OK;
 }
 
@@ -730,6 +740,8 @@ struct BatchPlan {
     std::vector<float*> x;
     int precond = 0, max_iter = 0, blocks_per_cu = 0, items_per_block = 4;
     int merged = 0;  // single-reduction iteration
+    int max_outer = 0;  // refinement passes (MFFV_FP32_IR), 0 for MFFV_FP32
+    double inner_tol = 0;
     double watchdog_s = 2.0;
     double tol = 0;
     void* dbuf = nullptr;
@@ -737,7 +749,6 @@ struct BatchPlan {
     int* dblock_sys = nullptr;
     unsigned* dbars = nullptr;
     BatchResult* dres = nullptr;
-    double* dres64 = nullptr;  // [2*s]: ||b_U||^2, [2*s+1]: ||r||^2
     int* derr = nullptr;
     int nblocks = 0;
     BatchRun run{};
@@ -816,7 +827,7 @@ int build_plan(BatchPlan* P, hipStream_t stream) {
     for (mffv_grid* G : P->grids)
         if (G->g.n >= (int64_t(1) << 30)) return fail(MFFV_EINVAL, "batched systems must have fewer than 2^30 cells");
     for (mffv_grid* G : P->grids) {
-        if ((rc = ensure_ws32(G)) || (rc = ensure_x64(G))) return rc;
+        if ((rc = ensure_ws32(G))) return rc;
         if (P->merged && (rc = ensure_merged(G))) return rc;
     }
     int dev = 0, cus = 0, rate_khz = 0;
@@ -836,7 +847,7 @@ int build_plan(BatchPlan* P, hipStream_t stream) {
     auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
     const size_t o_sys = take(sizeof(BatchSys) * ns), o_map = take(sizeof(int) * total),
                  o_part = take(sizeof(float) * 8 * total), o_bar = take(sizeof(unsigned) * (2 * (size_t)ns + 2 * (size_t)total)),
-                 o_res = take(sizeof(BatchResult) * ns), o_r64 = take(sizeof(double) * 2 * ns),
+                 o_res = take(sizeof(BatchResult) * ns), o_p64 = take(sizeof(double) * 2 * total),
                  o_err = take(sizeof(int));
     HIP_TRY(hipMalloc(&P->dbuf, off));
     char* base = static_cast<char*>(P->dbuf);
@@ -845,7 +856,7 @@ int build_plan(BatchPlan* P, hipStream_t stream) {
     float* dpart = reinterpret_cast<float*>(base + o_part);
     P->dbars = reinterpret_cast<unsigned*>(base + o_bar);
     P->dres = reinterpret_cast<BatchResult*>(base + o_res);
-    P->dres64 = reinterpret_cast<double*>(base + o_r64);
+    double* dpart64 = reinterpret_cast<double*>(base + o_p64);
     P->derr = reinterpret_cast<int*>(base + o_err);
     std::vector<BatchSys> hs(ns);
     std::vector<int> map(total);
@@ -855,6 +866,7 @@ int build_plan(BatchPlan* P, hipStream_t stream) {
         BatchSys& S = hs[s];
         S.g = G->g;
         S.c = coef_of(G);
+        S.cs = G->cdev;
         S.dinv = G->dinv;
         S.dmask = G->dmask;
         S.b = P->b[s];
@@ -864,9 +876,11 @@ int build_plan(BatchPlan* P, hipStream_t stream) {
         S.p1 = G->p1;
         S.q = G->q;
         S.z = G->z;
+        S.dx = G->xw;
         S.r2 = P->merged ? G->r2 : nullptr;
         S.q2 = P->merged ? G->q2 : nullptr;
         S.part = dpart + 8 * b0;
+        S.part64 = dpart64 + 2 * b0;
         S.bar = P->dbars + 2 * s;
         S.xch = reinterpret_cast<unsigned long long*>(P->dbars + 2 * ns) + b0;
         S.res = P->dres + s;
@@ -887,6 +901,9 @@ int build_plan(BatchPlan* P, hipStream_t stream) {
     P->run.max_iter = P->max_iter;
     P->run.precond = P->precond;
     P->run.merged = P->merged;
+    P->run.max_outer = P->max_outer;
+    P->run.tol = P->tol;
+    P->run.inner_tol = P->inner_tol;
     // limit of one per-system wait, in wall-clock ticks (0: a wait not satisfied
     // at once fails)
     P->run.limit_ticks = (uint64_t)((double)rate_khz * 1000.0 * P->watchdog_s);
@@ -900,8 +917,7 @@ int build_plan(BatchPlan* P, hipStream_t stream) {
 // Per-system results of an asynchronous batched solve, written into the
 // caller's device array of mffv_info (the same fields the synchronous call
 // fills on the host, without the timing).
-__global__ void batch_info(int ns, const BatchResult* res, const double* r64, const int* err, int merged,
-                           mffv_info* out) {
+__global__ void batch_info(int ns, const BatchResult* res, const int* err, int merged, mffv_info* out) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= ns) return;
     const BatchResult R = res[s];
@@ -909,24 +925,19 @@ __global__ void batch_info(int ns, const BatchResult* res, const double* r64, co
     I.status = *err ? MFFV_EHIP
                     : (R.status == 0 ? MFFV_OK : (R.status == 1 ? MFFV_NOT_CONVERGED : MFFV_EBREAKDOWN));
     I.iters = R.iters;
-    I.ir_steps = 1;
+    I.ir_steps = R.passes;
     I.rel_res_recursive = R.bnorm2 > 0.f ? sqrt((double)R.rr / (double)R.bnorm2) : 0.0;
-    I.rel_res_true = r64[2 * s] > 0 ? sqrt(r64[2 * s + 1] / r64[2 * s]) : sqrt(r64[2 * s + 1]);
+    I.rel_res_true = R.bb64 > 0 ? sqrt(R.rr64 / R.bb64) : sqrt(R.rr64);
     I.single_reduction = merged;
     out[s] = I;
 }
 
-// Enqueue the whole batch: persistent CG, then each system's FP64 residual.
+// Enqueue the whole batch: the persistent kernel, which also forms every
+// system's FP64 true residual (and refines with MFFV_FP32_IR).
 int enqueue_batch(BatchPlan* P, hipStream_t stream) {
     // barrier words of every system, then the 64-bit exchange slot of every block
     HIP_TRY(launch_batched_cg(P->dsys, P->dblock_sys, P->nblocks, P->dbars,
                               2 * (int)P->grids.size() + 2 * P->nblocks, P->derr, P->run, stream));
-    for (size_t s = 0; s < P->grids.size(); ++s) {
-        mffv_grid* G = P->grids[s];
-        HIP_TRY(launch_convert_f32_to_f64(G->g.n, P->x[s], G->x64, stream));
-        int rc = true_residual_f64(G, P->b[s], 0, G->x64, G->rres, P->dres64 + 2 * s);
-        if (rc) return rc;
-    }
     return MFFV_OK;
 }
 
@@ -1045,7 +1056,8 @@ int alloc_grid(mffv_grid* G, bool cartesian) {
     if ((rc = dalloc(&G->a, n)) || (rc = dalloc(&G->a64, n)) ||
         (cartesian && ((rc = dalloc(&G->tx, n)) || (rc = dalloc(&G->ty, n)) || (rc = dalloc(&G->tz, n)))) ||
         (rc = dalloc(&G->dinv, n)) || (rc = dalloc(&G->dmask, n)) ||
-        (rc = dalloc(&G->flags, 8)) || (rc = dalloc(&G->partA, (size_t)G->max_blocks)) ||
+        (rc = dalloc(&G->flags, 8)) || (rc = dalloc(&G->cdev, 1)) ||
+        (rc = dalloc(&G->partA, (size_t)G->max_blocks)) ||
         (rc = dalloc(&G->partB, 3 * (size_t)G->nb_vec)) ||
         (rc = dalloc(&G->partF, 4 * (size_t)G->nb_vec)) ||
         (rc = dalloc(&G->partR, (size_t)std::max(G->max_blocks, 1024))) || (rc = dalloc(&G->dscal, 8)))
@@ -1277,7 +1289,7 @@ void mffv_destroy_grid(mffv_grid* G) {
     drop_graphs(G);
     dfree(G->a); dfree(G->a64); dfree(G->tx); dfree(G->ty); dfree(G->tz); dfree(G->dinv); dfree(G->dmask);
     dfree(G->feat);
-    dfree(G->flags); dfree(G->partA); dfree(G->partB); dfree(G->partF); dfree(G->partR);
+    dfree(G->flags); dfree(G->cdev); dfree(G->partA); dfree(G->partB); dfree(G->partF); dfree(G->partR);
     dfree(G->dscal);
     dfree(G->r); dfree(G->p0); dfree(G->p1); dfree(G->q); dfree(G->z); dfree(G->xw);
     dfree(G->bw); dfree(G->st32); dfree(G->step_rhs);
@@ -1339,6 +1351,7 @@ int mffv_set_transmissibility(mffv_grid* G, const float* tx, const float* ty, co
     // coefficient is the accumulation itself on every plane not next to D
     G->a_uniform = accum == nullptr && dmask == nullptr;
     G->a_const = accum_scalar;
+    if ((rc = store_coef_scalars(G))) return rc;
     G->has_coef = true;
     return MFFV_OK;
 }
@@ -1371,6 +1384,7 @@ int mffv_set_face_transmissibility(mffv_grid* G, const float* T, const float* ac
     G->feat_valid = false;
     G->a_uniform = false;
     G->a_const = 0.f;
+    if ((rc = store_coef_scalars(G))) return rc;
     G->has_coef = true;
     return MFFV_OK;
 }
@@ -1426,8 +1440,9 @@ int mffv_cg_solve(mffv_grid* G, const float* b, float* x, const mffv_opts* opts,
         return rc;
     if (o.async) {
         // no host synchronisation: the whole solve runs in the persistent kernel
-        if (o.precision != MFFV_FP32 || o.precond == MFFV_PRECOND_LEARNED)
-            return fail(MFFV_EINVAL, "opts.async needs precision MFFV_FP32 and precond NONE or JACOBI");
+        if ((o.precision != MFFV_FP32 && o.precision != MFFV_FP32_IR) || o.precond == MFFV_PRECOND_LEARNED)
+            return fail(MFFV_EINVAL, "opts.async needs precision MFFV_FP32 or MFFV_FP32_IR and precond NONE or "
+                                     "JACOBI");
         mffv_grid* const gs[1] = {G};
         const float* const bs[1] = {b};
         float* const xs[1] = {x};
@@ -1550,7 +1565,9 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
     mffv_opts o = resolve_opts(opts);
     int rc = validate_opts(o);
     if (rc) return rc;
-    if (o.precision != MFFV_FP32) return fail(MFFV_EINVAL, "batched solves run in MFFV_FP32");
+    if (o.precision != MFFV_FP32 && o.precision != MFFV_FP32_IR)
+        return fail(MFFV_EINVAL, "batched solves run in MFFV_FP32 or MFFV_FP32_IR");
+    const int max_outer = o.precision == MFFV_FP32_IR ? std::max(1, o.max_outer) : 0;
     if (o.precond == MFFV_PRECOND_LEARNED)
         return fail(MFFV_EINVAL, "batched solves support precond NONE or JACOBI");
     if ((rc = set_device(grids[0]))) return rc;
@@ -1563,7 +1580,7 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
     for (BatchPlan* c : g_plans) {
         if ((int)c->grids.size() != nsys || c->precond != o.precond || c->tol != o.tol || c->merged != merged ||
             c->max_iter != o.max_iter || c->blocks_per_cu != bpc || c->items_per_block != g_batch_ipb ||
-            c->watchdog_s != g_batch_watchdog_s)
+            c->watchdog_s != g_batch_watchdog_s || c->max_outer != max_outer || c->inner_tol != o.inner_tol)
             continue;
         bool same = true;
         for (int s = 0; s < nsys && same; ++s)
@@ -1585,6 +1602,8 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
         P->merged = merged;
         P->tol = o.tol;
         P->max_iter = o.max_iter;
+        P->max_outer = max_outer;
+        P->inner_tol = o.inner_tol;
         P->blocks_per_cu = bpc;
         P->items_per_block = g_batch_ipb;
         P->watchdog_s = g_batch_watchdog_s;
@@ -1603,7 +1622,7 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
         if ((rc = enqueue_batch(P, stream))) return rc;
         if (info) {
             hipLaunchKernelGGL(batch_info, dim3((nsys + 255) / 256), dim3(256), 0, stream, nsys, P->dres,
-                               P->dres64, P->derr, P->merged, info);
+                               P->derr, P->merged, info);
             HIP_TRY(hipGetLastError());
         }
         return MFFV_OK;
@@ -1634,10 +1653,8 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, P->e0, P->e1));
     std::vector<BatchResult> res(nsys);
-    std::vector<double> r64(2 * (size_t)nsys);
     int err = 0;
     HIP_TRY(hipMemcpy(res.data(), P->dres, sizeof(BatchResult) * nsys, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(r64.data(), P->dres64, sizeof(double) * 2 * nsys, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(&err, P->derr, sizeof(int), hipMemcpyDeviceToHost));
     if (err) {
         HIP_TRY(hipMemset(P->derr, 0, sizeof(int)));
@@ -1655,9 +1672,9 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
             I = mffv_info{};
             I.status = st;
             I.iters = R.iters;
-            I.ir_steps = 1;
+            I.ir_steps = R.passes;
             I.rel_res_recursive = R.bnorm2 > 0 ? std::sqrt((double)R.rr / (double)R.bnorm2) : 0.0;
-            I.rel_res_true = r64[2 * s] > 0 ? std::sqrt(r64[2 * s + 1] / r64[2 * s]) : std::sqrt(r64[2 * s + 1]);
+            I.rel_res_true = R.bb64 > 0 ? std::sqrt(R.rr64 / R.bb64) : std::sqrt(R.rr64);
             I.ms = ms;
             I.single_reduction = P->merged;
         }

@@ -8,6 +8,12 @@
 // order, so all of them take the same decisions without further
 // communication; converged systems' blocks leave while the others go on.
 //
+// Every residual that starts a CG pass is computed in FP64 (b - A x with the
+// FP32 coefficients upcast). With refinement, a system whose FP64 true
+// residual misses the tolerance after a pass runs another FP32 pass on the
+// correction equation A dx = r from that residual and adds dx to x, all in
+// the same launch.
+//
 // Barriers spin on agent-scope atomics with a wall-clock watchdog: a block
 // that waits longer than the limit records an error and leaves, so a launch
 // whose blocks are not all resident ends with an error instead of hanging.
@@ -93,49 +99,6 @@ __device__ __forceinline__ bool exchange_sum(unsigned long long* xch, int t, int
     return ok != 0;
 }
 
-// Visit the cells of one work item (chunk pc of a plane, planes of group ic),
-// marching along x with the x-neighbours in registers. S(l) is the stencil's
-// source value at cell l; epi(l, s_l, (A s)_l) consumes each own cell.
-template <class SrcF, class EpiF>
-__device__ __forceinline__ void march_item(const Geom& g, const Coef& c, int pc, int ic, int ci,
-                                           SrcF S, EpiF epi) {
-    const int64_t P = g.plane;
-    const int64_t r0 = (int64_t)pc * kThreads + threadIdx.x;
-    if (r0 >= P) return;
-    const int i0 = ic * ci, i1 = min(g.nx, i0 + ci);
-    const int j = (int)(r0 / g.nz), k = (int)(r0 - (int64_t)j * g.nz);
-    const bool hasjm = j > 0, hasjp = j + 1 < g.ny, haskm = k > 0, haskp = k + 1 < g.nz;
-    const int nz = g.nz;
-    int64_t base = (int64_t)i0 * P + r0;
-    float sc = S(base), sm = sc, txm = 0.f;
-    if (i0 > 0) {
-        sm = S(base - P);
-        txm = c.tx[base - P];
-    }
-    for (int i = i0; i < i1; ++i, base += P) {
-        const float sp = (i + 1 < g.nx) ? S(base + P) : sc;
-        const float txc = c.tx[base], tyc = c.ty[base], tzc = c.tz[base];
-        const float ac = coef_plane_uniform(c, i, g.nx) ? c.a_const : c.a[base];
-        float tyl = 0.f, tzl = 0.f, sjm = sc, sjp = sc, skm = sc, skp = sc;
-        if (hasjm) {
-            tyl = c.ty[base - nz];
-            sjm = S(base - nz);
-        }
-        if (hasjp) sjp = S(base + nz);
-        if (haskm) {
-            tzl = c.tz[base - 1];
-            skm = S(base - 1);
-        }
-        if (haskp) skp = S(base + 1);
-        const float y = cell_op<float, float>(ac, sc, txc, sp, txm, sm, tyc, sjp, tyl, sjm, tzc, skp,
-                                              tzl, skm);
-        epi(base, sc, y);
-        sm = sc;
-        sc = sp;
-        txm = txc;
-    }
-}
-
 // Own cells of a work item without the stencil.
 template <class F>
 __device__ __forceinline__ void own_cells(const Geom& g, int pc, int ic, int ci, F f) {
@@ -185,7 +148,7 @@ struct CellA {
 };
 
 __device__ __forceinline__ void load_a(StepA& o, const BatchSys& S, const CellA& cc, const float* src,
-                                       const float* pold, bool up, uint32_t off, int i) {
+                                       const float* pold, const float* xv, bool up, uint32_t off, int i) {
     const Geom& g = S.g;
     o.zp = o.pp = o.zjm = o.pjm = o.zjp = o.pjp = o.zkm = o.pkm = o.zkp = o.pkp = 0.f;
     o.tyl = o.tzl = o.xo = 0.f;
@@ -215,7 +178,7 @@ __device__ __forceinline__ void load_a(StepA& o, const BatchSys& S, const CellA&
         o.zkp = ldo(src, off + 4u);
         if (up) o.pkp = ldo(pold, off + 4u);
     }
-    if (up) o.xo = ldo(S.x, off);
+    if (up) o.xo = ldo(xv, off);
 }
 
 // Phase A of one work item (chunk pc of a plane, planes of group ic): the
@@ -223,7 +186,7 @@ __device__ __forceinline__ void load_a(StepA& o, const BatchSys& S, const CellA&
 // the deferred x += alpha_{k-1} p_{k-1}, and the partial sum of p.q. Two plane
 // steps at a time: both steps' loads are issued before either is computed.
 __device__ __forceinline__ float phase_a_item(const BatchSys& S, int pc, int ic, const float* src,
-                                              const float* pold, float* pnew, bool up, float beta,
+                                              const float* pold, float* pnew, float* xv, bool up, float beta,
                                               float alpha_prev) {
     const Geom& g = S.g;
     const uint32_t P = (uint32_t)g.plane;
@@ -257,7 +220,7 @@ __device__ __forceinline__ float phase_a_item(const BatchSys& S, int pc, int ic,
             cell_op<float, float>(a.ac, sc, a.tx, sp, txm, sm, a.ty, sjp, a.tyl, sjm, a.tz, skp, a.tzl, skm);
         sto(pnew, o, sc);
         sto(S.q, o, y);
-        if (up) sto(S.x, o, a.xo + alpha_prev * poc);
+        if (up) sto(xv, o, a.xo + alpha_prev * poc);
         dot += sc * y;
         sm = sc;
         sc = sp;
@@ -268,13 +231,13 @@ __device__ __forceinline__ float phase_a_item(const BatchSys& S, int pc, int ic,
     for (; i + kUnrollA - 1 < i1; i += kUnrollA, off += kUnrollA * cc.P4) {
         StepA a[kUnrollA];
 #pragma unroll
-        for (int u = 0; u < kUnrollA; ++u) load_a(a[u], S, cc, src, pold, up, off + u * cc.P4, i + u);
+        for (int u = 0; u < kUnrollA; ++u) load_a(a[u], S, cc, src, pold, xv, up, off + u * cc.P4, i + u);
 #pragma unroll
         for (int u = 0; u < kUnrollA; ++u) step(a[u], off + u * cc.P4, i + u);
     }
     for (; i < i1; ++i, off += cc.P4) {
         StepA a0;
-        load_a(a0, S, cc, src, pold, up, off, i);
+        load_a(a0, S, cc, src, pold, xv, up, off, i);
         step(a0, off, i);
     }
     return dot;
@@ -335,7 +298,8 @@ struct StepM {
 };
 
 __device__ __forceinline__ void load_m(StepM& o, const BatchSys& S, const CellA& cc, const float* rin,
-                                       const float* qin, const float* pold, bool up, uint32_t off, int i) {
+                                       const float* qin, const float* pold, const float* xv, bool up, uint32_t off,
+                                       int i) {
     const Geom& g = S.g;
     o.zp = o.qp = o.pp = o.zjm = o.qjm = o.pjm = o.zjp = o.qjp = o.pjp = 0.f;
     o.zkm = o.qkm = o.pkm = o.zkp = o.qkp = o.pkp = 0.f;
@@ -362,7 +326,7 @@ __device__ __forceinline__ void load_m(StepM& o, const BatchSys& S, const CellA&
         three(off - 4u, o.zkm, o.qkm, o.pkm);
     }
     if (cc.haskp) three(off + 4u, o.zkp, o.qkp, o.pkp);
-    if (up) o.xo = ldo(S.x, off);
+    if (up) o.xo = ldo(xv, off);
 }
 
 // One work item of single-reduction iteration K (Alg. 1 with one reduction
@@ -373,7 +337,7 @@ __device__ __forceinline__ void load_m(StepM& o, const BatchSys& S, const CellA&
 // false) takes r_0 as it is.
 __device__ __forceinline__ float4 merged_item(const BatchSys& S, int pc, int ic, const float* rin,
                                               const float* qin, const float* pold, float* rout, float* qout,
-                                              float* pnew, bool up, float alpha, float beta) {
+                                              float* pnew, float* xv, bool up, float alpha, float beta) {
     const Geom& g = S.g;
     const uint32_t P = (uint32_t)g.plane;
     const uint32_t r0 = (uint32_t)pc * kThreads + threadIdx.x;
@@ -413,7 +377,7 @@ __device__ __forceinline__ float4 merged_item(const BatchSys& S, int pc, int ic,
         sto(rout, o, zc);
         sto(pnew, o, sc);
         sto(qout, o, y);
-        if (up) sto(S.x, o, a.xo + alpha * poc);
+        if (up) sto(xv, o, a.xo + alpha * poc);
         pq += sc * y;
         rr += zc * zc;
         rq += zc * y;
@@ -427,67 +391,109 @@ __device__ __forceinline__ float4 merged_item(const BatchSys& S, int pc, int ic,
     int i = i0;
     for (; i + 1 < i1; i += 2, off += 2u * cc.P4) {
         StepM a0, a1;
-        load_m(a0, S, cc, rin, qin, pold, up, off, i);
-        load_m(a1, S, cc, rin, qin, pold, up, off + cc.P4, i + 1);
+        load_m(a0, S, cc, rin, qin, pold, xv, up, off, i);
+        load_m(a1, S, cc, rin, qin, pold, xv, up, off + cc.P4, i + 1);
         step(a0, off, i);
         step(a1, off + cc.P4, i + 1);
     }
     if (i < i1) {
         StepM a0;
-        load_m(a0, S, cc, rin, qin, pold, up, off, i);
+        load_m(a0, S, cc, rin, qin, pold, xv, up, off, i);
         step(a0, off, i);
     }
     return make_float4(pq, rr, rq, qq);
 }
 
-__global__ __launch_bounds__(kThreads) void batched_cg(const BatchSys* __restrict__ systems,
-                                                       const int* __restrict__ block_sys, BatchRun run) {
-    __shared__ float red[kThreads / kWave];
-    const BatchSys S = systems[block_sys[blockIdx.x]];
-    const int t = (int)blockIdx.x - S.blk0, B = S.nblk;
-    const Geom g = S.g;
-    const Coef c = S.c;
-    const int W = S.nchunk * S.nich;
-    const bool jac = run.precond == 1;
+// Residual pass of one work item: r64 = b - A x' in FP64 at the item's own
+// cells (x' = b on Dirichlet cells, x elsewhere; FP32 coefficients upcast, the
+// FP64 identity coefficient), r = fl32(r64) on unknown cells and 0 on
+// Dirichlet cells, z = dinv r with Jacobi, and dx = 0 when asked. Partial sums:
+// r.r and r.z of the rounded r and ||b_U||^2 in FP32, ||r64||^2 and ||b_U||^2
+// in FP64.
+struct ResidSums {
+    float rr, rz, bb;
+    double rr64, bb64;
+};
+
+__device__ __forceinline__ void residual_item64(const BatchSys& S, int pc, int ic, bool jac, bool zero_dx,
+                                                ResidSums& acc) {
+    const Geom& g = S.g;
+    const Coef& c = S.c;
+    const int64_t P = g.plane;
+    const int64_t r0 = (int64_t)pc * kThreads + threadIdx.x;
+    if (r0 >= P) return;
+    const int i0 = ic * S.ci, i1 = min(g.nx, i0 + S.ci);
+    const int j = (int)(r0 / g.nz), k = (int)(r0 - (int64_t)j * g.nz);
+    const bool hasjm = j > 0, hasjp = j + 1 < g.ny, haskm = k > 0, haskp = k + 1 < g.nz;
+    const int nz = g.nz;
+    auto X = [&](int64_t l) -> double { return S.dmask[l] ? (double)S.b[l] : (double)S.x[l]; };
+    int64_t base = (int64_t)i0 * P + r0;
+    double sc = X(base), sm = sc;
+    double txm = 0.0;
+    if (i0 > 0) {
+        sm = X(base - P);
+        txm = c.tx[base - P];
+    }
+    for (int i = i0; i < i1; ++i, base += P) {
+        const double sp = (i + 1 < g.nx) ? X(base + P) : sc;
+        const double txc = c.tx[base], tyc = c.ty[base], tzc = c.tz[base];
+        const double ac = coef_plane_uniform(c, i, g.nx) ? (double)c.a_const : c.a64[base];
+        double tyl = 0.0, tzl = 0.0, sjm = sc, sjp = sc, skm = sc, skp = sc;
+        if (hasjm) {
+            tyl = c.ty[base - nz];
+            sjm = X(base - nz);
+        }
+        if (hasjp) sjp = X(base + nz);
+        if (haskm) {
+            tzl = c.tz[base - 1];
+            skm = X(base - 1);
+        }
+        if (haskp) skp = X(base + 1);
+        const double y = cell_op<double, double>(ac, sc, txc, sp, txm, sm, tyc, sjp, tyl, sjm, tzc, skp, tzl, skm);
+        const bool d = S.dmask[base] != 0;
+        const double bv = S.b[base];
+        const double r64 = d ? 0.0 : bv - y;
+        const float r = (float)r64;
+        S.r[base] = r;
+        acc.rr += r * r;
+        if (jac) {
+            const float z = S.dinv[base] * r;
+            S.z[base] = z;
+            acc.rz += r * z;
+        }
+        if (zero_dx) S.dx[base] = 0.f;
+        acc.rr64 += r64 * r64;
+        if (!d) {
+            acc.bb += (float)bv * (float)bv;
+            acc.bb64 += bv * bv;
+        }
+        sm = sc;
+        sc = sp;
+        txm = txc;
+    }
+}
+
+// Outcome of one FP32 CG pass of a system.
+struct PassOut {
+    int iters;      // iterations of the pass
+    int status;     // 0 converged (recursive residual), 1 iteration cap, -4 breakdown
+    int tail;       // the deferred step alpha_prev p_{iters-1} is still owed
+    float alpha_prev;
+    float rr;       // recursive r.r at exit
+    bool aborted;   // a wait expired (the error flag is set)
+};
+
+// One CG pass: from r (and z) as the residual pass left them, iterate until
+// r.r <= thresh2, kmax iterations, or a breakdown, accumulating the solution
+// in xv. Exchange tags continue from tag0 so that no tag repeats in a launch.
+__device__ PassOut cg_pass(const BatchSys& S, const BatchRun& run, int t, int B, int W, bool jac, float rr,
+                           float rz, float thresh2, int kmax, unsigned tag0, float* xv, float* red) {
+    PassOut out{0, 1, 0, 0.f, rr, false};
     float* rr_part = S.part + B;
     float* rz_part = S.part + 2 * B;
-    float* bb_part = S.part + 3 * B;
-
-    // initial residual r = b - A x' with x' = b on Dirichlet cells, x elsewhere
-    float rr = 0.f, rz = 0.f, bb = 0.f;
-    for (int w = t; w < W; w += B) {
-        const int pc = w % S.nchunk, ic = w / S.nchunk;
-        march_item(g, c, pc, ic, S.ci,
-                   [&](int64_t l) { return S.dmask[l] ? S.b[l] : S.x[l]; },
-                   [&](int64_t l, float, float y) {
-                       const float r = S.b[l] - y;
-                       S.r[l] = r;
-                       rr += r * r;
-                       if (jac) {
-                           const float z = S.dinv[l] * r;
-                           S.z[l] = z;
-                           rz += r * z;
-                       }
-                       if (!S.dmask[l]) bb += S.b[l] * S.b[l];
-                   });
-    }
-    {
-        const float a0 = block_sum(rr, red), a1 = block_sum(rz, red), a2 = block_sum(bb, red);
-        if (threadIdx.x == 0) {
-            rr_part[t] = a0;
-            rz_part[t] = a1;
-            bb_part[t] = a2;
-        }
-    }
-    if (!sys_barrier(S.bar, B, run.limit_ticks, run.err)) return;
-    rr = sum_partials(rr_part, B, red);
-    rz = sum_partials(rz_part, B, red);
-    bb = sum_partials(bb_part, B, red);
-    const float bnorm2 = bb > 0.f ? bb : rr;
-    const float thresh2 = run.tol2 * bnorm2;
     float rho = jac ? rz : rr;
     float beta = 0.f, alpha_prev = 0.f;
-    int k = 0, status = 0, tail = 0;
+    int k = 0;
     const float* src = jac ? S.z : S.r;
 
     if (run.merged) {
@@ -495,12 +501,12 @@ __global__ __launch_bounds__(kThreads) void batched_cg(const BatchSys* __restric
         // alpha_{K-1} = rho_{K-1} / p.q, rho_K = rho_{K-1} - 2 alpha r.q + alpha^2 q.q
         // (one step from the exact rho_{K-1}) and beta_{K-1} = rho_K / rho_{K-1}.
         // Convergence is tested on the exact rho_{K-1}; iteration K-1 completed
-        // x_{K-1}, so the run stops with no owed update. One barrier per iteration.
+        // x_{K-1}, so the pass stops with no owed update. One barrier per iteration.
         //
         // With a single barrier per iteration the partial sums are double
         // buffered: iteration K writes set (K+1) & 1 and iteration K+1 reads it,
         // so no block overwrites sums another block may still be reading (set 0
-        // holds the initial residual's sums, read before iteration 0's barrier).
+        // holds the residual pass's sums, read before iteration 0's barrier).
         float alpha = 0.f, bm = 0.f;
         int K = 0;
         for (;;) {
@@ -519,10 +525,11 @@ __global__ __launch_bounds__(kThreads) void batched_cg(const BatchSys* __restric
             const bool conv = isfinite(rr) && rr <= thresh2;
             bad = !conv && (bad || !isfinite(rr));
             const int done = K == 0 ? 0 : K - 1;
-            if (conv || bad || done >= run.max_iter) {
-                status = conv ? 0 : (bad ? -4 : 1);
-                k = done;
-                break;
+            if (conv || bad || done >= kmax) {
+                out.status = conv ? 0 : (bad ? -4 : 1);
+                out.iters = done;
+                out.rr = rr;
+                return out;
             }
             const bool up = K > 0;
             const float* rin = (K & 1) ? S.r2 : S.r;
@@ -533,8 +540,8 @@ __global__ __launch_bounds__(kThreads) void batched_cg(const BatchSys* __restric
             float* pnew = (K & 1) ? S.p1 : S.p0;
             float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
             for (int w = t; w < W; w += B) {
-                const float4 v =
-                    merged_item(S, w % S.nchunk, w / S.nchunk, rin, qin, pold, rout, qout, pnew, up, alpha, bm);
+                const float4 v = merged_item(S, w % S.nchunk, w / S.nchunk, rin, qin, pold, rout, qout, pnew, xv,
+                                             up, alpha, bm);
                 d.x += v.x;
                 d.y += v.y;
                 d.z += v.z;
@@ -551,17 +558,20 @@ __global__ __launch_bounds__(kThreads) void batched_cg(const BatchSys* __restric
                     wr[3 * B + t] = a3;
                 }
             }
-            if (!sys_barrier(S.bar, B, run.limit_ticks, run.err)) return;
+            if (!sys_barrier(S.bar, B, run.limit_ticks, run.err)) {
+                out.aborted = true;
+                return out;
+            }
             ++K;
         }
     }
 
-    while (!run.merged) {
+    for (;;) {
         const bool conv = isfinite(rr) && rr <= thresh2;
         const bool bad = !conv && (!isfinite(rr) || (jac && (!(rho > 0.f) || !isfinite(rho))));
-        if (conv || bad || k >= run.max_iter) {
-            status = conv ? 0 : (bad ? -4 : 1);
-            tail = k >= 1 ? 1 : 0;
+        if (conv || bad || k >= kmax) {
+            out.status = conv ? 0 : (bad ? -4 : 1);
+            out.tail = k >= 1 ? 1 : 0;
             break;
         }
         // phase A
@@ -570,18 +580,21 @@ __global__ __launch_bounds__(kThreads) void batched_cg(const BatchSys* __restric
         const bool up = k > 0;
         float dot = 0.f;
         for (int w = t; w < W; w += B)
-            dot += phase_a_item(S, w % S.nchunk, w / S.nchunk, src, pold, pnew, up, beta, alpha_prev);
+            dot += phase_a_item(S, w % S.nchunk, w / S.nchunk, src, pold, pnew, xv, up, beta, alpha_prev);
         // p.q: a fence-free exchange (phase B needs no other block's data)
         float pq = 0.f;
         if (B > 1) {
             const float a0 = block_sum(dot, red);
-            if (!exchange_sum(S.xch, t, B, (unsigned)k + 1u, a0, run.limit_ticks, run.err, red, &pq)) return;
+            if (!exchange_sum(S.xch, t, B, tag0 + (unsigned)k + 1u, a0, run.limit_ticks, run.err, red, &pq)) {
+                out.aborted = true;
+                return out;
+            }
         } else {
             pq = block_sum(dot, red);
         }
         if (!(pq > 0.f) || !isfinite(pq)) {
-            status = -4;
-            tail = 0;
+            out.status = -4;
+            out.tail = 0;
             break;
         }
         const float alpha = rho / pq;
@@ -599,7 +612,10 @@ __global__ __launch_bounds__(kThreads) void batched_cg(const BatchSys* __restric
                 rz_part[t] = a1;
             }
         }
-        if (!sys_barrier(S.bar, B, run.limit_ticks, run.err)) return;
+        if (!sys_barrier(S.bar, B, run.limit_ticks, run.err)) {
+            out.aborted = true;
+            return out;
+        }
         rr = sum_partials(rr_part, B, red);
         const float rho_new = jac ? sum_partials(rz_part, B, red) : rr;
         beta = rho_new / rho;
@@ -607,21 +623,118 @@ __global__ __launch_bounds__(kThreads) void batched_cg(const BatchSys* __restric
         alpha_prev = alpha;
         ++k;
     }
-    // owed step, Dirichlet values
-    const float* plast = ((k - 1) & 1) ? S.p1 : S.p0;
-    for (int w = t; w < W; w += B) {
-        const int pc = w % S.nchunk, ic = w / S.nchunk;
-        own_cells(g, pc, ic, S.ci, [&](int64_t l) {
-            if (S.dmask[l]) S.x[l] = S.b[l];
-            else if (tail) S.x[l] += alpha_prev * plast[l];
-        });
+    out.iters = k;
+    out.alpha_prev = alpha_prev;
+    out.rr = rr;
+    return out;
+}
+
+__global__ __launch_bounds__(kThreads) void batched_cg(const BatchSys* __restrict__ systems,
+                                                       const int* __restrict__ block_sys, BatchRun run) {
+    __shared__ float red[kThreads / kWave];
+    __shared__ double red64[kThreads / kWave];
+    BatchSys S = systems[block_sys[blockIdx.x]];
+    {
+        // the operator's scalars as set last (they live with the grid, not the plan)
+        const CoefScalars cs = *S.cs;
+        S.c.a_uniform = cs.a_uniform;
+        S.c.a_const = cs.a_const;
+    }
+    const int t = (int)blockIdx.x - S.blk0, B = S.nblk;
+    const int W = S.nchunk * S.nich;
+    const bool jac = run.precond == 1;
+    float* rr_part = S.part + B;
+    float* rz_part = S.part + 2 * B;
+    float* bb_part = S.part + 3 * B;
+
+    // Pass 0 solves A x = b from the caller's x in place. With refinement every
+    // later pass o solves A dx = r_o for the FP64 true residual r_o of the
+    // current x (rounded to FP32), to a reduction min(0.5, max(tol / rho_o,
+    // inner_tol)) of |r_o|, and then adds dx to x (one rounding to FP32 per
+    // pass), until the FP64 true relative residual rho meets tol.
+    int ktot = 0, passes = 0, status = 1;
+    float rr = 0.f, bnorm2 = 0.f, rr_exit = 0.f;
+    double rr64 = 0.0, bb64 = 0.0;
+    for (int outer = 0;; ++outer) {
+        // residual pass: r = b - A x' in FP64 (the initial residual, or the true
+        // residual of the updated x)
+        ResidSums acc{0.f, 0.f, 0.f, 0.0, 0.0};
+        for (int w = t; w < W; w += B) residual_item64(S, w % S.nchunk, w / S.nchunk, jac, outer > 0, acc);
+        {
+            const float a0 = block_sum(acc.rr, red), a1 = block_sum(acc.rz, red), a2 = block_sum(acc.bb, red);
+            const double d0 = block_sum(acc.rr64, red64), d1 = block_sum(acc.bb64, red64);
+            if (threadIdx.x == 0) {
+                rr_part[t] = a0;
+                rz_part[t] = a1;
+                bb_part[t] = a2;
+                S.part64[t] = d0;
+                S.part64[B + t] = d1;
+            }
+        }
+        if (!sys_barrier(S.bar, B, run.limit_ticks, run.err)) return;
+        rr = sum_partials(rr_part, B, red);
+        const float rz = sum_partials(rz_part, B, red);
+        rr64 = sum_partials(S.part64, B, red64);
+        if (outer == 0) {
+            const float bb = sum_partials(bb_part, B, red);
+            bnorm2 = bb > 0.f ? bb : rr;
+            bb64 = sum_partials(S.part64 + B, B, red64);
+        }
+        const double rho = bb64 > 0.0 ? sqrt(rr64 / bb64) : sqrt(rr64);
+        if (outer > 0) {
+            if (run.max_outer == 0 || status < 0) break;   // FP32: the pass's own status stands
+            if (rho <= run.tol) {
+                status = 0;
+                break;
+            }
+            if (outer > run.max_outer || ktot >= run.max_iter || !isfinite(rho)) {
+                status = isfinite(rho) ? 1 : -4;
+                break;
+            }
+        } else if (run.max_outer > 0 && rho <= run.tol) {
+            status = 0;                                      // the initial guess meets tol
+            break;
+        }
+        float thresh2 = run.tol2 * bnorm2;
+        if (outer > 0) {
+            const double inner = fmin(0.5, fmax(run.tol / rho, run.inner_tol));
+            thresh2 = (float)(inner * inner * rr64);
+        }
+        float* xv = outer == 0 ? S.x : S.dx;
+        const PassOut po = cg_pass(S, run, t, B, W, jac, rr, rz, thresh2, run.max_iter - ktot,
+                                   (unsigned)ktot + (unsigned)outer, xv, red);
+        if (po.aborted) return;
+        // owed step, the correction, Dirichlet values
+        const float* plast = ((po.iters - 1) & 1) ? S.p1 : S.p0;
+        for (int w = t; w < W; w += B) {
+            const int pc = w % S.nchunk, ic = w / S.nchunk;
+            own_cells(S.g, pc, ic, S.ci, [&](int64_t l) {
+                if (S.dmask[l]) {
+                    S.x[l] = S.b[l];
+                } else if (outer == 0) {
+                    if (po.tail) S.x[l] += po.alpha_prev * plast[l];
+                } else {
+                    const float d = po.tail ? S.dx[l] + po.alpha_prev * plast[l] : S.dx[l];
+                    S.x[l] = (float)((double)S.x[l] + (double)d);
+                }
+            });
+        }
+        ktot += po.iters;
+        passes += 1;
+        status = po.status;
+        rr_exit = po.rr;
+        // every block's x is complete before the residual pass reads neighbours
+        if (!sys_barrier(S.bar, B, run.limit_ticks, run.err)) return;
     }
     if (t == 0 && threadIdx.x == 0) {
         BatchResult* res = S.res;
-        res->iters = k;
+        res->iters = ktot;
         res->status = status;
-        res->rr = rr;
+        res->passes = passes;
+        res->rr = rr_exit;
         res->bnorm2 = bnorm2;
+        res->rr64 = rr64;
+        res->bb64 = bb64;
     }
 }
 

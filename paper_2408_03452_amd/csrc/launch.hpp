@@ -157,22 +157,37 @@ hipError_t launch_differ(int64_t n, const float* a, const float* b, int* flag, h
 
 // Batched persistent CG.
 struct BatchResult {
-    int iters;
-    int status;    // 0 converged, 1 iteration cap, -4 breakdown
-    float rr;      // r.r at exit
-    float bnorm2;  // ||b_U||^2
+    int iters;      // CG iterations over all passes
+    int status;     // 0 converged, 1 iteration or refinement cap, -4 breakdown
+    int passes;     // CG passes: 1 + refinement corrections
+    float rr;       // recursive r.r of the last pass at exit
+    float bnorm2;   // ||b_U||^2 (FP32)
+    int pad;
+    double rr64;    // ||b - A x||^2 over the unknown cells, FP64, at exit
+    double bb64;    // ||b_U||^2, FP64
+};
+
+// The scalar part of a grid's operator that may change when its coefficients
+// are set again (Coef::a_uniform, Coef::a_const), in device memory owned by the
+// grid, so that a batched plan or a captured graph never holds stale copies.
+struct CoefScalars {
+    int a_uniform;
+    float a_const;
 };
 
 struct BatchSys {
     Geom g;
-    Coef c;
+    Coef c;                      // a_uniform and a_const are read from cs at launch
+    const CoefScalars* cs;
     const float* dinv;
     const uint8_t* dmask;
     const float* b;
     float* x;
     float *r, *p0, *p1, *q, *z;  // workspace of the system's grid handle
+    float* dx;                   // refinement: the correction of a pass (grid workspace)
     float *r2, *q2;              // second r and q buffers (single-reduction form only)
     float* part;                 // 2 sets of 4 * nblk partial sums
+    double* part64;              // 2 * nblk FP64 partial sums of the residual pass
     unsigned* bar;               // barrier: arrival count, generation
     unsigned long long* xch;     // per block of the system: (tag << 32) | bits of its p.q partial
     BatchResult* res;
@@ -187,6 +202,12 @@ struct BatchRun {
     int merged;             // 1: single-reduction iteration (plain CG only)
     uint64_t limit_ticks;   // barrier watchdog, in wall-clock ticks
     int* err;               // set to 1 when a barrier wait expires
+    int max_outer;          // 0: one FP32 pass, its FP64 true residual reported;
+                            // > 0: up to this many FP32 correction passes, each
+                            // started from the FP64 true residual, until that
+                            // residual meets tol
+    double tol;             // target of the true residual (max_outer > 0)
+    double inner_tol;       // smallest relative reduction asked of one correction pass
 };
 
 int batched_blocks_per_cu();
