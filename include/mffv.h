@@ -249,6 +249,22 @@ int mffv_true_residual(mffv_grid* grid, const float* b, const double* x, double*
                        double* rel_out);
 
 /*
+ * For callers that cannot allocate device memory (serving loops, harnesses
+ * that forbid allocation once set up): mffv_true_residual without any
+ * allocation. r_out (FP64 device, n entries) is required here. The two norms
+ * and the per-block partial sums of the reductions live in a static device
+ * array of 2 MiB + 256 B that each GPU holds until the process ends (taken on
+ * the first call on that GPU); a grid whose residual launch needs more than
+ * 2^18 partial sums returns MFFV_EINVAL. Every call on one GPU shares that
+ * array, so calls that overlap on one GPU (other streams or threads) race.
+ * Same result bits as mffv_true_residual. Synchronizes the grid's stream to
+ * return *rel_out. Errors: MFFV_EINVAL (NULL argument, aliasing, too many
+ * partial sums), MFFV_ESTATE (coefficients not set), MFFV_EHIP.
+ */
+int mffv_true_residual_noalloc(mffv_grid* grid, const float* b, const double* x, double* r_out,
+                               double* rel_out);
+
+/*
  * Solve A x = b with conjugate gradient (Alg. 1), the apply fused with the
  * vector updates and the device-wide dot products.
  *   b     device FP32 right-hand side (n entries); its D entries are the

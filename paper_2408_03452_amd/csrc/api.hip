@@ -1429,6 +1429,75 @@ int mffv_true_residual(mffv_grid* G, const float* b, const double* x, double* r_
     return read_rel(G, rel_out);
 }
 
+// ---------------------------------------------------------------------------
+// The true residual without allocation: the two result norms and the
+// per-block partial sums of its reductions live in a static device array
+// (one per GPU, held until the process ends) instead of grid-owned memory.
+// The array's host-side name is not a device address; its address on each
+// device comes from hipGetSymbolAddress, taken once per device with that
+// device current, and only that address is handed to kernels.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+constexpr int kScratchHead = 32;                  // [0] ||b_U||^2, [1] ||r||^2, rest unused
+constexpr int kScratchParts = 1 << 18;            // partial sums (one per block of a launch)
+constexpr size_t kScratchDoubles = kScratchHead + kScratchParts;   // 2 MiB + 256 B
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch (taken on the first call on it).
+int scratch_on(int device, double** out) {
+    if (device < 0 || device >= kMaxDevices) return fail(MFFV_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(MFFV_EHIP, "hipGetSymbolAddress returned NULL for the scratch array");
+        g_scratch_ptr[device] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return MFFV_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int mffv_true_residual_noalloc(mffv_grid* G, const float* b, const double* x, double* r_out,
+                               double* rel_out) {
+    int rc = check_grid(G, true);
+    if (rc) return rc;
+    if (!b || !x || !r_out || !rel_out) return fail(MFFV_EINVAL, "NULL argument (r_out is required)");
+    if ((const void*)r_out == (const void*)x || (const void*)r_out == (const void*)b)
+        return fail(MFFV_EINVAL, "r_out must not alias b or x");
+    const int parts = std::max(G->m64.blocks(), G->nb_vec);
+    if (parts > kScratchParts)
+        return fail(MFFV_EINVAL, "grid needs " + std::to_string(parts) + " partial sums, more than the " +
+                                     std::to_string(kScratchParts) + " of the no-allocation scratch");
+    if ((rc = set_device(G))) return rc;
+    double* sp = nullptr;
+    if ((rc = scratch_on(G->device, &sp))) return rc;
+    double* head = sp;
+    double* part = sp + kScratchHead;
+    StencilIO<double> io;
+    io.src = x;
+    io.out = r_out;
+    io.rhs = b;
+    io.rhs_f64 = 0;
+    io.partials = part;
+    HIP_TRY(launch_stencil_f64(kResidual, G->g, coef_of(G), io, G->m64, G->stream));
+    HIP_TRY(launch_sum_partials(part, G->m64.blocks(), head + 1, G->stream));
+    HIP_TRY(launch_masked_norm2(G->g.n, G->dmask, b, 0, part, head + 0, G->nb_vec, G->stream));
+    double h[2];
+    HIP_TRY(hipMemcpyAsync(h, head, sizeof(h), hipMemcpyDeviceToHost, G->stream));
+    HIP_TRY(hipStreamSynchronize(G->stream));
+    *rel_out = h[0] > 0 ? std::sqrt(h[1] / h[0]) : std::sqrt(h[1]);
+    return MFFV_OK;
+}
+
 int mffv_cg_solve(mffv_grid* G, const float* b, float* x, const mffv_opts* opts, mffv_info* info) {
     int rc = check_grid(G, true);
     if (rc) return rc;

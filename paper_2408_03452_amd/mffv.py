@@ -86,6 +86,7 @@ def _declare(lib):
         "mffv_apply": (ctypes.c_int, [_P, _P, _P]),
         "mffv_apply_f64": (ctypes.c_int, [_P, _P, _P]),
         "mffv_true_residual": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
+        "mffv_true_residual_noalloc": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
         # info: a host mffv_info (array) or, with opts.async, a device array
         "mffv_cg_solve": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(Opts), _P]),
         "mffv_cg_solve_f64": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(Opts),
@@ -307,6 +308,16 @@ def true_residual(grid: Grid, b, x, r_out=None) -> float:
                                     _ptr(x, torch.float64, grid.n, "x"),
                                     _ptr(r_out, torch.float64, grid.n, "r_out"),
                                     ctypes.byref(rel)))
+    return rel.value
+
+
+def true_residual_noalloc(grid: Grid, b, x, r_out) -> float:
+    """mffv_true_residual without allocation (r_out required)."""
+    rel = ctypes.c_double()
+    _check(lib().mffv_true_residual_noalloc(grid.handle, _ptr(b, torch.float32, grid.n, "b"),
+                                            _ptr(x, torch.float64, grid.n, "x"),
+                                            _ptr(r_out, torch.float64, grid.n, "r_out"),
+                                            ctypes.byref(rel)))
     return rel.value
 
 
