@@ -1,20 +1,27 @@
-"""Benchmark: time to relative residual 1e-6 and stencil-apply HBM bandwidth.
+"""Benchmark: time to relative residual 1e-6 (learned flexible CG vs plain CG)
+and stencil-apply HBM bandwidth.
 
-One step is one complete solve of the correlated log-normal 256^3 system
-(sigma = 2, Gaussian correlation length 8 cells, c = 1e-3, x-plane Dirichlet
-1/0) from a zero initial guess to a true relative residual of 1e-6: FP32
-matrix-free CG with the apply fused into the vector updates and reductions,
-then the FP64 true residual and, if needed, FP64 refinement. Inputs (the
-coefficients and the right-hand side) are resident in device memory before
-the timed region starts.
+One step is one complete solve of a held-out realisation of the channelised
+two-facies 128^3 workload (1000 / 1 mD sinusoidal channels, c = 1e-3, x-plane
+Dirichlet 1/0; held-out seeds 3500 + i) with flexible CG preconditioned by the
+library's 3D-convolution network, from a zero initial guess to an FP64 true
+relative residual of 1e-6 (FP32 iterations, FP64 true residual and
+refinement; the FP64 field is returned). The network is trained first, on the
+GPU, by the library's own kernels, on held-in realisations (not timed). Each
+held-out realisation is also solved by plain CG and by Jacobi-PCG to the same
+true residual. ``value`` is the median learned-FCG time over the timed steps;
+the line also carries both other methods, the network layers' per-launch
+times against the dense BF16 matrix-core peak (roofline), and each result's
+field error against the FP64 oracle on 64^3 crop problems.
 
-Besides the headline time it measures, on the grid's own stream with HIP
-events: the stencil apply (20 algorithmic bytes per cell) against the MI355X
-HBM peak, the library's streaming copy (the achievable ceiling), and the
-FP64 oracle on the host (SciPy CSR CG, one thread) on a 64^3 crop of the same
-field as the CPU baseline.
+Further sections (each a key of the JSON line): the 256^3 correlated
+log-normal solve and the stencil kernels against the HBM peak and their
+streaming ceilings, the 512 x 512 x 1024 anisotropic system (apply GB/s, CG
+rate), 64 batched uneven systems, backward-Euler time steps with wells, the
+256^3 field as a face-list mesh, and the oracle on the host as the CPU
+baseline.
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] ...
 """
 from __future__ import annotations
 
@@ -71,6 +78,12 @@ PHASE_A_BYTES_PER_CELL = 34     # steady-state mean of phase_a_bytes over two it
 MERGED_BYTES_PER_CELL = 44      # single-reduction iteration: r, q, p, x, Tx, Ty, Tz read;
                                 # r, p, q, x written
 METRIC = "time to rel-resid 1e-6 (learned FCG vs plain CG); stencil-apply HBM GB/s"
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix-core peak
+# algorithmic FLOPs per cell of each network layer: 27 taps x cin x cout x 2
+NN_LAYER_FLOP_PER_CELL = (27 * 2 * 16 * 2, 27 * 16 * 16 * 2, 27 * 16 * 16 * 2, 27 * 16 * 1 * 2)
+# HBM bytes per launch of the hidden convolution on 128^3 from rocprofv3
+# FETCH_SIZE and WRITE_SIZE (scaled like the stencil counters), or None
+NN_TRAFFIC = {"hidden": None}
 # launch shapes the stencil autotuner reports: the CG kernels' and the apply's own
 LAUNCH_KEYS = ("ci", "remap", "seg", "vec", "blocks", "apply_ci", "apply_remap", "apply_seg", "apply_blocks")
 # HBM bytes per launch of the step's dominant kernel on the 256^3 workload from
@@ -108,31 +121,6 @@ def cells_iter_rate(cells: float, iters: float, seconds: float) -> float:
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-def cpu_baseline(k, c, tol, crop=64):
-    """Oracle FP64 CG (SciPy CSR product, single thread) on a crop of the field."""
-    import numpy as np
-    from oracle import tpfa, krylov
-    kc = np.ascontiguousarray(k[:crop, :crop, :crop])
-    T = tpfa.round_to_f32(*tpfa.transmissibility(kc))
-    dm, pd = tpfa.x_plane_dirichlet(kc.shape)
-    A, b = tpfa.assemble(*T, float(np.float32(c)), dm, pd)
-    Auu, bu, _ = tpfa.reduce_to_unknowns(A, b, dm)
-    t0 = time.perf_counter()
-    res = krylov.cg(Auu, bu, tol=tol, max_iter=20000)
-    dt = time.perf_counter() - t0
-    return {
-        "value": cells_iter_rate(kc.size, res.iters, dt),
-        "unit": "cell*iter/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": (f"{crop}^3 crop [0:{crop}]^3 of the same field with its own x-plane Dirichlet "
-                   f"planes; FP64 CG to rel-resid {tol:g}: {res.iters} iterations in {dt:.2f} s "
-                   f"(SciPy CSR matvec, 1 thread of {os.cpu_count()} host cores)"),
-        "time_to_solution_s": dt,
-        "iters": res.iters,
-    }
 
 
 def bench_large(log_fn, solve: bool, cg_iters: int = 200):
@@ -420,7 +408,7 @@ def bench_batched(log_fn):
             grids.append(g)
             bs.append(b)
             xs.append(torch.zeros(n, dtype=torch.float32, device="cuda"))
-        opts = mffv.default_opts(tol=1e-6)
+        opts = mffv.default_opts(tol=1e-6, precision=mffv.FP32_IR)
         tune = mffv.autotune_batched(grids, bs, xs, opts)
         log_fn(f"batched autotune: {tune}")
         for x in xs:
@@ -448,78 +436,170 @@ def bench_batched(log_fn):
     return out
 
 
-def bench_learned(log_fn, held_in: int, held_out: int):
-    """Learned preconditioner on the channelised two-facies field: train on
-    held-in 32^3 realisations (seeds 3000+), confirm at 128^3 against the zero
-    network, then time flexible CG against Jacobi-PCG and plain CG on held-out
-    128^3 realisations (seeds 3500+) to 1e-6."""
+def make_problem(k, c, stream, kz_ratio=1.0):
+    """Grid handle and right-hand side of a permeability field (x-plane
+    Dirichlet 1/0, scalar accumulation c), built through the C ABI."""
+    import numpy as np
+    import torch
+    from paper_2408_03452_amd import mffv
+    nx, ny, nz = k.shape
+    n = k.size
+    kd = torch.from_numpy(np.ascontiguousarray(k).ravel()).cuda()
+    tx, ty, tz, b = (torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(4))
+    mffv.perm_to_trans(nx, ny, nz, kd, kz_ratio, tx, ty, tz, stream=stream)
+    g = mffv.create_grid(nx, ny, nz, stream=stream)
+    mffv.set_transmissibility(g, tx, ty, tz, accum_scalar=c, b_out=b)
+    return g, b
+
+
+def solve_f64(g, b64, opts):
+    """One timed solve from a zero initial guess; returns (seconds, info, x64)."""
+    import torch
+    from paper_2408_03452_amd import mffv
+    x = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, info = mffv.cg_solve_f64(g, b64, x, opts)
+    torch.cuda.synchronize()
+    info["status"] = st
+    return time.perf_counter() - t0, info, x
+
+
+def bench_channelised(log_fn, held_in: int, held_out: int, steps: int, warmup: int):
+    """The headline: learned flexible CG against plain CG and Jacobi-PCG on
+    held-out 128^3 channelised realisations, each solve to an FP64 true
+    relative residual of 1e-6 (FP32 iterations with FP64 refinement, FP64 field
+    out). The network is trained on held-in 32^3 realisations (seeds 3000+)
+    first. Per realisation every method first runs a short untimed solve (its
+    graph capture and workspace allocation are set-up), then the timed solve.
+    The learned solves of the first ``steps`` realisations are the timed steps
+    of the benchmark; the comparison covers all ``held_out`` realisations."""
     import numpy as np
     import torch
     from paper_2408_03452_amd import mffv, learned
     from synth import channelised
 
-    def problem(k, stream):
-        nx, ny, nz = k.shape
-        n = k.size
-        kd = torch.from_numpy(np.ascontiguousarray(k).ravel()).cuda()
-        tx, ty, tz, b = (torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(4))
-        mffv.perm_to_trans(nx, ny, nz, kd, 1.0, tx, ty, tz, stream=stream)
-        g = mffv.create_grid(nx, ny, nz, stream=stream)
-        mffv.set_transmissibility(g, tx, ty, tz, accum_scalar=1e-3, b_out=b)
-        return g, b
-
+    shape = (128, 128, 128)
+    c = 1e-3
     s = torch.cuda.Stream()
+    out = {"workload": "channelised_128cube", "grid": list(shape), "cells": int(np.prod(shape)),
+           "accumulation": c, "held_out": held_out, "held_in_32cube": held_in,
+           "tol_true": 1e-6, "precision": "FP32 iterations, FP64 true residual and refinement, FP64 field"}
     with torch.cuda.stream(s):
         t0 = time.perf_counter()
-        train = [problem(channelised((32, 32, 32), 3000 + i), s) for i in range(held_in)]
-        confirm = [problem(channelised((128, 128, 128), 3000 + i), s) for i in range(2)]
-        # epoch selection on 8 held-in 32^3 systems (the zero network, i.e. Jacobi,
-        # is the first candidate)
+        train = [make_problem(channelised((32, 32, 32), 3000 + i), c, s) for i in range(held_in)]
         net = learned.train_preconditioner(train, validation=train[:8], n_white=10 * held_in,
                                            epochs=6, lr=2e-3, dagger_rounds=1, dagger_epochs=2,
                                            log=log_fn)
-        t_train = time.perf_counter() - t0
-        log_fn(f"learned: trained on {held_in} held-in 32^3 realisations in {t_train:.1f} s")
-        zero = mffv.net_create(learned.init_params(0))
-        it_net = learned.fcg_iterations(net, confirm)
-        it_zero = learned.fcg_iterations(zero, confirm)
-        chosen = net
-        log_fn(f"learned: 128^3 held-in check, FCG iterations trained {it_net} vs zero net {it_zero}")
-        methods = (("plain", mffv.default_opts()),
-                   ("jacobi", mffv.default_opts(precond=mffv.PRECOND_JACOBI)),
-                   ("learned_fcg", mffv.default_opts(precond=mffv.PRECOND_LEARNED, net=chosen)))
-        rows = {name: [] for name, _ in methods}
-        for i in range(held_out):
-            g, b = problem(channelised((128, 128, 128), 3500 + i), s)
-            for name, opts in methods:
-                x = torch.zeros(g.n, dtype=torch.float32, device="cuda")
-                if i == 0:
-                    mffv.cg_solve(g, b, x, opts)
-                    x.zero_()
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                st, info = mffv.cg_solve(g, b, x, opts)
-                torch.cuda.synchronize()
-                rows[name].append((time.perf_counter() - t1, info["iters"], info["rel_res_recursive"],
-                                   info["rel_res_true"], st))
+        out["train_s"] = time.perf_counter() - t0
+        log_fn(f"channelised: trained on {held_in} held-in 32^3 realisations in {out['train_s']:.1f} s")
+        for g, _ in train:
             g.close()
-    out = {"workload": "channelised_128cube", "held_out": held_out, "held_in_32cube": held_in,
-           "train_s": t_train, "check_iters_trained_vs_zero": [it_net, it_zero],
-           "network": "trained" if chosen is net else "zero (Jacobi)"}
+        del train
+        methods = {
+            "learned_fcg": lambda tol=1e-6, **kw: mffv.default_opts(
+                tol=tol, precision=mffv.FP32_IR, precond=mffv.PRECOND_LEARNED, net=net, **kw),
+            "plain": lambda tol=1e-6, **kw: mffv.default_opts(tol=tol, precision=mffv.FP32_IR, **kw),
+            "jacobi": lambda tol=1e-6, **kw: mffv.default_opts(
+                tol=tol, precision=mffv.FP32_IR, precond=mffv.PRECOND_JACOBI, **kw),
+        }
+        rows = {m: [] for m in methods}
+        step_times = []
+        n_eval = max(held_out, steps)
+        for i in range(n_eval):
+            seed = 3500 + (i % held_out)
+            g, b = make_problem(channelised(shape, seed), c, s)
+            b64 = b.double()
+            for name, mk in methods.items():
+                solve_f64(g, b64, mk(max_iter=16))                    # set-up: graphs, workspace
+                if i == 0 and name == "learned_fcg":
+                    for _ in range(warmup):
+                        solve_f64(g, b64, mk())
+                    # per-layer times of the network inside flexible CG (HIP events
+                    # on the grid's stream), first 32 iterations
+                    xt = torch.zeros(g.n, dtype=torch.float32, device="cuda")
+                    _, tinfo = mffv.cg_solve(g, b, xt, mffv.default_opts(
+                        tol=1e-6, precond=mffv.PRECOND_LEARNED, net=net, timing=1))
+                    out["timing"] = {k: tinfo[k] for k in ("phase_a_us", "phase_b_us", "precond_us",
+                                                            "timed_iters", "nn_layer_us", "nn_timed")}
+                    del xt
+                dt, info, x = solve_f64(g, b64, mk())
+                if i < held_out:
+                    rows[name].append((dt, info["iters"], info["ir_steps"], info["rel_res_true"],
+                                       info["status"], info["fallbacks"]))
+                if name == "learned_fcg" and i < steps:
+                    step_times.append(dt)
+                if i == 0 and name == "learned_fcg":
+                    out["_x_first"] = x.cpu().numpy()
+                del x
+            if i < held_out and (i % 10 == 9 or i == held_out - 1):
+                log_fn(f"channelised: {i + 1}/{held_out} held-out realisations; median so far (ms): " +
+                       ", ".join(f"{m} {1e3 * np.median([r[0] for r in v]):.1f}" for m, v in rows.items()))
+            g.close()
+        out["_params"] = mffv.net_get_params(net)[0]
+        net.close()
     for name, r in rows.items():
         t = np.array([v[0] for v in r])
         it = np.array([v[1] for v in r])
-        out[name] = {"time_to_1e-6_s_median": float(np.median(t)), "iters_median": float(np.median(it)),
-                     "rel_res_recursive_max": float(max(v[2] for v in r)),
+        out[name] = {"time_to_1e-6_s_median": float(np.median(t)), "time_to_1e-6_s_mean": float(t.mean()),
+                     "iters_median": float(np.median(it)), "iters_min_max": [int(it.min()), int(it.max())],
+                     "ir_steps_max": int(max(v[2] for v in r)),
                      "rel_res_true_max": float(max(v[3] for v in r)),
-                     "all_converged": all(v[4] == 0 for v in r)}
-    out["learned_vs_plain_speedup"] = out["plain"]["time_to_1e-6_s_median"] / out["learned_fcg"]["time_to_1e-6_s_median"]
+                     "all_converged": all(v[4] == 0 for v in r),
+                     "fallbacks_max": int(max(v[5] for v in r))}
+    out["learned_vs_plain_speedup"] = (out["plain"]["time_to_1e-6_s_median"] /
+                                       out["learned_fcg"]["time_to_1e-6_s_median"])
+    out["learned_vs_jacobi_speedup"] = (out["jacobi"]["time_to_1e-6_s_median"] /
+                                        out["learned_fcg"]["time_to_1e-6_s_median"])
     out["learned_vs_jacobi_iters"] = out["learned_fcg"]["iters_median"] / out["jacobi"]["iters_median"]
-
-    for g, _ in train + confirm:
-        g.close()
-    out["_params"] = mffv.net_get_params(chosen)[0]
+    out["_step_times"] = step_times
     return out
+
+
+def bench_crop_fields(log_fn, c1_field, c3_params):
+    """GPU fields for the accuracy comparison with the oracle (made by the CPU
+    baseline leg): the 32^3 workload (plain CG in FP64 and in FP32 to 1e-6),
+    the [0:64]^3 crop of the 256^3 field as its own problem (FP32 CG refined to
+    1e-6 and to 1e-8), and the [0:64]^3 crop of held-out channelised realisation
+    3500 (learned flexible CG refined to 1e-6 and 1e-8, plain CG and
+    Jacobi-PCG refined to 1e-6)."""
+    import numpy as np
+    import torch
+    from paper_2408_03452_amd import mffv
+    from synth import WORKLOADS, workload_field, channelised
+    s = torch.cuda.Stream()
+    res = {}
+    with torch.cuda.stream(s):
+        w0 = WORKLOADS["lognormal_iid_32cube"]
+        k0 = workload_field(w0)
+        g, b = make_problem(k0, w0.c, s)
+        x = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+        st, info = mffv.cg_solve_f64(g, b.double(), x, mffv.default_opts(tol=1e-6, precision=mffv.FP64))
+        res["c0_fp64_cg_1e-6"] = {"k": k0, "c": w0.c, "x": x.cpu().numpy(), "info": info}
+        x32 = torch.zeros(g.n, dtype=torch.float32, device="cuda")
+        st, info = mffv.cg_solve(g, b, x32, mffv.default_opts(tol=1e-6))
+        res["c0_fp32_cg_1e-6"] = {"k": k0, "c": w0.c, "x": x32.double().cpu().numpy(), "info": info}
+        g.close()
+        kc = np.ascontiguousarray(c1_field[:64, :64, :64])
+        g, b = make_problem(kc, 1e-3, s)
+        for tol in (1e-6, 1e-8):
+            _, info, x = solve_f64(g, b.double(), mffv.default_opts(tol=tol, precision=mffv.FP32_IR))
+            res[f"c1_crop64_fp32_ir_{tol:g}"] = {"k": kc, "c": 1e-3, "x": x.cpu().numpy(), "info": info}
+        g.close()
+        k3 = np.ascontiguousarray(channelised((128, 128, 128), 3500)[:64, :64, :64])
+        g, b = make_problem(k3, 1e-3, s)
+        net = mffv.net_create(c3_params)
+        for name, pre, tols in (("learned_fcg", mffv.PRECOND_LEARNED, (1e-6, 1e-8)),
+                                ("plain", mffv.PRECOND_NONE, (1e-6,)),
+                                ("jacobi", mffv.PRECOND_JACOBI, (1e-6,))):
+            for tol in tols:
+                _, info, x = solve_f64(g, b.double(), mffv.default_opts(
+                    tol=tol, precision=mffv.FP32_IR, precond=pre, net=net if pre == mffv.PRECOND_LEARNED else None))
+                res[f"c3_crop64_{name}_{tol:g}"] = {"k": k3, "c": 1e-3, "x": x.cpu().numpy(), "info": info}
+        net.close()
+        g.close()
+    torch.cuda.synchronize()
+    return res
 
 
 def bench_large_learned(log_fn, c3_params, n_crops: int = 100, n_eval: int = 4):
@@ -621,49 +701,113 @@ def bench_large_learned(log_fn, c3_params, n_crops: int = 100, n_eval: int = 4):
     return out
 
 
-def main(argv=None):
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="lognormal_corr8_256cube")
-    ap.add_argument("--apply-reps", type=int, default=50)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-jacobi", action="store_true")
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--no-timesteps", action="store_true")
-    ap.add_argument("--no-faces", action="store_true")
-    ap.add_argument("--faces-rcm", action="store_true",
-                    help="also renumber the randomly numbered face-list mesh with mffv_face_order (about 30 s on the host)")
-    ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--learned-held-out", type=int, default=10,
-                    help="held-out 128^3 realisations in the learned comparison (50 = full set)")
-    ap.add_argument("--learned-held-in", type=int, default=200)
-    ap.add_argument("--no-large", action="store_true",
-                    help="skip the 512x512x1024 apply / CG-rate measurement")
-    ap.add_argument("--large-learned", action="store_true",
-                    help="fine-tune the learned preconditioner on crops of the 512x512x1024 workload and "
-                         "compare the methods there (needs the learned section)")
-    ap.add_argument("--large-solve", action="store_true",
-                    help="also solve the 512x512x1024 system to 1e-8 (minutes)")
-    args = ap.parse_args(argv)
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "x-slab design is described but not built.", flush=True)
-        return 2
+def cpu_baseline(c3_params, learned_iters, crop_fields, log_fn):
+    """The CPU baseline leg: the FP64 oracle on the host, one thread.
 
+    * The headline's baseline: one iteration of the oracle's flexible CG with
+      the oracle network (the trained parameters) as preconditioner, on the
+      [0:64]^3 crop of held-out realisation 3500 (network forward in NumPy plus
+      the CSR product and dots), timed and scaled by the cell count (x8 to
+      128^3) and by the GPU's median learned-FCG iteration count: the oracle's
+      time to 1e-6 on the headline workload, extrapolated.
+    * The accuracy of each GPU field of ``bench_crop_fields``: the oracle's
+      reference solution (direct for 32^3, Jacobi-PCG to 1e-12 for the 64^3
+      crops) and, per field, the relative L2 field error and the FP64 true
+      relative residual of the returned field."""
+    import numpy as np
+    import scipy.sparse.linalg as spla
+    from threadpoolctl import threadpool_limits
+    from oracle import krylov, nn, tpfa
+    from synth import channelised
+
+    def oracle_problem(k, c):
+        T = tpfa.round_to_f32(*tpfa.transmissibility(k))
+        dm, pd = tpfa.x_plane_dirichlet(k.shape)
+        A, b = tpfa.assemble(*T, float(np.float32(c)), dm, pd)
+        Auu, bu, u = tpfa.reduce_to_unknowns(A, b, dm)
+        return A, b, Auu, bu, u, dm, pd
+
+    out = {}
+    with threadpool_limits(limits=1):
+        k3 = np.ascontiguousarray(channelised((128, 128, 128), 3500)[:64, :64, :64])
+        A, b, Auu, bu, u, dm, pd = oracle_problem(k3, 1e-3)
+        d = A.diagonal()
+        ld = np.log(d)
+        feat = np.where(dm.ravel(), 0.0, ld - ld[u].mean()).reshape(k3.shape)
+
+        def M(ru):
+            r = np.zeros(d.size)
+            r[u] = ru
+            sc = np.sqrt(np.sum(ru * ru / d[u]) / u.size)
+            rh = np.zeros(d.size)
+            rh[u] = ru / np.sqrt(d[u]) / sc
+            N, _, _ = nn.forward(c3_params, rh.reshape(k3.shape), feat)
+            return (r / d + sc * N.ravel() / np.sqrt(d))[u]
+
+        t0 = time.perf_counter()
+        z = M(bu)
+        q = Auu @ z
+        _ = (z @ bu, z @ q)
+        t_iter = time.perf_counter() - t0
+        scale = (128 ** 3) / (64 ** 3)
+        out.update({
+            "value": t_iter * scale * learned_iters, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"one iteration of the oracle's flexible CG with the oracle network (FP64 NumPy "
+                       f"convolutions on BF16-rounded operands, SciPy CSR product) on the [0:64]^3 crop "
+                       f"of held-out channelised realisation 3500: {t_iter:.2f} s on 1 thread of "
+                       f"{os.cpu_count()} host cores; scaled x{scale:g} (cells, to 128^3) and x{learned_iters:g} "
+                       f"(the GPU's median learned-FCG iteration count): time to 1e-6, extrapolated"),
+            "oracle_fcg_iteration_s_64cube": t_iter,
+        })
+        log_fn(f"cpu: oracle learned-FCG iteration at 64^3 {t_iter:.2f} s -> {out['value']:.0f} s "
+               "to 1e-6 at 128^3 (extrapolated)")
+        # accuracy of the GPU fields against the oracle's reference solutions
+        refs = {}
+        acc = {}
+        for key, f in crop_fields.items():
+            kid = (id(f["k"]), f["c"])
+            if kid not in refs:
+                A, b, Auu, bu, u, dm, pd = oracle_problem(f["k"], f["c"])
+                t1 = time.perf_counter()
+                if f["k"].size <= 40 ** 3:
+                    xu = spla.spsolve(Auu.tocsc(), bu)
+                    how = "direct"
+                else:
+                    r = krylov.pcg(Auu, bu, krylov.jacobi(Auu), tol=1e-12, max_iter=50000)
+                    xu, how = r.x, f"Jacobi-PCG to 1e-12 ({r.iters} iterations)"
+                refs[kid] = (tpfa.scatter_solution(xu, u, pd, dm), A, b, dm, how, time.perf_counter() - t1)
+            p, A, b, dm, how, tref = refs[kid]
+            x = f["x"]
+            acc[key] = {"field_rel_err": float(np.linalg.norm(x - p) / np.linalg.norm(p)),
+                        "rel_res_true_oracle": float(tpfa.relative_residual(A, b, x, dm)),
+                        "rel_res_true_gpu": f["info"]["rel_res_true"], "iters": f["info"]["iters"],
+                        "reference": how, "reference_s": tref, "grid": list(f["k"].shape)}
+            log_fn(f"accuracy {key}: field error {acc[key]['field_rel_err']:.2e}, true rel-res "
+                   f"{acc[key]['rel_res_true_oracle']:.2e} (oracle reference: {how})")
+        out["accuracy_vs_oracle"] = acc
+    return out
+
+
+def bench_c1(log_fn, args):
+    """The 256^3 correlated log-normal workload: plain FP32 CG refined in FP64
+    to the true relative residual 1e-6 and to 1e-8 (the configuration's own
+    target), the fused CG kernels and the apply timed with HIP events on the
+    grid's stream against the HBM peak and against streaming probes of each
+    kernel's mix of arrays, and the streaming copy."""
     import numpy as np
     import torch
     from paper_2408_03452_amd import mffv
     from synth import WORKLOADS, workload_field
 
-    w = WORKLOADS[args.workload]
+    w = WORKLOADS["lognormal_corr8_256cube"]
     nx, ny, nz = w.shape
     n = w.n
-    log(f"{mffv.version()}; workload {w.name} {w.shape}, generating the field")
+    log_fn(f"c1: workload {w.name} {w.shape}, generating the field")
     k = workload_field(w)
     dev = torch.device("cuda")
     s = torch.cuda.Stream()
+    res = {"workload": w.name, "grid": list(w.shape), "cells": n, "sigma": w.sigma,
+           "corr_len_cells": w.corr_len, "accumulation": w.c}
     with torch.cuda.stream(s):
         kd = torch.from_numpy(k.ravel()).to(dev)
         tx, ty, tz, b = (torch.empty(n, dtype=torch.float32, device=dev) for _ in range(4))
@@ -671,86 +815,46 @@ def main(argv=None):
         g = mffv.create_grid(nx, ny, nz, stream=s)
         mffv.set_transmissibility(g, tx, ty, tz, accum_scalar=w.c, b_out=b)
         del kd
-        # launch shape of the stencil kernels: the library's autotuner (bitwise
-        # apply probe, timed phase A), outside the timed region
         tune = mffv.autotune(g, None)
-        log(f"autotune: CG kernels ci {tune['ci']}, remap {tune['remap']}, seg {tune['seg']}, {tune['blocks']} "
-            f"blocks, phase A {tune['phase_a_us']:.1f} us; apply ci {tune['apply_ci']}, remap "
-            f"{tune['apply_remap']}, seg {tune['apply_seg']}, {tune['apply_us']:.1f} us ({tune['candidates']} candidates)")
+        res["launch"] = {kk: tune[kk] for kk in LAUNCH_KEYS}
+        log_fn(f"c1 autotune: CG kernels ci {tune['ci']}, remap {tune['remap']}, seg {tune['seg']}, "
+               f"{tune['blocks']} blocks, phase A {tune['phase_a_us']:.1f} us; apply ci {tune['apply_ci']}, "
+               f"remap {tune['apply_remap']}, {tune['apply_us']:.1f} us")
+        b64 = b.double()
+        for tol in (1e-6, 1e-8):
+            o = mffv.default_opts(tol=tol, precision=mffv.FP32_IR, check_every=16, use_graph=1)
+            solve_f64(g, b64, o)                                      # warm
+            dt, info, x = solve_f64(g, b64, o)
+            res[f"solve_{tol:g}"] = {"s": dt, "iters": info["iters"], "ir_steps": info["ir_steps"],
+                                     "rel_res_true": info["rel_res_true"], "status": info["status"],
+                                     "cells_iter_per_s": cells_iter_rate(n, info["iters"], dt)}
+            log_fn(f"c1: solve to true {tol:g}: {dt:.2f} s, {info['iters']} iterations, "
+                   f"{info['ir_steps']} refinement steps, true rel-res {info['rel_res_true']:.2e}")
+            del x
+        # per-launch times of the fused CG kernels (HIP events, first 32 iterations)
         x = torch.zeros(n, dtype=torch.float32, device=dev)
-        opts = mffv.default_opts(tol=w.tol, precision=mffv.FP32_IR, check_every=16, use_graph=1)
-
-        def step():
-            x.zero_()
-            st, info = mffv.cg_solve(g, b, x, opts)
-            if st != mffv.OK:
-                raise RuntimeError(f"solve did not converge: {info}")
-            return info
-
-        log(f"warmup x{args.warmup}")
-        for _ in range(args.warmup):
-            info = step()
-        torch.cuda.synchronize()
-        log(f"timed x{args.steps}")
-        infos = []
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            infos.append(step())
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ms_per_step = (t1 - t0) * 1e3 / args.steps
-        iters = statistics.mean(i["iters"] for i in infos)
-        log(f"solve: {ms_per_step:.2f} ms, {iters:.0f} iterations, true rel-res "
-            f"{infos[-1]['rel_res_true']:.3e}, ir_steps {infos[-1]['ir_steps']}")
-
-        # the dominant kernel of the step (the single-reduction CG iteration, or
-        # phase A of the two-phase iteration), timed per launch with HIP events on
-        # the grid's stream during one more (untimed) solve with the same options
-        x.zero_()
-        st, tinfo = mffv.cg_solve(g, b, x, mffv.default_opts(
-            tol=w.tol, precision=mffv.FP32_IR, check_every=16, use_graph=1, timing=1))
-        merged = tinfo["single_reduction"] == 1
-        dom_us = tinfo["phase_a_us"]
-        dom_bytes = MERGED_BYTES_PER_CELL if merged else phase_a_bytes_mean(tinfo["timed_iters"])
-        dom_gbps = dom_bytes * n / (dom_us * 1e-6) / 1e9
-        log(f"{'single-reduction iteration' if merged else 'phase A'}: {dom_us:.1f} us/launch "
-            f"({dom_gbps:.0f} GB/s algorithmic), over {tinfo['timed_iters']} iterations")
-        traffic = TRAFFIC["single_reduction" if merged else "two_phase"]
-        # both forms of the iteration, per launch (the other one for comparison)
         forms = {}
         for sr in (0, 1):
-            if sr == int(merged):
-                tf = tinfo
-            else:
-                x.zero_()
-                st, tf = mffv.cg_solve(g, b, x, mffv.default_opts(
-                    tol=w.tol, precision=mffv.FP32_IR, check_every=16, use_graph=1, timing=1,
-                    single_reduction=sr))
-            forms[sr] = tf
-        phase_a_us, phase_b_us = forms[0]["phase_a_us"], forms[0]["phase_b_us"]
-        phase_a_gbps = phase_a_bytes_mean(forms[0]["timed_iters"]) * n / (phase_a_us * 1e-6) / 1e9
+            x.zero_()
+            _, forms[sr] = mffv.cg_solve(g, b, x, mffv.default_opts(
+                tol=w.tol, precision=mffv.FP32_IR, check_every=16, use_graph=1, timing=1, single_reduction=sr))
+        tinfo = forms[0]
+        phase_a_us, phase_b_us = tinfo["phase_a_us"], tinfo["phase_b_us"]
+        pa_bytes = phase_a_bytes_mean(tinfo["timed_iters"])
+        phase_a_gbps = pa_bytes * n / (phase_a_us * 1e-6) / 1e9
         phase_b_gbps = PHASE_B_BYTES_PER_CELL * n / (phase_b_us * 1e-6) / 1e9
         merged_us = forms[1]["phase_a_us"]
-        merged_gbps = MERGED_BYTES_PER_CELL * n / (merged_us * 1e-6) / 1e9
-        log(f"two-phase: phase A {phase_a_us:.1f} us ({phase_a_gbps:.0f} GB/s) + phase B {phase_b_us:.1f} us "
-            f"({phase_b_gbps:.0f} GB/s); single-reduction: {merged_us:.1f} us ({merged_gbps:.0f} GB/s)")
-
-        # Jacobi-PCG on the same system (context for the preconditioned comparison)
-        jac = None
+        res.update({"phase_a_us": phase_a_us, "phase_a_GBps": phase_a_gbps, "phase_b_us": phase_b_us,
+                    "phase_b_GBps": phase_b_gbps, "single_reduction_us": merged_us,
+                    "single_reduction_GBps": MERGED_BYTES_PER_CELL * n / (merged_us * 1e-6) / 1e9})
+        log_fn(f"c1: phase A {phase_a_us:.1f} us ({phase_a_gbps:.0f} GB/s) + phase B {phase_b_us:.1f} us "
+               f"({phase_b_gbps:.0f} GB/s); single-reduction {merged_us:.1f} us")
         if not args.no_jacobi:
-            jopts = mffv.default_opts(tol=w.tol, precision=mffv.FP32_IR,
-                                      precond=mffv.PRECOND_JACOBI, check_every=16, use_graph=1)
-            x.zero_()
-            mffv.cg_solve(g, b, x, jopts)
-            x.zero_()
-            torch.cuda.synchronize()
-            tj = time.perf_counter()
-            st, jinfo = mffv.cg_solve(g, b, x, jopts)
-            torch.cuda.synchronize()
-            jac = {"ms": (time.perf_counter() - tj) * 1e3, "iters": jinfo["iters"],
-                   "rel_res_true": jinfo["rel_res_true"]}
-            log(f"jacobi-pcg: {jac['ms']:.2f} ms, {jac['iters']} iterations")
-
+            o = mffv.default_opts(tol=w.tol, precision=mffv.FP32_IR, precond=mffv.PRECOND_JACOBI)
+            solve_f64(g, b64, o)
+            dt, info, xj = solve_f64(g, b64, o)
+            res["jacobi_pcg_1e-6"] = {"s": dt, "iters": info["iters"], "rel_res_true": info["rel_res_true"]}
+            del xj
         # stencil apply: HIP events on the grid's stream around back-to-back launches
         xa = torch.randn(n, dtype=torch.float32, device=dev)
         ya = torch.empty_like(xa)
@@ -762,11 +866,12 @@ def main(argv=None):
             mffv.apply(g, xa, ya)
         e1.record(s)
         e1.synchronize()
-        apply_ms = e0.elapsed_time(e1) / args.apply_reps
-        apply_gbps = APPLY_BYTES_PER_CELL * n / (apply_ms * 1e-3) / 1e9
-        log(f"apply: {apply_ms * 1e3:.1f} us/launch, {apply_gbps:.0f} GB/s algorithmic")
-
-        # achievable streaming ceiling: the library's own copy kernel, 1 GiB
+        apply_us = e0.elapsed_time(e1) * 1e3 / args.apply_reps
+        res["apply_us"] = apply_us
+        res["apply_GBps"] = APPLY_BYTES_PER_CELL * n / (apply_us * 1e-6) / 1e9
+        log_fn(f"c1: apply {apply_us:.1f} us/launch, {res['apply_GBps']:.0f} GB/s algorithmic")
+        del xa, ya
+        # streaming ceilings: the library's copy (1 GiB) and each kernel's mix of arrays
         nbytes = 1 << 30
         src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -778,11 +883,18 @@ def main(argv=None):
         e1.record(s)
         e1.synchronize()
         copy_ms = e0.elapsed_time(e1) / 20
-        copy_gbps = 2 * nbytes / (copy_ms * 1e-3) / 1e9
-        log(f"copy probe: {copy_gbps:.0f} GB/s (read + write)")
+        res["copy_probe_GBps"] = 2 * nbytes / (copy_ms * 1e-3) / 1e9
+        # the runtime's own device-to-device copy of the same buffers, for comparison
+        for _ in range(3):
+            dst.copy_(src)
+        e0.record(s)
+        for _ in range(20):
+            dst.copy_(src)
+        e1.record(s)
+        e1.synchronize()
+        res["runtime_copy_GBps"] = 2 * nbytes / (e0.elapsed_time(e1) / 20 * 1e-3) / 1e9
+        log_fn(f"c1: copy probe {res['copy_probe_GBps']:.0f} GB/s, runtime copy {res['runtime_copy_GBps']:.0f} GB/s")
         del src, dst
-        # each kernel's mix of arrays read and written, streamed without its
-        # arithmetic or neighbours: the achievable ceiling of that mix
         arrs = [torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0) for _ in range(10)]
         stream_ceil = {}
         for name, (ni, no) in STREAM_MIXES.items():
@@ -797,23 +909,89 @@ def main(argv=None):
             us = e0.elapsed_time(e1) * 1e3 / 20
             stream_ceil[name] = {"in": ni, "out": no, "us": us, "GBps": 4 * (ni + no) * n / (us * 1e-6) / 1e9}
         del arrs
-        # phase A alternates between the odd and even mixes
         pa_ceiling_us = 0.5 * (stream_ceil["phase_a_odd"]["us"] + stream_ceil["phase_a_even"]["us"])
         stream_ceil["phase_a_vs_its_mix"] = pa_ceiling_us / phase_a_us
-        stream_ceil["apply_vs_its_mix"] = stream_ceil["apply"]["us"] / (apply_ms * 1e3)
-        log("stream mixes: " + ", ".join(f"{k} {v['us']:.1f} us ({v['GBps']:.0f} GB/s)"
-                                          for k, v in stream_ceil.items() if isinstance(v, dict))
-            + f"; phase A runs at {stream_ceil['phase_a_vs_its_mix']:.2f} of its mix's rate, the apply at "
-              f"{stream_ceil['apply_vs_its_mix']:.2f}")
+        stream_ceil["apply_vs_its_mix"] = stream_ceil["apply"]["us"] / apply_us
+        res["stream_ceilings"] = stream_ceil
+        traffic = TRAFFIC["two_phase"]
+        res["stencil_roofline"] = {
+            "kernel": "stencil_v4<1> (fused CG phase A: direction update, apply, deferred solution "
+                      "update, p.Ap partials)",
+            "bound": "hbm", "achieved": phase_a_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": phase_a_gbps / HBM_PEAK_GBPS, "traffic": traffic_for(traffic, tune),
+            "traffic_source": traffic["profile"], "bytes_per_cell": pa_bytes, "cells_per_launch": n,
+            "launch_us": phase_a_us}
+        g.close()
     torch.cuda.synchronize()
+    return res, k, tx, ty, tz
 
-    tsteps = None
-    if not args.no_timesteps:
-        tsteps = bench_time_steps(log, w.shape, tx, ty, tz)
-    face_res = None
-    if not args.no_faces:
-        face_res = bench_faces(log, w.shape, tx, ty, tz, w.c, rcm=args.faces_rcm)
-    del tx, ty, tz
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50,
+                    help="timed steps: learned-FCG solves of the first K held-out realisations")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--held-out", type=int, default=50,
+                    help="held-out 128^3 realisations compared (the configuration's 50)")
+    ap.add_argument("--held-in", type=int, default=200)
+    ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-jacobi", action="store_true")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 256^3 section (and the sections on its field)")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-timesteps", action="store_true")
+    ap.add_argument("--no-faces", action="store_true")
+    ap.add_argument("--faces-rcm", action="store_true",
+                    help="also renumber the randomly numbered face-list mesh with mffv_face_order (about 30 s on the host)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 512x512x1024 apply / CG-rate measurement")
+    ap.add_argument("--large-learned", action="store_true",
+                    help="fine-tune the learned preconditioner on crops of the 512x512x1024 workload and "
+                         "compare the methods there")
+    ap.add_argument("--large-solve", action="store_true",
+                    help="also solve the 512x512x1024 system to 1e-8 (minutes)")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "x-slab design is described but not built.", flush=True)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_2408_03452_amd import mffv
+
+    log(f"{mffv.version()}; headline: learned flexible CG on channelised 128^3, {args.held_out} held-out "
+        f"realisations, {args.steps} timed steps")
+    head = bench_channelised(log, args.held_in, args.held_out, args.steps, args.warmup)
+    step_times = head.pop("_step_times")
+    c3_params = head.pop("_params")
+    head.pop("_x_first", None)
+    lf = head["learned_fcg"]
+    log("channelised: median time to true 1e-6 (iterations): " + ", ".join(
+        f"{m} {head[m]['time_to_1e-6_s_median'] * 1e3:.1f} ms ({head[m]['iters_median']:.0f})"
+        for m in ("learned_fcg", "plain", "jacobi")))
+    # the step's dominant kernel: a hidden 16 -> 16 convolution of the network
+    n3 = head["cells"]
+    tm = head.get("timing", {})
+    layers = tm.get("nn_layer_us", [0.0] * 4)
+    hidden_us = 0.5 * (layers[1] + layers[2])
+    hidden_tflops = NN_LAYER_FLOP_PER_CELL[1] * n3 / (hidden_us * 1e-6) / 1e12 if hidden_us > 0 else 0.0
+    head["network_layers"] = [
+        {"layer": i + 1, "us": layers[i], "flop_per_cell": NN_LAYER_FLOP_PER_CELL[i],
+         "TFLOPs": NN_LAYER_FLOP_PER_CELL[i] * n3 / (layers[i] * 1e-6) / 1e12 if layers[i] > 0 else 0.0}
+        for i in range(4)]
+    log(f"network layers (us): {[round(v, 1) for v in layers]}; hidden layer {hidden_tflops:.0f} TFLOP/s")
+
+    c1 = tsteps = face_res = None
+    k1 = None
+    if not args.no_c1:
+        c1, k1, tx, ty, tz = bench_c1(log, args)
+        if not args.no_timesteps:
+            tsteps = bench_time_steps(log, tuple(c1["grid"]), tx, ty, tz)
+        if not args.no_faces:
+            face_res = bench_faces(log, tuple(c1["grid"]), tx, ty, tz, c1["accumulation"], rcm=args.faces_rcm)
+        del tx, ty, tz
     large = None
     if not args.no_large:
         large = bench_large(log, args.large_solve)
@@ -823,87 +1001,69 @@ def main(argv=None):
         batched = bench_batched(log)
         log(f"batched: {batched['cells_iter_per_s'] / 1e9:.1f} Gcell*iter/s, iters "
             f"{batched['iters_min_max']}, worst true rel-res {batched['rel_res_true_max']:.2e}")
-    learned_res = None
     large_learned = None
-    if not args.no_learned:
-        learned_res = bench_learned(log, args.learned_held_in, args.learned_held_out)
-        c3_params = learned_res.pop("_params")
-        log("learned: median time to 1e-6 (iterations): " + ", ".join(
-            f"{k} {learned_res[k]['time_to_1e-6_s_median']*1e3:.1f} ms ({learned_res[k]['iters_median']:.0f})"
-            for k in ("plain", "jacobi", "learned_fcg")))
-        if args.large_learned:
-            large_learned = bench_large_learned(log, c3_params)
-    elif args.large_learned:
-        log("large-learned: skipped (it fine-tunes the network of the learned section, which --no-learned removes)")
+    if args.large_learned:
+        large_learned = bench_large_learned(log, c3_params)
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle, 64^3 crop)")
-        cpu = cpu_baseline(k, w.c, w.tol)
-        log(f"cpu: {cpu['value'] / 1e6:.1f} Mcell*iter/s, {cpu['iters']} iterations")
+        if k1 is None:
+            from synth import WORKLOADS, workload_field
+            k1 = workload_field(WORKLOADS["lognormal_corr8_256cube"])
+        crops = bench_crop_fields(log, k1, c3_params)
+        log("cpu baseline (oracle on the host)")
+        cpu = cpu_baseline(c3_params, lf["iters_median"], crops, log)
 
-    gpu_rate = cells_iter_rate(n, iters, ms_per_step * 1e-3)
+    ms_per_step = 1e3 * float(np.mean(step_times))
     line = {
         "metric": METRIC,
-        "value": ms_per_step * 1e-3,
+        "value": lf["time_to_1e-6_s_median"],
         "unit": "s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": len(step_times),
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded Gaussian-filtered log-normal permeability)",
-        "config": {"workload": w.name, "grid": list(w.shape), "cells": n,
-                   "sigma": w.sigma, "corr_len_cells": w.corr_len, "accumulation": w.c,
-                   "tol": w.tol, "precision": "FP32 CG + FP64 true residual/refinement",
-                   "precond": "none", "initial_guess": "zero",
-                   "launch": {k: tune[k] for k in LAUNCH_KEYS}},
-        "iters": iters,
-        "rel_res_true": infos[-1]["rel_res_true"],
-        "ir_steps": infos[-1]["ir_steps"],
-        "cells_iter_per_s": gpu_rate,
-        "cg_effective_GBps": (MERGED_BYTES_PER_CELL if merged else CG_BYTES_PER_CELL_ITER) * gpu_rate / 1e9,
-        "single_reduction": merged,
-        "apply_us": apply_ms * 1e3,
-        "apply_GBps": apply_gbps,
-        "copy_probe_GBps": copy_gbps,
-        "jacobi_pcg": jac,
+        "data": "synthetic (seeded two-facies channelised permeability; trained network, no external data)",
+        "config": {"workload": "channelised_128cube", "grid": [128, 128, 128], "cells": n3,
+                   "held_out": args.held_out, "held_out_seeds": [3500, 3500 + args.held_out - 1],
+                   "held_in_32cube": args.held_in, "accumulation": 1e-3, "tol_true": 1e-6,
+                   "method": "flexible CG, 3D-conv network preconditioner (2-16-16-16-1, 3^3, BF16 MFMA)",
+                   "precision": "FP32 iterations, FP64 true residual and refinement, FP64 field",
+                   "initial_guess": "zero",
+                   "value_is": "median over the held-out realisations of the learned-FCG time to true rel-res 1e-6"},
+        "learned_fcg": lf,
+        "plain_cg": head["plain"],
+        "jacobi_pcg": head["jacobi"],
+        "learned_vs_plain_speedup": head["learned_vs_plain_speedup"],
+        "learned_vs_jacobi_speedup": head["learned_vs_jacobi_speedup"],
+        "channelised": {k: v for k, v in head.items() if k not in ("learned_fcg", "plain", "jacobi")},
+        "roofline": {
+            "kernel": "conv3d<16,0> (hidden 16->16 3^3 convolution + ReLU of the network inside flexible "
+                      "CG, BF16 MFMA with FP32 accumulation)",
+            "bound": "mfma",
+            "achieved": hidden_tflops,
+            "peak": MFMA_BF16_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": hidden_tflops / MFMA_BF16_PEAK_TFLOPS,
+            "traffic": NN_TRAFFIC["hidden"]["bytes"] if NN_TRAFFIC["hidden"] else None,
+            "traffic_source": NN_TRAFFIC["hidden"]["profile"] if NN_TRAFFIC["hidden"] else None,
+            "flop_per_cell": NN_LAYER_FLOP_PER_CELL[1],
+            "cells_per_launch": n3,
+            "launch_us": hidden_us,
+        },
+        "c1_256cube": c1,
         "large": large,
-        "stream_ceilings": stream_ceil,
         "time_steps": tsteps,
         "faces": face_res,
         "batched": batched,
-        "learned": learned_res,
         "large_learned": large_learned,
-        "phase_a_us": phase_a_us,
-        "phase_a_GBps": phase_a_gbps,
-        "phase_b_us": phase_b_us,
-        "phase_b_GBps": phase_b_gbps,
-        "single_reduction_us": merged_us,
-        "single_reduction_GBps": merged_gbps,
-        "roofline": {
-            "kernel": ("stencil_v4<3> (single-reduction CG iteration: residual and direction "
-                       "updates, apply, deferred solution update, four dot partials)" if merged else
-                       "stencil_v4<1> (fused CG phase A: direction update, apply, deferred "
-                       "solution update, p.Ap partials)"),
-            "bound": "hbm",
-            "achieved": dom_gbps,
-            "peak": HBM_PEAK_GBPS,
-            "unit": "GB/s",
-            "frac": dom_gbps / HBM_PEAK_GBPS,
-            "traffic": traffic_for(traffic, tune),
-            "traffic_source": traffic["profile"] if traffic else None,
-            "bytes_per_cell": dom_bytes,
-            "cells_per_launch": n,
-            "launch_us": dom_us,
-        },
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
-    g.close()
     return 0
 
 

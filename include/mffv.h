@@ -132,6 +132,12 @@ typedef struct {
     int timed_iters;
     int single_reduction;      /* 1 if the FP32 iterations ran the single-reduction loop
                                   (then phase_a_us is that one kernel, phase_b_us ~ 0) */
+    /* opts.timing with the learned preconditioner: mean duration per launch, in
+       microseconds, of each of the network's four convolution layers (HIP events
+       on the grid's stream around each layer's launch) over the timed iterations
+       that applied the network, and their count. */
+    double nn_layer_us[4];
+    int nn_timed;
 } mffv_info;
 
 /* Library version string, e.g. "mffv 1.0 gfx950". Never NULL. */

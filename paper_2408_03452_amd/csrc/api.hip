@@ -131,6 +131,8 @@ struct mffv_grid {
     float a_const = 0.f;
     // per-kernel timing of the first kTimedIters FP32 iterations (opts.timing)
     hipEvent_t tev[kTimedIters][4] = {};
+    hipEvent_t tnev[kTimedIters][5] = {};   // the network's layers (learned preconditioner)
+    bool tnev_used[kTimedIters] = {};
     bool tev_made = false;
     bool timing = false;
     int timed = 0;
@@ -280,7 +282,12 @@ int enqueue_iter32(mffv_grid* G, int precond, const mffv_net* net, int nn_every 
     // the others (the position in the loop is counted per enqueued iteration)
     const bool use_nn = (++G->flex_count % nn_every) == 0;
     hipEvent_t* ev = nullptr;
-    if (G->timing && G->timed < kTimedIters) ev = G->tev[G->timed++];
+    hipEvent_t* nev = nullptr;
+    if (G->timing && G->timed < kTimedIters) {
+        G->tnev_used[G->timed] = precond == MFFV_PRECOND_LEARNED && use_nn;
+        if (G->tnev_used[G->timed]) nev = G->tnev[G->timed];
+        ev = G->tev[G->timed++];
+    }
     if (ev) HIP_TRY(hipEventRecord(ev[0], G->stream));
     float* pa = reinterpret_cast<float*>(G->partA);
     float* pb = reinterpret_cast<float*>(G->partB);
@@ -320,7 +327,7 @@ int enqueue_iter32(mffv_grid* G, int precond, const mffv_net* net, int nn_every 
     if (precond == MFFV_PRECOND_LEARNED) {
         if (use_nn) {
             int rc = nn_precondition(net, G->g, G->r, G->dinv, G->dmask, G->z, pb + G->nb_vec, G->nb_vec,
-                                     G->feat, (float)G->n_unknown, G->stream);
+                                     G->feat, (float)G->n_unknown, G->stream, nev);
             if (rc) return rc;
         } else {
             HIP_TRY(launch_jacobi_z(G->g.n, G->r, G->dinv, G->dmask, G->z, G->stream));
@@ -338,8 +345,11 @@ int timing_begin(mffv_grid* G, bool on) {
     G->timing = on;
     G->timed = 0;
     G->timed_real = -1;
+    for (bool& u : G->tnev_used) u = false;
     if (!on || G->tev_made) return MFFV_OK;
     for (auto& row : G->tev)
+        for (auto& e : row) HIP_TRY(hipEventCreate(&e));
+    for (auto& row : G->tnev)
         for (auto& e : row) HIP_TRY(hipEventCreate(&e));
     G->tev_made = true;
     return MFFV_OK;
@@ -365,6 +375,19 @@ int timing_end(mffv_grid* G, mffv_info* inf) {
         inf->precond_us = 1e3 * sum[2] / nt;
     }
     inf->timed_iters = nt;
+    double lsum[4] = {0, 0, 0, 0};
+    int nn_t = 0;
+    for (int t = 0; t < nt; ++t) {
+        if (!G->tnev_used[t]) continue;
+        for (int k = 0; k < 4; ++k) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, G->tnev[t][k], G->tnev[t][k + 1]));
+            lsum[k] += ms;
+        }
+        ++nn_t;
+    }
+    for (int k = 0; k < 4; ++k) inf->nn_layer_us[k] = nn_t > 0 ? 1e3 * lsum[k] / nn_t : 0.0;
+    inf->nn_timed = nn_t;
     G->timing = false;
     return MFFV_OK;
 }
@@ -1305,6 +1328,9 @@ void mffv_destroy_grid(mffv_grid* G) {
     for (auto& row : G->tev)
         for (auto& e : row)
             if (e) (void)hipEventDestroy(e);
+    for (auto& row : G->tnev)
+        for (auto& e : row)
+            if (e) (void)hipEventDestroy(e);
     delete G;
 }
 
@@ -1543,7 +1569,8 @@ int mffv_cg_solve(mffv_grid* G, const float* b, float* x, const mffv_opts* opts,
         if ((rc = ensure_x64(G))) return rc;
         HIP_TRY(launch_convert_f32_to_f64(n, x, G->x64, G->stream));
         status = solve_ir(G, b, 0, o, &inf);
-        if (status < 0) return status;
+        // a breakdown still reports its info (x: the last iterate); other errors return at once
+        if (status < 0 && status != MFFV_EBREAKDOWN) return status;
         HIP_TRY(launch_convert_f64_to_f32(n, G->x64, x, G->stream));
     } else {
         if ((rc = ensure_ws64(G))) return rc;
@@ -1590,7 +1617,8 @@ int mffv_cg_solve_f64(mffv_grid* G, const double* b, double* x, const mffv_opts*
         if ((rc = ensure_x64(G))) return rc;
         HIP_TRY(hipMemcpyAsync(G->x64, x, n * sizeof(double), hipMemcpyDeviceToDevice, G->stream));
         status = solve_ir(G, b, 1, o, &inf);
-        if (status < 0) return status;
+        // a breakdown still reports its info (x: the last iterate); other errors return at once
+        if (status < 0 && status != MFFV_EBREAKDOWN) return status;
         HIP_TRY(hipMemcpyAsync(x, G->x64, n * sizeof(double), hipMemcpyDeviceToDevice, G->stream));
     } else {
         if ((rc = ensure_ws64(G))) return rc;

@@ -867,7 +867,8 @@ int conv(const Shape& S, const ConvArgs& a0, hipStream_t st) {
 // Forward through the four layers from N->x0 (already filled); the last layer
 // either stores y (training) or forms the preconditioned z.
 int forward(mffv_net* N, const Shape& S, bool keep_h3, int last_mode, const ConvArgs& last,
-            hipStream_t st) {
+            hipStream_t st, hipEvent_t* ev = nullptr) {
+    if (ev) NHIP(hipEventRecord(ev[0], st));
     ConvArgs a{};
     a.relu = N->relu;
     a.in = N->x0;
@@ -876,24 +877,29 @@ int forward(mffv_net* N, const Shape& S, bool keep_h3, int last_mode, const Conv
     a.out16 = N->h1;
     int rc;
     if ((rc = conv<2, kHiddenRelu>(S, a, st))) return rc;
+    if (ev) NHIP(hipEventRecord(ev[1], st));
     a.in = N->h1;
     a.W = N->W + kWf2;
     a.bias = N->params + offB(1);
     a.out16 = N->h2;
     if ((rc = conv<16, kHiddenRelu>(S, a, st))) return rc;
+    if (ev) NHIP(hipEventRecord(ev[2], st));
     uint16_t* h3 = keep_h3 ? N->h3 : N->h1;  // inference reuses h1's buffer
     a.in = N->h2;
     a.W = N->W + kWf3;
     a.bias = N->params + offB(2);
     a.out16 = h3;
     if ((rc = conv<16, kHiddenRelu>(S, a, st))) return rc;
+    if (ev) NHIP(hipEventRecord(ev[3], st));
     ConvArgs f = last;
     f.relu = N->relu;
     f.in = h3;
     f.W = N->W + kWf4;
     f.bias = N->params + offB(3);
-    if (last_mode == kFinal) return conv<16, kFinal>(S, f, st);
-    return conv<16, kPrecond>(S, f, st);
+    rc = last_mode == kFinal ? conv<16, kFinal>(S, f, st) : conv<16, kPrecond>(S, f, st);
+    if (rc) return rc;
+    if (ev) NHIP(hipEventRecord(ev[4], st));
+    return MFFV_OK;
 }
 
 int backward(mffv_net* N, const Shape& S, hipStream_t st) {
@@ -1014,7 +1020,7 @@ namespace mffv {
 
 int nn_precondition(const mffv_net* Nc, const Geom& g, const float* r, const float* dinv,
                     const uint8_t* dmask, float* z, const float* pb, int nb_b, const float* feat,
-                    float n_u, hipStream_t s) {
+                    float n_u, hipStream_t s, hipEvent_t* layer_ev) {
     mffv_net* N = const_cast<mffv_net*>(Nc);
     if (g.n > N->cap) return nfail(MFFV_ESTATE, "network workspace not prepared for this grid");
     const Shape S = shape_of(g.nx, g.ny, g.nz);
@@ -1027,7 +1033,7 @@ int nn_precondition(const mffv_net* Nc, const Geom& g, const float* r, const flo
     last.dinv = dinv;
     last.dmask = dmask;
     last.sscale = N->sscale;
-    return forward(N, S, false, kPrecond, last, s);
+    return forward(N, S, false, kPrecond, last, s, layer_ev);
 }
 
 int nn_feature(const Geom& g, const float* dinv, const uint8_t* dmask, float n_u, float* part,

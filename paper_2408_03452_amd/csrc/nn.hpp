@@ -9,9 +9,11 @@ namespace mffv {
 // z = dinv r + s N([r / s, feat]) on unknown cells (0 on Dirichlet cells) for
 // flexible CG, with s = ||r|| / sqrt(n_u) and ||r||^2 the sum of the nb_b
 // phase-B partials pb. Enqueued on s; allocates nothing if nn_prepare ran.
+// layer_ev (optional): 5 events, recorded before the first convolution and
+// after each of the four.
 int nn_precondition(const mffv_net* net, const Geom& g, const float* r, const float* dinv,
                     const uint8_t* dmask, float* z, const float* pb, int nb_b, const float* feat,
-                    float n_u, hipStream_t s);
+                    float n_u, hipStream_t s, hipEvent_t* layer_ev = nullptr);
 
 // Make sure the network's inference workspace holds n cells; returns the
 // workspace generation (changes whenever the workspace is reallocated), or a

@@ -70,9 +70,18 @@ def harvest(grid: mffv.Grid, b: torch.Tensor, iters=DEFAULT_ITERS, x_star=None) 
     return out
 
 
+def white_residuals(shape, count: int, seed: int):
+    """``count`` independent standard-normal FP32 fields of the grid's shape
+    (NumPy PCG64 from ``seed``), each rescaled to unit RMS."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = rng.standard_normal((count,) + tuple(shape)).astype(np.float32)
+    out /= np.sqrt(np.mean(out.reshape(count, -1) ** 2, axis=1)).reshape((count,) + (1,) * len(shape))
+    return out
+
+
 def white_samples(systems, count: int, seed: int) -> list:
     """``count`` white-noise residual samples spread over the systems' operators."""
-    from synth import white_residuals
     out = []
     per = -(-count // len(systems))
     for i, (grid, _b) in enumerate(systems):

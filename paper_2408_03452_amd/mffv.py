@@ -61,10 +61,12 @@ class Info(ctypes.Structure):
                 ("rel_res_true", ctypes.c_double), ("ms", ctypes.c_double),
                 ("phase_a_us", ctypes.c_double), ("phase_b_us", ctypes.c_double),
                 ("precond_us", ctypes.c_double), ("timed_iters", ctypes.c_int),
-                ("single_reduction", ctypes.c_int)]
+                ("single_reduction", ctypes.c_int), ("nn_layer_us", ctypes.c_double * 4),
+                ("nn_timed", ctypes.c_int)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: (list(v) if k == "nn_layer_us" else v)
+                for k, v in ((k, getattr(self, k)) for k, _ in self._fields_)}
 
 
 _lib = None

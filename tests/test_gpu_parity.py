@@ -390,3 +390,59 @@ def test_full_size_refined_solve_256cube(mf):
     assert abs(rel - info["rel_res_true"]) <= 1e-3 * rel
     # the discrete maximum principle holds for the refined field
     assert xh.min() >= -1e-6 and xh.max() <= 1 + 1e-6
+
+
+def test_crop_of_the_256cube_field_matches_the_oracle_elementwise(mf):
+    """The [0:64]^3 crop of the correlated 256^3 field (sigma 2, correlation
+    length 8, c = 1e-3) as its own problem: FP32 CG refined in FP64 to a true
+    relative residual of 1e-8, against the oracle's FP64 Jacobi-PCG to 1e-12.
+    The field lies in [0, 1] (maximum principle), so every cell must agree to
+    1e-5 absolute, and the L2 field error must be below 1e-5 relative."""
+    w = WORKLOADS["lognormal_corr8_256cube"]
+    k = np.ascontiguousarray(workload_field(w)[:64, :64, :64])
+    g, _, b = gpu_problem(mf, k, c=w.c)
+    x = torch.zeros(k.size, dtype=torch.float64, device="cuda")
+    st, info = mf.cg_solve_f64(g, b.double(), x, mf.default_opts(tol=1e-8, precision=mf.FP32_IR))
+    assert st == mf.OK and info["rel_res_true"] <= 1e-8
+    ref = OracleProblem(k, c=w.c)
+    orc = krylov.pcg(ref.Auu, ref.bu, krylov.jacobi(ref.Auu), tol=1e-12, max_iter=20000)
+    assert orc.converged
+    p = tpfa.scatter_solution(orc.x, ref.u, ref.pd, ref.dmask)
+    xh = x.cpu().numpy()
+    err = np.abs(xh - p)
+    assert err.max() <= 1e-5, (float(err.max()), np.unravel_index(int(err.argmax()), k.shape))
+    assert np.linalg.norm(xh - p) <= 1e-5 * np.linalg.norm(p)
+    assert ref.rel_residual(xh) <= 1.01e-8
+    g.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_ir", "batched", "async"])
+def test_non_finite_rhs_reports_breakdown(mf, precision):
+    """A NaN in the right-hand side makes every dot product non-finite: the
+    solve stops with MFFV_EBREAKDOWN (no hang, no fault) and fills info."""
+    shape = (10, 9, 12)
+    k = lognormal_iid(shape, 1.0, 31)
+    g, _, b = gpu_problem(mf, k, c=1e-3)
+    b[5 * 9 * 12 + 40] = float("nan")
+    x = torch.zeros(k.size, dtype=torch.float32, device="cuda")
+    if precision in ("fp32", "fp32_ir"):
+        o = mf.default_opts(precision=mf.FP32 if precision == "fp32" else mf.FP32_IR)
+        with pytest.raises(mf.MffvError) as e:
+            mf.cg_solve(g, b, x, o)
+        assert e.value.code == mf.EBREAKDOWN
+        # the raw call returns the code with info filled
+        import ctypes
+        info = mf.Info()
+        rc = mf.lib().mffv_cg_solve(g.handle, b.data_ptr(), x.data_ptr(), ctypes.byref(o), ctypes.addressof(info))
+        assert rc == mf.EBREAKDOWN and info.status == mf.EBREAKDOWN
+    elif precision == "batched":
+        with pytest.raises(mf.MffvError) as e:
+            mf.cg_solve_batched([g], [b], [x], mf.default_opts(precision=mf.FP32_IR))
+        assert e.value.code == mf.EBREAKDOWN
+    else:
+        o = mf.default_opts(precision=mf.FP32_IR)
+        o.async_ = 1
+        st, dinfo = mf.cg_solve(g, b, x, o)
+        infos = mf.infos_from_device(dinfo)
+        assert st == mf.OK and infos[0]["status"] == mf.EBREAKDOWN
+    g.close()
