@@ -2,14 +2,20 @@
 // 2 -> 16 -> 16 -> 16 -> 1, ReLU after the first three) applied inside
 // flexible CG, and its training kernels.
 //
-// Convolutions are implicit GEMMs on the matrix cores: for each of the 27 taps
-// a 16-cell x 16-channel slab of the input (from an LDS tile with a one-cell
-// halo) is multiplied by the tap's 16 x 16 weight block with
-// v_mfma_f32_16x16x16_bf16 (BF16 operands, FP32 accumulation). A block owns a
+// Convolutions are implicit GEMMs on the matrix cores with
+// v_mfma_f32_16x16x32_bf16 (BF16 operands, FP32 accumulation). A block owns a
 // 1 x 4 x 64 tile of output cells; each of its four waves computes one 64-cell
-// row as four 16-cell MFMA tiles. Activations are stored channels-last in
-// BF16 (32 bytes per cell for 16 channels). The first layer's two input
-// channels are packed as (tap, channel) pairs into K = 64 (54 used).
+// row as four 16-cell tiles. Activations are stored channels-last in BF16
+// (32 bytes per cell for 16 channels).
+//
+// 16-channel inputs: the z taps are applied on the output side. For a pair of
+// (dx, dy) tap groups, one 16-cell x 32-channel slab of the input (16 channels
+// of each group, unshifted, from an LDS tile with a one-cell halo) is the B
+// operand of three products, one per z offset dz, Q_dz = W_dz x; the output is
+// y[z] = Q_-1[z-1] + Q_0[z] + Q_+1[z+1], the z neighbours taken across lanes.
+// Each input slab is read from LDS once per pair instead of once per tap. A
+// fifth tile holds the two cells just beyond the row ends. The first layer's
+// two input channels are packed as (tap, channel) pairs into K = 64 (54 used).
 //
 // Backward: the input gradient is the forward convolution of the output
 // gradient with the taps mirrored and the channel roles swapped, followed by
@@ -30,7 +36,17 @@ namespace mffv {
 namespace {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+
+// D += A B on a 16 x 16 x 32 BF16 tile. Lane l holds A row l % 16 and B
+// column l % 16, each with the 8 K values of slot l / 16; it receives D rows
+// 4 (l / 16) .. 4 (l / 16) + 3 of column l % 16.
+__device__ __forceinline__ v4f mfma32(const v8s& a, const v8s& b, const v4f& c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c,
+                                                   0, 0, 0);
+}
 
 constexpr int TZ = 64, TY = 4;                  // output tile: 1 x TY x TZ cells
 constexpr int HX = 3, HY = TY + 2, HZ = TZ + 2;  // input tile with a one-cell halo
@@ -48,15 +64,22 @@ constexpr int offB(int l) { return offW(l) + 27 * kCin[l] * kCout[l]; }
 constexpr int kNParams = offW(4);
 static_assert(kNParams == 15169, "parameter count");
 
-// BF16 operand layouts (v4s per lane): forward and input-gradient weights
-constexpr int kWf1 = 0;                 // layer 1, 4 K-steps x 64 lanes
-constexpr int kWf2 = kWf1 + 4 * 64;     // layers 2..4, 27 taps x 64 lanes
-constexpr int kWf3 = kWf2 + 27 * 64;
-constexpr int kWf4 = kWf3 + 27 * 64;    // layer 4: 9 (dx, dy) groups x 64 lanes, rows = dz
-constexpr int kWb4 = kWf4 + 9 * 64;     // input gradient of layer 4 (2-channel path)
-constexpr int kWb3 = kWb4 + 4 * 64;
-constexpr int kWb2 = kWb3 + 27 * 64;
-constexpr int kWTotal = kWb2 + 27 * 64;  // in v4s units
+// BF16 A-operand layouts of the weights (v8s per lane, 64 lanes per operand):
+// forward and input-gradient (mirrored taps, channel roles swapped).
+//  2-channel input (layer 1, input gradient of layer 4): 2 operands, K = 64
+//    (tap, channel) pairs, k = 2 tap + channel.
+//  16-channel input, 16 outputs: 5 pairs of (dx, dy) groups x 3 dz operands
+//    (pair P: groups 2P and 2P+1 in K halves; group 9 is all zero).
+//  16-channel input, 1 output (layer 4): 5 pair operands with rows = dz + 1.
+constexpr int kPairs = 5;
+constexpr int kWf1 = 0;
+constexpr int kWf2 = kWf1 + 2 * 64;
+constexpr int kWf3 = kWf2 + 3 * kPairs * 64;
+constexpr int kWf4 = kWf3 + 3 * kPairs * 64;
+constexpr int kWb4 = kWf4 + kPairs * 64;
+constexpr int kWb3 = kWb4 + 2 * 64;
+constexpr int kWb2 = kWb3 + 3 * kPairs * 64;
+constexpr int kWTotal = kWb2 + 3 * kPairs * 64;  // in v8s units
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
     uint32_t u = __float_as_uint(f);
@@ -117,9 +140,10 @@ __device__ __forceinline__ void load_halo(const uint16_t* __restrict__ in, const
 constexpr int kRing = 4;
 constexpr int PCELLS = HY * HZ;  // cells of one haloed plane
 
-// In LDS the four 8-byte channel quads of a 16-channel cell are stored in the
-// order q ^ ((cell >> 2) & 3): the 16 lanes that read quad q of 16 consecutive
-// cells then touch 16 distinct 8-byte bank slots instead of four.
+// In LDS the two 16-byte channel halves of a 16-channel cell are stored in the
+// order h ^ ((cell >> 3) & 1): the 16 lanes that read half h of 16 consecutive
+// cells then cover all 64 banks once instead of half of them twice.
+__device__ __forceinline__ int half_pos(int cell, int h) { return cell * 16 + ((h ^ (cell >> 3)) & 1) * 8; }
 //
 // One haloed input plane held in registers between its fetch and its LDS store.
 template <int C>
@@ -166,10 +190,8 @@ __device__ __forceinline__ void store_plane(const PlaneRegs<C>& R, uint16_t* slo
         if constexpr (C == 16) {
             // 8-byte channel quad q of cell `cell` sits at quad position q ^ swz(cell)
             if (c < PCELLS * 2) {
-                const int cell = c >> 1, half = c & 1, sw = (cell >> 2) & 3;
-                uint4 v = R.v[u];
-                if (sw & 1) v = make_uint4(v.z, v.w, v.x, v.y);
-                *reinterpret_cast<uint4*>(slot + cell * 16 + (half ^ (sw >> 1)) * 8) = v;
+                const int cell = c >> 1, half = c & 1;
+                *reinterpret_cast<uint4*>(slot + half_pos(cell, half)) = R.v[u];
             }
         } else {
             if (c < PCELLS) *reinterpret_cast<uint32_t*>(slot + c * 2) = R.v[u];
@@ -177,83 +199,126 @@ __device__ __forceinline__ void store_plane(const PlaneRegs<C>& R, uint16_t* slo
     }
 }
 
-// Accumulate one wave's 64-cell output row (4 MFMA tiles of 16 cells) from the
-// three haloed planes at p[0..2] (x offsets -1, 0, +1). The weights are the A
-// operand (rows: output channels) and the activations the B operand (columns:
-// cells), so lane (m, g) ends with output channels 4g..4g+3 of cell m.
-// C = 16: K = 27 taps x 16 channels; C = 2: K = 64 (tap, channel) pairs.
-template <int C>
-__device__ __forceinline__ void conv_row(const uint16_t* const p[3], const v4s* wr, v4f acc[4]) {
+__device__ __forceinline__ float dpp_ror1(float v) {   // lane i of each 16-lane row gets lane i - 1 (mod 16)
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x121, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float dpp_rol1(float v) {   // lane i of each 16-lane row gets lane i + 1 (mod 16)
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x12f, 0xf, 0xf, false));
+}
+
+// Where lane (q, n) reads the B operand of (dx, dy) group pair P: group
+// 2P + (q >> 1) (the second group of pair 4 is empty: it reads the first
+// group's cells, which meet zero weights), channel half q & 1. dx picks the
+// plane; off is the offset in the plane (uint16 units) of tile 0 (cell n of
+// the row), halo the offset for the halo tile (column 15: the cell before the
+// row, the other columns: the cell after it). Tile t adds 256 t: 16 cells
+// further along z, the same swizzle (16 t does not change cell >> 3).
+struct SlabAt {
+    int dx, off, halo;
+};
+__device__ __forceinline__ SlabAt slab_at(int P) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int m = lane & 15, kg = lane >> 4;
-    if (C == 16) {
+    const int n = lane & 15, q = lane >> 4;
+    const int g = min(2 * P + (q >> 1), 8);
+    const int row = (w + g % 3) * HZ;
+    const int hz = n == 15 ? 0 : HZ - 1;
+    return SlabAt{g / 3, half_pos(row + n + 1, q & 1), half_pos(row + hz, q & 1)};
+}
+
+__device__ __forceinline__ const v8s& slab(const uint16_t* const p[3], const SlabAt& a, int t) {
+    return *reinterpret_cast<const v8s*>(p[a.dx] + (t < 4 ? a.off + 256 * t : a.halo));
+}
+
+// One wave's 64-cell output row of a 16 -> 16 convolution (z taps on the
+// output side): lane (q, n) ends with output channels 4q..4q+3 of cell n of
+// each of the four tiles. wr: 15 operands, index 3 P + dz + 1.
+__device__ __forceinline__ void conv_row16(const uint16_t* const p[3], const v8s* wr, v4f y[4]) {
+    const int n = threadIdx.x & 15;
+    v4f Q[4][3], H[2];
 #pragma unroll
-        for (int t = 0; t < 27; ++t) {
-            const int dx = t / 9, dy = (t / 3) % 3, dz = t % 3;
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                const int cell = (w + dy) * HZ + mt * 16 + m + dz;
-                const v4s x = *reinterpret_cast<const v4s*>(p[dx] + cell * 16 + ((kg ^ (cell >> 2)) & 3) * 4);
-                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wr[t], x, acc[mt], 0, 0, 0);
-            }
+        for (int d = 0; d < 3; ++d) Q[t][d] = v4f{0.f, 0.f, 0.f, 0.f};
+    H[0] = H[1] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int P = 0; P < kPairs; ++P) {
+        // keep one pair's slabs in flight: the scheduler would otherwise hoist
+        // every pair's loads and run out of registers
+        __builtin_amdgcn_sched_barrier(0);
+        const SlabAt at = slab_at(P);
+        v8s B[5];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) B[t] = slab(p, at, t);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Q[t][d] = mfma32(wr[3 * P + d], B[t], Q[t][d]);
+        H[0] = mfma32(wr[3 * P + 0], B[4], H[0]);   // dz = -1 at the cell before the row (column 15)
+        H[1] = mfma32(wr[3 * P + 2], B[4], H[1]);   // dz = +1 at the cell after the row (column 0)
+    }
+    // y[z] = Q_-1[z-1] + Q_0[z] + Q_+1[z+1] across the 16-lane rows of cells
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const float lsel = n == 15 ? (t > 0 ? Q[t - 1][0][v] : H[0][v]) : Q[t][0][v];
+            const float rsel = n == 0 ? (t < 3 ? Q[t + 1][2][v] : H[1][v]) : Q[t][2][v];
+            y[t][v] = Q[t][1][v] + dpp_ror1(lsel) + dpp_rol1(rsel);
         }
-    } else {
+}
+
+// One wave's 64-cell output row of a 2 -> 16 convolution: K = 64 (tap,
+// channel) pairs in two products per tile, k = 32 s + 8 q + v, tap = k / 2,
+// channel = k % 2; each lane gathers the 4-byte cells of its four taps.
+__device__ __forceinline__ void conv_row2(const uint16_t* const p[3], const v8s* wr, v4f y[4]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int n = lane & 15, q = lane >> 4;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int tA = s * 8 + 2 * kg, tB = tA + 1;
+    for (int t = 0; t < 4; ++t) y[t] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                uint32_t wa = 0, wb = 0;
-                if (tA < 27) {
-                    const int dx = tA / 9, dy = (tA / 3) % 3, dz = tA % 3;
-                    wa = *reinterpret_cast<const uint32_t*>(p[dx] + ((w + dy) * HZ + mt * 16 + m + dz) * 2);
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            uint32_t c[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int tap = 16 * s + 4 * q + j;
+                c[j] = 0;
+                if (tap < 27) {
+                    const int dx = tap / 9, dy = (tap / 3) % 3, dz = tap % 3;
+                    c[j] = *reinterpret_cast<const uint32_t*>(p[dx] + ((w + dy) * HZ + 16 * t + n + dz) * 2);
                 }
-                if (tB < 27) {
-                    const int dx = tB / 9, dy = (tB / 3) % 3, dz = tB % 3;
-                    wb = *reinterpret_cast<const uint32_t*>(p[dx] + ((w + dy) * HZ + mt * 16 + m + dz) * 2);
-                }
-                v4s x;
-                x.x = (short)(wa & 0xffff);
-                x.y = (short)(wa >> 16);
-                x.z = (short)(wb & 0xffff);
-                x.w = (short)(wb >> 16);
-                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wr[s], x, acc[mt], 0, 0, 0);
             }
+            const uint4 u = make_uint4(c[0], c[1], c[2], c[3]);
+            y[t] = mfma32(wr[s], __builtin_bit_cast(v8s, u), y[t]);
         }
     }
 }
 
-// The last layer (16 -> 1 channel) of one wave's 64-cell row. With a single
-// output channel the MFMA rows carry the three z taps instead: for each of the
-// 9 (dx, dy) groups, D[dz][z] += sum_ci W[dx][dy][dz][ci] x[i+dx-1][j+dy-1][z][ci]
-// over the unshifted cells z, and the output is D[0][z-1] + D[1][z] + D[2][z+1],
-// the z neighbours taken from the adjacent lanes. A fifth tile holds the two
-// cells beyond the row ends (column 0: z = k0-1, the others: z = k0+64).
-// Returns, on lanes 0..15, the outputs of cells m, m+16, m+32, m+48 of the row.
-__device__ __forceinline__ void conv_last_row(const uint16_t* const p[3], const v4s* wz, float y[4]) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int m = lane & 15, kg = lane >> 4;
-    v4f acc[5];
+// The last layer (16 -> 1 channel) of one wave's 64-cell row: the A rows are
+// the three z offsets (row dz + 1), so one product per pair and tile gives
+// Q_dz for every dz; the output is Q_-1[z-1] + Q_0[z] + Q_+1[z+1]. Returns, on
+// lanes 0..15, the outputs of cells n, n+16, n+32, n+48 of the row.
+__device__ __forceinline__ void conv_last_row(const uint16_t* const p[3], const v8s* wz, float y[4]) {
+    const int n = threadIdx.x & 15;
+    v4f Q[5];
 #pragma unroll
-    for (int t = 0; t < 5; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 5; ++t) Q[t] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int grp = 0; grp < 9; ++grp) {
-        const int dx = grp / 3, dy = grp % 3;
+    for (int P = 0; P < kPairs; ++P) {
+        __builtin_amdgcn_sched_barrier(0);
+        const SlabAt at = slab_at(P);
+        v8s B[5];
 #pragma unroll
-        for (int t = 0; t < 5; ++t) {
-            const int hz = t < 4 ? t * 16 + m + 1 : (m == 0 ? 0 : HZ - 1);
-            const int cell = (w + dy) * HZ + hz;
-            const v4s x = *reinterpret_cast<const v4s*>(p[dx] + cell * 16 + ((kg ^ (cell >> 2)) & 3) * 4);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wz[grp], x, acc[t], 0, 0, 0);
-        }
+        for (int t = 0; t < 5; ++t) B[t] = slab(p, at, t);
+#pragma unroll
+        for (int t = 0; t < 5; ++t) Q[t] = mfma32(wz[P], B[t], Q[t]);
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const float left = __shfl(acc[t][0], (lane + 63) & 63);
-        const float right = __shfl(acc[t][2], (lane + 1) & 63);
-        const float lb = __shfl(t > 0 ? acc[t - 1][0] : acc[4][0], t > 0 ? 15 : 0);
-        const float rb = __shfl(t < 3 ? acc[t + 1][2] : acc[4][2], t < 3 ? 0 : 1);
-        y[t] = acc[t][1] + (m == 0 ? lb : left) + (m == 15 ? rb : right);
+        const float lsel = n == 15 ? (t > 0 ? Q[t - 1][0] : Q[4][0]) : Q[t][0];
+        const float rsel = n == 0 ? (t < 3 ? Q[t + 1][2] : Q[4][2]) : Q[t][2];
+        y[t] = Q[t][1] + dpp_ror1(lsel) + dpp_rol1(rsel);
     }
 }
 
@@ -266,7 +331,7 @@ enum ConvOut {
 
 struct ConvArgs {
     const uint16_t* in;
-    const v4s* W;
+    const v8s* W;
     const float* bias;      // kHiddenRelu, kFinal, kPrecond
     uint16_t* out16;        // kHiddenRelu, kGradMasked
     const uint16_t* below;  // kGradMasked: activation of the layer below (ReLU mask)
@@ -297,8 +362,8 @@ __global__ __launch_bounds__(kThreads) void conv3d(Geom g, ConvArgs a) {
     const int i1 = min(g.nx, i0 + a.run);
     const int j = j0 + w;
     constexpr bool kLast = MODE == kFinal || MODE == kPrecond;
-    constexpr int NW = kLast ? 9 : (C == 16 ? 27 : 4);
-    v4s wr[NW];
+    constexpr int NW = kLast ? kPairs : (C == 16 ? 3 * kPairs : 2);
+    v8s wr[NW];
 #pragma unroll
     for (int t = 0; t < NW; ++t) wr[t] = a.W[t * 64 + lane];
     float bias[4] = {0.f, 0.f, 0.f, 0.f};
@@ -375,9 +440,8 @@ __global__ __launch_bounds__(kThreads) void conv3d(Geom g, ConvArgs a) {
                 }
             } else {
             v4f acc[4];
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt) acc[mt] = v4f{0.f, 0.f, 0.f, 0.f};
-            conv_row<C>(p, wr, acc);
+            if constexpr (C == 16) conv_row16(p, wr, acc);
+            else conv_row2(p, wr, acc);
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
                 const int k = k0 + mt * 16 + m;
@@ -657,39 +721,42 @@ __global__ void adam_kernel(int np, float* p, const float* gr, float* m, float* 
     p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
 }
 
-// BF16 operand layouts from the FP32 master weights.
-__global__ void prepare_weights(const float* p, v4s* W) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // one lane-slot (4 values)
+// BF16 operand layouts from the FP32 master weights: one thread per (operand,
+// lane), 8 values each (A row i = lane % 16, k = 8 (lane / 16) + v).
+__global__ void prepare_weights(const float* p, v8s* W) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= kWTotal) return;
-    const int lane = idx & 63, kg = lane >> 4, col = lane & 15;
-    short v[4];
-    for (int q = 0; q < 4; ++q) {
+    const int lane = idx & 63, i = lane & 15, q = lane >> 4;
+    v8s out;
+    for (int v = 0; v < 8; ++v) {
+        const int k = 8 * q + v;
         float x = 0.f;
-        const int r = kg * 4 + q;  // row of the B operand (K index within the step)
-        if (idx < kWf2) {                                   // layer 1 forward
-            const int s = idx / 64, k = s * 16 + r, tap = k >> 1, ch = k & 1;
-            if (tap < 27) x = p[offW(0) + (tap * 2 + ch) * 16 + col];
-        } else if (idx < kWf4) {                            // layers 2, 3 forward
-            const int l = idx < kWf3 ? 1 : 2;
-            const int base = l == 1 ? kWf2 : kWf3;
-            const int tap = (idx - base) / 64;
-            x = p[offW(l) + (tap * 16 + r) * 16 + col];
-        } else if (idx < kWb4) {                            // layer 4 forward: row = dz
-            const int grp = (idx - kWf4) / 64;              // (dx, dy) group
-            if (col < 3) x = p[offW(3) + (grp * 3 + col) * 16 + r];
-        } else if (idx < kWb3) {                            // layer 4 input gradient
-            const int s = (idx - kWb4) / 64, k = s * 16 + r, tap = k >> 1, ch = k & 1;
-            if (tap < 27 && ch == 0) x = p[offW(3) + (26 - tap) * 16 + col];
-        } else {                                            // layers 3, 2 input gradient
-            const int l = idx < kWb2 ? 2 : 1;
-            const int base = l == 2 ? kWb3 : kWb2;
-            const int tap = (idx - base) / 64;
-            // W'[tap][cin' = co][cout' = ci] = W[26 - tap][ci][co]
-            x = p[offW(l) + ((26 - tap) * 16 + col) * 16 + r];
+        if (idx < kWf2 || (idx >= kWb4 && idx < kWb3)) {          // 2-channel input, K = 64
+            const bool fwd = idx < kWf2;
+            const int s = (idx - (fwd ? kWf1 : kWb4)) / 64, kk = 32 * s + k, tap = kk >> 1, ch = kk & 1;
+            if (tap < 27) {
+                if (fwd) x = p[offW(0) + (tap * 2 + ch) * 16 + i];              // W1[tap][ch][i]
+                else if (ch == 0) x = p[offW(3) + (26 - tap) * 16 + i];         // W4[26 - tap][i][0]
+            }
+        } else if (idx < kWf4 || idx >= kWb3) {                    // 16 -> 16, pair x dz
+            const bool fwd = idx < kWf4;
+            const int l = fwd ? (idx < kWf3 ? 1 : 2) : (idx < kWb2 ? 2 : 1);
+            const int base = fwd ? (l == 1 ? kWf2 : kWf3) : (l == 2 ? kWb3 : kWb2);
+            const int op = (idx - base) / 64, P = op / 3, d = op % 3;
+            const int g = 2 * P + (k >> 4), c = k & 15;
+            if (g < 9) {
+                const int tap = 3 * g + d;
+                x = fwd ? p[offW(l) + (tap * 16 + c) * 16 + i]                  // W[tap][c][i]
+                        : p[offW(l) + ((26 - tap) * 16 + i) * 16 + c];         // W[26 - tap][i][c]
+            }
+        } else {                                                   // layer 4 forward: rows = dz + 1
+            const int P = (idx - kWf4) / 64;
+            const int g = 2 * P + (k >> 4), c = k & 15;
+            if (g < 9 && i < 3) x = p[offW(3) + ((3 * g + i) * 16 + c)];        // W4[3 g + i][c][0]
         }
-        v[q] = (short)f2bf(x);
+        out[v] = (short)f2bf(x);
     }
-    W[idx] = v4s{v[0], v[1], v[2], v[3]};
+    W[idx] = out;
 }
 
 // log-diagonal feature: log(d) - mean_U log(d) on unknown cells, 0 on Dirichlet
@@ -729,7 +796,7 @@ struct mffv_net {
     float* grads = nullptr;
     float* m = nullptr;
     float* v = nullptr;
-    v4s* W = nullptr;         // BF16 operand layouts
+    v8s* W = nullptr;         // BF16 operand layouts
     int step = 0;             // Adam steps taken
     // activation workspace, sized for `cap` cells
     int64_t cap = 0;

@@ -11,6 +11,11 @@ algorithmic bytes.
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT -o probe -- python3 -m paper_2408_03452_amd.kernel_probe
     rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT -o probe -- python3 -m paper_2408_03452_amd.kernel_probe
     python3 -m paper_2408_03452_amd.tracesum pmc OUT
+
+With --network it runs instead, on the channelised 128^3 workload, 10
+forward passes of the learned preconditioner's network (seeded random
+parameters of the trained network's scale) on a unit-RMS random input and
+the same 5 copies.
 """
 from __future__ import annotations
 
@@ -29,10 +34,13 @@ def main(argv=None) -> int:
     ap.add_argument("--remap", type=int, default=0, help="XCD-aware order (config.launch.remap)")
     ap.add_argument("--seg", type=int, default=0,
                     help="chunk shape: 0 default, -1 flat, else row-segment cells (config.launch.seg)")
+    ap.add_argument("--network", action="store_true", help="the network's forward passes on 128^3")
     args = ap.parse_args(argv)
     import torch
     from paper_2408_03452_amd import mffv
     from synth import WORKLOADS, workload_field
+    if args.network:
+        return network(torch, mffv)
 
     w = WORKLOADS["lognormal_corr8_256cube"]
     nx, ny, nz = w.shape
@@ -66,6 +74,34 @@ def main(argv=None) -> int:
             mffv.copy_probe(dst, src, nbytes, stream=s)
     torch.cuda.synchronize()
     g.close()
+    print("[probe] done", flush=True)
+    return 0
+
+
+def network(torch, mffv) -> int:
+    import numpy as np
+    from paper_2408_03452_amd import learned
+    shape = (128, 128, 128)
+    n = int(np.prod(shape))
+    print(f"[probe] {mffv.version()}: network forward on {shape}", flush=True)
+    rng = np.random.default_rng(5)
+    p = learned.init_params(0)
+    p[-(27 * 16 + 1):-1] = rng.normal(0.0, 0.05, 27 * 16)       # a nonzero last layer
+    net = mffv.net_create(p)
+    r = torch.from_numpy(rng.standard_normal(n).astype(np.float32)).cuda()
+    f = torch.from_numpy(rng.standard_normal(n).astype(np.float32)).cuda()
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    for _ in range(10):
+        mffv.nn_forward(net, shape, r, f, out)
+    torch.cuda.synchronize()
+    print(f"[probe] network: 10 forward passes, |out| {float(out.abs().mean()):.3e}", flush=True)
+    nbytes = 1 << 30
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        mffv.copy_probe(dst, src, nbytes)
+    torch.cuda.synchronize()
+    net.close()
     print("[probe] done", flush=True)
     return 0
 
