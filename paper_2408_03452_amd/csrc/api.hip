@@ -76,7 +76,7 @@ struct CgGraph {
     hipGraphExec_t exec = nullptr;
     int chunk = 0;
     const void* net = nullptr;  // learned preconditioner the graph was captured with
-    int net_gen = 0;            // and the generation of its workspace
+    int64_t net_gen = 0;        // and the token of its workspace (unique per network and allocation)
 };
 
 constexpr int kTimedIters = 32;
@@ -419,7 +419,7 @@ int enqueue_iter64(mffv_grid* G, int precond) {
 
 template <class F>
 int enqueue_chunk(mffv_grid* G, CgGraph& graph, int chunk, bool use_graph, F&& one_iter,
-                  const void* net = nullptr, int net_gen = 0) {
+                  const void* net = nullptr, int64_t net_gen = 0) {
     if (use_graph) {
         if (graph.exec && (graph.chunk != chunk || graph.net != net || graph.net_gen != net_gen)) {
             (void)hipGraphExecDestroy(graph.exec);
@@ -461,7 +461,7 @@ bool state_done(const MergedState& st) { return st.s[0].done || st.s[1].done; }
 // state to pinned memory behind it, then wait for the copy of chunk c-1.
 template <class State, class F>
 int drive_loop(mffv_grid* G, State* st, int max_iter, int chunk, CgGraph& graph, bool use_graph,
-               F&& one_iter, const void* net = nullptr, int net_gen = 0) {
+               F&& one_iter, const void* net = nullptr, int64_t net_gen = 0) {
     static_assert(sizeof(State) <= 256, "state mirror too small");
     const int max_chunks = max_iter / chunk + 3;
     bool stop = false;
@@ -609,7 +609,7 @@ int cg32(mffv_grid* G, double tol, int max_iter, int precond, const mffv_opts& o
     int rc = drive_loop(G, G->st32, max_iter, chunk, G->graph32[precond], use_graph,
                         [&]() { return enqueue_iter32(G, precond, net, nn_every); },
                         precond == MFFV_PRECOND_LEARNED ? (const void*)net : nullptr,
-                        net_gen * 64 + nn_every);
+                        (int64_t)net_gen * 64 + nn_every);
     if (rc) return rc;
     HIP_TRY(launch_finalize_f32(G->g.n, G->xw, G->p0, G->p1, G->st32, G->stream));
     CgState<float> hs;

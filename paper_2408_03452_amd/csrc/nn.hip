@@ -26,6 +26,7 @@
 #include "nn.hpp"
 #include "launch.hpp"
 
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -791,6 +792,16 @@ int nblocks_for(int64_t n, int cap) {
 
 using namespace mffv;
 
+namespace {
+std::atomic<int> g_ws_serial{0};
+// A positive value never handed out before in this process (wraps after 2^31
+// - 1 reallocations, far beyond any run).
+int next_ws_serial() {
+    int v = g_ws_serial.fetch_add(1) + 1;
+    return v > 0 ? v : 1;
+}
+}  // namespace
+
 struct mffv_net {
     float* params = nullptr;  // FP32 master weights, kNParams
     float* grads = nullptr;
@@ -817,7 +828,12 @@ struct mffv_net {
     double* loss = nullptr;
     int wg_blocks = 0;
     bool training_ws = false;
-    int ws_gen = 0;           // bumped whenever the workspace is reallocated
+    // identifies the network and its workspace for the solver's captured graphs:
+    // a fresh value, unique in the process, at creation and whenever the
+    // workspace is reallocated or a flag baked into kernel arguments changes,
+    // so that a graph captured with another (possibly destroyed) network at
+    // the same address is never replayed
+    int ws_gen = 0;
     int relu = 1;             // activation of the hidden layers
     int loss_kind = 0;        // 0 energy norm / functional, 1 residual space
 };
@@ -854,7 +870,7 @@ int ensure_ws(mffv_net* N, int64_t n, bool training) {
     if (n <= N->cap && (!training || N->training_ws)) return MFFV_OK;
     const int64_t cap = std::max<int64_t>(n, N->cap);
     free_ws(N);
-    N->ws_gen += 1;
+    N->ws_gen = next_ws_serial();
     int rc;
     if ((rc = nalloc(&N->x0, (size_t)cap * 2)) || (rc = nalloc(&N->h1, (size_t)cap * 16)) ||
         (rc = nalloc(&N->h2, (size_t)cap * 16)) || (rc = nalloc(&N->y, (size_t)cap))) {
@@ -1140,7 +1156,7 @@ int nn_prepare(const mffv_net* Nc, int64_t n) {
     const void* h1 = N->h1;
     int rc = ensure_ws(N, n, false);
     if (rc) return rc;
-    if (N->cap != before || N->h1 != h1) N->ws_gen += 1;
+    if (N->cap != before || N->h1 != h1) N->ws_gen = next_ws_serial();
     return N->ws_gen;
 }
 
@@ -1152,6 +1168,7 @@ int mffv_net_create(const float* params, mffv_net** out) {
     if (!out) return nfail(MFFV_EINVAL, "out is NULL");
     mffv_net* N = new (std::nothrow) mffv_net();
     if (!N) return nfail(MFFV_ENOMEM, "host allocation failed");
+    N->ws_gen = next_ws_serial();
     int rc;
     if ((rc = nalloc(&N->params, kNParams)) || (rc = nalloc(&N->grads, kNParams)) ||
         (rc = nalloc(&N->m, kNParams)) || (rc = nalloc(&N->v, kNParams)) ||
@@ -1212,7 +1229,7 @@ int mffv_net_set_activation(mffv_net* N, int relu) {
     if (relu != 0 && relu != 1) return nfail(MFFV_EINVAL, "activation must be 0 (identity) or 1 (ReLU)");
     NHIP(hipDeviceSynchronize());
     N->relu = relu;
-    N->ws_gen += 1;  // captured graphs baked the old flag into their kernel arguments
+    N->ws_gen = next_ws_serial();  // captured graphs baked the old flag into their kernel arguments
     return MFFV_OK;
 }
 

@@ -255,3 +255,33 @@ def test_finetuning_starts_from_the_given_network(mf):
     same = learned.train_preconditioner(systems, validation=systems[:2], n_white=4, epochs=1,
                                         lr=1e-12, lr_final=1e-12, dagger_rounds=0, init=p_start)
     assert np.array_equal(mf.net_get_params(same)[0], p_start)
+
+
+def test_new_network_after_a_destroyed_one_is_used(mf):
+    """A solve captures its iterations in a graph keyed by the network. After
+    that network is destroyed, a new network (whose handle may land at the
+    same address) must be the one applied: solving the same grid again gives
+    exactly what a fresh grid gives with the new network."""
+    shape = (20, 22, 24)
+    k = channelised(shape, 12)
+    g, _, b = gpu_problem(mf, k, c=1e-3)
+    p_old = nn.init_params(seed=5, last_scale=0.2)
+    p_new = harmful_params(0.5)          # z = 0.5 r / d: the directions of Jacobi-PCG
+    for _ in range(3):
+        old = mf.net_create(p_old)
+        x = torch.zeros(k.size, dtype=torch.float32, device="cuda")
+        st, _ = mf.cg_solve(g, b, x, mf.default_opts(precond=mf.PRECOND_LEARNED, net=old))
+        assert st == mf.OK
+        old.close()
+        new = mf.net_create(p_new)
+        x.zero_()
+        st, info = mf.cg_solve(g, b, x, mf.default_opts(precond=mf.PRECOND_LEARNED, net=new))
+        assert st == mf.OK
+        g2, _, b2 = gpu_problem(mf, k, c=1e-3)
+        x2 = torch.zeros(k.size, dtype=torch.float32, device="cuda")
+        st2, info2 = mf.cg_solve(g2, b2, x2, mf.default_opts(precond=mf.PRECOND_LEARNED, net=new))
+        assert st2 == mf.OK and info["iters"] == info2["iters"]
+        assert torch.equal(x, x2)
+        g2.close()
+        new.close()
+    g.close()
