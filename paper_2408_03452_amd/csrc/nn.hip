@@ -268,12 +268,30 @@ __device__ __forceinline__ void conv_row16(const uint16_t* const p[3], const v8s
         }
 }
 
+// Per-lane offsets (uint16 units from the slot of plane i - 1) of the eight
+// (tap, channel-pair) reads of a 2 -> 16 convolution: tap = 16 s + 4 q + j for
+// K slot s, lane group q, j = 0..3 (taps past 26 read tap 26's cell, which
+// meets zero weights); plane dx lies dx slots further (the ring's first two
+// slots are mirrored past its end). Computed once per kernel: decoding the
+// taps per lane in the loop costs more than the matrix work.
+constexpr int SLOT2 = PCELLS * 2;
+__device__ __forceinline__ void tap_offsets2(int toff[8]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int n = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int tap = min(16 * s2 + 4 * q + jj, 26);
+            const int dx = tap / 9, dy = (tap / 3) % 3, dz = tap % 3;
+            toff[4 * s2 + jj] = dx * SLOT2 + ((w + dy) * HZ + n + dz) * 2;
+        }
+}
+
 // One wave's 64-cell output row of a 2 -> 16 convolution: K = 64 (tap,
 // channel) pairs in two products per tile, k = 32 s + 8 q + v, tap = k / 2,
 // channel = k % 2; each lane gathers the 4-byte cells of its four taps.
-__device__ __forceinline__ void conv_row2(const uint16_t* const p[3], const v8s* wr, v4f y[4]) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int n = lane & 15, q = lane >> 4;
+__device__ __forceinline__ void conv_row2(const uint16_t* base, const int toff[8], const v8s* wr, v4f y[4]) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) y[t] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -282,16 +300,8 @@ __device__ __forceinline__ void conv_row2(const uint16_t* const p[3], const v8s*
         for (int t = 0; t < 4; ++t) {
             uint32_t c[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int tap = 16 * s + 4 * q + j;
-                c[j] = 0;
-                if (tap < 27) {
-                    const int dx = tap / 9, dy = (tap / 3) % 3, dz = tap % 3;
-                    c[j] = *reinterpret_cast<const uint32_t*>(p[dx] + ((w + dy) * HZ + 16 * t + n + dz) * 2);
-                }
-            }
-            const uint4 u = make_uint4(c[0], c[1], c[2], c[3]);
-            y[t] = mfma32(wr[s], __builtin_bit_cast(v8s, u), y[t]);
+            for (int j = 0; j < 4; ++j) c[j] = *reinterpret_cast<const uint32_t*>(base + toff[4 * s + j] + 32 * t);
+            y[t] = mfma32(wr[s], __builtin_bit_cast(v8s, make_uint4(c[0], c[1], c[2], c[3])), y[t]);
         }
     }
 }
@@ -354,7 +364,10 @@ __device__ __forceinline__ uint32_t pack_bf2(float lo, float hi) {
 // grid: ncols * ceil(nx / run) blocks of kThreads.
 template <int C, int MODE>
 __global__ __launch_bounds__(kThreads) void conv3d(Geom g, ConvArgs a) {
-    __shared__ __attribute__((aligned(16))) uint16_t lds[kRing * PCELLS * C];
+    // 2-channel input: the ring's slots 0 and 1 are mirrored in slots 4 and 5, so
+    // that planes i-1, i, i+1 always sit in three consecutive slots
+    constexpr int kSlots = C == 2 ? kRing + 2 : kRing;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[kSlots * PCELLS * C];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m = lane & 15, rg = lane >> 4;
     const int col = blockIdx.x % a.ncols, chunk = blockIdx.x / a.ncols;
@@ -387,7 +400,13 @@ __global__ __launch_bounds__(kThreads) void conv3d(Geom g, ConvArgs a) {
         store_plane<C>(R0, lds);
         store_plane<C>(R1, lds + PCELLS * C);
         store_plane<C>(R2, lds + 2 * PCELLS * C);
+        if constexpr (C == 2) {
+            store_plane<C>(R0, lds + 4 * PCELLS * C);
+            store_plane<C>(R1, lds + 5 * PCELLS * C);
+        }
     }
+    int toff[C == 2 ? 8 : 1];
+    if constexpr (C == 2) tap_offsets2(toff);
     __syncthreads();
 #pragma unroll 1
     for (int i = i0; i < i1; ++i) {
@@ -442,7 +461,7 @@ __global__ __launch_bounds__(kThreads) void conv3d(Geom g, ConvArgs a) {
             } else {
             v4f acc[4];
             if constexpr (C == 16) conv_row16(p, wr, acc);
-            else conv_row2(p, wr, acc);
+            else conv_row2(p[0], toff, wr, acc);
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
                 const int k = k0 + mt * 16 + m;
@@ -475,7 +494,11 @@ __global__ __launch_bounds__(kThreads) void conv3d(Geom g, ConvArgs a) {
             }
             }
         }
-        if (more) store_plane<C>(R, lds + ((i - i0 + 3) & 3) * PCELLS * C);
+        if (more) {
+            const int sl = (i - i0 + 3) & 3;
+            store_plane<C>(R, lds + sl * PCELLS * C);
+            if (C == 2 && sl < 2) store_plane<C>(R, lds + (sl + 4) * PCELLS * C);
+        }
         __syncthreads();
     }
 }
@@ -948,7 +971,8 @@ int conv(const Shape& S, const ConvArgs& a0, hipStream_t st) {
 }
 
 // Forward through the four layers from N->x0 (already filled); the last layer
-// either stores y (training) or forms the preconditioned z.
+// either stores y (training) or forms the preconditioned z. keep_h3
+// (training) keeps h3 for the backward pass; inference writes it over h1.
 int forward(mffv_net* N, const Shape& S, bool keep_h3, int last_mode, const ConvArgs& last,
             hipStream_t st, hipEvent_t* ev = nullptr) {
     if (ev) NHIP(hipEventRecord(ev[0], st));
@@ -1273,7 +1297,7 @@ int mffv_nn_forward(mffv_net* N, int nx, int ny, int nz, const float* r_hat, con
     NHIP(hipGetLastError());
     ConvArgs last{};
     last.out32 = out;
-    return forward(N, S, true, kFinal, last, st);
+    return forward(N, S, false, kFinal, last, st);
 }
 
 }  // extern "C"

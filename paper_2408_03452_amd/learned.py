@@ -204,6 +204,28 @@ def train_preconditioner(systems, validation=None, n_white: int = 256, epochs: i
     return net
 
 
+def train_best_of(systems, select_on, seeds=(0, 1, 2), log=None, **kw):
+    """Train one network per seed with :func:`train_preconditioner` and keep
+    the one with the fewest flexible-CG iterations on the ``select_on``
+    systems (held-in systems at the size the network will be used at: the
+    recipe's epoch selection works on small systems, and a network's benefit
+    at full size varies between seeds). Returns (network, {seed: iterations})."""
+    best, best_it, scores = None, None, {}
+    for seed in seeds:
+        net = train_preconditioner(systems, seed=seed, log=log, **kw)
+        it = fcg_iterations(net, select_on)
+        scores[seed] = it
+        if log:
+            log(f"seed {seed}: flexible-CG iterations on the selection systems {it}")
+        if best_it is None or it < best_it:
+            if best is not None:
+                best.close()
+            best, best_it = net, it
+        else:
+            net.close()
+    return best, scores
+
+
 def train(net: mffv.Net, samples: list, epochs: int = 4, lr: float = 1e-3, seed: int = 0,
           log_every: int = 0, lr_final: float | None = None):
     """Adam over the samples in shuffled order; returns the per-epoch mean loss
