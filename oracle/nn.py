@@ -251,3 +251,51 @@ def bias_mask() -> np.ndarray:
         mask[o:o + co] = True
         o += co
     return mask
+
+
+def learned_preconditioner(params, A, dmask, feat, omega: float = 0.5, relu: bool = True,
+                           bf16: bool = True):
+    """The preconditioner of flexible CG with the network, as a map on the
+    unknown cells' residual vector (``A``: the assembled full-grid operator,
+    ``feat``: the grid-shaped input feature).
+
+    The network's correction of a residual r is C(r) = s D^-1/2 N(r_hat, f)
+    with r_hat = D^-1/2 r / s, s^2 = r' D^-1 r / n_U (0 on Dirichlet cells).
+    With omega = 0 the preconditioned residual is z = D^-1 r + C(r): Jacobi
+    when N = 0. With omega > 0 the network sits between two damped Jacobi
+    sweeps, each taken from the residual it is given:
+
+        z1 = omega D^-1 r,  r1 = r - A z1,  z2 = z1 + D^-1 r1 + C(r1),
+        z  = z2 + omega D^-1 (r - A z2),
+
+    which with N = 0 is the polynomial preconditioner
+    D^-1/2 [(I - w A~)((1 + w) I - w A~) + w I] D^-1/2 of A~ = D^-1/2 A D^-1/2.
+    """
+    d = A.diagonal()
+    u = np.flatnonzero(~np.asarray(dmask, dtype=bool).ravel())
+    n = d.size
+    shape = np.shape(dmask)
+
+    def C(ru):
+        sc = np.sqrt(np.sum(ru * ru / d[u]) / u.size)
+        if sc == 0:
+            return np.zeros_like(ru)
+        rh = np.zeros(n)
+        rh[u] = ru / np.sqrt(d[u]) / sc
+        N, _, _ = forward(params, rh.reshape(shape), feat, bf16=bf16, relu=relu)
+        return sc * N.ravel()[u] / np.sqrt(d[u])
+
+    def Au(vu):
+        v = np.zeros(n)
+        v[u] = vu
+        return (A @ v)[u]
+
+    def M(ru):
+        ru = np.asarray(ru, dtype=np.float64)
+        if omega == 0:
+            return ru / d[u] + C(ru)
+        z1 = omega * ru / d[u]
+        r1 = ru - Au(z1)
+        z2 = z1 + r1 / d[u] + C(r1)
+        return z2 + omega * (ru - Au(z2)) / d[u]
+    return M

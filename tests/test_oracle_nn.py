@@ -321,3 +321,69 @@ def test_adam_frozen_entries_and_bias_mask():
     p1, m1, v1 = nn.adam(p, g, z, z, step=1, lr=0.1, frozen=mask)
     assert np.all(p1[mask] == 1.0) and np.all(m1[mask] == 0) and np.all(v1[mask] == 0)
     assert np.allclose(p1[~mask], 1.0 - 0.1 * 0.5 / (0.5 + 1e-8), rtol=1e-14)
+
+
+# --- the preconditioner around the network -----------------------------------
+
+def test_sandwich_preconditioner_without_network_is_the_polynomial():
+    """N = 0: the two damped Jacobi sweeps around the Jacobi step give the
+    polynomial D^-1/2 p(A~) D^-1/2 with p(l) = (1 - w l)(1 + w - w l) + w,
+    checked against the dense matrix polynomial on a 4^3 system; on a
+    diagonal operator (A~ = I, p(1) = 1) it is Jacobi exactly."""
+    import scipy.sparse as sp
+    shape = (4, 4, 4)
+    dmask, u, At, _ = _dense_scaled(shape, 21)
+    from oracle import tpfa
+    from synth import lognormal_iid
+    k = lognormal_iid(shape, 1.0, 21)
+    dm, pd = tpfa.x_plane_dirichlet(shape)
+    A, _ = tpfa.assemble(*tpfa.transmissibility(k), 1e-2, dm, pd)
+    zero = nn.init_params(seed=0, last_scale=0.0)
+    rng = np.random.default_rng(22)
+    d = A.diagonal()[u]
+    for w in (0.5, 0.8):
+        M = nn.learned_preconditioner(zero, A, dm, np.zeros(shape), omega=w)
+        r = rng.normal(size=u.sum())
+        I = np.eye(u.sum())
+        P = (I - w * At) @ ((1 + w) * I - w * At) + w * I
+        want = (P @ (r / np.sqrt(d))) / np.sqrt(d)
+        assert np.allclose(M(r), want, rtol=1e-12, atol=1e-14)
+        assert np.min(np.linalg.eigvalsh((P + P.T) / 2)) > 0          # SPD for A~'s spectrum
+    # omega = 0 and N = 0: Jacobi
+    M0 = nn.learned_preconditioner(zero, A, dm, np.zeros(shape), omega=0.0)
+    r = rng.normal(size=u.sum())
+    assert np.allclose(M0(r), r / d, rtol=1e-15, atol=0)
+    # a diagonal operator: A~ = I, so the sandwich is Jacobi too
+    n = int(np.prod(shape))
+    Ad = sp.diags(np.full(n, 4.0)).tocsr()
+    nod = np.zeros(shape, dtype=bool)
+    Md = nn.learned_preconditioner(zero, Ad, nod, np.zeros(shape), omega=0.5)
+    r = rng.normal(size=n)
+    assert np.allclose(Md(r), r / 4.0, rtol=1e-15, atol=1e-16)
+
+
+def test_sandwich_correction_is_the_network_through_the_post_sweep():
+    """With a pass-through network N = a r_hat the sandwich gives
+    z~ = p(A~) r~ + a (I - w A~)(I - w A~) r~ (the network sees the residual
+    after the first sweep and its output passes the second), in closed form."""
+    shape = (4, 4, 4)
+    from oracle import tpfa
+    from synth import lognormal_iid
+    k = lognormal_iid(shape, 1.0, 23)
+    dm, pd = tpfa.x_plane_dirichlet(shape)
+    A, _ = tpfa.assemble(*tpfa.transmissibility(k), 1e-2, dm, pd)
+    u = np.flatnonzero(~dm.ravel())
+    dis = 1.0 / np.sqrt(A.diagonal())
+    At = (dis[:, None] * A.toarray() * dis[None, :])[np.ix_(u, u)]
+    a, w = 0.3, 0.5
+    M = nn.learned_preconditioner(_pass_through(a), A, dm, np.zeros(shape), omega=w, relu=False,
+                                  bf16=False)
+    r = np.random.default_rng(24).normal(size=u.size)
+    rt = r * dis[u]
+    I = np.eye(u.size)
+    S = I - w * At
+    poly = S @ ((1 + w) * I - w * At) + w * I
+    # the network input is rounded to FP32: compare at FP32 resolution
+    assert np.allclose(M(r) / dis[u], poly @ rt + a * S @ S @ rt, rtol=1e-6, atol=1e-7)
+    # and the correction really passes through the second sweep (not (I - w A~) once)
+    assert not np.allclose(M(r) / dis[u], poly @ rt + a * S @ rt, rtol=1e-3, atol=1e-4)
