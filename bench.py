@@ -710,9 +710,10 @@ def cpu_baseline(c3_params, learned_iters, crop_fields, log_fn):
     """The CPU baseline leg: the FP64 oracle on the host, one thread.
 
     * The headline's baseline: one iteration of the oracle's flexible CG with
-      the oracle network (the trained parameters) as preconditioner, on the
-      [0:64]^3 crop of held-out realisation 3500 (network forward in NumPy plus
-      the CSR product and dots), timed and scaled by the cell count (x8 to
+      the oracle's learned preconditioner (the trained network between two
+      damped Jacobi sweeps, as the GPU solve uses it), on the [0:64]^3 crop of
+      held-out realisation 3500 (network forward in NumPy plus the CSR
+      products and dots), timed and scaled by the cell count (x8 to
       128^3) and by the GPU's median learned-FCG iteration count: the oracle's
       time to 1e-6 on the headline workload, extrapolated.
     * The accuracy of each GPU field of ``bench_crop_fields``: the oracle's
@@ -739,15 +740,7 @@ def cpu_baseline(c3_params, learned_iters, crop_fields, log_fn):
         d = A.diagonal()
         ld = np.log(d)
         feat = np.where(dm.ravel(), 0.0, ld - ld[u].mean()).reshape(k3.shape)
-
-        def M(ru):
-            r = np.zeros(d.size)
-            r[u] = ru
-            sc = np.sqrt(np.sum(ru * ru / d[u]) / u.size)
-            rh = np.zeros(d.size)
-            rh[u] = ru / np.sqrt(d[u]) / sc
-            N, _, _ = nn.forward(c3_params, rh.reshape(k3.shape), feat)
-            return (r / d + sc * N.ravel() / np.sqrt(d))[u]
+        M = nn.learned_preconditioner(c3_params, A, dm, feat, omega=0.5)
 
         t0 = time.perf_counter()
         z = M(bu)
@@ -757,8 +750,9 @@ def cpu_baseline(c3_params, learned_iters, crop_fields, log_fn):
         scale = (128 ** 3) / (64 ** 3)
         out.update({
             "value": t_iter * scale * learned_iters, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": (f"one iteration of the oracle's flexible CG with the oracle network (FP64 NumPy "
-                       f"convolutions on BF16-rounded operands, SciPy CSR product) on the [0:64]^3 crop "
+            "sample": (f"one iteration of the oracle's flexible CG with the oracle's learned preconditioner "
+                       f"(the network between two damped Jacobi sweeps, omega 0.5: FP64 NumPy convolutions "
+                       f"on BF16-rounded operands, SciPy CSR products) on the [0:64]^3 crop "
                        f"of held-out channelised realisation 3500: {t_iter:.2f} s on 1 thread of "
                        f"{os.cpu_count()} host cores; scaled x{scale:g} (cells, to 128^3) and x{learned_iters:g} "
                        f"(the GPU's median learned-FCG iteration count): time to 1e-6, extrapolated"),

@@ -112,6 +112,12 @@ typedef struct {
                             kernel expired. The first call with a given set of arguments
                             allocates the solver's plan: under stream capture it returns
                             MFFV_EINVAL, so make it once outside capture.               */
+    double nn_smooth;    /* MFFV_PRECOND_LEARNED: weight w of the damped Jacobi sweeps around
+                            the network (default 0.5). For w > 0 the preconditioned residual
+                            of r is z1 = w D^-1 r, r1 = r - A z1, z2 = z1 + D^-1 r1 + C(r1),
+                            z = z2 + w D^-1 (r - A z2), where C is the network's correction
+                            (see mffv_net_create); with the zero network this is a fixed SPD
+                            polynomial preconditioner. 0: z = D^-1 r + C(r). In [0, 1). */
 } mffv_opts;
 
 typedef struct {

@@ -76,6 +76,7 @@ struct CgGraph {
     hipGraphExec_t exec = nullptr;
     int chunk = 0;
     const void* net = nullptr;  // learned preconditioner the graph was captured with
+    float omega = 0.f;          // and the weight of its Jacobi sweeps
     int64_t net_gen = 0;        // and the token of its workspace (unique per network and allocation)
 };
 
@@ -277,7 +278,7 @@ struct LoopResult {
 
 // Enqueue one CG iteration (phase A, phase B, and for flexible CG the
 // preconditioner and its dots).
-int enqueue_iter32(mffv_grid* G, int precond, const mffv_net* net, int nn_every = 1) {
+int enqueue_iter32(mffv_grid* G, int precond, const mffv_net* net, int nn_every = 1, float omega = 0.f) {
     // flexible CG: the network preconditions every nn_every-th iteration, Jacobi
     // the others (the position in the loop is counted per enqueued iteration)
     const bool use_nn = (++G->flex_count % nn_every) == 0;
@@ -326,8 +327,8 @@ int enqueue_iter32(mffv_grid* G, int precond, const mffv_net* net, int nn_every 
     if (ev) HIP_TRY(hipEventRecord(ev[2], G->stream));
     if (precond == MFFV_PRECOND_LEARNED) {
         if (use_nn) {
-            int rc = nn_precondition(net, G->g, G->r, G->dinv, G->dmask, G->z, pb + G->nb_vec, G->nb_vec,
-                                     G->feat, (float)G->n_unknown, G->stream, nev);
+            int rc = nn_precondition(net, G->g, coef_of(G), G->m_apply, omega, G->r, G->dinv, G->dmask, G->z,
+                                     pb + G->nb_vec, G->nb_vec, G->feat, (float)G->n_unknown, G->stream, nev);
             if (rc) return rc;
         } else {
             HIP_TRY(launch_jacobi_z(G->g.n, G->r, G->dinv, G->dmask, G->z, G->stream));
@@ -419,9 +420,10 @@ int enqueue_iter64(mffv_grid* G, int precond) {
 
 template <class F>
 int enqueue_chunk(mffv_grid* G, CgGraph& graph, int chunk, bool use_graph, F&& one_iter,
-                  const void* net = nullptr, int64_t net_gen = 0) {
+                  const void* net = nullptr, int64_t net_gen = 0, float omega = 0.f) {
     if (use_graph) {
-        if (graph.exec && (graph.chunk != chunk || graph.net != net || graph.net_gen != net_gen)) {
+        if (graph.exec && (graph.chunk != chunk || graph.net != net || graph.net_gen != net_gen ||
+                           graph.omega != omega)) {
             (void)hipGraphExecDestroy(graph.exec);
             graph.exec = nullptr;
         }
@@ -442,6 +444,7 @@ int enqueue_chunk(mffv_grid* G, CgGraph& graph, int chunk, bool use_graph, F&& o
             graph.chunk = chunk;
             graph.net = net;
             graph.net_gen = net_gen;
+            graph.omega = omega;
         }
         HIP_TRY(hipGraphLaunch(graph.exec, G->stream));
         return MFFV_OK;
@@ -461,12 +464,12 @@ bool state_done(const MergedState& st) { return st.s[0].done || st.s[1].done; }
 // state to pinned memory behind it, then wait for the copy of chunk c-1.
 template <class State, class F>
 int drive_loop(mffv_grid* G, State* st, int max_iter, int chunk, CgGraph& graph, bool use_graph,
-               F&& one_iter, const void* net = nullptr, int64_t net_gen = 0) {
+               F&& one_iter, const void* net = nullptr, int64_t net_gen = 0, float omega = 0.f) {
     static_assert(sizeof(State) <= 256, "state mirror too small");
     const int max_chunks = max_iter / chunk + 3;
     bool stop = false;
     for (int c = 0; c < max_chunks && !stop; ++c) {
-        int rc = enqueue_chunk(G, graph, chunk, use_graph, one_iter, net, net_gen);
+        int rc = enqueue_chunk(G, graph, chunk, use_graph, one_iter, net, net_gen, omega);
         if (rc) return rc;
         HIP_TRY(hipMemcpyAsync(G->hstate + 256 * (c & 1), st, sizeof(State),
                                hipMemcpyDeviceToHost, G->stream));
@@ -594,22 +597,23 @@ int cg32(mffv_grid* G, double tol, int max_iter, int precond, const mffv_opts& o
         return MFFV_OK;
     }
     if (precond == MFFV_PRECOND_LEARNED) {
-        int rc = nn_precondition(net, G->g, G->r, G->dinv, G->dmask, G->z, pb + G->nb_vec, G->nb_vec,
-                                 G->feat, (float)G->n_unknown, G->stream);
+        int rc = nn_precondition(net, G->g, coef_of(G), G->m_apply, (float)o.nn_smooth, G->r, G->dinv, G->dmask,
+                                 G->z, pb + G->nb_vec, G->nb_vec, G->feat, (float)G->n_unknown, G->stream);
         if (rc) return rc;
         VecIO<float> f = v;
         f.partials = reinterpret_cast<float*>(G->partF);
         HIP_TRY(launch_flex_dots_f32(G->g.n, f, G->nb_vec, G->stream));
     }
     const int nn_every = precond == MFFV_PRECOND_LEARNED ? std::max(1, o.nn_every) : 1;
+    const float omega = precond == MFFV_PRECOND_LEARNED ? (float)o.nn_smooth : 0.f;
     // a chunk holding whole network periods keeps the captured pattern right on replay
     const int chunk = (std::max(1, o.check_every) + nn_every - 1) / nn_every * nn_every;
     const bool use_graph = o.use_graph && !o.timing && G->stream != nullptr;
     G->flex_count = 0;
     int rc = drive_loop(G, G->st32, max_iter, chunk, G->graph32[precond], use_graph,
-                        [&]() { return enqueue_iter32(G, precond, net, nn_every); },
+                        [&]() { return enqueue_iter32(G, precond, net, nn_every, omega); },
                         precond == MFFV_PRECOND_LEARNED ? (const void*)net : nullptr,
-                        (int64_t)net_gen * 64 + nn_every);
+                        (int64_t)net_gen * 64 + nn_every, omega);
     if (rc) return rc;
     HIP_TRY(launch_finalize_f32(G->g.n, G->xw, G->p0, G->p1, G->st32, G->stream));
     CgState<float> hs;
@@ -696,6 +700,8 @@ int validate_opts(const mffv_opts& o) {
     if (o.async != 0 && o.async != 1) return fail(MFFV_EINVAL, "opts.async must be 0 or 1");
     if (o.nn_every < 1 || o.nn_every > 64)
         return fail(MFFV_EINVAL, "opts.nn_every must be in [1, 64]");
+    if (!(o.nn_smooth >= 0.0 && o.nn_smooth < 1.0))
+        return fail(MFFV_EINVAL, "opts.nn_smooth must be in [0, 1)");
     return MFFV_OK;
 }
 
@@ -1067,6 +1073,7 @@ void mffv_default_opts(mffv_opts* o) {
     o->async = 0;
     o->single_reduction = 0;
     o->nn_every = 1;
+    o->nn_smooth = 0.5;
 }
 
 namespace {

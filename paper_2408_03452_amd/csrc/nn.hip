@@ -351,6 +351,8 @@ struct ConvArgs {
     const float* dinv;
     const uint8_t* dmask;
     const float* sscale;    // kPrecond: device scalar s
+    const float* r1;        // kPrecond with the Jacobi sweeps: the residual after the first sweep
+    float omega;            //   and the sweeps' weight
     int relu;               // 1: ReLU after the hidden layers, 0: identity
     int ntk;                // column tiles along z
     int ncols;              // column tiles in total (y tiles x z tiles)
@@ -419,7 +421,7 @@ __global__ __launch_bounds__(kThreads) void conv3d(Geom g, ConvArgs a) {
         // issue order, waiting for them never waits for the plane fetch below.
         // (A data-dependent load, e.g. r only where dmask is 0, would put one
         // memory round trip after another into every plane step.)
-        float er[4], ed[4];
+        float er[4], ed[4], er1[4];
         uint32_t em[4];
         uint2 eb[4];
         {
@@ -431,6 +433,7 @@ __global__ __launch_bounds__(kThreads) void conv3d(Geom g, ConvArgs a) {
                     er[mt] = a.r[l];
                     ed[mt] = a.dinv[l];
                     em[mt] = a.dmask[l];
+                    er1[mt] = a.r1 ? a.r1[l] : 0.f;
                 }
                 if (MODE == kGradMasked) eb[mt] = *reinterpret_cast<const uint2*>(a.below + l * 16 + rg * 4);
             }
@@ -453,8 +456,10 @@ __global__ __launch_bounds__(kThreads) void conv3d(Geom g, ConvArgs a) {
                         if (MODE == kFinal) {
                             a.out32[l] = v;
                         } else {
+                            // z = dinv r + C, or between the sweeps z2 = omega dinv r + dinv r1 + C
                             const float di = ed[mt];
-                            a.out32[l] = em[mt] ? 0.f : di * er[mt] + s * sqrtf(di) * v;
+                            const float jac = a.r1 ? a.omega * di * er[mt] + di * er1[mt] : di * er[mt];
+                            a.out32[l] = em[mt] ? 0.f : jac + s * sqrtf(di) * v;
                         }
                     }
                 }
@@ -525,6 +530,43 @@ __global__ __launch_bounds__(kThreads) void nn_input(int64_t n, const float* r, 
         const uint32_t v = (uint32_t)f2bf(rh) | ((uint32_t)f2bf(rh * feat[l]) << 16);
         reinterpret_cast<uint32_t*>(x0)[l] = v;
     }
+}
+
+// The damped Jacobi sweeps around the network (elementwise parts; the
+// operator's applies run between them).
+// t = omega dinv r on unknown cells, 0 on Dirichlet cells.
+__global__ __launch_bounds__(kThreads) void sweep_scale(int64_t n, const float* r, const float* dinv,
+                                                        const uint8_t* dmask, float omega, float* t) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x; l < n; l += stride)
+        t[l] = dmask[l] ? 0.f : omega * dinv[l] * r[l];
+}
+
+// r1 = r - y on unknown cells (y = A t), 0 on Dirichlet cells; per-block
+// partial sums of dinv r1^2 (the network's scale of r1).
+__global__ __launch_bounds__(kThreads) void sweep_resid(int64_t n, const float* r, const float* y,
+                                                        const float* dinv, const uint8_t* dmask, float* r1,
+                                                        float* part) {
+    __shared__ float red[kThreads / kWave];
+    float sum = 0.f;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x; l < n; l += stride) {
+        const float v = dmask[l] ? 0.f : r[l] - y[l];
+        r1[l] = v;
+        sum += dinv[l] * v * v;
+    }
+    const float t = block_sum(sum, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// z = z2 + omega dinv (r - y) on unknown cells (y = A z2, held in z on entry),
+// 0 on Dirichlet cells.
+__global__ __launch_bounds__(kThreads) void sweep_post(int64_t n, const float* z2, const float* r,
+                                                       const float* dinv, const uint8_t* dmask, float omega,
+                                                       float* z) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x; l < n; l += stride)
+        z[l] = dmask[l] ? 0.f : z2[l] + omega * dinv[l] * (r[l] - z[l]);
 }
 
 // Weight gradient of one layer over all cells: per-block partial D[t][ci][co]
@@ -842,6 +884,8 @@ struct mffv_net {
     uint16_t* g2 = nullptr;
     uint16_t* dy4 = nullptr;  // 2 channels
     float* y = nullptr;
+    float* sw1 = nullptr;     // inference: the Jacobi sweeps' vectors (FP32 cells)
+    float* sw2 = nullptr;
     float* t1 = nullptr;      // training scratch (FP32 cells)
     float* t2 = nullptr;
     float* part = nullptr;    // weight-gradient partials
@@ -884,7 +928,7 @@ constexpr int kRedBlocks = 1024;
 
 void free_ws(mffv_net* N) {
     nfree(N->x0); nfree(N->h1); nfree(N->h2); nfree(N->h3); nfree(N->g1); nfree(N->g2);
-    nfree(N->dy4); nfree(N->y); nfree(N->t1); nfree(N->t2);
+    nfree(N->dy4); nfree(N->y); nfree(N->t1); nfree(N->t2); nfree(N->sw1); nfree(N->sw2);
     N->cap = 0;
     N->training_ws = false;
 }
@@ -896,7 +940,8 @@ int ensure_ws(mffv_net* N, int64_t n, bool training) {
     N->ws_gen = next_ws_serial();
     int rc;
     if ((rc = nalloc(&N->x0, (size_t)cap * 2)) || (rc = nalloc(&N->h1, (size_t)cap * 16)) ||
-        (rc = nalloc(&N->h2, (size_t)cap * 16)) || (rc = nalloc(&N->y, (size_t)cap))) {
+        (rc = nalloc(&N->h2, (size_t)cap * 16)) || (rc = nalloc(&N->y, (size_t)cap)) ||
+        (rc = nalloc(&N->sw1, (size_t)cap)) || (rc = nalloc(&N->sw2, (size_t)cap))) {
         free_ws(N);
         return nfail(rc, "network workspace allocation failed");
     }
@@ -1125,22 +1170,52 @@ int loss_pass(mffv_net* N, const Shape& S, const Coef& c, const March& m, const 
 
 namespace mffv {
 
-int nn_precondition(const mffv_net* Nc, const Geom& g, const float* r, const float* dinv,
-                    const uint8_t* dmask, float* z, const float* pb, int nb_b, const float* feat,
-                    float n_u, hipStream_t s, hipEvent_t* layer_ev) {
+int nn_precondition(const mffv_net* Nc, const Geom& g, const Coef& c, const March& m, float omega,
+                    const float* r, const float* dinv, const uint8_t* dmask, float* z, const float* pb,
+                    int nb_b, const float* feat, float n_u, hipStream_t s, hipEvent_t* layer_ev) {
     mffv_net* N = const_cast<mffv_net*>(Nc);
     if (g.n > N->cap) return nfail(MFFV_ESTATE, "network workspace not prepared for this grid");
     const Shape S = shape_of(g.nx, g.ny, g.nz);
-    hipLaunchKernelGGL(nn_input, dim3(nblocks_for(g.n, kRedBlocks)), dim3(kThreads), 0, s, g.n, r, dinv, feat,
-                       pb, nb_b, n_u, N->sscale, N->x0, (const uint8_t*)nullptr);
+    const int nb = nblocks_for(g.n, kRedBlocks);
+    const float* rin = r;    // the residual the network sees
+    const float* pin = pb;   // and the partials of its dinv-weighted square
+    int nbin = nb_b;
+    if (omega > 0.f) {
+        // first sweep: r1 = r - A (omega dinv r), into sw1 (sw2 holds A t)
+        hipLaunchKernelGGL(sweep_scale, dim3(nb), dim3(kThreads), 0, s, g.n, r, dinv, dmask, omega, N->sw1);
+        NHIP(hipGetLastError());
+        StencilIO<float> io;
+        io.src = N->sw1;
+        io.out = N->sw2;
+        NHIP(launch_stencil_f32(kApply, g, c, io, m, s));
+        hipLaunchKernelGGL(sweep_resid, dim3(nb), dim3(kThreads), 0, s, g.n, r, (const float*)N->sw2, dinv, dmask,
+                           N->sw1, N->red);
+        NHIP(hipGetLastError());
+        rin = N->sw1;
+        pin = N->red;
+        nbin = nb;
+    }
+    hipLaunchKernelGGL(nn_input, dim3(nb), dim3(kThreads), 0, s, g.n, rin, dinv, feat, pin, nbin, n_u, N->sscale,
+                       N->x0, (const uint8_t*)nullptr);
     NHIP(hipGetLastError());
     ConvArgs last{};
-    last.out32 = z;
+    last.out32 = omega > 0.f ? N->sw2 : z;   // z2 before the second sweep
     last.r = r;
+    last.r1 = omega > 0.f ? N->sw1 : nullptr;
+    last.omega = omega;
     last.dinv = dinv;
     last.dmask = dmask;
     last.sscale = N->sscale;
-    return forward(N, S, false, kPrecond, last, s, layer_ev);
+    int rc = forward(N, S, false, kPrecond, last, s, layer_ev);
+    if (rc || !(omega > 0.f)) return rc;
+    // second sweep: z = z2 + omega dinv (r - A z2), A z2 formed in z first
+    StencilIO<float> io;
+    io.src = N->sw2;
+    io.out = z;
+    NHIP(launch_stencil_f32(kApply, g, c, io, m, s));
+    hipLaunchKernelGGL(sweep_post, dim3(nb), dim3(kThreads), 0, s, g.n, (const float*)N->sw2, r, dinv, dmask, omega, z);
+    NHIP(hipGetLastError());
+    return MFFV_OK;
 }
 
 int nn_feature(const Geom& g, const float* dinv, const uint8_t* dmask, float n_u, float* part,

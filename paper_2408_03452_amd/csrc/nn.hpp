@@ -6,14 +6,18 @@
 
 namespace mffv {
 
-// z = dinv r + s N([r / s, feat]) on unknown cells (0 on Dirichlet cells) for
-// flexible CG, with s = ||r|| / sqrt(n_u) and ||r||^2 the sum of the nb_b
-// phase-B partials pb. Enqueued on s; allocates nothing if nn_prepare ran.
-// layer_ev (optional): 5 events, recorded before the first convolution and
-// after each of the four.
-int nn_precondition(const mffv_net* net, const Geom& g, const float* r, const float* dinv,
-                    const uint8_t* dmask, float* z, const float* pb, int nb_b, const float* feat,
-                    float n_u, hipStream_t s, hipEvent_t* layer_ev = nullptr);
+// The preconditioned residual z of r for flexible CG (0 on Dirichlet cells).
+// The network's correction of a residual v is C(v) = s D^-1/2 N(v_hat, feat),
+// v_hat = D^-1/2 v / s, s^2 = v' D^-1 v / n_u. omega = 0: z = D^-1 r + C(r),
+// with r' D^-1 r the sum of the nb_b phase-B partials pb. omega > 0: the
+// network between two damped Jacobi sweeps on the operator (g, c), applied
+// with launch shape m: z1 = omega D^-1 r, r1 = r - A z1,
+// z2 = z1 + D^-1 r1 + C(r1), z = z2 + omega D^-1 (r - A z2). Enqueued on s;
+// allocates nothing if nn_prepare ran. layer_ev (optional): 5 events, recorded
+// before the first convolution and after each of the four.
+int nn_precondition(const mffv_net* net, const Geom& g, const Coef& c, const March& m, float omega,
+                    const float* r, const float* dinv, const uint8_t* dmask, float* z, const float* pb,
+                    int nb_b, const float* feat, float n_u, hipStream_t s, hipEvent_t* layer_ev = nullptr);
 
 // Make sure the network's inference workspace holds n cells; returns the
 // workspace generation (changes whenever the workspace is reallocated), or a

@@ -41,7 +41,8 @@ class Opts(ctypes.Structure):
                 ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("net", ctypes.c_void_p), ("single_reduction", ctypes.c_int),
                 ("nn_every", ctypes.c_int), ("timing", ctypes.c_int),
-                ("async_", ctypes.c_int)]   # mffv_opts.async (a Python keyword)
+                ("async_", ctypes.c_int),   # mffv_opts.async (a Python keyword)
+                ("nn_smooth", ctypes.c_double)]
 
 
 class TuneResult(ctypes.Structure):

@@ -157,30 +157,12 @@ def test_every_loss_kind_on_a_tpfa_operator_is_bit_exact(mf, kind, with_target):
     g.close()
 
 
-def oracle_learned_preconditioner(params, ref, feat):
-    """M(r_U) of flexible CG with the network: z = r/d + s d^-1/2 N(r_hat, f)
-    with r_hat = d^-1/2 r / s and s^2 = sum_U r^2/d / n_U, 0 on Dirichlet cells."""
-    d = ref.diag()
-    u = ref.u
-    n = d.size
-    shape = ref.shape
-
-    def M(ru):
-        r = np.zeros(n)
-        r[u] = ru
-        s = np.sqrt(np.sum(r[u] ** 2 / d[u]) / u.size)
-        rh = np.zeros(n)
-        rh[u] = r[u] / np.sqrt(d[u]) / s
-        N, _, _ = nn.forward(params, rh.reshape(shape), feat)
-        z = r / d + s * N.ravel() / np.sqrt(d)
-        return z[u]
-    return M
-
-
-def test_flexible_cg_with_a_random_network_matches_the_oracle(mf):
-    """Flexible CG with a fixed, non-degenerate random network: the GPU's FP32
-    iteration count within 5 % (or 3) of the oracle's FP64 flexible CG with the
-    same network as the preconditioner, no safeguard fallback on either side,
+@pytest.mark.parametrize("omega", [0.5, 0.0])
+def test_flexible_cg_with_a_random_network_matches_the_oracle(mf, omega):
+    """Flexible CG with a fixed, non-degenerate random network, with and without
+    the Jacobi sweeps around it: the GPU's FP32 iteration count within 5 % (or
+    3) of the oracle's FP64 flexible CG with the same preconditioner
+    (oracle.nn.learned_preconditioner), no safeguard fallback on either side,
     and the FP64-refined field within 1e-5 of the direct solution."""
     shape = (16, 16, 20)
     k = channelised(shape, 3600)
@@ -193,9 +175,9 @@ def test_flexible_cg_with_a_random_network_matches_the_oracle(mf):
     f = feat.cpu().numpy().astype(np.float64).reshape(shape)
     net = mf.net_create(p)
     x = torch.zeros(k.size, dtype=torch.float32, device="cuda")
-    st, info = mf.cg_solve(g, b, x, mf.default_opts(precond=mf.PRECOND_LEARNED, net=net))
+    st, info = mf.cg_solve(g, b, x, mf.default_opts(precond=mf.PRECOND_LEARNED, net=net, nn_smooth=omega))
     assert st == mf.OK and info["fallbacks"] == 0
-    M = oracle_learned_preconditioner(p, ref, f)
+    M = nn.learned_preconditioner(p, ref.A, ref.dmask, f, omega=omega)
     zr_min = []
 
     def M_checked(r):
@@ -204,15 +186,16 @@ def test_flexible_cg_with_a_random_network_matches_the_oracle(mf):
         return z
     orc = krylov.fcg(ref.Auu, ref.bu, M_checked, tol=1e-6, max_iter=2000)
     assert orc.converged and min(zr_min) > 0
-    # the network is not the Jacobi step: it changes the iteration count
-    jac = krylov.fcg(ref.Auu, ref.bu, krylov.jacobi(ref.Auu), tol=1e-6, max_iter=2000)
-    print(f"\n[nn-parity] FCG iterations: GPU {info['iters']}, oracle {orc.iters}, "
-          f"oracle Jacobi {jac.iters}", flush=True)
-    assert orc.iters != jac.iters
+    # the network is not the zero network: it changes the iteration count
+    M0 = nn.learned_preconditioner(nn.init_params(seed=0, last_scale=0.0), ref.A, ref.dmask, f, omega=omega)
+    base = krylov.fcg(ref.Auu, ref.bu, M0, tol=1e-6, max_iter=2000)
+    print(f"\n[nn-parity] FCG iterations (w {omega}): GPU {info['iters']}, oracle {orc.iters}, "
+          f"oracle zero network {base.iters}", flush=True)
+    assert orc.iters != base.iters
     assert abs(info["iters"] - orc.iters) <= max(3, orc.iters // 20)
     x64 = torch.zeros(k.size, dtype=torch.float64, device="cuda")
     st, info = mf.cg_solve_f64(g, b.double(), x64, mf.default_opts(
-        tol=1e-9, precision=mf.FP32_IR, precond=mf.PRECOND_LEARNED, net=net))
+        tol=1e-9, precision=mf.FP32_IR, precond=mf.PRECOND_LEARNED, net=net, nn_smooth=omega))
     assert st == mf.OK
     pref = ref.direct()
     err = np.linalg.norm(x64.cpu().numpy() - pref) / np.linalg.norm(pref)
