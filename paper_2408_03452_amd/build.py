@@ -24,6 +24,10 @@ SOURCES = ["api.hip", "stencil.hip", "vec.hip", "nn.hip", "batched.hip"]
 
 # Packed FP32 instructions are switched off for all device code.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Per-source device flags. nn.hip: keep MFMA accumulators in ordinary VGPRs
+# (the convolutions' epilogues read them with VALU instructions; in AGPRs each
+# value would first be copied out).
+SOURCE_FLAGS = {"nn.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
           "-Wno-unused-command-line-argument", f"-I{INCLUDE}", f"-I{CSRC}"]
 
@@ -37,7 +41,7 @@ def hipcc() -> str:
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *COMMON, *DEVICE_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *COMMON, *DEVICE_FLAGS, *SOURCE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

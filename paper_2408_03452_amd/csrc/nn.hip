@@ -82,12 +82,13 @@ constexpr int kWb3 = kWb4 + 2 * 64;
 constexpr int kWb2 = kWb3 + 3 * kPairs * 64;
 constexpr int kWTotal = kWb2 + 3 * kPairs * 64;  // in v8s units
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+// FP32 -> BF16, round to nearest even (v_cvt_pk_bf16_f32: two values at once).
+__device__ __forceinline__ uint32_t pack_bf2(float lo, float hi) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f){lo, hi}, v2bf));
 }
+__device__ __forceinline__ uint16_t f2bf(float f) { return (uint16_t)pack_bf2(f, 0.f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 struct Tile {
@@ -133,78 +134,114 @@ __device__ __forceinline__ void load_halo(const uint16_t* __restrict__ in, const
 }
 
 // Forward and input-gradient convolutions march along x: a block owns a
-// column of TY x TZ output cells and a run of consecutive x planes, and keeps
-// the haloed input planes i-1, i, i+1 (and the one being prefetched) in a ring
-// of four LDS slots, so every input plane is read from memory once per run
-// instead of three times. The next plane is fetched into registers while the
-// matrix cores work on the current one.
-constexpr int kRing = 4;
-constexpr int PCELLS = HY * HZ;  // cells of one haloed plane
+// column of TY x TZ output cells and a run of consecutive x planes, so every
+// input plane is read from memory once per run instead of three times. The
+// haloed input planes go from memory straight into a ring of kRingSlots LDS
+// slots (global_load_lds, no registers in between); plane p is requested at
+// the start of step p - kAhead, so while the matrix cores work on plane i
+// (slots of planes i-1, i, i+1) the planes up to i + kAhead are in flight.
+constexpr int kRingSlots = 6;
+constexpr int kAhead = kRingSlots - 2;  // the slot of plane p + kAhead was last read at step p - 1
+constexpr int PCELLS = HY * HZ;         // cells of one haloed plane
 
 // In LDS the two 16-byte channel halves of a 16-channel cell are stored in the
 // order h ^ ((cell >> 3) & 1): the 16 lanes that read half h of 16 consecutive
 // cells then cover all 64 banks once instead of half of them twice.
 __device__ __forceinline__ int half_pos(int cell, int h) { return cell * 16 + ((h ^ (cell >> 3)) & 1) * 8; }
-//
-// One haloed input plane held in registers between its fetch and its LDS store.
-template <int C>
-struct PlaneRegs {
-    static constexpr int kPer = C == 16 ? (PCELLS * 2 + kThreads - 1) / kThreads : (PCELLS + kThreads - 1) / kThreads;
-    typename std::conditional<C == 16, uint4, uint32_t>::type v[kPer];
-};
 
+typedef __attribute__((address_space(3))) uint16_t lds16;
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Source of the halo cells outside the grid and of the planes past a block's
+// run: 16 zero bytes.
+__device__ __attribute__((aligned(16))) uint32_t g_zero16[4];
+// Destination of the stores of lanes without an output cell: every store
+// instruction is issued by every wave that has a row, so the number of memory
+// operations a wave has in flight is known at each step.
+__device__ __attribute__((aligned(16))) uint32_t g_trash[64 * 4];
+
+// A plane is moved in 16-byte units (16 channels: cell, stored half) or
+// 4-byte units (2 channels: cell), 64 per wave instruction; wave w issues the
+// instructions 4 u + w. A slot holds a whole number of instructions' units
+// (the lanes past the plane's last unit write zeros into the padding).
 template <int C>
-__device__ __forceinline__ void fetch_plane(const uint16_t* __restrict__ in, const Geom& g, int i, int j0,
-                                            int k0, PlaneRegs<C>& R) {
-    const bool iin = i >= 0 && i < g.nx;
+constexpr int plane_units() { return C == 16 ? 2 * PCELLS : PCELLS; }
+template <int C>
+constexpr int plane_groups() { return (plane_units<C>() + 63) / 64; }
+template <int C>
+constexpr int slot_u16() { return plane_groups<C>() * 64 * (C == 16 ? 8 : 2); }  // slot stride, uint16 units
+template <int C>
+__device__ __forceinline__ int dma_per_plane(int w) { return (plane_groups<C>() - w + 3) / 4; }
+
+// Per lane and instruction u: where in an x plane of the input (uint16 units)
+// the unit this lane moves comes from, or -1 for zeros (halo cells outside the
+// grid, padding). Lane data lands at slot + 64 (4 u + w) size + lane size, so
+// the lane of unit c reads the global half that belongs there.
+template <int C>
+__device__ __forceinline__ void dma_offsets(const Geom& g, int j0, int k0, int doff[4]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int u = 0; u < PlaneRegs<C>::kPer; ++u) {
-        const int c = threadIdx.x + u * kThreads;
-        if constexpr (C == 16) {
-            const int cell = c >> 1, half = c & 1;
-            const int hy = cell / HZ, hz = cell % HZ;
-            const int j = j0 - 1 + hy, k = k0 - 1 + hz;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (cell < PCELLS && iin && j >= 0 && j < g.ny && k >= 0 && k < g.nz) {
-                const int64_t l = ((int64_t)i * g.ny + j) * g.nz + k;
-                v = *reinterpret_cast<const uint4*>(in + l * 16 + half * 8);
-            }
-            R.v[u] = v;
-        } else {
-            const int hy = c / HZ, hz = c % HZ;
-            const int j = j0 - 1 + hy, k = k0 - 1 + hz;
-            uint32_t v = 0;
-            if (c < PCELLS && iin && j >= 0 && j < g.ny && k >= 0 && k < g.nz) {
-                const int64_t l = ((int64_t)i * g.ny + j) * g.nz + k;
-                v = *reinterpret_cast<const uint32_t*>(in + l * 2);
-            }
-            R.v[u] = v;
+    for (int u = 0; u < 4; ++u) {
+        const int c = (4 * u + w) * 64 + lane;
+        int off = -1;
+        if (c < plane_units<C>()) {
+            const int cell = C == 16 ? c >> 1 : c;
+            const int j = j0 - 1 + cell / HZ, k = k0 - 1 + cell % HZ;
+            if (j >= 0 && j < g.ny && k >= 0 && k < g.nz)
+                off = C == 16 ? (j * g.nz + k) * 16 + ((c & 1) ^ ((cell >> 3) & 1)) * 8 : (j * g.nz + k) * 2;
         }
+        doff[u] = off;
     }
 }
 
+// Request haloed plane i (zeros if the block does not need it or it lies
+// outside the grid) into an LDS slot.
 template <int C>
-__device__ __forceinline__ void store_plane(const PlaneRegs<C>& R, uint16_t* slot) {
+__device__ __forceinline__ void dma_plane(const uint16_t* __restrict__ in, const Geom& g, int i, bool need,
+                                          const int doff[4], lds16* __restrict__ slot) {
+    const int w = threadIdx.x >> 6;
+    const bool iin = need && i >= 0 && i < g.nx;
+    const uint16_t* base = in + (int64_t)i * g.ny * g.nz * C;
 #pragma unroll
-    for (int u = 0; u < PlaneRegs<C>::kPer; ++u) {
-        const int c = threadIdx.x + u * kThreads;
-        if constexpr (C == 16) {
-            // 8-byte channel quad q of cell `cell` sits at quad position q ^ swz(cell)
-            if (c < PCELLS * 2) {
-                const int cell = c >> 1, half = c & 1;
-                *reinterpret_cast<uint4*>(slot + half_pos(cell, half)) = R.v[u];
-            }
-        } else {
-            if (c < PCELLS) *reinterpret_cast<uint32_t*>(slot + c * 2) = R.v[u];
-        }
+    for (int u = 0; u < 4; ++u) {
+        const int grp = 4 * u + w;
+        if (grp >= plane_groups<C>()) break;
+        const void* src = iin && doff[u] >= 0 ? (const void*)(base + doff[u]) : (const void*)g_zero16;
+        if constexpr (C == 16) __builtin_amdgcn_global_load_lds(src, (lds_void*)(slot + grp * 64 * 8), 16, 0, 0);
+        else __builtin_amdgcn_global_load_lds(src, (lds_void*)(slot + grp * 64 * 2), 4, 0, 0);
     }
 }
 
+// s_waitcnt vmcnt(n): wait until at most n vector memory operations of this
+// wave are in flight (they complete in issue order). n is wave-uniform.
+#define MFFV_VMCNT(n) ((n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8))
+__device__ __forceinline__ void wait_vmcnt(int n) {
+    switch (n < 0 ? 0 : n) {
+#define MFFV_WAIT_CASE(n) case n: __builtin_amdgcn_s_waitcnt(MFFV_VMCNT(n)); break;
+        MFFV_WAIT_CASE(0) MFFV_WAIT_CASE(1) MFFV_WAIT_CASE(2) MFFV_WAIT_CASE(3) MFFV_WAIT_CASE(4)
+        MFFV_WAIT_CASE(5) MFFV_WAIT_CASE(6) MFFV_WAIT_CASE(7) MFFV_WAIT_CASE(8) MFFV_WAIT_CASE(9)
+        MFFV_WAIT_CASE(10) MFFV_WAIT_CASE(11) MFFV_WAIT_CASE(12) MFFV_WAIT_CASE(13) MFFV_WAIT_CASE(14)
+        MFFV_WAIT_CASE(15) MFFV_WAIT_CASE(16) MFFV_WAIT_CASE(17) MFFV_WAIT_CASE(18) MFFV_WAIT_CASE(19)
+        MFFV_WAIT_CASE(20) MFFV_WAIT_CASE(21) MFFV_WAIT_CASE(22) MFFV_WAIT_CASE(23)
+#undef MFFV_WAIT_CASE
+        default: __builtin_amdgcn_s_waitcnt(MFFV_VMCNT(24)); break;
+    }
+}
+#undef MFFV_VMCNT
+
+// Workgroup barrier without a memory fence: the LDS data the waves exchange
+// arrives by global_load_lds, whose completion each wave waits for itself
+// (wait_vmcnt) before the barrier. The asm's memory clobber keeps the compiler
+// from moving memory accesses across it.
+__device__ __forceinline__ void ring_barrier() { asm volatile("s_barrier" ::: "memory"); }
+
+// Row rotations have a source for every lane, so bound_ctrl changes nothing;
+// set, it lets the compiler fold the move into the add that uses it.
 __device__ __forceinline__ float dpp_ror1(float v) {   // lane i of each 16-lane row gets lane i - 1 (mod 16)
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x121, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x121, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float dpp_rol1(float v) {   // lane i of each 16-lane row gets lane i + 1 (mod 16)
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x12f, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x12f, 0xf, 0xf, true));
 }
 
 // Where lane (q, n) reads the B operand of (dx, dy) group pair P: group
@@ -226,14 +263,16 @@ __device__ __forceinline__ SlabAt slab_at(int P) {
     return SlabAt{g / 3, half_pos(row + n + 1, q & 1), half_pos(row + hz, q & 1)};
 }
 
-__device__ __forceinline__ const v8s& slab(const uint16_t* const p[3], const SlabAt& a, int t) {
-    return *reinterpret_cast<const v8s*>(p[a.dx] + (t < 4 ? a.off + 256 * t : a.halo));
+// base: the ring; so[d]: offset of the slot of plane i - 1 + d (uint16 units).
+__device__ __forceinline__ v8s slab(const lds16* base, const int so[3], const SlabAt& a, int t) {
+    typedef __attribute__((address_space(3))) const v8s lds_v8s;
+    return *reinterpret_cast<lds_v8s*>(base + so[a.dx] + (t < 4 ? a.off + 256 * t : a.halo));
 }
 
 // One wave's 64-cell output row of a 16 -> 16 convolution (z taps on the
 // output side): lane (q, n) ends with output channels 4q..4q+3 of cell n of
 // each of the four tiles. wr: 15 operands, index 3 P + dz + 1.
-__device__ __forceinline__ void conv_row16(const uint16_t* const p[3], const v8s* wr, v4f y[4]) {
+__device__ __forceinline__ void conv_row16(const lds16* base, const int so[3], const v8s* wr, v4f y[4]) {
     const int n = threadIdx.x & 15;
     v4f Q[4][3], H[2];
 #pragma unroll
@@ -241,21 +280,33 @@ __device__ __forceinline__ void conv_row16(const uint16_t* const p[3], const v8s
 #pragma unroll
         for (int d = 0; d < 3; ++d) Q[t][d] = v4f{0.f, 0.f, 0.f, 0.f};
     H[0] = H[1] = v4f{0.f, 0.f, 0.f, 0.f};
+    // the next pair's slabs are read while the matrix cores work on this
+    // pair's (two sets in registers; the scheduling barriers keep the
+    // compiler from hoisting more and running out of registers)
+    v8s B[2][5];
+    {
+        const SlabAt at = slab_at(0);
+#pragma unroll
+        for (int t = 0; t < 5; ++t) B[0][t] = slab(base, so, at, t);
+    }
 #pragma unroll
     for (int P = 0; P < kPairs; ++P) {
-        // keep one pair's slabs in flight: the scheduler would otherwise hoist
-        // every pair's loads and run out of registers
         __builtin_amdgcn_sched_barrier(0);
-        const SlabAt at = slab_at(P);
-        v8s B[5];
+        const int cur = P & 1;
+        if (P + 1 < kPairs) {
+            const SlabAt at = slab_at(P + 1);
 #pragma unroll
-        for (int t = 0; t < 5; ++t) B[t] = slab(p, at, t);
+            for (int t = 0; t < 5; ++t) B[cur ^ 1][t] = slab(base, so, at, t);
+        }
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int d = 0; d < 3; ++d) Q[t][d] = mfma32(wr[3 * P + d], B[t], Q[t][d]);
-        H[0] = mfma32(wr[3 * P + 0], B[4], H[0]);   // dz = -1 at the cell before the row (column 15)
-        H[1] = mfma32(wr[3 * P + 2], B[4], H[1]);   // dz = +1 at the cell after the row (column 0)
+            for (int d = 0; d < 3; ++d) Q[t][d] = mfma32(wr[3 * P + d], B[cur][t], Q[t][d]);
+        H[0] = mfma32(wr[3 * P + 0], B[cur][4], H[0]);   // dz = -1 at the cell before the row (column 15)
+        H[1] = mfma32(wr[3 * P + 2], B[cur][4], H[1]);   // dz = +1 at the cell after the row (column 0)
+        // the next pair's reads first, then this pair's products
+        if (P + 1 < kPairs) __builtin_amdgcn_sched_group_barrier(0x100, 5, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 14, 0);
     }
     // y[z] = Q_-1[z-1] + Q_0[z] + Q_+1[z+1] across the 16-lane rows of cells
 #pragma unroll
@@ -274,7 +325,7 @@ __device__ __forceinline__ void conv_row16(const uint16_t* const p[3], const v8s
 // meets zero weights); plane dx lies dx slots further (the ring's first two
 // slots are mirrored past its end). Computed once per kernel: decoding the
 // taps per lane in the loop costs more than the matrix work.
-constexpr int SLOT2 = PCELLS * 2;
+constexpr int SLOT2 = slot_u16<2>();
 __device__ __forceinline__ void tap_offsets2(int toff[8]) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int n = lane & 15, q = lane >> 4;
@@ -291,7 +342,7 @@ __device__ __forceinline__ void tap_offsets2(int toff[8]) {
 // One wave's 64-cell output row of a 2 -> 16 convolution: K = 64 (tap,
 // channel) pairs in two products per tile, k = 32 s + 8 q + v, tap = k / 2,
 // channel = k % 2; each lane gathers the 4-byte cells of its four taps.
-__device__ __forceinline__ void conv_row2(const uint16_t* base, const int toff[8], const v8s* wr, v4f y[4]) {
+__device__ __forceinline__ void conv_row2(const lds16* base, const int toff[8], const v8s* wr, v4f y[4]) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) y[t] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -300,7 +351,8 @@ __device__ __forceinline__ void conv_row2(const uint16_t* base, const int toff[8
         for (int t = 0; t < 4; ++t) {
             uint32_t c[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) c[j] = *reinterpret_cast<const uint32_t*>(base + toff[4 * s + j] + 32 * t);
+            for (int j = 0; j < 4; ++j)
+                c[j] = *reinterpret_cast<__attribute__((address_space(3))) const uint32_t*>(base + toff[4 * s + j] + 32 * t);
             y[t] = mfma32(wr[s], __builtin_bit_cast(v8s, make_uint4(c[0], c[1], c[2], c[3])), y[t]);
         }
     }
@@ -310,20 +362,30 @@ __device__ __forceinline__ void conv_row2(const uint16_t* base, const int toff[8
 // the three z offsets (row dz + 1), so one product per pair and tile gives
 // Q_dz for every dz; the output is Q_-1[z-1] + Q_0[z] + Q_+1[z+1]. Returns, on
 // lanes 0..15, the outputs of cells n, n+16, n+32, n+48 of the row.
-__device__ __forceinline__ void conv_last_row(const uint16_t* const p[3], const v8s* wz, float y[4]) {
+__device__ __forceinline__ void conv_last_row(const lds16* base, const int so[3], const v8s* wz, float y[4]) {
     const int n = threadIdx.x & 15;
     v4f Q[5];
 #pragma unroll
     for (int t = 0; t < 5; ++t) Q[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    v8s B[2][5];
+    {
+        const SlabAt at = slab_at(0);
+#pragma unroll
+        for (int t = 0; t < 5; ++t) B[0][t] = slab(base, so, at, t);
+    }
 #pragma unroll
     for (int P = 0; P < kPairs; ++P) {
         __builtin_amdgcn_sched_barrier(0);
-        const SlabAt at = slab_at(P);
-        v8s B[5];
+        const int cur = P & 1;
+        if (P + 1 < kPairs) {
+            const SlabAt at = slab_at(P + 1);
 #pragma unroll
-        for (int t = 0; t < 5; ++t) B[t] = slab(p, at, t);
+            for (int t = 0; t < 5; ++t) B[cur ^ 1][t] = slab(base, so, at, t);
+        }
 #pragma unroll
-        for (int t = 0; t < 5; ++t) Q[t] = mfma32(wz[P], B[t], Q[t]);
+        for (int t = 0; t < 5; ++t) Q[t] = mfma32(wz[P], B[cur][t], Q[t]);
+        if (P + 1 < kPairs) __builtin_amdgcn_sched_group_barrier(0x100, 5, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 5, 0);
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -359,20 +421,154 @@ struct ConvArgs {
     int run;                // x planes per block
 };
 
-__device__ __forceinline__ uint32_t pack_bf2(float lo, float hi) {
-    return (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
+
+// Slot after slot x of the ring.
+__device__ __forceinline__ int ring_next(int x, int d) { return x + d >= kRingSlots ? x + d - kRingSlots : x + d; }
+
+// One step of the x march: request plane i + kAhead, then compute output plane
+// i from the slots of planes i-1, i, i+1 (sl: slot of plane i-1) and store it.
+// The LDS reads go through rd and the request through rq, both restrict (they
+// address different slots): the compiler then does not make the reads wait
+// for the request.
+template <int C, int MODE, int NW>
+__device__ __forceinline__ void conv_step(const Geom& g, const ConvArgs& a, const v8s (&wr)[NW],
+                                          const float (&bias)[4], float s, const int (&toff)[C == 2 ? 8 : 1],
+                                          const int (&doff)[4], int i, int i1, int j0, int k0, int sl,
+                                          const lds16* __restrict__ rd, lds16* __restrict__ rq) {
+    constexpr int SLOT = slot_u16<C>();
+    constexpr bool kLast = MODE == kFinal || MODE == kPrecond;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m = lane & 15, rg = lane >> 4;
+    const int j = j0 + w;
+    const float floor_act = a.relu ? 0.f : -INFINITY;   // hidden activation: max(x, floor)
+    const uint32_t keep_all = a.relu ? 0u : 1u;          // input gradient without a ReLU mask
+    const int64_t row = ((int64_t)i * g.ny + j) * g.nz;
+    // The epilogue's own operands are loaded first, by every lane from a
+    // clamped (always valid) address and without branches: their latency then
+    // overlaps the matrix work, and since memory operations complete in issue
+    // order, waiting for them never waits for the plane requests issued after.
+    float er[4], ed[4], er1[4];
+    uint32_t em[4];
+    uint2 eb[4];
+    {
+        const int64_t rowc = ((int64_t)i * g.ny + min(j, g.ny - 1)) * g.nz;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const int64_t l = rowc + min(k0 + mt * 16 + m, g.nz - 1);
+            if (MODE == kPrecond) {
+                er[mt] = a.r[l];
+                ed[mt] = a.dinv[l];
+                em[mt] = a.dmask[l];
+                er1[mt] = a.r1 ? a.r1[l] : 0.f;
+            }
+            if (MODE == kGradMasked) eb[mt] = *reinterpret_cast<const uint2*>(a.below + l * 16 + rg * 4);
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+        const int p = i + kAhead, sp = ring_next(sl, kAhead + 1);
+        dma_plane<C>(a.in, g, p, p <= i1, doff, rq + sp * SLOT);
+        if (C == 2 && sp < 2) dma_plane<C>(a.in, g, p, p <= i1, doff, rq + (sp + kRingSlots) * SLOT);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (j >= g.ny) return;
+    int so[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) so[d] = (C == 2 ? sl + d : ring_next(sl, d)) * SLOT;
+    if constexpr (kLast) {
+        float y[4];
+        conv_last_row(rd, so, wr, y);
+        if (rg == 0) {
+            float out[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const float v = y[mt] + bias[0];
+                if (MODE == kFinal) {
+                    out[mt] = v;
+                } else {
+                    // z = dinv r + C, or between the sweeps z2 = omega dinv r + dinv r1 + C
+                    const float di = ed[mt];
+                    const float jac = a.r1 ? a.omega * di * er[mt] + di * er1[mt] : di * er[mt];
+                    out[mt] = em[mt] ? 0.f : jac + s * sqrtf(di) * v;
+                }
+            }
+            if (k0 + TZ <= g.nz) {
+                float* dst = a.out32 + row + k0 + m;
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) dst[16 * mt] = out[mt];
+            } else {
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) {
+                    const int k = k0 + mt * 16 + m;
+                    float* dst = k < g.nz ? a.out32 + row + k : reinterpret_cast<float*>(g_trash) + lane;
+                    *dst = out[mt];
+                }
+            }
+        }
+    } else {
+        v4f acc[4];
+        if constexpr (C == 16) conv_row16(rd, so, wr, acc);
+        else conv_row2(rd + so[0], toff, wr, acc);
+        uint2 out[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            float h[4];
+            // Both epilogues are branch-free: hipcc (ROCm 7.2) miscompiled a
+            // per-lane select between the accumulator and 0 written with a
+            // branch here (the accumulator register was cleared on every lane).
+            if (MODE == kHiddenRelu) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) h[q] = fmaxf(acc[mt][q] + bias[q], floor_act);
+            } else {
+                const uint2 bl = eb[mt];
+                // ReLU mask: keep the gradient where the activation below is > 0
+                // (positive BF16 values are positive as signed 16-bit integers)
+                const uint32_t bw[4] = {bl.x << 16, bl.x & 0xffff0000u, bl.y << 16, bl.y & 0xffff0000u};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t pos = (uint32_t)((int32_t)bw[q] > 0);
+                    const uint32_t keep = 0u - (pos | keep_all);
+                    h[q] = __uint_as_float(__float_as_uint(acc[mt][q]) & keep);
+                }
+            }
+            out[mt] = make_uint2(pack_bf2(h[0], h[1]), pack_bf2(h[2], h[3]));
+        }
+        if (k0 + TZ <= g.nz) {
+            uint2* dst = reinterpret_cast<uint2*>(a.out16 + (row + k0 + m) * 16 + rg * 4);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) dst[64 * mt] = out[mt];  // 16 cells further per tile
+        } else {
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const int k = k0 + mt * 16 + m;
+                uint2* dst = k < g.nz ? reinterpret_cast<uint2*>(a.out16 + (row + k) * 16 + rg * 4)
+                                      : reinterpret_cast<uint2*>(g_trash) + lane;
+                *dst = out[mt];
+            }
+        }
+    }
 }
 
 // grid: ncols * ceil(nx / run) blocks of kThreads.
 template <int C, int MODE>
 __global__ __launch_bounds__(kThreads) void conv3d(Geom g, ConvArgs a) {
-    // 2-channel input: the ring's slots 0 and 1 are mirrored in slots 4 and 5, so
+    // 2-channel input: the ring's slots 0 and 1 are mirrored past its end, so
     // that planes i-1, i, i+1 always sit in three consecutive slots
-    constexpr int kSlots = C == 2 ? kRing + 2 : kRing;
-    __shared__ __attribute__((aligned(16))) uint16_t lds[kSlots * PCELLS * C];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int m = lane & 15, rg = lane >> 4;
-    const int col = blockIdx.x % a.ncols, chunk = blockIdx.x / a.ncols;
+    constexpr int kSlots = C == 2 ? kRingSlots + 2 : kRingSlots;
+    constexpr int SLOT = slot_u16<C>();
+    __shared__ __attribute__((aligned(16))) uint16_t lds[kSlots * SLOT];
+    lds16* ring = (lds16*)lds;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int rg = lane >> 4;
+    // XCD-aware order: blocks are dealt to the 8 XCDs in turn; block b takes
+    // work item x q + min(x, rem) + b / 8 (x = b % 8), so each XCD marches a
+    // contiguous range of columns and the y halo rows its neighbours share are
+    // found in its own L2
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int xcd = b & 7, nq = nb >> 3, nrem = nb & 7;
+    const int item = xcd * nq + min(xcd, nrem) + (b >> 3);
+    const int col = item % a.ncols, chunk = item / a.ncols;
     const int j0 = (col / a.ntk) * TY, k0 = (col % a.ntk) * TZ;
     const int i0 = chunk * a.run;
     const int i1 = min(g.nx, i0 + a.run);
@@ -390,122 +586,40 @@ __global__ __launch_bounds__(kThreads) void conv3d(Geom g, ConvArgs a) {
         bias[0] = a.bias[0];
     }
     const float s = (MODE == kPrecond) ? *a.sscale : 0.f;
-    const float floor_act = a.relu ? 0.f : -INFINITY;   // hidden activation: max(x, floor)
-    const uint32_t keep_all = a.relu ? 0u : 1u;          // input gradient without a ReLU mask
-    // slot of plane p: (p - i0 + 1) & 3
-    {
-        // the first three planes: all loads in flight before the first LDS store
-        PlaneRegs<C> R0, R1, R2;
-        fetch_plane<C>(a.in, g, i0 - 1, j0, k0, R0);
-        fetch_plane<C>(a.in, g, i0, j0, k0, R1);
-        fetch_plane<C>(a.in, g, i0 + 1, j0, k0, R2);
-        store_plane<C>(R0, lds);
-        store_plane<C>(R1, lds + PCELLS * C);
-        store_plane<C>(R2, lds + 2 * PCELLS * C);
-        if constexpr (C == 2) {
-            store_plane<C>(R0, lds + 4 * PCELLS * C);
-            store_plane<C>(R1, lds + 5 * PCELLS * C);
-        }
-    }
-    int toff[C == 2 ? 8 : 1];
+    int toff[C == 2 ? 8 : 1] = {0};
     if constexpr (C == 2) tap_offsets2(toff);
-    __syncthreads();
+    int doff[4];
+    dma_offsets<C>(g, j0, k0, doff);
+    // the planes i0-1 .. i0+kAhead-1 into slots 0 .. kAhead
+#pragma unroll
+    for (int d = 0; d <= kAhead; ++d) {
+        dma_plane<C>(a.in, g, i0 - 1 + d, i0 - 1 + d <= i1, doff, ring + d * SLOT);
+        if (C == 2 && d < 2) dma_plane<C>(a.in, g, i0 - 1 + d, i0 - 1 + d <= i1, doff, ring + (d + kRingSlots) * SLOT);
+    }
+    // Memory operations of this wave, counted from the kernel start: kq per
+    // plane request (a lower bound: the mirror copies are not counted) and,
+    // per step, ks stores; the epilogue loads are not counted either. Every
+    // count used below is at most the true number, so waiting until at most
+    // (issued now - issued up to a plane's request) operations are in flight
+    // always covers that request.
+    const int kq = dma_per_plane<C>(w);
+    const int ks = j < g.ny ? 4 : 0;
+    auto issued_through = [&](int p) {  // operations up to and including plane p's request
+        const int d = p - i0 + 1;
+        return d <= kAhead ? (d + 1) * kq : (kAhead + 1) * kq + (p - kAhead - i0) * (kq + ks) + kq;
+    };
+    wait_vmcnt((kAhead + 1) * kq - issued_through(i0 + 1));
+    ring_barrier();
+    int sl = 0;  // slot of plane i - 1
 #pragma unroll 1
     for (int i = i0; i < i1; ++i) {
-        const bool more = i + 1 < i1;
-        PlaneRegs<C> R;
-        const int64_t row = ((int64_t)i * g.ny + j) * g.nz;
-        // The epilogue's own operands are loaded first, by every lane from a
-        // clamped (always valid) address and without branches: their latency
-        // then overlaps the matrix work, and since memory counters drain in
-        // issue order, waiting for them never waits for the plane fetch below.
-        // (A data-dependent load, e.g. r only where dmask is 0, would put one
-        // memory round trip after another into every plane step.)
-        float er[4], ed[4], er1[4];
-        uint32_t em[4];
-        uint2 eb[4];
-        {
-            const int64_t rowc = ((int64_t)i * g.ny + min(j, g.ny - 1)) * g.nz;
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                const int64_t l = rowc + min(k0 + mt * 16 + m, g.nz - 1);
-                if (MODE == kPrecond) {
-                    er[mt] = a.r[l];
-                    ed[mt] = a.dinv[l];
-                    em[mt] = a.dmask[l];
-                    er1[mt] = a.r1 ? a.r1[l] : 0.f;
-                }
-                if (MODE == kGradMasked) eb[mt] = *reinterpret_cast<const uint2*>(a.below + l * 16 + rg * 4);
-            }
-        }
-        if (more) fetch_plane<C>(a.in, g, i + 2, j0, k0, R);
-        if (j < g.ny) {
-            const uint16_t* p[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) p[d] = lds + ((i - i0 + d) & 3) * PCELLS * C;
-            if constexpr (kLast) {
-                float y[4];
-                conv_last_row(p, wr, y);
-                if (rg == 0) {
-#pragma unroll
-                    for (int mt = 0; mt < 4; ++mt) {
-                        const int k = k0 + mt * 16 + m;
-                        if (k >= g.nz) continue;
-                        const int64_t l = row + k;
-                        const float v = y[mt] + bias[0];
-                        if (MODE == kFinal) {
-                            a.out32[l] = v;
-                        } else {
-                            // z = dinv r + C, or between the sweeps z2 = omega dinv r + dinv r1 + C
-                            const float di = ed[mt];
-                            const float jac = a.r1 ? a.omega * di * er[mt] + di * er1[mt] : di * er[mt];
-                            a.out32[l] = em[mt] ? 0.f : jac + s * sqrtf(di) * v;
-                        }
-                    }
-                }
-            } else {
-            v4f acc[4];
-            if constexpr (C == 16) conv_row16(p, wr, acc);
-            else conv_row2(p[0], toff, wr, acc);
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                const int k = k0 + mt * 16 + m;
-                if (k >= g.nz) continue;
-                const int64_t l = row + k;
-                // Both epilogues are branch-free: hipcc (ROCm 7.2) miscompiled a
-                // per-lane select between the accumulator and 0 written with a
-                // branch here (the accumulator register was cleared on every lane).
-                if (MODE == kHiddenRelu) {
-                    float h[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) h[q] = fmaxf(acc[mt][q] + bias[q], floor_act);
-                    *reinterpret_cast<uint2*>(a.out16 + l * 16 + rg * 4) =
-                        make_uint2(pack_bf2(h[0], h[1]), pack_bf2(h[2], h[3]));
-                } else if (MODE == kGradMasked) {
-                    float h[4];
-                    const uint2 bl = eb[mt];
-                    // ReLU mask: keep the gradient where the activation below is > 0
-                    // (positive BF16 values are positive as signed 16-bit integers)
-                    const uint32_t bw[4] = {bl.x << 16, bl.x & 0xffff0000u, bl.y << 16, bl.y & 0xffff0000u};
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const uint32_t pos = (uint32_t)((int32_t)bw[q] > 0);
-                        const uint32_t keep = 0u - (pos | keep_all);
-                        h[q] = __uint_as_float(__float_as_uint(acc[mt][q]) & keep);
-                    }
-                    *reinterpret_cast<uint2*>(a.out16 + l * 16 + rg * 4) =
-                        make_uint2(pack_bf2(h[0], h[1]), pack_bf2(h[2], h[3]));
-                }
-            }
-            }
-        }
-        if (more) {
-            const int sl = (i - i0 + 3) & 3;
-            store_plane<C>(R, lds + sl * PCELLS * C);
-            if (C == 2 && sl < 2) store_plane<C>(R, lds + (sl + 4) * PCELLS * C);
-        }
-        __syncthreads();
+        conv_step<C, MODE>(g, a, wr, bias, s, toff, doff, i, i1, j0, k0, sl, ring, ring);
+        // plane i + 2 must have arrived, in every wave, before the barrier
+        wait_vmcnt((kAhead + 1) * kq + (i - i0 + 1) * (kq + ks) - issued_through(i + 2));
+        ring_barrier();
+        sl = ring_next(sl, 1);
     }
+    wait_vmcnt(0);  // no LDS request outlives the block
 }
 
 // Network input channels (rh, rh * feat) in BF16. For inference rh is the
@@ -527,7 +641,7 @@ __global__ __launch_bounds__(kThreads) void nn_input(int64_t n, const float* r, 
     for (int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x; l < n; l += stride) {
         float rh = dinv ? sqrtf(dinv[l]) * r[l] * inv_s : r[l];
         if (dmask && dmask[l]) rh = 0.f;
-        const uint32_t v = (uint32_t)f2bf(rh) | ((uint32_t)f2bf(rh * feat[l]) << 16);
+        const uint32_t v = pack_bf2(rh, rh * feat[l]);
         reinterpret_cast<uint32_t*>(x0)[l] = v;
     }
 }
