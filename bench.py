@@ -11,8 +11,9 @@ GPU, by the library's own kernels, on held-in realisations (not timed). Each
 held-out realisation is also solved by plain CG and by Jacobi-PCG to the same
 true residual. ``value`` is the median learned-FCG time over the timed steps;
 the line also carries both other methods, the network layers' per-launch
-times against the dense BF16 matrix-core peak (roofline), and each result's
-field error against the FP64 oracle on 64^3 crop problems.
+times, the hidden convolution against its roofline (HBM: at 216 FLOP per byte
+it lies below the BF16 ridge point; its matrix-core fraction is given too),
+and each result's field error against the FP64 oracle on 64^3 crop problems.
 
 Further sections (each a key of the JSON line): the 256^3 correlated
 log-normal solve and the stencil kernels against the HBM peak and their
@@ -81,8 +82,13 @@ METRIC = "time to rel-resid 1e-6 (learned FCG vs plain CG); stencil-apply HBM GB
 MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix-core peak
 # algorithmic FLOPs per cell of each network layer: 27 taps x cin x cout x 2
 NN_LAYER_FLOP_PER_CELL = (27 * 2 * 16 * 2, 27 * 16 * 16 * 2, 27 * 16 * 16 * 2, 27 * 16 * 1 * 2)
+# algorithmic HBM bytes per cell of a hidden layer: 16 BF16 channels in, 16 out.
+# At 13824 FLOP per 64 bytes (216 FLOP/B) the layer sits below the MI355X ridge
+# point (2500 TFLOP/s / 8 TB/s = 312 FLOP/B): its roofline is the HBM one.
+NN_HIDDEN_BYTES_PER_CELL = 64
 # HBM bytes per launch of the hidden convolution on 128^3 from rocprofv3
-# FETCH_SIZE and WRITE_SIZE (scaled like the stencil counters), or None
+# FETCH_SIZE and WRITE_SIZE (FETCH_SIZE scaled by the same counter on a copy of
+# known size), or None
 NN_TRAFFIC = {"hidden": None}
 # launch shapes the stencil autotuner reports: the CG kernels' and the apply's own
 LAUNCH_KEYS = ("ci", "remap", "seg", "vec", "blocks", "apply_ci", "apply_remap", "apply_seg", "apply_blocks")
@@ -976,11 +982,13 @@ def main(argv=None):
     layers = tm.get("nn_layer_us", [0.0] * 4)
     hidden_us = 0.5 * (layers[1] + layers[2])
     hidden_tflops = NN_LAYER_FLOP_PER_CELL[1] * n3 / (hidden_us * 1e-6) / 1e12 if hidden_us > 0 else 0.0
+    hidden_gbs = NN_HIDDEN_BYTES_PER_CELL * n3 / (hidden_us * 1e-6) / 1e9 if hidden_us > 0 else 0.0
     head["network_layers"] = [
         {"layer": i + 1, "us": layers[i], "flop_per_cell": NN_LAYER_FLOP_PER_CELL[i],
          "TFLOPs": NN_LAYER_FLOP_PER_CELL[i] * n3 / (layers[i] * 1e-6) / 1e12 if layers[i] > 0 else 0.0}
         for i in range(4)]
-    log(f"network layers (us): {[round(v, 1) for v in layers]}; hidden layer {hidden_tflops:.0f} TFLOP/s")
+    log(f"network layers (us): {[round(v, 1) for v in layers]}; hidden layer {hidden_gbs:.0f} GB/s, "
+        f"{hidden_tflops:.0f} TFLOP/s")
 
     c1 = tsteps = face_res = None
     k1 = None
@@ -1043,16 +1051,19 @@ def main(argv=None):
         "roofline": {
             "kernel": "conv3d<16,0> (hidden 16->16 3^3 convolution + ReLU of the network inside flexible "
                       "CG, BF16 MFMA with FP32 accumulation)",
-            "bound": "mfma",
-            "achieved": hidden_tflops,
-            "peak": MFMA_BF16_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": hidden_tflops / MFMA_BF16_PEAK_TFLOPS,
+            "bound": "hbm",
+            "achieved": hidden_gbs,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": hidden_gbs / HBM_PEAK_GBPS,
             "traffic": NN_TRAFFIC["hidden"]["bytes"] if NN_TRAFFIC["hidden"] else None,
             "traffic_source": NN_TRAFFIC["hidden"]["profile"] if NN_TRAFFIC["hidden"] else None,
-            "flop_per_cell": NN_LAYER_FLOP_PER_CELL[1],
+            "bytes_per_cell": NN_HIDDEN_BYTES_PER_CELL,
             "cells_per_launch": n3,
             "launch_us": hidden_us,
+            "flop_per_cell": NN_LAYER_FLOP_PER_CELL[1],
+            "mfma_tflops": hidden_tflops,
+            "mfma_frac": hidden_tflops / MFMA_BF16_PEAK_TFLOPS,
         },
         "c1_256cube": c1,
         "large": large,

@@ -60,9 +60,14 @@ struct StencilIO {
     real* pout = nullptr;
     MergedState* ms = nullptr;
     int parity = 0;
+    float omega = 0.f;           // kSweep1 / kSweep2: the sweeps' weight
 };
 
-enum StencilMode { kApply = 0, kFusedCg = 1, kResidual = 2, kMergedCg = 3 };
+// kSweep1 / kSweep2: the damped Jacobi sweeps around the learned
+// preconditioner (FP32, Cartesian grids), each one pass over the operator:
+//   kSweep1: out = src - A (omega dinv src), per-block partials of dinv out^2;
+//   kSweep2: out = src + omega dinv (rres - A src).
+enum StencilMode { kApply = 0, kFusedCg = 1, kResidual = 2, kMergedCg = 3, kSweep1 = 4, kSweep2 = 5 };
 
 hipError_t launch_stencil_f32(int mode, const Geom& g, const Coef& c, const StencilIO<float>& io,
                               const March& m, hipStream_t s);

@@ -430,10 +430,43 @@ __device__ __forceinline__ int ring_next(int x, int d) { return x + d >= kRingSl
 // The LDS reads go through rd and the request through rq, both restrict (they
 // address different slots): the compiler then does not make the reads wait
 // for the request.
+// The epilogue's own per-cell operands of one output row (last layer in
+// flexible CG: r, dinv, dmask and the swept residual; input gradient: the
+// activation of the layer below, for its ReLU mask).
+struct EpiIn {
+    float r[4], d[4], r1[4];
+    uint32_t m[4];
+    uint2 b[4];
+};
+
+// Load them for plane i, by every lane from a clamped (always valid) address
+// and without branches. The march loads them one step ahead, after that
+// step's plane request: since memory operations complete in issue order,
+// waiting for them then waits only for requests at least a step old.
+template <int MODE>
+__device__ __forceinline__ void epi_load(const Geom& g, const ConvArgs& a, int i, int j0, int k0, EpiIn& e) {
+    if (MODE != kPrecond && MODE != kGradMasked) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m = lane & 15, rg = lane >> 4;
+    const int64_t rowc = ((int64_t)min(i, g.nx - 1) * g.ny + min(j0 + w, g.ny - 1)) * g.nz;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const int64_t l = rowc + min(k0 + mt * 16 + m, g.nz - 1);
+        if (MODE == kPrecond) {
+            e.r[mt] = a.r[l];
+            e.d[mt] = a.dinv[l];
+            e.m[mt] = a.dmask[l];
+            e.r1[mt] = (a.r1 ? a.r1 : a.r)[l];  // not used without the sweeps
+        }
+        if (MODE == kGradMasked) e.b[mt] = *reinterpret_cast<const uint2*>(a.below + l * 16 + rg * 4);
+    }
+}
+
 template <int C, int MODE, int NW>
 __device__ __forceinline__ void conv_step(const Geom& g, const ConvArgs& a, const v8s (&wr)[NW],
                                           const float (&bias)[4], float s, const int (&toff)[C == 2 ? 8 : 1],
                                           const int (&doff)[4], int i, int i1, int j0, int k0, int sl,
+                                          const EpiIn& cur, EpiIn& nxt,
                                           const lds16* __restrict__ rd, lds16* __restrict__ rq) {
     constexpr int SLOT = slot_u16<C>();
     constexpr bool kLast = MODE == kFinal || MODE == kPrecond;
@@ -443,27 +476,6 @@ __device__ __forceinline__ void conv_step(const Geom& g, const ConvArgs& a, cons
     const float floor_act = a.relu ? 0.f : -INFINITY;   // hidden activation: max(x, floor)
     const uint32_t keep_all = a.relu ? 0u : 1u;          // input gradient without a ReLU mask
     const int64_t row = ((int64_t)i * g.ny + j) * g.nz;
-    // The epilogue's own operands are loaded first, by every lane from a
-    // clamped (always valid) address and without branches: their latency then
-    // overlaps the matrix work, and since memory operations complete in issue
-    // order, waiting for them never waits for the plane requests issued after.
-    float er[4], ed[4], er1[4];
-    uint32_t em[4];
-    uint2 eb[4];
-    {
-        const int64_t rowc = ((int64_t)i * g.ny + min(j, g.ny - 1)) * g.nz;
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            const int64_t l = rowc + min(k0 + mt * 16 + m, g.nz - 1);
-            if (MODE == kPrecond) {
-                er[mt] = a.r[l];
-                ed[mt] = a.dinv[l];
-                em[mt] = a.dmask[l];
-                er1[mt] = a.r1 ? a.r1[l] : 0.f;
-            }
-            if (MODE == kGradMasked) eb[mt] = *reinterpret_cast<const uint2*>(a.below + l * 16 + rg * 4);
-        }
-    }
     __builtin_amdgcn_sched_barrier(0);
     {
         const int p = i + kAhead, sp = ring_next(sl, kAhead + 1);
@@ -471,6 +483,13 @@ __device__ __forceinline__ void conv_step(const Geom& g, const ConvArgs& a, cons
         if (C == 2 && sp < 2) dma_plane<C>(a.in, g, p, p <= i1, doff, rq + (sp + kRingSlots) * SLOT);
     }
     __builtin_amdgcn_sched_barrier(0);
+    epi_load<MODE>(g, a, i + 1, j0, k0, nxt);
+    __builtin_amdgcn_sched_barrier(0);
+    const float* er = cur.r;
+    const float* ed = cur.d;
+    const float* er1 = cur.r1;
+    const uint32_t* em = cur.m;
+    const uint2* eb = cur.b;
     if (j >= g.ny) return;
     int so[3];
 #pragma unroll
@@ -588,6 +607,11 @@ __global__ __launch_bounds__(kThreads) void conv3d(Geom g, ConvArgs a) {
     const float s = (MODE == kPrecond) ? *a.sscale : 0.f;
     int toff[C == 2 ? 8 : 1] = {0};
     if constexpr (C == 2) tap_offsets2(toff);
+    // the weights and scalars above have arrived before any plane is requested:
+    // no wait inside the march then counts them
+    wait_vmcnt(0);
+    EpiIn epi;
+    epi_load<MODE>(g, a, i0, j0, k0, epi);
     int doff[4];
     dma_offsets<C>(g, j0, k0, doff);
     // the planes i0-1 .. i0+kAhead-1 into slots 0 .. kAhead
@@ -611,39 +635,68 @@ __global__ __launch_bounds__(kThreads) void conv3d(Geom g, ConvArgs a) {
     wait_vmcnt((kAhead + 1) * kq - issued_through(i0 + 1));
     ring_barrier();
     int sl = 0;  // slot of plane i - 1
-#pragma unroll 1
-    for (int i = i0; i < i1; ++i) {
-        conv_step<C, MODE>(g, a, wr, bias, s, toff, doff, i, i1, j0, k0, sl, ring, ring);
-        // plane i + 2 must have arrived, in every wave, before the barrier
+    // plane i + 2 must have arrived, in every wave, before the barrier that ends step i
+    auto end_step = [&](int i) {
         wait_vmcnt((kAhead + 1) * kq + (i - i0 + 1) * (kq + ks) - issued_through(i + 2));
         ring_barrier();
         sl = ring_next(sl, 1);
+    };
+    // two steps per trip: the epilogue operands alternate between two register
+    // sets instead of being copied (a copy would wait for the loads at once)
+    EpiIn epi2;
+#pragma unroll 1
+    for (int i = i0; i < i1; i += 2) {
+        conv_step<C, MODE>(g, a, wr, bias, s, toff, doff, i, i1, j0, k0, sl, epi, epi2, ring, ring);
+        end_step(i);
+        if (i + 1 < i1) {
+            conv_step<C, MODE>(g, a, wr, bias, s, toff, doff, i + 1, i1, j0, k0, sl, epi2, epi, ring, ring);
+            end_step(i + 1);
+        }
     }
     wait_vmcnt(0);  // no LDS request outlives the block
 }
 
-// Network input channels (rh, rh * feat) in BF16. For inference rh is the
-// Jacobi-scaled residual sqrt(dinv) r / s with s^2 = sum(dinv r^2) / n_U, the
-// sum taken from the phase-B partials pb (every block sums them; block 0 keeps
-// s for the last layer); for training rh = r is given already scaled.
-__global__ __launch_bounds__(kThreads) void nn_input(int64_t n, const float* r, const float* dinv,
-                                                     const float* feat, const float* pb, int nb,
-                                                     float n_u, float* sscale, uint16_t* x0,
-                                                     const uint8_t* dmask) {
+// The network's scale of a residual from the partials pb of its
+// dinv-weighted square (one block, fixed order): scale[0] = s =
+// sqrt(sum(dinv r^2) / n_U), scale[1] = 1 / s (both 0 for a zero residual).
+__global__ __launch_bounds__(kThreads) void nn_scale(const float* pb, int nb, float n_u, float* scale) {
     __shared__ float red[kThreads / kWave];
-    float inv_s = 1.f;
-    if (pb) {
-        const float rr = sum_partials(pb, nb, red);
-        inv_s = rr > 0.f ? sqrtf(n_u / rr) : 0.f;
-        if (first_thread()) *sscale = rr > 0.f ? sqrtf(rr / n_u) : 0.f;
+    const float rr = sum_partials(pb, nb, red);
+    if (threadIdx.x == 0) {
+        scale[0] = rr > 0.f ? sqrtf(rr / n_u) : 0.f;
+        scale[1] = rr > 0.f ? sqrtf(n_u / rr) : 0.f;
     }
+}
+
+// Network input channels (rh, rh * feat) in BF16. For inference rh is the
+// Jacobi-scaled residual sqrt(dinv) r / s (inv_s: the device scalar 1 / s);
+// for training (dinv NULL) rh = r is given already scaled. Four cells per
+// thread where n allows (every array is 16-byte aligned).
+__global__ __launch_bounds__(kThreads) void nn_input(int64_t n, const float* r, const float* dinv,
+                                                     const float* feat, const float* inv_s_dev, uint16_t* x0,
+                                                     const uint8_t* dmask) {
+    const float inv_s = inv_s_dev ? *inv_s_dev : 1.f;
     const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x; l < n; l += stride) {
-        float rh = dinv ? sqrtf(dinv[l]) * r[l] * inv_s : r[l];
-        if (dmask && dmask[l]) rh = 0.f;
-        const uint32_t v = pack_bf2(rh, rh * feat[l]);
-        reinterpret_cast<uint32_t*>(x0)[l] = v;
+    auto one = [&](float rv, float dv, float fv, bool masked) -> uint32_t {
+        float rh = dinv ? sqrtf(dv) * rv * inv_s : rv;
+        if (masked) rh = 0.f;
+        return pack_bf2(rh, rh * fv);
+    };
+    int64_t l0 = 0;
+    if (n % 4 == 0) {
+        for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n / 4; e += stride) {
+            const float4 rv = reinterpret_cast<const float4*>(r)[e];
+            const float4 fv = reinterpret_cast<const float4*>(feat)[e];
+            const float4 dv = dinv ? reinterpret_cast<const float4*>(dinv)[e] : make_float4(1.f, 1.f, 1.f, 1.f);
+            const uint32_t mk = dmask ? reinterpret_cast<const uint32_t*>(dmask)[e] : 0u;
+            reinterpret_cast<uint4*>(x0)[e] =
+                make_uint4(one(rv.x, dv.x, fv.x, mk & 0xffu), one(rv.y, dv.y, fv.y, mk & 0xff00u),
+                           one(rv.z, dv.z, fv.z, mk & 0xff0000u), one(rv.w, dv.w, fv.w, mk & 0xff000000u));
+        }
+        l0 = n;
     }
+    for (int64_t l = l0 + (int64_t)blockIdx.x * kThreads + threadIdx.x; l < n; l += stride)
+        reinterpret_cast<uint32_t*>(x0)[l] = one(r[l], dinv ? dinv[l] : 1.f, feat[l], dmask && dmask[l]);
 }
 
 // The damped Jacobi sweeps around the network (elementwise parts; the
@@ -1000,6 +1053,8 @@ struct mffv_net {
     float* y = nullptr;
     float* sw1 = nullptr;     // inference: the Jacobi sweeps' vectors (FP32 cells)
     float* sw2 = nullptr;
+    float* swp = nullptr;     // per-block partials of the first sweep (swp_cap of them)
+    int64_t swp_cap = 0;
     float* t1 = nullptr;      // training scratch (FP32 cells)
     float* t2 = nullptr;
     float* part = nullptr;    // weight-gradient partials
@@ -1042,8 +1097,9 @@ constexpr int kRedBlocks = 1024;
 
 void free_ws(mffv_net* N) {
     nfree(N->x0); nfree(N->h1); nfree(N->h2); nfree(N->h3); nfree(N->g1); nfree(N->g2);
-    nfree(N->dy4); nfree(N->y); nfree(N->t1); nfree(N->t2); nfree(N->sw1); nfree(N->sw2);
+    nfree(N->dy4); nfree(N->y); nfree(N->t1); nfree(N->t2); nfree(N->sw1); nfree(N->sw2); nfree(N->swp);
     N->cap = 0;
+    N->swp_cap = 0;
     N->training_ws = false;
 }
 
@@ -1055,10 +1111,14 @@ int ensure_ws(mffv_net* N, int64_t n, bool training) {
     int rc;
     if ((rc = nalloc(&N->x0, (size_t)cap * 2)) || (rc = nalloc(&N->h1, (size_t)cap * 16)) ||
         (rc = nalloc(&N->h2, (size_t)cap * 16)) || (rc = nalloc(&N->y, (size_t)cap)) ||
-        (rc = nalloc(&N->sw1, (size_t)cap)) || (rc = nalloc(&N->sw2, (size_t)cap))) {
+        (rc = nalloc(&N->sw1, (size_t)cap)) || (rc = nalloc(&N->sw2, (size_t)cap)) ||
+        (rc = nalloc(&N->swp, (size_t)(cap / 256 + 8192)))) {
         free_ws(N);
         return nfail(rc, "network workspace allocation failed");
     }
+    // a stencil launch has at most about n / 256 + nx blocks; grids with more
+    // (very many thin planes) take the unfused sweeps
+    N->swp_cap = cap / 256 + 8192;
     if (training) {
         if ((rc = nalloc(&N->h3, (size_t)cap * 16)) || (rc = nalloc(&N->g1, (size_t)cap * 16)) ||
             (rc = nalloc(&N->g2, (size_t)cap * 16)) || (rc = nalloc(&N->dy4, (size_t)cap * 2)) ||
@@ -1238,7 +1298,7 @@ int loss_pass(mffv_net* N, const Shape& S, const Coef& c, const March& m, const 
     const int64_t n = S.g.n;
     const int nb = nblocks_for(n, kRedBlocks);
     hipLaunchKernelGGL(nn_input, dim3(nb), dim3(kThreads), 0, st, n, r_hat, (const float*)nullptr, feat,
-                       (const float*)nullptr, 0, 1.f, (float*)nullptr, N->x0, dmask);
+                       (const float*)nullptr, N->x0, dmask);
     NHIP(hipGetLastError());
     ConvArgs last{};
     last.out32 = N->y;
@@ -1294,8 +1354,23 @@ int nn_precondition(const mffv_net* Nc, const Geom& g, const Coef& c, const Marc
     const float* rin = r;    // the residual the network sees
     const float* pin = pb;   // and the partials of its dinv-weighted square
     int nbin = nb_b;
-    if (omega > 0.f) {
-        // first sweep: r1 = r - A (omega dinv r), into sw1 (sw2 holds A t)
+    // the sweeps as single passes over the operator (kSweep1 / kSweep2 of the
+    // stencil kernels) when the first one's partials fit
+    const bool fused = (int64_t)m.blocks() <= N->swp_cap;
+    if (omega > 0.f && fused) {
+        // first sweep: r1 = r - A (omega dinv r), into sw1, with the partials of dinv r1^2
+        StencilIO<float> io;
+        io.src = r;
+        io.dinv = dinv;
+        io.omega = omega;
+        io.out = N->sw1;
+        io.partials = N->swp;
+        NHIP(launch_stencil_f32(kSweep1, g, c, io, m, s));
+        rin = N->sw1;
+        pin = N->swp;
+        nbin = m.blocks();
+    } else if (omega > 0.f) {
+        // the same in three kernels: t = omega dinv r into sw1, A t into sw2, r1 into sw1
         hipLaunchKernelGGL(sweep_scale, dim3(nb), dim3(kThreads), 0, s, g.n, r, dinv, dmask, omega, N->sw1);
         NHIP(hipGetLastError());
         StencilIO<float> io;
@@ -1309,8 +1384,10 @@ int nn_precondition(const mffv_net* Nc, const Geom& g, const Coef& c, const Marc
         pin = N->red;
         nbin = nb;
     }
-    hipLaunchKernelGGL(nn_input, dim3(nb), dim3(kThreads), 0, s, g.n, rin, dinv, feat, pin, nbin, n_u, N->sscale,
-                       N->x0, (const uint8_t*)nullptr);
+    hipLaunchKernelGGL(nn_scale, dim3(1), dim3(kThreads), 0, s, pin, nbin, n_u, N->sscale);
+    NHIP(hipGetLastError());
+    hipLaunchKernelGGL(nn_input, dim3(nb), dim3(kThreads), 0, s, g.n, rin, dinv, feat,
+                       (const float*)(N->sscale + 1), N->x0, (const uint8_t*)nullptr);
     NHIP(hipGetLastError());
     ConvArgs last{};
     last.out32 = omega > 0.f ? N->sw2 : z;   // z2 before the second sweep
@@ -1322,11 +1399,18 @@ int nn_precondition(const mffv_net* Nc, const Geom& g, const Coef& c, const Marc
     last.sscale = N->sscale;
     int rc = forward(N, S, false, kPrecond, last, s, layer_ev);
     if (rc || !(omega > 0.f)) return rc;
-    // second sweep: z = z2 + omega dinv (r - A z2), A z2 formed in z first
+    // second sweep: z = z2 + omega dinv (r - A z2)
     StencilIO<float> io;
     io.src = N->sw2;
     io.out = z;
-    NHIP(launch_stencil_f32(kApply, g, c, io, m, s));
+    if (fused) {
+        io.rres = r;
+        io.dinv = dinv;
+        io.omega = omega;
+        NHIP(launch_stencil_f32(kSweep2, g, c, io, m, s));
+        return MFFV_OK;
+    }
+    NHIP(launch_stencil_f32(kApply, g, c, io, m, s));  // A z2 into z, then the update
     hipLaunchKernelGGL(sweep_post, dim3(nb), dim3(kThreads), 0, s, g.n, (const float*)N->sw2, r, dinv, dmask, omega, z);
     NHIP(hipGetLastError());
     return MFFV_OK;
@@ -1387,7 +1471,7 @@ int mffv_net_create(const float* params, mffv_net** out) {
         (rc = nalloc(&N->m, kNParams)) || (rc = nalloc(&N->v, kNParams)) ||
         (rc = nalloc(&N->W, kWTotal)) ||
         (rc = nalloc(&N->part, (size_t)512 * 27 * 256)) || (rc = nalloc(&N->dbpart, (size_t)512 * 16)) ||
-        (rc = nalloc(&N->red, 2 * (size_t)kRedBlocks)) || (rc = nalloc(&N->sscale, 1)) ||
+        (rc = nalloc(&N->red, 2 * (size_t)kRedBlocks)) || (rc = nalloc(&N->sscale, 2)) ||
         (rc = nalloc(&N->loss, 1))) {
         mffv_net_destroy(N);
         return nfail(rc, "network allocation failed");
@@ -1481,7 +1565,7 @@ int mffv_nn_forward(mffv_net* N, int nx, int ny, int nz, const float* r_hat, con
     if ((rc = ensure_ws(N, S.g.n, true))) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(nn_input, dim3(nblocks_for(S.g.n, kRedBlocks)), dim3(kThreads), 0, st, S.g.n, r_hat,
-                       (const float*)nullptr, feat, (const float*)nullptr, 0, 1.f, (float*)nullptr, N->x0,
+                       (const float*)nullptr, feat, (const float*)nullptr, N->x0,
                        (const uint8_t*)nullptr);
     NHIP(hipGetLastError());
     ConvArgs last{};

@@ -319,6 +319,11 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
             const float4 d = ld4(io.dinv + idx);
             v = make_float4(v.x * d.x, v.y * d.y, v.z * d.z, v.w * d.w);
         }
+        if (MODE == kSweep1) {  // the first sweep's step omega dinv r
+            const float4 d = ld4(io.dinv + idx);
+            const float w = io.omega;
+            v = make_float4(w * d.x * v.x, w * d.y * v.y, w * d.z * v.z, w * d.w * v.w);
+        }
         if (rupd) v = axpy4(-alpha_prev, ld4(io.qin + idx), v);
         return v;
     };
@@ -330,6 +335,7 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
     auto S1 = [&](int64_t idx) -> float {
         float v = zsrc[idx];
         if (jz) v *= io.dinv[idx];
+        if (MODE == kSweep1) v = io.omega * io.dinv[idx] * v;
         if (rupd) v -= alpha_prev * io.qin[idx];
         if (use_pold) v += beta * pold[idx];
         return v;
@@ -433,6 +439,18 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
                     d_rq += zc.x * y.x + zc.y * y.y + zc.z * y.z + zc.w * y.w;
                     d_qq += y.x * y.x + y.y * y.y + y.z * y.z + y.w * y.w;
                 }
+            } else if (MODE == kSweep1) {
+                // r1 = r - A (omega dinv r) and the partial sums of dinv r1^2
+                const float4 rv = ld4(io.src + base), d = ld4(io.dinv + base);
+                const float4 r1 = make_float4(rv.x - y.x, rv.y - y.y, rv.z - y.z, rv.w - y.w);
+                st4(io.out + base, r1);
+                dot += d.x * r1.x * r1.x + d.y * r1.y * r1.y + d.z * r1.z * r1.z + d.w * r1.w * r1.w;
+            } else if (MODE == kSweep2) {
+                // z = z2 + omega dinv (r - A z2); sc is z2 at the own cells
+                const float4 rv = ld4(io.rres + base), d = ld4(io.dinv + base);
+                const float w = io.omega;
+                st4(io.out + base, make_float4(sc.x + w * d.x * (rv.x - y.x), sc.y + w * d.y * (rv.y - y.y),
+                                               sc.z + w * d.z * (rv.z - y.z), sc.w + w * d.w * (rv.w - y.w)));
             } else {  // residual r = b - A x
                 float4 bb;
                 if (io.rhs_f64) {
@@ -451,7 +469,7 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
         zc = zp;
     }
 
-    if (MODE == kFusedCg) {
+    if (MODE == kFusedCg || MODE == kSweep1) {
         const float tot = block_sum(dot, red);
         if (threadIdx.x == 0) io.partials[blockIdx.x] = tot;
     } else if (MODE == kMergedCg) {
@@ -504,6 +522,7 @@ __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<
     auto Z = [&](int64_t idx) -> real {
         real v = zsrc[idx];
         if (jz) v *= (real)io.dinv[idx];
+        if (MODE == kSweep1) v = (real)(io.omega * io.dinv[idx]) * v;
         return v;
     };
     auto S = [&](int64_t idx) -> real {
@@ -557,6 +576,12 @@ __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<
                 pnew[base] = sc;
                 io.out[base] = y;
                 dot += sc * y;
+            } else if (MODE == kSweep1) {
+                const real r1 = io.src[base] - y;
+                io.out[base] = r1;
+                dot += (real)io.dinv[base] * r1 * r1;
+            } else if (MODE == kSweep2) {
+                io.out[base] = sc + (real)(io.omega * io.dinv[base]) * (io.rres[base] - y);
             } else {
                 const real bb = io.rhs_f64 ? (real) static_cast<const double*>(io.rhs)[base]
                                            : (real) static_cast<const float*>(io.rhs)[base];
@@ -571,7 +596,7 @@ __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<
         }
     }
 
-    if (MODE == kFusedCg || (MODE == kResidual && io.partials != nullptr)) {
+    if (MODE == kFusedCg || MODE == kSweep1 || (MODE == kResidual && io.partials != nullptr)) {
         const real tot = block_sum(dot, red);
         if (threadIdx.x == 0) io.partials[blockIdx.x] = tot;
     }
@@ -723,7 +748,7 @@ hipError_t launch_stencil_f32(int mode, const Geom& g, const Coef& c, const Sten
             case kApply: return launch_csr<float, kApply>(g, c, io, m, s);
             case kFusedCg: return launch_csr<float, kFusedCg>(g, c, io, m, s);
             case kResidual: return launch_csr<float, kResidual>(g, c, io, m, s);
-            default: return hipErrorInvalidValue;  // the single-reduction form is Cartesian only
+            default: return hipErrorInvalidValue;  // the single-reduction form and the sweeps are Cartesian only
         }
     }
     if (m.vec == 4) {
@@ -731,6 +756,8 @@ hipError_t launch_stencil_f32(int mode, const Geom& g, const Coef& c, const Sten
             case kApply: return launch_v4<kApply>(g, c, io, m, s);
             case kFusedCg: return launch_v4<kFusedCg>(g, c, io, m, s);
             case kMergedCg: return launch_v4<kMergedCg>(g, c, io, m, s);
+            case kSweep1: return launch_v4<kSweep1>(g, c, io, m, s);
+            case kSweep2: return launch_v4<kSweep2>(g, c, io, m, s);
             default: return launch_v4<kResidual>(g, c, io, m, s);
         }
     }
@@ -738,6 +765,8 @@ hipError_t launch_stencil_f32(int mode, const Geom& g, const Coef& c, const Sten
     switch (mode) {
         case kApply: return launch_s<float, kApply>(g, c, io, m, s);
         case kFusedCg: return launch_s<float, kFusedCg>(g, c, io, m, s);
+        case kSweep1: return launch_s<float, kSweep1>(g, c, io, m, s);
+        case kSweep2: return launch_s<float, kSweep2>(g, c, io, m, s);
         default: return launch_s<float, kResidual>(g, c, io, m, s);
     }
 }

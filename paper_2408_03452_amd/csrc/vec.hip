@@ -7,6 +7,8 @@
 // arrive sums them in a fixed order and updates the device-resident scalars.
 #include "launch.hpp"
 
+#include <type_traits>
+
 #include <cstring>
 
 namespace mffv {
@@ -139,7 +141,25 @@ __global__ __launch_bounds__(kThreads) void flex_dots(int64_t n, VecIO<real> io)
     const bool first = st->iterA == 0;
     real zr = 0, zq = 0, jr = 0, jq = 0;
     const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
+    int64_t e0 = 0;
+    if (std::is_same<real, float>::value) {
+        // four cells per load (every vector is 16-byte aligned); the tail below
+        const int64_t n4 = n / 4;
+        for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n4; e += stride) {
+            const float4 r = reinterpret_cast<const float4*>(io.r)[e];
+            const float4 z = reinterpret_cast<const float4*>(io.z)[e];
+            const float4 d = reinterpret_cast<const float4*>(io.dinv)[e];
+            zr += z.x * r.x + z.y * r.y + z.z * r.z + z.w * r.w;
+            jr += d.x * r.x * r.x + d.y * r.y * r.y + d.z * r.z * r.z + d.w * r.w * r.w;
+            if (!first) {
+                const float4 q = reinterpret_cast<const float4*>(io.q)[e];
+                zq += z.x * q.x + z.y * q.y + z.z * q.z + z.w * q.w;
+                jq += d.x * r.x * q.x + d.y * r.y * q.y + d.z * r.z * q.z + d.w * r.w * q.w;
+            }
+        }
+        e0 = n4 * 4;
+    }
+    for (int64_t e = e0 + (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
         const real r = io.r[e], z = io.z[e], d = (real)io.dinv[e];
         zr += z * r;
         jr += d * r * r;

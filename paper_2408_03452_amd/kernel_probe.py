@@ -15,7 +15,10 @@ algorithmic bytes.
 With --network it runs instead, on the channelised 128^3 workload, 10
 forward passes of the learned preconditioner's network (seeded random
 parameters of the trained network's scale) on a unit-RMS random input and
-the same 5 copies.
+the same 5 copies. With --learned it runs 30 iterations of flexible CG with
+that network as the preconditioner (between the two Jacobi sweeps) on
+held-out channelised realisation 3500, without graph replay, so that every
+kernel of an iteration is its own dispatch.
 """
 from __future__ import annotations
 
@@ -35,12 +38,15 @@ def main(argv=None) -> int:
     ap.add_argument("--seg", type=int, default=0,
                     help="chunk shape: 0 default, -1 flat, else row-segment cells (config.launch.seg)")
     ap.add_argument("--network", action="store_true", help="the network's forward passes on 128^3")
+    ap.add_argument("--learned", action="store_true", help="flexible-CG iterations with the network on 128^3")
     args = ap.parse_args(argv)
     import torch
     from paper_2408_03452_amd import mffv
     from synth import WORKLOADS, workload_field
     if args.network:
         return network(torch, mffv)
+    if args.learned:
+        return learned_iterations(torch, mffv)
 
     w = WORKLOADS["lognormal_corr8_256cube"]
     nx, ny, nz = w.shape
@@ -78,16 +84,46 @@ def main(argv=None) -> int:
     return 0
 
 
-def network(torch, mffv) -> int:
+def probe_params():
+    """Seeded random network parameters with a nonzero last layer."""
     import numpy as np
     from paper_2408_03452_amd import learned
+    rng = np.random.default_rng(5)
+    p = learned.init_params(0)
+    p[-(27 * 16 + 1):-1] = rng.normal(0.0, 0.05, 27 * 16)
+    return p
+
+
+def learned_iterations(torch, mffv) -> int:
+    from synth import channelised
+    shape = (128, 128, 128)
+    print(f"[probe] {mffv.version()}: 30 learned flexible-CG iterations on channelised {shape}", flush=True)
+    k = channelised(shape, 3500)
+    n = k.size
+    kd = torch.from_numpy(k.ravel()).cuda()
+    tx, ty, tz, b = (torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(4))
+    mffv.perm_to_trans(*shape, kd, 1.0, tx, ty, tz)
+    g = mffv.create_grid(*shape)
+    mffv.set_transmissibility(g, tx, ty, tz, accum_scalar=1e-3, b_out=b)
+    net = mffv.net_create(probe_params())
+    x = torch.zeros(n, dtype=torch.float32, device="cuda")
+    st, info = mffv.cg_solve(g, b, x, mffv.default_opts(tol=1e-12, max_iter=30, use_graph=0,
+                                                        precond=mffv.PRECOND_LEARNED, net=net))
+    torch.cuda.synchronize()
+    print(f"[probe] learned: {info['iters']} iterations, status {st}", flush=True)
+    net.close()
+    g.close()
+    print("[probe] done", flush=True)
+    return 0
+
+
+def network(torch, mffv) -> int:
+    import numpy as np
     shape = (128, 128, 128)
     n = int(np.prod(shape))
     print(f"[probe] {mffv.version()}: network forward on {shape}", flush=True)
     rng = np.random.default_rng(5)
-    p = learned.init_params(0)
-    p[-(27 * 16 + 1):-1] = rng.normal(0.0, 0.05, 27 * 16)       # a nonzero last layer
-    net = mffv.net_create(p)
+    net = mffv.net_create(probe_params())
     r = torch.from_numpy(rng.standard_normal(n).astype(np.float32)).cuda()
     f = torch.from_numpy(rng.standard_normal(n).astype(np.float32)).cuda()
     out = torch.empty(n, dtype=torch.float32, device="cuda")
