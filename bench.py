@@ -89,7 +89,8 @@ NN_HIDDEN_BYTES_PER_CELL = 64
 # HBM bytes per launch of the hidden convolution on 128^3 from rocprofv3
 # FETCH_SIZE and WRITE_SIZE (FETCH_SIZE scaled by the same counter on a copy of
 # known size), or None
-NN_TRAFFIC = {"hidden": None}
+NN_TRAFFIC = {"hidden": {"bytes": 141_862_093,  # 36,500.6 KiB x 2 fetched + 65,536 KiB written
+                          "profile": "profiles/conv3d_hidden_channelised_128cube_hbm_traffic.md"}}
 # launch shapes the stencil autotuner reports: the CG kernels' and the apply's own
 LAUNCH_KEYS = ("ci", "remap", "seg", "vec", "blocks", "apply_ci", "apply_remap", "apply_seg", "apply_blocks")
 # HBM bytes per launch of the step's dominant kernel on the 256^3 workload from
@@ -533,7 +534,15 @@ def bench_channelised(log_fn, held_in: int, held_out: int, steps: int, warmup: i
                         tol=1e-6, precond=mffv.PRECOND_LEARNED, net=net, timing=1))
                     out["timing"] = {k: tinfo[k] for k in ("phase_a_us", "phase_b_us", "precond_us",
                                                             "timed_iters", "nn_layer_us", "nn_timed")}
-                    del xt
+                    # each layer's launch duration: 20 back-to-back launches between
+                    # HIP events on this stream (the roofline's figure; the in-solve
+                    # events above also count the gap before each launch)
+                    feat = torch.empty(g.n, dtype=torch.float32, device="cuda")
+                    mffv.grid_feature(g, feat)
+                    gen = torch.Generator(device="cuda").manual_seed(11)
+                    rh = torch.randn(g.n, dtype=torch.float32, device="cuda", generator=gen)
+                    out["layer_us"] = mffv.nn_time_layers(net, shape, rh, feat, reps=20, stream=s)
+                    del xt, feat, rh
                 dt, info, x = solve_f64(g, b64, mk())
                 if i < held_out:
                     rows[name].append((dt, info["iters"], info["ir_steps"], info["rel_res_true"],
@@ -978,8 +987,7 @@ def main(argv=None):
         for m in ("learned_fcg", "plain", "jacobi")))
     # the step's dominant kernel: a hidden 16 -> 16 convolution of the network
     n3 = head["cells"]
-    tm = head.get("timing", {})
-    layers = tm.get("nn_layer_us", [0.0] * 4)
+    layers = head.get("layer_us", [0.0] * 4)
     hidden_us = 0.5 * (layers[1] + layers[2])
     hidden_tflops = NN_LAYER_FLOP_PER_CELL[1] * n3 / (hidden_us * 1e-6) / 1e12 if hidden_us > 0 else 0.0
     hidden_gbs = NN_HIDDEN_BYTES_PER_CELL * n3 / (hidden_us * 1e-6) / 1e9 if hidden_us > 0 else 0.0

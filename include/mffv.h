@@ -445,6 +445,17 @@ int mffv_nn_forward(mffv_net* net, int nx, int ny, int nz, const float* r_hat, c
                     float* out, void* stream);
 
 /*
+ * Measurement of the network's kernels (Sec. II-B's preconditioner as
+ * realised here): one forward pass as mffv_nn_forward (into the network's own
+ * workspace), then for each of the four layers `reps` back-to-back launches
+ * between two HIP events on `stream`. us[4] (host) receives the mean
+ * microseconds per launch of layers 1..4. Synchronizes the stream.
+ * Errors: MFFV_EINVAL for NULL arrays or reps < 1.
+ */
+int mffv_nn_time_layers(mffv_net* net, int nx, int ny, int nz, const float* r_hat, const float* feat,
+                        int reps, double* us, void* stream);
+
+/*
  * Loss and parameter gradient of one training pair on the grid's operator
  * (the gradient stays in the network; read it with mffv_net_get_params).
  * r_hat is the scaled residual and target the scaled error of

@@ -1573,4 +1573,51 @@ int mffv_nn_forward(mffv_net* N, int nx, int ny, int nz, const float* r_hat, con
     return forward(N, S, false, kFinal, last, st);
 }
 
+int mffv_nn_time_layers(mffv_net* N, int nx, int ny, int nz, const float* r_hat, const float* feat, int reps,
+                        double* us, void* stream) {
+    int rc;
+    if ((rc = check_net(N)) || (rc = check_shape(nx, ny, nz))) return rc;
+    if (!r_hat || !feat || !us) return nfail(MFFV_EINVAL, "NULL array");
+    if (reps < 1) return nfail(MFFV_EINVAL, "reps must be >= 1");
+    const Shape S = shape_of(nx, ny, nz);
+    if ((rc = ensure_ws(N, S.g.n, false))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // one whole pass first, so that every layer reads what the network computes
+    hipLaunchKernelGGL(nn_input, dim3(nblocks_for(S.g.n, kRedBlocks)), dim3(kThreads), 0, st, S.g.n, r_hat,
+                       (const float*)nullptr, feat, (const float*)nullptr, N->x0, (const uint8_t*)nullptr);
+    NHIP(hipGetLastError());
+    ConvArgs last{};
+    last.out32 = N->y;
+    if ((rc = forward(N, S, false, kFinal, last, st))) return rc;
+    hipEvent_t ev[2];
+    NHIP(hipEventCreate(&ev[0]));
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        return nfail(MFFV_EHIP, "hipEventCreate failed");
+    }
+    rc = MFFV_OK;
+    for (int l = 0; l < 4 && rc == MFFV_OK; ++l) {
+        ConvArgs a{};
+        a.relu = N->relu;
+        a.W = N->W + (l == 0 ? kWf1 : l == 1 ? kWf2 : l == 2 ? kWf3 : kWf4);
+        a.bias = N->params + offB(l);
+        a.in = l == 0 ? N->x0 : l == 1 ? N->h1 : l == 2 ? N->h2 : N->h1;
+        a.out16 = l == 0 ? N->h1 : l == 1 ? N->h2 : N->h1;  // inference keeps h3 in h1
+        a.out32 = N->y;
+        if (hipEventRecord(ev[0], st) != hipSuccess) rc = nfail(MFFV_EHIP, "hipEventRecord failed");
+        for (int k = 0; k < reps && rc == MFFV_OK; ++k)
+            rc = l == 0 ? conv<2, kHiddenRelu>(S, a, st) : l < 3 ? conv<16, kHiddenRelu>(S, a, st)
+                                                                 : conv<16, kFinal>(S, a, st);
+        if (rc == MFFV_OK && hipEventRecord(ev[1], st) != hipSuccess) rc = nfail(MFFV_EHIP, "hipEventRecord failed");
+        float ms = 0.f;
+        if (rc == MFFV_OK && (hipEventSynchronize(ev[1]) != hipSuccess ||
+                              hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess))
+            rc = nfail(MFFV_EHIP, "event timing failed");
+        if (rc == MFFV_OK) us[l] = 1e3 * (double)ms / reps;
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    return rc;
+}
+
 }  // extern "C"

@@ -116,6 +116,8 @@ def _declare(lib):
         "mffv_set_nn_run": (ctypes.c_int, [ctypes.c_int]),
         "mffv_nn_forward": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P,
                                            _P]),
+        "mffv_nn_time_layers": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P,
+                                               ctypes.c_int, _P, _P]),
         "mffv_nn_loss_grad": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
         "mffv_nn_train_step": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_float,
                                               ctypes.POINTER(ctypes.c_double)]),
@@ -529,6 +531,17 @@ def nn_forward(net: Net, shape, r_hat, feat, out, stream=None) -> None:
     _check(lib().mffv_nn_forward(net.handle, nx, ny, nz, _ptr(r_hat, torch.float32, n, "r_hat"),
                                  _ptr(feat, torch.float32, n, "feat"),
                                  _ptr(out, torch.float32, n, "out"), _stream(stream)))
+
+
+def nn_time_layers(net: Net, shape, r_hat, feat, reps: int = 20, stream=None) -> list:
+    """Mean microseconds per launch of each of the four layers (back-to-back launches)."""
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    us = (ctypes.c_double * 4)()
+    _check(lib().mffv_nn_time_layers(net.handle, nx, ny, nz, _ptr(r_hat, torch.float32, n, "r_hat"),
+                                     _ptr(feat, torch.float32, n, "feat"), int(reps), ctypes.addressof(us),
+                                     _stream(stream)))
+    return list(us)
 
 
 def nn_loss_grad(net: Net, grid: Grid, r_hat, target) -> float:
