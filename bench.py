@@ -395,7 +395,10 @@ def bench_faces(log_fn, shape, tx, ty, tz, c, cg_iters: int = 200, rcm: bool = F
 def bench_batched(log_fn):
     """64 independent uneven systems (dims uniform in [32, 128], log-normal
     sigma 1.5, c log-uniform in [1e-4, 1e-2]) in one persistent launch under a
-    HIP graph, launch shape picked by the autotuner."""
+    HIP graph, launch shape picked by the autotuner. Timed twice: with the
+    blocks shared by system size (a batch solved for the first time), and with
+    the shares the library takes from the previous solve's iteration counts
+    (the same batch solved again)."""
     import numpy as np
     import torch
     from paper_2408_03452_amd import mffv
@@ -416,25 +419,40 @@ def bench_batched(log_fn):
             bs.append(b)
             xs.append(torch.zeros(n, dtype=torch.float32, device="cuda"))
         opts = mffv.default_opts(tol=1e-6, precision=mffv.FP32_IR)
+        # first with block shares by size only (a batch never solved before)
+        mffv.set_batched_rebalance(False)
         tune = mffv.autotune_batched(grids, bs, xs, opts)
         log_fn(f"batched autotune: {tune}")
-        for x in xs:
-            x.zero_()
-        mffv.cg_solve_batched(grids, bs, xs, opts)        # graph capture
-        for x in xs:
-            x.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st, infos = mffv.cg_solve_batched(grids, bs, xs, opts)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+
+        def timed_solve():
+            for x in xs:
+                x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, infos = mffv.cg_solve_batched(grids, bs, xs, opts)
+            torch.cuda.synchronize()
+            return st, infos, time.perf_counter() - t0
+        timed_solve()                                    # graph capture
+        _, infos0, wall0 = timed_solve()
+        # then with shares following the iteration counts of the solve before
+        # (a batch solved again, e.g. at the next time step): one solve to see
+        # them, one to capture the graph of the new shares, then the timed one
+        mffv.set_batched_rebalance(True)
+        timed_solve()
+        mffv.set_batched_rebalance(False)
+        timed_solve()
+        st, infos, wall = timed_solve()
     cells = np.array([g.n for g in grids], dtype=np.float64)
     iters = np.array([i["iters"] for i in infos], dtype=np.float64)
     rr = np.array([i["rel_res_recursive"] for i in infos])
     rt = np.array([i["rel_res_true"] for i in infos])
+    iters0 = np.array([i["iters"] for i in infos0], dtype=np.float64)
     out = {"workload": "batched_64_uneven", "systems": len(grids), "cells_total": int(cells.sum()),
            "status": st, "wall_ms": 1e3 * wall, "device_ms": infos[0]["ms"],
            "cells_iter_per_s": float((cells * iters).sum() / wall),
+           "shares": "cells x iterations of the solve before",
+           "size_shares": {"wall_ms": 1e3 * wall0, "device_ms": infos0[0]["ms"],
+                           "cells_iter_per_s": float((cells * iters0).sum() / wall0)},
            "iters_min_max": [int(iters.min()), int(iters.max())],
            "rel_res_recursive_max": float(rr.max()), "rel_res_true_max": float(rt.max()),
            "rel_res_true_median": float(np.median(rt)), "launch": tune}
@@ -1014,7 +1032,8 @@ def main(argv=None):
     if not args.no_batched:
         log("batched: 64 uneven systems, one persistent launch")
         batched = bench_batched(log)
-        log(f"batched: {batched['cells_iter_per_s'] / 1e9:.1f} Gcell*iter/s, iters "
+        log(f"batched: {batched['cells_iter_per_s'] / 1e9:.1f} Gcell*iter/s (shares by size: "
+            f"{batched['size_shares']['cells_iter_per_s'] / 1e9:.1f}), iters "
             f"{batched['iters_min_max']}, worst true rel-res {batched['rel_res_true_max']:.2e}")
     large_learned = None
     if args.large_learned:

@@ -552,6 +552,21 @@ int mffv_set_batched_launch(int blocks_per_cu, int items_per_block);
 int mffv_set_batched_watchdog(double seconds);
 
 /*
+ * Block shares of repeated batched solves (process-wide, default on). The
+ * systems of a batch get the persistent kernel's blocks in proportion to their
+ * expected work, first cells x (nx + ny + nz). A system's blocks advance
+ * together and the launch lasts as long as its slowest system, so after each
+ * synchronous solve the plan compares those shares with shares in proportion
+ * to the cells x iterations it has just seen; if the latter would shorten the
+ * slowest system's time by more than 5 %, the next solve of the same batch
+ * (same grids, vectors and options) uses them, and captures its graph again.
+ * Results do not depend on the shares beyond FP32 rounding of the dot
+ * products. Asynchronous solves neither take nor change shares. on = 0 keeps
+ * the size-based shares.
+ */
+int mffv_set_batched_rebalance(int on);
+
+/*
  * Autotune the batched launch shape: solves the batch (as mffv_cg_solve_batched)
  * for every candidate (1, 2, 3, 4 or all-fitting blocks per CU x 1, 2, 4, 8, 16 work
  * items per block), each from the initial guess held in x, times each with HIP

@@ -784,12 +784,14 @@ struct BatchPlan {
     hipGraphExec_t exec = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     std::vector<int> blocks;   // per system
+    size_t o_part = 0, o_p64 = 0;  // offsets of the partial-sum arrays in dbuf
 };
 
 std::mutex g_plans_mu;
 int g_batch_bpc = 0;  // blocks per CU of the batched kernel (0 = occupancy limit)
 int g_batch_ipb = 4;  // work items per block of the batched kernel
 double g_batch_watchdog_s = 2.0;  // limit of one per-system wait of the batched kernel
+int g_batch_rebalance = 1;         // block shares follow the previous solve's iteration counts
 
 int batch_blocks_per_cu_override() { return g_batch_bpc; }
 std::vector<BatchPlan*> g_plans;
@@ -816,15 +818,13 @@ void drop_plans_with(const mffv_grid* G) {
 
 // Blocks per system in proportion to its work, estimated as cells times the
 // grid's extent (CG iterations grow with the extent).
-std::vector<int> share_blocks(const std::vector<mffv_grid*>& grids, int total) {
-    const int ns = (int)grids.size();
-    std::vector<double> w(ns);
+// Blocks of each system in proportion to its expected work w[s] (at least
+// one each; the remainder goes, block by block, to the system with the most
+// work per block).
+std::vector<int> share_blocks(const std::vector<double>& w, int total) {
+    const int ns = (int)w.size();
     double sw = 0;
-    for (int s = 0; s < ns; ++s) {
-        const Geom& g = grids[s]->g;
-        w[s] = (double)g.n * (double)(g.nx + g.ny + g.nz);
-        sw += w[s];
-    }
+    for (double v : w) sw += v;
     std::vector<int> B(ns);
     int sum = 0;
     for (int s = 0; s < ns; ++s) {
@@ -849,44 +849,24 @@ std::vector<int> share_blocks(const std::vector<mffv_grid*>& grids, int total) {
     return B;
 }
 
-int build_plan(BatchPlan* P, hipStream_t stream) {
+// Expected work of each system before any solve: cells x (nx + ny + nz), CG
+// iterations growing with the grid's extent.
+std::vector<double> size_weights(const std::vector<mffv_grid*>& grids) {
+    std::vector<double> w;
+    for (mffv_grid* G : grids) w.push_back((double)G->g.n * (double)(G->g.nx + G->g.ny + G->g.nz));
+    return w;
+}
+
+// The per-system descriptors and the block map for block shares following
+// the work weights w (the device buffer of the plan is already allocated; its
+// size depends only on the total block count).
+int fill_plan(BatchPlan* P, const std::vector<double>& w) {
     const int ns = (int)P->grids.size();
-    int rc;
-    // the batched kernel addresses a system's vectors with 32-bit byte offsets
-    for (mffv_grid* G : P->grids)
-        if (G->g.n >= (int64_t(1) << 30)) return fail(MFFV_EINVAL, "batched systems must have fewer than 2^30 cells");
-    for (mffv_grid* G : P->grids) {
-        if ((rc = ensure_ws32(G))) return rc;
-        if (P->merged && (rc = ensure_merged(G))) return rc;
-    }
-    int dev = 0, cus = 0, rate_khz = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HIP_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
-    const int occ = batched_blocks_per_cu();
-    if (occ <= 0) return fail(MFFV_EHIP, "occupancy query of the batched kernel failed");
-    const int per_cu = P->blocks_per_cu > 0 ? std::min(P->blocks_per_cu, occ) : occ;
-    const int total = per_cu * cus;
-    if (ns > total)
-        return fail(MFFV_EINVAL, "more systems than co-resident blocks (" + std::to_string(total) + ")");
-    P->blocks = share_blocks(P->grids, total);
-    P->nblocks = total;
-    // device buffer: descriptors, block map, partials, barriers, results
-    size_t off = 0;
-    auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
-    const size_t o_sys = take(sizeof(BatchSys) * ns), o_map = take(sizeof(int) * total),
-                 o_part = take(sizeof(float) * 8 * total), o_bar = take(sizeof(unsigned) * (2 * (size_t)ns + 2 * (size_t)total)),
-                 o_res = take(sizeof(BatchResult) * ns), o_p64 = take(sizeof(double) * 2 * total),
-                 o_err = take(sizeof(int));
-    HIP_TRY(hipMalloc(&P->dbuf, off));
+    const int total = P->nblocks;
+    P->blocks = share_blocks(w, total);
     char* base = static_cast<char*>(P->dbuf);
-    P->dsys = reinterpret_cast<BatchSys*>(base + o_sys);
-    P->dblock_sys = reinterpret_cast<int*>(base + o_map);
-    float* dpart = reinterpret_cast<float*>(base + o_part);
-    P->dbars = reinterpret_cast<unsigned*>(base + o_bar);
-    P->dres = reinterpret_cast<BatchResult*>(base + o_res);
-    double* dpart64 = reinterpret_cast<double*>(base + o_p64);
-    P->derr = reinterpret_cast<int*>(base + o_err);
+    float* dpart = reinterpret_cast<float*>(base + P->o_part);
+    double* dpart64 = reinterpret_cast<double*>(base + P->o_p64);
     std::vector<BatchSys> hs(ns);
     std::vector<int> map(total);
     int b0 = 0;
@@ -925,6 +905,47 @@ int build_plan(BatchPlan* P, hipStream_t stream) {
     }
     HIP_TRY(hipMemcpy(P->dsys, hs.data(), sizeof(BatchSys) * ns, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(P->dblock_sys, map.data(), sizeof(int) * total, hipMemcpyHostToDevice));
+    return MFFV_OK;
+}
+
+int build_plan(BatchPlan* P, hipStream_t stream) {
+    const int ns = (int)P->grids.size();
+    int rc;
+    // the batched kernel addresses a system's vectors with 32-bit byte offsets
+    for (mffv_grid* G : P->grids)
+        if (G->g.n >= (int64_t(1) << 30)) return fail(MFFV_EINVAL, "batched systems must have fewer than 2^30 cells");
+    for (mffv_grid* G : P->grids) {
+        if ((rc = ensure_ws32(G))) return rc;
+        if (P->merged && (rc = ensure_merged(G))) return rc;
+    }
+    int dev = 0, cus = 0, rate_khz = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
+    const int occ = batched_blocks_per_cu();
+    if (occ <= 0) return fail(MFFV_EHIP, "occupancy query of the batched kernel failed");
+    const int per_cu = P->blocks_per_cu > 0 ? std::min(P->blocks_per_cu, occ) : occ;
+    const int total = per_cu * cus;
+    if (ns > total)
+        return fail(MFFV_EINVAL, "more systems than co-resident blocks (" + std::to_string(total) + ")");
+    P->nblocks = total;
+    // device buffer: descriptors, block map, partials, barriers, results
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
+    const size_t o_sys = take(sizeof(BatchSys) * ns), o_map = take(sizeof(int) * total),
+                 o_part = take(sizeof(float) * 8 * total), o_bar = take(sizeof(unsigned) * (2 * (size_t)ns + 2 * (size_t)total)),
+                 o_res = take(sizeof(BatchResult) * ns), o_p64 = take(sizeof(double) * 2 * total),
+                 o_err = take(sizeof(int));
+    HIP_TRY(hipMalloc(&P->dbuf, off));
+    char* base = static_cast<char*>(P->dbuf);
+    P->dsys = reinterpret_cast<BatchSys*>(base + o_sys);
+    P->dblock_sys = reinterpret_cast<int*>(base + o_map);
+    P->o_part = o_part;
+    P->o_p64 = o_p64;
+    P->dbars = reinterpret_cast<unsigned*>(base + o_bar);
+    P->dres = reinterpret_cast<BatchResult*>(base + o_res);
+    P->derr = reinterpret_cast<int*>(base + o_err);
+    if ((rc = fill_plan(P, size_weights(P->grids)))) return rc;
     HIP_TRY(hipMemset(P->derr, 0, sizeof(int)));
     P->run.tol2 = (float)(P->tol * P->tol);
     P->run.max_iter = P->max_iter;
@@ -1765,6 +1786,28 @@ int mffv_cg_solve_batched(mffv_grid* const* grids, int nsys, const float* const*
         return fail(MFFV_EHIP, "batched CG: a per-system wait (barrier or partial-sum exchange) exceeded the "
                                 "watchdog limit (blocks not co-resident?)");
     }
+    if (g_batch_rebalance) {
+        // The systems' blocks advance together only within a system, so the
+        // launch lasts as long as the slowest system: cells x iterations / blocks.
+        // When shares in proportion to this solve's cells x iterations would
+        // shorten that by more than 5 %, the next solve of the batch takes them
+        // (its graph is captured again).
+        std::vector<double> w(nsys);
+        for (int s = 0; s < nsys; ++s) w[s] = (double)P->grids[s]->g.n * std::max(1, res[s].iters);
+        auto span = [&](const std::vector<int>& B) {
+            double m = 0;
+            for (int s = 0; s < nsys; ++s) m = std::max(m, w[s] / B[s]);
+            return m;
+        };
+        const std::vector<int> Bn = share_blocks(w, P->nblocks);
+        if (span(Bn) < 0.95 * span(P->blocks)) {
+            if ((rc = fill_plan(P, w))) return rc;
+            if (P->exec) {
+                (void)hipGraphExecDestroy(P->exec);
+                P->exec = nullptr;
+            }
+        }
+    }
     int status = MFFV_OK;
     for (int s = 0; s < nsys; ++s) {
         const BatchResult& R = res[s];
@@ -2175,6 +2218,12 @@ int mffv_set_batched_launch(int blocks_per_cu, int items_per_block) {
     std::lock_guard<std::mutex> lk(g_plans_mu);
     g_batch_bpc = blocks_per_cu;
     g_batch_ipb = items_per_block;
+    return MFFV_OK;
+}
+
+int mffv_set_batched_rebalance(int on) {
+    std::lock_guard<std::mutex> lk(g_plans_mu);
+    g_batch_rebalance = on ? 1 : 0;
     return MFFV_OK;
 }
 

@@ -18,7 +18,10 @@ parameters of the trained network's scale) on a unit-RMS random input and
 the same 5 copies. With --learned it runs 30 iterations of flexible CG with
 that network as the preconditioner (between the two Jacobi sweeps) on
 held-out channelised realisation 3500, without graph replay, so that every
-kernel of an iteration is its own dispatch.
+kernel of an iteration is its own dispatch. With --batched it solves the
+64-system uneven batch (the batched workload) once with the persistent
+batched kernel (default launch shape, block shares by size) and runs the
+same 5 copies.
 """
 from __future__ import annotations
 
@@ -39,6 +42,7 @@ def main(argv=None) -> int:
                     help="chunk shape: 0 default, -1 flat, else row-segment cells (config.launch.seg)")
     ap.add_argument("--network", action="store_true", help="the network's forward passes on 128^3")
     ap.add_argument("--learned", action="store_true", help="flexible-CG iterations with the network on 128^3")
+    ap.add_argument("--batched", action="store_true", help="one solve of the 64-system uneven batch")
     args = ap.parse_args(argv)
     import torch
     from paper_2408_03452_amd import mffv
@@ -47,6 +51,8 @@ def main(argv=None) -> int:
         return network(torch, mffv)
     if args.learned:
         return learned_iterations(torch, mffv)
+    if args.batched:
+        return batched(torch, mffv)
 
     w = WORKLOADS["lognormal_corr8_256cube"]
     nx, ny, nz = w.shape
@@ -113,6 +119,39 @@ def learned_iterations(torch, mffv) -> int:
     print(f"[probe] learned: {info['iters']} iterations, status {st}", flush=True)
     net.close()
     g.close()
+    print("[probe] done", flush=True)
+    return 0
+
+
+def batched(torch, mffv) -> int:
+    from synth import batch_systems
+    systems = batch_systems()
+    print(f"[probe] {mffv.version()}: batched solve of {len(systems)} uneven systems", flush=True)
+    grids, bs, xs = [], [], []
+    for sy in systems:
+        nx, ny, nz = sy.shape
+        n = sy.k.size
+        kd = torch.from_numpy(sy.k.ravel()).cuda()
+        tx, ty, tz, b = (torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(4))
+        mffv.perm_to_trans(nx, ny, nz, kd, 1.0, tx, ty, tz)
+        g = mffv.create_grid(nx, ny, nz)
+        mffv.set_transmissibility(g, tx, ty, tz, accum_scalar=sy.c, b_out=b)
+        grids.append(g)
+        bs.append(b)
+        xs.append(torch.zeros(n, dtype=torch.float32, device="cuda"))
+    mffv.set_batched_rebalance(False)
+    st, infos = mffv.cg_solve_batched(grids, bs, xs, mffv.default_opts(tol=1e-6, precision=mffv.FP32_IR))
+    torch.cuda.synchronize()
+    cells = sum(g.n * i["iters"] for g, i in zip(grids, infos))
+    print(f"[probe] batched: status {st}, {infos[0]['ms']:.1f} ms, {cells / 1e9:.2f} G cell-iterations", flush=True)
+    nbytes = 1 << 30
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        mffv.copy_probe(dst, src, nbytes)
+    torch.cuda.synchronize()
+    for g in grids:
+        g.close()
     print("[probe] done", flush=True)
     return 0
 

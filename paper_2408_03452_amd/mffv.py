@@ -126,6 +126,7 @@ def _declare(lib):
         "mffv_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.POINTER(TuneResult)]),
         "mffv_set_batched_launch": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
         "mffv_set_batched_watchdog": (ctypes.c_int, [ctypes.c_double]),
+        "mffv_set_batched_rebalance": (ctypes.c_int, [ctypes.c_int]),
         "mffv_autotune_batched": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int,
                                                  ctypes.POINTER(_P), ctypes.POINTER(_P),
                                                  ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_int),
@@ -424,6 +425,11 @@ def set_batched_launch(blocks_per_cu: int, items_per_block: int) -> None:
 def set_batched_watchdog(seconds: float) -> None:
     """Limit of one per-system wait of the batched kernel (0: fail at once)."""
     _check(lib().mffv_set_batched_watchdog(float(seconds)))
+
+
+def set_batched_rebalance(on: bool) -> None:
+    """Block shares of repeated batched solves follow the last solve's iterations (default on)."""
+    _check(lib().mffv_set_batched_rebalance(1 if on else 0))
 
 
 def autotune_batched(grids, b, x, opts: Opts | None = None) -> dict:

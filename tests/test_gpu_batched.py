@@ -285,3 +285,43 @@ def test_batched_solves_follow_new_coefficients(mf):
                                     pD=torch.from_numpy(pd.astype(np.float32).ravel()).cuda(), b_out=b)
             refs.append(OracleProblem(k, c=1e-3, dmask=dm, pd=pd))
         solve_all("mask", refs)
+
+
+def test_batched_shares_follow_iterations_and_keep_results(mf):
+    """With block shares taken from the previous solve's iteration counts
+    (mffv_set_batched_rebalance), the same batch solved again (graph captured
+    anew) still meets the true residual in every system and returns the
+    refined fields of the first solve to FP32 rounding of the dot products."""
+    systems = small_batch(11, n=9)
+    # uneven iteration counts: a larger, harder system among small ones with
+    # much accumulation
+    systems = [((30, 26, 28), lognormal_iid((30, 26, 28), 2.0, 9), 1e-4)] + \
+        [(sh, k, 1e-2) for sh, k, _ in systems[1:]]
+    s = torch.cuda.Stream()
+    mf.set_batched_rebalance(True)
+    grids = []
+    try:
+        with torch.cuda.stream(s):
+            probs = [gpu_problem(mf, k, c=c, stream=s) for _, k, c in systems]
+            grids = [p[0] for p in probs]
+            bs = [p[2] for p in probs]
+            xs = [torch.zeros(k.size, dtype=torch.float32, device="cuda") for _, k, _ in systems]
+            fields, iters = [], []
+            for rep in range(3):
+                for x in xs:
+                    x.zero_()
+                st, infos = mf.cg_solve_batched(grids, bs, xs, mf.default_opts(tol=1e-6, precision=mf.FP32_IR))
+                torch.cuda.synchronize()
+                assert st == mf.OK, infos
+                assert all(i["rel_res_true"] <= 1e-6 for i in infos), [i["rel_res_true"] for i in infos]
+                fields.append([host(x) for x in xs])
+                iters.append([i["iters"] for i in infos])
+        print(f"\n[batched] iterations per solve: {iters}")
+        for (shape, k, c), f0, f2 in zip(systems, fields[0], fields[2]):
+            p = OracleProblem(k, c=c).direct()
+            assert np.linalg.norm(f2 - p) <= 1e-5 * np.linalg.norm(p), shape
+            assert np.linalg.norm(f2 - f0) <= 1e-5 * np.linalg.norm(f0), shape
+    finally:
+        mf.set_batched_rebalance(True)
+        for g in grids:
+            g.close()
