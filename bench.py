@@ -283,6 +283,23 @@ def bench_time_steps(log_fn, shape, tx, ty, tz, nsteps: int = 8):
         e1.record(s)
         e1.synchronize()
         rhs_us = e0.elapsed_time(e1) * 1e3 / 50
+        # the operator with a per-cell diagonal (c + WI): the apply (24 B/cell)
+        # and the fused phase A (4 B/cell more than with a uniform diagonal),
+        # HIP events on the grid's stream
+        xa = torch.randn(n, dtype=torch.float32, device=dev)
+        ya = torch.empty_like(xa)
+        for _ in range(3):
+            mffv.apply(g, xa, ya)
+        e0.record(s)
+        for _ in range(20):
+            mffv.apply(g, xa, ya)
+        e1.record(s)
+        e1.synchronize()
+        apply_us = e0.elapsed_time(e1) * 1e3 / 20
+        xt = p_prev.clone()
+        _, tinfo = mffv.cg_solve(g, b, xt, mffv.default_opts(tol=1e-30, max_iter=64, timing=1))
+        pa_bytes = phase_a_bytes_mean(tinfo["timed_iters"]) + 4
+        del xa, ya, xt
         p0h, p1h = (t.cpu().numpy().astype(np.float64).reshape(shape) for t in (p_prev, p))
         T = [t.cpu().numpy().astype(np.float64).reshape(shape) for t in (tx, ty, tz)]
         g.close()
@@ -303,10 +320,19 @@ def bench_time_steps(log_fn, shape, tx, ty, tz, nsteps: int = 8):
            "mass_balance_rel": balance,
            "step_rhs_us": rhs_us,
            "step_rhs_GBps": STEP_RHS_BYTES_PER_CELL * n / (rhs_us * 1e-6) / 1e9,
+           "per_cell_diagonal": {
+               "apply_us": apply_us, "apply_bytes_per_cell": APPLY_BYTES_PER_CELL + 4,
+               "apply_GBps": (APPLY_BYTES_PER_CELL + 4) * n / (apply_us * 1e-6) / 1e9,
+               "phase_a_us": tinfo["phase_a_us"], "phase_a_bytes_per_cell": pa_bytes,
+               "phase_a_GBps": pa_bytes * n / (tinfo["phase_a_us"] * 1e-6) / 1e9,
+               "phase_b_us": tinfo["phase_b_us"]},
            "config": {"storage": c, "wells": "injector column pw 2, producer column pw -1, WI 1",
                       "tol": 1e-6, "initial": "p = 0 inside, Dirichlet planes 1 and 0"}}
+    pc = res["per_cell_diagonal"]
     log_fn(f"time steps: {ms_step:.1f} ms/step, iterations {res['iters_per_step']}, mass balance "
-           f"{balance:.1e}, rhs kernel {rhs_us:.1f} us ({res['step_rhs_GBps']:.0f} GB/s)")
+           f"{balance:.1e}, rhs kernel {rhs_us:.1f} us ({res['step_rhs_GBps']:.0f} GB/s); per-cell diagonal: "
+           f"apply {pc['apply_us']:.1f} us ({pc['apply_GBps']:.0f} GB/s at 24 B/cell), phase A "
+           f"{pc['phase_a_us']:.1f} us ({pc['phase_a_GBps']:.0f} GB/s at {pc['phase_a_bytes_per_cell']:.1f} B/cell)")
     return res
 
 
