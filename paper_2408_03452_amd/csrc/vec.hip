@@ -326,11 +326,17 @@ __global__ __launch_bounds__(kThreads) void differ(int64_t n, const uint32_t* __
     if (d && threadIdx.x == 0) flag[0] = 1;
 }
 
-__global__ __launch_bounds__(kThreads) void copy_probe(const uint4* __restrict__ src,
-                                                       uint4* __restrict__ dst, int64_t n16) {
+// One 16-byte element per thread and a grid of one block per 256 elements:
+// blocks finish and are replaced as the memory system drains them, which on
+// gfx950 streams faster than fewer resident blocks looping over the array
+// (measured on 1 GiB: 6.36 TB/s against 4.3-5.6 TB/s with 2,048-65,536 blocks
+// and 1-8 loads in flight per thread). Stores are nontemporal.
+typedef unsigned int pu4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(kThreads) void copy_probe(const pu4* __restrict__ src, pu4* __restrict__ dst,
+                                                       int64_t n16) {
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n16; e += stride)
-        dst[e] = src[e];
+        __builtin_nontemporal_store(src[e], dst + e);
 }
 
 // Streaming probe: every output array receives the sum of the input arrays,
@@ -710,14 +716,15 @@ hipError_t launch_differ(int64_t n, const float* a, const float* b, int* flag, h
 
 hipError_t launch_stream_probe(int64_t n, const StreamProbeIO& io, hipStream_t s) {
     const int64_t n4 = n / 4;
-    hipLaunchKernelGGL(stream_probe, dim3(grid_for(n4, 4, 16384)), dim3(kThreads), 0, s, n4, io);
+    // one float4 of every array per thread, one block per 256 of them (as the copy probe)
+    hipLaunchKernelGGL(stream_probe, dim3(grid_for(n4, 1, 1 << 24)), dim3(kThreads), 0, s, n4, io);
     return hipGetLastError();
 }
 
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s) {
     const int64_t n16 = (int64_t)(bytes / 16);
-    hipLaunchKernelGGL(copy_probe, dim3(grid_for(n16, 4, 16384)), dim3(kThreads), 0, s,
-                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
+    hipLaunchKernelGGL(copy_probe, dim3(grid_for(n16, 1, 1 << 24)), dim3(kThreads), 0, s,
+                       static_cast<const pu4*>(src), static_cast<pu4*>(dst), n16);
     return hipGetLastError();
 }
 
