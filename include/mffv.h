@@ -492,6 +492,17 @@ int mffv_grid_feature(mffv_grid* grid, float* feat);
 int mffv_harvest_pair(mffv_grid* grid, const float* b, const float* x, const double* x_star,
                       float* r_hat, float* target, float* scale);
 
+/*
+ * A training residual as the network sees it between the Jacobi sweeps (an
+ * addition of this library: its preconditioner applies the network to the
+ * residual left by a damped Jacobi step). For a Jacobi-scaled residual r_hat
+ * (mffv_harvest_pair's space), out = (I - omega A~) r_hat on the unknown cells
+ * and 0 on Dirichlet cells, A~ = D^-1/2 A D^-1/2, D = diag(A). r_hat, out:
+ * device FP32, n cells, may not alias. Enqueued on the grid's stream.
+ * Errors: MFFV_EINVAL for NULL arrays or omega outside [0, 1).
+ */
+int mffv_nn_smooth_sample(mffv_grid* grid, double omega, const float* r_hat, float* out);
+
 /* Launch shape chosen for a grid's stencil kernels. */
 typedef struct {
     int ci;          /* planes a block marches through along x */

@@ -1915,6 +1915,25 @@ int mffv_harvest_pair(mffv_grid* G, const float* b, const float* x, const double
     return MFFV_OK;
 }
 
+int mffv_nn_smooth_sample(mffv_grid* G, double omega, const float* r_hat, float* out) {
+    int rc = check_grid(G, true);
+    if (rc || (rc = check_cartesian(G, "mffv_nn_smooth_sample"))) return rc;
+    if (!r_hat || !out) return fail(MFFV_EINVAL, "NULL array");
+    if (!(omega >= 0.0 && omega < 1.0)) return fail(MFFV_EINVAL, "omega must lie in [0, 1)");
+    if ((rc = set_device(G)) || (rc = ensure_ws32(G))) return rc;
+    // r = D^1/2 r_hat, r1 = r - A (omega D^-1 r) (the first sweep's pass), out = D^-1/2 r1
+    HIP_TRY(launch_scale_dsqrt(G->g.n, r_hat, G->dinv, G->dmask, +1, G->z, G->stream));
+    StencilIO<float> io;
+    io.src = G->z;
+    io.dinv = G->dinv;
+    io.omega = (float)omega;
+    io.out = G->r;
+    io.partials = reinterpret_cast<float*>(G->partR);
+    HIP_TRY(launch_stencil_f32(kSweep1, G->g, coef_of(G), io, G->m_apply, G->stream));
+    HIP_TRY(launch_scale_dsqrt(G->g.n, G->r, G->dinv, G->dmask, -1, out, G->stream));
+    return MFFV_OK;
+}
+
 int mffv_nn_loss_grad(mffv_net* net, mffv_grid* G, const float* r_hat, const float* target,
                       double* loss) {
     int rc = check_grid(G, true);

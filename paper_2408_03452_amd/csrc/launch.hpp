@@ -157,6 +157,9 @@ hipError_t launch_stream_probe(int64_t n, const StreamProbeIO& io, hipStream_t s
 hipError_t launch_merged_init(MergedState* ms, float tol2, int max_iter, hipStream_t s);
 hipError_t launch_jacobi_z(int64_t n, const float* r, const float* dinv, const uint8_t* dmask, float* z,
                            hipStream_t s);
+// out = D^(power/2) v on unknown cells (power +1 or -1, D = diag(A)), 0 on Dirichlet cells.
+hipError_t launch_scale_dsqrt(int64_t n, const float* v, const float* dinv, const uint8_t* dmask, int power,
+                              float* out, hipStream_t s);
 // flag[0] = 1 if a and b (n floats) differ in any bit; flag[0] must be 0 before.
 hipError_t launch_differ(int64_t n, const float* a, const float* b, int* flag, hipStream_t s);
 

@@ -297,6 +297,17 @@ __global__ __launch_bounds__(kThreads) void jacobi_z(int64_t n, const float* __r
         z[l] = dmask[l] ? 0.f : dinv[l] * r[l];
 }
 
+// out = D^(power/2) v on unknown cells (power +1: v / sqrt(dinv); -1: v sqrt(dinv)), 0 on Dirichlet cells.
+__global__ __launch_bounds__(kThreads) void scale_dsqrt(int64_t n, const float* __restrict__ v,
+                                                        const float* __restrict__ dinv,
+                                                        const uint8_t* __restrict__ dmask, int power, float* out) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x; l < n; l += stride) {
+        const float sq = sqrtf(dinv[l]);
+        out[l] = dmask[l] ? 0.f : (power > 0 ? v[l] / sq : v[l] * sq);
+    }
+}
+
 // Scalars of a single-reduction CG run before kernel 0 (plain vector stores).
 __global__ void merged_init(MergedState* ms, float tol2, int max_iter) {
     if (threadIdx.x != 0) return;
@@ -700,6 +711,12 @@ hipError_t launch_fill_f32(int64_t n, float* a, float v, hipStream_t s) {
 hipError_t launch_jacobi_z(int64_t n, const float* r, const float* dinv, const uint8_t* dmask, float* z,
                            hipStream_t s) {
     hipLaunchKernelGGL(jacobi_z, dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, r, dinv, dmask, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_dsqrt(int64_t n, const float* v, const float* dinv, const uint8_t* dmask, int power,
+                              float* out, hipStream_t s) {
+    hipLaunchKernelGGL(scale_dsqrt, dim3(grid_for(n, 4)), dim3(kThreads), 0, s, n, v, dinv, dmask, power, out);
     return hipGetLastError();
 }
 

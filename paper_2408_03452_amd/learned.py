@@ -111,6 +111,23 @@ def dagger(net: mffv.Net, systems, iters=(2, 8, 32, 64, 128)) -> list:
     return out
 
 
+def smoothed(samples: list, omega: float) -> list:
+    """The samples as the network sees them between the Jacobi sweeps of the
+    solver's preconditioner: r_hat -> (I - omega A~) r_hat on each sample's
+    operator (mffv_nn_smooth_sample); samples with a target are kept as they are."""
+    if omega <= 0:
+        return samples
+    out = []
+    for s in samples:
+        if s.target is not None:
+            out.append(s)
+            continue
+        r1 = torch.empty_like(s.r_hat)
+        mffv.nn_smooth_sample(s.grid, omega, s.r_hat, r1)
+        out.append(Sample(s.grid, r1, None, s.iteration))
+    return out
+
+
 LAYERS = ((2, 16), (16, 16), (16, 16), (16, 1))
 
 
@@ -147,7 +164,7 @@ def fcg_iterations(net: mffv.Net, systems, max_iter=20000) -> int:
 def train_preconditioner(systems, validation=None, n_white: int = 256, epochs: int = 24,
                          lr: float = 2e-3, lr_final: float = 1e-4, dagger_rounds: int = 2,
                          dagger_epochs: int = 6, seed: int = 0, relu: bool = True,
-                         loss: int = 0, init=None, log=None) -> mffv.Net:
+                         loss: int = 0, init=None, smooth: float = 0.0, log=None) -> mffv.Net:
     """The training recipe on held-in systems [(grid, b), ...].
 
     White-noise residuals with the energy functional, then ``dagger_rounds``
@@ -158,7 +175,10 @@ def train_preconditioner(systems, validation=None, n_white: int = 256, epochs: i
     network (Jacobi) is the first candidate, so the result is never worse
     than Jacobi on the validation systems. With ``init`` (a parameter vector,
     e.g. a network trained on another field) training continues from it
-    (fine-tuning), and that network is the first candidate instead.
+    (fine-tuning), and that network is the first candidate instead. With
+    ``smooth`` = omega > 0 every target-free sample is first passed through
+    the first Jacobi sweep (:func:`smoothed`), so that the network is trained
+    on the residuals it sees inside the solver's preconditioner.
     """
     import numpy as np
     validation = systems[:2] if validation is None else validation
@@ -193,12 +213,12 @@ def train_preconditioner(systems, validation=None, n_white: int = 256, epochs: i
             if log:
                 log(f"{tag} epoch {ep}: validation FCG iterations {it} (best {best})")
 
-    run(white_samples(systems, n_white, seed), epochs, lr, lr_final, "white", seed)
+    run(smoothed(white_samples(systems, n_white, seed), smooth), epochs, lr, lr_final, "white", seed)
     for r in range(dagger_rounds):
         mffv.net_set_params(net, best_p)
         extra = dagger(net, systems)
         more = white_samples(systems, n_white // 2, seed + 1000 * (r + 1))
-        run(extra + more, dagger_epochs, lr / 4, lr_final, f"dagger{r}", seed + r + 1)
+        run(smoothed(extra + more, smooth), dagger_epochs, lr / 4, lr_final, f"dagger{r}", seed + r + 1)
     mffv.net_set_params(net, best_p)
     del np
     return net

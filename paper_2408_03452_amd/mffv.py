@@ -118,6 +118,7 @@ def _declare(lib):
                                            _P]),
         "mffv_nn_time_layers": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P,
                                                ctypes.c_int, _P, _P]),
+        "mffv_nn_smooth_sample": (ctypes.c_int, [_P, ctypes.c_double, _P, _P]),
         "mffv_nn_loss_grad": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
         "mffv_nn_train_step": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_float,
                                               ctypes.POINTER(ctypes.c_double)]),
@@ -537,6 +538,12 @@ def nn_forward(net: Net, shape, r_hat, feat, out, stream=None) -> None:
     _check(lib().mffv_nn_forward(net.handle, nx, ny, nz, _ptr(r_hat, torch.float32, n, "r_hat"),
                                  _ptr(feat, torch.float32, n, "feat"),
                                  _ptr(out, torch.float32, n, "out"), _stream(stream)))
+
+
+def nn_smooth_sample(grid: Grid, omega: float, r_hat, out) -> None:
+    """out = (I - omega A~) r_hat on the unknown cells (the residual the network sees between the sweeps)."""
+    _check(lib().mffv_nn_smooth_sample(grid.handle, float(omega), _ptr(r_hat, torch.float32, grid.n, "r_hat"),
+                                       _ptr(out, torch.float32, grid.n, "out")))
 
 
 def nn_time_layers(net: Net, shape, r_hat, feat, reps: int = 20, stream=None) -> list:
