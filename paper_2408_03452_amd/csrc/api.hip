@@ -95,6 +95,7 @@ struct mffv_grid {
     bool has_coef = false;
     int64_t n_unknown = 0;
     float* feat = nullptr;     // learned preconditioner input feature (lazy)
+    float* sqd = nullptr;      // sqrt(dinv) on unknown cells, 0 on Dirichlet cells (with feat)
     bool feat_valid = false;
     // FP32 workspace
     float *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr, *z = nullptr, *xw = nullptr,
@@ -217,8 +218,9 @@ int ensure_feature(mffv_grid* G) {
     if (G->feat_valid) return MFFV_OK;
     int rc;
     if (!G->feat && (rc = dalloc(&G->feat, (size_t)G->g.n))) return rc;
+    if (!G->sqd && (rc = dalloc(&G->sqd, (size_t)G->g.n))) return rc;
     if ((rc = nn_feature(G->g, G->dinv, G->dmask, (float)G->n_unknown,
-                         reinterpret_cast<float*>(G->partR), G->feat, G->stream)))
+                         reinterpret_cast<float*>(G->partR), G->feat, G->sqd, G->stream)))
         return rc;
     G->feat_valid = true;
     return MFFV_OK;
@@ -327,8 +329,8 @@ int enqueue_iter32(mffv_grid* G, int precond, const mffv_net* net, int nn_every 
     if (ev) HIP_TRY(hipEventRecord(ev[2], G->stream));
     if (precond == MFFV_PRECOND_LEARNED) {
         if (use_nn) {
-            int rc = nn_precondition(net, G->g, coef_of(G), G->m_apply, omega, G->r, G->dinv, G->dmask, G->z,
-                                     pb + G->nb_vec, G->nb_vec, G->feat, (float)G->n_unknown, G->stream, nev);
+            int rc = nn_precondition(net, G->g, coef_of(G), G->m_apply, omega, G->r, G->dinv, G->dmask, G->sqd,
+                                     G->z, pb + G->nb_vec, G->nb_vec, G->feat, (float)G->n_unknown, G->stream, nev);
             if (rc) return rc;
         } else {
             HIP_TRY(launch_jacobi_z(G->g.n, G->r, G->dinv, G->dmask, G->z, G->stream));
@@ -598,7 +600,7 @@ int cg32(mffv_grid* G, double tol, int max_iter, int precond, const mffv_opts& o
     }
     if (precond == MFFV_PRECOND_LEARNED) {
         int rc = nn_precondition(net, G->g, coef_of(G), G->m_apply, (float)o.nn_smooth, G->r, G->dinv, G->dmask,
-                                 G->z, pb + G->nb_vec, G->nb_vec, G->feat, (float)G->n_unknown, G->stream);
+                                 G->sqd, G->z, pb + G->nb_vec, G->nb_vec, G->feat, (float)G->n_unknown, G->stream);
         if (rc) return rc;
         VecIO<float> f = v;
         f.partials = reinterpret_cast<float*>(G->partF);
@@ -1340,6 +1342,7 @@ void mffv_destroy_grid(mffv_grid* G) {
     drop_graphs(G);
     dfree(G->a); dfree(G->a64); dfree(G->tx); dfree(G->ty); dfree(G->tz); dfree(G->dinv); dfree(G->dmask);
     dfree(G->feat);
+    dfree(G->sqd);
     dfree(G->flags); dfree(G->cdev); dfree(G->partA); dfree(G->partB); dfree(G->partF); dfree(G->partR);
     dfree(G->dscal);
     dfree(G->r); dfree(G->p0); dfree(G->p1); dfree(G->q); dfree(G->z); dfree(G->xw);

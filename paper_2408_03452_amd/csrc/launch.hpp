@@ -61,12 +61,18 @@ struct StencilIO {
     MergedState* ms = nullptr;
     int parity = 0;
     float omega = 0.f;           // kSweep1 / kSweep2: the sweeps' weight
+    float* sw_j = nullptr;             // kSweep1: written; kSweep2: read (see above)
+    const float* sw_sq = nullptr;      // kSweep2: sqrt(dinv), 0 on Dirichlet cells
+    const float* sw_scale = nullptr;   //   the network's scale s (device scalar)
 };
 
 // kSweep1 / kSweep2: the damped Jacobi sweeps around the learned
 // preconditioner (FP32, Cartesian grids), each one pass over the operator:
-//   kSweep1: out = src - A (omega dinv src), per-block partials of dinv out^2;
-//   kSweep2: out = src + omega dinv (rres - A src).
+//   kSweep1: out = src - A (omega dinv src), per-block partials of dinv out^2,
+//            and (sw_j) omega dinv src + dinv out;
+//   kSweep2: out = z2 + omega dinv (rres - A z2), where z2 = sw_j + s sw_sq src
+//            is formed at every stencil point from the network's output src
+//            (s = *sw_scale; sw_sq: sqrt(dinv), 0 on Dirichlet cells).
 enum StencilMode { kApply = 0, kFusedCg = 1, kResidual = 2, kMergedCg = 3, kSweep1 = 4, kSweep2 = 5 };
 
 hipError_t launch_stencil_f32(int mode, const Geom& g, const Coef& c, const StencilIO<float>& io,

@@ -435,7 +435,7 @@ __device__ __forceinline__ int ring_next(int x, int d) { return x + d >= kRingSl
 // activation of the layer below, for its ReLU mask).
 struct EpiIn {
     float r[4], d[4], r1[4];
-    uint32_t m[4];
+    uint8_t m[4];
     uint2 b[4];
 };
 
@@ -488,7 +488,7 @@ __device__ __forceinline__ void conv_step(const Geom& g, const ConvArgs& a, cons
     const float* er = cur.r;
     const float* ed = cur.d;
     const float* er1 = cur.r1;
-    const uint32_t* em = cur.m;
+    const uint8_t* em = cur.m;
     const uint2* eb = cur.b;
     if (j >= g.ny) return;
     int so[3];
@@ -1006,12 +1006,14 @@ __global__ __launch_bounds__(kThreads) void logd_partials(int64_t n, const float
 
 __global__ __launch_bounds__(kThreads) void feature_kernel(int64_t n, const float* dinv,
                                                            const uint8_t* dmask, const float* part,
-                                                           int nb, float n_u, float* feat) {
+                                                           int nb, float n_u, float* feat, float* sqd) {
     __shared__ float red[kThreads / kWave];
     const float mean = sum_partials(part, nb, red) / n_u;
     const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x; l < n; l += stride)
+    for (int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x; l < n; l += stride) {
         feat[l] = dmask[l] ? 0.f : -logf(dinv[l]) - mean;
+        sqd[l] = dmask[l] ? 0.f : sqrtf(dinv[l]);
+    }
 }
 
 int nblocks_for(int64_t n, int cap) {
@@ -1345,8 +1347,9 @@ int loss_pass(mffv_net* N, const Shape& S, const Coef& c, const March& m, const 
 namespace mffv {
 
 int nn_precondition(const mffv_net* Nc, const Geom& g, const Coef& c, const March& m, float omega,
-                    const float* r, const float* dinv, const uint8_t* dmask, float* z, const float* pb,
-                    int nb_b, const float* feat, float n_u, hipStream_t s, hipEvent_t* layer_ev) {
+                    const float* r, const float* dinv, const uint8_t* dmask, const float* sqd, float* z,
+                    const float* pb, int nb_b, const float* feat, float n_u, hipStream_t s,
+                    hipEvent_t* layer_ev) {
     mffv_net* N = const_cast<mffv_net*>(Nc);
     if (g.n > N->cap) return nfail(MFFV_ESTATE, "network workspace not prepared for this grid");
     const Shape S = shape_of(g.nx, g.ny, g.nz);
@@ -1365,6 +1368,7 @@ int nn_precondition(const mffv_net* Nc, const Geom& g, const Coef& c, const Marc
         io.omega = omega;
         io.out = N->sw1;
         io.partials = N->swp;
+        io.sw_j = N->sw2;   // omega dinv r + dinv r1, for z2
         NHIP(launch_stencil_f32(kSweep1, g, c, io, m, s));
         rin = N->sw1;
         pin = N->swp;
@@ -1389,6 +1393,27 @@ int nn_precondition(const mffv_net* Nc, const Geom& g, const Coef& c, const Marc
     hipLaunchKernelGGL(nn_input, dim3(nb), dim3(kThreads), 0, s, g.n, rin, dinv, feat,
                        (const float*)(N->sscale + 1), N->x0, (const uint8_t*)nullptr);
     NHIP(hipGetLastError());
+    if (omega > 0.f && fused) {
+        // the network's output y into N->y; the second sweep's pass forms
+        // z2 = (omega dinv r + dinv r1) + s sqrt(dinv) y (0 on Dirichlet cells,
+        // where both terms are 0) at every stencil point and writes
+        // z = z2 + omega dinv (r - A z2)
+        ConvArgs last{};
+        last.out32 = N->y;
+        int rc = forward(N, S, false, kFinal, last, s, layer_ev);
+        if (rc) return rc;
+        StencilIO<float> io;
+        io.src = N->y;
+        io.out = z;
+        io.rres = r;
+        io.dinv = dinv;
+        io.omega = omega;
+        io.sw_j = N->sw2;
+        io.sw_sq = sqd;
+        io.sw_scale = N->sscale;
+        NHIP(launch_stencil_f32(kSweep2, g, c, io, m, s));
+        return MFFV_OK;
+    }
     ConvArgs last{};
     last.out32 = omega > 0.f ? N->sw2 : z;   // z2 before the second sweep
     last.r = r;
@@ -1403,13 +1428,6 @@ int nn_precondition(const mffv_net* Nc, const Geom& g, const Coef& c, const Marc
     StencilIO<float> io;
     io.src = N->sw2;
     io.out = z;
-    if (fused) {
-        io.rres = r;
-        io.dinv = dinv;
-        io.omega = omega;
-        NHIP(launch_stencil_f32(kSweep2, g, c, io, m, s));
-        return MFFV_OK;
-    }
     NHIP(launch_stencil_f32(kApply, g, c, io, m, s));  // A z2 into z, then the update
     hipLaunchKernelGGL(sweep_post, dim3(nb), dim3(kThreads), 0, s, g.n, (const float*)N->sw2, r, dinv, dmask, omega, z);
     NHIP(hipGetLastError());
@@ -1417,12 +1435,12 @@ int nn_precondition(const mffv_net* Nc, const Geom& g, const Coef& c, const Marc
 }
 
 int nn_feature(const Geom& g, const float* dinv, const uint8_t* dmask, float n_u, float* part,
-               float* feat, hipStream_t s) {
+               float* feat, float* sqd, hipStream_t s) {
     const int nb = nblocks_for(g.n, kRedBlocks);
     hipLaunchKernelGGL(logd_partials, dim3(nb), dim3(kThreads), 0, s, g.n, dinv, dmask, part);
     NHIP(hipGetLastError());
     hipLaunchKernelGGL(feature_kernel, dim3(nb), dim3(kThreads), 0, s, g.n, dinv, dmask, (const float*)part, nb,
-                       n_u, feat);
+                       n_u, feat, sqd);
     NHIP(hipGetLastError());
     return MFFV_OK;
 }

@@ -12,12 +12,14 @@ namespace mffv {
 // with r' D^-1 r the sum of the nb_b phase-B partials pb. omega > 0: the
 // network between two damped Jacobi sweeps on the operator (g, c), applied
 // with launch shape m: z1 = omega D^-1 r, r1 = r - A z1,
-// z2 = z1 + D^-1 r1 + C(r1), z = z2 + omega D^-1 (r - A z2). Enqueued on s;
+// z2 = z1 + D^-1 r1 + C(r1), z = z2 + omega D^-1 (r - A z2) (sqd: sqrt(dinv),
+// 0 on Dirichlet cells, from nn_feature). Enqueued on s;
 // allocates nothing if nn_prepare ran. layer_ev (optional): 5 events, recorded
 // before the first convolution and after each of the four.
 int nn_precondition(const mffv_net* net, const Geom& g, const Coef& c, const March& m, float omega,
-                    const float* r, const float* dinv, const uint8_t* dmask, float* z, const float* pb,
-                    int nb_b, const float* feat, float n_u, hipStream_t s, hipEvent_t* layer_ev = nullptr);
+                    const float* r, const float* dinv, const uint8_t* dmask, const float* sqd, float* z,
+                    const float* pb, int nb_b, const float* feat, float n_u, hipStream_t s,
+                    hipEvent_t* layer_ev = nullptr);
 
 // Make sure the network's inference workspace holds n cells; returns the
 // workspace generation (changes whenever the workspace is reallocated), or a
@@ -35,8 +37,9 @@ int nn_adam(mffv_net* net, float lr, hipStream_t s);
 const double* nn_loss_ptr(const mffv_net* net);
 
 // Log-diagonal input feature of a grid: log(d) - mean over unknown cells of
-// log(d), d = 1 / dinv; 0 on Dirichlet cells. part: scratch of 1024 floats.
+// log(d), d = 1 / dinv; 0 on Dirichlet cells. Also sqd = sqrt(dinv) on unknown
+// cells, 0 on Dirichlet cells. part: scratch of 1024 floats.
 int nn_feature(const Geom& g, const float* dinv, const uint8_t* dmask, float n_u, float* part,
-               float* feat, hipStream_t s);
+               float* feat, float* sqd, hipStream_t s);
 
 }  // namespace mffv

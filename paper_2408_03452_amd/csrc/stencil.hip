@@ -313,6 +313,7 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
     const bool jm_in = jm_slot >= 0, jp_in = jp_slot < kThreads;
 
     // source value of the stencil: x, or r + beta p_old in the fused CG phase
+    const float sws = MODE == kSweep2 ? *io.sw_scale : 0.f;
     auto Z4 = [&](int64_t idx) -> float4 {
         float4 v = ld4(zsrc + idx);
         if (jz) {
@@ -323,6 +324,11 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
             const float4 d = ld4(io.dinv + idx);
             const float w = io.omega;
             v = make_float4(w * d.x * v.x, w * d.y * v.y, w * d.z * v.z, w * d.w * v.w);
+        }
+        if (MODE == kSweep2) {  // z2 from the network's output v
+            const float4 jv = ld4(io.sw_j + idx), q = ld4(io.sw_sq + idx);
+            v = make_float4(jv.x + sws * q.x * v.x, jv.y + sws * q.y * v.y, jv.z + sws * q.z * v.z,
+                            jv.w + sws * q.w * v.w);
         }
         if (rupd) v = axpy4(-alpha_prev, ld4(io.qin + idx), v);
         return v;
@@ -336,6 +342,7 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
         float v = zsrc[idx];
         if (jz) v *= io.dinv[idx];
         if (MODE == kSweep1) v = io.omega * io.dinv[idx] * v;
+        if (MODE == kSweep2) v = io.sw_j[idx] + sws * io.sw_sq[idx] * v;
         if (rupd) v -= alpha_prev * io.qin[idx];
         if (use_pold) v += beta * pold[idx];
         return v;
@@ -445,6 +452,11 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
                 const float4 r1 = make_float4(rv.x - y.x, rv.y - y.y, rv.z - y.z, rv.w - y.w);
                 st4(io.out + base, r1);
                 dot += d.x * r1.x * r1.x + d.y * r1.y * r1.y + d.z * r1.z * r1.z + d.w * r1.w * r1.w;
+                if (io.sw_j) {
+                    const float w = io.omega;
+                    st4(io.sw_j + base, make_float4(w * d.x * rv.x + d.x * r1.x, w * d.y * rv.y + d.y * r1.y,
+                                                    w * d.z * rv.z + d.z * r1.z, w * d.w * rv.w + d.w * r1.w));
+                }
             } else if (MODE == kSweep2) {
                 // z = z2 + omega dinv (r - A z2); sc is z2 at the own cells
                 const float4 rv = ld4(io.rres + base), d = ld4(io.dinv + base);
@@ -519,10 +531,12 @@ __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<
     const bool hasjm = j > 0, hasjp = j + 1 < g.ny, haskm = k > 0, haskp = k + 1 < g.nz;
     const int nz = g.nz;
 
+    const float sws = MODE == kSweep2 ? *io.sw_scale : 0.f;
     auto Z = [&](int64_t idx) -> real {
         real v = zsrc[idx];
         if (jz) v *= (real)io.dinv[idx];
         if (MODE == kSweep1) v = (real)(io.omega * io.dinv[idx]) * v;
+        if (MODE == kSweep2) v = (real)(io.sw_j[idx] + sws * io.sw_sq[idx] * (float)v);
         return v;
     };
     auto S = [&](int64_t idx) -> real {
@@ -579,7 +593,9 @@ __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<
             } else if (MODE == kSweep1) {
                 const real r1 = io.src[base] - y;
                 io.out[base] = r1;
-                dot += (real)io.dinv[base] * r1 * r1;
+                const real d = (real)io.dinv[base];
+                dot += d * r1 * r1;
+                if (io.sw_j) io.sw_j[base] = (real)io.omega * d * io.src[base] + d * r1;
             } else if (MODE == kSweep2) {
                 io.out[base] = sc + (real)(io.omega * io.dinv[base]) * (io.rres[base] - y);
             } else {
