@@ -96,6 +96,8 @@ struct mffv_grid {
     int64_t n_unknown = 0;
     float* feat = nullptr;     // learned preconditioner input feature (lazy)
     float* sqd = nullptr;      // sqrt(dinv) on unknown cells, 0 on Dirichlet cells (with feat)
+    const float* flex_part = nullptr;  // flexible-CG dot partials of the last preconditioner step
+    int flex_nb = 0;                   //   when the network's second sweep formed them
     bool feat_valid = false;
     // FP32 workspace
     float *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr, *z = nullptr, *xw = nullptr,
@@ -305,8 +307,10 @@ int enqueue_iter32(mffv_grid* G, int precond, const mffv_net* net, int nn_every 
     a.st = G->st32;
     a.pb = pb;
     a.nb_b = G->nb_vec;
-    a.pf = pf;
-    a.nb_f = G->nb_vec;
+    // the flexible-CG dots of the previous preconditioner step: from the
+    // fused second sweep (network-owned partials) or from flex_dots
+    a.pf = G->flex_part ? G->flex_part : pf;
+    a.nb_f = G->flex_part ? G->flex_nb : G->nb_vec;
     a.precond = precond;
     a.dinv = G->dinv;
     a.rres = G->r;
@@ -329,15 +333,23 @@ int enqueue_iter32(mffv_grid* G, int precond, const mffv_net* net, int nn_every 
     if (ev) HIP_TRY(hipEventRecord(ev[2], G->stream));
     if (precond == MFFV_PRECOND_LEARNED) {
         if (use_nn) {
-            int rc = nn_precondition(net, G->g, coef_of(G), G->m_apply, omega, G->r, G->dinv, G->dmask, G->sqd,
-                                     G->z, pb + G->nb_vec, G->nb_vec, G->feat, (float)G->n_unknown, G->stream, nev);
+            const float* fp = nullptr;
+            int nbf = 0;
+            int rc = nn_precondition(net, G->g, coef_of(G), G->m32, omega, G->r, G->dinv, G->dmask, G->sqd,
+                                     G->z, pb + G->nb_vec, G->nb_vec, G->feat, (float)G->n_unknown, G->stream,
+                                     G->q, &fp, &nbf, nev);
             if (rc) return rc;
+            G->flex_part = fp;
+            G->flex_nb = nbf;
         } else {
             HIP_TRY(launch_jacobi_z(G->g.n, G->r, G->dinv, G->dmask, G->z, G->stream));
+            G->flex_part = nullptr;
         }
-        VecIO<float> f = v;
-        f.partials = pf;
-        HIP_TRY(launch_flex_dots_f32(G->g.n, f, G->nb_vec, G->stream));
+        if (!G->flex_part) {
+            VecIO<float> f = v;
+            f.partials = pf;
+            HIP_TRY(launch_flex_dots_f32(G->g.n, f, G->nb_vec, G->stream));
+        }
     }
     if (ev) HIP_TRY(hipEventRecord(ev[3], G->stream));
     return MFFV_OK;
@@ -599,12 +611,19 @@ int cg32(mffv_grid* G, double tol, int max_iter, int precond, const mffv_opts& o
         return MFFV_OK;
     }
     if (precond == MFFV_PRECOND_LEARNED) {
-        int rc = nn_precondition(net, G->g, coef_of(G), G->m_apply, (float)o.nn_smooth, G->r, G->dinv, G->dmask,
-                                 G->sqd, G->z, pb + G->nb_vec, G->nb_vec, G->feat, (float)G->n_unknown, G->stream);
+        const float* fp = nullptr;
+        int nbf = 0;
+        int rc = nn_precondition(net, G->g, coef_of(G), G->m32, (float)o.nn_smooth, G->r, G->dinv, G->dmask,
+                                 G->sqd, G->z, pb + G->nb_vec, G->nb_vec, G->feat, (float)G->n_unknown, G->stream,
+                                 nullptr, &fp, &nbf);
         if (rc) return rc;
-        VecIO<float> f = v;
-        f.partials = reinterpret_cast<float*>(G->partF);
-        HIP_TRY(launch_flex_dots_f32(G->g.n, f, G->nb_vec, G->stream));
+        G->flex_part = fp;
+        G->flex_nb = nbf;
+        if (!fp) {
+            VecIO<float> f = v;
+            f.partials = reinterpret_cast<float*>(G->partF);
+            HIP_TRY(launch_flex_dots_f32(G->g.n, f, G->nb_vec, G->stream));
+        }
     }
     const int nn_every = precond == MFFV_PRECOND_LEARNED ? std::max(1, o.nn_every) : 1;
     const float omega = precond == MFFV_PRECOND_LEARNED ? (float)o.nn_smooth : 0.f;

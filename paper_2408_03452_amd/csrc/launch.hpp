@@ -64,6 +64,9 @@ struct StencilIO {
     float* sw_j = nullptr;             // kSweep1: written; kSweep2: read (see above)
     const float* sw_sq = nullptr;      // kSweep2: sqrt(dinv), 0 on Dirichlet cells
     const float* sw_scale = nullptr;   //   the network's scale s (device scalar)
+    float* sw_flex = nullptr;          //   optional: per-block partials [4][blocks] of the
+                                       //   flexible-CG dots z.r, z.q, dinv r.r, dinv r.q
+    const float* sw_q = nullptr;       //   q for those dots (NULL: the z.q and r.q sums are 0)
 };
 
 // kSweep1 / kSweep2: the damped Jacobi sweeps around the learned

@@ -1056,6 +1056,7 @@ struct mffv_net {
     float* sw1 = nullptr;     // inference: the Jacobi sweeps' vectors (FP32 cells)
     float* sw2 = nullptr;
     float* swp = nullptr;     // per-block partials of the first sweep (swp_cap of them)
+    float* swf = nullptr;     // per-block partials of the flexible-CG dots, [4][swp_cap]
     int64_t swp_cap = 0;
     float* t1 = nullptr;      // training scratch (FP32 cells)
     float* t2 = nullptr;
@@ -1096,10 +1097,11 @@ void nfree(T*& p) {
 }
 
 constexpr int kRedBlocks = 1024;
+constexpr int kFlexBlocks = 1024;  // target count of the fused flexible-CG dot partials
 
 void free_ws(mffv_net* N) {
     nfree(N->x0); nfree(N->h1); nfree(N->h2); nfree(N->h3); nfree(N->g1); nfree(N->g2);
-    nfree(N->dy4); nfree(N->y); nfree(N->t1); nfree(N->t2); nfree(N->sw1); nfree(N->sw2); nfree(N->swp);
+    nfree(N->dy4); nfree(N->y); nfree(N->t1); nfree(N->t2); nfree(N->sw1); nfree(N->sw2); nfree(N->swp); nfree(N->swf);
     N->cap = 0;
     N->swp_cap = 0;
     N->training_ws = false;
@@ -1114,7 +1116,7 @@ int ensure_ws(mffv_net* N, int64_t n, bool training) {
     if ((rc = nalloc(&N->x0, (size_t)cap * 2)) || (rc = nalloc(&N->h1, (size_t)cap * 16)) ||
         (rc = nalloc(&N->h2, (size_t)cap * 16)) || (rc = nalloc(&N->y, (size_t)cap)) ||
         (rc = nalloc(&N->sw1, (size_t)cap)) || (rc = nalloc(&N->sw2, (size_t)cap)) ||
-        (rc = nalloc(&N->swp, (size_t)(cap / 256 + 8192)))) {
+        (rc = nalloc(&N->swp, (size_t)(cap / 256 + 8192))) || (rc = nalloc(&N->swf, 4 * (size_t)(cap / 256 + 8192)))) {
         free_ws(N);
         return nfail(rc, "network workspace allocation failed");
     }
@@ -1349,7 +1351,9 @@ namespace mffv {
 int nn_precondition(const mffv_net* Nc, const Geom& g, const Coef& c, const March& m, float omega,
                     const float* r, const float* dinv, const uint8_t* dmask, const float* sqd, float* z,
                     const float* pb, int nb_b, const float* feat, float n_u, hipStream_t s,
-                    hipEvent_t* layer_ev) {
+                    const float* q, const float** flex_part, int* nb_flex, hipEvent_t* layer_ev) {
+    *flex_part = nullptr;
+    *nb_flex = 0;
     mffv_net* N = const_cast<mffv_net*>(Nc);
     if (g.n > N->cap) return nfail(MFFV_ESTATE, "network workspace not prepared for this grid");
     const Shape S = shape_of(g.nx, g.ny, g.nz);
@@ -1411,7 +1415,18 @@ int nn_precondition(const mffv_net* Nc, const Geom& g, const Coef& c, const Marc
         io.sw_j = N->sw2;
         io.sw_sq = sqd;
         io.sw_scale = N->sscale;
-        NHIP(launch_stencil_f32(kSweep2, g, c, io, m, s));
+        io.sw_flex = N->swf;
+        io.sw_q = q;
+        // every block of the next phase A sums these partials: at most about
+        // kFlexBlocks of them (more planes per block if the plan has more)
+        March m2 = m;
+        if (m.blocks() > kFlexBlocks) {
+            const int f = (m.blocks() + kFlexBlocks - 1) / kFlexBlocks;
+            m2 = plan_march(g, m.vec, std::min(g.nx, m.ci * f), m.remap, m.nseg ? m.seg : -1);
+        }
+        NHIP(launch_stencil_f32(kSweep2, g, c, io, m2, s));
+        *flex_part = N->swf;
+        *nb_flex = m2.blocks();
         return MFFV_OK;
     }
     ConvArgs last{};

@@ -16,10 +16,15 @@ namespace mffv {
 // 0 on Dirichlet cells, from nn_feature). Enqueued on s;
 // allocates nothing if nn_prepare ran. layer_ev (optional): 5 events, recorded
 // before the first convolution and after each of the four.
+// With the sweeps fused into the operator passes, the second one also forms
+// the per-block partials of the flexible-CG dots (z.r, z.q, dinv r.r, dinv r.q;
+// q may be NULL, then those of q are 0): *flex_part and *nb_flex receive them
+// (network-owned, [4][nb_flex]); otherwise *flex_part is NULL and the caller
+// forms the dots itself.
 int nn_precondition(const mffv_net* net, const Geom& g, const Coef& c, const March& m, float omega,
                     const float* r, const float* dinv, const uint8_t* dmask, const float* sqd, float* z,
                     const float* pb, int nb_b, const float* feat, float n_u, hipStream_t s,
-                    hipEvent_t* layer_ev = nullptr);
+                    const float* q, const float** flex_part, int* nb_flex, hipEvent_t* layer_ev = nullptr);
 
 // Make sure the network's inference workspace holds n cells; returns the
 // workspace generation (changes whenever the workspace is reallocated), or a

@@ -461,8 +461,18 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
                 // z = z2 + omega dinv (r - A z2); sc is z2 at the own cells
                 const float4 rv = ld4(io.rres + base), d = ld4(io.dinv + base);
                 const float w = io.omega;
-                st4(io.out + base, make_float4(sc.x + w * d.x * (rv.x - y.x), sc.y + w * d.y * (rv.y - y.y),
-                                               sc.z + w * d.z * (rv.z - y.z), sc.w + w * d.w * (rv.w - y.w)));
+                const float4 zo = make_float4(sc.x + w * d.x * (rv.x - y.x), sc.y + w * d.y * (rv.y - y.y),
+                                              sc.z + w * d.z * (rv.z - y.z), sc.w + w * d.w * (rv.w - y.w));
+                st4(io.out + base, zo);
+                if (io.sw_flex) {  // dot, d_rr, d_rq, d_qq hold z.r, z.q, dinv r.r, dinv r.q here
+                    dot += zo.x * rv.x + zo.y * rv.y + zo.z * rv.z + zo.w * rv.w;
+                    d_rq += d.x * rv.x * rv.x + d.y * rv.y * rv.y + d.z * rv.z * rv.z + d.w * rv.w * rv.w;
+                    if (io.sw_q) {
+                        const float4 qv = ld4(io.sw_q + base);
+                        d_rr += zo.x * qv.x + zo.y * qv.y + zo.z * qv.z + zo.w * qv.w;
+                        d_qq += d.x * rv.x * qv.x + d.y * rv.y * qv.y + d.z * rv.z * qv.z + d.w * rv.w * qv.w;
+                    }
+                }
             } else {  // residual r = b - A x
                 float4 bb;
                 if (io.rhs_f64) {
@@ -484,6 +494,18 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
     if (MODE == kFusedCg || MODE == kSweep1) {
         const float tot = block_sum(dot, red);
         if (threadIdx.x == 0) io.partials[blockIdx.x] = tot;
+    } else if (MODE == kSweep2) {
+        if (io.sw_flex) {  // z.r, z.q, dinv r.r, dinv r.q (the order flex_dots writes)
+            const int nb = gridDim.x;
+            const float a0 = block_sum(dot, red), a1 = block_sum(d_rr, red), a2 = block_sum(d_rq, red),
+                        a3 = block_sum(d_qq, red);
+            if (threadIdx.x == 0) {
+                io.sw_flex[blockIdx.x] = a0;
+                io.sw_flex[nb + blockIdx.x] = a1;
+                io.sw_flex[2 * nb + blockIdx.x] = a2;
+                io.sw_flex[3 * nb + blockIdx.x] = a3;
+            }
+        }
     } else if (MODE == kMergedCg) {
         const int nb = gridDim.x;
         const float a0 = block_sum(dot, red), a1 = block_sum(d_rr, red), a2 = block_sum(d_rq, red),
@@ -545,7 +567,7 @@ __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<
         return v;
     };
 
-    real dot = 0;
+    real dot = 0, f_zq = 0, f_jr = 0, f_jq = 0;  // kSweep2: the flexible-CG dots
     if (valid && i0 < i1) {
         int64_t base = (int64_t)i0 * P + r0;
         real poc = use_pold ? pold[base] : real(0);
@@ -597,7 +619,18 @@ __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<
                 dot += d * r1 * r1;
                 if (io.sw_j) io.sw_j[base] = (real)io.omega * d * io.src[base] + d * r1;
             } else if (MODE == kSweep2) {
-                io.out[base] = sc + (real)(io.omega * io.dinv[base]) * (io.rres[base] - y);
+                const real rv = io.rres[base], d = (real)io.dinv[base];
+                const real zo = sc + (real)io.omega * d * (rv - y);
+                io.out[base] = zo;
+                if (io.sw_flex) {
+                    dot += zo * rv;
+                    f_jr += d * rv * rv;
+                    if (io.sw_q) {
+                        const real qv = io.sw_q[base];
+                        f_zq += zo * qv;
+                        f_jq += d * rv * qv;
+                    }
+                }
             } else {
                 const real bb = io.rhs_f64 ? (real) static_cast<const double*>(io.rhs)[base]
                                            : (real) static_cast<const float*>(io.rhs)[base];
@@ -615,6 +648,17 @@ __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<
     if (MODE == kFusedCg || MODE == kSweep1 || (MODE == kResidual && io.partials != nullptr)) {
         const real tot = block_sum(dot, red);
         if (threadIdx.x == 0) io.partials[blockIdx.x] = tot;
+    }
+    if (MODE == kSweep2 && io.sw_flex) {
+        const int nb = gridDim.x;
+        const real a0 = block_sum(dot, red), a1 = block_sum(f_zq, red), a2 = block_sum(f_jr, red),
+                   a3 = block_sum(f_jq, red);
+        if (threadIdx.x == 0) {
+            io.sw_flex[blockIdx.x] = (float)a0;
+            io.sw_flex[nb + blockIdx.x] = (float)a1;
+            io.sw_flex[2 * nb + blockIdx.x] = (float)a2;
+            io.sw_flex[3 * nb + blockIdx.x] = (float)a3;
+        }
     }
 }
 
