@@ -88,6 +88,7 @@ typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t pack_bf2(float lo, float hi) {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f){lo, hi}, v2bf));
 }
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint16_t f2bf(float f) { return (uint16_t)pack_bf2(f, 0.f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -155,6 +156,10 @@ typedef __attribute__((address_space(3))) void lds_void;
 // Source of the halo cells outside the grid and of the planes past a block's
 // run: 16 zero bytes.
 __device__ __attribute__((aligned(16))) uint32_t g_zero16[4];
+// Buffer resource word 3 (CDNA: untyped 32-bit data format, raw addressing)
+// and the cache-policy bit of a nontemporal access.
+constexpr int kBufWord3 = 0x00020000;
+constexpr int kNonTemporal = 2;
 // Destination of the stores of lanes without an output cell: every store
 // instruction is issued by every wave that has a row, so the number of memory
 // operations a wave has in flight is known at each step.
@@ -194,6 +199,22 @@ __device__ __forceinline__ void dma_offsets(const Geom& g, int j0, int k0, int d
     }
 }
 
+// One LDS DMA instruction: every lane moves BYTES from src to the wave's
+// destination + lane * BYTES (M0 holds the destination; the nop separates
+// the M0 write from its use). Written as asm,
+// with no output register: the compiler then does not know of an LDS write
+// in flight and keeps exact LDS wait counts for the reads of the other slots
+// (with the builtin it waits for every LDS read at once). The march waits for
+// these requests itself (wait_vmcnt, before the barrier that publishes a slot).
+template <int BYTES>
+__device__ __forceinline__ void lds_dma(const void* src, lds16* dst) {
+    const uint32_t m0 = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)dst);
+    if constexpr (BYTES == 16)
+        asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "{m0}"(m0) : "memory");
+    else
+        asm volatile("s_nop 0\n\tglobal_load_lds_dword %0, off" ::"v"(src), "{m0}"(m0) : "memory");
+}
+
 // Request haloed plane i (zeros if the block does not need it or it lies
 // outside the grid) into an LDS slot.
 template <int C>
@@ -207,8 +228,7 @@ __device__ __forceinline__ void dma_plane(const uint16_t* __restrict__ in, const
         const int grp = 4 * u + w;
         if (grp >= plane_groups<C>()) break;
         const void* src = iin && doff[u] >= 0 ? (const void*)(base + doff[u]) : (const void*)g_zero16;
-        if constexpr (C == 16) __builtin_amdgcn_global_load_lds(src, (lds_void*)(slot + grp * 64 * 8), 16, 0, 0);
-        else __builtin_amdgcn_global_load_lds(src, (lds_void*)(slot + grp * 64 * 2), 4, 0, 0);
+        lds_dma<C == 16 ? 16 : 4>(src, slot + grp * 64 * (C == 16 ? 8 : 2));
     }
 }
 
@@ -270,53 +290,84 @@ __device__ __forceinline__ v8s slab(const lds16* base, const int so[3], const Sl
 }
 
 // One wave's 64-cell output row of a 16 -> 16 convolution (z taps on the
-// output side): lane (q, n) ends with output channels 4q..4q+3 of cell n of
-// each of the four tiles. wr: 15 operands, index 3 P + dz + 1.
-__device__ __forceinline__ void conv_row16(const lds16* base, const int so[3], const v8s* wr, v4f y[4]) {
+// output side), tile by tile: tile t's products Q_dz = W_dz x (dz = -1, 0, 1)
+// over the five group pairs, then y[z] = Q_-1[z-1] + Q_0[z] + Q_+1[z+1]
+// across the 16-lane rows of cells. Tile t - 1 is finished, and handed to
+// epi(t - 1, y) (lane (q, n): output channels 4q..4q+3 of cell n of that
+// tile), once tile t's Q_+1 exists; its vector work is independent of tile
+// t + 1's products, so the two overlap. The halo tile holds the cell before
+// the row (column 15, dz = -1) and the cell after it (the other columns,
+// dz = +1); hb / ha: those cells lie in the grid (outside it they are zeros
+// and their products are skipped). wr: 15 operands, index 3 P + dz + 1.
+template <class Epi>
+__device__ __forceinline__ void conv_row16(const lds16* base, const int so[3], const v8s* wr, bool hb, bool ha,
+                                           Epi&& epi) {
+    typedef __attribute__((address_space(3))) const v8s lds_v8s;
     const int n = threadIdx.x & 15;
-    v4f Q[4][3], H[2];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) Q[t][d] = v4f{0.f, 0.f, 0.f, 0.f};
-    H[0] = H[1] = v4f{0.f, 0.f, 0.f, 0.f};
-    // the next pair's slabs are read while the matrix cores work on this
-    // pair's (two sets in registers; the scheduling barriers keep the
-    // compiler from hoisting more and running out of registers)
-    v8s B[2][5];
-    {
-        const SlabAt at = slab_at(0);
-#pragma unroll
-        for (int t = 0; t < 5; ++t) B[0][t] = slab(base, so, at, t);
-    }
+    int ad[kPairs], ah[kPairs];
 #pragma unroll
     for (int P = 0; P < kPairs; ++P) {
-        __builtin_amdgcn_sched_barrier(0);
-        const int cur = P & 1;
-        if (P + 1 < kPairs) {
-            const SlabAt at = slab_at(P + 1);
-#pragma unroll
-            for (int t = 0; t < 5; ++t) B[cur ^ 1][t] = slab(base, so, at, t);
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) Q[t][d] = mfma32(wr[3 * P + d], B[cur][t], Q[t][d]);
-        H[0] = mfma32(wr[3 * P + 0], B[cur][4], H[0]);   // dz = -1 at the cell before the row (column 15)
-        H[1] = mfma32(wr[3 * P + 2], B[cur][4], H[1]);   // dz = +1 at the cell after the row (column 0)
-        // the next pair's reads first, then this pair's products
-        if (P + 1 < kPairs) __builtin_amdgcn_sched_group_barrier(0x100, 5, 0);
-        __builtin_amdgcn_sched_group_barrier(0x008, 14, 0);
+        const SlabAt at = slab_at(P);
+        ad[P] = so[at.dx] + at.off;
+        ah[P] = so[at.dx] + at.halo;
     }
-    // y[z] = Q_-1[z-1] + Q_0[z] + Q_+1[z+1] across the 16-lane rows of cells
+    auto rd = [&](int off) { return *reinterpret_cast<lds_v8s*>(base + off); };
+    // the row's 20 slabs in the order they are used (s = 5 t + P), read two
+    // ahead of their products through a ring of three
+    auto slab_off = [&](int s) { return ad[s % kPairs] + 256 * (s / kPairs); };  // 16 cells further per tile
+    v8s ring[3];
+    ring[0] = rd(slab_off(0));
+    ring[1] = rd(slab_off(1));
+    v4f H0 = v4f{0.f, 0.f, 0.f, 0.f}, H1 = H0;
+    if (hb || ha) {
+        v8s bh[kPairs];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+        for (int P = 0; P < kPairs; ++P) bh[P] = rd(ah[P]);
+        // (straight-line code per case)
+        if (hb && ha) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const float lsel = n == 15 ? (t > 0 ? Q[t - 1][0][v] : H[0][v]) : Q[t][0][v];
-            const float rsel = n == 0 ? (t < 3 ? Q[t + 1][2][v] : H[1][v]) : Q[t][2][v];
-            y[t][v] = Q[t][1][v] + dpp_ror1(lsel) + dpp_rol1(rsel);
+            for (int P = 0; P < kPairs; ++P) {
+                H0 = mfma32(wr[3 * P + 0], bh[P], H0);
+                H1 = mfma32(wr[3 * P + 2], bh[P], H1);
+            }
+        } else if (hb) {
+#pragma unroll
+            for (int P = 0; P < kPairs; ++P) H0 = mfma32(wr[3 * P + 0], bh[P], H0);
+        } else {
+#pragma unroll
+            for (int P = 0; P < kPairs; ++P) H1 = mfma32(wr[3 * P + 2], bh[P], H1);
         }
+    }
+    v4f L = H0, A, R;  // previous tile: its dz = -1 products, Q_0 + left part, dz = +1 products
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        v4f Q0 = v4f{0.f, 0.f, 0.f, 0.f}, Q1 = Q0, Q2 = Q0;
+#pragma unroll
+        for (int P = 0; P < kPairs; ++P) {
+            const int sidx = kPairs * t + P;
+            if (sidx + 2 < 4 * kPairs) ring[(sidx + 2) % 3] = rd(slab_off(sidx + 2));
+            const v8s b = ring[sidx % 3];
+            Q0 = mfma32(wr[3 * P + 0], b, Q0);
+            Q1 = mfma32(wr[3 * P + 1], b, Q1);
+            Q2 = mfma32(wr[3 * P + 2], b, Q2);
+            if (sidx + 2 < 4 * kPairs) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);
+        }
+        if (t > 0) {
+            v4f y;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) y[v] = A[v] + dpp_rol1(n == 0 ? Q2[v] : R[v]);
+            epi(t - 1, y);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) A[v] = Q1[v] + dpp_ror1(n == 15 ? L[v] : Q0[v]);
+        R = Q2;
+        L = Q0;
+    }
+    v4f y;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) y[v] = A[v] + dpp_rol1(n == 0 ? H1[v] : R[v]);
+    epi(3, y);
 }
 
 // Per-lane offsets (uint16 units from the slot of plane i - 1) of the eight
@@ -470,7 +521,7 @@ __device__ __forceinline__ void conv_step(const Geom& g, const ConvArgs& a, cons
                                           const lds16* __restrict__ rd, lds16* __restrict__ rq) {
     constexpr int SLOT = slot_u16<C>();
     constexpr bool kLast = MODE == kFinal || MODE == kPrecond;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int m = lane & 15, rg = lane >> 4;
     const int j = j0 + w;
     const float floor_act = a.relu ? 0.f : -INFINITY;   // hidden activation: max(x, floor)
@@ -525,19 +576,20 @@ __device__ __forceinline__ void conv_step(const Geom& g, const ConvArgs& a, cons
             }
         }
     } else {
-        v4f acc[4];
-        if constexpr (C == 16) conv_row16(rd, so, wr, acc);
-        else conv_row2(rd + so[0], toff, wr, acc);
-        uint2 out[4];
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
+        // the row as a buffer of nz cells: the stores of lanes past its end
+        // fall outside the buffer's range and are dropped
+        const __amdgpu_buffer_rsrc_t orow = __builtin_amdgcn_make_buffer_rsrc(a.out16 + row * 16, 0, g.nz * 32, kBufWord3);
+        const int vo = (k0 + m) * 32 + rg * 8;  // bytes: cell k0 + m, channels 4 rg..4 rg + 3
+        // epilogue of one 16-cell tile mt of the row: bias + activation (or the
+        // input gradient's ReLU mask), BF16, one 8-byte store per lane
+        auto epi = [&](int mt, const v4f& acc) {
             float h[4];
             // Both epilogues are branch-free: hipcc (ROCm 7.2) miscompiled a
             // per-lane select between the accumulator and 0 written with a
             // branch here (the accumulator register was cleared on every lane).
             if (MODE == kHiddenRelu) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) h[q] = fmaxf(acc[mt][q] + bias[q], floor_act);
+                for (int q = 0; q < 4; ++q) h[q] = fmaxf(acc[q] + bias[q], floor_act);
             } else {
                 const uint2 bl = eb[mt];
                 // ReLU mask: keep the gradient where the activation below is > 0
@@ -547,23 +599,21 @@ __device__ __forceinline__ void conv_step(const Geom& g, const ConvArgs& a, cons
                 for (int q = 0; q < 4; ++q) {
                     const uint32_t pos = (uint32_t)((int32_t)bw[q] > 0);
                     const uint32_t keep = 0u - (pos | keep_all);
-                    h[q] = __uint_as_float(__float_as_uint(acc[mt][q]) & keep);
+                    h[q] = __uint_as_float(__float_as_uint(acc[q]) & keep);
                 }
             }
-            out[mt] = make_uint2(pack_bf2(h[0], h[1]), pack_bf2(h[2], h[3]));
-        }
-        if (k0 + TZ <= g.nz) {
-            uint2* dst = reinterpret_cast<uint2*>(a.out16 + (row + k0 + m) * 16 + rg * 4);
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt) dst[64 * mt] = out[mt];  // 16 cells further per tile
+            const u32x2 out = {pack_bf2(h[0], h[1]), pack_bf2(h[2], h[3])};
+            // 16 cells further per tile; the next layer reads these from
+            // memory: streaming (nontemporal) stores
+            __builtin_amdgcn_raw_buffer_store_b64(out, orow, vo + 512 * mt, 0, kNonTemporal);
+        };
+        if constexpr (C == 16) {
+            conv_row16(rd, so, wr, k0 > 0, k0 + TZ < g.nz, epi);
         } else {
+            v4f acc[4];
+            conv_row2(rd + so[0], toff, wr, acc);
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                const int k = k0 + mt * 16 + m;
-                uint2* dst = k < g.nz ? reinterpret_cast<uint2*>(a.out16 + (row + k) * 16 + rg * 4)
-                                      : reinterpret_cast<uint2*>(g_trash) + lane;
-                *dst = out[mt];
-            }
+            for (int mt = 0; mt < 4; ++mt) epi(mt, acc[mt]);
         }
     }
 }
