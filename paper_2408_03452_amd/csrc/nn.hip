@@ -141,7 +141,10 @@ __device__ __forceinline__ void load_halo(const uint16_t* __restrict__ in, const
 // slots (global_load_lds, no registers in between); plane p is requested at
 // the start of step p - kAhead, so while the matrix cores work on plane i
 // (slots of planes i-1, i, i+1) the planes up to i + kAhead are in flight.
-constexpr int kRingSlots = 6;
+// Four slots (plane p is requested one step before it is needed) keep a
+// block's LDS at 52 KiB, so that three blocks (three waves per SIMD) fit a
+// CU: measured faster than six slots at two blocks per CU.
+constexpr int kRingSlots = 4;
 constexpr int kAhead = kRingSlots - 2;  // the slot of plane p + kAhead was last read at step p - 1
 constexpr int PCELLS = HY * HZ;         // cells of one haloed plane
 
@@ -618,9 +621,10 @@ __device__ __forceinline__ void conv_step(const Geom& g, const ConvArgs& a, cons
     }
 }
 
-// grid: ncols * ceil(nx / run) blocks of kThreads.
+// grid: ncols * ceil(nx / run) blocks of kThreads; at most 168 VGPRs, three
+// waves per SIMD.
 template <int C, int MODE>
-__global__ __launch_bounds__(kThreads) void conv3d(Geom g, ConvArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void conv3d(Geom g, ConvArgs a) {
     // 2-channel input: the ring's slots 0 and 1 are mirrored past its end, so
     // that planes i-1, i, i+1 always sit in three consecutive slots
     constexpr int kSlots = C == 2 ? kRingSlots + 2 : kRingSlots;
