@@ -164,6 +164,44 @@ __device__ __forceinline__ T sum_partials(const T* parts, int nparts, T* lds) {
     return block_sum(s, lds);
 }
 
+// N sums of partials at once, each in sum_partials' order (so each result
+// has the same bits as sum_partials of that array), with one pass over the
+// arrays and one block tree: the loads of all arrays are in flight together.
+// An array with count 0 sums to 0. lds: N * kThreads / kWave entries.
+template <class T, int N>
+__device__ __forceinline__ void sum_partials_n(const T* const (&parts)[N], const int (&counts)[N], T* lds,
+                                               T (&out)[N]) {
+    T s[N];
+    int mx = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        s[j] = T(0);
+        mx = counts[j] > mx ? counts[j] : mx;
+    }
+    for (int i = threadIdx.x; i < mx; i += kThreads) {
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+            if (i < counts[j]) s[j] += parts[j][i];
+    }
+    constexpr int NW = kThreads / kWave;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+#pragma unroll
+    for (int j = 0; j < N; ++j) s[j] = wave_sum(s[j]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) lds[j * NW + w] = s[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        T t = T(0);
+#pragma unroll
+        for (int i = 0; i < NW; ++i) t += lds[j * NW + i];
+        out[j] = t;
+    }
+}
+
 __device__ __forceinline__ bool first_thread() { return blockIdx.x == 0 && threadIdx.x == 0; }
 
 // Read a flag once per block (thread 0) and share it through LDS, so that all

@@ -95,23 +95,27 @@ __device__ bool phase_a_start(const StencilIO<real>& io, real* lds, PhaseA<real>
     CgState<real>* st = io.st;
     if (block_flag(&st->done)) return false;
     const int k = st->iterA;
-    const real rr = sum_partials(io.pb, io.nb_b, lds);
+    // r.r; Jacobi: r.z; at k = 0: ||b_U||^2; flexible CG: the preconditioner's
+    // z.r, z.q and the Jacobi safeguard's dinv r.r, dinv r.q; summed together
+    const int nb = io.nb_b, nf = io.precond == 2 ? io.nb_f : 0;
+    const real* parts[7] = {io.pb, io.pb + nb, io.pb + 2 * nb, io.pf, io.pf + nf, io.pf + 2 * nf, io.pf + 3 * nf};
+    const int counts[7] = {nb, io.precond == 1 ? nb : 0, k == 0 ? nb : 0, nf, nf, nf, nf};
+    real sums[7];
+    sum_partials_n(parts, counts, lds, sums);
+    const real rr = sums[0];
     real rho = rr, zq = 0;
     bool fallback = false;
     if (io.precond == 1) {
-        rho = sum_partials(io.pb + io.nb_b, io.nb_b, lds);
+        rho = sums[1];
     } else if (io.precond == 2) {
-        const real zr = sum_partials(io.pf, io.nb_f, lds);
-        const real zqv = sum_partials(io.pf + io.nb_f, io.nb_f, lds);
-        const real jr = sum_partials(io.pf + 2 * io.nb_f, io.nb_f, lds);
-        const real jq = sum_partials(io.pf + 3 * io.nb_f, io.nb_f, lds);
+        const real zr = sums[3], zqv = sums[4], jr = sums[5], jq = sums[6];
         fallback = !(zr > real(0)) || !isfinite(zr) || !isfinite(zqv);
         rho = fallback ? jr : zr;
         zq = fallback ? jq : zqv;
     }
     real thresh2 = st->thresh2, bnorm2 = st->bnorm2;
     if (k == 0) {
-        const real bb = sum_partials(io.pb + 2 * io.nb_b, io.nb_b, lds);
+        const real bb = sums[2];
         bnorm2 = bb > real(0) ? bb : rr;
         thresh2 = st->tol2 * bnorm2;
     }
@@ -235,7 +239,7 @@ __device__ bool merged_start(const StencilIO<float>& io, float* lds, MergedPh& o
 // ---------------------------------------------------------------------------
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO<float> io, March m) {
-    __shared__ float red[kThreads / kWave];
+    __shared__ float red[7 * kThreads / kWave];  // phase_a_start sums 7 arrays at once
     // the chunk's own source values and y faces of the current plane (double
     // buffered): y neighbours inside the chunk are read from here, only the
     // rows just outside it from memory
@@ -524,7 +528,7 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
 // ---------------------------------------------------------------------------
 template <class real, int MODE>
 __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<real> io, March m) {
-    __shared__ real red[kThreads / kWave];
+    __shared__ real red[7 * kThreads / kWave];  // phase_a_start sums 7 arrays at once
 
     PhaseA<real> ph{0, real(0), real(0), real(0), false};
     if (MODE == kFusedCg && !phase_a_start(io, red, ph)) return;
@@ -734,7 +738,7 @@ __global__ __launch_bounds__(kThreads) void stencil_csr(int64_t n, Coef c, Stenc
 // vector. The second finds the iteration in the state the first recorded.
 template <class real>
 __global__ __launch_bounds__(kThreads) void csr_direction(int64_t n, StencilIO<real> io) {
-    __shared__ real red[kThreads / kWave];
+    __shared__ real red[7 * kThreads / kWave];  // phase_a_start sums 7 arrays at once
     PhaseA<real> ph{0, real(0), real(0), real(0), false};
     if (!phase_a_start(io, red, ph)) return;
     const int it = ph.k;
