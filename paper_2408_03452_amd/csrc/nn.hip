@@ -69,8 +69,9 @@ static_assert(kNParams == 15169, "parameter count");
 // forward and input-gradient (mirrored taps, channel roles swapped).
 //  2-channel input (layer 1, input gradient of layer 4): 2 operands, K = 64
 //    (tap, channel) pairs, k = 2 tap + channel.
-//  16-channel input, 16 outputs: 5 pairs of (dx, dy) groups x 3 dz operands
-//    (pair P: groups 2P and 2P+1 in K halves; group 9 is all zero).
+//  16-channel input, 16 outputs: 4 pairs of (dx, dy) groups x 3 dz operands
+//    (pair P: groups 2P and 2P+1 in K halves), then group 8 with its z taps
+//    in K: [W_-1 | W_0] and [W_+1 | 0] (a 15th, zero operand keeps the stride).
 //  16-channel input, 1 output (layer 4): 5 pair operands with rows = dz + 1.
 constexpr int kPairs = 5;
 constexpr int kWf1 = 0;
@@ -292,53 +293,65 @@ __device__ __forceinline__ v8s slab(const lds16* base, const int so[3], const Sl
     return *reinterpret_cast<lds_v8s*>(base + so[a.dx] + (t < 4 ? a.off + 256 * t : a.halo));
 }
 
-// One wave's 64-cell output row of a 16 -> 16 convolution (z taps on the
-// output side), tile by tile: tile t's products Q_dz = W_dz x (dz = -1, 0, 1)
-// over the five group pairs, then y[z] = Q_-1[z-1] + Q_0[z] + Q_+1[z+1]
-// across the 16-lane rows of cells. Tile t - 1 is finished, and handed to
-// epi(t - 1, y) (lane (q, n): output channels 4q..4q+3 of cell n of that
-// tile), once tile t's Q_+1 exists; its vector work is independent of tile
-// t + 1's products, so the two overlap. The halo tile holds the cell before
-// the row (column 15, dz = -1) and the cell after it (the other columns,
-// dz = +1); hb / ha: those cells lie in the grid (outside it they are zeros
-// and their products are skipped). wr: 15 operands, index 3 P + dz + 1.
+// One wave's 64-cell output row of a 16 -> 16 convolution, tile by tile.
+// Group pairs 0-3 ((dx, dy) groups 0-7) take the z taps on the output side:
+// Q_dz = W_dz x (dz = -1, 0, 1), y[z] = Q_-1[z-1] + Q_0[z] + Q_+1[z+1] across
+// the 16-lane rows of cells. Group 8 takes them on the input side, in two
+// products into Q_0: [W_-1 | W_0] [x(z-1); x(z)] and [W_+1 | 0] [x(z+1); -]
+// (14 products a tile instead of 15 with a half-empty fifth pair, and no halo
+// products for group 8). Tile t - 1 is finished, and handed to epi(t - 1, y)
+// (lane (q, n): output channels 4q..4q+3 of cell n of that tile), once tile
+// t's Q_+1 exists; its vector work is independent of tile t + 1's products,
+// so the two overlap. The halo tile holds the cell before the row (column
+// 15, dz = -1) and the cell after it (the other columns, dz = +1) for pairs
+// 0-3; hb / ha: those cells lie in the grid (outside it they are zeros and
+// their products are skipped). wr: 14 operands, 3 P + dz + 1 for P < 4, then
+// group 8's two.
 template <class Epi>
 __device__ __forceinline__ void conv_row16(const lds16* base, const int so[3], const v8s* wr, bool hb, bool ha,
                                            Epi&& epi) {
     typedef __attribute__((address_space(3))) const v8s lds_v8s;
-    const int n = threadIdx.x & 15;
-    int ad[kPairs], ah[kPairs];
+    constexpr int kOut = kPairs - 1;  // pairs with the z taps on the output side
+    constexpr int kPer = kOut + 2;    // slab reads per tile
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int n = lane & 15, q = lane >> 4;
+    int ad[kPer], ah[kOut];
 #pragma unroll
-    for (int P = 0; P < kPairs; ++P) {
+    for (int P = 0; P < kOut; ++P) {
         const SlabAt at = slab_at(P);
         ad[P] = so[at.dx] + at.off;
         ah[P] = so[at.dx] + at.halo;
     }
+    {   // group 8 (dx = +1, dy = +1): cell n - 1 | n, then cell n + 1, of tile 0
+        const int row = (w + 2) * HZ, h = q & 1;
+        ad[kOut] = so[2] + half_pos(row + n + (q >> 1), h);
+        ad[kOut + 1] = so[2] + half_pos(row + n + 2, h);
+    }
     auto rd = [&](int off) { return *reinterpret_cast<lds_v8s*>(base + off); };
-    // the row's 20 slabs in the order they are used (s = 5 t + P), read two
+    // the row's 24 slabs in the order they are used (s = 6 t + e), read two
     // ahead of their products through a ring of three
-    auto slab_off = [&](int s) { return ad[s % kPairs] + 256 * (s / kPairs); };  // 16 cells further per tile
+    auto slab_off = [&](int s) { return ad[s % kPer] + 256 * (s / kPer); };  // 16 cells further per tile
     v8s ring[3];
     ring[0] = rd(slab_off(0));
     ring[1] = rd(slab_off(1));
     v4f H0 = v4f{0.f, 0.f, 0.f, 0.f}, H1 = H0;
     if (hb || ha) {
-        v8s bh[kPairs];
+        v8s bh[kOut];
 #pragma unroll
-        for (int P = 0; P < kPairs; ++P) bh[P] = rd(ah[P]);
+        for (int P = 0; P < kOut; ++P) bh[P] = rd(ah[P]);
         // (straight-line code per case)
         if (hb && ha) {
 #pragma unroll
-            for (int P = 0; P < kPairs; ++P) {
+            for (int P = 0; P < kOut; ++P) {
                 H0 = mfma32(wr[3 * P + 0], bh[P], H0);
                 H1 = mfma32(wr[3 * P + 2], bh[P], H1);
             }
         } else if (hb) {
 #pragma unroll
-            for (int P = 0; P < kPairs; ++P) H0 = mfma32(wr[3 * P + 0], bh[P], H0);
+            for (int P = 0; P < kOut; ++P) H0 = mfma32(wr[3 * P + 0], bh[P], H0);
         } else {
 #pragma unroll
-            for (int P = 0; P < kPairs; ++P) H1 = mfma32(wr[3 * P + 2], bh[P], H1);
+            for (int P = 0; P < kOut; ++P) H1 = mfma32(wr[3 * P + 2], bh[P], H1);
         }
     }
     v4f L = H0, A, R;  // previous tile: its dz = -1 products, Q_0 + left part, dz = +1 products
@@ -346,15 +359,20 @@ __device__ __forceinline__ void conv_row16(const lds16* base, const int so[3], c
     for (int t = 0; t < 4; ++t) {
         v4f Q0 = v4f{0.f, 0.f, 0.f, 0.f}, Q1 = Q0, Q2 = Q0;
 #pragma unroll
-        for (int P = 0; P < kPairs; ++P) {
-            const int sidx = kPairs * t + P;
-            if (sidx + 2 < 4 * kPairs) ring[(sidx + 2) % 3] = rd(slab_off(sidx + 2));
+        for (int e = 0; e < kPer; ++e) {
+            const int sidx = kPer * t + e;
+            if (sidx + 2 < 4 * kPer) ring[(sidx + 2) % 3] = rd(slab_off(sidx + 2));
             const v8s b = ring[sidx % 3];
-            Q0 = mfma32(wr[3 * P + 0], b, Q0);
-            Q1 = mfma32(wr[3 * P + 1], b, Q1);
-            Q2 = mfma32(wr[3 * P + 2], b, Q2);
-            if (sidx + 2 < 4 * kPairs) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);
+            if (e < kOut) {
+                Q0 = mfma32(wr[3 * e + 0], b, Q0);
+                Q1 = mfma32(wr[3 * e + 1], b, Q1);
+                Q2 = mfma32(wr[3 * e + 2], b, Q2);
+            } else {
+                Q1 = mfma32(wr[3 * kOut + e - kOut], b, Q1);
+            }
+            if (sidx + 2 < 4 * kPer) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            if (e < kOut) __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);
+            else __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
         }
         if (t > 0) {
             v4f y;
@@ -647,7 +665,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
     const int i1 = min(g.nx, i0 + a.run);
     const int j = j0 + w;
     constexpr bool kLast = MODE == kFinal || MODE == kPrecond;
-    constexpr int NW = kLast ? kPairs : (C == 16 ? 3 * kPairs : 2);
+    constexpr int NW = kLast ? kPairs : (C == 16 ? 3 * kPairs - 1 : 2);
     v8s wr[NW];
 #pragma unroll
     for (int t = 0; t < NW; ++t) wr[t] = a.W[t * 64 + lane];
@@ -1030,12 +1048,17 @@ __global__ void prepare_weights(const float* p, v8s* W) {
             const int l = fwd ? (idx < kWf3 ? 1 : 2) : (idx < kWb2 ? 2 : 1);
             const int base = fwd ? (l == 1 ? kWf2 : kWf3) : (l == 2 ? kWb3 : kWb2);
             const int op = (idx - base) / 64, P = op / 3, d = op % 3;
-            const int g = 2 * P + (k >> 4), c = k & 15;
-            if (g < 9) {
-                const int tap = 3 * g + d;
+            int tap = -1, c = k & 15;
+            if (P < kPairs - 1) {
+                tap = 3 * (2 * P + (k >> 4)) + d;            // group 2P + (k >> 4), dz = d - 1
+            } else if (d == 0) {
+                tap = 24 + (k >> 4);                         // group 8: [dz = -1 | dz = 0]
+            } else if (d == 1 && k < 16) {
+                tap = 26;                                    // group 8: [dz = +1 | 0]
+            }                                                // (operand 14 is unused: zeros)
+            if (tap >= 0)
                 x = fwd ? p[offW(l) + (tap * 16 + c) * 16 + i]                  // W[tap][c][i]
                         : p[offW(l) + ((26 - tap) * 16 + i) * 16 + c];         // W[26 - tap][i][c]
-            }
         } else {                                                   // layer 4 forward: rows = dz + 1
             const int P = (idx - kWf4) / 64;
             const int g = 2 * P + (k >> 4), c = k & 15;
