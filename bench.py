@@ -487,6 +487,20 @@ def bench_batched(log_fn):
     return out
 
 
+_TUNE_CACHE = None
+
+
+def tune_cache() -> str:
+    """A launch-shape cache file for this run (outside the repository): the
+    autotuner measures each grid shape once and every later grid of the same
+    shape takes its pick."""
+    global _TUNE_CACHE
+    if _TUNE_CACHE is None:
+        import tempfile
+        _TUNE_CACHE = os.path.join(tempfile.mkdtemp(prefix="mffv_tune_"), "tune.json")
+    return _TUNE_CACHE
+
+
 def make_problem(k, c, stream, kz_ratio=1.0):
     """Grid handle and right-hand side of a permeability field (x-plane
     Dirichlet 1/0, scalar accumulation c), built through the C ABI."""
@@ -500,6 +514,7 @@ def make_problem(k, c, stream, kz_ratio=1.0):
     mffv.perm_to_trans(nx, ny, nz, kd, kz_ratio, tx, ty, tz, stream=stream)
     g = mffv.create_grid(nx, ny, nz, stream=stream)
     mffv.set_transmissibility(g, tx, ty, tz, accum_scalar=c, b_out=b)
+    mffv.autotune(g, tune_cache())   # CG and stencil launch shapes (measured once per grid shape)
     return g, b
 
 
@@ -565,6 +580,8 @@ def bench_channelised(log_fn, held_in: int, held_out: int, steps: int, warmup: i
         for i in range(n_eval):
             seed = 3500 + (i % held_out)
             g, b = make_problem(channelised(shape, seed), c, s)
+            if i == 0:
+                out["launch"] = {kk: v for kk, v in mffv.autotune(g, tune_cache()).items() if kk in LAUNCH_KEYS}
             b64 = b.double()
             for name, mk in methods.items():
                 solve_f64(g, b64, mk(max_iter=16))                    # set-up: graphs, workspace

@@ -17,8 +17,9 @@ forward passes of the learned preconditioner's network (seeded random
 parameters of the trained network's scale) on a unit-RMS random input and
 the same 5 copies. With --learned it runs 30 iterations of flexible CG with
 that network as the preconditioner (between the two Jacobi sweeps) on
-held-out channelised realisation 3500, without graph replay, so that every
-kernel of an iteration is its own dispatch. With --batched it solves the
+held-out channelised realisation 3500 (launch shapes from the autotuner, as
+in the bench), without graph replay, so that every kernel of an iteration is
+its own dispatch. With --batched it solves the
 64-system uneven batch (the batched workload) once with the persistent
 batched kernel (default launch shape, block shares by size) and runs the
 same 5 copies.
@@ -111,6 +112,7 @@ def learned_iterations(torch, mffv) -> int:
     mffv.perm_to_trans(*shape, kd, 1.0, tx, ty, tz)
     g = mffv.create_grid(*shape)
     mffv.set_transmissibility(g, tx, ty, tz, accum_scalar=1e-3, b_out=b)
+    print(f"[probe] launch shapes {mffv.autotune(g, None)}", flush=True)
     net = mffv.net_create(probe_params())
     x = torch.zeros(n, dtype=torch.float32, device="cuda")
     st, info = mffv.cg_solve(g, b, x, mffv.default_opts(tol=1e-12, max_iter=30, use_graph=0,
