@@ -89,7 +89,7 @@ NN_HIDDEN_BYTES_PER_CELL = 64
 # HBM bytes per launch of the hidden convolution on 128^3 from rocprofv3
 # FETCH_SIZE and WRITE_SIZE (FETCH_SIZE scaled by the same counter on a copy of
 # known size), or None
-NN_TRAFFIC = {"hidden": {"bytes": 141_862_093,  # 36,500.6 KiB x 2 fetched + 65,536 KiB written
+NN_TRAFFIC = {"hidden": {"bytes": 146_468_454,  # 38,749.8 KiB x 2 fetched + 65,536 KiB written
                           "profile": "profiles/conv3d_hidden_channelised_128cube_hbm_traffic.md"}}
 # launch shapes the stencil autotuner reports: the CG kernels' and the apply's own
 LAUNCH_KEYS = ("ci", "remap", "seg", "vec", "blocks", "apply_ci", "apply_remap", "apply_seg", "apply_blocks")

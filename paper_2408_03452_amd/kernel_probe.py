@@ -44,6 +44,8 @@ def main(argv=None) -> int:
     ap.add_argument("--network", action="store_true", help="the network's forward passes on 128^3")
     ap.add_argument("--learned", action="store_true", help="flexible-CG iterations with the network on 128^3")
     ap.add_argument("--batched", action="store_true", help="one solve of the 64-system uneven batch")
+    ap.add_argument("--tune-cache", default=None,
+                    help="--learned: autotuner cache file (a run that finds its shape there launches no tuning kernels)")
     args = ap.parse_args(argv)
     import torch
     from paper_2408_03452_amd import mffv
@@ -51,7 +53,7 @@ def main(argv=None) -> int:
     if args.network:
         return network(torch, mffv)
     if args.learned:
-        return learned_iterations(torch, mffv)
+        return learned_iterations(torch, mffv, args.tune_cache)
     if args.batched:
         return batched(torch, mffv)
 
@@ -101,7 +103,7 @@ def probe_params():
     return p
 
 
-def learned_iterations(torch, mffv) -> int:
+def learned_iterations(torch, mffv, tune_cache=None) -> int:
     from synth import channelised
     shape = (128, 128, 128)
     print(f"[probe] {mffv.version()}: 30 learned flexible-CG iterations on channelised {shape}", flush=True)
@@ -112,7 +114,7 @@ def learned_iterations(torch, mffv) -> int:
     mffv.perm_to_trans(*shape, kd, 1.0, tx, ty, tz)
     g = mffv.create_grid(*shape)
     mffv.set_transmissibility(g, tx, ty, tz, accum_scalar=1e-3, b_out=b)
-    print(f"[probe] launch shapes {mffv.autotune(g, None)}", flush=True)
+    print(f"[probe] launch shapes {mffv.autotune(g, tune_cache)}", flush=True)
     net = mffv.net_create(probe_params())
     x = torch.zeros(n, dtype=torch.float32, device="cuda")
     st, info = mffv.cg_solve(g, b, x, mffv.default_opts(tol=1e-12, max_iter=30, use_graph=0,
