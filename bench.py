@@ -159,7 +159,7 @@ def bench_large(log_fn, solve: bool, cg_iters: int = 200):
         g = mffv.create_grid(nx, ny, nz, stream=s)
         mffv.set_transmissibility(g, tx, ty, tz, accum_scalar=w.c, b_out=b)
         del tx, ty, tz
-        tune = mffv.autotune(g, None)
+        tune = mffv.autotune(g, tune_cache())
         out["launch"] = {kk: tune[kk] for kk in LAUNCH_KEYS}
         xa = torch.randn(n, dtype=torch.float32, device=dev)
         ya = torch.empty_like(xa)
@@ -714,6 +714,7 @@ def bench_large_learned(log_fn, c3_params, n_crops: int = 100, n_eval: int = 4):
         mffv.perm_to_trans(cx, cy, cz, kd, w.kz_ratio, tx, ty, tz, stream=stream)
         g = mffv.create_grid(cx, cy, cz, stream=stream)
         mffv.set_transmissibility(g, tx, ty, tz, accum_scalar=w.c, b_out=b)
+        mffv.autotune(g, tune_cache())   # launch shapes, measured once per grid shape
         return g, b
 
     def crop(pos, size):
@@ -741,11 +742,11 @@ def bench_large_learned(log_fn, c3_params, n_crops: int = 100, n_eval: int = 4):
             g, b = problem(crop(pos, 128), s)
             for name, pre, net in methods:
                 x = torch.zeros(g.n, dtype=torch.float32, device="cuda")
-                mffv.cg_solve(g, b, x, mffv.default_opts(max_iter=4, precond=pre, net=net))
+                mffv.cg_solve(g, b, x, mffv.default_opts(max_iter=4, precision=mffv.FP32_IR, precond=pre, net=net))
                 x.zero_()
                 torch.cuda.synchronize()
                 t2 = time.perf_counter()
-                st, info = mffv.cg_solve(g, b, x, mffv.default_opts(precond=pre, net=net))
+                st, info = mffv.cg_solve(g, b, x, mffv.default_opts(precision=mffv.FP32_IR, precond=pre, net=net))
                 torch.cuda.synchronize()
                 rows[name].append((time.perf_counter() - t2, info["iters"], info["rel_res_true"], st))
             g.close()
@@ -1021,9 +1022,9 @@ def main(argv=None):
                     help="also renumber the randomly numbered face-list mesh with mffv_face_order (about 30 s on the host)")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 512x512x1024 apply / CG-rate measurement")
-    ap.add_argument("--large-learned", action="store_true",
-                    help="fine-tune the learned preconditioner on crops of the 512x512x1024 workload and "
-                         "compare the methods there")
+    ap.add_argument("--no-large-learned", action="store_true",
+                    help="skip fine-tuning the learned preconditioner on crops of the 512x512x1024 workload "
+                         "and comparing the methods there (on by default)")
     ap.add_argument("--large-solve", action="store_true",
                     help="also solve the 512x512x1024 system to 1e-8 (minutes)")
     args = ap.parse_args(argv)
@@ -1079,7 +1080,7 @@ def main(argv=None):
             f"{batched['size_shares']['cells_iter_per_s'] / 1e9:.1f}), iters "
             f"{batched['iters_min_max']}, worst true rel-res {batched['rel_res_true_max']:.2e}")
     large_learned = None
-    if args.large_learned:
+    if not args.no_large_learned:
         large_learned = bench_large_learned(log, c3_params)
 
     cpu = None
