@@ -337,7 +337,7 @@ int enqueue_iter32(mffv_grid* G, int precond, const mffv_net* net, int nn_every 
             int nbf = 0;
             int rc = nn_precondition(net, G->g, coef_of(G), G->m32, omega, G->r, G->dinv, G->dmask, G->sqd,
                                      G->z, pb + G->nb_vec, G->nb_vec, G->feat, (float)G->n_unknown, G->stream,
-                                     G->q, &fp, &nbf, nev);
+                                     G->q, &fp, &nbf, nev, &G->st32->done);
             if (rc) return rc;
             G->flex_part = fp;
             G->flex_nb = nbf;

@@ -67,6 +67,8 @@ struct StencilIO {
     float* sw_flex = nullptr;          //   optional: per-block partials [4][blocks] of the
                                        //   flexible-CG dots z.r, z.q, dinv r.r, dinv r.q
     const float* sw_q = nullptr;       //   q for those dots (NULL: the z.q and r.q sums are 0)
+    const int* done = nullptr;         // kSweep1 / kSweep2: the CG loop's done flag; once it is
+                                       //   set the pass returns at once (iterations after the end)
 };
 
 // kSweep1 / kSweep2: the damped Jacobi sweeps around the learned

@@ -491,6 +491,7 @@ struct ConvArgs {
     int ntk;                // column tiles along z
     int ncols;              // column tiles in total (y tiles x z tiles)
     int run;                // x planes per block
+    const int* done;        // optional: the CG loop's done flag (return at once once set)
 };
 
 
@@ -645,6 +646,7 @@ template <int C, int MODE>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void conv3d(Geom g, ConvArgs a) {
     // 2-channel input: the ring's slots 0 and 1 are mirrored past its end, so
     // that planes i-1, i, i+1 always sit in three consecutive slots
+    if (a.done && *a.done) return;  // the CG loop has ended (the flag is the same for all threads)
     constexpr int kSlots = C == 2 ? kRingSlots + 2 : kRingSlots;
     constexpr int SLOT = slot_u16<C>();
     __shared__ __attribute__((aligned(16))) uint16_t lds[kSlots * SLOT];
@@ -731,7 +733,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
 // The network's scale of a residual from the partials pb of its
 // dinv-weighted square (one block, fixed order): scale[0] = s =
 // sqrt(sum(dinv r^2) / n_U), scale[1] = 1 / s (both 0 for a zero residual).
-__global__ __launch_bounds__(kThreads) void nn_scale(const float* pb, int nb, float n_u, float* scale) {
+__global__ __launch_bounds__(kThreads) void nn_scale(const float* pb, int nb, float n_u, float* scale,
+                                                     const int* done) {
+    if (done && *done) return;  // the CG loop has ended
     __shared__ float red[kThreads / kWave];
     const float rr = sum_partials(pb, nb, red);
     if (threadIdx.x == 0) {
@@ -746,7 +750,8 @@ __global__ __launch_bounds__(kThreads) void nn_scale(const float* pb, int nb, fl
 // thread where n allows (every array is 16-byte aligned).
 __global__ __launch_bounds__(kThreads) void nn_input(int64_t n, const float* r, const float* dinv,
                                                      const float* feat, const float* inv_s_dev, uint16_t* x0,
-                                                     const uint8_t* dmask) {
+                                                     const uint8_t* dmask, const int* done) {
+    if (done && *done) return;  // the CG loop has ended
     const float inv_s = inv_s_dev ? *inv_s_dev : 1.f;
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     auto one = [&](float rv, float dv, float fv, bool masked) -> uint32_t {
@@ -1274,9 +1279,10 @@ int conv(const Shape& S, const ConvArgs& a0, hipStream_t st) {
 // either stores y (training) or forms the preconditioned z. keep_h3
 // (training) keeps h3 for the backward pass; inference writes it over h1.
 int forward(mffv_net* N, const Shape& S, bool keep_h3, int last_mode, const ConvArgs& last,
-            hipStream_t st, hipEvent_t* ev = nullptr) {
+            hipStream_t st, hipEvent_t* ev = nullptr, const int* done = nullptr) {
     if (ev) NHIP(hipEventRecord(ev[0], st));
     ConvArgs a{};
+    a.done = done;
     a.relu = N->relu;
     a.in = N->x0;
     a.W = N->W + kWf1;
@@ -1299,6 +1305,7 @@ int forward(mffv_net* N, const Shape& S, bool keep_h3, int last_mode, const Conv
     if ((rc = conv<16, kHiddenRelu>(S, a, st))) return rc;
     if (ev) NHIP(hipEventRecord(ev[3], st));
     ConvArgs f = last;
+    f.done = done;
     f.relu = N->relu;
     f.in = h3;
     f.W = N->W + kWf4;
@@ -1379,7 +1386,7 @@ int loss_pass(mffv_net* N, const Shape& S, const Coef& c, const March& m, const 
     const int64_t n = S.g.n;
     const int nb = nblocks_for(n, kRedBlocks);
     hipLaunchKernelGGL(nn_input, dim3(nb), dim3(kThreads), 0, st, n, r_hat, (const float*)nullptr, feat,
-                       (const float*)nullptr, N->x0, dmask);
+                       (const float*)nullptr, N->x0, dmask, (const int*)nullptr);
     NHIP(hipGetLastError());
     ConvArgs last{};
     last.out32 = N->y;
@@ -1428,7 +1435,8 @@ namespace mffv {
 int nn_precondition(const mffv_net* Nc, const Geom& g, const Coef& c, const March& m, float omega,
                     const float* r, const float* dinv, const uint8_t* dmask, const float* sqd, float* z,
                     const float* pb, int nb_b, const float* feat, float n_u, hipStream_t s,
-                    const float* q, const float** flex_part, int* nb_flex, hipEvent_t* layer_ev) {
+                    const float* q, const float** flex_part, int* nb_flex, hipEvent_t* layer_ev,
+                    const int* done) {
     *flex_part = nullptr;
     *nb_flex = 0;
     mffv_net* N = const_cast<mffv_net*>(Nc);
@@ -1450,6 +1458,7 @@ int nn_precondition(const mffv_net* Nc, const Geom& g, const Coef& c, const Marc
         io.out = N->sw1;
         io.partials = N->swp;
         io.sw_j = N->sw2;   // omega dinv r + dinv r1, for z2
+        io.done = done;
         NHIP(launch_stencil_f32(kSweep1, g, c, io, m, s));
         rin = N->sw1;
         pin = N->swp;
@@ -1469,10 +1478,10 @@ int nn_precondition(const mffv_net* Nc, const Geom& g, const Coef& c, const Marc
         pin = N->red;
         nbin = nb;
     }
-    hipLaunchKernelGGL(nn_scale, dim3(1), dim3(kThreads), 0, s, pin, nbin, n_u, N->sscale);
+    hipLaunchKernelGGL(nn_scale, dim3(1), dim3(kThreads), 0, s, pin, nbin, n_u, N->sscale, done);
     NHIP(hipGetLastError());
     hipLaunchKernelGGL(nn_input, dim3(nb), dim3(kThreads), 0, s, g.n, rin, dinv, feat,
-                       (const float*)(N->sscale + 1), N->x0, (const uint8_t*)nullptr);
+                       (const float*)(N->sscale + 1), N->x0, (const uint8_t*)nullptr, done);
     NHIP(hipGetLastError());
     if (omega > 0.f && fused) {
         // the network's output y into N->y; the second sweep's pass forms
@@ -1481,9 +1490,10 @@ int nn_precondition(const mffv_net* Nc, const Geom& g, const Coef& c, const Marc
         // z = z2 + omega dinv (r - A z2)
         ConvArgs last{};
         last.out32 = N->y;
-        int rc = forward(N, S, false, kFinal, last, s, layer_ev);
+        int rc = forward(N, S, false, kFinal, last, s, layer_ev, done);
         if (rc) return rc;
         StencilIO<float> io;
+        io.done = done;
         io.src = N->y;
         io.out = z;
         io.rres = r;
@@ -1676,7 +1686,7 @@ int mffv_nn_forward(mffv_net* N, int nx, int ny, int nz, const float* r_hat, con
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(nn_input, dim3(nblocks_for(S.g.n, kRedBlocks)), dim3(kThreads), 0, st, S.g.n, r_hat,
                        (const float*)nullptr, feat, (const float*)nullptr, N->x0,
-                       (const uint8_t*)nullptr);
+                       (const uint8_t*)nullptr, (const int*)nullptr);
     NHIP(hipGetLastError());
     ConvArgs last{};
     last.out32 = out;
@@ -1694,7 +1704,8 @@ int mffv_nn_time_layers(mffv_net* N, int nx, int ny, int nz, const float* r_hat,
     hipStream_t st = static_cast<hipStream_t>(stream);
     // one whole pass first, so that every layer reads what the network computes
     hipLaunchKernelGGL(nn_input, dim3(nblocks_for(S.g.n, kRedBlocks)), dim3(kThreads), 0, st, S.g.n, r_hat,
-                       (const float*)nullptr, feat, (const float*)nullptr, N->x0, (const uint8_t*)nullptr);
+                       (const float*)nullptr, feat, (const float*)nullptr, N->x0, (const uint8_t*)nullptr,
+                       (const int*)nullptr);
     NHIP(hipGetLastError());
     ConvArgs last{};
     last.out32 = N->y;

@@ -20,11 +20,14 @@ namespace mffv {
 // the per-block partials of the flexible-CG dots (z.r, z.q, dinv r.r, dinv r.q;
 // q may be NULL, then those of q are 0): *flex_part and *nb_flex receive them
 // (network-owned, [4][nb_flex]); otherwise *flex_part is NULL and the caller
-// forms the dots itself.
+// forms the dots itself. done (optional): the CG loop's done flag; every
+// kernel of the preconditioner returns at once once it is set, so the
+// iterations a chunk holds past the loop's end cost no network passes.
 int nn_precondition(const mffv_net* net, const Geom& g, const Coef& c, const March& m, float omega,
                     const float* r, const float* dinv, const uint8_t* dmask, const float* sqd, float* z,
                     const float* pb, int nb_b, const float* feat, float n_u, hipStream_t s,
-                    const float* q, const float** flex_part, int* nb_flex, hipEvent_t* layer_ev = nullptr);
+                    const float* q, const float** flex_part, int* nb_flex, hipEvent_t* layer_ev = nullptr,
+                    const int* done = nullptr);
 
 // Make sure the network's inference workspace holds n cells; returns the
 // workspace generation (changes whenever the workspace is reallocated), or a

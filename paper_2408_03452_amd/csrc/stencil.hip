@@ -249,6 +249,7 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
     constexpr bool kCg = MODE == kFusedCg || MODE == kMergedCg;
     PhaseA<float> ph{0, 0.f, 0.f, 0.f, false};
     if (MODE == kFusedCg && !phase_a_start(io, red, ph)) return;
+    if ((MODE == kSweep1 || MODE == kSweep2) && io.done && block_flag(io.done)) return;
     if (MODE == kMergedCg) {
         // r_K = r_{K-1} - alpha q_{K-1} on the fly, then the same direction
         // update and deferred solution update as phase A
@@ -532,6 +533,7 @@ __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<
 
     PhaseA<real> ph{0, real(0), real(0), real(0), false};
     if (MODE == kFusedCg && !phase_a_start(io, red, ph)) return;
+    if ((MODE == kSweep1 || MODE == kSweep2) && io.done && block_flag(io.done)) return;
     const int it = ph.k;
     const real beta = ph.beta, alpha_prev = ph.alpha_prev, alpha_prev2 = ph.alpha_prev2;
     // two deferred steps on even k >= 2, as in the four-cells-per-thread kernel
