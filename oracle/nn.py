@@ -5,8 +5,8 @@ Test infrastructure only (see the package docstring).
 The network maps two input channels per cell through four 3x3x3 convolutions
 with 2 -> 16 -> 16 -> 16 -> 1 channels and a ReLU after each of the first
 three. It works on the Jacobi-scaled system A~ = D^-1/2 A D^-1/2 (D = diag A):
-the input channels are the scaled residual r~ = D^-1/2 r / s (s makes its RMS
-over the unknown cells 1) and r~ times the log-diagonal feature
+the input channels are the scaled residual r~ = D^-1/2 r / s (s, a power of
+two, brings its RMS over the unknown cells within a factor sqrt 2 of 1) and r~ times the log-diagonal feature
 f = log d - mean_U log d, so the output vanishes with the residual; the
 preconditioned residual is z = D^-1/2 (r~ + N) (times s), which is Jacobi
 when N = 0. A convolution here is
@@ -253,6 +253,14 @@ def bias_mask() -> np.ndarray:
     return mask
 
 
+def network_scale(ru, du) -> float:
+    """The scale s of the network's input for the residual ru on the unknown
+    cells (du: their diagonal): the power of two nearest the D^-1-weighted RMS,
+    2^round(log2 rms) with rms^2 = sum(ru^2 / du) / n_U; 0 for a zero residual."""
+    rms = np.sqrt(np.sum(ru * ru / du) / ru.size)
+    return 0.0 if rms == 0 else float(2.0 ** np.round(np.log2(rms)))
+
+
 def learned_preconditioner(params, A, dmask, feat, omega: float = 0.5, relu: bool = True,
                            bf16: bool = True):
     """The preconditioner of flexible CG with the network, as a map on the
@@ -260,7 +268,10 @@ def learned_preconditioner(params, A, dmask, feat, omega: float = 0.5, relu: boo
     ``feat``: the grid-shaped input feature).
 
     The network's correction of a residual r is C(r) = s D^-1/2 N(r_hat, f)
-    with r_hat = D^-1/2 r / s, s^2 = r' D^-1 r / n_U (0 on Dirichlet cells).
+    with r_hat = D^-1/2 r / s (0 on Dirichlet cells), s the power of two
+    nearest the D^-1-weighted RMS of r: s = 2^round(log2 rms),
+    rms^2 = r' D^-1 r / n_U, so the input's RMS lies within a factor sqrt 2
+    of one and dividing by s is exact in floating point.
     With omega = 0 the preconditioned residual is z = D^-1 r + C(r): Jacobi
     when N = 0. With omega > 0 the network sits between two damped Jacobi
     sweeps, each taken from the residual it is given:
@@ -277,7 +288,7 @@ def learned_preconditioner(params, A, dmask, feat, omega: float = 0.5, relu: boo
     shape = np.shape(dmask)
 
     def C(ru):
-        sc = np.sqrt(np.sum(ru * ru / d[u]) / u.size)
+        sc = network_scale(ru, d[u])
         if sc == 0:
             return np.zeros_like(ru)
         rh = np.zeros(n)

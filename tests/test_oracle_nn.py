@@ -387,3 +387,41 @@ def test_sandwich_correction_is_the_network_through_the_post_sweep():
     assert np.allclose(M(r) / dis[u], poly @ rt + a * S @ S @ rt, rtol=1e-6, atol=1e-7)
     # and the correction really passes through the second sweep (not (I - w A~) once)
     assert not np.allclose(M(r) / dis[u], poly @ rt + a * S @ rt, rtol=1e-3, atol=1e-4)
+
+
+def test_network_scale_is_a_power_of_two_so_power_of_two_residual_scalings_commute():
+    """The network's input scale s is the power of two nearest the
+    D^-1-weighted RMS of the residual it is given: scaling r by 2^k scales s by
+    2^k and leaves the network input r_hat unchanged, so C(2^k r) = 2^k C(r)
+    exactly for any network (nonzero biases, BF16 input rounding and all),
+    with and without the sweeps. A scaling that moves the RMS across
+    2^(j + 1/2) changes s by a factor 2 instead of the RMS's factor; with
+    nonzero biases the result then is not proportional."""
+    from oracle import tpfa
+    from synth import lognormal_iid
+    shape = (6, 5, 7)
+    k = lognormal_iid(shape, 1.0, 31)
+    dm, pd = tpfa.x_plane_dirichlet(shape)
+    A, _ = tpfa.assemble(*tpfa.transmissibility(k), 1e-2, dm, pd)
+    u = ~dm.ravel()
+    d = A.diagonal()[u]
+    rng = np.random.default_rng(32)
+    params = nn.init_params(seed=33, last_scale=0.5)
+    params[nn.bias_mask()] = rng.normal(0.0, 0.3, int(nn.bias_mask().sum()))   # nonzero biases
+    feat = rng.normal(size=shape)
+    r = rng.normal(size=int(u.sum()))
+    for w in (0.0, 0.5):
+        M = nn.learned_preconditioner(params, A, dm, feat, omega=w)
+        base = M(r)
+        for kk in (-20, -3, 1, 7):
+            assert np.array_equal(M(r * 2.0 ** kk), base * 2.0 ** kk)
+    # s itself: a power of two within a factor sqrt 2 of the RMS (the nearest),
+    # switching from 1 to 2 where the RMS crosses sqrt 2
+    rms = np.sqrt(np.sum(r * r / d) / r.size)
+    for target in (1e-9, 0.3, 0.7, 0.9999, 1.0, 1.3, 1.41, 1.42, 5.0, 3e7):
+        sc = nn.network_scale(r * (target / rms), d)
+        e = np.log2(sc)
+        assert e == np.round(e) and abs(np.log2(target / sc)) <= 0.5 + 1e-12
+    assert nn.network_scale(r * (0.999 * np.sqrt(2.0) / rms), d) == 1.0
+    assert nn.network_scale(r * (1.001 * np.sqrt(2.0) / rms), d) == 2.0
+    assert nn.network_scale(np.zeros_like(r), d) == 0.0
