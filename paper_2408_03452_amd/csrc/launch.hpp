@@ -67,6 +67,8 @@ struct StencilIO {
     float* sw_flex = nullptr;          //   optional: per-block partials [4][blocks] of the
                                        //   flexible-CG dots z.r, z.q, dinv r.r, dinv r.q
     const float* sw_q = nullptr;       //   q for those dots (NULL: the z.q and r.q sums are 0)
+    uint32_t* nn_x0 = nullptr;         // kSweep1, optional: the network's BF16 input pairs
+    const float* nn_feat = nullptr;    //   (sqrt(dinv) r1, sqrt(dinv) r1 feat), unscaled
     const int* done = nullptr;         // kSweep1 / kSweep2: the CG loop's done flag; once it is
                                        //   set the pass returns at once (iterations after the end)
 };

@@ -492,6 +492,8 @@ struct ConvArgs {
     int ncols;              // column tiles in total (y tiles x z tiles)
     int run;                // x planes per block
     const int* done;        // optional: the CG loop's done flag (return at once once set)
+    const float* in_scale;  // first layer, optional: device scalar multiplying its products (the
+                            //   network input's 1/s, a power of two, when the input is unscaled)
 };
 
 
@@ -610,8 +612,10 @@ __device__ __forceinline__ void conv_step(const Geom& g, const ConvArgs& a, cons
             // per-lane select between the accumulator and 0 written with a
             // branch here (the accumulator register was cleared on every lane).
             if (MODE == kHiddenRelu) {
+                // (the first layer's products times the input scale: a power of
+                // two, so this equals the products of the scaled input exactly)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) h[q] = fmaxf(acc[q] + bias[q], floor_act);
+                for (int q = 0; q < 4; ++q) h[q] = fmaxf((C == 2 ? acc[q] * s : acc[q]) + bias[q], floor_act);
             } else {
                 const uint2 bl = eb[mt];
                 // ReLU mask: keep the gradient where the activation below is > 0
@@ -678,7 +682,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
     } else if (MODE == kFinal || MODE == kPrecond) {
         bias[0] = a.bias[0];
     }
-    const float s = (MODE == kPrecond) ? *a.sscale : 0.f;
+    // kPrecond: the output scale s; first layer: the input scale (1 if none)
+    const float s = (MODE == kPrecond) ? *a.sscale
+                  : (C == 2 && MODE == kHiddenRelu && a.in_scale) ? *a.in_scale : 1.f;
     int toff[C == 2 ? 8 : 1] = {0};
     if constexpr (C == 2) tap_offsets2(toff);
     // the weights and scalars above have arrived before any plane is requested:
@@ -739,8 +745,10 @@ __global__ __launch_bounds__(kThreads) void nn_scale(const float* pb, int nb, fl
     __shared__ float red[kThreads / kWave];
     const float rr = sum_partials(pb, nb, red);
     if (threadIdx.x == 0) {
-        scale[0] = rr > 0.f ? sqrtf(rr / n_u) : 0.f;
-        scale[1] = rr > 0.f ? sqrtf(n_u / rr) : 0.f;
+        // the power of two nearest the RMS: 2^e with e = floor(log2(rms sqrt 2))
+        const int e = rr > 0.f ? ilogbf(sqrtf(rr / n_u) * 1.41421356f) : 0;
+        scale[0] = rr > 0.f ? ldexpf(1.f, e) : 0.f;
+        scale[1] = rr > 0.f ? ldexpf(1.f, -e) : 0.f;
     }
 }
 
@@ -1279,10 +1287,12 @@ int conv(const Shape& S, const ConvArgs& a0, hipStream_t st) {
 // either stores y (training) or forms the preconditioned z. keep_h3
 // (training) keeps h3 for the backward pass; inference writes it over h1.
 int forward(mffv_net* N, const Shape& S, bool keep_h3, int last_mode, const ConvArgs& last,
-            hipStream_t st, hipEvent_t* ev = nullptr, const int* done = nullptr) {
+            hipStream_t st, hipEvent_t* ev = nullptr, const int* done = nullptr,
+            const float* in_scale = nullptr) {
     if (ev) NHIP(hipEventRecord(ev[0], st));
     ConvArgs a{};
     a.done = done;
+    a.in_scale = in_scale;
     a.relu = N->relu;
     a.in = N->x0;
     a.W = N->W + kWf1;
@@ -1290,6 +1300,7 @@ int forward(mffv_net* N, const Shape& S, bool keep_h3, int last_mode, const Conv
     a.out16 = N->h1;
     int rc;
     if ((rc = conv<2, kHiddenRelu>(S, a, st))) return rc;
+    a.in_scale = nullptr;
     if (ev) NHIP(hipEventRecord(ev[1], st));
     a.in = N->h1;
     a.W = N->W + kWf2;
@@ -1450,19 +1461,54 @@ int nn_precondition(const mffv_net* Nc, const Geom& g, const Coef& c, const Marc
     // stencil kernels) when the first one's partials fit
     const bool fused = (int64_t)m.blocks() <= N->swp_cap;
     if (omega > 0.f && fused) {
-        // first sweep: r1 = r - A (omega dinv r), into sw1, with the partials of dinv r1^2
+        // first sweep: r1 = r - A (omega dinv r), with the partials of dinv r1^2;
+        // r1 itself goes out only as the network's unscaled BF16 input
+        // (sqrt(dinv) r1, sqrt(dinv) r1 f), the first convolution applying 1/s
         StencilIO<float> io;
         io.src = r;
         io.dinv = dinv;
         io.omega = omega;
-        io.out = N->sw1;
+        io.out = nullptr;
+        io.nn_x0 = reinterpret_cast<uint32_t*>(N->x0);
+        io.nn_feat = feat;
         io.partials = N->swp;
         io.sw_j = N->sw2;   // omega dinv r + dinv r1, for z2
         io.done = done;
         NHIP(launch_stencil_f32(kSweep1, g, c, io, m, s));
-        rin = N->sw1;
-        pin = N->swp;
-        nbin = m.blocks();
+        hipLaunchKernelGGL(nn_scale, dim3(1), dim3(kThreads), 0, s, (const float*)N->swp, (int)m.blocks(), n_u,
+                           N->sscale, done);
+        NHIP(hipGetLastError());
+        // the network's output y into N->y; the second sweep's pass forms
+        // z2 = (omega dinv r + dinv r1) + s sqrt(dinv) y (0 on Dirichlet cells,
+        // where both terms are 0) at every stencil point and writes
+        // z = z2 + omega dinv (r - A z2)
+        ConvArgs last{};
+        last.out32 = N->y;
+        int rc = forward(N, S, false, kFinal, last, s, layer_ev, done, N->sscale + 1);
+        if (rc) return rc;
+        StencilIO<float> io2;
+        io2.done = done;
+        io2.src = N->y;
+        io2.out = z;
+        io2.rres = r;
+        io2.dinv = dinv;
+        io2.omega = omega;
+        io2.sw_j = N->sw2;
+        io2.sw_sq = sqd;
+        io2.sw_scale = N->sscale;
+        io2.sw_flex = N->swf;
+        io2.sw_q = q;
+        // every block of the next phase A sums these partials: at most about
+        // kFlexBlocks of them (more planes per block if the plan has more)
+        March m2 = m;
+        if (m.blocks() > kFlexBlocks) {
+            const int f = (m.blocks() + kFlexBlocks - 1) / kFlexBlocks;
+            m2 = plan_march(g, m.vec, std::min(g.nx, m.ci * f), m.remap, m.nseg ? m.seg : -1);
+        }
+        NHIP(launch_stencil_f32(kSweep2, g, c, io2, m2, s));
+        *flex_part = N->swf;
+        *nb_flex = m2.blocks();
+        return MFFV_OK;
     } else if (omega > 0.f) {
         // the same in three kernels: t = omega dinv r into sw1, A t into sw2, r1 into sw1
         hipLaunchKernelGGL(sweep_scale, dim3(nb), dim3(kThreads), 0, s, g.n, r, dinv, dmask, omega, N->sw1);
@@ -1483,39 +1529,6 @@ int nn_precondition(const mffv_net* Nc, const Geom& g, const Coef& c, const Marc
     hipLaunchKernelGGL(nn_input, dim3(nb), dim3(kThreads), 0, s, g.n, rin, dinv, feat,
                        (const float*)(N->sscale + 1), N->x0, (const uint8_t*)nullptr, done);
     NHIP(hipGetLastError());
-    if (omega > 0.f && fused) {
-        // the network's output y into N->y; the second sweep's pass forms
-        // z2 = (omega dinv r + dinv r1) + s sqrt(dinv) y (0 on Dirichlet cells,
-        // where both terms are 0) at every stencil point and writes
-        // z = z2 + omega dinv (r - A z2)
-        ConvArgs last{};
-        last.out32 = N->y;
-        int rc = forward(N, S, false, kFinal, last, s, layer_ev, done);
-        if (rc) return rc;
-        StencilIO<float> io;
-        io.done = done;
-        io.src = N->y;
-        io.out = z;
-        io.rres = r;
-        io.dinv = dinv;
-        io.omega = omega;
-        io.sw_j = N->sw2;
-        io.sw_sq = sqd;
-        io.sw_scale = N->sscale;
-        io.sw_flex = N->swf;
-        io.sw_q = q;
-        // every block of the next phase A sums these partials: at most about
-        // kFlexBlocks of them (more planes per block if the plan has more)
-        March m2 = m;
-        if (m.blocks() > kFlexBlocks) {
-            const int f = (m.blocks() + kFlexBlocks - 1) / kFlexBlocks;
-            m2 = plan_march(g, m.vec, std::min(g.nx, m.ci * f), m.remap, m.nseg ? m.seg : -1);
-        }
-        NHIP(launch_stencil_f32(kSweep2, g, c, io, m2, s));
-        *flex_part = N->swf;
-        *nb_flex = m2.blocks();
-        return MFFV_OK;
-    }
     ConvArgs last{};
     last.out32 = omega > 0.f ? N->sw2 : z;   // z2 before the second sweep
     last.r = r;

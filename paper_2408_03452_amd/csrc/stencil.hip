@@ -72,6 +72,19 @@ __device__ __forceinline__ void st4(float* p, float4 v) {
     __builtin_nontemporal_store(w, reinterpret_cast<f4v*>(p));
 }
 __device__ __forceinline__ float4 f4(float v) { return make_float4(v, v, v, v); }
+// Two FP32 values as BF16 (round to nearest even), lo in the low half.
+typedef float nn_v2f __attribute__((ext_vector_type(2)));
+typedef __bf16 nn_v2bf __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16_pair(float lo, float hi) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((nn_v2f){lo, hi}, nn_v2bf));
+}
+// The network's input channels of one cell from the swept residual r1:
+// t = sqrt(dinv) r1 and t f in BF16 (the scale 1/s, a power of two, is
+// applied by the first convolution).
+__device__ __forceinline__ uint32_t nn_pair(float d, float r1, float f) {
+    const float t = sqrtf(d) * r1;
+    return bf16_pair(t, t * f);
+}
 __device__ __forceinline__ float4 axpy4(float a, float4 x, float4 y) {
     return make_float4(y.x + a * x.x, y.y + a * x.y, y.z + a * x.z, y.w + a * x.w);
 }
@@ -455,7 +468,13 @@ __global__ __launch_bounds__(kThreads) void stencil_v4(Geom g, Coef c, StencilIO
                 // r1 = r - A (omega dinv r) and the partial sums of dinv r1^2
                 const float4 rv = ld4(io.src + base), d = ld4(io.dinv + base);
                 const float4 r1 = make_float4(rv.x - y.x, rv.y - y.y, rv.z - y.z, rv.w - y.w);
-                st4(io.out + base, r1);
+                if (io.out) st4(io.out + base, r1);
+                if (io.nn_x0) {
+                    const float4 f = ld4(io.nn_feat + base);
+                    *reinterpret_cast<uint4*>(io.nn_x0 + base) =
+                        make_uint4(nn_pair(d.x, r1.x, f.x), nn_pair(d.y, r1.y, f.y), nn_pair(d.z, r1.z, f.z),
+                                   nn_pair(d.w, r1.w, f.w));
+                }
                 dot += d.x * r1.x * r1.x + d.y * r1.y * r1.y + d.z * r1.z * r1.z + d.w * r1.w * r1.w;
                 if (io.sw_j) {
                     const float w = io.omega;
@@ -620,8 +639,9 @@ __global__ __launch_bounds__(kThreads) void stencil_s(Geom g, Coef c, StencilIO<
                 dot += sc * y;
             } else if (MODE == kSweep1) {
                 const real r1 = io.src[base] - y;
-                io.out[base] = r1;
+                if (io.out) io.out[base] = r1;
                 const real d = (real)io.dinv[base];
+                if (io.nn_x0) io.nn_x0[base] = nn_pair((float)d, (float)r1, io.nn_feat[base]);
                 dot += d * r1 * r1;
                 if (io.sw_j) io.sw_j[base] = (real)io.omega * d * io.src[base] + d * r1;
             } else if (MODE == kSweep2) {
