@@ -1011,6 +1011,9 @@ def main(argv=None):
     ap.add_argument("--held-out", type=int, default=50,
                     help="held-out 128^3 realisations compared (the configuration's 50)")
     ap.add_argument("--held-in", type=int, default=200)
+    ap.add_argument("--train-seeds", type=int, default=3,
+                    help="networks trained (seeds 0..N-1); the one with the fewest iterations on two held-in "
+                         "128^3 realisations is kept")
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-jacobi", action="store_true")
@@ -1039,7 +1042,8 @@ def main(argv=None):
 
     log(f"{mffv.version()}; headline: learned flexible CG on channelised 128^3, {args.held_out} held-out "
         f"realisations, {args.steps} timed steps")
-    head = bench_channelised(log, args.held_in, args.held_out, args.steps, args.warmup)
+    head = bench_channelised(log, args.held_in, args.held_out, args.steps, args.warmup,
+                             train_seeds=tuple(range(args.train_seeds)))
     step_times = head.pop("_step_times")
     c3_params = head.pop("_params")
     head.pop("_x_first", None)
