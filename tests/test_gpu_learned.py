@@ -347,3 +347,59 @@ def test_smooth_sample_matches_the_oracle(mf):
     with pytest.raises(mf.MffvError):
         mf.nn_smooth_sample(g, 1.0, dev(rh), out)
     g.close()
+
+
+def test_power_of_two_scaled_right_hand_side_scales_the_solve_exactly(mf):
+    """The network's input scale is a power of two (the power of two nearest
+    the residual's D^-1-weighted RMS), the first sweep writes the unscaled BF16
+    input and the first convolution multiplies its products by 1/s. Every step
+    of flexible CG with this preconditioner is then exactly equivariant under
+    b -> 2^k b, even with a network whose biases are nonzero (which is not
+    homogeneous): the solve takes the same iterations and returns exactly
+    2^k x, in FP32 and with the FP64 refinement."""
+    shape = (24, 20, 28)
+    k = channelised(shape, 17)
+    g, _, b = gpu_problem(mf, k, c=1e-3)
+    net = mf.net_create(random_params(18))
+    base = None
+    for kk in (0, -7, 5):
+        bs = b * (2.0 ** kk)
+        x = torch.zeros(k.size, dtype=torch.float32, device="cuda")
+        st, info = mf.cg_solve(g, bs, x, mf.default_opts(precond=mf.PRECOND_LEARNED, net=net, tol=1e-6))
+        x64 = torch.zeros(k.size, dtype=torch.float64, device="cuda")
+        st64, info64 = mf.cg_solve_f64(g, bs.double(), x64, mf.default_opts(
+            tol=1e-8, precision=mf.FP32_IR, precond=mf.PRECOND_LEARNED, net=net))
+        assert st == mf.OK and st64 == mf.OK
+        got = (info["iters"], host(x) / 2.0 ** kk, info64["iters"], x64.cpu().numpy() / 2.0 ** kk)
+        if base is None:
+            base = got
+            continue
+        assert got[0] == base[0] and got[2] == base[2]
+        assert np.array_equal(got[1], base[1]) and np.array_equal(got[3], base[3])
+    net.close()
+    g.close()
+
+
+def test_learned_solve_does_not_depend_on_the_host_poll_chunk(mf):
+    """Iterations enqueued past convergence (the host polls the loop state one
+    chunk behind) find the loop's done flag set, and every kernel of the
+    preconditioner then returns at once: the solve's result and iteration
+    count are exactly those of a run polled after every iteration."""
+    shape = (22, 26, 20)
+    k = channelised(shape, 19)
+    g, _, b = gpu_problem(mf, k, c=1e-3)
+    net = mf.net_create(random_params(20))
+    runs = []
+    for every in (1, 5, 16, 64):
+        for max_iter in (7, 100000):
+            x = torch.zeros(k.size, dtype=torch.float32, device="cuda")
+            st, info = mf.cg_solve(g, b, x, mf.default_opts(precond=mf.PRECOND_LEARNED, net=net, tol=1e-6,
+                                                            check_every=every, max_iter=max_iter))
+            assert st == (mf.NOT_CONVERGED if max_iter == 7 else mf.OK)
+            runs.append((every, max_iter, info["iters"], host(x)))
+    for every, max_iter, iters, x in runs:
+        ref = next(r for r in runs if r[0] == 1 and r[1] == max_iter)
+        assert iters == ref[2], (every, max_iter)
+        assert np.array_equal(x, ref[3]), (every, max_iter)
+    net.close()
+    g.close()
