@@ -496,8 +496,12 @@ def tune_cache() -> str:
     shape takes its pick."""
     global _TUNE_CACHE
     if _TUNE_CACHE is None:
+        import atexit
+        import shutil
         import tempfile
-        _TUNE_CACHE = os.path.join(tempfile.mkdtemp(prefix="mffv_tune_"), "tune.json")
+        d = tempfile.mkdtemp(prefix="mffv_tune_")
+        atexit.register(shutil.rmtree, d, True)
+        _TUNE_CACHE = os.path.join(d, "tune.json")
     return _TUNE_CACHE
 
 
