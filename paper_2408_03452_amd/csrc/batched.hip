@@ -144,8 +144,20 @@ struct StepA {
 
 struct CellA {
     bool hasjm, hasjp, haskm, haskp;
+    bool ldkm, ldkp;   // the z neighbour lies in another wave: loaded (wave's first / last lane)
     uint32_t nz4, P4;  // byte strides of y and x
 };
+
+// Wavefront shifts by one lane (DPP wave_shr / wave_shl): lane l gets lane
+// l - 1 (l + 1). The z neighbours of a cell are the neighbouring lanes of its
+// wave (a work item's cells run along z), except at the wave's ends, where
+// the neighbour is loaded, and at a row's ends, where its face is 0.
+__device__ __forceinline__ float wave_shr1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float wave_shl1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
 
 __device__ __forceinline__ void load_a(StepA& o, const BatchSys& S, const CellA& cc, const float* src,
                                        const float* pold, const float* xv, bool up, uint32_t off, int i) {
@@ -169,12 +181,12 @@ __device__ __forceinline__ void load_a(StepA& o, const BatchSys& S, const CellA&
         o.zjp = ldo(src, off + cc.nz4);
         if (up) o.pjp = ldo(pold, off + cc.nz4);
     }
-    if (cc.haskm) {
+    if (cc.ldkm) {
         o.tzl = ldo(S.c.tz, off - 4u);
         o.zkm = ldo(src, off - 4u);
         if (up) o.pkm = ldo(pold, off - 4u);
     }
-    if (cc.haskp) {
+    if (cc.ldkp) {
         o.zkp = ldo(src, off + 4u);
         if (up) o.pkp = ldo(pold, off + 4u);
     }
@@ -200,6 +212,11 @@ __device__ __forceinline__ float phase_a_item(const BatchSys& S, int pc, int ic,
     cc.hasjp = (int)j + 1 < g.ny;
     cc.haskm = k > 0;
     cc.haskp = (int)k + 1 < g.nz;
+    const int lane = threadIdx.x & 63;
+    // the last lane of the wave that has a cell (the plane may end inside it)
+    const int last = (int)min(63u, P - 1u - (r0 - (uint32_t)lane));
+    cc.ldkm = cc.haskm && lane == 0;
+    cc.ldkp = cc.haskp && lane == last;
     cc.nz4 = 4u * (uint32_t)g.nz;
     cc.P4 = 4u * P;
     uint32_t off = 4u * ((uint32_t)i0 * P + r0);
@@ -214,10 +231,13 @@ __device__ __forceinline__ float phase_a_item(const BatchSys& S, int pc, int ic,
         const float sp = i + 1 < g.nx ? a.zp + beta * a.pp : sc;
         const float sjm = cc.hasjm ? a.zjm + beta * a.pjm : sc;
         const float sjp = cc.hasjp ? a.zjp + beta * a.pjp : sc;
-        const float skm = cc.haskm ? a.zkm + beta * a.pkm : sc;
-        const float skp = cc.haskp ? a.zkp + beta * a.pkp : sc;
+        // z neighbours: the neighbouring lanes' own values (same bits as loading them)
+        const float sl = wave_shr1(sc), sr = wave_shl1(sc), tl = wave_shr1(a.tz);
+        const float skm = !cc.haskm ? sc : cc.ldkm ? a.zkm + beta * a.pkm : sl;
+        const float skp = !cc.haskp ? sc : cc.ldkp ? a.zkp + beta * a.pkp : sr;
+        const float tzl = !cc.haskm ? 0.f : cc.ldkm ? a.tzl : tl;
         const float y =
-            cell_op<float, float>(a.ac, sc, a.tx, sp, txm, sm, a.ty, sjp, a.tyl, sjm, a.tz, skp, a.tzl, skm);
+            cell_op<float, float>(a.ac, sc, a.tx, sp, txm, sm, a.ty, sjp, a.tyl, sjm, a.tz, skp, tzl, skm);
         sto(pnew, o, sc);
         sto(S.q, o, y);
         if (up) sto(xv, o, a.xo + alpha_prev * poc);
