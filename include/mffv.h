@@ -385,8 +385,9 @@ int mffv_time_steps(mffv_grid* grid, int nsteps, const float* b, const float* c,
  *
  * The network works on the Jacobi-scaled system A~ = D^-1/2 A D^-1/2,
  * D = diag(A). Its two input channels per cell are the scaled residual
- * r_hat = D^-1/2 r / s, with s^2 = r' D^-1 r / n_U, and r_hat times the
- * log-diagonal feature of mffv_grid_feature; four 3x3x3 convolutions with
+ * r_hat = D^-1/2 r / s, s the power of two nearest the D^-1-weighted RMS of r
+ * (2^round(log2 rms), rms^2 = r' D^-1 r / n_U; dividing by it is exact), and
+ * r_hat times the log-diagonal feature of mffv_grid_feature; four 3x3x3 convolutions with
  * 2 -> 16 -> 16 -> 16 -> 1 channels and a ReLU after each of the first three
  * (zero padding at the grid boundary; y[K, o] = b[o] + sum_tap sum_c
  * W[tap, c, o] x[K + offset(tap), c] with tap = 9 (dx+1) + 3 (dy+1) + (dz+1))
