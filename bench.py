@@ -566,6 +566,11 @@ def bench_channelised(log_fn, held_in: int, held_out: int, steps: int, warmup: i
                                             dagger_epochs=2, log=log_fn)
         out["train_s"] = time.perf_counter() - t0
         out["train_seed_scores_128cube_held_in"] = {str(k): v for k, v in scores.items()}
+        # the sweeps' weight, chosen with the network on the same held-in 128^3 systems
+        omega, wscores = learned.select_smoothing(net, select)
+        out["nn_smooth"] = omega
+        out["nn_smooth_scores_128cube_held_in"] = {str(w): v for w, v in wscores.items()}
+        log_fn(f"channelised: sweep weight {omega} (iterations on the selection systems {wscores})")
         log_fn(f"channelised: trained {len(train_seeds)} networks on {held_in} held-in 32^3 realisations in "
                f"{out['train_s']:.1f} s; selection iterations {scores}")
         for g, _ in train + select:
@@ -573,7 +578,7 @@ def bench_channelised(log_fn, held_in: int, held_out: int, steps: int, warmup: i
         del train, select
         methods = {
             "learned_fcg": lambda tol=1e-6, **kw: mffv.default_opts(
-                tol=tol, precision=mffv.FP32_IR, precond=mffv.PRECOND_LEARNED, net=net, **kw),
+                tol=tol, precision=mffv.FP32_IR, precond=mffv.PRECOND_LEARNED, net=net, nn_smooth=omega, **kw),
             "plain": lambda tol=1e-6, **kw: mffv.default_opts(tol=tol, precision=mffv.FP32_IR, **kw),
             "jacobi": lambda tol=1e-6, **kw: mffv.default_opts(
                 tol=tol, precision=mffv.FP32_IR, precond=mffv.PRECOND_JACOBI, **kw),
@@ -596,7 +601,7 @@ def bench_channelised(log_fn, held_in: int, held_out: int, steps: int, warmup: i
                     # on the grid's stream), first 32 iterations
                     xt = torch.zeros(g.n, dtype=torch.float32, device="cuda")
                     _, tinfo = mffv.cg_solve(g, b, xt, mffv.default_opts(
-                        tol=1e-6, precond=mffv.PRECOND_LEARNED, net=net, timing=1))
+                        tol=1e-6, precond=mffv.PRECOND_LEARNED, net=net, nn_smooth=omega, timing=1))
                     out["timing"] = {k: tinfo[k] for k in ("phase_a_us", "phase_b_us", "precond_us",
                                                             "timed_iters", "nn_layer_us", "nn_timed")}
                     # each layer's launch duration: 20 back-to-back launches between
@@ -641,7 +646,7 @@ def bench_channelised(log_fn, held_in: int, held_out: int, steps: int, warmup: i
     return out
 
 
-def bench_crop_fields(log_fn, c1_field, c3_params):
+def bench_crop_fields(log_fn, c1_field, c3_params, omega: float = 0.5):
     """GPU fields for the accuracy comparison with the oracle (made by the CPU
     baseline leg): the 32^3 workload (plain CG in FP64 and in FP32 to 1e-6),
     the [0:64]^3 crop of the 256^3 field as its own problem (FP32 CG refined to
@@ -678,8 +683,9 @@ def bench_crop_fields(log_fn, c1_field, c3_params):
                                 ("plain", mffv.PRECOND_NONE, (1e-6,)),
                                 ("jacobi", mffv.PRECOND_JACOBI, (1e-6,))):
             for tol in tols:
+                lk = {"net": net, "nn_smooth": omega} if pre == mffv.PRECOND_LEARNED else {}
                 _, info, x = solve_f64(g, b.double(), mffv.default_opts(
-                    tol=tol, precision=mffv.FP32_IR, precond=pre, net=net if pre == mffv.PRECOND_LEARNED else None))
+                    tol=tol, precision=mffv.FP32_IR, precond=pre, **lk))
                 res[f"c3_crop64_{name}_{tol:g}"] = {"k": k3, "c": 1e-3, "x": x.cpu().numpy(), "info": info}
         net.close()
         g.close()
@@ -687,7 +693,7 @@ def bench_crop_fields(log_fn, c1_field, c3_params):
     return res
 
 
-def bench_large_learned(log_fn, c3_params, n_crops: int = 100, n_eval: int = 4):
+def bench_large_learned(log_fn, c3_params, n_crops: int = 100, n_eval: int = 4, omega: float = 0.5):
     """Learned preconditioner on the 512 x 512 x 1024 anisotropic workload: the
     network trained on the channelised field is fine-tuned on 32^3 crops of this
     field (white noise, then its own flexible-CG residuals), flexible CG with
@@ -725,7 +731,7 @@ def bench_large_learned(log_fn, c3_params, n_crops: int = 100, n_eval: int = 4):
         i, j, l = pos
         return k[i:i + size, j:j + size, l:l + size]
 
-    out = {"workload": w.name, "finetune_crops_32cube": n_crops, "eval_crops_128cube": n_eval}
+    out = {"workload": w.name, "finetune_crops_32cube": n_crops, "eval_crops_128cube": n_eval, "nn_smooth": omega}
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         t1 = time.perf_counter()
@@ -746,11 +752,11 @@ def bench_large_learned(log_fn, c3_params, n_crops: int = 100, n_eval: int = 4):
             g, b = problem(crop(pos, 128), s)
             for name, pre, net in methods:
                 x = torch.zeros(g.n, dtype=torch.float32, device="cuda")
-                mffv.cg_solve(g, b, x, mffv.default_opts(max_iter=4, precision=mffv.FP32_IR, precond=pre, net=net))
+                mffv.cg_solve(g, b, x, mffv.default_opts(max_iter=4, precision=mffv.FP32_IR, precond=pre, net=net, nn_smooth=omega))
                 x.zero_()
                 torch.cuda.synchronize()
                 t2 = time.perf_counter()
-                st, info = mffv.cg_solve(g, b, x, mffv.default_opts(precision=mffv.FP32_IR, precond=pre, net=net))
+                st, info = mffv.cg_solve(g, b, x, mffv.default_opts(precision=mffv.FP32_IR, precond=pre, net=net, nn_smooth=omega))
                 torch.cuda.synchronize()
                 rows[name].append((time.perf_counter() - t2, info["iters"], info["rel_res_true"], st))
             g.close()
@@ -771,8 +777,8 @@ def bench_large_learned(log_fn, c3_params, n_crops: int = 100, n_eval: int = 4):
         for name, pre, net in methods:
             iters = 20 if pre == mffv.PRECOND_LEARNED else 100
             x = torch.zeros(g.n, dtype=torch.float32, device="cuda")
-            o = mffv.default_opts(tol=1e-30, max_iter=iters, precond=pre, net=net)
-            mffv.cg_solve(g, b, x, mffv.default_opts(tol=1e-30, max_iter=4, precond=pre, net=net))
+            o = mffv.default_opts(tol=1e-30, max_iter=iters, precond=pre, net=net, nn_smooth=omega)
+            mffv.cg_solve(g, b, x, mffv.default_opts(tol=1e-30, max_iter=4, precond=pre, net=net, nn_smooth=omega))
             x.zero_()
             torch.cuda.synchronize()
             t3 = time.perf_counter()
@@ -787,7 +793,7 @@ def bench_large_learned(log_fn, c3_params, n_crops: int = 100, n_eval: int = 4):
     return out
 
 
-def cpu_baseline(c3_params, learned_iters, crop_fields, log_fn):
+def cpu_baseline(c3_params, learned_iters, crop_fields, log_fn, omega: float = 0.5):
     """The CPU baseline leg: the FP64 oracle on the host, one thread.
 
     * The headline's baseline: one iteration of the oracle's flexible CG with
@@ -821,7 +827,7 @@ def cpu_baseline(c3_params, learned_iters, crop_fields, log_fn):
         d = A.diagonal()
         ld = np.log(d)
         feat = np.where(dm.ravel(), 0.0, ld - ld[u].mean()).reshape(k3.shape)
-        M = nn.learned_preconditioner(c3_params, A, dm, feat, omega=0.5)
+        M = nn.learned_preconditioner(c3_params, A, dm, feat, omega=omega)
 
         t0 = time.perf_counter()
         z = M(bu)
@@ -832,7 +838,7 @@ def cpu_baseline(c3_params, learned_iters, crop_fields, log_fn):
         out.update({
             "value": t_iter * scale * learned_iters, "unit": "s", "cores": 1, "kind": "oracle",
             "sample": (f"one iteration of the oracle's flexible CG with the oracle's learned preconditioner "
-                       f"(the network between two damped Jacobi sweeps, omega 0.5: FP64 NumPy convolutions "
+                       f"(the network between two damped Jacobi sweeps, omega {omega:g}: FP64 NumPy convolutions "
                        f"on BF16-rounded operands, SciPy CSR products) on the [0:64]^3 crop "
                        f"of held-out channelised realisation 3500: {t_iter:.2f} s on 1 thread of "
                        f"{os.cpu_count()} host cores; scaled x{scale:g} (cells, to 128^3) and x{learned_iters:g} "
@@ -1089,16 +1095,16 @@ def main(argv=None):
             f"{batched['iters_min_max']}, worst true rel-res {batched['rel_res_true_max']:.2e}")
     large_learned = None
     if not args.no_large_learned:
-        large_learned = bench_large_learned(log, c3_params)
+        large_learned = bench_large_learned(log, c3_params, omega=head["nn_smooth"])
 
     cpu = None
     if not args.no_cpu_baseline:
         if k1 is None:
             from synth import WORKLOADS, workload_field
             k1 = workload_field(WORKLOADS["lognormal_corr8_256cube"])
-        crops = bench_crop_fields(log, k1, c3_params)
+        crops = bench_crop_fields(log, k1, c3_params, omega=head["nn_smooth"])
         log("cpu baseline (oracle on the host)")
-        cpu = cpu_baseline(c3_params, lf["iters_median"], crops, log)
+        cpu = cpu_baseline(c3_params, lf["iters_median"], crops, log, omega=head["nn_smooth"])
 
     ms_per_step = 1e3 * float(np.mean(step_times))
     line = {

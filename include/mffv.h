@@ -117,7 +117,8 @@ typedef struct {
                             of r is z1 = w D^-1 r, r1 = r - A z1, z2 = z1 + D^-1 r1 + C(r1),
                             z = z2 + w D^-1 (r - A z2), where C is the network's correction
                             (see mffv_net_create); with the zero network this is a fixed SPD
-                            polynomial preconditioner. 0: z = D^-1 r + C(r). In [0, 1). */
+                            polynomial preconditioner (for every w in (0, 4): the spectrum of
+                            D^-1/2 A D^-1/2 lies in (0, 2)). 0: z = D^-1 r + C(r). In [0, 2). */
 } mffv_opts;
 
 typedef struct {
@@ -500,7 +501,7 @@ int mffv_harvest_pair(mffv_grid* grid, const float* b, const float* x, const dou
  * (mffv_harvest_pair's space), out = (I - omega A~) r_hat on the unknown cells
  * and 0 on Dirichlet cells, A~ = D^-1/2 A D^-1/2, D = diag(A). r_hat, out:
  * device FP32, n cells, may not alias. Enqueued on the grid's stream.
- * Errors: MFFV_EINVAL for NULL arrays or omega outside [0, 1).
+ * Errors: MFFV_EINVAL for NULL arrays or omega outside [0, 2).
  */
 int mffv_nn_smooth_sample(mffv_grid* grid, double omega, const float* r_hat, float* out);
 

@@ -721,8 +721,8 @@ int validate_opts(const mffv_opts& o) {
     if (o.async != 0 && o.async != 1) return fail(MFFV_EINVAL, "opts.async must be 0 or 1");
     if (o.nn_every < 1 || o.nn_every > 64)
         return fail(MFFV_EINVAL, "opts.nn_every must be in [1, 64]");
-    if (!(o.nn_smooth >= 0.0 && o.nn_smooth < 1.0))
-        return fail(MFFV_EINVAL, "opts.nn_smooth must be in [0, 1)");
+    if (!(o.nn_smooth >= 0.0 && o.nn_smooth < 2.0))
+        return fail(MFFV_EINVAL, "opts.nn_smooth must be in [0, 2)");
     return MFFV_OK;
 }
 
@@ -1941,7 +1941,7 @@ int mffv_nn_smooth_sample(mffv_grid* G, double omega, const float* r_hat, float*
     int rc = check_grid(G, true);
     if (rc || (rc = check_cartesian(G, "mffv_nn_smooth_sample"))) return rc;
     if (!r_hat || !out) return fail(MFFV_EINVAL, "NULL array");
-    if (!(omega >= 0.0 && omega < 1.0)) return fail(MFFV_EINVAL, "omega must lie in [0, 1)");
+    if (!(omega >= 0.0 && omega < 2.0)) return fail(MFFV_EINVAL, "omega must lie in [0, 2)");
     if ((rc = set_device(G)) || (rc = ensure_ws32(G))) return rc;
     // r = D^1/2 r_hat, r1 = r - A (omega D^-1 r) (the first sweep's pass), out = D^-1/2 r1
     HIP_TRY(launch_scale_dsqrt(G->g.n, r_hat, G->dinv, G->dmask, +1, G->z, G->stream));

@@ -147,18 +147,29 @@ def init_params(seed: int = 0):
     return p
 
 
-def fcg_iterations(net: mffv.Net, systems, max_iter=20000) -> int:
+def fcg_iterations(net: mffv.Net, systems, max_iter=20000, omega: float | None = None) -> int:
     """Total flexible-CG iterations to 1e-6 over the systems (validation metric);
     a system that does not converge within max_iter (a number, or one per
-    system) counts max_iter."""
+    system) counts max_iter. omega: the weight of the Jacobi sweeps around the
+    network (None: the library's default)."""
     caps = max_iter if isinstance(max_iter, (list, tuple)) else [max_iter] * len(systems)
+    kw = {} if omega is None else {"nn_smooth": float(omega)}
     tot = 0
     for (grid, b), cap in zip(systems, caps):
         x = torch.zeros(grid.n, dtype=torch.float32, device=b.device)
         st, info = mffv.cg_solve(grid, b, x, mffv.default_opts(
-            precond=mffv.PRECOND_LEARNED, net=net, max_iter=int(cap)))
+            precond=mffv.PRECOND_LEARNED, net=net, max_iter=int(cap), **kw))
         tot += info["iters"] if st == mffv.OK else int(cap)
     return tot
+
+
+def select_smoothing(net: mffv.Net, systems, omegas=(0.5, 0.7, 0.85, 0.95, 1.0, 1.1)):
+    """The sweep weight omega (opts.nn_smooth) for a trained network: the one
+    with the fewest flexible-CG iterations on the given (held-in) systems; the
+    first of equal counts. Returns (omega, {omega: iterations})."""
+    scores = {float(w): fcg_iterations(net, systems, omega=w) for w in omegas}
+    best = min(scores, key=lambda w: (scores[w], list(scores).index(w)))
+    return best, scores
 
 
 def train_preconditioner(systems, validation=None, n_white: int = 256, epochs: int = 24,

@@ -319,7 +319,7 @@ def test_zero_network_between_the_sweeps_is_the_polynomial_pcg(mf, omega):
     p = ref.direct()
     assert np.linalg.norm(x64.cpu().numpy() - p) <= 1e-6 * np.linalg.norm(p)
     with pytest.raises(mf.MffvError):
-        mf.cg_solve(g, b, x, mf.default_opts(precond=mf.PRECOND_LEARNED, net=net, nn_smooth=1.0))
+        mf.cg_solve(g, b, x, mf.default_opts(precond=mf.PRECOND_LEARNED, net=net, nn_smooth=2.0))
 
 
 def test_smooth_sample_matches_the_oracle(mf):
