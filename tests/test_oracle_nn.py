@@ -341,7 +341,7 @@ def test_sandwich_preconditioner_without_network_is_the_polynomial():
     zero = nn.init_params(seed=0, last_scale=0.0)
     rng = np.random.default_rng(22)
     d = A.diagonal()[u]
-    for w in (0.5, 0.8):
+    for w in (0.5, 0.8, 1.0, 1.9):   # the library accepts [0, 2): SPD on the whole range
         M = nn.learned_preconditioner(zero, A, dm, np.zeros(shape), omega=w)
         r = rng.normal(size=u.sum())
         I = np.eye(u.sum())
