@@ -333,7 +333,7 @@ def test_smooth_sample_matches_the_oracle(mf):
     rng = np.random.default_rng(8)
     rh = rng.standard_normal(k.size).astype(np.float32)
     out = torch.empty(k.size, dtype=torch.float32, device="cuda")
-    for omega in (0.5, 0.0):
+    for omega in (0.5, 0.0, 1.5):
         mf.nn_smooth_sample(g, omega, dev(rh), out)
         torch.cuda.synchronize()
         d = ref.A.diagonal()
@@ -344,8 +344,8 @@ def test_smooth_sample_matches_the_oracle(mf):
         got = host(out)
         assert np.all(got[~u] == 0.0)
         assert np.max(np.abs(got - want)) <= 1e-5 * np.max(np.abs(want)), omega
-    with pytest.raises(mf.MffvError):
-        mf.nn_smooth_sample(g, 1.0, dev(rh), out)
+    with pytest.raises(mf.MffvError):   # the weight lies in [0, 2)
+        mf.nn_smooth_sample(g, 2.0, dev(rh), out)
     g.close()
 
 
