@@ -741,22 +741,26 @@ def bench_large_learned(log_fn, c3_params, n_crops: int = 100, n_eval: int = 4, 
                                              log=log_fn)
         out["finetune_s"] = time.perf_counter() - t1
         log_fn(f"large-learned: fine-tuned on {n_crops} crops of 32^3 in {out['finetune_s']:.1f} s")
+        # the fine-tuned network's own sweep weight, chosen on its held-in validation crops
+        omega_t, wscores = learned.select_smoothing(tuned, train[:8])
+        out["nn_smooth_finetuned"] = omega_t
+        log_fn(f"large-learned: sweep weight of the fine-tuned network {omega_t} (validation crops {wscores})")
         c3 = mffv.net_create(c3_params)
-        # (name, preconditioner, network)
-        methods = (("plain", mffv.PRECOND_NONE, None),
-                   ("jacobi", mffv.PRECOND_JACOBI, None),
-                   ("learned_fcg_channelised_net", mffv.PRECOND_LEARNED, c3),
-                   ("learned_fcg_finetuned", mffv.PRECOND_LEARNED, tuned))
-        rows = {name: [] for name, _, _ in methods}
+        # (name, preconditioner, network, sweep weight)
+        methods = (("plain", mffv.PRECOND_NONE, None, omega),
+                   ("jacobi", mffv.PRECOND_JACOBI, None, omega),
+                   ("learned_fcg_channelised_net", mffv.PRECOND_LEARNED, c3, omega),
+                   ("learned_fcg_finetuned", mffv.PRECOND_LEARNED, tuned, omega_t))
+        rows = {name: [] for name, _, _, _ in methods}
         for pos in positions(128, n_eval):
             g, b = problem(crop(pos, 128), s)
-            for name, pre, net in methods:
+            for name, pre, net, w_ in methods:
                 x = torch.zeros(g.n, dtype=torch.float32, device="cuda")
-                mffv.cg_solve(g, b, x, mffv.default_opts(max_iter=4, precision=mffv.FP32_IR, precond=pre, net=net, nn_smooth=omega))
+                mffv.cg_solve(g, b, x, mffv.default_opts(max_iter=4, precision=mffv.FP32_IR, precond=pre, net=net, nn_smooth=w_))
                 x.zero_()
                 torch.cuda.synchronize()
                 t2 = time.perf_counter()
-                st, info = mffv.cg_solve(g, b, x, mffv.default_opts(precision=mffv.FP32_IR, precond=pre, net=net, nn_smooth=omega))
+                st, info = mffv.cg_solve(g, b, x, mffv.default_opts(precision=mffv.FP32_IR, precond=pre, net=net, nn_smooth=w_))
                 torch.cuda.synchronize()
                 rows[name].append((time.perf_counter() - t2, info["iters"], info["rel_res_true"], st))
             g.close()
@@ -774,11 +778,11 @@ def bench_large_learned(log_fn, c3_params, n_crops: int = 100, n_eval: int = 4, 
         g, b = problem(k, s)
         del k
         full = {}
-        for name, pre, net in methods:
+        for name, pre, net, w_ in methods:
             iters = 20 if pre == mffv.PRECOND_LEARNED else 100
             x = torch.zeros(g.n, dtype=torch.float32, device="cuda")
-            o = mffv.default_opts(tol=1e-30, max_iter=iters, precond=pre, net=net, nn_smooth=omega)
-            mffv.cg_solve(g, b, x, mffv.default_opts(tol=1e-30, max_iter=4, precond=pre, net=net, nn_smooth=omega))
+            o = mffv.default_opts(tol=1e-30, max_iter=iters, precond=pre, net=net, nn_smooth=w_)
+            mffv.cg_solve(g, b, x, mffv.default_opts(tol=1e-30, max_iter=4, precond=pre, net=net, nn_smooth=w_))
             x.zero_()
             torch.cuda.synchronize()
             t3 = time.perf_counter()
