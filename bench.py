@@ -741,10 +741,23 @@ def bench_large_learned(log_fn, c3_params, n_crops: int = 100, n_eval: int = 4, 
                                              log=log_fn)
         out["finetune_s"] = time.perf_counter() - t1
         log_fn(f"large-learned: fine-tuned on {n_crops} crops of 32^3 in {out['finetune_s']:.1f} s")
-        # the fine-tuned network's own sweep weight, chosen on its held-in validation crops
-        omega_t, wscores = learned.select_smoothing(tuned, train[:8])
+        eval_pos = positions(128, n_eval)
+        # the fine-tuned network's own sweep weight, chosen on two held-in 128^3
+        # crops that overlap none of the evaluation crops (the 32^3 training
+        # crops favour another weight than the 128^3 systems do)
+        def overlaps(p, q):
+            return all(abs(a - b_) < 128 for a, b_ in zip(p, q))
+        sel_pos = []
+        while len(sel_pos) < 2:
+            cand = positions(128, 1)[0]
+            if not any(overlaps(cand, q) for q in eval_pos + sel_pos):
+                sel_pos.append(cand)
+        sel = [problem(crop(p, 128), s) for p in sel_pos]
+        omega_t, wscores = learned.select_smoothing(tuned, sel)
+        for g, _ in sel:
+            g.close()
         out["nn_smooth_finetuned"] = omega_t
-        log_fn(f"large-learned: sweep weight of the fine-tuned network {omega_t} (validation crops {wscores})")
+        log_fn(f"large-learned: sweep weight of the fine-tuned network {omega_t} (held-in 128^3 crops {wscores})")
         c3 = mffv.net_create(c3_params)
         # (name, preconditioner, network, sweep weight)
         methods = (("plain", mffv.PRECOND_NONE, None, omega),
@@ -752,7 +765,7 @@ def bench_large_learned(log_fn, c3_params, n_crops: int = 100, n_eval: int = 4, 
                    ("learned_fcg_channelised_net", mffv.PRECOND_LEARNED, c3, omega),
                    ("learned_fcg_finetuned", mffv.PRECOND_LEARNED, tuned, omega_t))
         rows = {name: [] for name, _, _, _ in methods}
-        for pos in positions(128, n_eval):
+        for pos in eval_pos:
             g, b = problem(crop(pos, 128), s)
             for name, pre, net, w_ in methods:
                 x = torch.zeros(g.n, dtype=torch.float32, device="cuda")
