@@ -158,8 +158,9 @@ def test_batched_uneven_64_systems_workload(mf):
         assert xh.min() >= -1e-4 and xh.max() <= 1 + 1e-4
     # the refined FP32 fields meet the tolerance on the true residual
     assert worst <= 1e-6
-    # and the fields of the smaller systems match the oracle's direct solution
-    small = sorted(range(len(systems)), key=lambda i: systems[i].k.size)[:4]
+    # and the fields of the two smallest systems (44k and 77k unknowns) match
+    # the oracle's direct solution
+    small = sorted(range(len(systems)), key=lambda i: systems[i].k.size)[:2]
     for i in small:
         ref = OracleProblem(systems[i].k, c=systems[i].c)
         p = ref.direct()
