@@ -154,13 +154,25 @@ __device__ __forceinline__ T block_sum(T v, T* lds /* kThreads/kWave entries */)
     return s;
 }
 
+// Partial values a thread loads before adding them: the loads of a batch are
+// in flight together (one memory latency per batch instead of one per value).
+constexpr int kPartBatch = 4;
+
 // Sum nparts partial values written by an earlier kernel, in a fixed order
 // (strided per thread, then the block tree): every block that calls it gets
 // the same bits, and the result is reproducible for a given launch shape.
+// A thread adds its values in index order whatever the batching of the loads.
 template <class T>
 __device__ __forceinline__ T sum_partials(const T* parts, int nparts, T* lds) {
     T s = T(0);
-    for (int i = threadIdx.x; i < nparts; i += kThreads) s += parts[i];
+    for (int i = threadIdx.x; i < nparts; i += kPartBatch * kThreads) {
+        T v[kPartBatch];
+#pragma unroll
+        for (int k = 0; k < kPartBatch; ++k) v[k] = i + k * kThreads < nparts ? parts[i + k * kThreads] : T(0);
+#pragma unroll
+        for (int k = 0; k < kPartBatch; ++k)
+            if (i + k * kThreads < nparts) s += v[k];
+    }
     return block_sum(s, lds);
 }
 
@@ -178,10 +190,18 @@ __device__ __forceinline__ void sum_partials_n(const T* const (&parts)[N], const
         s[j] = T(0);
         mx = counts[j] > mx ? counts[j] : mx;
     }
-    for (int i = threadIdx.x; i < mx; i += kThreads) {
+    for (int i = threadIdx.x; i < mx; i += kPartBatch * kThreads) {
+        T v[N][kPartBatch];
 #pragma unroll
         for (int j = 0; j < N; ++j)
-            if (i < counts[j]) s[j] += parts[j][i];
+#pragma unroll
+            for (int k = 0; k < kPartBatch; ++k)
+                v[j][k] = i + k * kThreads < counts[j] ? parts[j][i + k * kThreads] : T(0);
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+#pragma unroll
+            for (int k = 0; k < kPartBatch; ++k)
+                if (i + k * kThreads < counts[j]) s[j] += v[j][k];
     }
     constexpr int NW = kThreads / kWave;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
