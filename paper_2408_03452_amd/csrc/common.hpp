@@ -176,13 +176,53 @@ __device__ __forceinline__ T sum_partials(const T* parts, int nparts, T* lds) {
     return block_sum(s, lds);
 }
 
+// The first batch of sum_partials_n's loads of thread threadIdx.x (values at
+// or past a count read as 0). Issued on its own, these loads can be in flight
+// together with a kernel's other start-up reads: one memory round trip
+// instead of several in a row.
+// Indexes past the count are clamped to the last entry (an array with count 0
+// is not read): every load is unconditional within the block-uniform test, so
+// the compiler does not fold a load into the add that consumes it.
+template <class T, int N>
+__device__ __forceinline__ void load_partials_first(const T* const (&parts)[N], const int (&counts)[N],
+                                                    T (&v)[N][kPartBatch]) {
+    const int i = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+#pragma unroll
+        for (int k = 0; k < kPartBatch; ++k) v[j][k] = T(0);
+        if (counts[j] > 0) {
+#pragma unroll
+            for (int k = 0; k < kPartBatch; ++k) {
+                const int e = i + k * kThreads;
+                v[j][k] = parts[j][e < counts[j] ? e : counts[j] - 1];
+            }
+        }
+    }
+}
+
+// A relaxed load of a value that no block changes during the kernel (or whose
+// change every block would reach by itself): the compiler keeps it where it is
+// written, neither moving it past a barrier nor into a branch, so it overlaps
+// the loads issued next to it.
+template <class T>
+__device__ __forceinline__ T early_load(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait for every load the wave has issued: a kernel that returns early after
+// such early loads ends with none of them in flight.
+__device__ __forceinline__ void drain_loads() { __builtin_amdgcn_s_waitcnt(0); }
+
 // N sums of partials at once, each in sum_partials' order (so each result
 // has the same bits as sum_partials of that array), with one pass over the
 // arrays and one block tree: the loads of all arrays are in flight together.
+// first: the thread's first batch, loaded by load_partials_first with counts
+// at least these (a larger load count reads entries that are then not added).
 // An array with count 0 sums to 0. lds: N * kThreads / kWave entries.
 template <class T, int N>
-__device__ __forceinline__ void sum_partials_n(const T* const (&parts)[N], const int (&counts)[N], T* lds,
-                                               T (&out)[N]) {
+__device__ __forceinline__ void sum_partials_n_rest(const T* const (&parts)[N], const int (&counts)[N],
+                                                    const T (&first)[N][kPartBatch], T* lds, T (&out)[N]) {
     T s[N];
     int mx = 0;
 #pragma unroll
@@ -190,7 +230,18 @@ __device__ __forceinline__ void sum_partials_n(const T* const (&parts)[N], const
         s[j] = T(0);
         mx = counts[j] > mx ? counts[j] : mx;
     }
-    for (int i = threadIdx.x; i < mx; i += kPartBatch * kThreads) {
+    const int i0 = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+        for (int k = 0; k < kPartBatch; ++k) {
+            // the value enters here and no earlier: the compiler cannot start
+            // the adds (and wait for the loads) ahead of a barrier before this
+            T v = first[j][k];
+            asm volatile("" : "+v"(v));
+            if (i0 + k * kThreads < counts[j]) s[j] += v;
+        }
+    for (int i = i0 + kPartBatch * kThreads; i < mx; i += kPartBatch * kThreads) {
         T v[N][kPartBatch];
 #pragma unroll
         for (int j = 0; j < N; ++j)
@@ -222,7 +273,28 @@ __device__ __forceinline__ void sum_partials_n(const T* const (&parts)[N], const
     }
 }
 
+template <class T, int N>
+__device__ __forceinline__ void sum_partials_n(const T* const (&parts)[N], const int (&counts)[N], T* lds,
+                                               T (&out)[N]) {
+    T first[N][kPartBatch];
+    load_partials_first(parts, counts, first);
+    sum_partials_n_rest(parts, counts, first, lds, out);
+}
+
 __device__ __forceinline__ bool first_thread() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
+// Thread 0's copy of a flag that every thread has read (so that the read can
+// be in flight with other loads), shared through LDS: all waves of the block
+// take the same branch even if another block of the same kernel sets the
+// flag meanwhile.
+__device__ __forceinline__ bool block_uniform(int v) {
+    __shared__ int s;
+    if (threadIdx.x == 0) s = v;
+    __syncthreads();
+    const bool r = s != 0;
+    __syncthreads();
+    return r;
+}
 
 // Read a flag once per block (thread 0) and share it through LDS, so that all
 // waves of the block take the same branch even if another block of the same

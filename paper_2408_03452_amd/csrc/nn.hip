@@ -741,9 +741,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
 // sqrt(sum(dinv r^2) / n_U), scale[1] = 1 / s (both 0 for a zero residual).
 __global__ __launch_bounds__(kThreads) void nn_scale(const float* pb, int nb, float n_u, float* scale,
                                                      const int* done) {
-    if (done && *done) return;  // the CG loop has ended
+    // the first batch of partials in flight with the read of the loop's done flag
+    const float* pp[1] = {pb};
+    const int np[1] = {nb};
+    float first[1][kPartBatch];
+    load_partials_first(pp, np, first);
+    if (done && block_uniform(early_load(done))) {  // the CG loop has ended
+        drain_loads();
+        return;
+    }
     __shared__ float red[kThreads / kWave];
-    const float rr = sum_partials(pb, nb, red);
+    float rrs[1];
+    sum_partials_n_rest(pp, np, first, red, rrs);
+    const float rr = rrs[0];
     if (threadIdx.x == 0) {
         // the power of two nearest the RMS: 2^e with e = floor(log2(rms sqrt 2))
         const int e = rr > 0.f ? ilogbf(sqrtf(rr / n_u) * 1.41421356f) : 0;

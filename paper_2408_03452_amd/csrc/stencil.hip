@@ -106,15 +106,32 @@ struct PhaseA {
 template <class real>
 __device__ bool phase_a_start(const StencilIO<real>& io, real* lds, PhaseA<real>& o) {
     CgState<real>* st = io.st;
-    if (block_flag(&st->done)) return false;
-    const int k = st->iterA;
     // r.r; Jacobi: r.z; at k = 0: ||b_U||^2; flexible CG: the preconditioner's
     // z.r, z.q and the Jacobi safeguard's dinv r.r, dinv r.q; summed together
     const int nb = io.nb_b, nf = io.precond == 2 ? io.nb_f : 0;
     const real* parts[7] = {io.pb, io.pb + nb, io.pb + 2 * nb, io.pf, io.pf + nf, io.pf + 2 * nf, io.pf + 3 * nf};
+    // The done flag, the loop's scalars and the first batch of partials are
+    // read together, in one memory round trip. No block writes any of these
+    // scalars during this kernel (block 0 writes other slots, and thresh2 and
+    // bnorm2 only at k = 0, where they are formed here rather than read); the
+    // ||b_U||^2 partials are loaded before k is known (their buffer always
+    // holds nb entries) and added at k = 0 only.
+    const int loads[7] = {nb, io.precond == 1 ? nb : 0, nb, nf, nf, nf, nf};
+    real first[7][kPartBatch];
+    load_partials_first(parts, loads, first);
+    const int done = early_load(&st->done), k = early_load(&st->iterA), max_iter = early_load(&st->max_iter);
+    const real thresh2_st = early_load(&st->thresh2), bnorm2_st = early_load(&st->bnorm2),
+               tol2 = early_load(&st->tol2);
+    const real alpha0 = early_load(&st->alpha[0]), alpha1 = early_load(&st->alpha[1]);
+    const real rho0 = early_load(&st->rho[0]), rho1 = early_load(&st->rho[1]);
+    const real pq0 = early_load(&st->pq[0]), pq1 = early_load(&st->pq[1]);
+    if (block_uniform(done)) {
+        drain_loads();
+        return false;
+    }
     const int counts[7] = {nb, io.precond == 1 ? nb : 0, k == 0 ? nb : 0, nf, nf, nf, nf};
     real sums[7];
-    sum_partials_n(parts, counts, lds, sums);
+    sum_partials_n_rest(parts, counts, first, lds, sums);
     const real rr = sums[0];
     real rho = rr, zq = 0;
     bool fallback = false;
@@ -126,15 +143,15 @@ __device__ bool phase_a_start(const StencilIO<real>& io, real* lds, PhaseA<real>
         rho = fallback ? jr : zr;
         zq = fallback ? jq : zqv;
     }
-    real thresh2 = st->thresh2, bnorm2 = st->bnorm2;
+    real thresh2 = thresh2_st, bnorm2 = bnorm2_st;
     if (k == 0) {
         const real bb = sums[2];
         bnorm2 = bb > real(0) ? bb : rr;
-        thresh2 = st->tol2 * bnorm2;
+        thresh2 = tol2 * bnorm2;
     }
     const bool conv = isfinite(rr) && rr <= thresh2;
     const bool bad = !conv && (!isfinite(rr) || (io.precond != 0 && (!(rho > real(0)) || !isfinite(rho))));
-    const bool cap = k >= st->max_iter;
+    const bool cap = k >= max_iter;
     if (conv || bad || cap) {
         if (first_thread()) {
             st->done = 1;
@@ -153,10 +170,11 @@ __device__ bool phase_a_start(const StencilIO<real>& io, real* lds, PhaseA<real>
     }
     o.k = k;
     o.fallback = fallback;
-    o.alpha_prev = k >= 1 ? st->alpha[(k - 1) & 1] : real(0);
-    o.alpha_prev2 = k >= 2 ? st->alpha[k & 1] : real(0);  // phase B_k has not written it yet
-    o.beta = k == 0 ? real(0)
-                    : (io.precond == 2 ? -zq / st->pq[(k - 1) & 1] : rho / st->rho[(k - 1) & 1]);
+    // slot (k - 1) & 1 and slot k & 1 (selects, not indexing: the values stay in registers)
+    const bool odd = k & 1;
+    o.alpha_prev = k >= 1 ? (odd ? alpha0 : alpha1) : real(0);
+    o.alpha_prev2 = k >= 2 ? (odd ? alpha1 : alpha0) : real(0);  // phase B_k has not written it yet
+    o.beta = k == 0 ? real(0) : (io.precond == 2 ? -zq / (odd ? pq0 : pq1) : rho / (odd ? rho0 : rho1));
     if (first_thread()) {
         st->rho[k & 1] = rho;
         st->iterB = k;

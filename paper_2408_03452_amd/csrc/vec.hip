@@ -42,9 +42,22 @@ __global__ __launch_bounds__(kThreads) void phase_b(int64_t n, VecIO<real> io) {
     CgState<real>* st = io.st;
     real alpha = 0;
     if (MODE != kBInit) {
-        if (block_flag(&st->done)) return;
-        const int k = st->iterB;
-        const real pq = sum_partials(io.pa, io.nb_a, red);
+        // the done flag, k, rho and the first batch of phase A's partials in
+        // one memory round trip (phase A_k wrote rho; no block of this kernel
+        // writes it), then the sum in sum_partials' order
+        const real* pa[1] = {io.pa};
+        const int na[1] = {io.nb_a};
+        real first[1][kPartBatch];
+        load_partials_first(pa, na, first);
+        const int done = early_load(&st->done), k = early_load(&st->iterB);
+        const real rho0 = early_load(&st->rho[0]), rho1 = early_load(&st->rho[1]);
+        if (block_uniform(done)) {
+            drain_loads();
+            return;
+        }
+        real pqs[1];
+        sum_partials_n_rest(pa, na, first, red, pqs);
+        const real pq = pqs[0];
         if (!(pq > real(0)) || !isfinite(pq)) {
             if (first_thread()) {
                 st->done = 1;
@@ -56,7 +69,7 @@ __global__ __launch_bounds__(kThreads) void phase_b(int64_t n, VecIO<real> io) {
             }
             return;
         }
-        alpha = st->rho[k & 1] / pq;
+        alpha = ((k & 1) ? rho1 : rho0) / pq;
         if (first_thread()) {
             st->alpha[k & 1] = alpha;
             st->pq[k & 1] = pq;
